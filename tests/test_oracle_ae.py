@@ -1,0 +1,212 @@
+"""Pins of the autoencoder, rounding and checkpointing oracles (paper
+Sec. 3.1 layout, Sec. 3.3 dense network and training, Sec. 3.3.1
+normalisation; Sec. 1 checkpointing)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ae as oae
+from oracle import revolve as orv
+from oracle import rounding as rd
+
+
+# ----- layout and normalisation ------------------------------------------------------------
+def test_patch_layout_brute_force():
+    rng = np.random.default_rng(0)
+    st = rng.standard_normal((4, 16, 8, 24))
+    X = oae.patchify(st)
+    Py, Px = 1, 3
+    for p in range(X.shape[0]):
+        pz, rem = divmod(p, Py * Px)
+        py, px = divmod(rem, Px)
+        for f in range(4):
+            for lz in (0, 5, 7):
+                for ly in (0, 3, 7):
+                    for lx in (0, 6, 7):
+                        assert X[p, f * 512 + lz * 64 + ly * 8 + lx] == \
+                            st[f, pz * 8 + lz, py * 8 + ly, px * 8 + lx]
+    assert np.array_equal(oae.unpatchify(X, 16, 8, 24), st)
+
+
+def test_normalisation_special_cases():
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((6, 2048)) * 10.0 ** rng.uniform(-12, 3, size=(6, 1))
+    X[2, 512:1024] = 3.25                      # constant field slice
+    beta = np.array([1e-7, 2e-7, 3e-7, 4e-7])
+    Y, lo, r = oae.normalize(X, beta)
+    Yf = Y.reshape(6, 4, 512)
+    assert np.all(Yf >= 0.0) and np.all(Yf <= 1.0)
+    for p in range(6):
+        for f in range(4):
+            if p == 2 and f == 1:
+                assert r[p, f] == beta[f] and np.all(Yf[p, f] == 0.0) and lo[p, f] == 3.25
+                continue
+            if r[p, f] > beta[f]:
+                assert Yf[p, f].min() == 0.0 and Yf[p, f].max() == 1.0
+    Xr = oae.denormalize(Y, lo, r).reshape(6, 4, 512)
+    bound = 4 * np.finfo(float).eps * (np.abs(lo) + r)[..., None]
+    assert np.all(np.abs(Xr - X.reshape(6, 4, 512)) <= bound)
+
+
+# ----- activation ---------------------------------------------------------------------------------
+def test_gelu_matches_torch_exact_form():
+    x = np.linspace(-8, 8, 2001)
+    ref = torch.nn.functional.gelu(torch.tensor(x, dtype=torch.float64)).numpy()
+    assert np.max(np.abs(oae.gelu(x) - ref)) < 1e-15
+    h = 1e-6
+    fd = (oae.gelu(x + h) - oae.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(fd - oae.gelu_prime(x))) < 1e-8
+
+
+# ----- network backward and Adam --------------------------------------------------------------------
+def _tiny_params(seed=3, dims=(24, 10, 4)):
+    i, h, l = dims
+    return W.ae_init(i, h, l, seed=seed)
+
+
+def test_backward_matches_finite_differences():
+    ae = oae.AE(_tiny_params())
+    rng = np.random.default_rng(2)
+    Y = rng.random((7, 24))
+    loss, g = ae.loss_and_grads(Y)
+    for name in oae.NAMES:
+        P = ae.p[name]
+        for _ in range(4):
+            idx = tuple(rng.integers(0, s) for s in P.shape)
+            old = P[idx]
+            h = 1e-6
+            P[idx] = old + h
+            lp, _ = ae.loss_and_grads(Y)
+            P[idx] = old - h
+            lm, _ = ae.loss_and_grads(Y)
+            P[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name][idx]) <= 1e-7 * max(1.0, abs(fd)) + 1e-10
+
+
+def test_backward_matches_torch_autograd():
+    """Independent check of every gradient with torch's CPU autograd in FP64."""
+    prm = _tiny_params(seed=5, dims=(32, 16, 6))
+    ae = oae.AE(prm)
+    rng = np.random.default_rng(3)
+    Y = rng.random((9, 32))
+    loss, g = ae.loss_and_grads(Y)
+    t = {k: torch.tensor(v, requires_grad=True) for k, v in prm.items()}
+    y = torch.tensor(Y)
+    gel = torch.nn.functional.gelu
+    z = gel(y @ t["W1"] + t["b1"]) @ t["W2"] + t["b2"]
+    yh = gel(z @ t["W3"] + t["b3"]) @ t["W4"] + t["b4"]
+    lt = torch.mean((yh - y) ** 2)
+    lt.backward()
+    assert abs(lt.item() - loss) < 1e-14
+    for k in oae.NAMES:
+        assert np.allclose(t[k].grad.numpy(), g[k], rtol=1e-12, atol=1e-15)
+
+
+def test_adam_first_step_closed_form():
+    """Bias correction makes the first Adam step -lr g / (|g| + eps)."""
+    rng = np.random.default_rng(4)
+    p = {"w": rng.standard_normal(50)}
+    g = {"w": rng.standard_normal(50) * 10.0 ** rng.uniform(-6, 2, 50)}
+    w0 = p["w"].copy()
+    opt = oae.Adam(p, lr=1e-3)
+    opt.step(p, g)
+    assert np.allclose(p["w"] - w0, -1e-3 * g["w"] / (np.abs(g["w"]) + 1e-8), rtol=1e-12)
+
+
+def test_linear_autoencoder_reaches_pca_optimum():
+    """With identity activations the trained affine AE attains the PCA
+    optimum: MSE = (sum of covariance eigenvalues beyond the latent size) / n."""
+    rng = np.random.default_rng(5)
+    n, lat, ns = 16, 3, 400
+    A = rng.standard_normal((n, n)) * np.exp(-0.35 * np.arange(n))[None, :]
+    Y = 0.5 + rng.standard_normal((ns, n)) @ A.T * 0.2
+    ev = np.sort(np.linalg.eigvalsh(np.cov(Y.T, bias=True)))[::-1]
+    opt_mse = ev[lat:].sum() / n
+    ae = oae.AE(W.ae_init(n, 8, lat, seed=6), act="identity")
+    perms = np.tile(np.arange(ns), (1, 1))
+    opt = oae.Adam(ae.p, lr=1e-2)
+    for it in range(6000):
+        lr = 1e-2 if it < 3000 else (3e-3 if it < 5000 else 1e-3)
+        loss, g = ae.loss_and_grads(Y)
+        opt.step(ae.p, g, lr=lr)
+    loss, _ = ae.loss_and_grads(Y)
+    assert loss >= opt_mse * (1 - 1e-9)
+    assert loss <= opt_mse * 1.01
+
+
+def test_emulated_forward_close_to_fp64():
+    prm = W.ae_init(2048, 512, 32, seed=4)
+    ae = oae.AE(prm)
+    rng = np.random.default_rng(6)
+    Y = rng.random((16, 2048))
+    a = ae.forward(Y)["yhat"]
+    b = ae.forward(Y, emulate=True)["yhat"]
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 2e-2
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) > 0.0
+
+
+# ----- rounding -------------------------------------------------------------------------------------
+def test_bf16_codes_roundtrip_and_nearest():
+    codes = np.arange(1 << 16, dtype=np.uint16)
+    vals = rd.bf16_from_bits(codes)
+    fin = np.isfinite(vals)
+    assert np.array_equal(rd.bf16_bits(vals[fin]), codes[fin])
+    rng = np.random.default_rng(7)
+    x = rd.f32(rng.standard_normal(200000) * 10.0 ** rng.uniform(-30, 30, 200000))
+    r = rd.bf16(x)
+    # brute force: no representable neighbour is strictly closer; ties go to even code
+    b = rd.bf16_bits(x).astype(np.int64)
+    for d in (-1, 1):
+        nb = rd.bf16_from_bits((b + d).astype(np.uint16))
+        ok = np.isfinite(nb)
+        closer = np.abs(nb - x) < np.abs(r - x)
+        assert not np.any(closer & ok)
+        tie = (np.abs(nb - x) == np.abs(r - x)) & ok
+        assert np.all((b[tie] & 1) == 0)
+    t = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(t, r)
+
+
+def test_e4m3_table_and_rounding():
+    codes = np.arange(256, dtype=np.uint8)
+    vals = rd.e4m3_decode(codes)
+    finite = np.isfinite(vals)
+    assert finite.sum() == 254 and np.nanmax(vals) == 448.0
+    assert np.nanmin(np.abs(vals[vals != 0])) == 2.0 ** -9
+    pos = np.unique(vals[finite & (vals >= 0)])
+    # every midpoint between neighbours rounds to the neighbour with even code
+    mids = 0.5 * (pos[1:] + pos[:-1])
+    got = rd.e4m3(mids)
+    lo_codes = rd.e4m3_bits(pos[:-1])
+    expect = np.where((lo_codes & 1) == 0, pos[:-1], pos[1:])
+    assert np.array_equal(got, expect)
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-460, 460, 100000) * 10.0 ** rng.integers(-4, 1, 100000)
+    r = rd.e4m3(x)
+    allv = np.concatenate([-pos, pos])
+    nearest = np.min(np.abs(allv[None, :] - x[:, None]), axis=1)
+    assert np.allclose(np.abs(r - x), nearest, rtol=0, atol=0)
+    assert np.all(np.abs(r) <= 448.0)
+    assert np.array_equal(rd.e4m3_decode(rd.e4m3_bits(r)), r)
+    inr = np.abs(x) <= 448.0
+    t = torch.tensor(x[inr]).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(t, r[inr])
+
+
+# ----- checkpointing cost -----------------------------------------------------------------------------
+def test_revolve_closed_form_equals_dp():
+    T = orv.dp_table(120, 7)
+    for l in range(1, 121):
+        for s in range(1, 8):
+            assert T[l, s] == orv.closed_form(l, s), (l, s)
+
+
+def test_revolve_counts_for_the_workloads():
+    assert orv.closed_form(2000, 64) == 3934
+    assert orv.closed_form(3000, 64) == 6789
+    assert orv.closed_form(4000, 64) == 9789
+    assert orv.closed_form(50, 1) == 50 * 49 // 2
