@@ -1,0 +1,256 @@
+/*
+ * wavecomp.h - C ABI of the MI355X (gfx950) library for the autoencoder-
+ * compressed adjoint gradient and Gauss-Newton Hessian-vector product of
+ * the acoustic velocity-strain inverse problem.
+ *
+ * Method: Wittmer, Badger, Sundar, Bui-Thanh, "An Autoencoder Compression
+ * Approach for Accelerating Large-scale Inverse Problems" (arXiv 2304.04781).
+ *   - forward model: Sec. 2, Eq. (model) with density 1: dv/dt = grad(c^2 e) + b,
+ *     de/dt = div v, zero initial state, traction-free top surface;
+ *   - parameter-to-observable map F = B A, B samples the vertical velocity at
+ *     receivers (Sec. 2);
+ *   - misfit J = 1/2 ||F(c) - d||^2 weighted by the noise covariance sigma^2 I
+ *     (Sec. 2, MAP objective), time quadrature dt * sum over steps 1..T;
+ *   - gradient by the adjoint method and Hv by incremental forward +
+ *     incremental adjoint solves (Sec. 1 and Sec. 4); the adjoint is the
+ *     exact transpose of the discrete forward map;
+ *   - every forward state is stored compressed by a dense autoencoder and
+ *     decompressed in the time-reversed solves (Sec. 3, 3.1, 3.3); states
+ *     are normalised per vector by r = max(max - min, beta) (Sec. 3.3.1).
+ *
+ * Discretisation: cells (k, j, i) with k the depth index (k = 0 at the free
+ * surface), x fastest. e at cell centres; v_z[k] on the face between cells
+ * k-1 and k (v_y, v_x likewise). One step n -> n+1:
+ *     v_a <- S_va (v_a + dt G_a(c^2 e) + dt b_a^n),   e <- S_e (e + dt D v),
+ * G_a q[i] = (q[i]-q[i-1])/dx with q[-1] = 0; D v[i] = sum_a (v_a[i+1]-v_a[i])/dx
+ * with v_a[n_a] = 0; S = exp(-dt * sum of absorbing profiles) (quadratic
+ * profile over `sponge` cells on the bottom and the four sides, strength
+ * 3 c_ref ln(1e3) / (2 sponge dx)); p^{n+1}_r = v_z at receiver face r.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless their name starts with h_ (host).
+ *     The caller owns all argument buffers; the library never frees them.
+ *   - State arrays are float32 [S][4][nz][ny][nx], field order (e, v_z, v_y, v_x),
+ *     S = number of sources (one wavefield per source).
+ *   - Traces, observations and residuals are float32 [S][T][R]; index n holds
+ *     time level n+1.
+ *   - Work is enqueued on the context's (or the given) HIP stream. Calls that
+ *     return a host scalar (h_misfit, h_loss) synchronise that stream.
+ *   - Return value: WV_OK (0) or WV_OK_FALLBACK (1) on success, a negative
+ *     WV_E* code on failure; wv_last_error() then describes it (thread-local
+ *     message). No C++ exception crosses this interface.
+ *   - A wv_ctx is bound to one device and one stream and is not thread-safe.
+ */
+#ifndef WAVECOMP_H
+#define WAVECOMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WV_OK            0
+#define WV_OK_FALLBACK   1   /* compressed result rejected by the accuracy guard;
+                                checkpointed result returned instead */
+#define WV_EINVAL      (-1)  /* bad argument (null pointer, size, NaN/negative speed) */
+#define WV_ENOMEM      (-2)  /* device allocation failed or exceeds the memory budget */
+#define WV_EDEVICE     (-3)  /* a HIP runtime call failed */
+#define WV_ESTATE      (-4)  /* call order violated (e.g. hessvec without a matching forward) */
+#define WV_EUNSTABLE   (-5)  /* c_max dt / dx >= 1/sqrt(dims): leapfrog unstable */
+#define WV_ESHAPE      (-6)  /* grid not divisible into 8^3 patches for autoencoder storage */
+
+/* Storage of the forward history consumed by the reverse-time solves. */
+#define WV_STORE_NONE        0  /* forward only; adjoint calls fail with WV_ESTATE */
+#define WV_STORE_FULL        1  /* every e^n, n = 1..T-1, in float32 (small problems) */
+#define WV_STORE_CHECKPOINT  2  /* optimal binomial checkpointing ("revolve") with
+                                   n_checkpoints state slots, the zero initial
+                                   state counted as one (Sec. 1 checkpointing) */
+#define WV_STORE_AE_BF16     3  /* autoencoder latents in bfloat16 (Sec. 3.1 space
+                                   compression, 8^3-cell x 4-field patches) */
+#define WV_STORE_AE_FP8      4  /* autoencoder latents in OCP FP8 E4M3FN with one
+                                   float32 scale per patch */
+
+/* Latent formats of ae_encode / ae_decode. */
+#define AE_LATENT_BF16  0
+#define AE_LATENT_FP8   1
+
+/* Fallback policy of wv_set_storage. */
+#define WV_FALLBACK_NONE        0  /* report guard failures only through the guard error */
+#define WV_FALLBACK_CHECKPOINT  1  /* recompute with checkpointing when the guard trips */
+
+typedef struct wv_grid {
+    int32_t nz, ny, nx;   /* cells; ny == 1 selects the 2D (z, x) mode (no y terms) */
+    double dx;            /* cell size [m] */
+    double dt;            /* time step [s] */
+    int32_t nt;           /* number of time steps T (states 1..T, traces 1..T) */
+    int32_t sponge;       /* absorbing layer width in cells (0 = none) */
+    double c_ref;         /* speed setting the absorbing strength (e.g. max of the
+                             true model); fixed so the layer does not depend on c */
+    int32_t nsrc;         /* S: sources = independent wavefields (>= 1) */
+    int32_t nrec;         /* R: receivers (>= 0) */
+} wv_grid;
+
+typedef struct wv_ctx wv_ctx;  /* opaque: grid, stream, history store, work buffers */
+typedef struct ae_net ae_net;  /* opaque: autoencoder weights, Adam moments, scales */
+
+typedef struct ae_train_cfg {
+    int32_t epochs;        /* passes over the samples */
+    int32_t batch;         /* samples per Adam step; a last partial batch is dropped */
+    double lr;             /* initial learning rate */
+    int32_t decay_every;   /* the rate is multiplied by decay_factor every this many epochs */
+    double decay_factor;
+    double beta1, beta2, eps;  /* Adam constants */
+} ae_train_cfg;
+
+/* ---- context --------------------------------------------------------------------- */
+
+/* Create a solver context on the current device. h_src: [nsrc][3] (k, j, i) of
+ * the v_z face carrying each source's vertical point force; h_rec: [nrec][3]
+ * (k, j, i) of the sampled v_z faces (shared by all sources). stream: a
+ * hipStream_t (NULL = default stream). Fails with WV_EINVAL for indices outside
+ * the grid, WV_ENOMEM when work buffers cannot be allocated. */
+int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec,
+              void* stream, wv_ctx** out);
+
+/* Free every buffer the context owns. Safe on NULL. */
+int wv_destroy(wv_ctx* ctx);
+
+/* Choose how wave_forward keeps the history (WV_STORE_*). n_checkpoints is used
+ * by WV_STORE_CHECKPOINT and by the fallback; ae must be non-NULL for the AE
+ * modes (the context keeps a reference; the net must outlive it).
+ * mem_budget_bytes > 0 caps the history allocation (WV_ENOMEM beyond it).
+ * guard_tol > 0 enables the accuracy guard of the AE modes: after each forward
+ * solve the last stored state is decoded and compared with the true state;
+ * a relative L2 error above guard_tol marks the store degraded, and with
+ * fallback_policy WV_FALLBACK_CHECKPOINT gradient/hessvec then recompute with
+ * checkpointing and return WV_OK_FALLBACK. Allocation happens here. */
+int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
+                   int64_t mem_budget_bytes, double guard_tol, int fallback_policy);
+
+/* Bytes of history storage the current mode holds (after wv_set_storage). */
+int wv_storage_bytes(const wv_ctx* ctx, int64_t* h_bytes);
+
+/* ---- wave solves (paper Sec. 2; Sec. 1 and 4 for the adjoint solves) ------------- */
+
+/* Forward solve from the zero state over T steps at wave speed c [nz*ny*nx] for
+ * every source; wavelet [S][T] is the force density b^n (already divided by
+ * dx^dims). Writes traces [S][T][R]; final_state [S][4][N] if non-NULL. Fills the
+ * history store of the current mode (compressing each state for the AE modes).
+ * capture (if non-NULL) receives raw float32 states [ncap][S][4][N] of steps
+ * n = capture_every, 2 capture_every, ... (ncap = floor((T-1)/capture_every)):
+ * the training snapshots of the learned compressor. */
+int wave_forward(wv_ctx* ctx, const float* c, const float* wavelet, float* traces,
+                 float* final_state, float* capture, int32_t capture_every);
+
+/* Reverse-time adjoint solve consuming the store of the last wave_forward at the
+ * same c: returns g = J_F^T w, i.e. g = -2 dt c * sum_n e^n * q^n for the adjoint
+ * source w = residual [S][T][R] (pass dt/sigma^2 (p - d) for the misfit
+ * gradient). g is summed over sources. WV_ESTATE if no store is available
+ * (checkpoint slots are consumed by one reverse sweep). */
+int wave_adjoint(wv_ctx* ctx, const float* c, const float* residual, float* g);
+
+/* Misfit gradient: forward solve (filling the store), J = dt/(2 sigma^2)
+ * sum (p - d)^2 in float64, residual dt/sigma^2 (p - d), adjoint solve.
+ * d_obs [S][T][R]; g [N]; *h_misfit receives J. */
+int gradient(wv_ctx* ctx, const float* c, const float* wavelet, const float* d_obs,
+             double sigma, float* g, double* h_misfit);
+
+/* Gauss-Newton Hessian-vector product Hdc = J_F^T (dt/sigma^2) J_F dc at the c of
+ * the last gradient() (sigma taken from that call): incremental forward with
+ * source dm e^n (dm = 2 c dc) and incremental adjoint, both reading the forward
+ * history (decompressed again for the AE modes: compress once, decompress in
+ * every Hv). gauss_newton must be 1 (the full-Newton term is not provided).
+ * WV_ESTATE when c differs from the last gradient's c or no store exists. */
+int hessvec(wv_ctx* ctx, const float* c, const float* dc, float* Hdc, int gauss_newton);
+
+/* Incremental forward only: dp [S][T][R] = J_F dc (uses the stored history). */
+int wave_inc_forward(wv_ctx* ctx, const float* c, const float* dc, float* dtraces);
+
+/* ---- autoencoder (paper Sec. 3.3 architecture, Eq. (single_layer); Sec. 3.3.1) --- */
+
+/* Create a dense autoencoder in_dim -> hidden -> latent -> hidden -> in_dim with
+ * GELU on the hidden layers (in_dim must be 2048 = 4 fields x 8^3, hidden a
+ * multiple of 64, latent a multiple of 16). h_init: host float32 parameters in
+ * the order W1 [in][hid], b1 [hid], W2 [hid][lat], b2 [lat], W3 [lat][hid],
+ * b3 [hid], W4 [hid][in], b4 [in] (input-major weights, y W + b). The library
+ * keeps float32 master weights, bfloat16 copies and Adam moments on the device.
+ * h_beta: per-field normalisation floors beta_f [4] (NULL = 1e-7 each). */
+int ae_create(int32_t in_dim, int32_t hidden, int32_t latent, const float* h_init,
+              const double* h_beta, ae_net** out);
+void ae_destroy(ae_net* net);
+
+/* Number of float32 parameters (layout as h_init). */
+int ae_param_count(const ae_net* net, int64_t* h_count);
+/* Copy the float32 master parameters to / from host memory (layout as h_init). */
+int ae_get_params(const ae_net* net, float* h_out);
+int ae_set_params(ae_net* net, const float* h_in);
+/* Set / get the per-field floors beta_f. */
+int ae_set_beta(ae_net* net, const double* h_beta);
+int ae_get_beta(const ae_net* net, double* h_beta);
+/* Set beta_f = rel * max |x_f| over nstates raw states [nstates][4][N]
+ * (field-wise maxima; the paper's beta = 1e-7 taken relative to each
+ * field's scale). */
+int ae_fit_beta(ae_net* net, const wv_grid* grid, const float* states, int64_t nstates,
+                double rel, void* stream);
+/* Save / load weights, biases, Adam moments, step count and floors (binary file). */
+int ae_save(const ae_net* net, const char* path);
+int ae_load(const char* path, ae_net** out);
+
+/* Normalise one state [4][N] into the network input layout: y [P][2048] bfloat16
+ * (bit patterns, patch p = (pz*Py + py)*Px + px, entry f*512 + lz*64 + ly*8 + lx),
+ * meta [P][4][2] = (min, r) per patch and field with r = max(max - min, beta_f). */
+int ae_normalize(const ae_net* net, const wv_grid* grid, const float* state, uint16_t* y,
+                 float* meta, void* stream);
+
+/* Compress one state [4][N]: per-patch normalisation, encoder, latent store.
+ * latent: [P][latent] bfloat16 (AE_LATENT_BF16) or e4m3 bytes (AE_LATENT_FP8);
+ * qscale [P] float32 scales (FP8 only, else may be NULL); meta [P][4][2]. */
+int ae_encode(const ae_net* net, const wv_grid* grid, const float* state, int latent_fmt,
+              void* latent, float* meta, float* qscale, void* stream);
+
+/* Decompress into state [4][N]: decoder, de-normalisation x = min + r y. Only
+ * the fields whose bit is set in field_mask (bit f = field f) are computed and
+ * written (the gradient needs only e, mask 1). */
+int ae_decode(const ae_net* net, const wv_grid* grid, const void* latent, const float* meta,
+              const float* qscale, int latent_fmt, uint32_t field_mask, float* state,
+              void* stream);
+
+/* Train on nsamples normalised vectors y [nsamples][2048] (bfloat16 bits, e.g.
+ * from ae_normalize) by minimising the mean squared reconstruction error with
+ * Adam (Sec. 3.3.1 loss, Table 2 schedule). perm: device int32
+ * [epochs][nsamples] visiting order per epoch (NULL = in order).
+ * h_loss_per_epoch (host, may be NULL) receives the mean batch loss per epoch. */
+int ae_train(ae_net* net, const uint16_t* y, int64_t nsamples, const ae_train_cfg* h_cfg,
+             const int32_t* perm, float* h_loss_per_epoch, void* stream);
+
+/* One training step on a batch given explicitly (rows idx[0..batch) of y) and,
+ * if h_grads is non-NULL, the float32 parameter gradients of that step (layout
+ * as h_init) copied to the host before the Adam update. Returns the batch loss. */
+int ae_train_step(ae_net* net, const uint16_t* y, const int32_t* idx, int32_t batch,
+                  double lr, const ae_train_cfg* h_cfg, float* h_grads, double* h_loss,
+                  void* stream);
+
+/* ---- host-only helpers ---------------------------------------------------------- */
+
+/* Optimal checkpoint schedule for reversing nsteps steps with nslots slots (the
+ * slot of the zero initial state included). Actions are int32 triples
+ * (kind, a, b): kind 0 = advance from state a by b steps, 1 = store the current
+ * state (step a) in slot b, 2 = restore slot b (step a), 3 = deliver state a to
+ * the adjoint. Writes at most cap triples to h_actions and the count to
+ * *h_count; *h_forward_steps = number of step evaluations. Runs on the host. */
+int wv_revolve_schedule(int32_t nsteps, int32_t nslots, int32_t* h_actions, int64_t cap,
+                        int64_t* h_count, int64_t* h_forward_steps);
+
+/* Diagnostics of the last solve: step evaluations of the forward model (sweep
+ * plus checkpoint recomputation), relative L2 error measured by the accuracy
+ * guard (-1 if not run) and whether it tripped. Any pointer may be NULL. */
+int wv_stats(const wv_ctx* ctx, int64_t* h_forward_steps, double* h_guard_err, int* h_degraded);
+
+const char* wv_last_error(void);
+const char* wv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WAVECOMP_H */

@@ -1,0 +1,29 @@
+// Internal interface between the solver context and the autoencoder code.
+#pragma once
+
+#include "wv_internal.h"
+
+namespace wv {
+
+struct PatchGrid {
+    int nz, ny, nx;
+    long long P;  // patches = (nz/8)(ny/8)(nx/8)
+};
+
+inline PatchGrid patch_grid(int nz, int ny, int nx)
+{
+    return PatchGrid{nz, ny, nx, (long long)(nz / 8) * (ny / 8) * (nx / 8)};
+}
+
+int ae_latent_dim(const ae_net* net);
+// bytes per patch of the latent store (latent codes only)
+long long ae_latent_bytes_per_patch(const ae_net* net, int fmt);
+
+// Compress one state [4][N] into latent [P][L] (+ meta [P][4][2], qscale [P] for FP8).
+void ae_encode_state(const ae_net* net, const PatchGrid& pg, const float* state, int fmt,
+                     void* latent, float* meta, float* qscale, hipStream_t st);
+// Decompress the fields in field_mask into state [4][N].
+void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
+                     const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st);
+
+}  // namespace wv

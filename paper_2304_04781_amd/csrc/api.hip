@@ -1,0 +1,843 @@
+// Solver context, history storage policies, time loops and the C entry points
+// of wavecomp.h (forward, adjoint, gradient, incremental forward, Hv).
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ae_internal.h"
+#include "wv_internal.h"
+
+namespace wv {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+template <class F>
+int guarded(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return WV_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return WV_EDEVICE;
+    }
+}
+
+template <class T>
+T* dev_alloc(size_t count)
+{
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        throw Error{WV_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    if (e != hipSuccess) throw Error{WV_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    return static_cast<T*>(p);
+}
+
+template <class T>
+void dev_free(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace wv
+
+using namespace wv;
+
+struct wv_ctx {
+    wv_grid g{};
+    bool has_y = true;
+    long long N = 0;
+    int S = 1, T = 1, R = 0;
+    hipStream_t st = nullptr;
+
+    float* tab = nullptr;  // wzc wzf wyc wyf wxc wxf
+    float *wzc = nullptr, *wzf = nullptr, *wyc = nullptr, *wyf = nullptr, *wxc = nullptr, *wxf = nullptr;
+    Tiling tl;
+
+    float* m = nullptr;
+    float* c_last = nullptr;
+    float* wavelet = nullptr;
+    float* work[2] = {nullptr, nullptr};
+    float* adj[2] = {nullptr, nullptr};
+    float* incb[2] = {nullptr, nullptr};
+    float* acc = nullptr;
+    float* ebuf = nullptr;
+    float* dm = nullptr;
+    float* traces = nullptr;
+    float* resid = nullptr;
+    float* dtr = nullptr;
+    double* partial = nullptr;
+    double* dscal = nullptr;
+    int* dflag = nullptr;
+    int nblk_red = 1024;
+
+    // history store
+    int mode = WV_STORE_NONE;
+    int nslots = 0;
+    ae_net* ae = nullptr;
+    int64_t budget = 0;
+    double guard_tol = 0.0;
+    int fallback = WV_FALLBACK_NONE;
+    float* slots = nullptr;      // checkpoint slots 1..nslots-1
+    float* ehist = nullptr;      // full storage of e^1..e^{T-1}
+    uint8_t* lat = nullptr;      // AE latents [T-1][S][P][L]
+    float* meta = nullptr;       // [T-1][S][P][4][2]
+    float* qs = nullptr;         // [T-1][S][P]
+    long long P = 0;
+    long long lat_bytes = 0;     // per patch
+    int64_t store_bytes = 0;
+
+    bool store_ok = false;       // the store matches c_last
+    bool degraded = false;       // accuracy guard tripped
+    double guard_err = -1.0;
+    bool have_grad = false;
+    double sigma = 1.0;
+    long long last_fwd_steps = 0;
+
+    long long state_floats() const { return 4LL * N * S; }
+    float* slot_ptr(int b) const { return slots + (long long)(b - 1) * state_floats(); }
+};
+
+namespace {
+
+double axis_sigma(double pos, int n, bool low_absorbs, int ns, double smax)
+{
+    double s = 0.0;
+    if (ns <= 0) return 0.0;
+    if (low_absorbs && pos < ns) s += smax * std::pow((ns - pos) / ns, 2);
+    const double w = n - pos;
+    if (w < ns) s += smax * std::pow((ns - w) / ns, 2);
+    return s;
+}
+
+void build_tables(wv_ctx* c)
+{
+    const wv_grid& g = c->g;
+    const int ns = g.sponge;
+    const double smax = ns > 0 ? 3.0 * g.c_ref * std::log(1000.0) / (2.0 * ns * g.dx) : 0.0;
+    const int nz = g.nz, ny = g.ny, nx = g.nx;
+    std::vector<float> h(2 * (size_t)(nz + ny + nx));
+    float* wzc = h.data();
+    float* wzf = wzc + nz;
+    float* wyc = wzf + nz;
+    float* wyf = wyc + ny;
+    float* wxc = wyf + ny;
+    float* wxf = wxc + nx;
+    for (int k = 0; k < nz; ++k) {
+        wzc[k] = (float)std::exp(-g.dt * axis_sigma(k + 0.5, nz, false, ns, smax));
+        wzf[k] = (float)std::exp(-g.dt * axis_sigma(k, nz, false, ns, smax));
+    }
+    for (int j = 0; j < ny; ++j) {
+        wyc[j] = c->has_y ? (float)std::exp(-g.dt * axis_sigma(j + 0.5, ny, true, ns, smax)) : 1.0f;
+        wyf[j] = c->has_y ? (float)std::exp(-g.dt * axis_sigma(j, ny, true, ns, smax)) : 1.0f;
+    }
+    for (int i = 0; i < nx; ++i) {
+        wxc[i] = (float)std::exp(-g.dt * axis_sigma(i + 0.5, nx, true, ns, smax));
+        wxf[i] = (float)std::exp(-g.dt * axis_sigma(i, nx, true, ns, smax));
+    }
+    c->tab = dev_alloc<float>(h.size());
+    WV_HIP(hipMemcpy(c->tab, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->wzc = c->tab;
+    c->wzf = c->wzc + nz;
+    c->wyc = c->wzf + nz;
+    c->wyf = c->wyc + ny;
+    c->wxc = c->wyf + ny;
+    c->wxf = c->wxc + nx;
+}
+
+StepArgs base_args(const wv_ctx* c)
+{
+    StepArgs a{};
+    a.nz = c->g.nz;
+    a.ny = c->g.ny;
+    a.nx = c->g.nx;
+    a.N = c->N;
+    a.sstride = 4 * c->N;
+    a.dtdx = (float)(c->g.dt / c->g.dx);
+    a.dt = (float)c->g.dt;
+    a.wzc = c->wzc; a.wzf = c->wzf; a.wyc = c->wyc; a.wyf = c->wyf; a.wxc = c->wxc; a.wxf = c->wxf;
+    a.m = c->m;
+    a.src_ptr = c->tl.src_ptr;
+    a.src_ent = c->tl.src_ent;
+    a.wavelet = c->wavelet;
+    a.nt = c->T;
+    a.rec_ptr = c->tl.rec_ptr;
+    a.rec_ent = c->tl.rec_ent;
+    a.nrec = c->R;
+    a.tiles_x = c->tl.tiles_x;
+    a.tiles_y = c->tl.tiles_y;
+    a.chunks_z = c->tl.chunks_z;
+    a.kc = c->tl.kc;
+    return a;
+}
+
+// one forward step n: state in -> out; traces (nullptr: not recorded)
+void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces)
+{
+    StepArgs a = base_args(c);
+    a.in = in;
+    a.out = out;
+    a.step = n;
+    a.tidx = n;
+    a.traces = traces;
+    if (!traces) a.nrec = 0;
+    launch_step(MODE_FWD, c->has_y, a, c->S, c->st);
+}
+
+// adjoint launch k: (mu^{k+2}, eta^{k+1}) -> (mu^{k+1}, eta^k), consuming e^k
+void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid, const float* ek,
+              long long ekstride)
+{
+    StepArgs a = base_args(c);
+    a.in = in;
+    a.out = out;
+    a.tidx = k;
+    a.resid = resid;
+    a.ek = ek;
+    a.ekstride = ekstride;
+    a.acc = c->acc;
+    launch_step(MODE_ADJ, c->has_y, a, c->S, c->st);
+}
+
+void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, long long enstride,
+              float* dtraces)
+{
+    StepArgs a = base_args(c);
+    a.in = in;
+    a.out = out;
+    a.tidx = n;
+    a.step = n;
+    a.traces = dtraces;
+    a.dm = c->dm;
+    a.en = en;
+    a.enstride = enstride;
+    launch_step(MODE_INC, c->has_y, a, c->S, c->st);
+}
+
+void ensure_adj(wv_ctx* c)
+{
+    if (!c->adj[0]) {
+        c->adj[0] = dev_alloc<float>(c->state_floats());
+        c->adj[1] = dev_alloc<float>(c->state_floats());
+        c->acc = dev_alloc<float>(2 * c->N * c->S);
+        c->ebuf = dev_alloc<float>(c->N * c->S);
+    }
+}
+
+void ensure_inc(wv_ctx* c)
+{
+    if (!c->incb[0]) {
+        c->incb[0] = dev_alloc<float>(c->state_floats());
+        c->incb[1] = dev_alloc<float>(c->state_floats());
+        c->dm = dev_alloc<float>(c->N);
+    }
+}
+
+void free_store(wv_ctx* c)
+{
+    dev_free(c->slots);
+    dev_free(c->ehist);
+    dev_free(c->lat);
+    dev_free(c->meta);
+    dev_free(c->qs);
+    c->store_bytes = 0;
+    c->store_ok = false;
+}
+
+void alloc_slots(wv_ctx* c, int nslots)
+{
+    if (nslots < 1) throw Error{WV_EINVAL, "checkpointing needs at least one slot"};
+    const long long bytes = (long long)(nslots - 1) * c->state_floats() * 4;
+    if (c->budget > 0 && bytes > c->budget) throw Error{WV_ENOMEM, "checkpoint slots exceed the memory budget"};
+    dev_free(c->slots);
+    c->nslots = nslots;
+    if (nslots > 1) c->slots = dev_alloc<float>((size_t)(nslots - 1) * c->state_floats());
+}
+
+// check c: positive, finite and stable for leapfrog
+void check_speed(wv_ctx* c, const float* cdev)
+{
+    launch_range(cdev, c->N, c->partial, c->nblk_red, c->dscal, c->st);
+    double h[3];
+    WV_HIP(hipMemcpyAsync(h, c->dscal, sizeof(h), hipMemcpyDeviceToHost, c->st));
+    WV_HIP(hipStreamSynchronize(c->st));
+    WV_REQUIRE(h[2] == 0.0, WV_EINVAL, "wave speed contains NaN");
+    WV_REQUIRE(h[0] > 0.0, WV_EINVAL, "wave speed must be positive");
+    const double dims = c->has_y ? 3.0 : 2.0;
+    const double cfl = h[1] * c->g.dt / c->g.dx;
+    WV_REQUIRE(cfl < 1.0 / std::sqrt(dims), WV_EUNSTABLE,
+               "c_max dt/dx = " + std::to_string(cfl) + " exceeds the leapfrog limit 1/sqrt(dims)");
+}
+
+void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
+{
+    check_speed(c, cdev);
+    launch_square(cdev, c->m, c->N, c->st);
+    launch_copy(c->c_last, cdev, c->N, c->st);
+    if (wavelet)
+        WV_HIP(hipMemcpyAsync(c->wavelet, wavelet, sizeof(float) * c->S * c->T, hipMemcpyDeviceToDevice, c->st));
+}
+
+bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
+int ae_fmt(int mode) { return mode == WV_STORE_AE_FP8 ? AE_LATENT_FP8 : AE_LATENT_BF16; }
+
+uint8_t* lat_slot(wv_ctx* c, int idx, int s)
+{
+    return c->lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
+}
+float* meta_slot(wv_ctx* c, int idx, int s) { return c->meta + ((long long)idx * c->S + s) * c->P * 8; }
+float* qs_slot(wv_ctx* c, int idx, int s)
+{
+    return c->qs ? c->qs + ((long long)idx * c->S + s) * c->P : nullptr;
+}
+
+// store x_n (n = 1..T-1) of every source
+void store_state(wv_ctx* c, int n, const float* state)
+{
+    if (n < 1 || n > c->T - 1) return;
+    if (c->mode == WV_STORE_FULL) {
+        for (int s = 0; s < c->S; ++s)
+            WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
+                                  sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
+    } else if (is_ae(c->mode)) {
+        const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+        for (int s = 0; s < c->S; ++s)
+            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
+                            meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
+    }
+}
+
+// e^n of every source from the FULL or AE store: pointer + per-source stride
+const float* load_e(wv_ctx* c, int n, long long* stride)
+{
+    *stride = c->N;
+    if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    for (int s = 0; s < c->S; ++s)
+        ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
+                        ae_fmt(c->mode), 1u, c->ebuf + s * c->N, c->st);
+    return c->ebuf;
+}
+
+float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->work[1] : c->work[0]; }
+
+// Forward sweep over T steps from the zero state. Records traces, fills the FULL/AE
+// store, writes checkpoint snapshots (snap[n] = slot of x_n or 0), captures.
+// Returns the buffer holding x_{T-1}; *last receives the one holding x_T.
+float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, float* capture, int every,
+                     float** last)
+{
+    launch_fill(c->work[0], c->state_floats(), 0.f, c->st);
+    float* cur = c->work[0];
+    float* prev = cur;
+    const int ncap = (capture && every > 0) ? (c->T - 1) / every : 0;
+    for (int n = 0; n < c->T; ++n) {
+        float* out = (snap && (*snap)[n + 1] > 0) ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
+        fwd_step(c, cur, out, n, traces);
+        if (n + 1 <= c->T - 1) store_state(c, n + 1, out);
+        if (ncap > 0 && (n + 1) % every == 0 && (n + 1) / every <= ncap)
+            WV_HIP(hipMemcpyAsync(capture + (long long)((n + 1) / every - 1) * c->state_floats(), out,
+                                  sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice, c->st));
+        prev = cur;
+        cur = out;
+    }
+    c->last_fwd_steps = c->T;
+    if (last) *last = cur;
+    return prev;
+}
+
+// accuracy guard: decode the last stored state and compare its e field
+void run_guard(wv_ctx* c, const float* x_tm1)
+{
+    c->degraded = false;
+    c->guard_err = -1.0;
+    if (!is_ae(c->mode) || c->guard_tol <= 0.0 || c->T < 2) return;
+    long long stride;
+    const float* e = load_e(c, c->T - 1, &stride);
+    double worst = 0.0;
+    for (int s = 0; s < c->S; ++s) {
+        launch_rel_err(e + s * stride, x_tm1 + s * 4 * c->N, c->N, c->partial, c->nblk_red, c->dscal, c->st);
+        double h;
+        WV_HIP(hipMemcpyAsync(&h, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+        WV_HIP(hipStreamSynchronize(c->st));
+        worst = std::max(worst, h);
+    }
+    c->guard_err = worst;
+    c->degraded = !(worst <= c->guard_tol);
+}
+
+// snapshot map of the initial sweep of a schedule: snap[n] = slot holding x_n
+std::vector<int> sweep_snapshots(const std::vector<RevAction>& acts, int T, size_t* first_deliver)
+{
+    std::vector<int> snap(T + 1, 0);
+    size_t q = 0;
+    for (; q < acts.size(); ++q) {
+        if (acts[q].kind == 3) break;
+        if (acts[q].kind == 1) snap[acts[q].a] = acts[q].b;
+    }
+    *first_deliver = q;
+    return snap;
+}
+
+// Reverse sweep. e^k comes from the FULL/AE store, or (checkpointing) from the
+// action list starting at `first` with x_{T-1} in `xtm1`.
+void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* acts, size_t first,
+                   float* xtm1)
+{
+    ensure_adj(c);
+    launch_fill(c->adj[0], c->state_floats(), 0.f, c->st);
+    launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
+    float* ain = c->adj[0];
+    float* aout = c->adj[1];
+    auto adjoint_k = [&](int k, const float* ek, long long stride) {
+        adj_step(c, ain, aout, k, resid, ek, stride);
+        std::swap(ain, aout);
+    };
+    if (!acts) {
+        for (int k = c->T - 1; k >= 1; --k) {
+            long long stride;
+            const float* e = load_e(c, k, &stride);
+            adjoint_k(k, e, stride);
+        }
+        return;
+    }
+    float* cur = xtm1;
+    long long extra = 0;
+    for (size_t q = first; q < acts->size(); ++q) {
+        const RevAction& A = (*acts)[q];
+        if (A.kind == 3) {
+            if (A.a >= 1) adjoint_k(A.a, cur, 4 * c->N);
+        } else if (A.kind == 2) {
+            if (A.b == 0) {
+                launch_fill(c->work[0], c->state_floats(), 0.f, c->st);
+                cur = c->work[0];
+            } else {
+                cur = c->slot_ptr(A.b);
+            }
+        } else if (A.kind == 0) {
+            const bool to_slot = q + 1 < acts->size() && (*acts)[q + 1].kind == 1;
+            for (int t = 0; t < A.b; ++t) {
+                float* out = (to_slot && t == A.b - 1) ? c->slot_ptr((*acts)[q + 1].b) : other_work(c, cur);
+                fwd_step(c, cur, out, A.a + t, nullptr);
+                cur = out;
+            }
+            extra += A.b;
+        }
+    }
+    c->last_fwd_steps += extra;
+}
+
+void finish_grad(wv_ctx* c, const float* cdev, float* g)
+{
+    launch_grad_finish(cdev, c->acc, c->N, c->S, -2.0 * c->g.dt / c->g.dx, g, c->st);
+}
+
+// gradient with checkpointing regardless of the store mode (also the fallback)
+double gradient_checkpoint(wv_ctx* c, const float* cdev, const float* d_obs, double sigma, float* g,
+                           int nslots)
+{
+    if (!c->slots || c->nslots != nslots) alloc_slots(c, nslots);
+    long long fsteps = 0;
+    const auto acts = revolve_schedule(c->T, c->nslots, &fsteps);
+    size_t first = 0;
+    const auto snap = sweep_snapshots(acts, c->T, &first);
+    float* last = nullptr;
+    const int saved = c->mode;
+    c->mode = WV_STORE_CHECKPOINT;
+    float* xtm1 = forward_sweep(c, c->traces, &snap, nullptr, 0, &last);
+    c->mode = saved;
+    const long long n = (long long)c->S * c->T * c->R;
+    launch_misfit(c->traces, d_obs, c->resid, n, c->g.dt / (sigma * sigma), c->g.dt / (2 * sigma * sigma),
+                  c->partial, c->nblk_red, c->dscal, c->st);
+    double J;
+    WV_HIP(hipMemcpyAsync(&J, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    reverse_sweep(c, c->resid, &acts, first, xtm1);
+    finish_grad(c, cdev, g);
+    WV_HIP(hipStreamSynchronize(c->st));
+    return J;
+}
+
+}  // namespace
+
+// ====================================================================================
+extern "C" {
+
+int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, void* stream, wv_ctx** out)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(grid && out, WV_EINVAL, "null argument");
+        const wv_grid g = *grid;
+        WV_REQUIRE(g.nz >= 2 && g.ny >= 1 && g.nx >= 2, WV_EINVAL, "grid too small");
+        WV_REQUIRE(g.dx > 0 && g.dt > 0 && g.nt >= 1, WV_EINVAL, "dx, dt must be > 0 and nt >= 1");
+        WV_REQUIRE(g.sponge >= 0 && g.nsrc >= 1 && g.nrec >= 0, WV_EINVAL, "bad sponge/nsrc/nrec");
+        WV_REQUIRE(g.sponge == 0 || g.c_ref > 0, WV_EINVAL, "c_ref must be > 0 with an absorbing layer");
+        WV_REQUIRE(h_src && (g.nrec == 0 || h_rec), WV_EINVAL, "null source/receiver list");
+        std::unique_ptr<wv_ctx> c(new wv_ctx());
+        c->g = g;
+        c->has_y = g.ny > 1;
+        c->N = (long long)g.nz * g.ny * g.nx;
+        c->S = g.nsrc;
+        c->T = g.nt;
+        c->R = g.nrec;
+        c->st = (hipStream_t)stream;
+        std::vector<int> src(h_src, h_src + 3 * g.nsrc), rec;
+        if (g.nrec) rec.assign(h_rec, h_rec + 3 * g.nrec);
+        auto check_pts = [&](const std::vector<int>& v, const char* what) {
+            for (size_t q = 0; q < v.size(); q += 3) {
+                WV_REQUIRE(v[q] >= 0 && v[q] < g.nz && v[q + 1] >= 0 && v[q + 1] < g.ny && v[q + 2] >= 0 &&
+                               v[q + 2] < g.nx,
+                           WV_EINVAL, std::string(what) + " index outside the grid");
+            }
+        };
+        check_pts(src, "source");
+        check_pts(rec, "receiver");
+        build_tables(c.get());
+        c->tl = make_tiling(g.nz, g.ny, g.nx, src, rec);
+        c->m = dev_alloc<float>(c->N);
+        c->c_last = dev_alloc<float>(c->N);
+        c->wavelet = dev_alloc<float>((size_t)c->S * c->T);
+        c->work[0] = dev_alloc<float>(c->state_floats());
+        c->work[1] = dev_alloc<float>(c->state_floats());
+        const size_t ntr = (size_t)c->S * c->T * std::max(c->R, 1);
+        c->traces = dev_alloc<float>(ntr);
+        c->resid = dev_alloc<float>(ntr);
+        c->dtr = dev_alloc<float>(ntr);
+        c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
+        c->dscal = dev_alloc<double>(8);
+        c->dflag = dev_alloc<int>(1);
+        *out = c.release();
+        return WV_OK;
+    });
+}
+
+int wv_destroy(wv_ctx* c)
+{
+    if (!c) return WV_OK;
+    (void)hipStreamSynchronize(c->st);
+    free_store(c);
+    free_tiling(c->tl);
+    dev_free(c->tab);
+    for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
+                      &c->incb[0], &c->incb[1], &c->acc, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr})
+        dev_free(*p);
+    dev_free(c->partial);
+    dev_free(c->dscal);
+    dev_free(c->dflag);
+    delete c;
+    return WV_OK;
+}
+
+int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64_t mem_budget_bytes,
+                   double guard_tol, int fallback_policy)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c, WV_EINVAL, "null context");
+        WV_REQUIRE(mode >= WV_STORE_NONE && mode <= WV_STORE_AE_FP8, WV_EINVAL, "unknown storage mode");
+        WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE || fallback_policy == WV_FALLBACK_CHECKPOINT, WV_EINVAL,
+                   "unknown fallback policy");
+        WV_HIP(hipStreamSynchronize(c->st));
+        free_store(c);
+        dev_free(c->slots);
+        c->mode = mode;
+        c->budget = mem_budget_bytes;
+        c->guard_tol = guard_tol;
+        c->fallback = fallback_policy;
+        c->ae = ae;
+        c->nslots = n_checkpoints;
+        c->degraded = false;
+        c->have_grad = false;
+        const int T = c->T;
+        if (mode == WV_STORE_FULL) {
+            const long long n = (long long)std::max(T - 1, 1) * c->S * c->N;
+            WV_REQUIRE(c->budget <= 0 || n * 4 <= c->budget, WV_ENOMEM, "full history exceeds the memory budget");
+            c->ehist = dev_alloc<float>(n);
+            c->store_bytes = n * 4;
+        } else if (mode == WV_STORE_CHECKPOINT) {
+            alloc_slots(c, n_checkpoints);
+            c->store_bytes = (int64_t)(n_checkpoints - 1) * c->state_floats() * 4;
+        } else if (is_ae(mode)) {
+            WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
+            WV_REQUIRE(c->has_y && c->g.nz % 8 == 0 && c->g.ny % 8 == 0 && c->g.nx % 8 == 0, WV_ESHAPE,
+                       "autoencoder storage needs a 3D grid divisible into 8^3 patches");
+            const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+            c->P = pg.P;
+            c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
+            const long long slots = (long long)std::max(T - 1, 1) * c->S;
+            const long long bytes = slots * c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0));
+            WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
+            c->lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
+            c->meta = dev_alloc<float>(slots * c->P * 8);
+            if (mode == WV_STORE_AE_FP8) c->qs = dev_alloc<float>(slots * c->P);
+            c->store_bytes = bytes;
+            if (fallback_policy == WV_FALLBACK_CHECKPOINT)
+                WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
+        }
+        return WV_OK;
+    });
+}
+
+int wv_storage_bytes(const wv_ctx* c, int64_t* h_bytes)
+{
+    if (!c || !h_bytes) {
+        set_error("null argument");
+        return WV_EINVAL;
+    }
+    *h_bytes = c->store_bytes;
+    return WV_OK;
+}
+
+int wave_forward(wv_ctx* c, const float* cdev, const float* wavelet, float* traces, float* final_state,
+                 float* capture, int32_t capture_every)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && wavelet, WV_EINVAL, "null argument");
+        WV_REQUIRE(!capture || capture_every >= 1, WV_EINVAL, "capture_every must be >= 1");
+        prepare_model(c, cdev, wavelet);
+        c->store_ok = false;
+        c->have_grad = false;
+        float* last = nullptr;
+        float* xtm1;
+        std::vector<RevAction> acts;
+        if (c->mode == WV_STORE_CHECKPOINT) {
+            long long fs = 0;
+            acts = revolve_schedule(c->T, c->nslots, &fs);
+            size_t first = 0;
+            const auto snap = sweep_snapshots(acts, c->T, &first);
+            xtm1 = forward_sweep(c, c->traces, &snap, capture, capture_every, &last);
+        } else {
+            xtm1 = forward_sweep(c, c->traces, nullptr, capture, capture_every, &last);
+        }
+        if (traces)
+            WV_HIP(hipMemcpyAsync(traces, c->traces, sizeof(float) * c->S * c->T * c->R, hipMemcpyDeviceToDevice,
+                                  c->st));
+        if (final_state)
+            WV_HIP(hipMemcpyAsync(final_state, last, sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice,
+                                  c->st));
+        run_guard(c, xtm1);
+        c->store_ok = c->mode != WV_STORE_NONE;
+        return WV_OK;
+    });
+}
+
+int wave_adjoint(wv_ctx* c, const float* cdev, const float* residual, float* g)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && residual && g, WV_EINVAL, "null argument");
+        WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored (call wave_forward first)");
+        if (c->mode == WV_STORE_CHECKPOINT) {
+            // the snapshots of the last sweep are intact; re-run the forward to place x_{T-1}
+            long long fs = 0;
+            const auto acts = revolve_schedule(c->T, c->nslots, &fs);
+            size_t first = 0;
+            const auto snap = sweep_snapshots(acts, c->T, &first);
+            float* last = nullptr;
+            float* xtm1 = forward_sweep(c, c->dtr, &snap, nullptr, 0, &last);
+            reverse_sweep(c, residual, &acts, first, xtm1);
+            c->store_ok = false;
+        } else {
+            reverse_sweep(c, residual, nullptr, 0, nullptr);
+        }
+        finish_grad(c, cdev, g);
+        return WV_OK;
+    });
+}
+
+int gradient(wv_ctx* c, const float* cdev, const float* wavelet, const float* d_obs, double sigma, float* g,
+             double* h_misfit)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && wavelet && d_obs && g, WV_EINVAL, "null argument");
+        WV_REQUIRE(sigma > 0 && std::isfinite(sigma), WV_EINVAL, "sigma must be positive");
+        WV_REQUIRE(c->mode != WV_STORE_NONE, WV_ESTATE, "gradient needs a storage mode");
+        c->sigma = sigma;
+        int status = WV_OK;
+        double J = 0.0;
+        if (c->mode == WV_STORE_CHECKPOINT) {
+            prepare_model(c, cdev, wavelet);
+            J = gradient_checkpoint(c, cdev, d_obs, sigma, g, c->nslots);
+            c->store_ok = false;
+        } else {
+            prepare_model(c, cdev, wavelet);
+            float* last = nullptr;
+            float* xtm1 = forward_sweep(c, c->traces, nullptr, nullptr, 0, &last);
+            run_guard(c, xtm1);
+            c->store_ok = true;
+            if (c->degraded && c->fallback == WV_FALLBACK_CHECKPOINT) {
+                J = gradient_checkpoint(c, cdev, d_obs, sigma, g, std::max(c->nslots, 2));
+                status = WV_OK_FALLBACK;
+            } else {
+                const long long n = (long long)c->S * c->T * c->R;
+                launch_misfit(c->traces, d_obs, c->resid, n, c->g.dt / (sigma * sigma),
+                              c->g.dt / (2 * sigma * sigma), c->partial, c->nblk_red, c->dscal, c->st);
+                WV_HIP(hipMemcpyAsync(&J, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+                reverse_sweep(c, c->resid, nullptr, 0, nullptr);
+                finish_grad(c, cdev, g);
+                WV_HIP(hipStreamSynchronize(c->st));
+            }
+        }
+        c->have_grad = true;
+        if (h_misfit) *h_misfit = J;
+        return status;
+    });
+}
+
+namespace {
+
+// incremental forward into c->dtr; CHECKPOINT runs the companion forward and
+// places snapshots for a following reverse sweep (returns x_{T-1} there).
+float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const std::vector<int>* snap)
+{
+    ensure_inc(c);
+    ensure_adj(c);
+    launch_dm(cdev, dc, c->dm, c->N, c->st);
+    launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
+    launch_fill(c->ebuf, c->N * c->S, 0.f, c->st);
+    float* din = c->incb[0];
+    float* dout = c->incb[1];
+    const bool ckpt = snap != nullptr;
+    float* cur = nullptr;
+    float* prev = nullptr;
+    if (ckpt) {
+        launch_fill(c->work[0], c->state_floats(), 0.f, c->st);
+        cur = c->work[0];
+    }
+    for (int n = 0; n < c->T; ++n) {
+        const float* en;
+        long long stride;
+        if (ckpt) {
+            en = cur;
+            stride = 4 * c->N;
+        } else if (n == 0) {
+            en = c->ebuf;  // e^0 = 0
+            stride = c->N;
+        } else {
+            en = load_e(c, n, &stride);
+        }
+        inc_step(c, din, dout, n, en, stride, c->dtr);
+        std::swap(din, dout);
+        if (ckpt) {
+            float* out = (*snap)[n + 1] > 0 ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
+            fwd_step(c, cur, out, n, nullptr);
+            prev = cur;
+            cur = out;
+        }
+    }
+    if (ckpt) c->last_fwd_steps = c->T;
+    return prev;
+}
+
+}  // namespace
+
+int wave_inc_forward(wv_ctx* c, const float* cdev, const float* dc, float* dtraces)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && dc && dtraces, WV_EINVAL, "null argument");
+        WV_REQUIRE(c->mode == WV_STORE_FULL || is_ae(c->mode) || c->mode == WV_STORE_CHECKPOINT, WV_ESTATE,
+                   "incremental forward needs a storage mode");
+        if (c->mode == WV_STORE_CHECKPOINT) {
+            prepare_model(c, cdev, nullptr);
+            std::vector<int> snap(c->T + 1, 0);
+            inc_forward_sweep(c, cdev, dc, &snap);
+        } else {
+            WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored");
+            inc_forward_sweep(c, cdev, dc, nullptr);
+        }
+        WV_HIP(hipMemcpyAsync(dtraces, c->dtr, sizeof(float) * c->S * c->T * c->R, hipMemcpyDeviceToDevice, c->st));
+        return WV_OK;
+    });
+}
+
+int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss_newton)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && dc && Hdc, WV_EINVAL, "null argument");
+        WV_REQUIRE(gauss_newton == 1, WV_EINVAL, "only the Gauss-Newton Hessian is provided");
+        WV_REQUIRE(c->have_grad, WV_ESTATE, "hessvec needs a preceding gradient() call");
+        // the stored history must belong to this c
+        WV_HIP(hipMemsetAsync(c->dflag, 0, sizeof(int), c->st));
+        launch_compare(cdev, c->c_last, c->N, c->dflag, c->st);
+        int flag = 0;
+        WV_HIP(hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+        WV_HIP(hipStreamSynchronize(c->st));
+        WV_REQUIRE(flag == 0, WV_ESTATE, "c differs from the c of the last gradient()");
+        const double w = c->g.dt / (c->sigma * c->sigma);
+        const long long ntr = (long long)c->S * c->T * c->R;
+        int status = WV_OK;
+        const bool use_ckpt = c->mode == WV_STORE_CHECKPOINT || (c->degraded && c->fallback == WV_FALLBACK_CHECKPOINT);
+        if (use_ckpt) {
+            if (!c->slots || c->nslots < 2) alloc_slots(c, std::max(c->nslots, 2));
+            long long fs = 0;
+            const auto acts = revolve_schedule(c->T, c->nslots, &fs);
+            size_t first = 0;
+            const auto snap = sweep_snapshots(acts, c->T, &first);
+            float* xtm1 = inc_forward_sweep(c, cdev, dc, &snap);
+            launch_scale_weights(c->dtr, c->resid, ntr, w, c->st);
+            reverse_sweep(c, c->resid, &acts, first, xtm1);
+            if (c->mode != WV_STORE_CHECKPOINT) status = WV_OK_FALLBACK;
+            if (c->mode == WV_STORE_CHECKPOINT) c->store_ok = false;
+        } else {
+            WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored");
+            inc_forward_sweep(c, cdev, dc, nullptr);
+            launch_scale_weights(c->dtr, c->resid, ntr, w, c->st);
+            reverse_sweep(c, c->resid, nullptr, 0, nullptr);
+        }
+        finish_grad(c, cdev, Hdc);
+        WV_HIP(hipStreamSynchronize(c->st));
+        return status;
+    });
+}
+
+int wv_revolve_schedule(int32_t nsteps, int32_t nslots, int32_t* h_actions, int64_t cap, int64_t* h_count,
+                        int64_t* h_forward_steps)
+{
+    return guarded([&]() -> int {
+        long long fs = 0;
+        const auto acts = revolve_schedule(nsteps, nslots, &fs);
+        if (h_count) *h_count = (int64_t)acts.size();
+        if (h_forward_steps) *h_forward_steps = fs;
+        if (h_actions)
+            for (size_t q = 0; q < acts.size() && (int64_t)q < cap; ++q) {
+                h_actions[3 * q] = acts[q].kind;
+                h_actions[3 * q + 1] = acts[q].a;
+                h_actions[3 * q + 2] = acts[q].b;
+            }
+        return WV_OK;
+    });
+}
+
+// diagnostics used by tests and the benchmark
+int wv_stats(const wv_ctx* c, int64_t* h_forward_steps, double* h_guard_err, int* h_degraded)
+{
+    if (!c) {
+        set_error("null context");
+        return WV_EINVAL;
+    }
+    if (h_forward_steps) *h_forward_steps = c->last_fwd_steps;
+    if (h_guard_err) *h_guard_err = c->guard_err;
+    if (h_degraded) *h_degraded = c->degraded ? 1 : 0;
+    return WV_OK;
+}
+
+const char* wv_last_error(void) { return g_error.c_str(); }
+const char* wv_version(void) { return "wavecomp 0.1 gfx950"; }
+
+}  // extern "C"

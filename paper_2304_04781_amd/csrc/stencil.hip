@@ -1,0 +1,360 @@
+// Staggered-grid leapfrog step kernels for gfx950: forward, fused adjoint with
+// Kahan-compensated gradient accumulation, and incremental (linearised) forward.
+//
+// All three share one z-marching structure. A work-group owns a BX x BY tile of
+// the (y, x) plane and a chunk of depth levels; per level it
+//   1. builds the "potential" P on the plane tile plus a one-cell cross-shaped
+//      ring in LDS (P = c^2 e forward, c^2 de + dm e^n incremental, S_e eta
+//      adjoint), carrying the tile's own P of the next level in registers;
+//   2. updates the face fields v_y, v_x from differences of P (the +1 faces just
+//      outside the tile are recomputed by the edge threads), and v_z of the next
+//      face from the register-carried column;
+//   3. updates the cell field from the divergence of the new faces.
+// Every cell is read and written once per step (plus L2-resident halos), so a
+// step costs the algorithmic 36 B/cell forward, 56 B/cell adjoint.
+//
+// Forward (paper Sec. 2, Eq. (model), rho = 1):
+//   v_a' = S_va (v_a + dt G_a(c^2 e) + dt b_a),   e' = S_e (e + dt D v').
+// Adjoint (exact transpose of the forward step). With mu lagging eta by half a
+// step, one launch maps (mu^{k+2}, eta^{k+1}) to (mu^{k+1}, eta^k):
+//   mu_a' = S_va mu_a - dt G_a(S_e eta) + B^T r^{k+1},
+//   q = D(S_v mu'),  eta' = S_e eta - dt c^2 q,  acc += e^k q.
+// so dJ/d(c^2) = -dt sum_k e^k q^k (accumulated here without the 1/dx factor).
+// Incremental forward: the forward step with c^2 e replaced by c^2 de + dm e^n.
+
+#include "wv_internal.h"
+
+namespace wv {
+
+namespace {
+
+constexpr int NF = 4;  // fields per state: e, v_z, v_y, v_x
+
+template <int BX, int BY, int MODE, bool HAS_Y>
+__global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
+{
+    __shared__ float sP[BY + 2][BX + 2];
+    __shared__ float sWy[HAS_Y ? BY + 1 : 1][BX];
+    __shared__ float sWx[BY][BX + 1];
+
+    // ---- block -> (x tile, y tile, z chunk); spread so one XCD gets a contiguous range
+    const int nblk = a.tiles_x * a.tiles_y * a.chunks_z;
+    int b = blockIdx.x;
+    if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int txx = b % a.tiles_x;
+    const int tyy = (b / a.tiles_x) % a.tiles_y;
+    const int cz = b / (a.tiles_x * a.tiles_y);
+    const int s = blockIdx.y;
+    const int tile = tyy * a.tiles_x + txx;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int i0 = txx * BX, j0 = tyy * BY;
+    const int i = i0 + tx, j = j0 + ty;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const bool in_x = i < nx, in_y = j < ny;
+    const bool inside = in_x && in_y;
+    const int local = ty * BX + tx;
+    const int k0 = cz * a.kc;
+    const int k1 = min(nz, k0 + a.kc);
+    const long long plane = (long long)ny * nx;
+    const long long N = a.N;
+    const long long cell = inside ? (long long)j * nx + i : 0;
+
+    const float* __restrict__ inA = a.in + s * a.sstride;
+    const float* __restrict__ inVz = inA + N;
+    const float* __restrict__ inVy = inA + 2 * N;
+    const float* __restrict__ inVx = inA + 3 * N;
+    float* __restrict__ outA = a.out + s * a.sstride;
+    float* __restrict__ outVz = outA + N;
+    float* __restrict__ outVy = outA + 2 * N;
+    float* __restrict__ outVx = outA + 3 * N;
+    const float* __restrict__ mm = a.m;
+    const float* __restrict__ en = (MODE == MODE_INC) ? a.en + s * a.enstride : nullptr;
+    const float* __restrict__ ek = (MODE == MODE_ADJ) ? a.ek + s * a.ekstride : nullptr;
+    float* __restrict__ acc = (MODE == MODE_ADJ) ? a.acc + s * 2 * N : nullptr;
+    float* __restrict__ cmp = (MODE == MODE_ADJ) ? acc + N : nullptr;
+
+    // layer factors: S = wz * (wy * wx), the (y, x) product fixed per column
+    const int jc = in_y ? j : 0, ic = in_x ? i : 0;
+    const float wyx_c = a.wyc[jc] * a.wxc[ic];
+    const float wyx_vy = a.wyf[jc] * a.wxc[ic];
+    const float wyx_vx = a.wyc[jc] * a.wxf[ic];
+    const int jh = j0 + BY, ih = i0 + BX;  // the +1 faces just outside the tile
+    const bool halo_y = HAS_Y && ty == BY - 1 && in_x && jh < ny;
+    const bool halo_x = tx == BX - 1 && in_y && ih < nx;
+    const float wyx_vy_h = halo_y ? a.wyf[jh] * a.wxc[ic] : 0.f;
+    const float wyx_vx_h = halo_x ? a.wyc[jc] * a.wxf[ih] : 0.f;
+
+    // ring of P around the tile: rows j0-1, j0+BY (HAS_Y) and columns i0-1, i0+BX
+    constexpr int NRING = HAS_Y ? 2 * BX + 2 * BY : 2;
+    int rj = 0, ri = 0, rsy = 0, rsx = 0;
+    bool ring = false, ring_in = false;
+    if (tid < NRING) {
+        ring = true;
+        if (HAS_Y) {
+            if (tid < BX) { rj = j0 - 1; ri = i0 + tid; rsy = 0; rsx = tid + 1; }
+            else if (tid < 2 * BX) { rj = jh; ri = i0 + tid - BX; rsy = BY + 1; rsx = tid - BX + 1; }
+            else if (tid < 2 * BX + BY) { rj = j0 + tid - 2 * BX; ri = i0 - 1; rsy = tid - 2 * BX + 1; rsx = 0; }
+            else { rj = j0 + tid - 2 * BX - BY; ri = ih; rsy = tid - 2 * BX - BY + 1; rsx = BX + 1; }
+        } else {
+            rj = 0; ri = (tid == 0) ? i0 - 1 : ih; rsy = 1; rsx = (tid == 0) ? 0 : BX + 1;
+        }
+        ring_in = rj >= 0 && rj < ny && ri >= 0 && ri < nx;
+    }
+    const long long rcell = ring_in ? (long long)rj * nx + ri : 0;
+    const float ring_wyx = ring_in ? a.wyc[rj] * a.wxc[ri] : 0.f;
+
+    auto P_at = [&](int k, long long off, float wyx) -> float {
+        if (MODE == MODE_FWD) return mm[off] * inA[off];
+        if (MODE == MODE_INC) return mm[off] * inA[off] + a.dm[off] * en[off];
+        return (a.wzc[k] * wyx) * inA[off];
+    };
+
+    // point-list cursors (uniform across the work-group)
+    int sp = 0, se = 0, rp = 0, re = 0;
+    if (MODE == MODE_FWD) { sp = a.src_ptr[tile]; se = a.src_ptr[tile + 1]; }
+    if (a.nrec > 0) { rp = a.rec_ptr[tile]; re = a.rec_ptr[tile + 1]; }
+    int tp = rp;  // trace-recording cursor (forward / incremental)
+
+    // extra term on the v_z face kk: dt b (forward source), B^T r (adjoint)
+    auto face_inj = [&](int kk) -> float {
+        float add = 0.f;
+        if (MODE == MODE_FWD) {
+            while (sp < se && a.src_ent[sp].x < kk) ++sp;
+            for (int q = sp; q < se; ++q) {
+                const int4 e = a.src_ent[q];
+                if (e.x != kk) break;
+                if (e.y == local && e.z == s) add += a.dt * a.wavelet[(long long)s * a.nt + a.step];
+            }
+        } else if (MODE == MODE_ADJ) {
+            while (rp < re && a.rec_ent[rp].x < kk) ++rp;
+            for (int q = rp; q < re; ++q) {
+                const int4 e = a.rec_ent[q];
+                if (e.x != kk) break;
+                if (e.y == local)
+                    add += a.resid[((long long)s * a.nt + a.tidx) * a.nrec + e.z];
+            }
+        }
+        return add;
+    };
+    // new face value from old value V, difference dP and extra term
+    auto face_new = [&](float S, float V, float dP, float add) -> float {
+        if (MODE == MODE_ADJ) return S * V - a.dtdx * dP + add;
+        return S * (V + a.dtdx * dP + add);
+    };
+    // what enters the divergence: v' (forward) or S_v mu' (adjoint)
+    auto face_w = [&](float S, float Vn) -> float { return MODE == MODE_ADJ ? S * Vn : Vn; };
+
+    // ---- prologue: P(k0), cell value, v_z'(k0)
+    float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
+    {
+        const long long off = (long long)k0 * plane + cell;
+        float P_lo = 0.f, Vz_in = 0.f;
+        if (inside) {
+            A_cur = inA[off];
+            m_cur = mm[off];
+            P_cur = P_at(k0, off, wyx_c);
+            if (k0 > 0) P_lo = P_at(k0 - 1, off - plane, wyx_c);
+            Vz_in = inVz[off];
+        }
+        const float add = face_inj(k0);
+        const float S = a.wzf[k0] * wyx_c;
+        Vz_cur = face_new(S, Vz_in, P_cur - P_lo, add);
+        Wz_cur = face_w(S, Vz_cur);
+    }
+
+    for (int k = k0; k < k1; ++k) {
+        const long long offk = (long long)k * plane + cell;
+        const bool has_next = k + 1 < nz;
+
+        float A_nx = 0.f, m_nx = 0.f, P_nx = 0.f, Vz_nx_in = 0.f;
+        float Vy_in = 0.f, Vx_in = 0.f, e_k = 0.f, s_acc = 0.f, s_cmp = 0.f;
+        if (inside) {
+            if (has_next) {
+                const long long o1 = offk + plane;
+                A_nx = inA[o1];
+                m_nx = mm[o1];
+                P_nx = P_at(k + 1, o1, wyx_c);
+                Vz_nx_in = inVz[o1];
+            }
+            if (HAS_Y) Vy_in = inVy[offk];
+            Vx_in = inVx[offk];
+            if (MODE == MODE_ADJ) {
+                e_k = ek[offk];
+                s_acc = acc[offk];
+                s_cmp = cmp[offk];
+            }
+        }
+        float Vy_h = 0.f, Vx_h = 0.f;
+        if (halo_y) Vy_h = inVy[(long long)k * plane + (long long)jh * nx + i];
+        if (halo_x) Vx_h = inVx[(long long)k * plane + (long long)j * nx + ih];
+        float Pr = 0.f;
+        if (ring_in) Pr = P_at(k, (long long)k * plane + rcell, ring_wyx);
+
+        sP[ty + 1][tx + 1] = P_cur;
+        if (ring) sP[rsy][rsx] = Pr;
+        __syncthreads();
+
+        // ---- faces in the plane
+        const float wzc = a.wzc[k];
+        float Vy_new = 0.f, Vx_new = 0.f;
+        if (HAS_Y) {
+            const float S = wzc * wyx_vy;
+            Vy_new = face_new(S, Vy_in, sP[ty + 1][tx + 1] - sP[ty][tx + 1], 0.f);
+            sWy[ty][tx] = face_w(S, Vy_new);
+            if (ty == BY - 1) {
+                const float Sh = wzc * wyx_vy_h;
+                const float Vh = face_new(Sh, Vy_h, sP[BY + 1][tx + 1] - sP[BY][tx + 1], 0.f);
+                sWy[BY][tx] = face_w(Sh, Vh);
+            }
+        }
+        {
+            const float S = wzc * wyx_vx;
+            Vx_new = face_new(S, Vx_in, sP[ty + 1][tx + 1] - sP[ty + 1][tx], 0.f);
+            sWx[ty][tx] = face_w(S, Vx_new);
+            if (tx == BX - 1) {
+                const float Sh = wzc * wyx_vx_h;
+                const float Vh = face_new(Sh, Vx_h, sP[ty + 1][BX + 1] - sP[ty + 1][BX], 0.f);
+                sWx[ty][BX] = face_w(Sh, Vh);
+            }
+        }
+        // ---- next z face of the own column
+        float Vz_nx = 0.f, Wz_nx = 0.f;
+        {
+            const float add = face_inj(k + 1);
+            if (has_next) {
+                const float S = a.wzf[k + 1] * wyx_c;
+                Vz_nx = face_new(S, Vz_nx_in, P_nx - P_cur, add);
+                Wz_nx = face_w(S, Vz_nx);
+            }
+        }
+        __syncthreads();
+
+        // ---- cell update from the divergence of the new faces
+        float dsum = Wz_nx - Wz_cur;
+        if (HAS_Y) dsum += ((j + 1 < ny) ? sWy[ty + 1][tx] : 0.f) - sWy[ty][tx];
+        dsum += ((i + 1 < nx) ? sWx[ty][tx + 1] : 0.f) - sWx[ty][tx];
+        const float Se = wzc * wyx_c;
+        float A_new;
+        if (MODE == MODE_ADJ) {
+            A_new = Se * A_cur - a.dtdx * m_cur * dsum;
+            // Kahan: s_acc += e_k * dsum
+            const float y = e_k * dsum - s_cmp;
+            const float t = s_acc + y;
+            s_cmp = (t - s_acc) - y;
+            s_acc = t;
+        } else {
+            A_new = Se * (A_cur + a.dtdx * dsum);
+        }
+        if (inside) {
+            outA[offk] = A_new;
+            outVz[offk] = Vz_cur;
+            if (HAS_Y) outVy[offk] = Vy_new;
+            outVx[offk] = Vx_new;
+            if (MODE == MODE_ADJ) {
+                acc[offk] = s_acc;
+                cmp[offk] = s_cmp;
+            }
+        }
+        if (MODE != MODE_ADJ && a.nrec > 0) {
+            while (tp < re && a.rec_ent[tp].x < k) ++tp;
+            for (int q = tp; q < re; ++q) {
+                const int4 e = a.rec_ent[q];
+                if (e.x != k) break;
+                if (e.y == local && inside)
+                    a.traces[((long long)s * a.nt + a.tidx) * a.nrec + e.z] = Vz_cur;
+            }
+        }
+        P_cur = P_nx;
+        A_cur = A_nx;
+        m_cur = m_nx;
+        Vz_cur = Vz_nx;
+        Wz_cur = Wz_nx;
+    }
+}
+
+template <int BX, int BY, bool HAS_Y>
+void launch_mode(int mode, const StepArgs& a, int nsrc, hipStream_t st)
+{
+    dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
+    dim3 block(BX * BY);
+    switch (mode) {
+    case MODE_FWD: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y>), grid, block, 0, st, a); break;
+    case MODE_ADJ: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y>), grid, block, 0, st, a); break;
+    }
+}
+
+}  // namespace
+
+constexpr int TILE_BX = 64;
+constexpr int TILE_BY = 8;
+
+void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t st)
+{
+    if (has_y)
+        launch_mode<TILE_BX, TILE_BY, true>(mode, a, nsrc, st);
+    else
+        launch_mode<TILE_BX, 1, false>(mode, a, nsrc, st);
+    WV_HIP(hipGetLastError());
+}
+
+Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& src_kji,
+                   const std::vector<int>& rec_kji)
+{
+    Tiling t;
+    const bool has_y = ny > 1;
+    t.bx = TILE_BX;
+    t.by = has_y ? TILE_BY : 1;
+    t.tiles_x = (nx + t.bx - 1) / t.bx;
+    t.tiles_y = (ny + t.by - 1) / t.by;
+    const int tiles = t.tiles_x * t.tiles_y;
+    // enough work-groups to fill 256 CUs several times; chunks of >= 8 levels
+    int chunks = (2048 + tiles - 1) / tiles;
+    chunks = std::max(1, std::min(chunks, nz / 8 > 0 ? nz / 8 : 1));
+    int kc = (nz + chunks - 1) / chunks;
+    if (kc >= 8) kc = (kc + 7) / 8 * 8;
+    t.kc = kc;
+    t.chunks_z = (nz + kc - 1) / kc;
+
+    auto bucket = [&](const std::vector<int>& kji, int** d_ptr, int4** d_ent) {
+        const int n = (int)kji.size() / 3;
+        std::vector<std::vector<int4>> per(tiles);
+        for (int q = 0; q < n; ++q) {
+            const int k = kji[3 * q], j = kji[3 * q + 1], i = kji[3 * q + 2];
+            const int tl = (j / t.by) * t.tiles_x + (i / t.bx);
+            per[tl].push_back(make_int4(k, (j % t.by) * t.bx + (i % t.bx), q, 0));
+        }
+        std::vector<int> ptr(tiles + 1, 0);
+        std::vector<int4> ent;
+        for (int tl = 0; tl < tiles; ++tl) {
+            std::stable_sort(per[tl].begin(), per[tl].end(),
+                             [](const int4& x, const int4& y) { return x.x < y.x; });
+            ptr[tl] = (int)ent.size();
+            ent.insert(ent.end(), per[tl].begin(), per[tl].end());
+        }
+        ptr[tiles] = (int)ent.size();
+        WV_HIP(hipMalloc(d_ptr, sizeof(int) * ptr.size()));
+        WV_HIP(hipMemcpy(*d_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice));
+        const size_t ne = std::max<size_t>(ent.size(), 1);
+        WV_HIP(hipMalloc(d_ent, sizeof(int4) * ne));
+        if (!ent.empty())
+            WV_HIP(hipMemcpy(*d_ent, ent.data(), sizeof(int4) * ent.size(), hipMemcpyHostToDevice));
+    };
+    bucket(src_kji, &t.src_ptr, &t.src_ent);
+    bucket(rec_kji, &t.rec_ptr, &t.rec_ent);
+    return t;
+}
+
+void free_tiling(Tiling& t)
+{
+    if (t.rec_ptr) (void)hipFree(t.rec_ptr);
+    if (t.rec_ent) (void)hipFree(t.rec_ent);
+    if (t.src_ptr) (void)hipFree(t.src_ptr);
+    if (t.src_ent) (void)hipFree(t.src_ent);
+    t.rec_ptr = t.src_ptr = nullptr;
+    t.rec_ent = t.src_ent = nullptr;
+}
+
+}  // namespace wv

@@ -1,0 +1,117 @@
+// Internal declarations shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wavecomp.h"
+
+namespace wv {
+
+void set_error(const std::string& msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// Throwing check used inside the library; every C entry point converts
+// the exception into a return code (no exception crosses the ABI).
+#define WV_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            throw ::wv::Error{WV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define WV_REQUIRE(cond, code, text)                                                    \
+    do {                                                                               \
+        if (!(cond)) throw ::wv::Error{code, text};                                    \
+    } while (0)
+
+// ---- stencil -----------------------------------------------------------------------
+
+enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2 };
+
+// Tiling of the (y, x) plane and of z into chunks, plus the point lists
+// (sources, receivers) bucketed per (y, x) tile and sorted by depth.
+struct Tiling {
+    int bx = 64, by = 8;
+    int tiles_x = 0, tiles_y = 0, chunks_z = 0, kc = 0;
+    int* rec_ptr = nullptr;   // [tiles + 1]
+    int4* rec_ent = nullptr;  // (k, local, r, 0)
+    int* src_ptr = nullptr;
+    int4* src_ent = nullptr;  // (k, local, s, 0)
+};
+
+struct StepArgs {
+    int nz, ny, nx;
+    long long N;         // cells per field
+    long long sstride;   // floats between sources in a state array (4 N)
+    float dtdx, dt;
+    const float *wzc, *wzf, *wyc, *wyf, *wxc, *wxf;   // per-axis layer factors
+    const float* m;      // c^2
+    const float* in;     // state in  [S][4][N]
+    float* out;          // state out [S][4][N]
+    // sources (forward)
+    const int* src_ptr;
+    const int4* src_ent;
+    const float* wavelet;  // [S][T]
+    int nt, step;
+    // receivers
+    const int* rec_ptr;
+    const int4* rec_ent;
+    int nrec, tidx;        // time index into traces / residual
+    float* traces;         // forward / incremental: [S][T][R]
+    const float* resid;    // adjoint: [S][T][R]
+    // adjoint: forward e at this level and the Kahan accumulators (per source)
+    const float* ek;       // [S][ekstride]
+    long long ekstride;
+    float* acc;            // [S][2][N]: sum, compensation
+    // incremental forward: dm and forward e^n
+    const float* dm;
+    const float* en;
+    long long enstride;
+    int tiles_x, tiles_y, chunks_z, kc;
+};
+
+void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t st);
+Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& src_kji,
+                   const std::vector<int>& rec_kji);
+void free_tiling(Tiling& t);
+
+// ---- reductions / elementwise -------------------------------------------------------
+
+void launch_square(const float* c, float* m, long long n, hipStream_t st);
+// J partial sums and residual; returns nothing (result in d_out[0] after finalize).
+void launch_misfit(const float* p, const float* d, float* resid, long long n, double wres,
+                   double wJ, double* partial, int nblocks, double* d_out, hipStream_t st);
+void launch_scale_weights(const float* p, float* resid, long long n, double w, hipStream_t st);
+void launch_grad_finish(const float* c, const float* acc, long long N, int nsrc, double scale,
+                        float* g, hipStream_t st);
+void launch_fill(float* p, long long n, float v, hipStream_t st);
+void launch_compare(const float* a, const float* b, long long n, int* flag, hipStream_t st);
+void launch_copy(float* dst, const float* src, long long n, hipStream_t st);
+void launch_rel_err(const float* a, const float* b, long long n, double* partial, int nblocks,
+                    double* d_out, hipStream_t st);
+void launch_absmax_fields(const float* states, long long nstates, long long N, double* d_out4,
+                          hipStream_t st);
+// min, max and NaN count of x into d_out3 (float64)
+void launch_range(const float* x, long long n, double* partial, int nblocks, double* d_out3,
+                  hipStream_t st);
+// dm = 2 c dc
+void launch_dm(const float* c, const float* dc, float* dm, long long n, hipStream_t st);
+
+// ---- revolve --------------------------------------------------------------------------
+
+struct RevAction {
+    int kind;  // 0 advance(a -> a+b), 1 store(step a, slot b), 2 restore(step a, slot b), 3 deliver(a)
+    int a, b;
+};
+long long revolve_cost(long long l, int s);
+std::vector<RevAction> revolve_schedule(int nsteps, int nslots, long long* forward_steps);
+
+}  // namespace wv

@@ -1,0 +1,108 @@
+"""A solver context with torch-allocated device buffers around the C ABI.
+
+Only argument marshalling and buffer allocation happen here; every step of
+the forward, adjoint, incremental and autoencoder computations runs in
+libwavecomp.so on the current HIP stream."""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class WaveSolver:
+    """One wv_ctx: grid, sources, receivers, history storage.
+
+    Shapes: c [nz, ny, nx] float32; wavelet [S, T]; traces / data [S, T, R];
+    states [S, 4, nz, ny, nx] with field order (e, v_z, v_y, v_x)."""
+
+    def __init__(self, nz, ny, nx, dx, dt, nt, sponge, c_ref, src, rec, device="cuda", stream=None):
+        L.load()
+        self.shape = (int(nz), int(ny), int(nx))
+        self.dx, self.dt, self.nt = float(dx), float(dt), int(nt)
+        self.src = np.asarray(src, dtype=np.int32).reshape(-1, 3)
+        self.rec = np.asarray(rec, dtype=np.int32).reshape(-1, 3)
+        self.S, self.R = len(self.src), len(self.rec)
+        self.device = torch.device(device)
+        self.grid = L.make_grid(nz, ny, nx, dx, dt, nt, sponge, c_ref, self.S, self.R)
+        self.stream = stream
+        self.ctx = L.wv_create(self.grid, self.src, self.rec, stream)
+        self.ae = None
+
+    @classmethod
+    def for_problem(cls, p, **kw):
+        return cls(p.nz, p.ny, p.nx, p.dx, p.dt, p.nt, p.sponge, p.c_ref, p.src, p.rec, **kw)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.wv_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----- storage ---------------------------------------------------------------------------
+    def set_storage(self, mode, n_checkpoints=64, ae=None, mem_budget_bytes=0, guard_tol=0.0,
+                    fallback_policy=L.FALLBACK_NONE):
+        self.ae = ae
+        L.wv_set_storage(self.ctx, mode, n_checkpoints, None if ae is None else ae.handle,
+                         mem_budget_bytes, guard_tol, fallback_policy)
+
+    def storage_bytes(self) -> int:
+        return L.wv_storage_bytes(self.ctx)
+
+    def stats(self):
+        return L.wv_stats(self.ctx)
+
+    # ----- helpers ------------------------------------------------------------------------------
+    def _f32(self, x) -> torch.Tensor:
+        if isinstance(x, torch.Tensor):
+            t = x.to(device=self.device, dtype=torch.float32)
+        else:
+            t = torch.as_tensor(np.asarray(x, dtype=np.float32), device=self.device)
+        return t.contiguous()
+
+    def empty_traces(self):
+        return torch.empty((self.S, self.nt, self.R), dtype=torch.float32, device=self.device)
+
+    def empty_state(self):
+        return torch.empty((self.S, 4) + self.shape, dtype=torch.float32, device=self.device)
+
+    # ----- solves ---------------------------------------------------------------------------------
+    def forward(self, c, wavelet, final_state: bool = False, capture_every: int = 0):
+        c, w = self._f32(c), self._f32(wavelet)
+        tr = self.empty_traces()
+        fs = self.empty_state() if final_state else None
+        cap = None
+        if capture_every:
+            ncap = (self.nt - 1) // capture_every
+            cap = torch.empty((ncap, self.S, 4) + self.shape, dtype=torch.float32, device=self.device)
+        L.wave_forward(self.ctx, c, w, tr, fs, cap, capture_every)
+        return tr, fs, cap
+
+    def adjoint(self, c, residual):
+        g = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        L.wave_adjoint(self.ctx, self._f32(c), self._f32(residual), g)
+        return g
+
+    def gradient(self, c, wavelet, d_obs, sigma):
+        g = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        status, J = L.gradient(self.ctx, self._f32(c), self._f32(wavelet), self._f32(d_obs), sigma, g)
+        self.last_status = status
+        return J, g
+
+    def hessvec(self, c, dc):
+        H = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        self.last_status = L.hessvec(self.ctx, self._f32(c), self._f32(dc), H, 1)
+        return H
+
+    def inc_forward(self, c, dc):
+        dtr = self.empty_traces()
+        L.wave_inc_forward(self.ctx, self._f32(c), self._f32(dc), dtr)
+        return dtr
