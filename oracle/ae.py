@@ -23,7 +23,8 @@ Rounding emulation (emulate=True) applies the HIP path's precision
 contract so that differences reduce to FP32 summation order:
   y, W, hidden activations, latent -> bfloat16 (RNE); biases float32;
   products exact and summed (here in FP64); GELU on the unrounded
-  pre-activation; output float32. Backward: upstream gradients are
+  pre-activation; output float32. An FP8 latent (per-patch scale
+  s = max|z|/448, code = e4m3(z/s)) enters the decoder as bfloat16(code*s). Backward: upstream gradients are
   rounded to bfloat16 before they meet a bfloat16 operand in a product,
   bias gradients are plain sums, GELU' uses the stored pre-activation,
   and the latent rounding is treated as the identity.
@@ -123,7 +124,7 @@ class AE:
         z = h1 @ w["W2"] + w["b2"]
         if emulate:
             zs = rd.f32(z)
-            zq = rd.bf16(zs) if latent == "bf16" else fp8_roundtrip(zs)
+            zq = rd.bf16(zs) if latent == "bf16" else rd.bf16(fp8_roundtrip(zs))
         else:
             zq = z
         a3 = zq @ w["W3"] + w["b3"]

@@ -1,33 +1,1018 @@
-// Autoencoder entry points (placeholder until the MFMA kernels land).
+// Patch autoencoder on gfx950: per-vector normalisation, bfloat16 MFMA
+// encoder/decoder with fused epilogues, FP8 latent quantisation, training
+// (forward, backward, MSE loss, Adam) and the autoencoder C entry points.
+//
+// Network (paper Sec. 3.3, Eq. (single_layer), dense layers sigma(y W + b)):
+//   encoder 2048 -> hid (GELU) -> lat,  decoder lat -> hid (GELU) -> 2048.
+// Vectors (Sec. 3.1 space compression): one 8^3-cell patch of the 4 state
+// fields, entry f*512 + lz*64 + ly*8 + lx; normalised per field slice by
+// r = max(max - min, beta_f), y = (x - min)/r (Sec. 3.3.1).
+//
+// Precision: y, weights, hidden activations and latents are bfloat16 (RNE);
+// products accumulate in float32 on the matrix cores; biases, GELU and the
+// output are float32. FP8 latents are OCP E4M3FN codes with one float32 scale
+// per patch, s = max|z| / 448; the decoder consumes bfloat16(code * s).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
 #include "ae_internal.h"
 
-struct ae_net { int dummy; };
+namespace wv {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime(float x)
+{
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// OCP E4M3FN, round to nearest even, saturating at 448
+__device__ __forceinline__ uint8_t f2e4m3(float x)
+{
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float a = fabsf(x);
+    uint32_t code;
+    if (a >= 448.0f) {
+        code = 0x7E;
+    } else {
+        const int e = (int)((__float_as_uint(a) >> 23) & 0xFF) - 127;
+        if (e < -6) {
+            code = (uint32_t)rintf(a * 512.0f);  // subnormal quantum 2^-9
+        } else {
+            const float q = rintf(ldexpf(a, 3 - e));  // in [8, 16]
+            code = (uint32_t)((e + 7) << 3) + ((uint32_t)q - 8u);
+        }
+        if (code > 0x7E) code = 0x7E;
+    }
+    return (uint8_t)(code | sign);
+}
+__device__ __forceinline__ float e4m32f(uint8_t c)
+{
+    const int E = (c >> 3) & 0xF, m = c & 7;
+    const float v = E == 0 ? (float)m * 0.001953125f : ldexpf(1.0f + (float)m * 0.125f, E - 7);
+    return (c & 0x80) ? -v : v;
+}
+
+// ------------------------------------------------------------------------------------
+// GEMM  C[M][N] = sum_k A(m, k) B(n, k), bf16 operands, fp32 accumulation.
+// 256 threads = 4 waves; each wave owns a WM x WN block of 16x16 MFMA tiles.
+// A and B tiles (BM x BK, BN x BK, k fastest) are staged through LDS by loaders
+// that know the source layout; epilogues consume (row, col, value).
+// ------------------------------------------------------------------------------------
+constexpr int BK = 32;
+constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row
+
+// source stored [rows][ld] with k contiguous; optional row gather
+struct LoadK {
+    const uint16_t* p;
+    long long ld;
+    const int* rows;  // nullable: logical row r reads source row rows[r]
+    int nrows;        // logical rows
+    int k_total;
+    __device__ __forceinline__ void load(int r0, int k0, int tid, int BR, uint16_t (*lds)[BK + LDS_PAD]) const
+    {
+        // BR x BK tile = BR*4 chunks of 8 bf16
+        for (int c = tid; c < BR * (BK / 8); c += 256) {
+            const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+            const int gr = r0 + r, gk = k0 + kc;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && gk < k_total) {
+                const long long src = rows ? rows[gr] : gr;
+                v = *reinterpret_cast<const uint4*>(p + src * ld + gk);
+            }
+            *reinterpret_cast<uint4*>(&lds[r][kc]) = v;
+        }
+    }
+};
+
+// source stored [k][ld] with rows contiguous (a transposed operand); optional k gather
+struct LoadT {
+    const uint16_t* p;
+    long long ld;
+    const int* kidx;  // nullable: logical k reads source row kidx[k]
+    int nrows;
+    int k_total;
+    __device__ __forceinline__ void load(int r0, int k0, int tid, int BR, uint16_t (*lds)[BK + LDS_PAD]) const
+    {
+        // each chunk: 8 consecutive rows at one k
+        for (int c = tid; c < BK * (BR / 8); c += 256) {
+            const int kk = c / (BR / 8), rc = (c % (BR / 8)) * 8;
+            const int gk = k0 + kk, gr = r0 + rc;
+            uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (gk < k_total) {
+                const long long src = kidx ? kidx[gk] : gk;
+                const uint16_t* q = p + src * ld + gr;
+                if (gr + 8 <= nrows) {
+                    const uint4 w = *reinterpret_cast<const uint4*>(q);
+                    memcpy(v, &w, 16);
+                } else {
+                    for (int t = 0; t < 8; ++t)
+                        if (gr + t < nrows) v[t] = q[t];
+                }
+            }
+            for (int t = 0; t < 8; ++t) lds[rc + t][kk] = v[t];
+        }
+    }
+};
+
+template <int BM, int BN, int WM, int WN, class LA, class LB, class EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_per_split, LA la, LB lb, EPI epi)
+{
+    static_assert((BM / WM) * (BN / WN) == 4, "4 waves");
+    constexpr int TM = WM / 16, TN = WN / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[BM][BK + LDS_PAD];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[BN][BK + LDS_PAD];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm0 = (wave / (BN / WN)) * WM, wn0 = (wave % (BN / WN)) * WN;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kb = blockIdx.z * k_per_split;
+    const int ke = min(K, kb + k_per_split);
+
+    f32x4 acc[TM][TN];
+    for (int a = 0; a < TM; ++a)
+        for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        la.load(m0, k0, tid, BM, sA);
+        lb.load(n0, k0, tid, BN, sB);
+        __syncthreads();
+        bf16x8 af[TM], bfr[TN];
+        for (int a = 0; a < TM; ++a)
+            af[a] = *reinterpret_cast<const bf16x8*>(&sA[wm0 + a * 16 + fr][fk]);
+        for (int b = 0; b < TN; ++b)
+            bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[wn0 + b * 16 + fr][fk]);
+        for (int a = 0; a < TM; ++a)
+            for (int b = 0; b < TN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+    // C layout of a 16x16 tile: lane holds column lane%16, rows 4*(lane/16) + r
+    const int cc = lane & 15, cr = (lane >> 4) * 4;
+    for (int a = 0; a < TM; ++a)
+        for (int b = 0; b < TN; ++b) {
+            const int col = n0 + wn0 + b * 16 + cc;
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm0 + a * 16 + cr + r;
+                if (row < M && col < N) epi(row, col, acc[a][b][r], blockIdx.z);
+            }
+        }
+}
+
+// ---- epilogues ----------------------------------------------------------------------
+struct EpiF32 {  // out[z][row][col] = v (+ bias[col])
+    float* out;
+    long long ld, zstride;
+    const float* bias;
+    __device__ __forceinline__ void operator()(int r, int c, float v, int z) const
+    {
+        out[z * zstride + (long long)r * ld + c] = v + (bias ? bias[c] : 0.f);
+    }
+};
+struct EpiBF16 {  // bf16(v + bias), optional fp32 copy
+    uint16_t* out;
+    long long ld;
+    const float* bias;
+    float* f32out;
+    __device__ __forceinline__ void operator()(int r, int c, float v, int) const
+    {
+        const float x = v + (bias ? bias[c] : 0.f);
+        out[(long long)r * ld + c] = f2bf(x);
+        if (f32out) f32out[(long long)r * ld + c] = x;
+    }
+};
+struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
+    uint16_t* out;
+    long long ld;
+    const float* bias;
+    float* pre;
+    __device__ __forceinline__ void operator()(int r, int c, float v, int) const
+    {
+        const float a = v + bias[c];
+        if (pre) pre[(long long)r * ld + c] = a;
+        out[(long long)r * ld + c] = f2bf(gelu(a));
+    }
+};
+struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
+    uint16_t* out;
+    float* f32out;
+    const float* pre;
+    long long ld;
+    __device__ __forceinline__ void operator()(int r, int c, float v, int) const
+    {
+        const long long o = (long long)r * ld + c;
+        const float d = v * gelu_prime(pre[o]);
+        out[o] = f2bf(d);
+        f32out[o] = d;
+    }
+};
+struct EpiDenorm {  // decoder output of field f -> lo + r (v + b) scattered into the state
+    float* state;
+    const float* meta;  // [P][4][2]
+    const float* bias;  // b4 + f*512
+    int f, Py, Px, ny, nx;
+    long long N;
+    __device__ __forceinline__ void operator()(int p, int c, float v, int) const
+    {
+        const float y = v + bias[c];
+        const float lo = meta[(long long)p * 8 + 2 * f], rr = meta[(long long)p * 8 + 2 * f + 1];
+        const int px = p % Px, py = (p / Px) % Py, pz = p / (Px * Py);
+        const int lz = c >> 6, ly = (c >> 3) & 7, lx = c & 7;
+        const long long z = pz * 8 + lz, yy = py * 8 + ly, x = px * 8 + lx;
+        state[f * N + (z * ny + yy) * nx + x] = lo + rr * y;
+    }
+};
+
+template <int BM, int BN, int WM, int WN, class LA, class LB, class EPI>
+void gemm(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
+{
+    WV_REQUIRE(K % BK == 0, WV_EINVAL, "GEMM depth must be a multiple of 32");
+    const int kps = ((K / BK + splits - 1) / splits) * BK;
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, LA, LB, EPI>), grid, dim3(256), 0, st, M, N, K, kps, la, lb, epi);
+    WV_HIP(hipGetLastError());
+}
+
+// wide N (>= 128) and narrow N (<= 32) tile shapes
+template <class LA, class LB, class EPI>
+void gemm_auto(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
+{
+    if (N <= 32)
+        gemm<128, 32, 32, 32>(M, N, K, la, lb, epi, st, splits);
+    else
+        gemm<128, 128, 64, 64>(M, N, K, la, lb, epi, st, splits);
+}
+
+// ------------------------------------------------------------------------------------
+// normalisation: one work-group per patch, one wave per field (8 values per lane)
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict__ state, int ny, int nx,
+                                                       long long N, int Py, int Px, const float* __restrict__ beta,
+                                                       uint16_t* __restrict__ y, float* __restrict__ meta)
+{
+    const long long p = blockIdx.x;
+    const int f = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int px = p % Px, py = (p / Px) % Py, pz = p / ((long long)Px * Py);
+    const int lz = l >> 3, ly = l & 7;
+    const float* src = state + f * N + ((long long)(pz * 8 + lz) * ny + (py * 8 + ly)) * nx + px * 8;
+    const float4 a = *reinterpret_cast<const float4*>(src);
+    const float4 b = *reinterpret_cast<const float4*>(src + 4);
+    float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    float lo = v[0], hi = v[0];
+    for (int t = 1; t < 8; ++t) {
+        lo = fminf(lo, v[t]);
+        hi = fmaxf(hi, v[t]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    const float r = fmaxf(hi - lo, beta[f]);
+    uint16_t o8[8];
+    for (int t = 0; t < 8; ++t) o8[t] = f2bf((v[t] - lo) / r);
+    *reinterpret_cast<uint4*>(y + p * 2048 + f * 512 + l * 8) = *reinterpret_cast<const uint4*>(o8);
+    if (l == 0) {
+        meta[p * 8 + 2 * f] = lo;
+        meta[p * 8 + 2 * f + 1] = r;
+    }
+}
+
+// latent fp32 [P][L] -> e4m3 codes + per-patch scale; one wave per patch
+__global__ void quantize_kernel(const float* __restrict__ z, long long P, int L, uint8_t* __restrict__ q,
+                                float* __restrict__ scale)
+{
+    const long long p = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (p >= P) return;
+    const float v = l < L ? z[p * L + l] : 0.f;
+    float m = fabsf(v);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const float s = m > 0.f ? m / 448.0f : 1.0f;
+    if (l < L) q[p * L + l] = f2e4m3(v / s);
+    if (l == 0) scale[p] = s;
+}
+
+// e4m3 codes + scale -> bf16(code * s)
+__global__ void dequantize_kernel(const uint8_t* __restrict__ q, const float* __restrict__ scale, long long P,
+                                  int L, uint16_t* __restrict__ zb)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= P * L) return;
+    zb[i] = f2bf(e4m32f(q[i]) * scale[i / L]);
+}
+
+// ------------------------------------------------------------------------------------
+// training helpers
+// ------------------------------------------------------------------------------------
+// yhat fp32 [B][n], y = bf16 rows idx -> d = 2 (yhat - y)/(B n) (bf16 + fp32), loss partials
+__global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ yhat, const uint16_t* __restrict__ y,
+                                                 const int* __restrict__ idx, int B, int n, float scale,
+                                                 uint16_t* __restrict__ dq, float* __restrict__ df,
+                                                 double* __restrict__ partial)
+{
+    const int b = blockIdx.x;
+    const long long src = idx ? idx[b] : b;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const float diff = yhat[(long long)b * n + c] - bf2f(y[src * n + c]);
+        acc += (double)diff * diff;
+        const float d = scale * diff;
+        dq[(long long)b * n + c] = f2bf(d);
+        df[(long long)b * n + c] = d;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[b] = sh[0];
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
+                                    int accumulate)
+{
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) a += partial[q];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (accumulate ? out[0] : 0.0) + scale * sh[0];
+}
+
+// column sums of d [B][n] (bias gradients): 64 columns x 4 row lanes per block,
+// 16 row chunks -> partial [16][n], then a fixed-order sum
+constexpr int COLSUM_CHUNKS = 16;
+__global__ void colsum_partial_kernel(const float* __restrict__ d, int B, int n, float* __restrict__ part)
+{
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int rl = threadIdx.x >> 6;
+    const int rows = (B + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
+    const int r0 = blockIdx.y * rows, r1 = min(B, r0 + rows);
+    float s = 0.f;
+    if (c < n)
+        for (int b = r0 + rl; b < r1; b += 4) s += d[(long long)b * n + c];
+    __shared__ float sh[4][64];
+    sh[rl][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rl == 0 && c < n) part[(long long)blockIdx.y * n + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
+                                                             (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+// sum split-K partials [splits][n] -> out[n]
+__global__ void splitsum_kernel(const float* __restrict__ part, int splits, long long n, float* __restrict__ out)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[z * n + i];
+    out[i] = s;
+}
+
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, long long n, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    w[i] = w[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// fp32 W [fi][fo] -> bf16 W [fi][fo] and bf16 W^T [fo][fi]
+__global__ void convert_kernel(const float* __restrict__ w, int fi, int fo, uint16_t* __restrict__ wb,
+                               uint16_t* __restrict__ wt)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= (long long)fi * fo) return;
+    const int r = i / fo, c = i % fo;
+    const uint16_t b = f2bf(w[i]);
+    wb[i] = b;
+    wt[(long long)c * fi + r] = b;
+}
+
+int blocks(long long n, int bs) { return (int)std::max<long long>(1, (n + bs - 1) / bs); }
+
+void colsum(const float* d, int B, int n, float* part, float* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks(n, 64), COLSUM_CHUNKS), dim3(256), 0, st, d, B, n, part);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, part, COLSUM_CHUNKS, (long long)n, out);
+}
+
+}  // namespace
+}  // namespace wv
+
+using namespace wv;
+
+// ======================================================================================
+struct ae_net {
+    int in = 2048, hid = 512, lat = 32;
+    long long nparam = 0;
+    long long oW[4] = {0, 0, 0, 0}, ob[4] = {0, 0, 0, 0};
+    int fi[4] = {0, 0, 0, 0}, fo[4] = {0, 0, 0, 0};
+    float* master = nullptr;
+    float* m1 = nullptr;
+    float* m2 = nullptr;
+    float* grad = nullptr;
+    uint16_t* wb[4] = {nullptr, nullptr, nullptr, nullptr};  // bf16 W   [fi][fo]
+    uint16_t* wt[4] = {nullptr, nullptr, nullptr, nullptr};  // bf16 W^T [fo][fi]
+    float* beta_d = nullptr;
+    double* loss_d = nullptr;
+    double beta[4] = {1e-7, 1e-7, 1e-7, 1e-7};
+    long long step = 0;
+    // workspace (grown on demand)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+
+    const float* bias(int l) const { return master + ob[l]; }
+};
 
 namespace wv {
-int ae_latent_dim(const ae_net*) { throw Error{WV_ESTATE, "autoencoder not built"}; }
-long long ae_latent_bytes_per_patch(const ae_net*, int) { throw Error{WV_ESTATE, "autoencoder not built"}; }
-void ae_encode_state(const ae_net*, const PatchGrid&, const float*, int, void*, float*, float*, hipStream_t)
-{ throw Error{WV_ESTATE, "autoencoder not built"}; }
-void ae_decode_state(const ae_net*, const PatchGrid&, const void*, const float*, const float*, int, uint32_t,
-                     float*, hipStream_t)
-{ throw Error{WV_ESTATE, "autoencoder not built"}; }
+namespace {
+
+template <class T>
+T* dalloc(size_t n)
+{
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{e == hipErrorOutOfMemory ? WV_ENOMEM : WV_EDEVICE,
+                    "autoencoder allocation of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+    }
+    return static_cast<T*>(p);
 }
 
-extern "C" {
-#define WV_STUB { wv::set_error("autoencoder not built"); return WV_ESTATE; }
-int ae_create(int32_t, int32_t, int32_t, const float*, const double*, ae_net**) WV_STUB
-void ae_destroy(ae_net*) {}
-int ae_param_count(const ae_net*, int64_t*) WV_STUB
-int ae_get_params(const ae_net*, float*) WV_STUB
-int ae_set_params(ae_net*, const float*) WV_STUB
-int ae_set_beta(ae_net*, const double*) WV_STUB
-int ae_get_beta(const ae_net*, double*) WV_STUB
-int ae_fit_beta(ae_net*, const wv_grid*, const float*, int64_t, double, void*) WV_STUB
-int ae_save(const ae_net*, const char*) WV_STUB
-int ae_load(const char*, ae_net**) WV_STUB
-int ae_normalize(const ae_net*, const wv_grid*, const float*, uint16_t*, float*, void*) WV_STUB
-int ae_encode(const ae_net*, const wv_grid*, const float*, int, void*, float*, float*, void*) WV_STUB
-int ae_decode(const ae_net*, const wv_grid*, const void*, const float*, const float*, int, uint32_t, float*, void*) WV_STUB
-int ae_train(ae_net*, const uint16_t*, int64_t, const ae_train_cfg*, const int32_t*, float*, void*) WV_STUB
-int ae_train_step(ae_net*, const uint16_t*, const int32_t*, int32_t, double, const ae_train_cfg*, float*, double*, void*) WV_STUB
+void layout(ae_net* a)
+{
+    const int dims[5] = {a->in, a->hid, a->lat, a->hid, a->in};
+    long long o = 0;
+    for (int l = 0; l < 4; ++l) {
+        a->fi[l] = dims[l];
+        a->fo[l] = dims[l + 1];
+        a->oW[l] = o;
+        o += (long long)a->fi[l] * a->fo[l];
+        a->ob[l] = o;
+        o += a->fo[l];
+    }
+    a->nparam = o;
 }
+
+void refresh_bf16(ae_net* a, hipStream_t st)
+{
+    for (int l = 0; l < 4; ++l) {
+        const long long n = (long long)a->fi[l] * a->fo[l];
+        hipLaunchKernelGGL(convert_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, a->master + a->oW[l], a->fi[l],
+                           a->fo[l], a->wb[l], a->wt[l]);
+    }
+    WV_HIP(hipGetLastError());
+}
+
+void upload_beta(ae_net* a)
+{
+    float b[4];
+    for (int f = 0; f < 4; ++f) b[f] = (float)a->beta[f];
+    WV_HIP(hipMemcpy(a->beta_d, b, sizeof(b), hipMemcpyHostToDevice));
+}
+
+void* workspace(const ae_net* ac, size_t bytes)
+{
+    ae_net* a = const_cast<ae_net*>(ac);
+    if (bytes > a->ws_bytes) {
+        WV_HIP(hipDeviceSynchronize());
+        if (a->ws) (void)hipFree(a->ws);
+        a->ws = nullptr;
+        a->ws_bytes = 0;
+        a->ws = dalloc<uint8_t>(bytes);
+        a->ws_bytes = bytes;
+    }
+    return a->ws;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+void check_grid(const wv_grid* g)
+{
+    WV_REQUIRE(g, WV_EINVAL, "null grid");
+    WV_REQUIRE(g->ny > 1 && g->nz % 8 == 0 && g->ny % 8 == 0 && g->nx % 8 == 0, WV_ESHAPE,
+               "autoencoder needs a 3D grid divisible into 8^3 patches");
+}
+
+void normalize_state(const ae_net* a, const PatchGrid& pg, const float* state, uint16_t* y, float* meta,
+                     hipStream_t st)
+{
+    const long long N = (long long)pg.nz * pg.ny * pg.nx;
+    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)pg.P), dim3(256), 0, st, state, pg.ny, pg.nx, N, pg.ny / 8,
+                       pg.nx / 8, a->beta_d, y, meta);
+    WV_HIP(hipGetLastError());
+}
+
+template <class F>
+int guarded_ae(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return WV_EDEVICE;
+    }
+}
+
+}  // namespace
+
+int ae_latent_dim(const ae_net* net) { return net->lat; }
+
+long long ae_latent_bytes_per_patch(const ae_net* net, int fmt)
+{
+    return (long long)net->lat * (fmt == AE_LATENT_FP8 ? 1 : 2);
+}
+
+void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, int fmt, void* latent, float* meta,
+                     float* qscale, hipStream_t st)
+{
+    const long long P = pg.P;
+    const size_t oy = 0, oh = align256(oy + P * 2048 * 2), oz = align256(oh + P * (size_t)a->hid * 2);
+    uint8_t* ws = (uint8_t*)workspace(a, align256(oz + P * (size_t)a->lat * 4));
+    uint16_t* y = (uint16_t*)(ws + oy);
+    uint16_t* h = (uint16_t*)(ws + oh);
+    float* z = (float*)(ws + oz);
+    normalize_state(a, pg, state, y, meta, st);
+    gemm_auto((int)P, a->hid, a->in, LoadK{y, a->in, nullptr, (int)P, a->in},
+              LoadK{a->wt[0], a->in, nullptr, a->hid, a->in}, EpiGelu{h, a->hid, a->bias(0), nullptr}, st);
+    const LoadK lh{h, a->hid, nullptr, (int)P, a->hid};
+    const LoadK lw{a->wt[1], a->hid, nullptr, a->lat, a->hid};
+    if (fmt == AE_LATENT_BF16) {
+        gemm_auto((int)P, a->lat, a->hid, lh, lw, EpiBF16{(uint16_t*)latent, a->lat, a->bias(1), nullptr}, st);
+    } else {
+        gemm_auto((int)P, a->lat, a->hid, lh, lw, EpiF32{z, a->lat, 0, a->bias(1)}, st);
+        hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
+                           qscale);
+        WV_HIP(hipGetLastError());
+    }
+}
+
+void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
+                     const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st)
+{
+    const long long P = pg.P;
+    const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
+    uint8_t* ws = (uint8_t*)workspace(a, align256(ozb + P * (size_t)a->lat * 2));
+    uint16_t* h = (uint16_t*)(ws + oh);
+    const uint16_t* zb = (const uint16_t*)latent;
+    if (fmt == AE_LATENT_FP8) {
+        uint16_t* zq = (uint16_t*)(ws + ozb);
+        hipLaunchKernelGGL(dequantize_kernel, dim3(blocks(P * a->lat, 256)), dim3(256), 0, st, (const uint8_t*)latent,
+                           qscale, P, a->lat, zq);
+        WV_HIP(hipGetLastError());
+        zb = zq;
+    }
+    gemm_auto((int)P, a->hid, a->lat, LoadK{zb, a->lat, nullptr, (int)P, a->lat},
+              LoadK{a->wt[2], a->lat, nullptr, a->hid, a->lat}, EpiGelu{h, a->hid, a->bias(2), nullptr}, st);
+    const long long N = (long long)pg.nz * pg.ny * pg.nx;
+    for (int f = 0; f < 4; ++f) {
+        if (!(mask & (1u << f))) continue;
+        gemm_auto((int)P, 512, a->hid, LoadK{h, a->hid, nullptr, (int)P, a->hid},
+                  LoadK{a->wt[3] + (long long)f * 512 * a->hid, a->hid, nullptr, 512, a->hid},
+                  EpiDenorm{state, meta, a->bias(3) + f * 512, f, pg.ny / 8, pg.nx / 8, pg.ny, pg.nx, N}, st);
+    }
+}
+
+namespace {
+
+// One Adam step on a batch. Returns (device) the batch loss in *dloss (added if accumulate).
+struct TrainBufs {
+    float *a1, *a3, *yhat, *d4f, *d3f, *dzf, *d1f, *zf, *part;
+    uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
+    double* lpart;
+};
+
+TrainBufs train_buffers(const ae_net* a, int B, int splits)
+{
+    const size_t in = a->in, hid = a->hid, lat = a->lat;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    const size_t o_a1 = take(B * hid * 4), o_a3 = take(B * hid * 4), o_yh = take(B * in * 4), o_d4f = take(B * in * 4),
+                 o_d3f = take(B * hid * 4), o_dzf = take(B * lat * 4), o_d1f = take(B * hid * 4),
+                 o_zf = take(B * lat * 4), o_part = take((size_t)splits * in * hid * 4), o_h1 = take(B * hid * 2),
+                 o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
+                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8);
+    uint8_t* w = (uint8_t*)workspace(a, o);
+    TrainBufs t;
+    t.a1 = (float*)(w + o_a1);
+    t.a3 = (float*)(w + o_a3);
+    t.yhat = (float*)(w + o_yh);
+    t.d4f = (float*)(w + o_d4f);
+    t.d3f = (float*)(w + o_d3f);
+    t.dzf = (float*)(w + o_dzf);
+    t.d1f = (float*)(w + o_d1f);
+    t.zf = (float*)(w + o_zf);
+    t.part = (float*)(w + o_part);
+    t.h1 = (uint16_t*)(w + o_h1);
+    t.zb = (uint16_t*)(w + o_zb);
+    t.h3 = (uint16_t*)(w + o_h3);
+    t.d4 = (uint16_t*)(w + o_d4);
+    t.d3 = (uint16_t*)(w + o_d3);
+    t.dz = (uint16_t*)(w + o_dz);
+    t.d1 = (uint16_t*)(w + o_d1);
+    t.lpart = (double*)(w + o_lp);
+    return t;
+}
+
+// weight gradient dW[fi][fo] = X^T D with split-K over the batch
+template <class LX, class LD>
+void weight_grad(ae_net* a, int l, int B, const LX& lx, const LD& ld, float* part, int splits, hipStream_t st)
+{
+    const int fi = a->fi[l], fo = a->fo[l];
+    const long long n = (long long)fi * fo;
+    gemm_auto(fi, fo, B, lx, ld, EpiF32{part, fo, n, nullptr}, st, splits);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, part, splits, n, a->grad + a->oW[l]);
+}
+
+void train_batch(ae_net* a, const uint16_t* y, const int* idx, int B, TrainBufs& t, int splits, double* dloss,
+                 int accumulate, hipStream_t st)
+{
+    const int in = a->in, hid = a->hid, lat = a->lat;
+    // forward
+    gemm_auto(B, hid, in, LoadK{y, in, idx, B, in}, LoadK{a->wt[0], in, nullptr, hid, in},
+              EpiGelu{t.h1, hid, a->bias(0), t.a1}, st);
+    gemm_auto(B, lat, hid, LoadK{t.h1, hid, nullptr, B, hid}, LoadK{a->wt[1], hid, nullptr, lat, hid},
+              EpiBF16{t.zb, lat, a->bias(1), t.zf}, st);
+    gemm_auto(B, hid, lat, LoadK{t.zb, lat, nullptr, B, lat}, LoadK{a->wt[2], lat, nullptr, hid, lat},
+              EpiGelu{t.h3, hid, a->bias(2), t.a3}, st);
+    gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
+              EpiF32{t.yhat, in, 0, a->bias(3)}, st);
+    hipLaunchKernelGGL(mse_kernel, dim3(B), dim3(256), 0, st, t.yhat, y, idx, B, in, 2.0f / ((float)B * in), t.d4,
+                       t.d4f, t.lpart);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lpart, B, 1.0 / ((double)B * in), dloss,
+                       accumulate);
+    // backward: layer 4
+    weight_grad(a, 3, B, LoadT{t.h3, hid, nullptr, hid, B}, LoadT{t.d4, in, nullptr, in, B}, t.part, splits, st);
+    colsum(t.d4f, B, in, t.part, a->grad + a->ob[3], st);
+    gemm_auto(B, hid, in, LoadK{t.d4, in, nullptr, B, in}, LoadK{a->wb[3], in, nullptr, hid, in},
+              EpiGeluBack{t.d3, t.d3f, t.a3, hid}, st);
+    // layer 3
+    weight_grad(a, 2, B, LoadT{t.zb, lat, nullptr, lat, B}, LoadT{t.d3, hid, nullptr, hid, B}, t.part, splits, st);
+    colsum(t.d3f, B, hid, t.part, a->grad + a->ob[2], st);
+    gemm_auto(B, lat, hid, LoadK{t.d3, hid, nullptr, B, hid}, LoadK{a->wb[2], hid, nullptr, lat, hid},
+              EpiBF16{t.dz, lat, nullptr, t.dzf}, st);
+    // layer 2
+    weight_grad(a, 1, B, LoadT{t.h1, hid, nullptr, hid, B}, LoadT{t.dz, lat, nullptr, lat, B}, t.part, splits, st);
+    colsum(t.dzf, B, lat, t.part, a->grad + a->ob[1], st);
+    gemm_auto(B, hid, lat, LoadK{t.dz, lat, nullptr, B, lat}, LoadK{a->wb[1], lat, nullptr, hid, lat},
+              EpiGeluBack{t.d1, t.d1f, t.a1, hid}, st);
+    // layer 1
+    weight_grad(a, 0, B, LoadT{y, in, idx, in, B}, LoadT{t.d1, hid, nullptr, hid, B}, t.part, splits, st);
+    colsum(t.d1f, B, hid, t.part, a->grad + a->ob[0], st);
+    WV_HIP(hipGetLastError());
+}
+
+void adam_update(ae_net* a, double lr, const ae_train_cfg& cfg, hipStream_t st)
+{
+    a->step += 1;
+    const double c1 = 1.0 - std::pow(cfg.beta1, (double)a->step);
+    const double c2 = 1.0 - std::pow(cfg.beta2, (double)a->step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks(a->nparam, 256)), dim3(256), 0, st, a->master, a->m1, a->m2, a->grad,
+                       a->nparam, (float)lr, (float)cfg.beta1, (float)cfg.beta2, (float)cfg.eps, (float)c1, (float)c2);
+    WV_HIP(hipGetLastError());
+    refresh_bf16(a, st);
+}
+
+ae_net* new_net(int in, int hid, int lat)
+{
+    WV_REQUIRE(in == 2048, WV_EINVAL, "in_dim must be 2048 (4 fields x 8^3 cells)");
+    WV_REQUIRE(hid >= 64 && hid % 64 == 0, WV_EINVAL, "hidden must be a positive multiple of 64");
+    WV_REQUIRE(lat >= 16 && lat <= 64 && lat % 16 == 0, WV_EINVAL, "latent must be 16, 32, 48 or 64");
+    std::unique_ptr<ae_net> a(new ae_net());
+    a->in = in;
+    a->hid = hid;
+    a->lat = lat;
+    layout(a.get());
+    a->master = dalloc<float>(a->nparam);
+    a->m1 = dalloc<float>(a->nparam);
+    a->m2 = dalloc<float>(a->nparam);
+    a->grad = dalloc<float>(a->nparam);
+    WV_HIP(hipMemset(a->m1, 0, a->nparam * 4));
+    WV_HIP(hipMemset(a->m2, 0, a->nparam * 4));
+    WV_HIP(hipMemset(a->grad, 0, a->nparam * 4));
+    for (int l = 0; l < 4; ++l) {
+        a->wb[l] = dalloc<uint16_t>((size_t)a->fi[l] * a->fo[l]);
+        a->wt[l] = dalloc<uint16_t>((size_t)a->fi[l] * a->fo[l]);
+    }
+    a->beta_d = dalloc<float>(4);
+    a->loss_d = dalloc<double>(1);
+    upload_beta(a.get());
+    return a.release();
+}
+
+void free_net(ae_net* a)
+{
+    if (!a) return;
+    (void)hipDeviceSynchronize();
+    for (float* p : {a->master, a->m1, a->m2, a->grad, a->beta_d})
+        if (p) (void)hipFree(p);
+    if (a->loss_d) (void)hipFree(a->loss_d);
+    for (int l = 0; l < 4; ++l) {
+        if (a->wb[l]) (void)hipFree(a->wb[l]);
+        if (a->wt[l]) (void)hipFree(a->wt[l]);
+    }
+    if (a->ws) (void)hipFree(a->ws);
+    delete a;
+}
+
+}  // namespace
+}  // namespace wv
+
+// ======================================================================================
+extern "C" {
+
+int ae_create(int32_t in_dim, int32_t hidden, int32_t latent, const float* h_init, const double* h_beta, ae_net** out)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(out && h_init, WV_EINVAL, "null argument");
+        ae_net* a = new_net(in_dim, hidden, latent);
+        try {
+            WV_HIP(hipMemcpy(a->master, h_init, a->nparam * 4, hipMemcpyHostToDevice));
+            if (h_beta)
+                for (int f = 0; f < 4; ++f) a->beta[f] = h_beta[f];
+            upload_beta(a);
+            refresh_bf16(a, nullptr);
+            WV_HIP(hipDeviceSynchronize());
+        } catch (...) {
+            free_net(a);
+            throw;
+        }
+        *out = a;
+        return WV_OK;
+    });
+}
+
+void ae_destroy(ae_net* net) { free_net(net); }
+
+int ae_param_count(const ae_net* a, int64_t* n)
+{
+    if (!a || !n) {
+        set_error("null argument");
+        return WV_EINVAL;
+    }
+    *n = a->nparam;
+    return WV_OK;
+}
+
+int ae_get_params(const ae_net* a, float* h_out)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && h_out, WV_EINVAL, "null argument");
+        WV_HIP(hipDeviceSynchronize());
+        WV_HIP(hipMemcpy(h_out, a->master, a->nparam * 4, hipMemcpyDeviceToHost));
+        return WV_OK;
+    });
+}
+
+int ae_set_params(ae_net* a, const float* h_in)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && h_in, WV_EINVAL, "null argument");
+        WV_HIP(hipDeviceSynchronize());
+        WV_HIP(hipMemcpy(a->master, h_in, a->nparam * 4, hipMemcpyHostToDevice));
+        refresh_bf16(a, nullptr);
+        WV_HIP(hipDeviceSynchronize());
+        return WV_OK;
+    });
+}
+
+int ae_set_beta(ae_net* a, const double* h_beta)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && h_beta, WV_EINVAL, "null argument");
+        for (int f = 0; f < 4; ++f) {
+            WV_REQUIRE(h_beta[f] > 0 && std::isfinite(h_beta[f]), WV_EINVAL, "beta must be positive");
+            a->beta[f] = h_beta[f];
+        }
+        upload_beta(a);
+        return WV_OK;
+    });
+}
+
+int ae_get_beta(const ae_net* a, double* h_beta)
+{
+    if (!a || !h_beta) {
+        set_error("null argument");
+        return WV_EINVAL;
+    }
+    for (int f = 0; f < 4; ++f) h_beta[f] = a->beta[f];
+    return WV_OK;
+}
+
+int ae_fit_beta(ae_net* a, const wv_grid* g, const float* states, int64_t nstates, double rel, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && g && states && nstates > 0 && rel > 0, WV_EINVAL, "bad argument");
+        hipStream_t st = (hipStream_t)stream;
+        const long long N = (long long)g->nz * g->ny * g->nx;
+        double* d = dalloc<double>(4);
+        launch_absmax_fields(states, nstates, N, d, st);
+        double h[4];
+        WV_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        (void)hipFree(d);
+        for (int f = 0; f < 4; ++f) a->beta[f] = h[f] > 0 ? rel * h[f] : rel;
+        upload_beta(a);
+        return WV_OK;
+    });
+}
+
+int ae_save(const ae_net* a, const char* path)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && path, WV_EINVAL, "null argument");
+        WV_HIP(hipDeviceSynchronize());
+        std::vector<float> buf(a->nparam);
+        FILE* f = fopen(path, "wb");
+        WV_REQUIRE(f, WV_EINVAL, std::string("cannot open ") + path);
+        const char magic[8] = {'W', 'V', 'A', 'E', '0', '0', '0', '1'};
+        const int32_t dims[3] = {a->in, a->hid, a->lat};
+        fwrite(magic, 1, 8, f);
+        fwrite(dims, sizeof(int32_t), 3, f);
+        fwrite(&a->step, sizeof(long long), 1, f);
+        fwrite(a->beta, sizeof(double), 4, f);
+        for (const float* p : {a->master, a->m1, a->m2}) {
+            WV_HIP(hipMemcpy(buf.data(), p, a->nparam * 4, hipMemcpyDeviceToHost));
+            fwrite(buf.data(), 4, a->nparam, f);
+        }
+        const bool ok = fclose(f) == 0;
+        WV_REQUIRE(ok, WV_EINVAL, "write failed");
+        return WV_OK;
+    });
+}
+
+int ae_load(const char* path, ae_net** out)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(path && out, WV_EINVAL, "null argument");
+        FILE* f = fopen(path, "rb");
+        WV_REQUIRE(f, WV_EINVAL, std::string("cannot open ") + path);
+        char magic[8];
+        int32_t dims[3];
+        long long step;
+        double beta[4];
+        bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "WVAE0001", 8) == 0 &&
+                  fread(dims, sizeof(int32_t), 3, f) == 3 && fread(&step, sizeof(long long), 1, f) == 1 &&
+                  fread(beta, sizeof(double), 4, f) == 4;
+        if (!ok) {
+            fclose(f);
+            throw Error{WV_EINVAL, "not an autoencoder file"};
+        }
+        ae_net* a = new_net(dims[0], dims[1], dims[2]);
+        std::vector<float> buf(a->nparam);
+        for (float* p : {a->master, a->m1, a->m2}) {
+            if (fread(buf.data(), 4, a->nparam, f) != (size_t)a->nparam) {
+                fclose(f);
+                free_net(a);
+                throw Error{WV_EINVAL, "truncated autoencoder file"};
+            }
+            WV_HIP(hipMemcpy(p, buf.data(), a->nparam * 4, hipMemcpyHostToDevice));
+        }
+        fclose(f);
+        a->step = step;
+        for (int q = 0; q < 4; ++q) a->beta[q] = beta[q];
+        upload_beta(a);
+        refresh_bf16(a, nullptr);
+        WV_HIP(hipDeviceSynchronize());
+        *out = a;
+        return WV_OK;
+    });
+}
+
+int ae_normalize(const ae_net* a, const wv_grid* g, const float* state, uint16_t* y, float* meta, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && state && y && meta, WV_EINVAL, "null argument");
+        check_grid(g);
+        normalize_state(a, patch_grid(g->nz, g->ny, g->nx), state, y, meta, (hipStream_t)stream);
+        return WV_OK;
+    });
+}
+
+int ae_encode(const ae_net* a, const wv_grid* g, const float* state, int fmt, void* latent, float* meta,
+              float* qscale, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && state && latent && meta, WV_EINVAL, "null argument");
+        WV_REQUIRE(fmt == AE_LATENT_BF16 || (fmt == AE_LATENT_FP8 && qscale), WV_EINVAL, "bad latent format/scale");
+        check_grid(g);
+        ae_encode_state(a, patch_grid(g->nz, g->ny, g->nx), state, fmt, latent, meta, qscale, (hipStream_t)stream);
+        return WV_OK;
+    });
+}
+
+int ae_decode(const ae_net* a, const wv_grid* g, const void* latent, const float* meta, const float* qscale, int fmt,
+              uint32_t mask, float* state, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && latent && meta && state, WV_EINVAL, "null argument");
+        WV_REQUIRE(fmt == AE_LATENT_BF16 || (fmt == AE_LATENT_FP8 && qscale), WV_EINVAL, "bad latent format/scale");
+        WV_REQUIRE((mask & ~0xFu) == 0, WV_EINVAL, "field mask has bits beyond the 4 fields");
+        check_grid(g);
+        ae_decode_state(a, patch_grid(g->nz, g->ny, g->nx), latent, meta, qscale, fmt, mask, state,
+                        (hipStream_t)stream);
+        return WV_OK;
+    });
+}
+
+int ae_train_step(ae_net* a, const uint16_t* y, const int32_t* idx, int32_t B, double lr, const ae_train_cfg* cfg,
+                  float* h_grads, double* h_loss, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && y && cfg && B > 0, WV_EINVAL, "bad argument");
+        WV_REQUIRE(B % 32 == 0, WV_EINVAL, "batch must be a multiple of 32");
+        hipStream_t st = (hipStream_t)stream;
+        const int splits = std::max(1, std::min(8, B / 512));
+        TrainBufs t = train_buffers(a, B, splits);
+        double* dloss = a->loss_d;
+        train_batch(a, y, idx, B, t, splits, dloss, 0, st);
+        if (h_grads) WV_HIP(hipMemcpyAsync(h_grads, a->grad, a->nparam * 4, hipMemcpyDeviceToHost, st));
+        adam_update(a, lr, *cfg, st);
+        double L = 0;
+        WV_HIP(hipMemcpyAsync(&L, dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        if (h_loss) *h_loss = L;
+        return WV_OK;
+    });
+}
+
+int ae_train(ae_net* a, const uint16_t* y, int64_t nsamples, const ae_train_cfg* cfg, const int32_t* perm,
+             float* h_loss, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && y && cfg, WV_EINVAL, "null argument");
+        WV_REQUIRE(cfg->batch > 0 && cfg->batch % 32 == 0, WV_EINVAL, "batch must be a positive multiple of 32");
+        WV_REQUIRE(cfg->epochs >= 0 && nsamples >= cfg->batch, WV_EINVAL, "need at least one full batch");
+        hipStream_t st = (hipStream_t)stream;
+        const int B = cfg->batch;
+        const int splits = std::max(1, std::min(8, B / 512));
+        TrainBufs t = train_buffers(a, B, splits);
+        double* dloss = a->loss_d;
+        const long long nb = nsamples / B;
+        std::vector<int> seq;
+        int* dseq = nullptr;
+        if (!perm) {
+            seq.resize(nsamples);
+            for (long long q = 0; q < nsamples; ++q) seq[q] = (int)q;
+            dseq = dalloc<int>(nsamples);
+            WV_HIP(hipMemcpyAsync(dseq, seq.data(), sizeof(int) * nsamples, hipMemcpyHostToDevice, st));
+        }
+        for (int e = 0; e < cfg->epochs; ++e) {
+            const double lr = cfg->lr * std::pow(cfg->decay_factor, (double)(e / std::max(cfg->decay_every, 1)));
+            const int* order = perm ? perm + (long long)e * nsamples : dseq;
+            for (long long b = 0; b < nb; ++b) {
+                train_batch(a, y, order + b * B, B, t, splits, dloss, b > 0, st);
+                adam_update(a, lr, *cfg, st);
+            }
+            double L = 0;
+            WV_HIP(hipMemcpyAsync(&L, dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+            WV_HIP(hipStreamSynchronize(st));
+            if (h_loss) h_loss[e] = (float)(L / (double)nb);
+        }
+        WV_HIP(hipStreamSynchronize(st));
+        if (dseq) (void)hipFree(dseq);
+        return WV_OK;
+    });
+}
+
+}  // extern "C"

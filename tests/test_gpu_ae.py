@@ -1,0 +1,275 @@
+"""GPU parity of the patch autoencoder against the FP64 oracle (rounding
+emulation mode), and the compressed gradient / Hv against the uncompressed
+ones.
+
+Tolerances follow from the precision contract: bfloat16 carries 8
+significant bits (relative spacing 2^-8), so a value that sits near a
+rounding tie can round one way in the float32-accumulated kernel and the
+other way in the float64 oracle. Such flips are rare and one ulp each, so
+outputs agree to a few 1e-3 in relative L2; normalisation itself (min,
+range, quotient) is exact and compared bit for bit."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ae as oae
+from oracle import rounding as rd
+from oracle import wave as ow
+from paper_2304_04781_amd import _lib as L
+from paper_2304_04781_amd.solver import WaveSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def flat_params(prm):
+    return np.concatenate([np.asarray(prm[k], np.float64).ravel() for k in oae.NAMES])
+
+
+def unflat(vec, dims=(2048, 512, 32)):
+    i, h, l = dims
+    shapes = [(i, h), (h,), (h, l), (l,), (l, h), (h,), (h, i), (i,)]
+    out, o = {}, 0
+    for k, s in zip(oae.NAMES, shapes):
+        n = int(np.prod(s))
+        out[k] = np.asarray(vec[o:o + n], np.float64).reshape(s)
+        o += n
+    return out
+
+
+class Net:
+    def __init__(self, prm, beta=(1e-7,) * 4):
+        self.prm32 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in prm.items()}
+        self.handle = L.ae_create(2048, 512, 32, flat_params(self.prm32), np.asarray(beta, np.float64))
+
+    def __del__(self):
+        L.ae_destroy(self.handle)
+
+
+def grid_of(shape):
+    nz, ny, nx = shape
+    return L.make_grid(nz, ny, nx, 20.0, 1e-3, 10, 0, 1.0, 1, 0)
+
+
+def state_tensor(shape, seed):
+    st = W.smooth_random_state(4, *shape, seed=seed).astype(np.float32)
+    return st, torch.tensor(st, device="cuda")
+
+
+SHAPE = (16, 24, 40)   # 2 x 3 x 5 = 30 patches (not a multiple of the 128-row GEMM tile)
+
+
+def test_normalize_bitwise():
+    net = Net(W.ae_init(seed=4), beta=(1e-9, 2e-9, 3e-9, 4e-9))
+    st, ts = state_tensor(SHAPE, 1)
+    st[0, :8, :8, :8] = 0.25            # a constant field slice: r = beta
+    ts = torch.tensor(st, device="cuda")
+    P = 30
+    y = torch.empty((P, 2048), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    L.ae_normalize(net.handle, grid_of(SHAPE), ts, y, meta)
+    torch.cuda.synchronize()
+    X = oae.patchify(st.astype(np.float64))
+    Y, lo, r = oae.normalize(X, np.float32([1e-9, 2e-9, 3e-9, 4e-9]).astype(np.float64), emulate=True)
+    m = meta.cpu().numpy()
+    assert np.array_equal(m[:, :, 0], lo) and np.array_equal(m[:, :, 1], r)
+    assert np.array_equal(y.cpu().numpy().view(np.uint16), rd.bf16_bits(Y))
+    assert np.all(y.cpu().numpy().view(np.uint16)[0, :512] == 0)
+
+
+@pytest.mark.parametrize("fmt", [L.LATENT_BF16, L.LATENT_FP8])
+def test_encode_decode_against_oracle(fmt):
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    st, ts = state_tensor(SHAPE, 2)
+    P = 30
+    lat = torch.empty((P, 32), dtype=torch.int16 if fmt == L.LATENT_BF16 else torch.uint8, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    qs = torch.empty((P,), dtype=torch.float32, device="cuda") if fmt == L.LATENT_FP8 else None
+    L.ae_encode(net.handle, grid_of(SHAPE), ts, fmt, lat, meta, qs)
+    out = torch.zeros((4,) + SHAPE, dtype=torch.float32, device="cuda")
+    L.ae_decode(net.handle, grid_of(SHAPE), lat, meta, qs, fmt, 0xF, out)
+    torch.cuda.synchronize()
+    ae = oae.AE(net.prm32)
+    X = oae.patchify(st.astype(np.float64))
+    Y, lo, r = oae.normalize(X, [1e-7] * 4, emulate=True)
+    z_o = ae.encode(Y, emulate=True)
+    if fmt == L.LATENT_BF16:
+        z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16))
+        z_ref = rd.bf16(z_o)
+        assert rel(z_gpu, z_ref) < 5e-3
+        # decoder on identical latents
+        dec_ref = ae.decode(z_gpu, emulate=True)
+    else:
+        codes = lat.cpu().numpy()
+        s = qs.cpu().numpy().astype(np.float64)
+        z_gpu = rd.e4m3_decode(codes) * s[:, None]
+        q_o, s_o = oae.fp8_quantize(z_o)
+        assert np.allclose(s, s_o, rtol=1e-5)
+        assert np.mean(codes == q_o) > 0.97
+        assert rel(z_gpu, rd.e4m3_decode(q_o) * s_o[:, None]) < 3e-2
+        dec_ref = ae.decode(rd.bf16(z_gpu), emulate=True)
+    x_ref = oae.unpatchify(oae.denormalize(dec_ref, lo, r), *SHAPE)
+    assert rel(out.cpu().numpy(), x_ref) < 5e-3
+    # e-only decode writes the e field and leaves the others untouched
+    out2 = torch.full((4,) + SHAPE, 7.0, dtype=torch.float32, device="cuda")
+    L.ae_decode(net.handle, grid_of(SHAPE), lat, meta, qs, fmt, 0x1, out2)
+    o2 = out2.cpu().numpy()
+    assert np.array_equal(o2[0], out.cpu().numpy()[0]) and np.all(o2[1:] == 7.0)
+
+
+def test_train_step_gradients_and_adam_against_oracle():
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    rng = np.random.default_rng(3)
+    n, B = 256, 128
+    X = np.concatenate([oae.patchify(W.smooth_random_state(4, 32, 32, 32, seed=s)) for s in range(5, 9)])[:n]
+    Y, _, _ = oae.normalize(X, [1e-7] * 4)
+    ybits = rd.bf16_bits(Y)
+    yt = torch.tensor(ybits.view(np.int16), device="cuda")
+    idx = rng.permutation(n)[:B].astype(np.int32)
+    it = torch.tensor(idx, device="cuda")
+    cfg = L.train_cfg(epochs=1, batch=B)
+    loss, g = L.ae_train_step(net.handle, yt, it, B, 1e-3, cfg, want_grads=True)
+    ae = oae.AE(net.prm32)
+    loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True)
+    assert abs(loss - loss_o) / loss_o < 1e-3
+    gg = unflat(g)
+    for k in oae.NAMES:
+        assert rel(gg[k], g_o[k]) < 2e-2, k
+    # Adam: the first step applied to the GPU's own gradients, in float64
+    new = unflat(L.ae_get_params(net.handle))
+    ref = {k: v.copy() for k, v in net.prm32.items()}
+    oae.Adam(ref, lr=1e-3).step(ref, {k: gg[k] for k in oae.NAMES})
+    for k in oae.NAMES:
+        assert np.allclose(new[k], ref[k], rtol=0, atol=2e-6 + 1e-6 * np.abs(ref[k]).max()), k
+
+
+def test_training_reduces_loss_and_beats_untrained():
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    states = [W.smooth_random_state(4, 32, 32, 32, seed=s).astype(np.float32) for s in range(10, 18)]
+    Ys = []
+    for st in states:
+        y = torch.empty((64, 2048), dtype=torch.int16, device="cuda")
+        meta = torch.empty((64, 4, 2), dtype=torch.float32, device="cuda")
+        L.ae_normalize(net.handle, grid_of((32, 32, 32)), torch.tensor(st, device="cuda"), y, meta)
+        Ys.append(y)
+    y = torch.cat(Ys)
+    n = y.shape[0]
+    perm = torch.tensor(W.shuffles(n, 30, seed=5), device="cuda")
+    cfg = L.train_cfg(epochs=30, batch=64, lr=1e-3, decay_every=10)
+    losses = L.ae_train(net.handle, y, n, cfg, perm)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_save_load_roundtrip():
+    net = Net(W.ae_init(seed=4), beta=(1e-7, 2e-7, 3e-7, 4e-7))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ae.bin")
+        L.ae_save(net.handle, path)
+        h = L.ae_load(path)
+        try:
+            assert np.array_equal(L.ae_get_params(h), L.ae_get_params(net.handle))
+            assert np.array_equal(L.ae_get_beta(h), L.ae_get_beta(net.handle))
+        finally:
+            L.ae_destroy(h)
+
+
+# ----- compressed gradient and Hv -------------------------------------------------------------------
+def ae_problem(nt=240, shape=(48, 48, 48)):
+    p = W.problem_3d(*shape, nt, f0=15.0, sponge=8, name="ae3d")
+    for k in ("c_true", "c_start", "wavelet"):
+        setattr(p, k, np.asarray(getattr(p, k), np.float32).astype(np.float64))
+    return p
+
+
+def trained_net(p, every=4, epochs=40):
+    """Snapshots of the forward solve at the start model train the network."""
+    net = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    _, _, cap = s.forward(p.c_start, p.wavelet, capture_every=every)
+    ncap = cap.shape[0]
+    g = s.grid
+    L.ae_fit_beta(net.handle, g, cap, ncap, 1e-7)
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    y = torch.empty((ncap * P, 2048), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    for q in range(ncap):
+        L.ae_normalize(net.handle, g, cap[q, 0], y[q * P:(q + 1) * P], meta)
+    n = ncap * P
+    batch = 64
+    perm = torch.tensor(W.shuffles(n, epochs, seed=5), device="cuda")
+    losses = L.ae_train(net.handle, y, n, L.train_cfg(epochs=epochs, batch=batch, lr=1e-3, decay_every=10), perm)
+    s.close()
+    return net, losses
+
+
+def test_compressed_gradient_and_hessvec():
+    p = ae_problem()
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    d = np.asarray(d, np.float32)
+    net, losses = trained_net(p)
+    print("training loss per epoch", losses[:3], losses[-3:], flush=True)
+    plain = WaveSolver.for_problem(p)
+    plain.set_storage(L.STORE_FULL)
+    J0, g0 = plain.gradient(p.c_start, p.wavelet, d, sigma)
+    res = {}
+    for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
+        s = WaveSolver.for_problem(p)
+        s.set_storage(mode, ae=net)
+        J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+        g0n, gn = g0.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+        err = rel(gn, g0n)
+        cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
+        res[mode] = (err, cos)
+        print("mode", mode, "J", J, J0, "rel err", err, "cos", cos, flush=True)
+        assert J == J0                  # the forward solve itself is not compressed
+        assert err < 0.15 and cos > 0.99
+        if mode == L.STORE_AE_BF16:
+            dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
+            H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+            H = s.hessvec(p.c_start, dc).cpu().numpy()
+            herr = rel(H, H0)
+            print("hessvec rel err", herr, flush=True)
+            assert herr < 0.15
+            assert s.storage_bytes() * 10 < plain.storage_bytes()
+    # an untrained network is clearly worse than the trained one
+    raw = Net(W.ae_init(seed=4))
+    L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_AE_BF16, ae=raw)
+    _, gu = s.gradient(p.c_start, p.wavelet, d, sigma)
+    err_u = rel(gu.cpu().numpy(), g0.cpu().numpy())
+    print("untrained rel err", err_u, flush=True)
+    assert err_u > 2 * res[L.STORE_AE_BF16][0]
+
+
+def test_guard_falls_back_to_checkpointing():
+    p = ae_problem(nt=120, shape=(32, 32, 32))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))          # untrained: the guard must trip
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_AE_BF16, n_checkpoints=6, ae=raw, guard_tol=0.05,
+                  fallback_policy=L.FALLBACK_CHECKPOINT)
+    J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+    assert s.last_status == L.OK_FALLBACK
+    _, gerr, degraded = s.stats()
+    assert degraded and gerr > 0.05
+    ref = WaveSolver.for_problem(p)
+    ref.set_storage(L.STORE_CHECKPOINT, n_checkpoints=6)
+    Jr, gr = ref.gradient(p.c_start, p.wavelet, d, sigma)
+    assert J == Jr and torch.equal(g, gr)
