@@ -562,6 +562,8 @@ long long ae_latent_bytes_per_patch(const ae_net* net, int fmt)
 void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, int fmt, void* latent, float* meta,
                      float* qscale, hipStream_t st)
 {
+    WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
+               "encode: null buffer");
     const long long P = pg.P;
     const size_t oy = 0, oh = align256(oy + P * 2048 * 2), oz = align256(oh + P * (size_t)a->hid * 2);
     uint8_t* ws = (uint8_t*)workspace(a, align256(oz + P * (size_t)a->lat * 4));
@@ -586,6 +588,8 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
 void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st)
 {
+    WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
+               "decode: null buffer");
     const long long P = pg.P;
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
     uint8_t* ws = (uint8_t*)workspace(a, align256(ozb + P * (size_t)a->lat * 2));

@@ -233,16 +233,6 @@ void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, lo
     launch_step(MODE_INC, c->has_y, a, c->S, c->st);
 }
 
-void ensure_adj(wv_ctx* c)
-{
-    if (!c->adj[0]) {
-        c->adj[0] = dev_alloc<float>(c->state_floats());
-        c->adj[1] = dev_alloc<float>(c->state_floats());
-        c->acc = dev_alloc<float>(2 * c->N * c->S);
-        c->ebuf = dev_alloc<float>(c->N * c->S);
-    }
-}
-
 void ensure_inc(wv_ctx* c)
 {
     if (!c->incb[0]) {
@@ -326,11 +316,23 @@ void store_state(wv_ctx* c, int n, const float* state)
     }
 }
 
+void ensure_adj(wv_ctx* c)
+{
+    if (!c->adj[0]) {
+        c->adj[0] = dev_alloc<float>(c->state_floats());
+        c->adj[1] = dev_alloc<float>(c->state_floats());
+        c->acc = dev_alloc<float>(2 * c->N * c->S);
+        c->ebuf = dev_alloc<float>(c->N * c->S);
+    }
+}
+
 // e^n of every source from the FULL or AE store: pointer + per-source stride
 const float* load_e(wv_ctx* c, int n, long long* stride)
 {
+    WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     *stride = c->N;
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
+    ensure_adj(c);  // owns the decode target ebuf
     const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
     for (int s = 0; s < c->S; ++s)
         ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),

@@ -216,6 +216,24 @@ def trained_net(p, every=4, epochs=40):
     return net, losses
 
 
+def test_guard_falls_back_to_checkpointing():
+    p = ae_problem(nt=120, shape=(32, 32, 32))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))          # untrained: the guard must trip
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_AE_BF16, n_checkpoints=6, ae=raw, guard_tol=0.05,
+                  fallback_policy=L.FALLBACK_CHECKPOINT)
+    J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+    assert s.last_status == L.OK_FALLBACK
+    _, gerr, degraded = s.stats()
+    assert degraded and gerr > 0.05
+    ref = WaveSolver.for_problem(p)
+    ref.set_storage(L.STORE_CHECKPOINT, n_checkpoints=6)
+    Jr, gr = ref.gradient(p.c_start, p.wavelet, d, sigma)
+    assert J == Jr and torch.equal(g, gr)
+
+
 def test_compressed_gradient_and_hessvec():
     p = ae_problem()
     sol = ow.solver_for(p)
@@ -255,21 +273,3 @@ def test_compressed_gradient_and_hessvec():
     err_u = rel(gu.cpu().numpy(), g0.cpu().numpy())
     print("untrained rel err", err_u, flush=True)
     assert err_u > 2 * res[L.STORE_AE_BF16][0]
-
-
-def test_guard_falls_back_to_checkpointing():
-    p = ae_problem(nt=120, shape=(32, 32, 32))
-    sol = ow.solver_for(p)
-    d, sigma, _ = ow.observed_data(sol, p)
-    raw = Net(W.ae_init(seed=4))          # untrained: the guard must trip
-    s = WaveSolver.for_problem(p)
-    s.set_storage(L.STORE_AE_BF16, n_checkpoints=6, ae=raw, guard_tol=0.05,
-                  fallback_policy=L.FALLBACK_CHECKPOINT)
-    J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
-    assert s.last_status == L.OK_FALLBACK
-    _, gerr, degraded = s.stats()
-    assert degraded and gerr > 0.05
-    ref = WaveSolver.for_problem(p)
-    ref.set_storage(L.STORE_CHECKPOINT, n_checkpoints=6)
-    Jr, gr = ref.gradient(p.c_start, p.wavelet, d, sigma)
-    assert J == Jr and torch.equal(g, gr)
