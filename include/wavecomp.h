@@ -101,6 +101,10 @@ typedef struct ae_train_cfg {
     int32_t decay_every;   /* the rate is multiplied by decay_factor every this many epochs */
     double decay_factor;
     double beta1, beta2, eps;  /* Adam constants */
+    int32_t weighting;     /* 0: plain mean squared error over the normalised
+                              vectors (Sec. 3.3.1); 1: each (sample, field)
+                              weighted by (r / beta_f)^2, i.e. the squared error
+                              in the field's physical scale (needs meta) */
 } ae_train_cfg;
 
 /* ---- context --------------------------------------------------------------------- */
@@ -112,6 +116,14 @@ typedef struct ae_train_cfg {
  * the grid, WV_ENOMEM when work buffers cannot be allocated. */
 int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec,
               void* stream, wv_ctx** out);
+
+/* Spatial shape of every source (paper Sec. 4.1: the Ricker force is smoothed
+ * by a narrow Gaussian in space). The force density on the v_z faces is
+ * wavelet[s][n] * w[dk][(dj)][di] at offsets |dk|, |dj|, |di| <= radius from the
+ * source face (dk slowest; no dj in 2D), truncated at the grid boundary.
+ * h_weights: host float32 [(2 radius + 1)^dims]. Default: radius 0, weight 1
+ * (a point force). Invalidates the stored history. */
+int wv_set_source_stencil(wv_ctx* ctx, int32_t radius, const float* h_weights);
 
 /* Free every buffer the context owns. Safe on NULL. */
 int wv_destroy(wv_ctx* ctx);
@@ -127,6 +139,14 @@ int wv_destroy(wv_ctx* ctx);
  * checkpointing and return WV_OK_FALLBACK. Allocation happens here. */
 int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
                    int64_t mem_budget_bytes, double guard_tol, int fallback_policy);
+
+/* Error bounding for the AE modes: after compressing a state, the k_per_step
+ * patches with the largest e-field range r (ties: lower patch index first) also
+ * keep their e values exactly (float32), and decompression of e restores them.
+ * 0 (default) stores latents only, as in the paper; the paper mentions storing
+ * residuals to bound the error (Sec. 1, Sec. 3.3). Takes effect at the next
+ * wv_set_storage. */
+int wv_set_ae_exceptions(wv_ctx* ctx, int32_t k_per_step);
 
 /* Bytes of history storage the current mode holds (after wv_set_storage). */
 int wv_storage_bytes(const wv_ctx* ctx, int64_t* h_bytes);
@@ -217,19 +237,23 @@ int ae_decode(const ae_net* net, const wv_grid* grid, const void* latent, const 
               void* stream);
 
 /* Train on nsamples normalised vectors y [nsamples][2048] (bfloat16 bits, e.g.
- * from ae_normalize) by minimising the mean squared reconstruction error with
- * Adam (Sec. 3.3.1 loss, Table 2 schedule). perm: device int32
- * [epochs][nsamples] visiting order per epoch (NULL = in order).
- * h_loss_per_epoch (host, may be NULL) receives the mean batch loss per epoch. */
-int ae_train(ae_net* net, const uint16_t* y, int64_t nsamples, const ae_train_cfg* h_cfg,
-             const int32_t* perm, float* h_loss_per_epoch, void* stream);
+ * from ae_normalize) by minimising the (optionally weighted) mean squared
+ * reconstruction error with Adam (Sec. 3.3.1 loss, Table 2 schedule).
+ * meta: [nsamples][4][2] from ae_normalize (required when h_cfg->weighting = 1,
+ * else may be NULL). perm: device int32 [epochs][nsamples] visiting order per
+ * epoch (NULL = in order). h_loss_per_epoch (host, may be NULL) receives the
+ * mean batch loss per epoch. The batch must be a multiple of 32. */
+int ae_train(ae_net* net, const uint16_t* y, const float* meta, int64_t nsamples,
+             const ae_train_cfg* h_cfg, const int32_t* perm, float* h_loss_per_epoch,
+             void* stream);
 
-/* One training step on a batch given explicitly (rows idx[0..batch) of y) and,
- * if h_grads is non-NULL, the float32 parameter gradients of that step (layout
- * as h_init) copied to the host before the Adam update. Returns the batch loss. */
-int ae_train_step(ae_net* net, const uint16_t* y, const int32_t* idx, int32_t batch,
-                  double lr, const ae_train_cfg* h_cfg, float* h_grads, double* h_loss,
-                  void* stream);
+/* One training step on a batch given explicitly (rows idx[0..batch) of y and
+ * meta) and, if h_grads is non-NULL, the float32 parameter gradients of that
+ * step (layout as h_init) copied to the host before the Adam update. Returns
+ * the batch loss. */
+int ae_train_step(ae_net* net, const uint16_t* y, const float* meta, const int32_t* idx,
+                  int32_t batch, double lr, const ae_train_cfg* h_cfg, float* h_grads,
+                  double* h_loss, void* stream);
 
 /* ---- host-only helpers ---------------------------------------------------------- */
 

@@ -151,16 +151,27 @@ class AE:
         out = h3 @ W4 + b4
         return rd.f32(out) if emulate else out
 
-    def loss_and_grads(self, Y: np.ndarray, emulate: bool = False, latent: str = "bf16"):
-        """MSE loss (1/(B*n)) sum (yhat - y)^2 and its parameter gradients."""
+    def loss_and_grads(self, Y: np.ndarray, emulate: bool = False, latent: str = "bf16",
+                       field_weights: Optional[np.ndarray] = None):
+        """MSE loss (1/(B*n)) sum (yhat - y)^2 and its parameter gradients.
+        field_weights [B, F] (optional) weights each sample's F equal field
+        slices of length n/F: loss = sum_bf w_bf sum_i (yhat - y)^2 /
+        ((n/F) sum_bf w_bf), which reduces to the plain MSE for equal weights."""
         w = self.weights(emulate)
         f = self.forward(Y, emulate, latent)
         q = rd.bf16 if emulate else (lambda t: t)
         B, n = Y.shape
         diff = f["yhat"] - f["y"]
-        loss = float(np.sum(diff * diff)) / (B * n)
+        if field_weights is None:
+            fw, norm = 1.0, float(B * n)
+        else:
+            fwb = np.asarray(field_weights, dtype=np.float64)
+            seg = n // fwb.shape[1]
+            fw = np.repeat(fwb, seg, axis=1)
+            norm = seg * float(np.sum(fwb))
+        loss = float(np.sum(fw * diff * diff)) / norm
         g = {}
-        d4 = 2.0 * diff / (B * n)
+        d4 = 2.0 * fw * diff / norm
         d4q = q(d4)
         g["W4"] = f["h3"].T @ d4q
         g["b4"] = d4.sum(axis=0)

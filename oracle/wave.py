@@ -120,19 +120,35 @@ class Solver:
 
     def step(self, v: dict, e: np.ndarray, m: np.ndarray, force: Optional[Tuple] = None,
              extra: Optional[np.ndarray] = None):
-        """One leapfrog step. `force` = ((k, j, i), b) adds dt*b to v_z at that
-        face; `extra` is an additional field inside G (used by the incremental
+        """One leapfrog step. `force` = ((k, j, i), b, w) adds dt*b*w to v_z on
+        the faces of the box of half-width R = (w.shape[0]-1)/2 centred at
+        (k, j, i), truncated at the grid boundary (w = None: point force);
+        `extra` is an additional field inside G (used by the incremental
         forward for the dm * e term)."""
         q = m * e if extra is None else m * e + extra
         vn = {}
         for a in self.axes:
             g = self.G(q, a)
             if a == 0 and force is not None:
-                (k, j, i), b = force
-                g[k, j, i] += b
+                (k, j, i), b, w = force
+                if w is None:
+                    g[k, j, i] += b
+                else:
+                    self._add_box(g, (k, j, i), b * w)
             vn[a] = self.S_v[a] * (v[a] + self.dt * g)
         en = self.S_e * (e + self.dt * self.D(vn))
         return vn, en
+
+    def _add_box(self, g: np.ndarray, centre, vals: np.ndarray):
+        lo, src = [], []
+        for ax in range(3):
+            r = (vals.shape[ax] - 1) // 2
+            a0 = centre[ax] - r
+            s0 = max(0, -a0)
+            s1 = vals.shape[ax] - max(0, a0 + vals.shape[ax] - self.shape[ax])
+            lo.append(slice(a0 + s0, a0 + s1))
+            src.append(slice(s0, s1))
+        g[tuple(lo)] += vals[tuple(src)]
 
     def step_T(self, mu: dict, eta: np.ndarray, m: np.ndarray):
         """Transpose of the linear map (v^n, e^n) -> (v^{n+1}, e^{n+1}) of
@@ -154,10 +170,10 @@ def _rec_index(rec: np.ndarray):
 
 
 def forward(sol: Solver, c: np.ndarray, wavelet: np.ndarray, src: np.ndarray, rec: np.ndarray,
-            store_e: bool = True, store_v: bool = False):
+            store_e: bool = True, store_v: bool = False, src_w: Optional[np.ndarray] = None):
     """Forward solve for every source. Returns traces [S, T, R] (traces[s, n]
     = p^{n+1}) and, if requested, e history [S, T+1, ...] (index n = e^n) and
-    the final states."""
+    the final states. src_w: spatial weights of every source (None: point)."""
     m = c * c
     T = sol.nt
     S = len(src)
@@ -171,7 +187,7 @@ def forward(sol: Solver, c: np.ndarray, wavelet: np.ndarray, src: np.ndarray, re
         ks, js, is_ = (int(x) for x in src[s])
         vs = [] if store_v else None
         for n in range(T):
-            v, e = sol.step(v, e, m, force=((ks, js, is_), wavelet[s, n]))
+            v, e = sol.step(v, e, m, force=((ks, js, is_), wavelet[s, n], src_w))
             traces[s, n] = v[0][ri]
             if store_e:
                 e_hist[s, n + 1] = e
@@ -219,9 +235,10 @@ def adjoint_acc(sol: Solver, c: np.ndarray, e_hist_s: np.ndarray, resid_s: np.nd
     return (acc, dacc) if second else acc
 
 
-def gradient(sol: Solver, c: np.ndarray, wavelet: np.ndarray, src, rec, d_obs, sigma: float):
+def gradient(sol: Solver, c: np.ndarray, wavelet: np.ndarray, src, rec, d_obs, sigma: float,
+             src_w: Optional[np.ndarray] = None):
     """Misfit J and dJ/dc = -2 dt c * sum_s acc_s (summed over sources)."""
-    traces, e_hist, _, _ = forward(sol, c, wavelet, src, rec)
+    traces, e_hist, _, _ = forward(sol, c, wavelet, src, rec, src_w=src_w)
     J, resid = misfit(sol, traces, d_obs, sigma)
     acc = np.zeros(sol.shape)
     for s in range(len(src)):
@@ -282,7 +299,7 @@ def observed_data(sol: Solver, problem, noise_level: Optional[float] = None):
     """d = F(c_true) + sigma xi, sigma = noise_level * max|F(c_true)| (per run)."""
     lvl = problem.noise_level if noise_level is None else noise_level
     clean, _, _, _ = forward(sol, problem.c_true, problem.wavelet, problem.src, problem.rec,
-                             store_e=False)
+                             store_e=False, src_w=problem.src_w)
     sigma = lvl * float(np.max(np.abs(clean)))
     if sigma == 0.0:
         sigma = 1.0

@@ -36,13 +36,14 @@ class WvGrid(C.Structure):
 class AeTrainCfg(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
                 ("decay_every", C.c_int32), ("decay_factor", C.c_double), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("weighting", C.c_int32)]
 
 
 EXPORTS = {
     # name: (restype, argtypes)
     "wv_create": (C.c_int, [C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "wv_destroy": (C.c_int, [C.c_void_p]),
+    "wv_set_source_stencil": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "wv_set_storage": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int64, C.c_double, C.c_int]),
     "wv_storage_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "wave_forward": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_int32]),
@@ -65,10 +66,11 @@ EXPORTS = {
                             C.c_void_p, C.c_void_p]),
     "ae_decode": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                             C.c_uint32, C.c_void_p, C.c_void_p]),
-    "ae_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(AeTrainCfg), C.c_void_p, C.c_void_p,
-                           C.c_void_p]),
-    "ae_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+    "ae_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(AeTrainCfg), C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "ae_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                                 C.POINTER(AeTrainCfg), C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "wv_set_ae_exceptions": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_revolve_schedule": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
     "wv_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -142,6 +144,13 @@ def wv_set_storage(ctx, mode, n_checkpoints=0, ae=None, mem_budget_bytes=0, guar
                    fallback_policy=FALLBACK_NONE) -> int:
     return _check(load().wv_set_storage(ctx, mode, n_checkpoints, ae, mem_budget_bytes, guard_tol,
                                         fallback_policy))
+
+
+def wv_set_source_stencil(ctx, weights: np.ndarray) -> int:
+    """weights: (2R+1, 2R+1 | 1, 2R+1) array; R inferred from its first axis."""
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    R = (w.shape[0] - 1) // 2
+    return _check(load().wv_set_source_stencil(ctx, R, w.ctypes.data))
 
 
 def wv_storage_bytes(ctx) -> int:
@@ -269,26 +278,30 @@ def ae_decode(net, grid: WvGrid, latent, meta, qscale, latent_fmt, field_mask, s
 
 
 def train_cfg(epochs=20, batch=4096, lr=1e-3, decay_every=5, decay_factor=0.5, beta1=0.9, beta2=0.999,
-              eps=1e-8) -> AeTrainCfg:
+              eps=1e-8, weighting=0) -> AeTrainCfg:
     return AeTrainCfg(int(epochs), int(batch), float(lr), int(decay_every), float(decay_factor),
-                      float(beta1), float(beta2), float(eps))
+                      float(beta1), float(beta2), float(eps), int(weighting))
 
 
-def ae_train(net, y, nsamples: int, cfg: AeTrainCfg, perm=None, stream=None) -> np.ndarray:
+def ae_train(net, y, nsamples: int, cfg: AeTrainCfg, perm=None, meta=None, stream=None) -> np.ndarray:
     loss = np.zeros(max(cfg.epochs, 1), dtype=np.float32)
-    _check(load().ae_train(net, ptr(y, torch.int16), int(nsamples), C.byref(cfg), ptr(perm, torch.int32),
-                           loss.ctypes.data, stream_handle(stream)))
+    _check(load().ae_train(net, ptr(y, torch.int16), ptr(meta, torch.float32), int(nsamples), C.byref(cfg),
+                           ptr(perm, torch.int32), loss.ctypes.data, stream_handle(stream)))
     return loss
 
 
 def ae_train_step(net, y, idx, batch: int, lr: float, cfg: AeTrainCfg, want_grads: bool = False,
-                  stream=None):
+                  meta=None, stream=None):
     grads = np.zeros(ae_param_count(net), dtype=np.float32) if want_grads else None
     loss = C.c_double()
-    _check(load().ae_train_step(net, ptr(y, torch.int16), ptr(idx, torch.int32), int(batch), float(lr),
-                                C.byref(cfg), None if grads is None else grads.ctypes.data, C.byref(loss),
-                                stream_handle(stream)))
+    _check(load().ae_train_step(net, ptr(y, torch.int16), ptr(meta, torch.float32), ptr(idx, torch.int32),
+                                int(batch), float(lr), C.byref(cfg), None if grads is None else grads.ctypes.data,
+                                C.byref(loss), stream_handle(stream)))
     return loss.value, grads
+
+
+def wv_set_ae_exceptions(ctx, k_per_step: int) -> int:
+    return _check(load().wv_set_ae_exceptions(ctx, int(k_per_step)))
 
 
 def wv_last_error() -> str:

@@ -323,19 +323,51 @@ __global__ void dequantize_kernel(const uint8_t* __restrict__ q, const float* __
 // ------------------------------------------------------------------------------------
 // training helpers
 // ------------------------------------------------------------------------------------
-// yhat fp32 [B][n], y = bf16 rows idx -> d = 2 (yhat - y)/(B n) (bf16 + fp32), loss partials
+// per-sample field weights w[b][f] = (r / beta_f)^2 (weighting = 1) or 1, and
+// their float64 total
+__global__ void batch_weights_kernel(const float* __restrict__ meta, const int* __restrict__ idx, int B,
+                                     const float* __restrict__ beta, int weighting, float* __restrict__ w,
+                                     double* __restrict__ wsum)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < 4 * B; q += 256) {
+        const int b = q >> 2, f = q & 3;
+        float v = 1.0f;
+        if (weighting) {
+            const long long src = idx ? idx[b] : b;
+            const float t = meta[src * 8 + 2 * f + 1] / beta[f];
+            v = t * t;
+        }
+        w[q] = v;
+        acc += v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wsum[0] = sh[0];
+}
+
+// yhat fp32 [B][n], y = bf16 rows idx: loss = sum_b,f w_bf sum_i (yhat - y)^2 / (512 W),
+// d = 2 w_bf (yhat - y) / (512 W) (bf16 + fp32), per-sample loss partials
 __global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ yhat, const uint16_t* __restrict__ y,
-                                                 const int* __restrict__ idx, int B, int n, float scale,
+                                                 const int* __restrict__ idx, int B, int n,
+                                                 const float* __restrict__ w, const double* __restrict__ wsum,
                                                  uint16_t* __restrict__ dq, float* __restrict__ df,
                                                  double* __restrict__ partial)
 {
     const int b = blockIdx.x;
     const long long src = idx ? idx[b] : b;
+    const double norm = 512.0 * wsum[0];
     double acc = 0.0;
     for (int c = threadIdx.x; c < n; c += 256) {
+        const float wf = w[b * 4 + (c >> 9)];
         const float diff = yhat[(long long)b * n + c] - bf2f(y[src * n + c]);
-        acc += (double)diff * diff;
-        const float d = scale * diff;
+        acc += (double)wf * diff * diff;
+        const float d = (float)(2.0 * wf / norm) * diff;
         dq[(long long)b * n + c] = f2bf(d);
         df[(long long)b * n + c] = d;
     }
@@ -346,7 +378,7 @@ __global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ yhat
         if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[b] = sh[0];
+    if (threadIdx.x == 0) partial[b] = sh[0] / norm;
 }
 
 __global__ void sum_partials_kernel(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
@@ -617,9 +649,9 @@ namespace {
 
 // One Adam step on a batch. Returns (device) the batch loss in *dloss (added if accumulate).
 struct TrainBufs {
-    float *a1, *a3, *yhat, *d4f, *d3f, *dzf, *d1f, *zf, *part;
+    float *a1, *a3, *yhat, *d4f, *d3f, *dzf, *d1f, *zf, *part, *w;
     uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
-    double* lpart;
+    double *lpart, *wsum;
 };
 
 TrainBufs train_buffers(const ae_net* a, int B, int splits)
@@ -635,7 +667,8 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
                  o_d3f = take(B * hid * 4), o_dzf = take(B * lat * 4), o_d1f = take(B * hid * 4),
                  o_zf = take(B * lat * 4), o_part = take((size_t)splits * in * hid * 4), o_h1 = take(B * hid * 2),
                  o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
-                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8);
+                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8), o_w = take(B * 16),
+                 o_ws = take(8);
     uint8_t* w = (uint8_t*)workspace(a, o);
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
@@ -655,6 +688,8 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
     t.dz = (uint16_t*)(w + o_dz);
     t.d1 = (uint16_t*)(w + o_d1);
     t.lpart = (double*)(w + o_lp);
+    t.w = (float*)(w + o_w);
+    t.wsum = (double*)(w + o_ws);
     return t;
 }
 
@@ -668,8 +703,8 @@ void weight_grad(ae_net* a, int l, int B, const LX& lx, const LD& ld, float* par
     hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, part, splits, n, a->grad + a->oW[l]);
 }
 
-void train_batch(ae_net* a, const uint16_t* y, const int* idx, int B, TrainBufs& t, int splits, double* dloss,
-                 int accumulate, hipStream_t st)
+void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting, const int* idx, int B,
+                 TrainBufs& t, int splits, double* dloss, int accumulate, hipStream_t st)
 {
     const int in = a->in, hid = a->hid, lat = a->lat;
     // forward
@@ -681,10 +716,11 @@ void train_batch(ae_net* a, const uint16_t* y, const int* idx, int B, TrainBufs&
               EpiGelu{t.h3, hid, a->bias(2), t.a3}, st);
     gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
               EpiF32{t.yhat, in, 0, a->bias(3)}, st);
-    hipLaunchKernelGGL(mse_kernel, dim3(B), dim3(256), 0, st, t.yhat, y, idx, B, in, 2.0f / ((float)B * in), t.d4,
-                       t.d4f, t.lpart);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lpart, B, 1.0 / ((double)B * in), dloss,
-                       accumulate);
+    hipLaunchKernelGGL(batch_weights_kernel, dim3(1), dim3(256), 0, st, meta, idx, B, a->beta_d, weighting, t.w,
+                       t.wsum);
+    hipLaunchKernelGGL(mse_kernel, dim3(B), dim3(256), 0, st, t.yhat, y, idx, B, in, t.w, t.wsum, t.d4, t.d4f,
+                       t.lpart);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lpart, B, 1.0, dloss, accumulate);
     // backward: layer 4
     weight_grad(a, 3, B, LoadT{t.h3, hid, nullptr, hid, B}, LoadT{t.d4, in, nullptr, in, B}, t.part, splits, st);
     colsum(t.d4f, B, in, t.part, a->grad + a->ob[3], st);
@@ -959,17 +995,18 @@ int ae_decode(const ae_net* a, const wv_grid* g, const void* latent, const float
     });
 }
 
-int ae_train_step(ae_net* a, const uint16_t* y, const int32_t* idx, int32_t B, double lr, const ae_train_cfg* cfg,
-                  float* h_grads, double* h_loss, void* stream)
+int ae_train_step(ae_net* a, const uint16_t* y, const float* meta, const int32_t* idx, int32_t B, double lr,
+                  const ae_train_cfg* cfg, float* h_grads, double* h_loss, void* stream)
 {
     return guarded_ae([&]() -> int {
         WV_REQUIRE(a && y && cfg && B > 0, WV_EINVAL, "bad argument");
+        WV_REQUIRE(!cfg->weighting || meta, WV_EINVAL, "weighted loss needs meta");
         WV_REQUIRE(B % 32 == 0, WV_EINVAL, "batch must be a multiple of 32");
         hipStream_t st = (hipStream_t)stream;
         const int splits = std::max(1, std::min(8, B / 512));
         TrainBufs t = train_buffers(a, B, splits);
         double* dloss = a->loss_d;
-        train_batch(a, y, idx, B, t, splits, dloss, 0, st);
+        train_batch(a, y, meta, cfg->weighting, idx, B, t, splits, dloss, 0, st);
         if (h_grads) WV_HIP(hipMemcpyAsync(h_grads, a->grad, a->nparam * 4, hipMemcpyDeviceToHost, st));
         adam_update(a, lr, *cfg, st);
         double L = 0;
@@ -980,11 +1017,12 @@ int ae_train_step(ae_net* a, const uint16_t* y, const int32_t* idx, int32_t B, d
     });
 }
 
-int ae_train(ae_net* a, const uint16_t* y, int64_t nsamples, const ae_train_cfg* cfg, const int32_t* perm,
-             float* h_loss, void* stream)
+int ae_train(ae_net* a, const uint16_t* y, const float* meta, int64_t nsamples, const ae_train_cfg* cfg,
+             const int32_t* perm, float* h_loss, void* stream)
 {
     return guarded_ae([&]() -> int {
         WV_REQUIRE(a && y && cfg, WV_EINVAL, "null argument");
+        WV_REQUIRE(!cfg->weighting || meta, WV_EINVAL, "weighted loss needs meta");
         WV_REQUIRE(cfg->batch > 0 && cfg->batch % 32 == 0, WV_EINVAL, "batch must be a positive multiple of 32");
         WV_REQUIRE(cfg->epochs >= 0 && nsamples >= cfg->batch, WV_EINVAL, "need at least one full batch");
         hipStream_t st = (hipStream_t)stream;
@@ -1005,7 +1043,7 @@ int ae_train(ae_net* a, const uint16_t* y, int64_t nsamples, const ae_train_cfg*
             const double lr = cfg->lr * std::pow(cfg->decay_factor, (double)(e / std::max(cfg->decay_every, 1)));
             const int* order = perm ? perm + (long long)e * nsamples : dseq;
             for (long long b = 0; b < nb; ++b) {
-                train_batch(a, y, order + b * B, B, t, splits, dloss, b > 0, st);
+                train_batch(a, y, meta, cfg->weighting, order + b * B, B, t, splits, dloss, b > 0, st);
                 adam_update(a, lr, *cfg, st);
             }
             double L = 0;

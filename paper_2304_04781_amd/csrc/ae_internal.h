@@ -26,4 +26,11 @@ void ae_encode_state(const ae_net* net, const PatchGrid& pg, const float* state,
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st);
 
+// Select the K largest-e-range patches of one compressed state (meta [P][4][2])
+// into idx [K] (increasing patch order) and copy their e values to exc [K][512].
+void exceptions_store(const PatchGrid& pg, const float* state, const float* meta, int K, int* idx, float* exc,
+                      hipStream_t st);
+// Write the stored e values back into an e field [N].
+void exceptions_restore(const PatchGrid& pg, float* e, int K, const int* idx, const float* exc, hipStream_t st);
+
 }  // namespace wv

@@ -73,6 +73,9 @@ struct wv_ctx {
     float *wzc = nullptr, *wzf = nullptr, *wyc = nullptr, *wyf = nullptr, *wxc = nullptr, *wxf = nullptr;
     Tiling tl;
 
+    int* src_kji = nullptr;      // [S][3]
+    float* src_w = nullptr;      // source stencil weights
+    int src_radius = 0;
     float* m = nullptr;
     float* c_last = nullptr;
     float* wavelet = nullptr;
@@ -102,6 +105,10 @@ struct wv_ctx {
     uint8_t* lat = nullptr;      // AE latents [T-1][S][P][L]
     float* meta = nullptr;       // [T-1][S][P][4][2]
     float* qs = nullptr;         // [T-1][S][P]
+    int exc_req = 0;             // requested exception patches per state
+    int K = 0;                   // active exception patches per state
+    int* exc_idx = nullptr;      // [T-1][S][K]
+    float* exc = nullptr;        // [T-1][S][K][512]
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -176,8 +183,9 @@ StepArgs base_args(const wv_ctx* c)
     a.dt = (float)c->g.dt;
     a.wzc = c->wzc; a.wzf = c->wzf; a.wyc = c->wyc; a.wyf = c->wyf; a.wxc = c->wxc; a.wxf = c->wxf;
     a.m = c->m;
-    a.src_ptr = c->tl.src_ptr;
-    a.src_ent = c->tl.src_ent;
+    a.src_kji = c->src_kji;
+    a.src_radius = c->src_radius;
+    a.src_w = c->src_w;
     a.wavelet = c->wavelet;
     a.nt = c->T;
     a.rec_ptr = c->tl.rec_ptr;
@@ -249,6 +257,9 @@ void free_store(wv_ctx* c)
     dev_free(c->lat);
     dev_free(c->meta);
     dev_free(c->qs);
+    dev_free(c->exc_idx);
+    dev_free(c->exc);
+    c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
 }
@@ -310,9 +321,15 @@ void store_state(wv_ctx* c, int n, const float* state)
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-        for (int s = 0; s < c->S; ++s)
+        for (int s = 0; s < c->S; ++s) {
             ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
                             meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
+            if (c->K > 0) {
+                const long long q = (long long)(n - 1) * c->S + s;
+                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
+                                 c->exc + q * c->K * 512, c->st);
+            }
+        }
     }
 }
 
@@ -334,9 +351,14 @@ const float* load_e(wv_ctx* c, int n, long long* stride)
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
     ensure_adj(c);  // owns the decode target ebuf
     const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-    for (int s = 0; s < c->S; ++s)
+    for (int s = 0; s < c->S; ++s) {
         ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
                         ae_fmt(c->mode), 1u, c->ebuf + s * c->N, c->st);
+        if (c->K > 0) {
+            const long long q = (long long)(n - 1) * c->S + s;
+            exceptions_restore(pg, c->ebuf + s * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512, c->st);
+        }
+    }
     return c->ebuf;
 }
 
@@ -513,7 +535,12 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         check_pts(src, "source");
         check_pts(rec, "receiver");
         build_tables(c.get());
-        c->tl = make_tiling(g.nz, g.ny, g.nx, src, rec);
+        c->tl = make_tiling(g.nz, g.ny, g.nx, rec);
+        c->src_kji = dev_alloc<int>(src.size());
+        WV_HIP(hipMemcpy(c->src_kji, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice));
+        const float one = 1.0f;
+        c->src_w = dev_alloc<float>(1);
+        WV_HIP(hipMemcpy(c->src_w, &one, sizeof(float), hipMemcpyHostToDevice));
         c->m = dev_alloc<float>(c->N);
         c->c_last = dev_alloc<float>(c->N);
         c->wavelet = dev_alloc<float>((size_t)c->S * c->T);
@@ -538,6 +565,8 @@ int wv_destroy(wv_ctx* c)
     free_store(c);
     free_tiling(c->tl);
     dev_free(c->tab);
+    dev_free(c->src_kji);
+    dev_free(c->src_w);
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
                       &c->incb[0], &c->incb[1], &c->acc, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr})
         dev_free(*p);
@@ -584,17 +613,54 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             c->P = pg.P;
             c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
             const long long slots = (long long)std::max(T - 1, 1) * c->S;
-            const long long bytes = slots * c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0));
+            const int K = (int)std::min<long long>(c->exc_req, c->P);
+            const long long bytes = slots * (c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0)) +
+                                             (long long)K * (512 * 4 + 4));
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
             c->lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
             c->meta = dev_alloc<float>(slots * c->P * 8);
             if (mode == WV_STORE_AE_FP8) c->qs = dev_alloc<float>(slots * c->P);
+            if (K > 0) {
+                c->exc_idx = dev_alloc<int>(slots * K);
+                c->exc = dev_alloc<float>(slots * K * 512);
+            }
+            c->K = K;
             c->store_bytes = bytes;
             if (fallback_policy == WV_FALLBACK_CHECKPOINT)
                 WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
         }
         return WV_OK;
     });
+}
+
+int wv_set_source_stencil(wv_ctx* c, int32_t radius, const float* h_weights)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && h_weights, WV_EINVAL, "null argument");
+        WV_REQUIRE(radius >= 0 && radius <= 64, WV_EINVAL, "source radius must be in [0, 64]");
+        const long long w = 2LL * radius + 1;
+        const long long n = c->has_y ? w * w * w : w * w;
+        for (long long q = 0; q < n; ++q)
+            WV_REQUIRE(std::isfinite(h_weights[q]), WV_EINVAL, "source weights must be finite");
+        WV_HIP(hipStreamSynchronize(c->st));
+        dev_free(c->src_w);
+        c->src_w = dev_alloc<float>(n);
+        WV_HIP(hipMemcpy(c->src_w, h_weights, sizeof(float) * n, hipMemcpyHostToDevice));
+        c->src_radius = radius;
+        c->store_ok = false;
+        c->have_grad = false;
+        return WV_OK;
+    });
+}
+
+int wv_set_ae_exceptions(wv_ctx* c, int32_t k_per_step)
+{
+    if (!c || k_per_step < 0) {
+        set_error("bad argument");
+        return WV_EINVAL;
+    }
+    c->exc_req = k_per_step;
+    return WV_OK;
 }
 
 int wv_storage_bytes(const wv_ctx* c, int64_t* h_bytes)

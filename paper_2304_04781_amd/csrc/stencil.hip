@@ -111,22 +111,31 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
         return (a.wzc[k] * wyx) * inA[off];
     };
 
-    // point-list cursors (uniform across the work-group)
-    int sp = 0, se = 0, rp = 0, re = 0;
-    if (MODE == MODE_FWD) { sp = a.src_ptr[tile]; se = a.src_ptr[tile + 1]; }
+    // receiver-list cursors (uniform across the work-group)
+    int rp = 0, re = 0;
     if (a.nrec > 0) { rp = a.rec_ptr[tile]; re = a.rec_ptr[tile + 1]; }
+    // source of this wavefield: force density wavelet[s][n] * w[dk][dj][di] on the
+    // v_z faces of a (2R+1)^dims box centred on its face
+    int sk = 0, sj = 0, si = 0, R = 0;
+    float bsrc = 0.f;
+    if (MODE == MODE_FWD) {
+        sk = a.src_kji[3 * s];
+        sj = a.src_kji[3 * s + 1];
+        si = a.src_kji[3 * s + 2];
+        R = a.src_radius;
+        bsrc = a.dt * a.wavelet[(long long)s * a.nt + a.step];
+    }
+    const int wdj = HAS_Y ? 2 * R + 1 : 1;
+    const bool src_col = MODE == MODE_FWD && inside && abs(i - si) <= R && (HAS_Y ? abs(j - sj) <= R : true);
+    const int src_col_off = src_col ? (HAS_Y ? (j - sj + R) : 0) * (2 * R + 1) + (i - si + R) : 0;
     int tp = rp;  // trace-recording cursor (forward / incremental)
 
     // extra term on the v_z face kk: dt b (forward source), B^T r (adjoint)
     auto face_inj = [&](int kk) -> float {
         float add = 0.f;
         if (MODE == MODE_FWD) {
-            while (sp < se && a.src_ent[sp].x < kk) ++sp;
-            for (int q = sp; q < se; ++q) {
-                const int4 e = a.src_ent[q];
-                if (e.x != kk) break;
-                if (e.y == local && e.z == s) add += a.dt * a.wavelet[(long long)s * a.nt + a.step];
-            }
+            if (src_col && abs(kk - sk) <= R)
+                add = bsrc * a.src_w[(kk - sk + R) * wdj * (2 * R + 1) + src_col_off];
         } else if (MODE == MODE_ADJ) {
             while (rp < re && a.rec_ent[rp].x < kk) ++rp;
             for (int q = rp; q < re; ++q) {
@@ -300,8 +309,7 @@ void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t 
     WV_HIP(hipGetLastError());
 }
 
-Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& src_kji,
-                   const std::vector<int>& rec_kji)
+Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji)
 {
     Tiling t;
     const bool has_y = ny > 1;
@@ -342,7 +350,6 @@ Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& src_kji,
         if (!ent.empty())
             WV_HIP(hipMemcpy(*d_ent, ent.data(), sizeof(int4) * ent.size(), hipMemcpyHostToDevice));
     };
-    bucket(src_kji, &t.src_ptr, &t.src_ent);
     bucket(rec_kji, &t.rec_ptr, &t.rec_ent);
     return t;
 }
@@ -351,10 +358,8 @@ void free_tiling(Tiling& t)
 {
     if (t.rec_ptr) (void)hipFree(t.rec_ptr);
     if (t.rec_ent) (void)hipFree(t.rec_ent);
-    if (t.src_ptr) (void)hipFree(t.src_ptr);
-    if (t.src_ent) (void)hipFree(t.src_ent);
-    t.rec_ptr = t.src_ptr = nullptr;
-    t.rec_ent = t.src_ent = nullptr;
+    t.rec_ptr = nullptr;
+    t.rec_ent = nullptr;
 }
 
 }  // namespace wv

@@ -36,15 +36,13 @@ struct Error {
 
 enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2 };
 
-// Tiling of the (y, x) plane and of z into chunks, plus the point lists
-// (sources, receivers) bucketed per (y, x) tile and sorted by depth.
+// Tiling of the (y, x) plane and of z into chunks, plus the receiver list
+// bucketed per (y, x) tile and sorted by depth.
 struct Tiling {
     int bx = 64, by = 8;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, kc = 0;
     int* rec_ptr = nullptr;   // [tiles + 1]
     int4* rec_ent = nullptr;  // (k, local, r, 0)
-    int* src_ptr = nullptr;
-    int4* src_ent = nullptr;  // (k, local, s, 0)
 };
 
 struct StepArgs {
@@ -56,9 +54,11 @@ struct StepArgs {
     const float* m;      // c^2
     const float* in;     // state in  [S][4][N]
     float* out;          // state out [S][4][N]
-    // sources (forward)
-    const int* src_ptr;
-    const int4* src_ent;
+    // sources (forward): centre face of each wavefield's source, box radius and
+    // weights [(2R+1)^dims] (dk slowest)
+    const int* src_kji;
+    int src_radius;
+    const float* src_w;
     const float* wavelet;  // [S][T]
     int nt, step;
     // receivers
@@ -79,8 +79,7 @@ struct StepArgs {
 };
 
 void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t st);
-Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& src_kji,
-                   const std::vector<int>& rec_kji);
+Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji);
 void free_tiling(Tiling& t);
 
 // ---- reductions / elementwise -------------------------------------------------------

@@ -34,7 +34,13 @@ class WaveSolver:
 
     @classmethod
     def for_problem(cls, p, **kw):
-        return cls(p.nz, p.ny, p.nx, p.dx, p.dt, p.nt, p.sponge, p.c_ref, p.src, p.rec, **kw)
+        s = cls(p.nz, p.ny, p.nx, p.dx, p.dt, p.nt, p.sponge, p.c_ref, p.src, p.rec, **kw)
+        if getattr(p, "src_w", None) is not None:
+            s.set_source_stencil(p.src_w)
+        return s
+
+    def set_source_stencil(self, weights):
+        L.wv_set_source_stencil(self.ctx, weights)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -127,21 +127,25 @@ def test_encode_decode_against_oracle(fmt):
     assert np.array_equal(o2[0], out.cpu().numpy()[0]) and np.all(o2[1:] == 7.0)
 
 
-def test_train_step_gradients_and_adam_against_oracle():
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_train_step_gradients_and_adam_against_oracle(weighting):
     prm = W.ae_init(seed=4)
     net = Net(prm)
     rng = np.random.default_rng(3)
     n, B = 256, 128
     X = np.concatenate([oae.patchify(W.smooth_random_state(4, 32, 32, 32, seed=s)) for s in range(5, 9)])[:n]
-    Y, _, _ = oae.normalize(X, [1e-7] * 4)
+    Y, lo, r = oae.normalize(X, [1e-7] * 4)
+    meta = np.stack([lo, r], axis=2).astype(np.float32)
     ybits = rd.bf16_bits(Y)
     yt = torch.tensor(ybits.view(np.int16), device="cuda")
+    mt = torch.tensor(meta, device="cuda")
     idx = rng.permutation(n)[:B].astype(np.int32)
     it = torch.tensor(idx, device="cuda")
-    cfg = L.train_cfg(epochs=1, batch=B)
-    loss, g = L.ae_train_step(net.handle, yt, it, B, 1e-3, cfg, want_grads=True)
+    cfg = L.train_cfg(epochs=1, batch=B, weighting=weighting)
+    loss, g = L.ae_train_step(net.handle, yt, it, B, 1e-3, cfg, want_grads=True, meta=mt)
     ae = oae.AE(net.prm32)
-    loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True)
+    fw = (meta[idx, :, 1].astype(np.float64) / np.float32(1e-7)) ** 2 if weighting else None
+    loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True, field_weights=fw)
     assert abs(loss - loss_o) / loss_o < 1e-3
     gg = unflat(g)
     for k in oae.NAMES:
@@ -214,6 +218,38 @@ def trained_net(p, every=4, epochs=40):
     losses = L.ae_train(net.handle, y, n, L.train_cfg(epochs=epochs, batch=batch, lr=1e-3, decay_every=10), perm)
     s.close()
     return net, losses
+
+
+def test_all_patches_exact_reproduces_full_storage():
+    """With every patch kept exactly (K = P) the compressed store returns the
+    true e, so gradient and Hv equal the full-storage ones bit for bit."""
+    p = ae_problem(nt=100, shape=(32, 32, 40))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    P = 4 * 4 * 5
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    J0, g0 = full.gradient(p.c_start, p.wavelet, d, sigma)
+    dc = p.c_start * 0.01
+    H0 = full.hessvec(p.c_start, dc)
+    for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
+        s = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s.ctx, P)
+        s.set_storage(mode, ae=raw)
+        J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+        assert J == J0 and torch.equal(g, g0)
+        assert torch.equal(s.hessvec(p.c_start, dc), H0)
+        # fewer exact patches: still valid, error between the two extremes
+        s2 = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s2.ctx, P // 4)
+        s2.set_storage(mode, ae=raw)
+        s3 = WaveSolver.for_problem(p)
+        s3.set_storage(mode, ae=raw)
+        e2 = rel(s2.gradient(p.c_start, p.wavelet, d, sigma)[1].cpu().numpy(), g0.cpu().numpy())
+        e3 = rel(s3.gradient(p.c_start, p.wavelet, d, sigma)[1].cpu().numpy(), g0.cpu().numpy())
+        print("mode", mode, "K=P/4 err", e2, "K=0 err", e3, flush=True)
+        assert e2 < e3
 
 
 def test_guard_falls_back_to_checkpointing():

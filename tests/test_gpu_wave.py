@@ -64,7 +64,7 @@ def test_forward_states_and_traces(which):
     p = rounded(W.problem_2d_small()) if which == "2d" else small3d()
     print("case", which, p.name, flush=True)
     sol = ow.solver_for(p)
-    tr_o, e_hist, finals, v_hist = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, store_v=True)
+    tr_o, e_hist, finals, v_hist = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, store_v=True, src_w=p.src_w)
     s = solver_for(p, L.STORE_NONE)
     tr, fin, cap = s.forward(p.c_start, p.wavelet, final_state=True, capture_every=1)
     torch.cuda.synchronize()
@@ -90,7 +90,7 @@ def test_gradient_matches_oracle(which, mode):
     p = rounded(W.problem_2d_small()) if which == "2d" else small3d()
     print("case", which, mode, flush=True)
     sol, d, sigma = oracle_data(p)
-    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma)
+    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
     s = solver_for(p, mode, nslots=8)
     J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
     g = g.cpu().numpy()
@@ -120,7 +120,7 @@ def test_checkpoint_gradient_bitwise_equals_full_storage():
 def test_gradient_multisource():
     p = small3d(nt=250, nsrc=2)
     sol, d, sigma = oracle_data(p)
-    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma)
+    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
     s = solver_for(p, L.STORE_FULL)
     J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
     assert abs(J - J_o) / J_o < 1e-5
@@ -148,7 +148,7 @@ def test_zero_residual_gives_zero_gradient():
 def test_inc_forward_and_jacobian_dot_test():
     p = small3d(nt=200)
     sol = ow.solver_for(p)
-    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec)
+    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, src_w=p.src_w)
     rng = np.random.default_rng(3)
     dc = f32(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2))
     w = f32(rng.standard_normal((1, p.nt, len(p.rec))))
@@ -167,7 +167,7 @@ def test_inc_forward_and_jacobian_dot_test():
 def test_gn_hessvec_matches_oracle(mode):
     p = small3d(nt=200)
     sol, d, sigma = oracle_data(p)
-    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec)
+    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, src_w=p.src_w)
     dc = f32(p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2))
     H_o = ow.hessvec_gn(sol, p.c_start, dc, e_hist, p.rec, sigma)
     s = solver_for(p, mode, nslots=6)
@@ -187,7 +187,7 @@ def test_autograd_gradient_and_double_backward():
     J = WaveMisfit.apply(c, s, torch.tensor(p.wavelet, dtype=torch.float32, device="cuda"),
                          torch.tensor(d, dtype=torch.float32, device="cuda"), sigma)
     (g,) = torch.autograd.grad(J, c, create_graph=True)
-    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma)
+    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
     assert rel(g.detach().cpu().numpy(), g_o) < 1e-4
     v = torch.tensor(f32(W.direction_grf(p.c_start.shape, 6.0, 2)), dtype=torch.float32, device="cuda")
     (Hv,) = torch.autograd.grad(g, c, grad_outputs=v)

@@ -210,3 +210,29 @@ def test_revolve_counts_for_the_workloads():
     assert orv.closed_form(3000, 64) == 6789
     assert orv.closed_form(4000, 64) == 9789
     assert orv.closed_form(50, 1) == 50 * 49 // 2
+
+
+def test_weighted_loss_reduces_to_mse_and_matches_fd():
+    ae = oae.AE(_tiny_params(seed=7, dims=(24, 10, 4)))
+    rng = np.random.default_rng(9)
+    Y = rng.random((6, 24))
+    l0, g0 = ae.loss_and_grads(Y)
+    l1, g1 = ae.loss_and_grads(Y, field_weights=np.full((6, 4), 3.5))
+    assert abs(l0 - l1) < 1e-15 and all(np.allclose(g0[k], g1[k], rtol=1e-13) for k in oae.NAMES)
+    w = rng.uniform(0.1, 10.0, (6, 4))
+    loss, g = ae.loss_and_grads(Y, field_weights=w)
+    # brute force: weighted sum of per-slice squared errors
+    yh = ae.forward(Y)["yhat"]
+    ref = sum(w[b, f] * np.sum((yh[b, 6 * f:6 * f + 6] - Y[b, 6 * f:6 * f + 6]) ** 2)
+              for b in range(6) for f in range(4)) / (6 * w.sum())
+    assert abs(loss - ref) < 1e-14
+    for name in ("W1", "b4", "W3"):
+        P = ae.p[name]
+        idx = tuple(rng.integers(0, s) for s in P.shape)
+        old = P[idx]
+        P[idx] = old + 1e-6
+        lp, _ = ae.loss_and_grads(Y, field_weights=w)
+        P[idx] = old - 1e-6
+        lm, _ = ae.loss_and_grads(Y, field_weights=w)
+        P[idx] = old
+        assert abs((lp - lm) / 2e-6 - g[name][idx]) <= 1e-7 * max(1.0, abs(g[name][idx]))

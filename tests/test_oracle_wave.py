@@ -185,14 +185,14 @@ def test_gradient_taylor_2d_workload():
     p = W.problem_2d_small()
     sol = ow.solver_for(p)
     d, sigma, _ = ow.observed_data(sol, p)
-    J, g, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma)
+    J, g, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
     assert J > 0
     dc = p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 8.0, 7)
     an = float(np.sum(g * dc))
     errs = []
     for h in (1e-2, 1e-3, 1e-4):
-        Jp = ow.gradient(sol, p.c_start + h * dc, p.wavelet, p.src, p.rec, d, sigma)[0]
-        Jm = ow.gradient(sol, p.c_start - h * dc, p.wavelet, p.src, p.rec, d, sigma)[0]
+        Jp = ow.gradient(sol, p.c_start + h * dc, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)[0]
+        Jm = ow.gradient(sol, p.c_start - h * dc, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)[0]
         errs.append(abs((Jp - Jm) / (2 * h) - an) / abs(an))
     assert errs[2] < 1e-8
     assert errs[0] / errs[1] > 50.0       # slope ~2 (ratio 100)
@@ -271,3 +271,20 @@ def test_full_hessvec_matches_fd_and_differs_from_gn():
     fd = _fd_hess(sol, c, wav, src, rec, d, sigma, dc)
     assert np.linalg.norm(Hf - fd) / np.linalg.norm(fd) < 1e-6
     assert np.linalg.norm(Hg - fd) / np.linalg.norm(fd) > 1e-3
+
+
+def test_unit_box_source_equals_point_force_and_is_linear():
+    sol, c, wav, src, rec = small_3d(nt=40)
+    tp, _, _, _ = ow.forward(sol, c, wav, src, rec, store_e=False)
+    w = np.zeros((5, 5, 5))
+    w[2, 2, 2] = 1.0
+    tb, _, _, _ = ow.forward(sol, c, wav, src, rec, store_e=False, src_w=w)
+    assert np.array_equal(tp, tb)
+    # a box straddling the top surface is truncated, and the response is linear in the weights
+    w1 = W.source_weights(10.0, 3, 20.0)
+    w2 = np.random.default_rng(3).random(w1.shape)
+    t1 = ow.forward(sol, c, wav, src, rec, store_e=False, src_w=w1)[0]
+    t2 = ow.forward(sol, c, wav, src, rec, store_e=False, src_w=w2)[0]
+    t12 = ow.forward(sol, c, wav, src, rec, store_e=False, src_w=2.0 * w1 - w2)[0]
+    assert np.allclose(t12, 2.0 * t1 - t2, rtol=1e-12, atol=1e-12 * np.abs(t1).max())
+    assert abs(w1.sum() - 1.0) < 1e-14 and w1.shape[0] == 2 * 6 + 1

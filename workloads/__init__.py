@@ -13,8 +13,11 @@ Recipes (paper Sec. 2 problem statement; Sec. 4.1 workload shape):
     the small 2D case uses 4 layers and one Gaussian anomaly instead.
   * start model: the true model smoothed by a Gaussian filter.
   * source: Ricker wavelet (the paper's Sec. 4.1 source time function
-    with sigma_t = 1/(sqrt(2) pi f0), delayed by 1.5/f0), point vertical
-    force of strength 1/dx^d.
+    with sigma_t = 1/(sqrt(2) pi f0), delayed by 1.5/f0) times a spatial
+    Gaussian of std 50 m (Sec. 4.1 smooths its sources with a narrow
+    Gaussian of std 0.05 in a 1 km box), truncated at 3 std and normalised
+    to unit sum, acting on the vertical velocity; wavelet values carry the
+    1/dx^d of a cell volume.
   * receivers: vertical-velocity faces at depth index 2 on a regular
     surface grid.
   * dt = CFL * dx / max(c_true) with CFL = 0.4.
@@ -50,8 +53,13 @@ class Problem:
     wavelet: np.ndarray          # [S, T] force density b_z^n (already divided by dx^d)
     f0: np.ndarray               # [S] peak frequencies
     noise: np.ndarray            # [S, T, R] standard normal draws for the data noise
+    src_w: np.ndarray = None     # [2R+1, 2R+1 | 1, 2R+1] spatial weights of every source
     noise_level: float = 0.01    # sigma = noise_level * max|d_clean|
     periodic: int = 0
+
+    @property
+    def src_radius(self) -> int:
+        return 0 if self.src_w is None else (self.src_w.shape[0] - 1) // 2
 
     @property
     def dims(self) -> int:
@@ -101,8 +109,23 @@ def _surface_grid(first: int, step: int, count: int, k: int = 2) -> np.ndarray:
     return np.stack([np.full(jj.size, k), jj.ravel(), ii.ravel()], axis=1).astype(np.int32)
 
 
+SOURCE_STD_M = 50.0
+
+
+def source_weights(dx: float, dims: int, std_m: float = SOURCE_STD_M) -> np.ndarray:
+    """Gaussian of std `std_m` sampled on the v_z faces around the source face,
+    truncated at 3 std, normalised to unit sum; shape (2R+1, 2R+1 | 1, 2R+1)."""
+    sc = std_m / dx
+    R = int(math.ceil(3.0 * sc))
+    k = np.arange(-R, R + 1, dtype=np.float64)
+    g = np.exp(-k * k / (2.0 * sc * sc))
+    gy = g if dims == 3 else np.ones(1)
+    w = g[:, None, None] * gy[None, :, None] * g[None, None, :]
+    return w / w.sum()
+
+
 def _finish(name, nz, ny, nx, dx, nt, c_true, c_start, src, f0, rec, sponge=16,
-            noise_seed=1, dt=None, periodic=0) -> Problem:
+            noise_seed=1, dt=None, periodic=0, src_std=SOURCE_STD_M) -> Problem:
     c_ref = float(c_true.max())
     if dt is None:
         dt = CFL * dx / c_ref
@@ -110,11 +133,12 @@ def _finish(name, nz, ny, nx, dx, nt, c_true, c_start, src, f0, rec, sponge=16,
     wav = np.stack([ricker(f, dt, nt) for f in f0]) / dx ** d
     rng = np.random.default_rng(noise_seed)
     noise = rng.standard_normal((len(src), nt, len(rec)))
+    src_w = source_weights(dx, d, src_std) if src_std and src_std > 0 else None
     return Problem(name=name, nz=nz, ny=ny, nx=nx, dx=dx, dt=dt, nt=nt, sponge=sponge,
                    c_ref=c_ref, c_true=c_true, c_start=c_start,
                    src=np.asarray(src, dtype=np.int32), rec=np.asarray(rec, dtype=np.int32),
                    wavelet=wav, f0=np.asarray(f0, dtype=np.float64), noise=noise,
-                   periodic=periodic)
+                   src_w=src_w, periodic=periodic)
 
 
 def problem_2d_small(nt: int = 500) -> Problem:
