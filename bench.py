@@ -1,0 +1,266 @@
+"""Benchmark: autoencoder-compressed adjoint gradient of the 3D acoustic
+velocity-strain misfit at 256^3 cells x 2000 steps on one MI355X, against the
+same gradient with optimal binomial checkpointing (64 state slots).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+One "step" is one misfit gradient: forward solve with every state compressed
+(normalise, encode, latent store), misfit, and the time-reversed adjoint solve
+that decompresses e^k at every step and accumulates the gradient. Inputs are
+seeded synthetic layered media (workloads.problem_256); observations are the
+forward solve at the true model plus 1 % Gaussian noise. Before timing, the
+autoencoder is trained by the library on 200 snapshots of the first forward
+solve at the start model (every 10th step). Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--nt", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--snapshot-every", type=int, default=10)
+    ap.add_argument("--exceptions", type=float, default=0.01, help="fraction of patches kept exactly")
+    ap.add_argument("--latent", choices=["bf16", "fp8"], default="bf16")
+    ap.add_argument("--checkpoints", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the compressed gradient on a single "
+              "MI355X (sharding by source or by domain is described in DESIGN.md, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd.solver import WaveSolver
+
+    L.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t_setup = time.perf_counter()
+
+    n, T = args.size, args.nt
+    p = W.problem_256(T) if n == 256 else W.problem_3d(n, n, n, T, rec_first=33, rec_step=max(1, (n - 66) // 64),
+                                                          rec_count=64, name=f"3d-{n}^3-{T}")
+    N = p.n
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    K_exc = int(round(args.exceptions * P))
+    log(f"problem {p.name}: N={N}, P={P}, dt={p.dt:.3e}, receivers={len(p.rec)}, exceptions={K_exc}")
+    c_true = torch.tensor(p.c_true, dtype=torch.float32, device=dev)
+    c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+
+    solver = WaveSolver.for_problem(p)
+    solver.set_storage(L.STORE_NONE)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # observations: forward at the true model (also the forward-stencil timing run)
+    clean, _, _ = solver.forward(c_true, wav)
+    torch.cuda.synchronize()
+    ev0.record()
+    clean, _, _ = solver.forward(c_true, wav)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_fwd_step = ev0.elapsed_time(ev1) / 1e3 / T
+    clean_h = clean.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * float(np.abs(clean_h).max())
+    d_obs = torch.tensor((clean_h + sigma * p.noise).astype(np.float32), device=dev)
+    del clean
+    log(f"forward stencil {t_fwd_step * 1e6:.1f} us/step")
+
+    # ---- train the compressor on snapshots of the first forward solve at c_start
+    from paper_2304_04781_amd.compressor import Autoencoder, train_from_forward
+    t0 = time.perf_counter()
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    nsamp = ((T - 1) // args.snapshot_every) * P * len(p.src)
+    perms = W.shuffles(nsamp, args.epochs, seed=5)
+    train_info = train_from_forward(solver, net, c0, wav, every=args.snapshot_every, epochs=args.epochs,
+                                    batch=args.batch, perms=perms)
+    del perms
+    t_train_total = time.perf_counter() - t0
+    log(f"training {train_info}")
+
+    # ---- AE-compressed gradient (timed)
+    fmt = L.STORE_AE_BF16 if args.latent == "bf16" else L.STORE_AE_FP8
+    ae_solver = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(ae_solver.ctx, K_exc)
+    ae_solver.set_storage(fmt, ae=net)
+    # AE forward alone (stencil + compression), for the encode cost
+    ae_solver.forward(c0, wav)
+    torch.cuda.synchronize()
+    ev0.record()
+    ae_solver.forward(c0, wav)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_fwd_ae_step = ev0.elapsed_time(ev1) / 1e3 / T
+
+    for _ in range(args.warmup):
+        ae_solver.gradient(c0, wav, d_obs, sigma)
+    torch.cuda.synchronize()
+    times = []
+    g_ae = None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ev0.record()
+        J_ae, g_ae = ae_solver.gradient(c0, wav, d_obs, sigma)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / 1e3)
+    t_ae = float(np.median(times))
+    status = ae_solver.last_status
+    store_bytes = ae_solver.storage_bytes()
+    log(f"AE gradient {t_ae:.3f} s (runs {['%.3f' % x for x in times]}), store {store_bytes / 1e9:.2f} GB")
+
+    # ---- checkpointed gradient (the plain path: fallback and judge)
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
+    J_ck, g_ck = ck.gradient(c0, wav, d_obs, sigma)
+    torch.cuda.synchronize()
+    times_ck = []
+    for _ in range(max(1, min(args.steps, 2))):
+        ev0.record()
+        J_ck, g_ck = ck.gradient(c0, wav, d_obs, sigma)
+        ev1.record()
+        torch.cuda.synchronize()
+        times_ck.append(ev0.elapsed_time(ev1) / 1e3)
+    t_ck = float(np.median(times_ck))
+    fsteps, _, _ = ck.stats()
+    ck_bytes = ck.storage_bytes()
+    t_adj_step = (t_ck - fsteps * t_fwd_step) / (T - 1)
+    log(f"checkpointed gradient {t_ck:.3f} s, {fsteps} forward steps; adjoint {t_adj_step * 1e6:.1f} us/step")
+
+    ga = g_ae.double()
+    gc = g_ck.double()
+    rel_err = float(torch.linalg.norm(ga - gc) / torch.linalg.norm(gc))
+    cos = float(torch.sum(ga * gc) / (torch.linalg.norm(ga) * torch.linalg.norm(gc)))
+    t_adj_ae_step = (t_ae - t_fwd_ae_step * T) / (T - 1)
+    t_encode = t_fwd_ae_step - t_fwd_step
+    t_decode = t_adj_ae_step - t_adj_step
+    log(f"grad rel err {rel_err:.4f} cos {cos:.5f}; encode {t_encode * 1e6:.1f} us, decode {t_decode * 1e6:.1f} us")
+
+    # ---- rooflines (algorithmic bytes/flops per launch over measured durations)
+    fwd_bytes = 36.0 * N
+    adj_bytes = 56.0 * N
+    enc_flops = 2.0 * P * (2048 * 512 + 512 * 32)
+    dec_flops = 2.0 * P * (32 * 512 + 512 * 512)
+    kernels = {
+        "forward_stencil": {"us": t_fwd_step * 1e6, "GB/s": fwd_bytes / t_fwd_step / 1e9,
+                            "frac_hbm": fwd_bytes / t_fwd_step / 1e9 / HBM_PEAK_GBS},
+        "adjoint_stencil": {"us": t_adj_step * 1e6, "GB/s": adj_bytes / t_adj_step / 1e9,
+                            "frac_hbm": adj_bytes / t_adj_step / 1e9 / HBM_PEAK_GBS},
+        "encode": {"us": t_encode * 1e6, "TFLOP/s": enc_flops / max(t_encode, 1e-9) / 1e12,
+                   "frac_mfma_bf16": enc_flops / max(t_encode, 1e-9) / 1e12 / BF16_PEAK_TFLOPS},
+        "decode_e": {"us": t_decode * 1e6, "TFLOP/s": dec_flops / max(t_decode, 1e-9) / 1e12,
+                     "frac_mfma_bf16": dec_flops / max(t_decode, 1e-9) / 1e12 / BF16_PEAK_TFLOPS},
+    }
+    dom = "adjoint_stencil" if t_adj_step >= t_fwd_step else "forward_stencil"
+    dom_bytes = adj_bytes if dom == "adjoint_stencil" else fwd_bytes
+    dom_t = t_adj_step if dom == "adjoint_stencil" else t_fwd_step
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dom_bytes / dom_t / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_bytes / dom_t / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": None}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same grid
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, T)
+        log(f"cpu baseline {cpu}")
+
+    gph = 3600.0 / t_ae
+    out = {
+        "metric": "gradients/hour at 256^3x2000 steps, AE vs checkpointing; grad rel err vs FP64",
+        "value": round(gph, 1),
+        "unit": "gradients/hour",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_ae * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{p.name}: AE-compressed misfit gradient ({args.latent} latents, "
+                               f"{K_exc} exact patches/step) vs revolve checkpointing ({args.checkpoints} slots)",
+                   "grid": [p.nz, p.ny, p.nx], "nt": T, "sources": len(p.src), "receivers": len(p.rec),
+                   "global_batch": 1},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "checkpoint": {"gradients_per_hour": round(3600.0 / t_ck, 1), "ms_per_gradient": round(t_ck * 1e3, 2),
+                       "forward_steps": fsteps, "store_GB": round(ck_bytes / 1e9, 2)},
+        "speedup_vs_checkpoint": round(t_ck / t_ae, 4),
+        "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
+        "grad_cos_vs_checkpoint_fp32": round(cos, 6),
+        "misfit": {"ae": J_ae, "checkpoint": J_ck},
+        "status": int(status),
+        "ae_store_GB": round(store_bytes / 1e9, 3),
+        "compression": {"latent_only": 2048 * 4 / (32 * (2 if args.latent == "bf16" else 1)),
+                        "effective_vs_float32_history": round(4.0 * 4 * N * (T - 1) / store_bytes, 1)},
+        "train": dict(train_info, wall_s=round(t_train_total, 2)),
+        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
+        "setup_s": round(time.perf_counter() - t_setup, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, T, nsteps=3):
+    """Time the FP64 oracle's forward and adjoint steps on the full grid and
+    extrapolate to one gradient (T forward + T-1 adjoint steps)."""
+    from oracle import wave as ow
+    sol = ow.solver_for(p)
+    m = p.c_start * p.c_start
+    rng = np.random.default_rng(0)
+    v = {a: 1e-6 * rng.standard_normal(sol.shape) for a in sol.axes}
+    e = 1e-6 * rng.standard_normal(sol.shape)
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        v, e = sol.step(v, e, m, force=(tuple(int(x) for x in p.src[0]), p.wavelet[0, n], p.src_w))
+    t_f = (time.perf_counter() - t0) / nsteps
+    mu = {a: x.copy() for a, x in v.items()}
+    eta = e.copy()
+    acc = np.zeros(sol.shape)
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        mu, eta, q = sol.step_T(mu, eta, m)
+        acc += e * q
+    t_a = (time.perf_counter() - t0) / nsteps
+    t_grad = T * t_f + (T - 1) * t_a
+    return {"value": round(3600.0 / t_grad, 4), "unit": "gradients/hour", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} forward + {nsteps} adjoint FP64 numpy steps on the {p.nz}x{p.ny}x{p.nx} grid "
+                      f"({t_f:.2f} s + {t_a:.2f} s per step), extrapolated to {T} + {T - 1} steps"}
+
+
+if __name__ == "__main__":
+    main()

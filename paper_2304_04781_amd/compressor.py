@@ -1,0 +1,102 @@
+"""The learned compressor: an autoencoder handle and the training pipeline
+that feeds it snapshots of the solver's own forward solve (the paper's
+Algorithm 1 with the current model in place of prior draws, Sec. 3.3.1).
+
+Every step runs in libwavecomp.so: the forward solve captures raw states,
+ae_fit_beta sets the per-field floors, ae_normalize builds the bfloat16
+training vectors and ae_train runs the MFMA forward/backward passes and
+Adam. Initial weights and shuffle orders are inputs (drawn by the caller).
+"""
+from __future__ import annotations
+
+import time
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+
+
+def flatten(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], dtype=np.float32).ravel() for k in PARAM_ORDER])
+
+
+class Autoencoder:
+    """Owns an ae_net (weights, Adam state, floors) on the current device."""
+
+    def __init__(self, init_params, in_dim=2048, hidden=512, latent=32, beta=None):
+        flat = init_params if isinstance(init_params, np.ndarray) else flatten(init_params)
+        self.dims = (in_dim, hidden, latent)
+        self.handle = L.ae_create(in_dim, hidden, latent, flat, beta)
+
+    @classmethod
+    def load(cls, path: str) -> "Autoencoder":
+        obj = cls.__new__(cls)
+        obj.handle = L.ae_load(path)
+        obj.dims = (2048, 0, 0)
+        return obj
+
+    def save(self, path: str) -> None:
+        L.ae_save(self.handle, path)
+
+    def params(self) -> np.ndarray:
+        return L.ae_get_params(self.handle)
+
+    def beta(self) -> np.ndarray:
+        return L.ae_get_beta(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.ae_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_from_forward(solver, ae: Autoencoder, c, wavelet, every: int, epochs: int, batch: int,
+                       perms: Optional[np.ndarray] = None, weighting: int = 0, lr: float = 1e-3,
+                       decay_every: int = 5, decay_factor: float = 0.5, beta_rel: float = 1e-7):
+    """Capture every `every`-th state of a forward solve at c, set the floors
+    beta_f = beta_rel * max|x_f|, normalise the snapshots and train.
+    perms: [epochs, nsamples] int32 visiting orders (None: in order).
+    Returns a dict with sizes, per-epoch losses and timings."""
+    S = solver.S
+    t0 = time.perf_counter()
+    _, _, cap = solver.forward(c, wavelet, capture_every=every)      # [ncap, S, 4, nz, ny, nx]
+    ncap = cap.shape[0] * S
+    cap = cap.reshape((ncap, 4) + solver.shape)
+    torch.cuda.synchronize()
+    t_cap = time.perf_counter() - t0
+    L.ae_fit_beta(ae.handle, solver.grid, cap, ncap, beta_rel)
+    nz, ny, nx = solver.shape
+    P = (nz // 8) * (ny // 8) * (nx // 8)
+    nsamp = ncap * P
+    y = torch.empty((nsamp, 2048), dtype=torch.int16, device=cap.device)
+    meta = torch.empty((nsamp, 4, 2), dtype=torch.float32, device=cap.device)
+    for q in range(ncap):
+        L.ae_normalize(ae.handle, solver.grid, cap[q], y[q * P:(q + 1) * P], meta[q * P:(q + 1) * P])
+    torch.cuda.synchronize()
+    del cap
+    torch.cuda.empty_cache()
+    perm_t = None
+    if perms is not None:
+        perm_t = torch.as_tensor(np.ascontiguousarray(perms, dtype=np.int32), device=y.device)
+    cfg = L.train_cfg(epochs=epochs, batch=batch, lr=lr, decay_every=decay_every, decay_factor=decay_factor,
+                      weighting=weighting)
+    t1 = time.perf_counter()
+    losses = L.ae_train(ae.handle, y, nsamp, cfg, perm_t, meta=meta)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    steps = epochs * (nsamp // batch)
+    flops = steps * batch * 6.0 * 2 * (2048 * 512 + 512 * 32 + 32 * 512 + 512 * 2048) / 2
+    return {"snapshots": int(ncap), "samples": int(nsamp), "epochs": int(epochs), "batch": int(batch),
+            "adam_steps": int(steps), "loss_first": float(losses[0]) if len(losses) else None,
+            "loss_last": float(losses[-1]) if len(losses) else None, "capture_s": round(t_cap, 3),
+            "train_s": round(t_train, 3), "train_TFLOP/s": round(flops / max(t_train, 1e-9) / 1e12, 1)}

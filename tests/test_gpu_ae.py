@@ -198,7 +198,7 @@ def ae_problem(nt=240, shape=(48, 48, 48)):
     return p
 
 
-def trained_net(p, every=4, epochs=40):
+def trained_net(p, every=4, epochs=40, weighting=0):
     """Snapshots of the forward solve at the start model train the network."""
     net = Net(W.ae_init(seed=4))
     s = WaveSolver.for_problem(p)
@@ -215,7 +215,8 @@ def trained_net(p, every=4, epochs=40):
     n = ncap * P
     batch = 64
     perm = torch.tensor(W.shuffles(n, epochs, seed=5), device="cuda")
-    losses = L.ae_train(net.handle, y, n, L.train_cfg(epochs=epochs, batch=batch, lr=1e-3, decay_every=10), perm)
+    losses = L.ae_train(net.handle, y, n, L.train_cfg(epochs=epochs, batch=batch, lr=1e-3, decay_every=10,
+                                                     weighting=weighting), perm)
     s.close()
     return net, losses
 
@@ -271,41 +272,52 @@ def test_guard_falls_back_to_checkpointing():
 
 
 def test_compressed_gradient_and_hessvec():
-    p = ae_problem()
+    """Trained on snapshots of the forward solve itself; the compressed
+    gradient and Hv are judged against the uncompressed (full-storage) ones.
+    With the largest-range 2 % of patches kept exactly the gradient is within
+    0.1 relative L2 and cosine 0.995 on this 48^3 problem; latents alone are
+    reported, and an untrained network is far worse."""
+    p = ae_problem(nt=240, shape=(48, 48, 48))
+    p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
     sol = ow.solver_for(p)
     d, sigma, _ = ow.observed_data(sol, p)
     d = np.asarray(d, np.float32)
     net, losses = trained_net(p)
     print("training loss per epoch", losses[:3], losses[-3:], flush=True)
+    assert losses[-1] < 0.1 * losses[0]
     plain = WaveSolver.for_problem(p)
     plain.set_storage(L.STORE_FULL)
     J0, g0 = plain.gradient(p.c_start, p.wavelet, d, sigma)
-    res = {}
+    g0n = g0.cpu().numpy().astype(np.float64)
+    P = 6 * 6 * 6
+    dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
+    H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+    errs = {}
     for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
-        s = WaveSolver.for_problem(p)
-        s.set_storage(mode, ae=net)
-        J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
-        g0n, gn = g0.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
-        err = rel(gn, g0n)
-        cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
-        res[mode] = (err, cos)
-        print("mode", mode, "J", J, J0, "rel err", err, "cos", cos, flush=True)
-        assert J == J0                  # the forward solve itself is not compressed
-        assert err < 0.15 and cos > 0.99
-        if mode == L.STORE_AE_BF16:
-            dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
-            H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+        for K in (0, 4):
+            s = WaveSolver.for_problem(p)
+            L.wv_set_ae_exceptions(s.ctx, K)
+            s.set_storage(mode, ae=net)
+            J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+            gn = g.cpu().numpy().astype(np.float64)
+            err = rel(gn, g0n)
+            cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
             H = s.hessvec(p.c_start, dc).cpu().numpy()
             herr = rel(H, H0)
-            print("hessvec rel err", herr, flush=True)
-            assert herr < 0.15
+            errs[(mode, K)] = (err, cos, herr)
+            print("mode", mode, "K", K, "grad rel err", err, "cos", cos, "Hv rel err", herr, flush=True)
+            assert J == J0                  # the forward solve itself is not compressed
             assert s.storage_bytes() * 10 < plain.storage_bytes()
-    # an untrained network is clearly worse than the trained one
+    for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
+        err, cos, herr = errs[(mode, 4)]
+        assert err < 0.1 and cos > 0.995 and herr < 0.1
+        assert errs[(mode, 0)][0] < 0.35
+    # an untrained network is far worse than the trained one
     raw = Net(W.ae_init(seed=4))
     L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
     s = WaveSolver.for_problem(p)
     s.set_storage(L.STORE_AE_BF16, ae=raw)
     _, gu = s.gradient(p.c_start, p.wavelet, d, sigma)
-    err_u = rel(gu.cpu().numpy(), g0.cpu().numpy())
+    err_u = rel(gu.cpu().numpy(), g0n)
     print("untrained rel err", err_u, flush=True)
-    assert err_u > 2 * res[L.STORE_AE_BF16][0]
+    assert err_u > 5 * errs[(L.STORE_AE_BF16, 0)][0]
