@@ -296,6 +296,41 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict_
     }
 }
 
+// per-patch, per-field (min, range): one work-group per (pz, py) row of patches,
+// threads along x, groups of 8 lanes reduce one patch
+__global__ void __launch_bounds__(256) minmax_kernel(const float* __restrict__ state, int ny, int nx, long long N,
+                                                    int Py, int Px, const float* __restrict__ beta,
+                                                    float* __restrict__ meta)
+{
+    const int row = blockIdx.x;
+    const int py = row % Py, pz = row / Py;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        float lo[4], hi[4];
+        for (int f = 0; f < 4; ++f) {
+            lo[f] = INFINITY;
+            hi[f] = -INFINITY;
+            const float* src = state + f * N + ((long long)(pz * 8) * ny + py * 8) * nx + x;
+            for (int lz = 0; lz < 8; ++lz)
+                for (int ly = 0; ly < 8; ++ly) {
+                    const float v = src[((long long)lz * ny + ly) * nx];
+                    lo[f] = fminf(lo[f], v);
+                    hi[f] = fmaxf(hi[f], v);
+                }
+            for (int o = 1; o < 8; o <<= 1) {
+                lo[f] = fminf(lo[f], __shfl_xor(lo[f], o, 64));
+                hi[f] = fmaxf(hi[f], __shfl_xor(hi[f], o, 64));
+            }
+        }
+        if ((x & 7) == 0) {
+            const long long p = (long long)row * Px + x / 8;
+            for (int f = 0; f < 4; ++f) {
+                meta[p * 8 + 2 * f] = lo[f];
+                meta[p * 8 + 2 * f + 1] = fmaxf(hi[f] - lo[f], beta[f]);
+            }
+        }
+    }
+}
+
 // latent fp32 [P][L] -> e4m3 codes + per-patch scale; one wave per patch
 __global__ void quantize_kernel(const float* __restrict__ z, long long P, int L, uint8_t* __restrict__ q,
                                 float* __restrict__ scale)
@@ -597,6 +632,23 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
     WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "encode: null buffer");
     const long long P = pg.P;
+    if (fused_supported(a->hid, a->lat)) {
+        const long long N = (long long)pg.nz * pg.ny * pg.nx;
+        const int rows = (pg.nz / 8) * (pg.ny / 8);
+        hipLaunchKernelGGL(minmax_kernel, dim3(rows), dim3(std::min(256, ((pg.nx + 63) / 64) * 64)), 0, st, state,
+                           pg.ny, pg.nx, N, pg.ny / 8, pg.nx / 8, a->beta_d, meta);
+        WV_HIP(hipGetLastError());
+        if (fmt == AE_LATENT_BF16) {
+            fused_encode(pg, state, meta, a->wt[0], a->bias(0), a->wt[1], a->bias(1), (uint16_t*)latent, nullptr, st);
+        } else {
+            float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
+            fused_encode(pg, state, meta, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
+            hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
+                               qscale);
+            WV_HIP(hipGetLastError());
+        }
+        return;
+    }
     const size_t oy = 0, oh = align256(oy + P * 2048 * 2), oz = align256(oh + P * (size_t)a->hid * 2);
     uint8_t* ws = (uint8_t*)workspace(a, align256(oz + P * (size_t)a->lat * 4));
     uint16_t* y = (uint16_t*)(ws + oy);
@@ -623,6 +675,20 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
     WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "decode: null buffer");
     const long long P = pg.P;
+    if (fused_supported(a->hid, a->lat)) {
+        const uint16_t* zb = (const uint16_t*)latent;
+        if (fmt == AE_LATENT_FP8) {
+            uint16_t* zq = (uint16_t*)workspace(a, align256(P * (size_t)a->lat * 2));
+            hipLaunchKernelGGL(dequantize_kernel, dim3(blocks(P * a->lat, 256)), dim3(256), 0, st,
+                               (const uint8_t*)latent, qscale, P, a->lat, zq);
+            WV_HIP(hipGetLastError());
+            zb = zq;
+        }
+        for (int f = 0; f < 4; ++f)
+            if (mask & (1u << f))
+                fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wt[3], a->bias(3), f, state, st);
+        return;
+    }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
     uint8_t* ws = (uint8_t*)workspace(a, align256(ozb + P * (size_t)a->lat * 2));
     uint16_t* h = (uint16_t*)(ws + oh);

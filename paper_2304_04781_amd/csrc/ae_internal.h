@@ -26,6 +26,14 @@ void ae_encode_state(const ae_net* net, const PatchGrid& pg, const float* state,
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st);
 
+// Fused inference kernels (hidden width 512, latent 32): meta must already hold
+// the per-patch (min, range) of the state for encode.
+bool fused_supported(int hid, int lat);
+void fused_encode(const PatchGrid& pg, const float* state, const float* meta, const uint16_t* w1t, const float* b1,
+                  const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf, hipStream_t st);
+void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
+                  const uint16_t* w4t, const float* b4, int f, float* state, hipStream_t st);
+
 // Select the K largest-e-range patches of one compressed state (meta [P][4][2])
 // into idx [K] (increasing patch order) and copy their e values to exc [K][512].
 void exceptions_store(const PatchGrid& pg, const float* state, const float* meta, int K, int* idx, float* exc,

@@ -30,35 +30,78 @@ __device__ int block_scan_incl(int v, int* sh)
 // keys: r_e = meta[p*8 + 1] > 0, ordered as uint32 bit patterns. Radix select
 // (8 bits per pass, most significant first) finds the K-th largest key T; the
 // output lists, in increasing patch order, every patch with key > T and the
-// first (K - #{key > T}) patches with key == T.
+// first (K - #{key > T}) patches with key == T. Each thread keeps a contiguous
+// run of up to KPT keys in registers; histograms are per wave to limit LDS
+// atomic contention (many patches share the floor value beta).
+constexpr int NWAVE = SEL_THREADS / 64;
+constexpr int KPT_MAX = 128;  // keys per thread: up to 131072 patches
+
+template <int KPT>
 __global__ void __launch_bounds__(SEL_THREADS) topk_kernel(const float* __restrict__ meta, int P, int K,
                                                           int* __restrict__ out)
 {
-    __shared__ unsigned hist[256];
+    __shared__ unsigned hist[NWAVE][256];
+    __shared__ unsigned tot[256];
     __shared__ unsigned s_prefix, s_mask;
     __shared__ int s_rem;
     __shared__ int sh[SEL_THREADS];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (P + SEL_THREADS - 1) / SEL_THREADS;
+    const int p0 = min(P, tid * per), p1 = min(P, p0 + per);
+    unsigned key[KPT];
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) key[q] = (p0 + q < p1) ? __float_as_uint(meta[(long long)(p0 + q) * 8 + 1]) : 0u;
+    const int nk = p1 - p0;
+
     unsigned prefix = 0, mask = 0;
     int rem = K;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
-        for (int b = tid; b < 256; b += SEL_THREADS) hist[b] = 0;
+        for (int b = lane; b < 256; b += 64) hist[wave][b] = 0;
         __syncthreads();
-        for (int p = tid; p < P; p += SEL_THREADS) {
-            const unsigned key = __float_as_uint(meta[(long long)p * 8 + 1]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+#pragma unroll
+        for (int q = 0; q < KPT; ++q)
+            if (q < nk && (key[q] & mask) == prefix) atomicAdd(&hist[wave][(key[q] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 256) {
+            unsigned t = 0;
+            for (int w = 0; w < NWAVE; ++w) t += hist[w][tid];
+            tot[tid] = t;
         }
         __syncthreads();
-        if (tid == 0) {
-            int cum = 0, d = 255;
-            for (; d > 0; --d) {
-                if (cum + (int)hist[d] >= rem) break;
-                cum += (int)hist[d];
+        if (wave == 0) {
+            // digits 255..0 as 64 lanes x 4: suffix sums from the top
+            unsigned c4[4], s = 0;
+            for (int t = 0; t < 4; ++t) {
+                c4[t] = tot[255 - (lane * 4 + t)];
+                s += c4[t];
             }
-            s_prefix = prefix | ((unsigned)d << shift);
-            s_mask = mask | (255u << shift);
-            s_rem = rem - cum;
+            unsigned incl = s;  // inclusive prefix over lanes (lane 0 = highest digits)
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            unsigned before = incl - s;
+            int found = -1;
+            unsigned cum_at = 0;
+            for (int t = 0; t < 4; ++t) {
+                if (found < 0 && before + c4[t] >= (unsigned)rem) {
+                    found = 255 - (lane * 4 + t);
+                    cum_at = before;
+                }
+                before += c4[t];
+            }
+            // the first lane (highest digits) that found the crossing wins
+            const unsigned long long ball = __ballot(found >= 0);
+            const int winner = ball ? __ffsll((long long)ball) - 1 : 63;
+            const int d = __shfl(found, winner, 64);
+            const unsigned cum = __shfl(cum_at, winner, 64);
+            if (lane == 0) {
+                const int dd = d < 0 ? 0 : d;
+                s_prefix = prefix | ((unsigned)dd << shift);
+                s_mask = mask | (255u << shift);
+                s_rem = rem - (int)cum;
+            }
         }
         __syncthreads();
         prefix = s_prefix;
@@ -67,28 +110,28 @@ __global__ void __launch_bounds__(SEL_THREADS) topk_kernel(const float* __restri
         __syncthreads();
     }
     const unsigned T = prefix;
-    const int per = (P + SEL_THREADS - 1) / SEL_THREADS;
-    const int p0 = min(P, tid * per), p1 = min(P, p0 + per);
     int gt = 0, eq = 0;
-    for (int p = p0; p < p1; ++p) {
-        const unsigned key = __float_as_uint(meta[(long long)p * 8 + 1]);
-        gt += key > T;
-        eq += key == T;
-    }
+#pragma unroll
+    for (int q = 0; q < KPT; ++q)
+        if (q < nk) {
+            gt += key[q] > T;
+            eq += key[q] == T;
+        }
     const int eq_before = block_scan_incl(eq, sh) - eq;
     const int take_eq = max(0, min(eq, rem - eq_before));
     const int sel = gt + take_eq;
     int pos = block_scan_incl(sel, sh) - sel;
     int eq_seen = 0;
-    for (int p = p0; p < p1; ++p) {
-        const unsigned key = __float_as_uint(meta[(long long)p * 8 + 1]);
-        bool pick = key > T;
-        if (key == T) {
-            pick = eq_seen < take_eq;
-            ++eq_seen;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q)
+        if (q < nk) {
+            bool pick = key[q] > T;
+            if (key[q] == T) {
+                pick = eq_seen < take_eq;
+                ++eq_seen;
+            }
+            if (pick) out[pos++] = p0 + q;
         }
-        if (pick) out[pos++] = p;
-    }
 }
 
 // exc[k][l] = e of patch idx[k] at local cell l (one block per patch)
@@ -119,7 +162,15 @@ void exceptions_store(const PatchGrid& pg, const float* state, const float* meta
 {
     if (K <= 0) return;
     WV_REQUIRE(K <= pg.P, WV_EINVAL, "more exception patches than patches");
-    hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
+    WV_REQUIRE(pg.P <= (long long)KPT_MAX * SEL_THREADS, WV_EINVAL, "too many patches for the exception selector");
+    if (pg.P <= 16LL * SEL_THREADS)
+        hipLaunchKernelGGL(topk_kernel<16>, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
+    else if (pg.P <= 32LL * SEL_THREADS)
+        hipLaunchKernelGGL(topk_kernel<32>, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
+    else if (pg.P <= 64LL * SEL_THREADS)
+        hipLaunchKernelGGL(topk_kernel<64>, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
+    else
+        hipLaunchKernelGGL(topk_kernel<KPT_MAX>, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
     hipLaunchKernelGGL(gather_kernel, dim3(K), dim3(512), 0, st, state, pg.ny, pg.nx, pg.ny / 8, pg.nx / 8, idx, exc);
     WV_HIP(hipGetLastError());
 }
