@@ -148,7 +148,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     const int ke = min(K, kb + k_per_split);
 
     f32x4 acc[TM][TN];
+#pragma unroll
     for (int a = 0; a < TM; ++a)
+#pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
@@ -157,20 +159,27 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
         lb.load(n0, k0, tid, BN, sB);
         __syncthreads();
         bf16x8 af[TM], bfr[TN];
+#pragma unroll
         for (int a = 0; a < TM; ++a)
             af[a] = *reinterpret_cast<const bf16x8*>(&sA[wm0 + a * 16 + fr][fk]);
+#pragma unroll
         for (int b = 0; b < TN; ++b)
             bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[wn0 + b * 16 + fr][fk]);
+#pragma unroll
         for (int a = 0; a < TM; ++a)
+#pragma unroll
             for (int b = 0; b < TN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
         __syncthreads();
     }
     // C layout of a 16x16 tile: lane holds column lane%16, rows 4*(lane/16) + r
     const int cc = lane & 15, cr = (lane >> 4) * 4;
+#pragma unroll
     for (int a = 0; a < TM; ++a)
+#pragma unroll
         for (int b = 0; b < TN; ++b) {
             const int col = n0 + wn0 + b * 16 + cc;
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm0 + a * 16 + cr + r;
                 if (row < M && col < N) epi(row, col, acc[a][b][r], blockIdx.z);

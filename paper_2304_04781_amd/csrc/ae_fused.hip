@@ -78,97 +78,119 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
     const long long pa = m0 + am;
     const bool a_ok = pa < a.P;
     long long abase = 0;
-    float lo[4] = {0.f, 0.f, 0.f, 0.f}, rr[4] = {1.f, 1.f, 1.f, 1.f};
+    // per-field (min, range) of the block's patches, in LDS after the hidden-layer area
+    float* sMeta = reinterpret_cast<float*>(smem + BM * (HID + HPAD));  // [BM][8]
     if (a_ok) {
         const int px = (int)(pa % a.Px), py = (int)((pa / a.Px) % a.Py), pz = (int)(pa / ((long long)a.Px * a.Py));
         abase = ((long long)pz * 8 * a.ny + py * 8) * a.nx + px * 8;
-        for (int f = 0; f < 4; ++f) {
-            lo[f] = a.meta[pa * 8 + 2 * f];
-            rr[f] = a.meta[pa * 8 + 2 * f + 1];
-        }
     }
-    // k-step kk covers field f = kk/16, lz = (kk%16)/2, ly = 4*(kk%2) + aq
-    auto load_a = [&](int kk, float4& x0, float4& x1) {
-        if (!a_ok) {
-            x0 = x1 = make_float4(0.f, 0.f, 0.f, 0.f);
-            return;
-        }
-        const int f = kk >> 4, lz = (kk & 15) >> 1, ly = 4 * (kk & 1) + aq;
-        const float* src = a.state + f * a.N + abase + ((long long)lz * a.ny + ly) * a.nx;
-        x0 = *reinterpret_cast<const float4*>(src);
-        x1 = *reinterpret_cast<const float4*>(src + 4);
-    };
-    auto store_a = [&](int kk, int buf, const float4& x0, const float4& x1) {
-        const int f = kk >> 4;
-        const float l = lo[f], r = rr[f];
-        uint16_t v[8];
-        if (a_ok) {
-            v[0] = f2bf((x0.x - l) / r); v[1] = f2bf((x0.y - l) / r); v[2] = f2bf((x0.z - l) / r); v[3] = f2bf((x0.w - l) / r);
-            v[4] = f2bf((x1.x - l) / r); v[5] = f2bf((x1.y - l) / r); v[6] = f2bf((x1.z - l) / r); v[7] = f2bf((x1.w - l) / r);
-        } else {
-            for (int t = 0; t < 8; ++t) v[t] = 0;
-        }
-        *reinterpret_cast<uint4*>(&sA[buf][am][aq * 8]) = *reinterpret_cast<const uint4*>(v);
-    };
-    // B fragments: wave owns hidden units [64*wave, 64*wave + 64)
+    if (tid < BM) {
+        const long long p = m0 + tid;
+        const float4 m01 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8) : make_float4(0.f, 1.f, 0.f, 1.f);
+        const float4 m23 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8 + 4) : make_float4(0.f, 1.f, 0.f, 1.f);
+        *reinterpret_cast<float4*>(sMeta + tid * 8) = m01;
+        *reinterpret_cast<float4*>(sMeta + tid * 8 + 4) = m23;
+    }
+    __syncthreads();
+    // k-step kk covers field f = kk/16, lz = (kk%16)/2, ly = 4*(kk%2) + aq: rows of 8 x-cells
     const int fr = lane & 15, fq = (lane >> 4) * 8;
-    const uint16_t* wb = a.w1t + (long long)(wave * 64 + fr) * 2048 + fq;
-    auto load_b = [&](int kk, bf16x8 (&b)[4]) {
-        for (int tj = 0; tj < 4; ++tj) b[tj] = *reinterpret_cast<const bf16x8*>(wb + (long long)tj * 16 * 2048 + kk * KB);
-    };
+    const uint16_t* wb = a.w1t + (long long)(wave * 64 + fr) * 2048 + fq;  // B: hidden units of this wave
 
     f32x4 acc[8][4];
+#pragma unroll
     for (int i = 0; i < 8; ++i)
+#pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    constexpr int KSTEPS = 2048 / KB;
-    float4 x0, x1;
-    bf16x8 bcur[4], bnxt[4];
-    load_a(0, x0, x1);
-    store_a(0, 0, x0, x1);
-    load_b(0, bcur);
+    float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
+    bf16x8 b0, b1, b2, b3;          // B fragments of the current k-step
+    bf16x8 n0, n1, n2, n3;          // prefetched B fragments of the next k-step
+#define WV_LOAD_A(kk)                                                                              \
+    if (a_ok) {                                                                                    \
+        const int f_ = (kk) >> 4, lz_ = ((kk)&15) >> 1, ly_ = 4 * ((kk)&1) + aq;                   \
+        const float* src_ = a.state + f_ * a.N + abase + ((long long)lz_ * a.ny + ly_) * a.nx;     \
+        x0 = *reinterpret_cast<const float4*>(src_);                                               \
+        x1 = *reinterpret_cast<const float4*>(src_ + 4);                                           \
+    }
+#define WV_STORE_A(buf, l, r)                                                                      \
+    {                                                                                              \
+        uint4 w_ = make_uint4(0, 0, 0, 0);                                                         \
+        if (a_ok) {                                                                                \
+            w_.x = (uint32_t)f2bf((x0.x - (l)) / (r)) | ((uint32_t)f2bf((x0.y - (l)) / (r)) << 16); \
+            w_.y = (uint32_t)f2bf((x0.z - (l)) / (r)) | ((uint32_t)f2bf((x0.w - (l)) / (r)) << 16); \
+            w_.z = (uint32_t)f2bf((x1.x - (l)) / (r)) | ((uint32_t)f2bf((x1.y - (l)) / (r)) << 16); \
+            w_.w = (uint32_t)f2bf((x1.z - (l)) / (r)) | ((uint32_t)f2bf((x1.w - (l)) / (r)) << 16); \
+        }                                                                                          \
+        *reinterpret_cast<uint4*>(&sA[(buf)][am][aq * 8]) = w_;                                     \
+    }
+#define WV_LOAD_B(kk, d0, d1, d2, d3)                                                              \
+    {                                                                                              \
+        const uint16_t* q_ = wb + (kk) * KB;                                                       \
+        d0 = *reinterpret_cast<const bf16x8*>(q_);                                                 \
+        d1 = *reinterpret_cast<const bf16x8*>(q_ + 16 * 2048);                                     \
+        d2 = *reinterpret_cast<const bf16x8*>(q_ + 32 * 2048);                                     \
+        d3 = *reinterpret_cast<const bf16x8*>(q_ + 48 * 2048);                                     \
+    }
+
+    WV_LOAD_A(0);
+    WV_STORE_A(0, sMeta[am * 8], sMeta[am * 8 + 1]);
+    WV_LOAD_B(0, b0, b1, b2, b3);
     __syncthreads();
-    for (int kk = 0; kk < KSTEPS; ++kk) {
+    for (int kk = 0; kk < 64; ++kk) {
         const int buf = kk & 1;
-        const bool more = kk + 1 < KSTEPS;
+        const bool more = kk + 1 < 64;
         if (more) {
-            load_a(kk + 1, x0, x1);
-            load_b(kk + 1, bnxt);
+            WV_LOAD_A(kk + 1);
+            WV_LOAD_B(kk + 1, n0, n1, n2, n3);
         }
-        bf16x8 af[8];
-        for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][i * 16 + fr][fq]);
-        for (int i = 0; i < 8; ++i)
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bcur[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[buf][i * 16 + fr][fq]);
+            acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b0, acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b1, acc[i][1], 0, 0, 0);
+            acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b2, acc[i][2], 0, 0, 0);
+            acc[i][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b3, acc[i][3], 0, 0, 0);
+        }
         if (more) {
-            store_a(kk + 1, buf ^ 1, x0, x1);
-            for (int j = 0; j < 4; ++j) bcur[j] = bnxt[j];
+            const int fn = (kk + 1) >> 4;
+            WV_STORE_A(buf ^ 1, sMeta[am * 8 + 2 * fn], sMeta[am * 8 + 2 * fn + 1]);
+            b0 = n0; b1 = n1; b2 = n2; b3 = n3;
         }
         __syncthreads();
     }
+#undef WV_LOAD_A
+#undef WV_STORE_A
+#undef WV_LOAD_B
     // hidden layer: bias + GELU -> bf16 in LDS (aliases the A buffers)
     const int cr = (lane >> 4) * 4;
+    #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int n = wave * 64 + j * 16 + fr;
         const float bias = a.b1[n];
+        #pragma unroll
         for (int i = 0; i < 8; ++i)
+            #pragma unroll
             for (int r = 0; r < 4; ++r) sH[i * 16 + cr + r][n] = f2bf(gelu(acc[i][j][r] + bias));
     }
     __syncthreads();
     // second layer: Z[BM][L] = H W2^T; wave handles rows [16*wave, 16*wave+16), all L columns
     constexpr int TJ = L / 16;
     f32x4 z[TJ];
+    #pragma unroll
     for (int j = 0; j < TJ; ++j) z[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kk = 0; kk < HID / KB; ++kk) {
         const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sH[wave * 16 + fr][kk * KB + fq]);
+        #pragma unroll
         for (int j = 0; j < TJ; ++j) {
             const bf16x8 bw = *reinterpret_cast<const bf16x8*>(a.w2t + (long long)(j * 16 + fr) * HID + kk * KB + fq);
             z[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw, z[j], 0, 0, 0);
         }
     }
+    #pragma unroll
     for (int j = 0; j < TJ; ++j) {
         const int n = j * 16 + fr;
         const float bias = a.b2[n];
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long long p = m0 + wave * 16 + cr + r;
             if (p < a.P) {
@@ -192,12 +214,17 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
     // layer 3: H[BM][HID] = GELU(Z W3^T + b3); wave owns hidden units [64 wave, +64)
     {
         f32x4 acc[8][4];
+        #pragma unroll
         for (int i = 0; i < 8; ++i)
+            #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int kk = 0; kk < L / KB; ++kk) {
             bf16x8 bw[4];
+            #pragma unroll
             for (int j = 0; j < 4; ++j)
                 bw[j] = *reinterpret_cast<const bf16x8*>(a.w3t + (long long)(wave * 64 + j * 16 + fr) * L + kk * KB + fq);
+            #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const long long p = m0 + i * 16 + fr;
                 bf16x8 az;
@@ -207,45 +234,60 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
                     const uint4 zero = make_uint4(0, 0, 0, 0);
                     az = *reinterpret_cast<const bf16x8*>(&zero);
                 }
+                #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(az, bw[j], acc[i][j], 0, 0, 0);
             }
         }
+        #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = wave * 64 + j * 16 + fr;
             const float bias = a.b3[n];
+            #pragma unroll
             for (int i = 0; i < 8; ++i)
+                #pragma unroll
                 for (int r = 0; r < 4; ++r) sH[i * 16 + cr + r][n] = f2bf(gelu(acc[i][j][r] + bias));
         }
     }
     __syncthreads();
     // layer 4, rows of field f: wave owns outputs [64 wave, +64) = the lz = wave plane of every patch
     f32x4 acc[8][4];
+    #pragma unroll
     for (int i = 0; i < 8; ++i)
+        #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t* wb = a.w4t + (long long)(a.f * 512 + wave * 64 + fr) * HID + fq;
     bf16x8 bcur[4], bnxt[4];
+    #pragma unroll
     for (int j = 0; j < 4; ++j) bcur[j] = *reinterpret_cast<const bf16x8*>(wb + (long long)j * 16 * HID);
     for (int kk = 0; kk < HID / KB; ++kk) {
         const bool more = kk + 1 < HID / KB;
         if (more)
+            #pragma unroll
             for (int j = 0; j < 4; ++j)
                 bnxt[j] = *reinterpret_cast<const bf16x8*>(wb + (long long)j * 16 * HID + (kk + 1) * KB);
         bf16x8 af[8];
+        #pragma unroll
         for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sH[i * 16 + fr][kk * KB + fq]);
+        #pragma unroll
         for (int i = 0; i < 8; ++i)
+            #pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bcur[j], acc[i][j], 0, 0, 0);
         if (more)
+            #pragma unroll
             for (int j = 0; j < 4; ++j) bcur[j] = bnxt[j];
     }
     // de-normalise and write: column n = 64 wave + 16 j + fr -> (lz, ly, lx)
+    #pragma unroll
     for (int i = 0; i < 8; ++i)
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long long p = m0 + i * 16 + cr + r;
             if (p >= a.P) continue;
             const float lo = a.meta[p * 8 + 2 * a.f], rg = a.meta[p * 8 + 2 * a.f + 1];
             const int px = (int)(p % a.Px), py = (int)((p / a.Px) % a.Py), pz = (int)(p / ((long long)a.Px * a.Py));
+            #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = j * 16 + fr;  // within the lz plane
                 const int n = wave * 64 + c;
@@ -258,7 +300,7 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
 size_t enc_smem()
 {
     const size_t a = 2 * BM * (KB + APAD) * 2, h = (size_t)BM * (HID + HPAD) * 2;
-    return a > h ? a : h;
+    return (a > h ? a : h) + (size_t)BM * 8 * 4;  // + per-patch (min, range) table
 }
 
 template <class K>

@@ -60,8 +60,19 @@ __global__ void __launch_bounds__(SEL_THREADS) topk_kernel(const float* __restri
         for (int b = lane; b < 256; b += 64) hist[wave][b] = 0;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < KPT; ++q)
-            if (q < nk && (key[q] & mask) == prefix) atomicAdd(&hist[wave][(key[q] >> shift) & 255u], 1u);
+        for (int q = 0; q < KPT; ++q) {
+            // one LDS atomic per distinct digit in the wave (many keys share the floor value)
+            const unsigned d = (key[q] >> shift) & 255u;
+            bool pending = q < nk && (key[q] & mask) == prefix;
+            while (__any(pending)) {
+                const unsigned long long live = __ballot(pending);
+                const int leader = __ffsll((long long)live) - 1;
+                const unsigned ld = __shfl(d, leader, 64);
+                const unsigned long long same = __ballot(pending && d == ld);
+                if (lane == leader) atomicAdd(&hist[wave][ld], (unsigned)__popcll(same));
+                if (d == ld) pending = false;
+            }
+        }
         __syncthreads();
         if (tid < 256) {
             unsigned t = 0;
