@@ -648,10 +648,12 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
                            pg.ny, pg.nx, N, pg.ny / 8, pg.nx / 8, a->beta_d, meta);
         WV_HIP(hipGetLastError());
         if (fmt == AE_LATENT_BF16) {
-            fused_encode(pg, state, meta, a->wt[0], a->bias(0), a->wt[1], a->bias(1), (uint16_t*)latent, nullptr, st);
+            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1),
+                         (uint16_t*)latent, nullptr, st);
         } else {
             float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
-            fused_encode(pg, state, meta, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
+            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr,
+                         z, st);
             hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                                qscale);
             WV_HIP(hipGetLastError());
@@ -672,6 +674,28 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
         gemm_auto((int)P, a->lat, a->hid, lh, lw, EpiBF16{(uint16_t*)latent, a->lat, a->bias(1), nullptr}, st);
     } else {
         gemm_auto((int)P, a->lat, a->hid, lh, lw, EpiF32{z, a->lat, 0, a->bias(1)}, st);
+        hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
+                           qscale);
+        WV_HIP(hipGetLastError());
+    }
+}
+
+void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state, const float* mm, int H, int fmt,
+                        void* latent, float* meta, float* qscale, hipStream_t st)
+{
+    if (!fused_supported(a->hid, a->lat)) {
+        ae_encode_state(a, pg, state, fmt, latent, meta, qscale, st);
+        return;
+    }
+    WV_REQUIRE(a && state && mm && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
+               "encode: null buffer");
+    const long long P = pg.P;
+    if (fmt == AE_LATENT_BF16) {
+        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1),
+                     (uint16_t*)latent, nullptr, st);
+    } else {
+        float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
+        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
         hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                            qscale);
         WV_HIP(hipGetLastError());

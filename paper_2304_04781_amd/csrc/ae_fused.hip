@@ -38,7 +38,10 @@ constexpr int HPAD = 8;
 
 struct EncArgs {
     const float* state;   // [4][N]
-    const float* meta;    // [P][4][2] (min, range)
+    const float* meta;    // [P][4][2] (min, range); output when mm is given
+    const float* mm;      // optional [P][H][4][2] partial (min, max) from the forward step
+    int H;
+    const float* beta;    // [4] range floors (with mm)
     const uint16_t* w1t;  // [HID][2048]
     const float* b1;      // [HID]
     const uint16_t* w2t;  // [L][HID]
@@ -86,10 +89,31 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
     }
     if (tid < BM) {
         const long long p = m0 + tid;
-        const float4 m01 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8) : make_float4(0.f, 1.f, 0.f, 1.f);
-        const float4 m23 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8 + 4) : make_float4(0.f, 1.f, 0.f, 1.f);
-        *reinterpret_cast<float4*>(sMeta + tid * 8) = m01;
-        *reinterpret_cast<float4*>(sMeta + tid * 8 + 4) = m23;
+        if (a.mm) {
+            // combine the y sub-tile partials: r = max(max - min, beta_f); publish the metadata
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                float lo = 0.f, r = 1.f;
+                if (p < a.P) {
+                    lo = a.mm[(p * a.H) * 8 + 2 * f];
+                    float hi = a.mm[(p * a.H) * 8 + 2 * f + 1];
+                    for (int h = 1; h < a.H; ++h) {
+                        lo = fminf(lo, a.mm[(p * a.H + h) * 8 + 2 * f]);
+                        hi = fmaxf(hi, a.mm[(p * a.H + h) * 8 + 2 * f + 1]);
+                    }
+                    r = fmaxf(hi - lo, a.beta[f]);
+                    const_cast<float*>(a.meta)[p * 8 + 2 * f] = lo;
+                    const_cast<float*>(a.meta)[p * 8 + 2 * f + 1] = r;
+                }
+                sMeta[tid * 8 + 2 * f] = lo;
+                sMeta[tid * 8 + 2 * f + 1] = r;
+            }
+        } else {
+            const float4 m01 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8) : make_float4(0.f, 1.f, 0.f, 1.f);
+            const float4 m23 = p < a.P ? *reinterpret_cast<const float4*>(a.meta + p * 8 + 4) : make_float4(0.f, 1.f, 0.f, 1.f);
+            *reinterpret_cast<float4*>(sMeta + tid * 8) = m01;
+            *reinterpret_cast<float4*>(sMeta + tid * 8 + 4) = m23;
+        }
     }
     __syncthreads();
     // k-step kk covers field f = kk/16, lz = (kk%16)/2, ly = 4*(kk%2) + aq: rows of 8 x-cells
@@ -317,11 +341,12 @@ void allow_smem(K kernel, size_t bytes)
 
 bool fused_supported(int hid, int lat) { return hid == HID && lat == 32; }
 
-void fused_encode(const PatchGrid& pg, const float* state, const float* meta, const uint16_t* w1t, const float* b1,
-                  const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf, hipStream_t st)
+void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
+                  const uint16_t* w1t, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
+                  hipStream_t st)
 {
-    EncArgs a{state, meta, w1t, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
-              pg.ny / 8, pg.nx / 8};
+    EncArgs a{state, meta, mm, H, beta, w1t, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny,
+              pg.nx, pg.ny / 8, pg.nx / 8};
     const size_t sm = enc_smem();
     allow_smem(encode_kernel<32>, sm);
     hipLaunchKernelGGL(encode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), sm, st, a);

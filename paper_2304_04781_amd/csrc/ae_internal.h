@@ -22,6 +22,10 @@ long long ae_latent_bytes_per_patch(const ae_net* net, int fmt);
 // Compress one state [4][N] into latent [P][L] (+ meta [P][4][2], qscale [P] for FP8).
 void ae_encode_state(const ae_net* net, const PatchGrid& pg, const float* state, int fmt,
                      void* latent, float* meta, float* qscale, hipStream_t st);
+// Compress with the per-patch (min, max) partials [P][H][4][2] computed by the
+// forward step (no separate pass over the state for the normalisation).
+void ae_encode_state_mm(const ae_net* net, const PatchGrid& pg, const float* state, const float* mm, int H, int fmt,
+                        void* latent, float* meta, float* qscale, hipStream_t st);
 // Decompress the fields in field_mask into state [4][N].
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st);
@@ -29,8 +33,11 @@ void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent,
 // Fused inference kernels (hidden width 512, latent 32): meta must already hold
 // the per-patch (min, range) of the state for encode.
 bool fused_supported(int hid, int lat);
-void fused_encode(const PatchGrid& pg, const float* state, const float* meta, const uint16_t* w1t, const float* b1,
-                  const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf, hipStream_t st);
+// meta: input (min, range), or output when the partial (min, max) table mm
+// [P][H][4][2] of the forward step is given (then r = max(max - min, beta_f)).
+void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
+                  const uint16_t* w1t, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
+                  hipStream_t st);
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4t, const float* b4, int f, float* state, hipStream_t st);
 

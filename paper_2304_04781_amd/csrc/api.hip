@@ -109,6 +109,12 @@ struct wv_ctx {
     int K = 0;                   // active exception patches per state
     int* exc_idx = nullptr;      // [T-1][S][K]
     float* exc = nullptr;        // [T-1][S][K][512]
+    float* mmpart = nullptr;     // [S][P][H][4][2] (min, max) partials of the forward step
+    int H = 1;                   // y sub-tiles per patch
+    hipStream_t side = nullptr;  // exception selection/gather, overlapped with the time loop
+    hipEvent_t ev_enc = nullptr;
+    hipEvent_t ev_gather[2] = {nullptr, nullptr};
+    bool gather_pending[2] = {false, false};
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -195,11 +201,15 @@ StepArgs base_args(const wv_ctx* c)
     a.tiles_y = c->tl.tiles_y;
     a.chunks_z = c->tl.chunks_z;
     a.kc = c->tl.kc;
+    a.chunks_adj = c->tl.chunks_adj;
+    a.kc_adj = c->tl.kc_adj;
+    a.mm_out = nullptr;
     return a;
 }
 
-// one forward step n: state in -> out; traces (nullptr: not recorded)
-void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces)
+// one forward step n: state in -> out; traces (nullptr: not recorded); mm: per-patch
+// (min, max) partials of the new state (nullptr: not computed)
+void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, float* mm = nullptr)
 {
     StepArgs a = base_args(c);
     a.in = in;
@@ -207,6 +217,7 @@ void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces)
     a.step = n;
     a.tidx = n;
     a.traces = traces;
+    a.mm_out = mm;
     if (!traces) a.nrec = 0;
     launch_step(MODE_FWD, c->has_y, a, c->S, c->st);
 }
@@ -259,6 +270,7 @@ void free_store(wv_ctx* c)
     dev_free(c->qs);
     dev_free(c->exc_idx);
     dev_free(c->exc);
+    dev_free(c->mmpart);
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -311,8 +323,9 @@ float* qs_slot(wv_ctx* c, int idx, int s)
     return c->qs ? c->qs + ((long long)idx * c->S + s) * c->P : nullptr;
 }
 
-// store x_n (n = 1..T-1) of every source
-void store_state(wv_ctx* c, int n, const float* state)
+// store x_n (n = 1..T-1) of every source; wi = index of the work buffer holding
+// it (-1: not a work buffer), whose reuse must wait for the exception gather
+void store_state(wv_ctx* c, int n, const float* state, int wi = -1, bool have_mm = false)
 {
     if (n < 1 || n > c->T - 1) return;
     if (c->mode == WV_STORE_FULL) {
@@ -322,12 +335,29 @@ void store_state(wv_ctx* c, int n, const float* state)
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
         for (int s = 0; s < c->S; ++s) {
-            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
-                            meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
-            if (c->K > 0) {
+            if (have_mm)
+                ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, c->mmpart + (long long)s * c->P * c->H * 8, c->H,
+                                   ae_fmt(c->mode), lat_slot(c, n - 1, s), meta_slot(c, n - 1, s),
+                                   qs_slot(c, n - 1, s), c->st);
+            else
+                ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
+                                meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
+        }
+        if (c->K > 0) {
+            // select and copy the exact patches on the side stream, overlapped with the next step
+            hipStream_t xs = wi >= 0 ? c->side : c->st;
+            if (wi >= 0) {
+                WV_HIP(hipEventRecord(c->ev_enc, c->st));
+                WV_HIP(hipStreamWaitEvent(c->side, c->ev_enc, 0));
+            }
+            for (int s = 0; s < c->S; ++s) {
                 const long long q = (long long)(n - 1) * c->S + s;
                 exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
-                                 c->exc + q * c->K * 512, c->st);
+                                 c->exc + q * c->K * 512, xs);
+            }
+            if (wi >= 0) {
+                WV_HIP(hipEventRecord(c->ev_gather[wi], c->side));
+                c->gather_pending[wi] = true;
             }
         }
     }
@@ -374,16 +404,28 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
     float* cur = c->work[0];
     float* prev = cur;
     const int ncap = (capture && every > 0) ? (c->T - 1) / every : 0;
+    const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
     for (int n = 0; n < c->T; ++n) {
         float* out = (snap && (*snap)[n + 1] > 0) ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
-        fwd_step(c, cur, out, n, traces);
-        if (n + 1 <= c->T - 1) store_state(c, n + 1, out);
+        const int wi = out == c->work[0] ? 0 : (out == c->work[1] ? 1 : -1);
+        if (wi >= 0 && c->gather_pending[wi]) {
+            WV_HIP(hipStreamWaitEvent(c->st, c->ev_gather[wi], 0));
+            c->gather_pending[wi] = false;
+        }
+        const bool store = n + 1 <= c->T - 1;
+        fwd_step(c, cur, out, n, traces, (ae && store) ? c->mmpart : nullptr);
+        if (store) store_state(c, n + 1, out, wi, ae);
         if (ncap > 0 && (n + 1) % every == 0 && (n + 1) / every <= ncap)
             WV_HIP(hipMemcpyAsync(capture + (long long)((n + 1) / every - 1) * c->state_floats(), out,
                                   sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice, c->st));
         prev = cur;
         cur = out;
     }
+    for (int w = 0; w < 2; ++w)
+        if (c->gather_pending[w]) {
+            WV_HIP(hipStreamWaitEvent(c->st, c->ev_gather[w], 0));
+            c->gather_pending[w] = false;
+        }
     c->last_fwd_steps = c->T;
     if (last) *last = cur;
     return prev;
@@ -550,6 +592,10 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->traces = dev_alloc<float>(ntr);
         c->resid = dev_alloc<float>(ntr);
         c->dtr = dev_alloc<float>(ntr);
+        WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        WV_HIP(hipEventCreateWithFlags(&c->ev_enc, hipEventDisableTiming));
+        WV_HIP(hipEventCreateWithFlags(&c->ev_gather[0], hipEventDisableTiming));
+        WV_HIP(hipEventCreateWithFlags(&c->ev_gather[1], hipEventDisableTiming));
         c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
         c->dscal = dev_alloc<double>(8);
         c->dflag = dev_alloc<int>(1);
@@ -562,8 +608,13 @@ int wv_destroy(wv_ctx* c)
 {
     if (!c) return WV_OK;
     (void)hipStreamSynchronize(c->st);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     free_store(c);
     free_tiling(c->tl);
+    if (c->ev_enc) (void)hipEventDestroy(c->ev_enc);
+    for (int w = 0; w < 2; ++w)
+        if (c->ev_gather[w]) (void)hipEventDestroy(c->ev_gather[w]);
+    if (c->side) (void)hipStreamDestroy(c->side);
     dev_free(c->tab);
     dev_free(c->src_kji);
     dev_free(c->src_w);
@@ -625,6 +676,8 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
                 c->exc = dev_alloc<float>(slots * K * 512);
             }
             c->K = K;
+            c->H = 8 / c->tl.by;
+            c->mmpart = dev_alloc<float>((size_t)c->S * c->P * c->H * 8);
             c->store_bytes = bytes;
             if (fallback_policy == WV_FALLBACK_CHECKPOINT)
                 WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");

@@ -24,6 +24,10 @@
 
 #include "wv_internal.h"
 
+#ifndef WV_NT_STORE
+#define WV_NT_STORE 1
+#endif
+
 namespace wv {
 
 namespace {
@@ -36,6 +40,7 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
     __shared__ float sP[BY + 2][BX + 2];
     __shared__ float sWy[HAS_Y ? BY + 1 : 1][BX];
     __shared__ float sWx[BY][BX + 1];
+    __shared__ float sMM[BY][BX / 8][8];  // per-row partial (min, max) of 8 patches
 
     // ---- block -> (x tile, y tile, z chunk); spread so one XCD gets a contiguous range
     const int nblk = a.tiles_x * a.tiles_y * a.chunks_z;
@@ -105,12 +110,6 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
     const long long rcell = ring_in ? (long long)rj * nx + ri : 0;
     const float ring_wyx = ring_in ? a.wyc[rj] * a.wxc[ri] : 0.f;
 
-    auto P_at = [&](int k, long long off, float wyx) -> float {
-        if (MODE == MODE_FWD) return mm[off] * inA[off];
-        if (MODE == MODE_INC) return mm[off] * inA[off] + a.dm[off] * en[off];
-        return (a.wzc[k] * wyx) * inA[off];
-    };
-
     // receiver-list cursors (uniform across the work-group)
     int rp = 0, re = 0;
     if (a.nrec > 0) { rp = a.rec_ptr[tile]; re = a.rec_ptr[tile + 1]; }
@@ -155,51 +154,101 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
     // what enters the divergence: v' (forward) or S_v mu' (adjoint)
     auto face_w = [&](float S, float Vn) -> float { return MODE == MODE_ADJ ? S * Vn : Vn; };
 
-    // ---- prologue: P(k0), cell value, v_z'(k0)
-    float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
-    {
-        const long long off = (long long)k0 * plane + cell;
-        float P_lo = 0.f, Vz_in = 0.f;
-        if (inside) {
-            A_cur = inA[off];
-            m_cur = mm[off];
-            P_cur = P_at(k0, off, wyx_c);
-            if (k0 > 0) P_lo = P_at(k0 - 1, off - plane, wyx_c);
-            Vz_in = inVz[off];
+    // Software pipeline: the column data of level k+2 and the in-plane data of
+    // level k+1 are loaded while level k is computed.
+    struct Col {  // own column at one level
+        float A, m, Vz, dm, en;
+    };
+    struct Pln {  // in-plane operands of one level
+        float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp;
+    };
+    auto load_col = [&](int kk, Col& c) {
+        c.A = c.m = c.Vz = c.dm = c.en = 0.f;
+        if (inside && kk >= 0 && kk < nz) {
+            const long long o = (long long)kk * plane + cell;
+            c.A = inA[o];
+            c.m = mm[o];
+            c.Vz = inVz[o];
+            if (MODE == MODE_INC) {
+                c.dm = a.dm[o];
+                c.en = en[o];
+            }
         }
+    };
+    auto load_pln = [&](int kk, Pln& q) {
+        q.Vy = q.Vx = q.Vyh = q.Vxh = q.rA = q.rm = q.rdm = q.ren = q.ek = q.acc = q.cmp = 0.f;
+        const long long ok = (long long)kk * plane;
+        if (inside) {
+            if (HAS_Y) q.Vy = inVy[ok + cell];
+            q.Vx = inVx[ok + cell];
+            if (MODE == MODE_ADJ) {
+                q.ek = ek[ok + cell];
+                q.acc = acc[ok + cell];
+                q.cmp = cmp[ok + cell];
+            }
+        }
+        if (halo_y) q.Vyh = inVy[ok + (long long)jh * nx + i];
+        if (halo_x) q.Vxh = inVx[ok + (long long)j * nx + ih];
+        if (ring_in) {
+            q.rA = inA[ok + rcell];
+            if (MODE != MODE_ADJ) q.rm = mm[ok + rcell];
+            if (MODE == MODE_INC) {
+                q.rdm = a.dm[ok + rcell];
+                q.ren = en[ok + rcell];
+            }
+        }
+    };
+    auto P_col = [&](int kk, const Col& c) -> float {
+        if (MODE == MODE_FWD) return c.m * c.A;
+        if (MODE == MODE_INC) return c.m * c.A + c.dm * c.en;
+        return (a.wzc[kk] * wyx_c) * c.A;
+    };
+    auto P_ring = [&](int kk, const Pln& q) -> float {
+        if (!ring_in) return 0.f;
+        if (MODE == MODE_FWD) return q.rm * q.rA;
+        if (MODE == MODE_INC) return q.rm * q.rA + q.rdm * q.ren;
+        return (a.wzc[kk] * ring_wyx) * q.rA;
+    };
+
+    // ---- prologue: P(k0), cell value, v_z'(k0); first pipeline stages
+    float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
+    Col cn, cnn;
+    Pln pc, pn;
+    {
+        Col c0, cl;
+        load_col(k0, c0);
+        load_col(k0 - 1, cl);
+        load_col(k0 + 1, cn);
+        load_pln(k0, pc);
+        A_cur = c0.A;
+        m_cur = c0.m;
+        P_cur = inside ? P_col(k0, c0) : 0.f;
+        const float P_lo = (inside && k0 > 0) ? P_col(k0 - 1, cl) : 0.f;
         const float add = face_inj(k0);
         const float S = a.wzf[k0] * wyx_c;
-        Vz_cur = face_new(S, Vz_in, P_cur - P_lo, add);
+        Vz_cur = face_new(S, c0.Vz, P_cur - P_lo, add);
         Wz_cur = face_w(S, Vz_cur);
     }
+
+    // running (min, max) of the 4 new fields over the current patch layer
+    const bool want_mm = MODE == MODE_FWD && HAS_Y && a.mm_out != nullptr;
+    float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY;
+    float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY, mx3 = -INFINITY;
 
     for (int k = k0; k < k1; ++k) {
         const long long offk = (long long)k * plane + cell;
         const bool has_next = k + 1 < nz;
-
-        float A_nx = 0.f, m_nx = 0.f, P_nx = 0.f, Vz_nx_in = 0.f;
-        float Vy_in = 0.f, Vx_in = 0.f, e_k = 0.f, s_acc = 0.f, s_cmp = 0.f;
-        if (inside) {
-            if (has_next) {
-                const long long o1 = offk + plane;
-                A_nx = inA[o1];
-                m_nx = mm[o1];
-                P_nx = P_at(k + 1, o1, wyx_c);
-                Vz_nx_in = inVz[o1];
-            }
-            if (HAS_Y) Vy_in = inVy[offk];
-            Vx_in = inVx[offk];
-            if (MODE == MODE_ADJ) {
-                e_k = ek[offk];
-                s_acc = acc[offk];
-                s_cmp = cmp[offk];
-            }
+        // issue the loads of the next pipeline stages
+        if (k + 1 < k1) {
+            load_col(k + 2, cnn);
+            load_pln(k + 1, pn);
         }
-        float Vy_h = 0.f, Vx_h = 0.f;
-        if (halo_y) Vy_h = inVy[(long long)k * plane + (long long)jh * nx + i];
-        if (halo_x) Vx_h = inVx[(long long)k * plane + (long long)j * nx + ih];
-        float Pr = 0.f;
-        if (ring_in) Pr = P_at(k, (long long)k * plane + rcell, ring_wyx);
+        const float P_nx = (inside && has_next) ? P_col(k + 1, cn) : 0.f;
+        const float Vz_nx_in = cn.Vz;
+        const float Vy_in = pc.Vy, Vx_in = pc.Vx, Vy_h = pc.Vyh, Vx_h = pc.Vxh;
+        const float e_k = pc.ek;
+        float s_acc = pc.acc, s_cmp = pc.cmp;
+        const float Pr = P_ring(k, pc);
 
         sP[ty + 1][tx + 1] = P_cur;
         if (ring) sP[rsy][rsx] = Pr;
@@ -257,13 +306,60 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
             A_new = Se * (A_cur + a.dtdx * dsum);
         }
         if (inside) {
+#if WV_NT_STORE
+            __builtin_nontemporal_store(A_new, &outA[offk]);
+            __builtin_nontemporal_store(Vz_cur, &outVz[offk]);
+            if (HAS_Y) __builtin_nontemporal_store(Vy_new, &outVy[offk]);
+            __builtin_nontemporal_store(Vx_new, &outVx[offk]);
+#else
             outA[offk] = A_new;
             outVz[offk] = Vz_cur;
             if (HAS_Y) outVy[offk] = Vy_new;
             outVx[offk] = Vx_new;
+#endif
             if (MODE == MODE_ADJ) {
                 acc[offk] = s_acc;
                 cmp[offk] = s_cmp;
+            }
+        }
+        if (want_mm) {
+            if (inside) {
+                mn0 = fminf(mn0, A_new); mx0 = fmaxf(mx0, A_new);
+                mn1 = fminf(mn1, Vz_cur); mx1 = fmaxf(mx1, Vz_cur);
+                mn2 = fminf(mn2, Vy_new); mx2 = fmaxf(mx2, Vy_new);
+                mn3 = fminf(mn3, Vx_new); mx3 = fmaxf(mx3, Vx_new);
+            }
+            if (((k + 1) & 7) == 0) {
+                // reduce the 8 x-lanes of each patch, then the BY rows of the tile
+#pragma unroll
+                for (int o = 1; o < 8; o <<= 1) {
+                    mn0 = fminf(mn0, __shfl_xor(mn0, o, 64)); mx0 = fmaxf(mx0, __shfl_xor(mx0, o, 64));
+                    mn1 = fminf(mn1, __shfl_xor(mn1, o, 64)); mx1 = fmaxf(mx1, __shfl_xor(mx1, o, 64));
+                    mn2 = fminf(mn2, __shfl_xor(mn2, o, 64)); mx2 = fmaxf(mx2, __shfl_xor(mx2, o, 64));
+                    mn3 = fminf(mn3, __shfl_xor(mn3, o, 64)); mx3 = fmaxf(mx3, __shfl_xor(mx3, o, 64));
+                }
+                if ((tx & 7) == 0) {
+                    float* d = sMM[ty][tx >> 3];
+                    d[0] = mn0; d[1] = mx0; d[2] = mn1; d[3] = mx1;
+                    d[4] = mn2; d[5] = mx2; d[6] = mn3; d[7] = mx3;
+                }
+                __syncthreads();
+                if (tid < (BX / 8) * 8) {
+                    const int q = tid >> 3, v = tid & 7;
+                    float r = sMM[0][q][v];
+#pragma unroll
+                    for (int y = 1; y < BY; ++y) r = (v & 1) ? fmaxf(r, sMM[y][q][v]) : fminf(r, sMM[y][q][v]);
+                    const int Px = nx >> 3, Py = ny >> 3;
+                    const int px = txx * (BX / 8) + q, py = j0 >> 3, pz = k >> 3;
+                    const int H = 8 / BY, h = (j0 & 7) / BY;
+                    if (px < Px) {
+                        const long long p = ((long long)pz * Py + py) * Px + px;
+                        const long long P = (long long)(nz >> 3) * Py * Px;
+                        a.mm_out[(((long long)s * P + p) * H + h) * 8 + v] = r;
+                    }
+                }
+                mn0 = mn1 = mn2 = mn3 = INFINITY;
+                mx0 = mx1 = mx2 = mx3 = -INFINITY;
             }
         }
         if (MODE != MODE_ADJ && a.nrec > 0) {
@@ -276,16 +372,24 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
             }
         }
         P_cur = P_nx;
-        A_cur = A_nx;
-        m_cur = m_nx;
+        A_cur = cn.A;
+        m_cur = cn.m;
         Vz_cur = Vz_nx;
         Wz_cur = Wz_nx;
+        cn = cnn;
+        pc = pn;
     }
 }
 
 template <int BX, int BY, bool HAS_Y>
-void launch_mode(int mode, const StepArgs& a, int nsrc, hipStream_t st)
+void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
 {
+    StepArgs a = a0;
+    if (mode == MODE_ADJ) {
+        a.kc = a.kc_adj;
+        a.chunks_z = a.chunks_adj;
+    }
+    if (mode != MODE_FWD || !HAS_Y) a.mm_out = nullptr;
     dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
     dim3 block(BX * BY);
     switch (mode) {
@@ -297,8 +401,17 @@ void launch_mode(int mode, const StepArgs& a, int nsrc, hipStream_t st)
 
 }  // namespace
 
+#ifndef WV_TILE_BY
+#define WV_TILE_BY 4
+#endif
+#ifndef WV_CHUNK_TARGET
+#define WV_CHUNK_TARGET 2048
+#endif
+#ifndef WV_CHUNK_TARGET_ADJ
+#define WV_CHUNK_TARGET_ADJ 8192
+#endif
 constexpr int TILE_BX = 64;
-constexpr int TILE_BY = 8;
+constexpr int TILE_BY = WV_TILE_BY;
 
 void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t st)
 {
@@ -318,13 +431,18 @@ Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji)
     t.tiles_x = (nx + t.bx - 1) / t.bx;
     t.tiles_y = (ny + t.by - 1) / t.by;
     const int tiles = t.tiles_x * t.tiles_y;
-    // enough work-groups to fill 256 CUs several times; chunks of >= 8 levels
-    int chunks = (2048 + tiles - 1) / tiles;
-    chunks = std::max(1, std::min(chunks, nz / 8 > 0 ? nz / 8 : 1));
-    int kc = (nz + chunks - 1) / chunks;
-    if (kc >= 8) kc = (kc + 7) / 8 * 8;
-    t.kc = kc;
-    t.chunks_z = (nz + kc - 1) / kc;
+    // enough work-groups to fill 256 CUs several times; chunks of a multiple of
+    // 8 levels (patch layers) when the depth allows
+    auto chunking = [&](int target, int* kc_out, int* chunks_out) {
+        int chunks = (target + tiles - 1) / tiles;
+        chunks = std::max(1, std::min(chunks, nz / 8 > 0 ? nz / 8 : 1));
+        int kc = (nz + chunks - 1) / chunks;
+        if (kc >= 8) kc = (kc + 7) / 8 * 8;
+        *kc_out = kc;
+        *chunks_out = (nz + kc - 1) / kc;
+    };
+    chunking(WV_CHUNK_TARGET, &t.kc, &t.chunks_z);
+    chunking(WV_CHUNK_TARGET_ADJ, &t.kc_adj, &t.chunks_adj);
 
     auto bucket = [&](const std::vector<int>& kji, int** d_ptr, int4** d_ent) {
         const int n = (int)kji.size() / 3;

@@ -40,7 +40,8 @@ enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2 };
 // bucketed per (y, x) tile and sorted by depth.
 struct Tiling {
     int bx = 64, by = 8;
-    int tiles_x = 0, tiles_y = 0, chunks_z = 0, kc = 0;
+    int tiles_x = 0, tiles_y = 0, chunks_z = 0, kc = 0;  // forward / incremental chunks
+    int chunks_adj = 0, kc_adj = 0;                       // adjoint chunks
     int* rec_ptr = nullptr;   // [tiles + 1]
     int4* rec_ent = nullptr;  // (k, local, r, 0)
 };
@@ -76,6 +77,10 @@ struct StepArgs {
     const float* en;
     long long enstride;
     int tiles_x, tiles_y, chunks_z, kc;
+    int chunks_adj, kc_adj;
+    // forward only: per-(patch, y sub-tile) min/max of the 4 new fields,
+    // [S][P][8/BY][4][2] = (min, max), written when non-null (3D, grid of 8^3 patches)
+    float* mm_out;
 };
 
 void launch_step(int mode, bool has_y, const StepArgs& a, int nsrc, hipStream_t st);
