@@ -23,7 +23,9 @@ Rounding emulation (emulate=True) applies the HIP path's precision
 contract so that differences reduce to FP32 summation order:
   y, W, hidden activations, latent -> bfloat16 (RNE); biases float32;
   products exact and summed (here in FP64); GELU on the unrounded
-  pre-activation; output float32. An FP8 latent (per-patch scale
+  pre-activation (here with the exact erf; the kernels use a published
+  erf approximation whose error, at most 1.5e-7, sits far below the
+  bfloat16 rounding that follows); output float32. An FP8 latent (per-patch scale
   s = max|z|/448, code = e4m3(z/s)) enters the decoder as bfloat16(code*s). Backward: upstream gradients are
   rounded to bfloat16 before they meet a bfloat16 operand in a product,
   bias gradients are plain sums, GELU' uses the stored pre-activation,
@@ -65,8 +67,9 @@ def unpatchify(X: np.ndarray, nz: int, ny: int, nx: int) -> np.ndarray:
 # ----- normalisation ----------------------------------------------------------
 def normalize(X: np.ndarray, beta, emulate: bool = False):
     """Per-(patch, field) min/range normalisation. Returns Y [P, 2048],
-    lo [P, 4], r [P, 4]. emulate=True forms the range and the quotient in
-    FP32 as the kernels do."""
+    lo [P, 4], r [P, 4]. emulate=True forms the range in FP32 and the
+    quotient as the FP32 product of FP32(x - lo) with the FP32-rounded
+    reciprocal of the range, as the kernels do."""
     P = X.shape[0]
     Xf = X.reshape(P, NFIELD, 512)
     lo = Xf.min(axis=2)
@@ -74,7 +77,8 @@ def normalize(X: np.ndarray, beta, emulate: bool = False):
     beta = np.asarray(beta, dtype=np.float64)[None, :]
     if emulate:
         r = np.maximum(rd.f32(hi - lo), rd.f32(beta))
-        Y = rd.f32(rd.f32(Xf - lo[..., None]) / r[..., None])
+        rinv = rd.f32(1.0 / r)
+        Y = rd.f32(rd.f32(Xf - lo[..., None]) * rinv[..., None])
     else:
         r = np.maximum(hi - lo, beta)
         Y = (Xf - lo[..., None]) / r[..., None]

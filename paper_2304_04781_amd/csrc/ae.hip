@@ -22,26 +22,13 @@
 #include <vector>
 
 #include "ae_internal.h"
+#include "ae_math.h"
 
 namespace wv {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t f2bf(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_prime(float x)
-{
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
 
 // OCP E4M3FN, round to nearest even, saturating at 448
 __device__ __forceinline__ uint8_t f2e4m3(float x)
@@ -296,9 +283,10 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict_
         hi = fmaxf(hi, __shfl_xor(hi, o, 64));
     }
     const float r = fmaxf(hi - lo, beta[f]);
-    uint16_t o8[8];
-    for (int t = 0; t < 8; ++t) o8[t] = f2bf((v[t] - lo) / r);
-    *reinterpret_cast<uint4*>(y + p * 2048 + f * 512 + l * 8) = *reinterpret_cast<const uint4*>(o8);
+    const float rinv = 1.0f / r;
+    const uint4 o8 = make_uint4(f2bf2((v[0] - lo) * rinv, (v[1] - lo) * rinv), f2bf2((v[2] - lo) * rinv, (v[3] - lo) * rinv),
+                                f2bf2((v[4] - lo) * rinv, (v[5] - lo) * rinv), f2bf2((v[6] - lo) * rinv, (v[7] - lo) * rinv));
+    *reinterpret_cast<uint4*>(y + p * 2048 + f * 512 + l * 8) = o8;
     if (l == 0) {
         meta[p * 8 + 2 * f] = lo;
         meta[p * 8 + 2 * f + 1] = r;
@@ -521,6 +509,8 @@ struct ae_net {
     float* grad = nullptr;
     uint16_t* wb[4] = {nullptr, nullptr, nullptr, nullptr};  // bf16 W   [fi][fo]
     uint16_t* wt[4] = {nullptr, nullptr, nullptr, nullptr};  // bf16 W^T [fo][fi]
+    uint16_t* wp1 = nullptr;  // W1^T and W4^T in MFMA fragment order (fused kernels only)
+    uint16_t* wp4 = nullptr;
     float* beta_d = nullptr;
     double* loss_d = nullptr;
     double beta[4] = {1e-7, 1e-7, 1e-7, 1e-7};
@@ -571,6 +561,10 @@ void refresh_bf16(ae_net* a, hipStream_t st)
                            a->fo[l], a->wb[l], a->wt[l]);
     }
     WV_HIP(hipGetLastError());
+    if (a->wp1) {
+        fused_pack(a->wt[0], a->hid, a->in, a->wp1, st);
+        fused_pack(a->wt[3], a->in, a->hid, a->wp4, st);
+    }
 }
 
 void upload_beta(ae_net* a)
@@ -648,11 +642,11 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
                            pg.ny, pg.nx, N, pg.ny / 8, pg.nx / 8, a->beta_d, meta);
         WV_HIP(hipGetLastError());
         if (fmt == AE_LATENT_BF16) {
-            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1),
+            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
                          (uint16_t*)latent, nullptr, st);
         } else {
             float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
-            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr,
+            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr,
                          z, st);
             hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                                qscale);
@@ -691,11 +685,11 @@ void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state
                "encode: null buffer");
     const long long P = pg.P;
     if (fmt == AE_LATENT_BF16) {
-        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1),
+        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
                      (uint16_t*)latent, nullptr, st);
     } else {
         float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
-        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wt[0], a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
+        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
         hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                            qscale);
         WV_HIP(hipGetLastError());
@@ -719,7 +713,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
         }
         for (int f = 0; f < 4; ++f)
             if (mask & (1u << f))
-                fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wt[3], a->bias(3), f, state, st);
+                fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wp4, a->bias(3), f, state, st);
         return;
     }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
@@ -873,6 +867,10 @@ ae_net* new_net(int in, int hid, int lat)
         a->wb[l] = dalloc<uint16_t>((size_t)a->fi[l] * a->fo[l]);
         a->wt[l] = dalloc<uint16_t>((size_t)a->fi[l] * a->fo[l]);
     }
+    if (fused_supported(hid, lat)) {
+        a->wp1 = dalloc<uint16_t>((size_t)in * hid);
+        a->wp4 = dalloc<uint16_t>((size_t)in * hid);
+    }
     a->beta_d = dalloc<float>(4);
     a->loss_d = dalloc<double>(1);
     upload_beta(a.get());
@@ -890,6 +888,8 @@ void free_net(ae_net* a)
         if (a->wb[l]) (void)hipFree(a->wb[l]);
         if (a->wt[l]) (void)hipFree(a->wt[l]);
     }
+    if (a->wp1) (void)hipFree(a->wp1);
+    if (a->wp4) (void)hipFree(a->wp4);
     if (a->ws) (void)hipFree(a->ws);
     delete a;
 }

@@ -33,13 +33,18 @@ void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent,
 // Fused inference kernels (hidden width 512, latent 32): meta must already hold
 // the per-patch (min, range) of the state for encode.
 bool fused_supported(int hid, int lat);
+// Repack a bf16 matrix [rows][K] (rows % 16 == 0, K % 32 == 0) into MFMA fragment
+// order [K/32][rows/16][64 lanes][8]: lane l of block (ks, r) holds row 16 r + l % 16,
+// k = 32 ks + 8 (l / 16) .. +7, so one k-step of a row range is contiguous.
+void fused_pack(const uint16_t* w, int rows, int K, uint16_t* out, hipStream_t st);
 // meta: input (min, range), or output when the partial (min, max) table mm
 // [P][H][4][2] of the forward step is given (then r = max(max - min, beta_f)).
+// w1p: W1^T packed by fused_pack; w4p: W4^T packed by fused_pack.
 void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
-                  const uint16_t* w1t, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
+                  const uint16_t* w1p, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
                   hipStream_t st);
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
-                  const uint16_t* w4t, const float* b4, int f, float* state, hipStream_t st);
+                  const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st);
 
 // Select the K largest-e-range patches of one compressed state (meta [P][4][2])
 // into idx [K] (increasing patch order) and copy their e values to exc [K][512].

@@ -1,0 +1,49 @@
+// Scalar numerics shared by the autoencoder kernels (training and inference):
+// bfloat16 rounding, the GELU activation and its derivative.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wv {
+
+typedef __bf16 ae_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float ae_f32x2 __attribute__((ext_vector_type(2)));
+
+// float -> bfloat16 bits, round to nearest even (v_cvt_pk_bf16_f32; finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    const ae_bf16x2 b = __builtin_convertvector((ae_f32x2{x, 0.0f}), ae_bf16x2);
+    return (uint16_t)(__builtin_bit_cast(uint32_t, b) & 0xFFFFu);
+}
+// two floats -> packed bfloat16 pair (x in the low half)
+__device__ __forceinline__ uint32_t f2bf2(float x, float y)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((ae_f32x2{x, y}), ae_bf16x2));
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// erf(x) by the rational-exponential approximation of Abramowitz & Stegun 7.1.26
+// (Hastings): |error| <= 1.5e-7, far below the bfloat16 rounding of the hidden
+// layer that follows every use. Branch-free: one reciprocal and one exp2.
+__device__ __forceinline__ float erf_as(float x)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float y = fmaf(1.061405429f, t, -1.453152027f);
+    y = fmaf(y, t, 1.421413741f);
+    y = fmaf(y, t, -0.284496736f);
+    y = fmaf(y, t, 0.254829592f);
+    y *= t;
+    const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+    return copysignf(fmaf(-y, e, 1.0f), x);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime(float x)
+{
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+           x * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f) * 0.39894228040143268f;
+}
+
+}  // namespace wv
