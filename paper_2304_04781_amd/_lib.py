@@ -74,6 +74,8 @@ EXPORTS = {
     "wv_revolve_schedule": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
     "wv_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "wv_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "wv_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "wv_last_error": (C.c_char_p, []),
     "wv_version": (C.c_char_p, []),
 }
@@ -193,6 +195,22 @@ def wv_stats(ctx):
     fs, ge, dg = C.c_int64(), C.c_double(), C.c_int()
     _check(load().wv_stats(ctx, C.byref(fs), C.byref(ge), C.byref(dg)))
     return fs.value, ge.value, bool(dg.value)
+
+
+# kernel classes of wv_kernel_time
+TIMED_KERNELS = ("forward_stencil", "adjoint_stencil", "incremental_stencil", "encode", "decode_e",
+                 "exceptions_select", "exceptions_restore", "exceptions_gather")
+
+
+def wv_set_timing(ctx, every: int) -> None:
+    _check(load().wv_set_timing(ctx, int(every)))
+
+
+def wv_kernel_time(ctx, cls: int):
+    """(mean duration in microseconds, number of timed launches) of one kernel class."""
+    m, n = C.c_double(), C.c_int64()
+    _check(load().wv_kernel_time(ctx, int(cls), C.byref(m), C.byref(n)))
+    return m.value, n.value
 
 
 def wv_revolve_schedule(nsteps: int, nslots: int):

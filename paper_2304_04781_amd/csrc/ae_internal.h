@@ -46,8 +46,18 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st);
 
-// Select the K largest-e-range patches of one compressed state (meta [P][4][2])
-// into idx [K] (increasing patch order) and copy their e values to exc [K][512].
+// Exception patches: the K largest-e-range patches of one compressed state are
+// kept exactly. Ranges are compared by key = bits(r_e) >> EXC_BIN_SHIFT (bins 2^-5
+// wide in relative terms); within the bin of the K-th largest, lower patch indices
+// win.
+constexpr int EXC_BIN_SHIFT = 18;
+constexpr int EXC_NBIN = 1 << (32 - EXC_BIN_SHIFT);
+// selection from meta [P][4][2] into idx [K] (increasing patch order); a single
+// work-group kernel, cheap to overlap with other work
+void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st);
+// copy the e values of the selected patches to exc [K][512]
+void exceptions_gather(const PatchGrid& pg, const float* state, int K, const int* idx, float* exc, hipStream_t st);
+// both
 void exceptions_store(const PatchGrid& pg, const float* state, const float* meta, int K, int* idx, float* exc,
                       hipStream_t st);
 // Write the stored e values back into an e field [N].

@@ -58,11 +58,97 @@ void dev_free(T*& p)
     p = nullptr;
 }
 
+// Sampled per-class kernel timing with HIP events recorded on the stream the
+// timed work runs on (every `every`-th launch of each class).
+struct KernelTimer {
+    static constexpr int NCLS = 8;
+    int every = 0;
+    long long seen[NCLS] = {};
+    double sum_ms[NCLS] = {};
+    long long cnt[NCLS] = {};
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        WV_HIP(hipEventCreate(&e));
+        return e;
+    }
+    // fold finished records into the totals (waits for them)
+    void collect()
+    {
+        for (const Rec& r : recs) {
+            WV_HIP(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            WV_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            sum_ms[r.cls] += ms;
+            cnt[r.cls] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    // returns the record index to close with end(), or -1 when this launch is not sampled
+    int begin(int cls, hipStream_t st)
+    {
+        if (every <= 0 || (seen[cls]++ % every) != 0) return -1;
+        if (recs.size() >= 4096) collect();
+        Rec r{cls, get(), get()};
+        WV_HIP(hipEventRecord(r.a, st));
+        recs.push_back(r);
+        return (int)recs.size() - 1;
+    }
+    void end(int idx, hipStream_t st)
+    {
+        if (idx >= 0) WV_HIP(hipEventRecord(recs[idx].b, st));
+    }
+    void reset(int ev)
+    {
+        collect();
+        every = ev;
+        for (int i = 0; i < NCLS; ++i) {
+            seen[i] = cnt[i] = 0;
+            sum_ms[i] = 0.0;
+        }
+    }
+    void destroy()
+    {
+        for (const Rec& r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        recs.clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+enum {
+    TM_FWD = 0,
+    TM_ADJ = 1,
+    TM_INC = 2,
+    TM_ENCODE = 3,
+    TM_DECODE = 4,
+    TM_EXC_SELECT = 5,
+    TM_EXC_RESTORE = 6,
+    TM_EXC_GATHER = 7
+};
+
 }  // namespace wv
 
 using namespace wv;
 
 struct wv_ctx {
+    KernelTimer tm;
     wv_grid g{};
     bool has_y = true;
     long long N = 0;
@@ -113,8 +199,9 @@ struct wv_ctx {
     int H = 1;                   // y sub-tiles per patch
     hipStream_t side = nullptr;  // exception selection/gather, overlapped with the time loop
     hipEvent_t ev_enc = nullptr;
-    hipEvent_t ev_gather[2] = {nullptr, nullptr};
-    bool gather_pending[2] = {false, false};
+    hipEvent_t ev_sel = nullptr;
+    int pend_n = 0;                  // state whose exception copy is pending (0: none)
+    const float* pend_state = nullptr;
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -219,7 +306,9 @@ void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, floa
     a.traces = traces;
     a.mm_out = mm;
     if (!traces) a.nrec = 0;
+    const int t = c->tm.begin(TM_FWD, c->st);
     launch_step(MODE_FWD, c->has_y, a, c->S, c->st);
+    c->tm.end(t, c->st);
 }
 
 // adjoint launch k: (mu^{k+2}, eta^{k+1}) -> (mu^{k+1}, eta^k), consuming e^k
@@ -234,7 +323,9 @@ void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid,
     a.ek = ek;
     a.ekstride = ekstride;
     a.acc = c->acc;
+    const int t = c->tm.begin(TM_ADJ, c->st);
     launch_step(MODE_ADJ, c->has_y, a, c->S, c->st);
+    c->tm.end(t, c->st);
 }
 
 void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, long long enstride,
@@ -249,7 +340,9 @@ void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, lo
     a.dm = c->dm;
     a.en = en;
     a.enstride = enstride;
+    const int t = c->tm.begin(TM_INC, c->st);
     launch_step(MODE_INC, c->has_y, a, c->S, c->st);
+    c->tm.end(t, c->st);
 }
 
 void ensure_inc(wv_ctx* c)
@@ -271,6 +364,7 @@ void free_store(wv_ctx* c)
     dev_free(c->exc_idx);
     dev_free(c->exc);
     dev_free(c->mmpart);
+    c->pend_n = 0;
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -313,6 +407,7 @@ void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
 bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
 int ae_fmt(int mode) { return mode == WV_STORE_AE_FP8 ? AE_LATENT_FP8 : AE_LATENT_BF16; }
 
+
 uint8_t* lat_slot(wv_ctx* c, int idx, int s)
 {
     return c->lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
@@ -325,7 +420,29 @@ float* qs_slot(wv_ctx* c, int idx, int s)
 
 // store x_n (n = 1..T-1) of every source; wi = index of the work buffer holding
 // it (-1: not a work buffer), whose reuse must wait for the exception gather
-void store_state(wv_ctx* c, int n, const float* state, int wi = -1, bool have_mm = false)
+// copy the e values of the exception patches selected for the state the last
+// store_state left pending (main stream, after its selection)
+void flush_gather(wv_ctx* c)
+{
+    if (c->pend_n <= 0) return;
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    WV_HIP(hipStreamWaitEvent(c->st, c->ev_sel, 0));
+    const int tg = c->tm.begin(TM_EXC_GATHER, c->st);
+    for (int s = 0; s < c->S; ++s) {
+        const long long q = (long long)(c->pend_n - 1) * c->S + s;
+        exceptions_gather(pg, c->pend_state + s * 4 * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512,
+                          c->st);
+    }
+    c->tm.end(tg, c->st);
+    c->pend_n = 0;
+    c->pend_state = nullptr;
+}
+
+// store x_n (n = 1..T-1) of every source. With have_mm (the forward sweep's fused
+// min/max) the exception selection runs on the side stream, overlapped with the
+// next step, and the copy is left pending for flush_gather, which must run before
+// the buffer holding x_n is overwritten and before the next store_state.
+void store_state(wv_ctx* c, int n, const float* state, bool have_mm = false)
 {
     if (n < 1 || n > c->T - 1) return;
     if (c->mode == WV_STORE_FULL) {
@@ -334,6 +451,7 @@ void store_state(wv_ctx* c, int n, const float* state, int wi = -1, bool have_mm
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+        const int te = c->tm.begin(TM_ENCODE, c->st);
         for (int s = 0; s < c->S; ++s) {
             if (have_mm)
                 ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, c->mmpart + (long long)s * c->P * c->H * 8, c->H,
@@ -343,21 +461,28 @@ void store_state(wv_ctx* c, int n, const float* state, int wi = -1, bool have_mm
                 ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
                                 meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
         }
+        c->tm.end(te, c->st);
         if (c->K > 0) {
-            // select and copy the exact patches on the side stream, overlapped with the next step
-            hipStream_t xs = wi >= 0 ? c->side : c->st;
-            if (wi >= 0) {
+            if (have_mm) {
+                // selection on the side stream, copy left pending
                 WV_HIP(hipEventRecord(c->ev_enc, c->st));
                 WV_HIP(hipStreamWaitEvent(c->side, c->ev_enc, 0));
-            }
-            for (int s = 0; s < c->S; ++s) {
-                const long long q = (long long)(n - 1) * c->S + s;
-                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
-                                 c->exc + q * c->K * 512, xs);
-            }
-            if (wi >= 0) {
-                WV_HIP(hipEventRecord(c->ev_gather[wi], c->side));
-                c->gather_pending[wi] = true;
+                const int tx = c->tm.begin(TM_EXC_SELECT, c->side);
+                for (int s = 0; s < c->S; ++s)
+                    exceptions_select(pg, meta_slot(c, n - 1, s), c->K,
+                                      c->exc_idx + ((long long)(n - 1) * c->S + s) * c->K, c->side);
+                c->tm.end(tx, c->side);
+                WV_HIP(hipEventRecord(c->ev_sel, c->side));
+                c->pend_n = n;
+                c->pend_state = state;
+            } else {
+                const int tx = c->tm.begin(TM_EXC_SELECT, c->st);
+                for (int s = 0; s < c->S; ++s) {
+                    const long long q = (long long)(n - 1) * c->S + s;
+                    exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
+                                     c->exc + q * c->K * 512, c->st);
+                }
+                c->tm.end(tx, c->st);
             }
         }
     }
@@ -382,11 +507,15 @@ const float* load_e(wv_ctx* c, int n, long long* stride)
     ensure_adj(c);  // owns the decode target ebuf
     const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
     for (int s = 0; s < c->S; ++s) {
+        const int td = c->tm.begin(TM_DECODE, c->st);
         ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
                         ae_fmt(c->mode), 1u, c->ebuf + s * c->N, c->st);
+        c->tm.end(td, c->st);
         if (c->K > 0) {
             const long long q = (long long)(n - 1) * c->S + s;
+            const int tr = c->tm.begin(TM_EXC_RESTORE, c->st);
             exceptions_restore(pg, c->ebuf + s * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512, c->st);
+            c->tm.end(tr, c->st);
         }
     }
     return c->ebuf;
@@ -400,6 +529,7 @@ float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->w
 float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, float* capture, int every,
                      float** last)
 {
+    c->pend_n = 0;  // nothing pending from an interrupted sweep
     launch_fill(c->work[0], c->state_floats(), 0.f, c->st);
     float* cur = c->work[0];
     float* prev = cur;
@@ -407,25 +537,17 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
     const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
     for (int n = 0; n < c->T; ++n) {
         float* out = (snap && (*snap)[n + 1] > 0) ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
-        const int wi = out == c->work[0] ? 0 : (out == c->work[1] ? 1 : -1);
-        if (wi >= 0 && c->gather_pending[wi]) {
-            WV_HIP(hipStreamWaitEvent(c->st, c->ev_gather[wi], 0));
-            c->gather_pending[wi] = false;
-        }
         const bool store = n + 1 <= c->T - 1;
         fwd_step(c, cur, out, n, traces, (ae && store) ? c->mmpart : nullptr);
-        if (store) store_state(c, n + 1, out, wi, ae);
+        flush_gather(c);  // exceptions of x_n, still in cur
+        if (store) store_state(c, n + 1, out, ae);
         if (ncap > 0 && (n + 1) % every == 0 && (n + 1) / every <= ncap)
             WV_HIP(hipMemcpyAsync(capture + (long long)((n + 1) / every - 1) * c->state_floats(), out,
                                   sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice, c->st));
         prev = cur;
         cur = out;
     }
-    for (int w = 0; w < 2; ++w)
-        if (c->gather_pending[w]) {
-            WV_HIP(hipStreamWaitEvent(c->st, c->ev_gather[w], 0));
-            c->gather_pending[w] = false;
-        }
+    flush_gather(c);
     c->last_fwd_steps = c->T;
     if (last) *last = cur;
     return prev;
@@ -594,8 +716,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->dtr = dev_alloc<float>(ntr);
         WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         WV_HIP(hipEventCreateWithFlags(&c->ev_enc, hipEventDisableTiming));
-        WV_HIP(hipEventCreateWithFlags(&c->ev_gather[0], hipEventDisableTiming));
-        WV_HIP(hipEventCreateWithFlags(&c->ev_gather[1], hipEventDisableTiming));
+        WV_HIP(hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming));
         c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
         c->dscal = dev_alloc<double>(8);
         c->dflag = dev_alloc<int>(1);
@@ -609,11 +730,11 @@ int wv_destroy(wv_ctx* c)
     if (!c) return WV_OK;
     (void)hipStreamSynchronize(c->st);
     if (c->side) (void)hipStreamSynchronize(c->side);
+    c->tm.destroy();
     free_store(c);
     free_tiling(c->tl);
     if (c->ev_enc) (void)hipEventDestroy(c->ev_enc);
-    for (int w = 0; w < 2; ++w)
-        if (c->ev_gather[w]) (void)hipEventDestroy(c->ev_gather[w]);
+    if (c->ev_sel) (void)hipEventDestroy(c->ev_sel);
     if (c->side) (void)hipStreamDestroy(c->side);
     dev_free(c->tab);
     dev_free(c->src_kji);
@@ -673,6 +794,7 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             if (mode == WV_STORE_AE_FP8) c->qs = dev_alloc<float>(slots * c->P);
             if (K > 0) {
                 c->exc_idx = dev_alloc<int>(slots * K);
+                WV_HIP(hipMemset(c->exc_idx, 0, sizeof(int) * slots * K));
                 c->exc = dev_alloc<float>(slots * K * 512);
             }
             c->K = K;
@@ -956,6 +1078,29 @@ int wv_stats(const wv_ctx* c, int64_t* h_forward_steps, double* h_guard_err, int
     if (h_guard_err) *h_guard_err = c->guard_err;
     if (h_degraded) *h_degraded = c->degraded ? 1 : 0;
     return WV_OK;
+}
+
+int wv_set_timing(wv_ctx* c, int32_t every)
+{
+    return guarded([&] {
+        WV_REQUIRE(c, WV_EINVAL, "null context");
+        WV_REQUIRE(every >= 0, WV_EINVAL, "every must be >= 0");
+        c->tm.reset(every);
+        return WV_OK;
+    });
+}
+
+int wv_kernel_time(wv_ctx* c, int32_t cls, double* h_mean_us, int64_t* h_count)
+{
+    return guarded([&] {
+        WV_REQUIRE(c, WV_EINVAL, "null context");
+        WV_REQUIRE(cls >= 0 && cls < KernelTimer::NCLS, WV_EINVAL, "unknown kernel class");
+        c->tm.collect();
+        const long long n = c->tm.cnt[cls];
+        if (h_mean_us) *h_mean_us = n > 0 ? 1e3 * c->tm.sum_ms[cls] / (double)n : 0.0;
+        if (h_count) *h_count = n;
+        return WV_OK;
+    });
 }
 
 const char* wv_last_error(void) { return g_error.c_str(); }

@@ -34,13 +34,28 @@ namespace {
 
 constexpr int NF = 4;  // fields per state: e, v_z, v_y, v_x
 
-template <int BX, int BY, int MODE, bool HAS_Y>
-__global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
+// Minimum waves per SIMD asked of the register allocator (occupancy of these
+// latency-bound kernels), per variant.
+#ifndef WV_WAVES_FWD_MM
+#define WV_WAVES_FWD_MM 7
+#endif
+#ifndef WV_WAVES_ADJ
+#define WV_WAVES_ADJ 7
+#endif
+#ifndef WV_WAVES_OTHER
+#define WV_WAVES_OTHER 7
+#endif
+
+// MM: also write the per-patch (min, max) partials of the new state (forward only)
+template <int BX, int BY, int MODE, bool HAS_Y, bool MM>
+__global__ void __launch_bounds__(BX* BY)
+    __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_ADJ ? WV_WAVES_ADJ : WV_WAVES_OTHER)))
+    wave_step_kernel(const StepArgs a)
 {
     __shared__ float sP[BY + 2][BX + 2];
     __shared__ float sWy[HAS_Y ? BY + 1 : 1][BX];
     __shared__ float sWx[BY][BX + 1];
-    __shared__ float sMM[BY][BX / 8][8];  // per-row partial (min, max) of 8 patches
+    __shared__ float sMM[MM ? BY : 1][BX / 8][8];  // per-row partial (min, max) of 8 patches
 
     // ---- block -> (x tile, y tile, z chunk); spread so one XCD gets a contiguous range
     const int nblk = a.tiles_x * a.tiles_y * a.chunks_z;
@@ -231,7 +246,7 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
     }
 
     // running (min, max) of the 4 new fields over the current patch layer
-    const bool want_mm = MODE == MODE_FWD && HAS_Y && a.mm_out != nullptr;
+    constexpr bool want_mm = MM && MODE == MODE_FWD && HAS_Y;
     float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY;
     float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY, mx3 = -INFINITY;
 
@@ -322,7 +337,7 @@ __global__ void __launch_bounds__(BX* BY) wave_step_kernel(const StepArgs a)
                 cmp[offk] = s_cmp;
             }
         }
-        if (want_mm) {
+        if constexpr (want_mm) {
             if (inside) {
                 mn0 = fminf(mn0, A_new); mx0 = fmaxf(mx0, A_new);
                 mn1 = fminf(mn1, Vz_cur); mx1 = fmaxf(mx1, Vz_cur);
@@ -393,9 +408,14 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
     dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
     dim3 block(BX * BY);
     switch (mode) {
-    case MODE_FWD: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y>), grid, block, 0, st, a); break;
-    case MODE_ADJ: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y>), grid, block, 0, st, a); break;
+    case MODE_FWD:
+        if (HAS_Y && a.mm_out)
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, HAS_Y>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, false>), grid, block, 0, st, a);
+        break;
+    case MODE_ADJ: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false>), grid, block, 0, st, a); break;
     }
 }
 

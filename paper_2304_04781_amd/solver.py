@@ -66,6 +66,14 @@ class WaveSolver:
     def stats(self):
         return L.wv_stats(self.ctx)
 
+    def set_timing(self, every: int) -> None:
+        """Time every `every`-th launch of each kernel class with HIP events (0: off)."""
+        L.wv_set_timing(self.ctx, every)
+
+    def kernel_times(self) -> dict:
+        """{class name: (mean microseconds, timed launches)} since set_timing."""
+        return {name: L.wv_kernel_time(self.ctx, i) for i, name in enumerate(L.TIMED_KERNELS)}
+
     # ----- helpers ------------------------------------------------------------------------------
     def _f32(self, x) -> torch.Tensor:
         if isinstance(x, torch.Tensor):

@@ -216,3 +216,26 @@ def test_error_codes():
     with pytest.raises(L.WvError) as e:
         s3.set_storage(L.STORE_CHECKPOINT, n_checkpoints=8, mem_budget_bytes=1000)
     assert e.value.code == -2
+
+
+# ----- kernel timing ------------------------------------------------------------------------------
+@pytest.mark.gpu
+def test_kernel_timing_counts_and_durations():
+    """Sampled event timing: every 2nd launch of each stencil class is timed on the
+    context's stream; the counts follow from the step counts of the solve."""
+    p = small3d(nt=21)
+    s = solver_for(p, L.STORE_CHECKPOINT, nslots=4)
+    d = torch.zeros((len(p.src), p.nt, len(p.rec)), dtype=torch.float32, device="cuda")
+    s.set_timing(2)
+    s.gradient(p.c_start, p.wavelet, d, 1.0)
+    kt = s.kernel_times()
+    fsteps, _, _ = s.stats()
+    assert kt["forward_stencil"][1] == (fsteps + 1) // 2
+    assert kt["adjoint_stencil"][1] == (p.nt - 1 + 1) // 2
+    assert kt["forward_stencil"][0] > 0 and kt["adjoint_stencil"][0] > 0
+    assert kt["encode"][1] == 0 and kt["decode_e"][1] == 0
+    s.set_timing(0)
+    assert s.kernel_times()["forward_stencil"][1] == 0
+    with pytest.raises(L.WvError) as e:
+        L.wv_kernel_time(s.ctx, 8)
+    assert e.value.code == -1
