@@ -96,8 +96,6 @@ def test_encode_decode_against_oracle(fmt):
     meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
     qs = torch.empty((P,), dtype=torch.float32, device="cuda") if fmt == L.LATENT_FP8 else None
     L.ae_encode(net.handle, grid_of(SHAPE), ts, fmt, lat, meta, qs)
-    out = torch.zeros((4,) + SHAPE, dtype=torch.float32, device="cuda")
-    L.ae_decode(net.handle, grid_of(SHAPE), lat, meta, qs, fmt, 0xF, out)
     torch.cuda.synchronize()
     ae = oae.AE(net.prm32)
     X = oae.patchify(st.astype(np.float64))
@@ -105,24 +103,41 @@ def test_encode_decode_against_oracle(fmt):
     z_o = ae.encode(Y, emulate=True)
     if fmt == L.LATENT_BF16:
         z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16))
-        z_ref = rd.bf16(z_o)
-        assert rel(z_gpu, z_ref) < 5e-3
-        # decoder on identical latents
-        dec_ref = ae.decode(z_gpu, emulate=True)
+        assert rel(z_gpu, rd.bf16(z_o)) < 5e-3
     else:
         codes = lat.cpu().numpy()
         s = qs.cpu().numpy().astype(np.float64)
-        z_gpu = rd.e4m3_decode(codes) * s[:, None]
         q_o, s_o = oae.fp8_quantize(z_o)
         assert np.allclose(s, s_o, rtol=1e-5)
         assert np.mean(codes == q_o) > 0.97
-        assert rel(z_gpu, rd.e4m3_decode(q_o) * s_o[:, None]) < 3e-2
-        dec_ref = ae.decode(rd.bf16(z_gpu), emulate=True)
-    x_ref = oae.unpatchify(oae.denormalize(dec_ref, lo, r), *SHAPE)
+        assert rel(rd.e4m3_decode(codes) * s[:, None], rd.e4m3_decode(q_o) * s_o[:, None]) < 3e-2
+    # decoder on seeded latents and metadata (both sides get the same inputs)
+    rng = np.random.default_rng(17)
+    ms = np.zeros((P, 4, 2), np.float32)
+    ms[:, :, 0] = rng.uniform(-1.0, 1.0, (P, 4))
+    ms[:, :, 1] = rng.uniform(0.5, 2.0, (P, 4))
+    if fmt == L.LATENT_BF16:
+        zs = rd.bf16(0.5 * rng.standard_normal((P, 32)))
+        lat_in = torch.tensor(rd.bf16_bits(zs).view(np.int16), device="cuda")
+        qs_in = None
+        z_dec = zs
+    else:
+        codes = rng.integers(0, 256, (P, 32)).astype(np.uint8)
+        codes[(codes & 0x7F) == 0x7F] = 0x00          # no NaN codes
+        sc = rng.uniform(0.001, 0.01, P).astype(np.float32)
+        lat_in = torch.tensor(codes, device="cuda")
+        qs_in = torch.tensor(sc, device="cuda")
+        z_dec = rd.bf16(rd.e4m3_decode(codes) * sc.astype(np.float64)[:, None])
+    out = torch.zeros((4,) + SHAPE, dtype=torch.float32, device="cuda")
+    L.ae_decode(net.handle, grid_of(SHAPE), lat_in, torch.tensor(ms, device="cuda"), qs_in, fmt, 0xF, out)
+    torch.cuda.synchronize()
+    dec_ref = ae.decode(z_dec, emulate=True)
+    x_ref = oae.unpatchify(oae.denormalize(dec_ref, ms[:, :, 0].astype(np.float64), ms[:, :, 1].astype(np.float64)),
+                           *SHAPE)
     assert rel(out.cpu().numpy(), x_ref) < 5e-3
     # e-only decode writes the e field and leaves the others untouched
     out2 = torch.full((4,) + SHAPE, 7.0, dtype=torch.float32, device="cuda")
-    L.ae_decode(net.handle, grid_of(SHAPE), lat, meta, qs, fmt, 0x1, out2)
+    L.ae_decode(net.handle, grid_of(SHAPE), lat_in, torch.tensor(ms, device="cuda"), qs_in, fmt, 0x1, out2)
     o2 = out2.cpu().numpy()
     assert np.array_equal(o2[0], out.cpu().numpy()[0]) and np.all(o2[1:] == 7.0)
 

@@ -1,0 +1,219 @@
+"""Parity and properties at the full sizes of the workloads, in the launch
+configuration the benchmark times (same grid, same kernels, same tiling).
+
+* 256^3 (the gradient workload): a full-grid gradient over a short horizon
+  against the FP64 oracle; checkpointed and all-patches-exact compressed
+  stores bit for bit against full storage; the fused encoder and decoder on
+  sampled patches of a full-grid state against the oracle.
+* 384^3 x 3000 (the Gauss-Newton workload): symmetry of the checkpointed GN
+  Hessian and the compressed Hv against the checkpointed one.
+* 512 x 512 x 256 with 8 sources (the multi-source FP8 workload) on the full
+  grid with a shortened horizon: compressed FP8 gradient against the
+  checkpointed one.
+
+The oracle's cost sets the short horizons: one FP64 numpy step of the 256^3
+grid takes about a quarter of a second on one core."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ae as oae
+from oracle import rounding as rd
+from oracle import wave as ow
+from paper_2304_04781_amd import _lib as L
+from paper_2304_04781_amd.compressor import Autoencoder, train_from_forward
+from paper_2304_04781_amd.solver import WaveSolver
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cosine(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / np.linalg.norm(a) / np.linalg.norm(b))
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def rounded(p):
+    p.c_true = f32(p.c_true)
+    p.c_start = f32(p.c_start)
+    p.wavelet = f32(p.wavelet)
+    return p
+
+
+# ----- 256^3 ----------------------------------------------------------------------------------------
+def test_gradient_256_cube_matches_oracle():
+    """Forward, misfit, adjoint and gradient over the full 256^3 grid (40 steps)
+    against the FP64 oracle; revolve checkpointing and an all-exact compressed
+    store reproduce full storage bit for bit at this size."""
+    p = rounded(W.problem_256(40))
+    print("case", p.name, flush=True)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    d = f32(d)
+    J_o, g_o, _, e_hist = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
+    del e_hist
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    J, g = full.gradient(p.c_start, p.wavelet, d, sigma)
+    g = g.cpu().numpy()
+    print("J", J, J_o, "grad rel err", rel(g, g_o), flush=True)
+    assert abs(J - J_o) / J_o < 1e-5
+    assert rel(g, g_o) < 1e-4
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=8)
+    _, gc = ck.gradient(p.c_start, p.wavelet, d, sigma)
+    assert np.array_equal(gc.cpu().numpy(), g)
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    ae = WaveSolver.for_problem(p)
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    L.wv_set_ae_exceptions(ae.ctx, P)
+    ae.set_storage(L.STORE_AE_BF16, ae=net)
+    Ja, ga = ae.gradient(p.c_start, p.wavelet, d, sigma)
+    assert Ja == J
+    assert np.array_equal(ga.cpu().numpy(), g)
+
+
+def test_encode_decode_256_cube_sampled_patches():
+    """The fused encoder over a full 256^3 state and the decoder over full-grid
+    latents, checked on sampled patches against the oracle's emulated network.
+    Decoder inputs are seeded synthetic latents and metadata (not the encoder's
+    output), so each direction is checked on its own."""
+    shape = (256, 256, 256)
+    P = 32 ** 3
+    prm = W.ae_init(seed=4)
+    prm32 = {k: f32(v) for k, v in prm.items()}
+    flat = np.concatenate([prm32[k].ravel() for k in oae.NAMES])
+    net = L.ae_create(2048, 512, 32, flat, np.full(4, 1e-7))
+    g = L.make_grid(*shape, 20.0, 1e-3, 10, 0, 1.0, 1, 0)
+    st = W.smooth_random_state(4, *shape, seed=7).astype(np.float32)
+    ts = torch.tensor(st, device="cuda")
+    lat = torch.empty((P, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    L.ae_encode(net, g, ts, L.LATENT_BF16, lat, meta)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(P, 96, replace=False))
+    pz, py, px = sample // (32 * 32), (sample // 32) % 32, sample % 32
+    X = np.stack([st[:, 8 * z:8 * z + 8, 8 * y:8 * y + 8, 8 * x:8 * x + 8].reshape(4, 512)
+                  for z, y, x in zip(pz, py, px)]).reshape(-1, 2048).astype(np.float64)
+    Y, lo, r = oae.normalize(X, [1e-7] * 4, emulate=True)
+    meta_g = meta.cpu().numpy()[sample]
+    assert np.array_equal(meta_g[:, :, 0], np.asarray(lo, np.float32))
+    assert np.array_equal(meta_g[:, :, 1], np.asarray(r, np.float32))
+    ae = oae.AE(prm32)
+    z_ref = rd.bf16(ae.encode(Y, emulate=True))
+    z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16)[sample])
+    print("encode rel err on sampled patches", rel(z_gpu, z_ref), flush=True)
+    assert rel(z_gpu, z_ref) < 5e-3
+    # decoder: seeded latents (bf16) and metadata for every patch of the grid
+    zs = rd.bf16(0.5 * rng.standard_normal((P, 32)))
+    ms = np.zeros((P, 4, 2), np.float32)
+    ms[:, :, 0] = rng.uniform(-1.0, 1.0, (P, 4))
+    ms[:, :, 1] = rng.uniform(0.5, 2.0, (P, 4))
+    lat_in = torch.tensor(rd.bf16_bits(zs).view(np.int16), device="cuda")
+    meta_in = torch.tensor(ms, device="cuda")
+    out = torch.zeros((4,) + shape, dtype=torch.float32, device="cuda")
+    L.ae_decode(net, g, lat_in, meta_in, None, L.LATENT_BF16, 0x1, out)
+    torch.cuda.synchronize()
+    e_gpu = out[0].cpu().numpy()
+    got = np.stack([e_gpu[8 * z:8 * z + 8, 8 * y:8 * y + 8, 8 * x:8 * x + 8].ravel()
+                    for z, y, x in zip(pz, py, px)])
+    yhat = ae.decode(zs[sample], emulate=True)[:, :512]
+    ref = ms[sample, 0, 0][:, None].astype(np.float64) + ms[sample, 0, 1][:, None].astype(np.float64) * yhat
+    print("decode rel err on sampled patches", rel(got, ref), flush=True)
+    assert rel(got, ref) < 5e-3
+    L.ae_destroy(net)
+
+
+# ----- 384^3 x 3000 ---------------------------------------------------------------------------------
+def test_gn_hessvec_384_cube():
+    """The Gauss-Newton workload at full size: the checkpointed GN Hessian is
+    symmetric to FP32 round-off, and the compressed Hv (trained network, 1 %
+    exact patches) agrees with the checkpointed one."""
+    p = rounded(W.problem_384(3000))
+    print("case", p.name, flush=True)
+    dev = torch.device("cuda", 0)
+    c = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    u = torch.tensor(p.c_start * W.direction_grf(p.c_start.shape, 12.0, 2), dtype=torch.float32, device=dev)
+    w = torch.tensor(p.c_start * W.direction_grf(p.c_start.shape, 12.0, 9), dtype=torch.float32, device=dev)
+    d = torch.zeros((len(p.src), p.nt, len(p.rec)), dtype=torch.float32, device=dev)
+    sigma = 1.0  # GN Hv depends on the data only through the weight dt / sigma^2
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=64)
+    ck.gradient(c, wav, d, sigma)             # Hv linearises about the last gradient's solve
+    Hu = ck.hessvec(c, u)
+    Hw = ck.hessvec(c, w)
+    a = float(torch.sum(w.double() * Hu.double()))
+    b = float(torch.sum(u.double() * Hw.double()))
+    print("symmetry", a, b, abs(a - b) / abs(a), flush=True)
+    assert abs(a - b) / abs(a) < 1e-4
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    nsamp = ((p.nt - 1) // 60) * P
+    info = train_from_forward(ck, net, c, wav, every=60, epochs=6, batch=4096,
+                              perms=W.shuffles(nsamp, 6, seed=5))
+    print("training", info, flush=True)
+    ae = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(ae.ctx, int(round(0.01 * P)))
+    ae.set_storage(L.STORE_AE_BF16, ae=net)
+    ae.gradient(c, wav, d, sigma)
+    assert ae.last_status == 0  # compressed, no fallback
+    Hu_ae = ae.hessvec(c, u)
+    assert ae.last_status == 0
+    err = rel(Hu_ae.cpu().numpy(), Hu.cpu().numpy())
+    cs = cosine(Hu_ae.cpu().numpy(), Hu.cpu().numpy())
+    print("compressed Hv rel err", err, "cos", cs, flush=True)
+    assert err < 0.1 and cs > 0.995
+
+
+# ----- 512 x 512 x 256, 8 sources ---------------------------------------------------------------
+def test_multisource_fp8_gradient_full_grid():
+    """All 8 sources of the multi-source workload in one launch per step on its
+    full grid (horizon shortened to 400 steps), FP8 latents with per-patch
+    scales: the summed compressed gradient against the checkpointed one."""
+    T = 400
+    p = rounded(W.problem_multisource(T))
+    print("case", p.name, flush=True)
+    dev = torch.device("cuda", 0)
+    c = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=6)
+    clean, _, _ = ck.forward(torch.tensor(p.c_true, dtype=torch.float32, device=dev), wav)
+    clean = clean.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * float(np.abs(clean).max())
+    d = torch.tensor((clean + sigma * p.noise).astype(np.float32), device=dev)
+    J0, g0 = ck.gradient(c, wav, d, sigma)
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    nsamp = ((T - 1) // 50) * P * len(p.src)
+    info = train_from_forward(ck, net, c, wav, every=50, epochs=4, batch=4096,
+                              perms=W.shuffles(nsamp, 4, seed=5))
+    print("training", info, flush=True)
+    errs = {}
+    for K in (0, int(round(0.01 * P))):
+        ae = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(ae.ctx, K)
+        ae.set_storage(L.STORE_AE_FP8, ae=net)
+        J, g = ae.gradient(c, wav, d, sigma)
+        assert ae.last_status == 0  # compressed, no fallback
+        err = rel(g.cpu().numpy(), g0.cpu().numpy())
+        cs = cosine(g.cpu().numpy(), g0.cpu().numpy())
+        print("J", J, J0, "K", K, "FP8 compressed gradient rel err", err, "cos", cs, flush=True)
+        assert J == J0
+        errs[K] = (err, cs)
+        ae.close()
+    err, cs = errs[int(round(0.01 * P))]
+    assert err < 0.1 and cs > 0.995
