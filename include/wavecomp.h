@@ -141,8 +141,10 @@ int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
                    int64_t mem_budget_bytes, double guard_tol, int fallback_policy);
 
 /* Error bounding for the AE modes: after compressing a state, the k_per_step
- * patches with the largest e-field range r (ties: lower patch index first) also
- * keep their e values exactly (float32), and decompression of e restores them.
+ * patches with the largest e-field range r also keep their e values exactly
+ * (float32), and decompression of e restores them. Ranges are compared at a
+ * resolution of 2^-5 relative (the top 14 bits of the float); within the bin of
+ * the k-th largest range, lower patch indices come first.
  * 0 (default) stores latents only, as in the paper; the paper mentions storing
  * residuals to bound the error (Sec. 1, Sec. 3.3). Takes effect at the next
  * wv_set_storage. */
