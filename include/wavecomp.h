@@ -113,7 +113,8 @@ typedef struct ae_train_cfg {
  * the v_z face carrying each source's vertical point force; h_rec: [nrec][3]
  * (k, j, i) of the sampled v_z faces (shared by all sources). stream: a
  * hipStream_t (NULL = default stream). Fails with WV_EINVAL for indices outside
- * the grid, WV_ENOMEM when work buffers cannot be allocated. */
+ * the grid or a (y, x) plane of 2^30 cells or more, WV_ENOMEM when work buffers
+ * cannot be allocated. */
 int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec,
               void* stream, wv_ctx** out);
 

@@ -697,7 +697,8 @@ void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state
 }
 
 void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
-                     const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st)
+                     const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st,
+                     const ExcPatches* exc)
 {
     WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "decode: null buffer");
@@ -713,7 +714,8 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
         }
         for (int f = 0; f < 4; ++f)
             if (mask & (1u << f))
-                fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wp4, a->bias(3), f, state, st);
+                fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wp4, a->bias(3), f, state, st,
+                             (exc && exc->K > 0 && f == 0) ? exc : nullptr);
         return;
     }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
@@ -736,6 +738,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
                   LoadK{a->wt[3] + (long long)f * 512 * a->hid, a->hid, nullptr, 512, a->hid},
                   EpiDenorm{state, meta, a->bias(3) + f * 512, f, pg.ny / 8, pg.nx / 8, pg.ny, pg.nx, N}, st);
     }
+    if (exc && exc->K > 0 && (mask & 1u)) exceptions_restore(pg, state, exc->K, exc->idx, exc->exc, st);
 }
 
 namespace {

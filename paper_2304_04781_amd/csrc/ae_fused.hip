@@ -70,6 +70,11 @@ struct DecArgs {
     int f;
     long long P, N;
     int ny, nx, Py, Px;
+    // exception patches (none when eidx is null): increasing indices, exact values
+    // [K][512], per-work-group ranges into eidx
+    const int* eidx;
+    const float* exc;
+    const int* erng;
 };
 
 template <int L>
@@ -354,20 +359,39 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
     }
 }
 
+// Decode: NW waves per work-group of BM patches; wave w owns hidden units and
+// field-f outputs [OPW w, OPW w + OPW). W4 fragments are read from L2 PFD k-steps
+// ahead of their use.
+#ifndef WV_DEC_WAVES
+#define WV_DEC_WAVES 16
+#endif
+#ifndef WV_DEC_PF
+#define WV_DEC_PF 2
+#endif
+constexpr int DEC_NW = WV_DEC_WAVES;
+constexpr int DEC_NT = DEC_NW * 64;
+
 template <int L>
-__global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
+__global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
 {
+    constexpr int OPW = HID / DEC_NW;  // hidden units / outputs per wave
+    constexpr int JT = OPW / 16;       // 16-wide column tiles per wave
+    constexpr int NK = HID / KB;       // k-steps of layer 4
+    constexpr int PFD = WV_DEC_PF;
     extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
     uint16_t(*sH)[HID + HPAD] = reinterpret_cast<uint16_t(*)[HID + HPAD]>(smem);
     // per-patch tables after the hidden layer: field offset of the patch origin, (min, range) of field f
     long long* sBase = reinterpret_cast<long long*>(smem + BM * (HID + HPAD));
     float* sLo = reinterpret_cast<float*>(sBase + BM);
     float* sRg = sLo + BM;
+    int* sExc = reinterpret_cast<int*>(sRg + BM);  // exception slot of each patch, or -1
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int fr = lane & 15, fq = (lane >> 4) * 8, cr = (lane >> 4) * 4, q = lane >> 4;
     const long long m0 = (long long)blockIdx.x * BM;
+    const bool has_exc = a.eidx != nullptr;
 
     if (tid < BM) {
+        sExc[tid] = -1;
         const long long p = m0 + tid;
         long long base = 0;
         float lo = 0.f, rg = 0.f;
@@ -382,19 +406,29 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
         sRg[tid] = rg;
     }
 
-    // layer 3: H[BM][HID] = GELU(Z W3^T + b3); wave owns hidden units [64 wave, +64)
+    // fragment-ordered W4: block (ks, r) at ((ks * 128 + r) * 64) * 8, rows of field f at r = 32 f
+    const uint16_t* wb = a.w4p + ((long long)(a.f * 32 + wave * JT) * 64 + lane) * 8;
+    bf16x8 bq[PFD + 1][JT];
+    // the first W4 stages are in flight during layer 3
+    #pragma unroll
+    for (int u = 0; u < PFD; ++u)
+        #pragma unroll
+        for (int j = 0; j < JT; ++j)
+            bq[u][j] = *reinterpret_cast<const bf16x8*>(wb + (long long)u * (128 * 512) + j * 512);
+
+    // layer 3: H[BM][HID] = GELU(Z W3^T + b3) for this wave's hidden units
     {
-        f32x4 acc[8][4];
+        f32x4 acc[8][JT];
         #pragma unroll
         for (int i = 0; i < 8; ++i)
             #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < JT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < L / KB; ++kk) {
-            bf16x8 bw[4];
+            bf16x8 bw[JT];
             #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bw[j] = *reinterpret_cast<const bf16x8*>(a.w3t + (long long)(wave * 64 + j * 16 + fr) * L + kk * KB + fq);
+            for (int j = 0; j < JT; ++j)
+                bw[j] = *reinterpret_cast<const bf16x8*>(a.w3t + (long long)(wave * OPW + j * 16 + fr) * L + kk * KB + fq);
             #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const long long p = m0 + i * 16 + fr;
@@ -406,13 +440,13 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
                     az = *reinterpret_cast<const bf16x8*>(&zero);
                 }
                 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < JT; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(az, bw[j], acc[i][j], 0, 0, 0);
             }
         }
         #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = wave * 64 + j * 16 + fr;
+        for (int j = 0; j < JT; ++j) {
+            const int n = wave * OPW + j * 16 + fr;
             const float bias = a.b3[n];
             #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -421,48 +455,49 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
         }
     }
     __syncthreads();
-    // layer 4, rows of field f: wave owns outputs [64 wave, +64) = the lz = wave plane of every patch.
-    // A row m of tile i is patch 16 i + 4 (m % 4) + m / 4, so that the C rows held for one r by the
-    // four lane groups are four x-adjacent patches: each store then covers whole 128-byte rows.
-    f32x4 acc[8][4];
+    if (has_exc) {
+        const int e0 = a.erng[blockIdx.x], e1 = a.erng[blockIdx.x + 1];
+        for (int t = e0 + tid; t < e1; t += DEC_NT) {
+            const long long d = a.eidx[t] - m0;
+            if (d >= 0 && d < BM) sExc[d] = t;
+        }
+    }
+    // layer 4, rows of field f. A row m of tile i is patch 16 i + 4 (m % 4) + m / 4, so that the C rows
+    // held for one r by the four lane groups are four x-adjacent patches: each store then covers whole
+    // 128-byte rows.
+    f32x4 acc[8][JT];
     #pragma unroll
     for (int i = 0; i < 8; ++i)
         #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < JT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = 4 * (fr & 3) + (fr >> 2);
-    // fragment-ordered W4: block (ks, r) at ((ks * 128 + r) * 64) * 8, rows of field f at r = 32 f
-    const uint16_t* wb = a.w4p + ((long long)(a.f * 32 + wave * 4) * 64 + lane) * 8;
-    bf16x8 bcur[4], bnxt[4];
     #pragma unroll
-    for (int j = 0; j < 4; ++j) bcur[j] = *reinterpret_cast<const bf16x8*>(wb + j * 512);
-    for (int kk = 0; kk < HID / KB; ++kk) {
-        const bool more = kk + 1 < HID / KB;
-        if (more)
+    for (int kk = 0; kk < NK; ++kk) {
+        if (kk + PFD < NK)
             #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bnxt[j] = *reinterpret_cast<const bf16x8*>(wb + (long long)(kk + 1) * (128 * 512) + j * 512);
+            for (int j = 0; j < JT; ++j)
+                bq[(kk + PFD) % (PFD + 1)][j] =
+                    *reinterpret_cast<const bf16x8*>(wb + (long long)(kk + PFD) * (128 * 512) + j * 512);
         bf16x8 af[8];
         #pragma unroll
         for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sH[i * 16 + arow][kk * KB + fq]);
         #pragma unroll
         for (int i = 0; i < 8; ++i)
             #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bcur[j], acc[i][j], 0, 0, 0);
-        if (more)
-            #pragma unroll
-            for (int j = 0; j < 4; ++j) bcur[j] = bnxt[j];
+            for (int j = 0; j < JT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bq[kk % (PFD + 1)][j], acc[i][j], 0, 0, 0);
     }
-    // de-normalise and write: column c = 16 j + fr of the lz = wave plane -> (ly, lx) = (c / 8, c % 8)
-    float bias[4];
-    long long off[4];
+    // de-normalise and write: output o = OPW wave + 16 j + fr of the patch -> (lz, ly, lx) = (o / 64, o / 8 % 8, o % 8)
+    float bias[JT];
+    long long off[JT];
     #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int c = j * 16 + fr;
-        bias[j] = a.b4[a.f * 512 + wave * 64 + c];
-        off[j] = ((long long)wave * a.ny + (c >> 3)) * a.nx + (c & 7);
+    for (int j = 0; j < JT; ++j) {
+        const int o = wave * OPW + j * 16 + fr;
+        bias[j] = a.b4[a.f * 512 + o];
+        off[j] = ((long long)(o >> 6) * a.ny + ((o >> 3) & 7)) * a.nx + (o & 7);
     }
     float* out = a.state + a.f * a.N;
+    if (has_exc) __syncthreads();  // sExc complete
     #pragma unroll
     for (int i = 0; i < 8; ++i)
         #pragma unroll
@@ -471,8 +506,15 @@ __global__ void __launch_bounds__(NT) decode_kernel(const DecArgs a)
             if (m0 + pl >= a.P) continue;
             const long long base = sBase[pl];
             const float lo = sLo[pl], rg = sRg[pl];
-            #pragma unroll
-            for (int j = 0; j < 4; ++j) out[base + off[j]] = lo + rg * (acc[i][j][r] + bias[j]);
+            const int slot = has_exc ? sExc[pl] : -1;
+            if (slot < 0) {
+                #pragma unroll
+                for (int j = 0; j < JT; ++j) out[base + off[j]] = lo + rg * (acc[i][j][r] + bias[j]);
+            } else {
+                #pragma unroll
+                for (int j = 0; j < JT; ++j)
+                    out[base + off[j]] = a.exc[(long long)slot * 512 + wave * OPW + j * 16 + fr];
+            }
         }
 }
 
@@ -525,13 +567,20 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 }
 
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
-                  const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st)
+                  const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st, const ExcPatches* exc)
 {
+    static_assert(BM == DEC_BM, "exception ranges are built per decode work-group");
     DecArgs a{z, meta, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
-              pg.ny / 8, pg.nx / 8};
-    const size_t sm = (size_t)BM * (HID + HPAD) * 2 + (size_t)BM * 16;
+              pg.ny / 8, pg.nx / 8, nullptr, nullptr, nullptr};
+    if (exc && exc->K > 0) {
+        WV_REQUIRE(exc->idx && exc->exc && exc->rng, WV_EINVAL, "decode: null exception buffer");
+        a.eidx = exc->idx;
+        a.exc = exc->exc;
+        a.erng = exc->rng;
+    }
+    const size_t sm = (size_t)BM * (HID + HPAD) * 2 + (size_t)BM * 20;
     allow_smem(decode_kernel<32>, sm);
-    hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), sm, st, a);
+    hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(DEC_NT), sm, st, a);
     WV_HIP(hipGetLastError());
 }
 

@@ -48,6 +48,9 @@ T* dev_alloc(size_t count)
         throw Error{WV_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
     }
     if (e != hipSuccess) throw Error{WV_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    // zero-filled: fields a mode never writes (v_y in 2D) read as zero in every state buffer
+    WV_HIP(hipMemsetAsync(p, 0, count * sizeof(T), nullptr));
+    WV_HIP(hipStreamSynchronize(nullptr));
     return static_cast<T*>(p);
 }
 
@@ -165,11 +168,11 @@ struct wv_ctx {
     float* m = nullptr;
     float* c_last = nullptr;
     float* wavelet = nullptr;
-    float* work[2] = {nullptr, nullptr};
+    float* work[3] = {nullptr, nullptr, nullptr};  // [2]: only for autoencoder stores
     float* adj[2] = {nullptr, nullptr};
     float* incb[2] = {nullptr, nullptr};
     float* acc = nullptr;
-    float* ebuf = nullptr;
+    float* ebuf = nullptr;       // [2][S][N]: decoded e, double-buffered
     float* dm = nullptr;
     float* traces = nullptr;
     float* resid = nullptr;
@@ -195,13 +198,22 @@ struct wv_ctx {
     int K = 0;                   // active exception patches per state
     int* exc_idx = nullptr;      // [T-1][S][K]
     float* exc = nullptr;        // [T-1][S][K][512]
-    float* mmpart = nullptr;     // [S][P][H][4][2] (min, max) partials of the forward step
+    int* exc_rng = nullptr;      // [T-1][S][nbd + 1]: exceptions per decode work-group
+    int nbd = 0;                 // decode work-groups per state
+    float* mmpart = nullptr;     // [3][S][P][H][4][2] (min, max) partials of the forward step
     int H = 1;                   // y sub-tiles per patch
-    hipStream_t side = nullptr;  // exception selection/gather, overlapped with the time loop
-    hipEvent_t ev_enc = nullptr;
-    hipEvent_t ev_sel = nullptr;
-    int pend_n = 0;                  // state whose exception copy is pending (0: none)
-    const float* pend_state = nullptr;
+    // Autoencoder stores and decodes run beside the stencil steps: `side` encodes
+    // x_j (and decodes e^k for the reverse sweeps), `side2` selects and copies the
+    // exception patches of x_j. Forward states rotate through three buffers, so
+    // the store of x_j may take until the step that overwrites x_j, two later.
+    hipStream_t side = nullptr;
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_step[3] = {};    // main: x_j written (j mod 3)
+    hipEvent_t ev_enc[3] = {};     // side: x_j encoded
+    hipEvent_t ev_stored[3] = {};  // x_j fully stored: its buffer and mmpart slot are free
+    hipEvent_t ev_ready[2] = {};   // side: e^k decoded into ebuf slot
+    hipEvent_t ev_free[2] = {};    // main: ebuf slot consumed
+    hipEvent_t ev_join = nullptr;
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -363,8 +375,9 @@ void free_store(wv_ctx* c)
     dev_free(c->qs);
     dev_free(c->exc_idx);
     dev_free(c->exc);
+    dev_free(c->exc_rng);
     dev_free(c->mmpart);
-    c->pend_n = 0;
+    dev_free(c->work[2]);
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -413,36 +426,15 @@ uint8_t* lat_slot(wv_ctx* c, int idx, int s)
     return c->lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
 }
 float* meta_slot(wv_ctx* c, int idx, int s) { return c->meta + ((long long)idx * c->S + s) * c->P * 8; }
+int* rng_slot(wv_ctx* c, long long q) { return c->exc_rng + q * (c->nbd + 1); }
 float* qs_slot(wv_ctx* c, int idx, int s)
 {
     return c->qs ? c->qs + ((long long)idx * c->S + s) * c->P : nullptr;
 }
 
-// store x_n (n = 1..T-1) of every source; wi = index of the work buffer holding
-// it (-1: not a work buffer), whose reuse must wait for the exception gather
-// copy the e values of the exception patches selected for the state the last
-// store_state left pending (main stream, after its selection)
-void flush_gather(wv_ctx* c)
-{
-    if (c->pend_n <= 0) return;
-    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-    WV_HIP(hipStreamWaitEvent(c->st, c->ev_sel, 0));
-    const int tg = c->tm.begin(TM_EXC_GATHER, c->st);
-    for (int s = 0; s < c->S; ++s) {
-        const long long q = (long long)(c->pend_n - 1) * c->S + s;
-        exceptions_gather(pg, c->pend_state + s * 4 * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512,
-                          c->st);
-    }
-    c->tm.end(tg, c->st);
-    c->pend_n = 0;
-    c->pend_state = nullptr;
-}
-
-// store x_n (n = 1..T-1) of every source. With have_mm (the forward sweep's fused
-// min/max) the exception selection runs on the side stream, overlapped with the
-// next step, and the copy is left pending for flush_gather, which must run before
-// the buffer holding x_n is overwritten and before the next store_state.
-void store_state(wv_ctx* c, int n, const float* state, bool have_mm = false)
+// store x_n (n = 1..T-1) of every source on the main stream (full storage, or
+// an autoencoder store without the forward step's min/max)
+void store_state(wv_ctx* c, int n, const float* state)
 {
     if (n < 1 || n > c->T - 1) return;
     if (c->mode == WV_STORE_FULL) {
@@ -452,39 +444,79 @@ void store_state(wv_ctx* c, int n, const float* state, bool have_mm = false)
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
         const int te = c->tm.begin(TM_ENCODE, c->st);
-        for (int s = 0; s < c->S; ++s) {
-            if (have_mm)
-                ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, c->mmpart + (long long)s * c->P * c->H * 8, c->H,
-                                   ae_fmt(c->mode), lat_slot(c, n - 1, s), meta_slot(c, n - 1, s),
-                                   qs_slot(c, n - 1, s), c->st);
-            else
-                ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
-                                meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
-        }
+        for (int s = 0; s < c->S; ++s)
+            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
+                            meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
         c->tm.end(te, c->st);
         if (c->K > 0) {
-            if (have_mm) {
-                // selection on the side stream, copy left pending
-                WV_HIP(hipEventRecord(c->ev_enc, c->st));
-                WV_HIP(hipStreamWaitEvent(c->side, c->ev_enc, 0));
-                const int tx = c->tm.begin(TM_EXC_SELECT, c->side);
-                for (int s = 0; s < c->S; ++s)
-                    exceptions_select(pg, meta_slot(c, n - 1, s), c->K,
-                                      c->exc_idx + ((long long)(n - 1) * c->S + s) * c->K, c->side);
-                c->tm.end(tx, c->side);
-                WV_HIP(hipEventRecord(c->ev_sel, c->side));
-                c->pend_n = n;
-                c->pend_state = state;
-            } else {
-                const int tx = c->tm.begin(TM_EXC_SELECT, c->st);
-                for (int s = 0; s < c->S; ++s) {
-                    const long long q = (long long)(n - 1) * c->S + s;
-                    exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
-                                     c->exc + q * c->K * 512, c->st);
-                }
-                c->tm.end(tx, c->st);
+            const int tx = c->tm.begin(TM_EXC_SELECT, c->st);
+            for (int s = 0; s < c->S; ++s) {
+                const long long q = (long long)(n - 1) * c->S + s;
+                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
+                                 c->exc + q * c->K * 512, c->st);
+                exceptions_ranges(pg, c->K, c->exc_idx + q * c->K, DEC_BM, rng_slot(c, q), c->st);
             }
+            c->tm.end(tx, c->st);
         }
+    }
+}
+
+// 1: autoencoder stores and decodes run on the side streams, beside the stencil
+// steps; 2: only the exception selection and copy do; 0: everything on the main
+// stream in order
+#ifndef WV_OVERLAP
+#define WV_OVERLAP 1
+#endif
+hipStream_t side_stream(wv_ctx* c, int which)
+{
+    if (which) return WV_OVERLAP >= 1 ? c->side2 : c->st;
+    return WV_OVERLAP == 1 ? c->side : c->st;
+}
+
+// Autoencoder store of x_j (1 <= j <= T-1) written by the forward step just
+// launched on the main stream, with its min/max partials in mm: encode on `side`,
+// exception selection and copy on `side2`; ev_stored[j % 3] marks the end.
+void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
+{
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    const int b = j % 3;
+    hipStream_t s1 = side_stream(c, 0), s2 = side_stream(c, 1);
+    WV_HIP(hipEventRecord(c->ev_step[b], c->st));
+    WV_HIP(hipStreamWaitEvent(s1, c->ev_step[b], 0));
+    const int te = c->tm.begin(TM_ENCODE, s1);
+    for (int s = 0; s < c->S; ++s)
+        ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
+                           ae_fmt(c->mode), lat_slot(c, j - 1, s), meta_slot(c, j - 1, s), qs_slot(c, j - 1, s),
+                           s1);
+    c->tm.end(te, s1);
+    if (c->K <= 0) {
+        WV_HIP(hipEventRecord(c->ev_stored[b], s1));
+        return;
+    }
+    WV_HIP(hipEventRecord(c->ev_enc[b], s1));
+    WV_HIP(hipStreamWaitEvent(s2, c->ev_enc[b], 0));
+    const int tx = c->tm.begin(TM_EXC_SELECT, s2);
+    for (int s = 0; s < c->S; ++s) {
+        const long long q = (long long)(j - 1) * c->S + s;
+        exceptions_select(pg, meta_slot(c, j - 1, s), c->K, c->exc_idx + q * c->K, s2);
+        exceptions_ranges(pg, c->K, c->exc_idx + q * c->K, DEC_BM, rng_slot(c, q), s2);
+    }
+    c->tm.end(tx, s2);
+    const int tg = c->tm.begin(TM_EXC_GATHER, s2);
+    for (int s = 0; s < c->S; ++s) {
+        const long long q = (long long)(j - 1) * c->S + s;
+        exceptions_gather(pg, state + s * 4 * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512, s2);
+    }
+    c->tm.end(tg, s2);
+    WV_HIP(hipEventRecord(c->ev_stored[b], s2));
+}
+
+// make the main stream wait for everything queued on the side streams
+void join_side(wv_ctx* c)
+{
+    for (hipStream_t st : {c->side, c->side2}) {
+        WV_HIP(hipEventRecord(c->ev_join, st));
+        WV_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
     }
 }
 
@@ -494,32 +526,65 @@ void ensure_adj(wv_ctx* c)
         c->adj[0] = dev_alloc<float>(c->state_floats());
         c->adj[1] = dev_alloc<float>(c->state_floats());
         c->acc = dev_alloc<float>(2 * c->N * c->S);
-        c->ebuf = dev_alloc<float>(c->N * c->S);
+        c->ebuf = dev_alloc<float>(2 * c->N * c->S);
     }
 }
 
 // e^n of every source from the FULL or AE store: pointer + per-source stride
+float* ebuf_slot(wv_ctx* c, int b) { return c->ebuf + (long long)b * c->S * c->N; }
+
+// decode e^n of every source from the AE store into ebuf slot b on stream st
+void decode_e(wv_ctx* c, int n, int b, hipStream_t st)
+{
+    WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    float* e = ebuf_slot(c, b);
+    for (int s = 0; s < c->S; ++s) {
+        // the exception patches are written with their exact values by the decode
+        const long long q = (long long)(n - 1) * c->S + s;
+        const ExcPatches ex{c->exc_idx + q * c->K, c->K, c->exc + q * c->K * 512, c->K > 0 ? rng_slot(c, q) : nullptr};
+        const int td = c->tm.begin(TM_DECODE, st);
+        ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
+                        ae_fmt(c->mode), 1u, e + s * c->N, st, c->K > 0 ? &ex : nullptr);
+        c->tm.end(td, st);
+    }
+}
+
+// e^n of every source from the FULL or AE store (decoded on the main stream into
+// ebuf slot 0): pointer + per-source stride
 const float* load_e(wv_ctx* c, int n, long long* stride)
 {
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     *stride = c->N;
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
     ensure_adj(c);  // owns the decode target ebuf
-    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-    for (int s = 0; s < c->S; ++s) {
-        const int td = c->tm.begin(TM_DECODE, c->st);
-        ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
-                        ae_fmt(c->mode), 1u, c->ebuf + s * c->N, c->st);
-        c->tm.end(td, c->st);
-        if (c->K > 0) {
-            const long long q = (long long)(n - 1) * c->S + s;
-            const int tr = c->tm.begin(TM_EXC_RESTORE, c->st);
-            exceptions_restore(pg, c->ebuf + s * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512, c->st);
-            c->tm.end(tr, c->st);
-        }
-    }
-    return c->ebuf;
+    decode_e(c, n, 0, c->st);
+    return ebuf_slot(c, 0);
 }
+
+// Decode pipeline of the sweeps that read the AE store (adjoint, incremental
+// forward): e^n is decoded on `side` into one ebuf slot while the main stream
+// steps with the other. pipe_start marks both slots free; pipe_issue queues the
+// decode of e^n into slot b once its last reader is done; pipe_take makes the
+// main stream wait for it; pipe_release marks slot b read.
+void pipe_start(wv_ctx* c)
+{
+    ensure_adj(c);
+    for (int b = 0; b < 2; ++b) WV_HIP(hipEventRecord(c->ev_free[b], c->st));
+}
+void pipe_issue(wv_ctx* c, int n, int b)
+{
+    hipStream_t s1 = side_stream(c, 0);
+    WV_HIP(hipStreamWaitEvent(s1, c->ev_free[b], 0));
+    decode_e(c, n, b, s1);
+    WV_HIP(hipEventRecord(c->ev_ready[b], s1));
+}
+const float* pipe_take(wv_ctx* c, int b)
+{
+    WV_HIP(hipStreamWaitEvent(c->st, c->ev_ready[b], 0));
+    return ebuf_slot(c, b);
+}
+void pipe_release(wv_ctx* c, int b) { WV_HIP(hipEventRecord(c->ev_free[b], c->st)); }
 
 float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->work[1] : c->work[0]; }
 
@@ -529,25 +594,40 @@ float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->w
 float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, float* capture, int every,
                      float** last)
 {
-    c->pend_n = 0;  // nothing pending from an interrupted sweep
+    // autoencoder stores run beside the steps (x_j in work[j % 3])
+    const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
+    if (ae && !c->work[2]) c->work[2] = dev_alloc<float>(c->state_floats());
     launch_fill(c->work[0], c->state_floats(), 0.f, c->st);
     float* cur = c->work[0];
     float* prev = cur;
     const int ncap = (capture && every > 0) ? (c->T - 1) / every : 0;
-    const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
+    const long long mm_stride = (long long)c->S * c->P * c->H * 8;
     for (int n = 0; n < c->T; ++n) {
-        float* out = (snap && (*snap)[n + 1] > 0) ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
-        const bool store = n + 1 <= c->T - 1;
-        fwd_step(c, cur, out, n, traces, (ae && store) ? c->mmpart : nullptr);
-        flush_gather(c);  // exceptions of x_n, still in cur
-        if (store) store_state(c, n + 1, out, ae);
-        if (ncap > 0 && (n + 1) % every == 0 && (n + 1) / every <= ncap)
-            WV_HIP(hipMemcpyAsync(capture + (long long)((n + 1) / every - 1) * c->state_floats(), out,
+        const int j = n + 1;  // this step writes x_j
+        const bool store = j <= c->T - 1;
+        float* out;
+        if (ae) {
+            out = c->work[j % 3];
+            // the buffer and min/max slot held x_{j-3}: its store must be done
+            if (j - 3 >= 1 && j - 3 <= c->T - 1) WV_HIP(hipStreamWaitEvent(c->st, c->ev_stored[j % 3], 0));
+        } else {
+            out = (snap && (*snap)[j] > 0) ? c->slot_ptr((*snap)[j]) : other_work(c, cur);
+        }
+        float* mm = (ae && store) ? c->mmpart + (j % 3) * mm_stride : nullptr;
+        fwd_step(c, cur, out, n, traces, mm);
+        if (store) {
+            if (ae)
+                store_state_async(c, j, out, mm);
+            else
+                store_state(c, j, out);
+        }
+        if (ncap > 0 && j % every == 0 && j / every <= ncap)
+            WV_HIP(hipMemcpyAsync(capture + (long long)(j / every - 1) * c->state_floats(), out,
                                   sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice, c->st));
         prev = cur;
         cur = out;
     }
-    flush_gather(c);
+    if (ae) join_side(c);
     c->last_fwd_steps = c->T;
     if (last) *last = cur;
     return prev;
@@ -600,6 +680,18 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
         adj_step(c, ain, aout, k, resid, ek, stride);
         std::swap(ain, aout);
     };
+    if (!acts && is_ae(c->mode)) {
+        // e^{k-1} is decoded beside the adjoint step k
+        pipe_start(c);
+        if (c->T - 1 >= 1) pipe_issue(c, c->T - 1, 0);
+        for (int k = c->T - 1; k >= 1; --k) {
+            const int b = (c->T - 1 - k) & 1;
+            if (k - 1 >= 1) pipe_issue(c, k - 1, b ^ 1);
+            adjoint_k(k, pipe_take(c, b), c->N);
+            pipe_release(c, b);
+        }
+        return;
+    }
     if (!acts) {
         for (int k = c->T - 1; k >= 1; --k) {
             long long stride;
@@ -675,6 +767,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         WV_REQUIRE(grid && out, WV_EINVAL, "null argument");
         const wv_grid g = *grid;
         WV_REQUIRE(g.nz >= 2 && g.ny >= 1 && g.nx >= 2, WV_EINVAL, "grid too small");
+        WV_REQUIRE((long long)g.ny * g.nx < (1LL << 30), WV_EINVAL, "a (y, x) plane must hold fewer than 2^30 cells");
         WV_REQUIRE(g.dx > 0 && g.dt > 0 && g.nt >= 1, WV_EINVAL, "dx, dt must be > 0 and nt >= 1");
         WV_REQUIRE(g.sponge >= 0 && g.nsrc >= 1 && g.nrec >= 0, WV_EINVAL, "bad sponge/nsrc/nrec");
         WV_REQUIRE(g.sponge == 0 || g.c_ref > 0, WV_EINVAL, "c_ref must be > 0 with an absorbing layer");
@@ -715,8 +808,17 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->resid = dev_alloc<float>(ntr);
         c->dtr = dev_alloc<float>(ntr);
         WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        WV_HIP(hipEventCreateWithFlags(&c->ev_enc, hipEventDisableTiming));
-        WV_HIP(hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming));
+        WV_HIP(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
+        for (int b = 0; b < 3; ++b) {
+            WV_HIP(hipEventCreateWithFlags(&c->ev_step[b], hipEventDisableTiming));
+            WV_HIP(hipEventCreateWithFlags(&c->ev_enc[b], hipEventDisableTiming));
+            WV_HIP(hipEventCreateWithFlags(&c->ev_stored[b], hipEventDisableTiming));
+        }
+        for (int b = 0; b < 2; ++b) {
+            WV_HIP(hipEventCreateWithFlags(&c->ev_ready[b], hipEventDisableTiming));
+            WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
+        }
+        WV_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
         c->dscal = dev_alloc<double>(8);
         c->dflag = dev_alloc<int>(1);
@@ -730,12 +832,16 @@ int wv_destroy(wv_ctx* c)
     if (!c) return WV_OK;
     (void)hipStreamSynchronize(c->st);
     if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->side2) (void)hipStreamSynchronize(c->side2);
     c->tm.destroy();
     free_store(c);
     free_tiling(c->tl);
-    if (c->ev_enc) (void)hipEventDestroy(c->ev_enc);
-    if (c->ev_sel) (void)hipEventDestroy(c->ev_sel);
+    for (hipEvent_t e : {c->ev_step[0], c->ev_step[1], c->ev_step[2], c->ev_enc[0], c->ev_enc[1], c->ev_enc[2],
+                         c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_ready[0], c->ev_ready[1],
+                         c->ev_free[0], c->ev_free[1], c->ev_join})
+        if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->side2) (void)hipStreamDestroy(c->side2);
     dev_free(c->tab);
     dev_free(c->src_kji);
     dev_free(c->src_w);
@@ -786,8 +892,9 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
             const long long slots = (long long)std::max(T - 1, 1) * c->S;
             const int K = (int)std::min<long long>(c->exc_req, c->P);
+            const long long nbd = (c->P + DEC_BM - 1) / DEC_BM;
             const long long bytes = slots * (c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0)) +
-                                             (long long)K * (512 * 4 + 4));
+                                             (long long)K * (512 * 4 + 4) + (K > 0 ? (nbd + 1) * 4 : 0));
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
             c->lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
             c->meta = dev_alloc<float>(slots * c->P * 8);
@@ -796,10 +903,13 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
                 c->exc_idx = dev_alloc<int>(slots * K);
                 WV_HIP(hipMemset(c->exc_idx, 0, sizeof(int) * slots * K));
                 c->exc = dev_alloc<float>(slots * K * 512);
+                c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
+                c->exc_rng = dev_alloc<int>(slots * (c->nbd + 1));
+                WV_HIP(hipMemset(c->exc_rng, 0, sizeof(int) * slots * (c->nbd + 1)));
             }
             c->K = K;
             c->H = 8 / c->tl.by;
-            c->mmpart = dev_alloc<float>((size_t)c->S * c->P * c->H * 8);
+            c->mmpart = dev_alloc<float>((size_t)3 * c->S * c->P * c->H * 8);
             c->store_bytes = bytes;
             if (fallback_policy == WV_FALLBACK_CHECKPOINT)
                 WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
@@ -953,7 +1063,9 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
     ensure_adj(c);
     launch_dm(cdev, dc, c->dm, c->N, c->st);
     launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
-    launch_fill(c->ebuf, c->N * c->S, 0.f, c->st);
+    const bool pipe = !snap && is_ae(c->mode);
+    if (pipe) pipe_start(c);
+    launch_fill(ebuf_slot(c, 0), c->N * c->S, 0.f, c->st);  // e^0 = 0
     float* din = c->incb[0];
     float* dout = c->incb[1];
     const bool ckpt = snap != nullptr;
@@ -969,13 +1081,19 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         if (ckpt) {
             en = cur;
             stride = 4 * c->N;
+        } else if (pipe) {
+            // e^{n+1} is decoded beside the step n; slot n & 1 holds e^n
+            if (n + 1 <= c->T - 1) pipe_issue(c, n + 1, (n + 1) & 1);
+            en = n == 0 ? ebuf_slot(c, 0) : pipe_take(c, n & 1);
+            stride = c->N;
         } else if (n == 0) {
-            en = c->ebuf;  // e^0 = 0
+            en = ebuf_slot(c, 0);  // e^0 = 0
             stride = c->N;
         } else {
             en = load_e(c, n, &stride);
         }
         inc_step(c, din, dout, n, en, stride, c->dtr);
+        if (pipe) pipe_release(c, n & 1);
         std::swap(din, dout);
         if (ckpt) {
             float* out = (*snap)[n + 1] > 0 ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);

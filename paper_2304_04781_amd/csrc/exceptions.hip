@@ -187,6 +187,21 @@ __global__ void scatter_kernel(float* __restrict__ e, int ny, int nx, int Py, in
     e[(z * ny + y) * nx + x] = exc[(long long)k * 512 + l];
 }
 
+// rng[b] = lower bound of patch bm b in the increasing list idx [K]
+__global__ void ranges_kernel(const int* __restrict__ idx, int K, int bm, int nb, int* __restrict__ rng)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    const long long target = (long long)b * bm;
+    int lo = 0, hi = K;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (idx[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    rng[b] = lo;
+}
+
 }  // namespace
 
 void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st)
@@ -212,6 +227,13 @@ void exceptions_store(const PatchGrid& pg, const float* state, const float* meta
     if (K <= 0) return;
     exceptions_select(pg, meta, K, idx, st);
     exceptions_gather(pg, state, K, idx, exc, st);
+}
+
+void exceptions_ranges(const PatchGrid& pg, int K, const int* idx, int bm, int* rng, hipStream_t st)
+{
+    const int nb = (int)((pg.P + bm - 1) / bm);
+    hipLaunchKernelGGL(ranges_kernel, dim3((nb + 1 + 255) / 256), dim3(256), 0, st, idx, K, bm, nb, rng);
+    WV_HIP(hipGetLastError());
 }
 
 void exceptions_restore(const PatchGrid& pg, float* e, int K, const int* idx, const float* exc, hipStream_t st)

@@ -34,16 +34,56 @@ namespace {
 
 constexpr int NF = 4;  // fields per state: e, v_z, v_y, v_x
 
+// Read-only tables indexed by a work-group-uniform index (layer factors per
+// level, receiver pointers) are read through the constant address space, so
+// they become scalar loads. As plain global loads they would be vector loads
+// whose wait also drains the column / plane prefetch of the next levels.
+template <class T>
+__device__ __forceinline__ T ldu(const T* p, long long idx)
+{
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wold-style-cast"
+    return ((const __attribute__((address_space(4))) T*)p)[idx];
+#pragma clang diagnostic pop
+}
+
+// Field access at a level base (uniform) plus a 32-bit byte offset within the
+// plane, as raw buffer operations: the base stays in scalar registers, so the
+// compiler cannot hoist per-lane 64-bit pointers (two VGPRs per field) out of
+// the level loop. `bytes` bounds the offsets (one plane).
+constexpr int BUF_DW3 = 0x00020000;  // raw 32-bit data format, no swizzle
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, BUF_DW3);
+}
+__device__ __forceinline__ float ld_plane(const float* base, unsigned bytes, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(base, bytes), (int)off, 0, 0));
+}
+// aux 2: non-temporal (streamed output, not re-read by this launch)
+__device__ __forceinline__ void st_plane_nt(float v, float* base, unsigned bytes, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), plane_rsrc(base, bytes), (int)off, 0, 2);
+}
+__device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), plane_rsrc(base, bytes), (int)off, 0, 0);
+}
+
 // Minimum waves per SIMD asked of the register allocator (occupancy of these
 // latency-bound kernels), per variant.
 #ifndef WV_WAVES_FWD_MM
-#define WV_WAVES_FWD_MM 7
+#define WV_WAVES_FWD_MM 5
 #endif
 #ifndef WV_WAVES_ADJ
-#define WV_WAVES_ADJ 7
+#define WV_WAVES_ADJ 5
 #endif
 #ifndef WV_WAVES_OTHER
-#define WV_WAVES_OTHER 7
+#define WV_WAVES_OTHER 6
+#endif
+// prefetch distance in levels of the software pipeline
+#ifndef WV_PF
+#define WV_PF 1
 #endif
 
 // MM: also write the per-patch (min, max) partials of the new state (forward only)
@@ -56,6 +96,7 @@ __global__ void __launch_bounds__(BX* BY)
     __shared__ float sWy[HAS_Y ? BY + 1 : 1][BX];
     __shared__ float sWx[BY][BX + 1];
     __shared__ float sMM[MM ? BY : 1][BX / 8][8];  // per-row partial (min, max) of 8 patches
+    __shared__ float sRec[BY * BX];                  // receiver exchange (levels with receivers)
 
     // ---- block -> (x tile, y tile, z chunk); spread so one XCD gets a contiguous range
     const int nblk = a.tiles_x * a.tiles_y * a.chunks_z;
@@ -125,9 +166,8 @@ __global__ void __launch_bounds__(BX* BY)
     const long long rcell = ring_in ? (long long)rj * nx + ri : 0;
     const float ring_wyx = ring_in ? a.wyc[rj] * a.wxc[ri] : 0.f;
 
-    // receiver-list cursors (uniform across the work-group)
-    int rp = 0, re = 0;
-    if (a.nrec > 0) { rp = a.rec_ptr[tile]; re = a.rec_ptr[tile + 1]; }
+    // receivers of this tile per level: rec_ent[lp[k] .. lp[k + 1])
+    const int* lp = a.rec_ptr + (long long)tile * (nz + 1);
     // source of this wavefield: force density wavelet[s][n] * w[dk][dj][di] on the
     // v_z faces of a (2R+1)^dims box centred on its face
     int sk = 0, sj = 0, si = 0, R = 0;
@@ -142,21 +182,37 @@ __global__ void __launch_bounds__(BX* BY)
     const int wdj = HAS_Y ? 2 * R + 1 : 1;
     const bool src_col = MODE == MODE_FWD && inside && abs(i - si) <= R && (HAS_Y ? abs(j - sj) <= R : true);
     const int src_col_off = src_col ? (HAS_Y ? (j - sj + R) : 0) * (2 * R + 1) + (i - si + R) : 0;
-    int tp = rp;  // trace-recording cursor (forward / incremental)
+    const long long trow = ((long long)s * a.nt + a.tidx) * a.nrec;  // traces / residual row
 
-    // extra term on the v_z face kk: dt b (forward source), B^T r (adjoint)
+    // extra term on the v_z face kk: dt b (forward source), B^T r (adjoint). The
+    // adjoint gathers the residuals of the level's receivers into sRec: one thread
+    // per run of entries on the same cell sums the run in receiver order. Called by
+    // the whole work-group (the receiver test is uniform).
     auto face_inj = [&](int kk) -> float {
         float add = 0.f;
         if (MODE == MODE_FWD) {
             if (src_col && abs(kk - sk) <= R)
                 add = bsrc * a.src_w[(kk - sk + R) * wdj * (2 * R + 1) + src_col_off];
         } else if (MODE == MODE_ADJ) {
-            while (rp < re && a.rec_ent[rp].x < kk) ++rp;
-            for (int q = rp; q < re; ++q) {
-                const int4 e = a.rec_ent[q];
-                if (e.x != kk) break;
-                if (e.y == local)
-                    add += a.resid[((long long)s * a.nt + a.tidx) * a.nrec + e.z];
+            if (a.nrec > 0 && kk < nz) {
+                const int q0 = ldu(lp, kk), q1 = ldu(lp, kk + 1);
+                if (q1 > q0) {
+                    sRec[local] = 0.f;
+                    __syncthreads();
+                    for (int q = q0 + tid; q < q1; q += BX * BY) {
+                        const int4 e = a.rec_ent[q];
+                        if (q > q0 && a.rec_ent[q - 1].y == e.y) continue;
+                        float r = 0.f;
+                        for (int u = q; u < q1; ++u) {
+                            const int4 f = a.rec_ent[u];
+                            if (f.y != e.y) break;
+                            r += a.resid[trow + f.z];
+                        }
+                        sRec[e.y] = r;
+                    }
+                    __syncthreads();
+                    add = sRec[local];
+                }
             }
         }
         return add;
@@ -169,78 +225,89 @@ __global__ void __launch_bounds__(BX* BY)
     // what enters the divergence: v' (forward) or S_v mu' (adjoint)
     auto face_w = [&](float S, float Vn) -> float { return MODE == MODE_ADJ ? S * Vn : Vn; };
 
-    // Software pipeline: the column data of level k+2 and the in-plane data of
-    // level k+1 are loaded while level k is computed.
+    // Software pipeline: the column data of level k+1+PF and the in-plane data of
+    // level k+PF are loaded while level k is computed, into a ring of PF+1
+    // register sets (no copies between levels). Every lane issues every load,
+    // at a clamped in-grid address where its own operand does not exist (outside
+    // lanes read cell 0, out-of-range levels the nearest level); such values are
+    // never used, so the loads need no branches and the compiler can count the
+    // outstanding ones instead of draining them.
     struct Col {  // own column at one level
         float A, m, Vz, dm, en;
     };
     struct Pln {  // in-plane operands of one level
         float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp;
     };
+    // Addresses are a level base (uniform, scalar registers) plus a 32-bit byte
+    // offset within the plane (a plane holds fewer than 2^30 cells).
+    const unsigned o_c = (unsigned)cell * 4u;
+    const unsigned o_r = (unsigned)rcell * 4u;
+    const unsigned o_hy = halo_y ? (unsigned)(jh * nx + i) * 4u : o_c;
+    const unsigned o_hx = halo_x ? (unsigned)(j * nx + ih) * 4u : o_c;
+    const unsigned pb4 = (unsigned)plane * 4u;
+    auto ld = [&](const float* f, long long lo, unsigned off) { return ld_plane(f + lo, pb4, off); };
     auto load_col = [&](int kk, Col& c) {
-        c.A = c.m = c.Vz = c.dm = c.en = 0.f;
-        if (inside && kk >= 0 && kk < nz) {
-            const long long o = (long long)kk * plane + cell;
-            c.A = inA[o];
-            c.m = mm[o];
-            c.Vz = inVz[o];
-            if (MODE == MODE_INC) {
-                c.dm = a.dm[o];
-                c.en = en[o];
-            }
+        const long long lo = (long long)min(max(kk, 0), nz - 1) * plane;
+        c.A = ld(inA, lo, o_c);
+        c.m = ld(mm, lo, o_c);
+        c.Vz = ld(inVz, lo, o_c);
+        if (MODE == MODE_INC) {
+            c.dm = ld(a.dm, lo, o_c);
+            c.en = ld(en, lo, o_c);
         }
     };
     auto load_pln = [&](int kk, Pln& q) {
-        q.Vy = q.Vx = q.Vyh = q.Vxh = q.rA = q.rm = q.rdm = q.ren = q.ek = q.acc = q.cmp = 0.f;
-        const long long ok = (long long)kk * plane;
-        if (inside) {
-            if (HAS_Y) q.Vy = inVy[ok + cell];
-            q.Vx = inVx[ok + cell];
-            if (MODE == MODE_ADJ) {
-                q.ek = ek[ok + cell];
-                q.acc = acc[ok + cell];
-                q.cmp = cmp[ok + cell];
-            }
+        const long long lo = (long long)kk * plane;
+        if (HAS_Y) {
+            q.Vy = ld(inVy, lo, o_c);
+            q.Vyh = ld(inVy, lo, o_hy);
         }
-        if (halo_y) q.Vyh = inVy[ok + (long long)jh * nx + i];
-        if (halo_x) q.Vxh = inVx[ok + (long long)j * nx + ih];
-        if (ring_in) {
-            q.rA = inA[ok + rcell];
-            if (MODE != MODE_ADJ) q.rm = mm[ok + rcell];
-            if (MODE == MODE_INC) {
-                q.rdm = a.dm[ok + rcell];
-                q.ren = en[ok + rcell];
-            }
+        q.Vx = ld(inVx, lo, o_c);
+        q.Vxh = ld(inVx, lo, o_hx);
+        if (MODE == MODE_ADJ) {
+            q.ek = ld(ek, lo, o_c);
+            q.acc = ld(acc, lo, o_c);
+            q.cmp = ld(cmp, lo, o_c);
+        }
+        q.rA = ld(inA, lo, o_r);
+        if (MODE != MODE_ADJ) q.rm = ld(mm, lo, o_r);
+        if (MODE == MODE_INC) {
+            q.rdm = ld(a.dm, lo, o_r);
+            q.ren = ld(en, lo, o_r);
         }
     };
     auto P_col = [&](int kk, const Col& c) -> float {
         if (MODE == MODE_FWD) return c.m * c.A;
         if (MODE == MODE_INC) return c.m * c.A + c.dm * c.en;
-        return (a.wzc[kk] * wyx_c) * c.A;
+        return (ldu(a.wzc, kk) * wyx_c) * c.A;
     };
     auto P_ring = [&](int kk, const Pln& q) -> float {
         if (!ring_in) return 0.f;
         if (MODE == MODE_FWD) return q.rm * q.rA;
         if (MODE == MODE_INC) return q.rm * q.rA + q.rdm * q.ren;
-        return (a.wzc[kk] * ring_wyx) * q.rA;
+        return (ldu(a.wzc, kk) * ring_wyx) * q.rA;
     };
 
-    // ---- prologue: P(k0), cell value, v_z'(k0); first pipeline stages
+    // ---- prologue: P(k0), cell value, v_z'(k0); first pipeline stages.
+    // Ring slot u holds column level k0+u (mod NB) and plane level k0+u (mod NB).
+    constexpr int NB = WV_PF + 1;
     float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
-    Col cn, cnn;
-    Pln pc, pn;
+    Col cb[NB];
+    Pln pb[NB];
     {
         Col c0, cl;
         load_col(k0, c0);
         load_col(k0 - 1, cl);
-        load_col(k0 + 1, cn);
-        load_pln(k0, pc);
+#pragma unroll
+        for (int u = 1; u <= WV_PF; ++u) load_col(k0 + u, cb[u % NB]);
+#pragma unroll
+        for (int u = 0; u < WV_PF; ++u) load_pln(min(k0 + u, k1 - 1), pb[u]);
         A_cur = c0.A;
         m_cur = c0.m;
         P_cur = inside ? P_col(k0, c0) : 0.f;
         const float P_lo = (inside && k0 > 0) ? P_col(k0 - 1, cl) : 0.f;
         const float add = face_inj(k0);
-        const float S = a.wzf[k0] * wyx_c;
+        const float S = ldu(a.wzf, k0) * wyx_c;
         Vz_cur = face_new(S, c0.Vz, P_cur - P_lo, add);
         Wz_cur = face_w(S, Vz_cur);
     }
@@ -250,14 +317,15 @@ __global__ void __launch_bounds__(BX* BY)
     float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY;
     float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY, mx3 = -INFINITY;
 
-    for (int k = k0; k < k1; ++k) {
-        const long long offk = (long long)k * plane + cell;
+    // one level k: reads cn (column level k+1) and pc (plane level k), loads
+    // cnn (column level k+1+PF) and pn (plane level k+PF)
+    auto level = [&](const int k, const Col& cn, Col& cnn, const Pln& pc, Pln& pn) {
+        const long long lk = (long long)k * plane;
         const bool has_next = k + 1 < nz;
-        // issue the loads of the next pipeline stages
-        if (k + 1 < k1) {
-            load_col(k + 2, cnn);
-            load_pln(k + 1, pn);
-        }
+        // issue the loads of the next pipeline stages (levels past the chunk
+        // re-read its last plane rather than branching)
+        load_col(k + 1 + WV_PF, cnn);
+        load_pln(min(k + WV_PF, k1 - 1), pn);
         const float P_nx = (inside && has_next) ? P_col(k + 1, cn) : 0.f;
         const float Vz_nx_in = cn.Vz;
         const float Vy_in = pc.Vy, Vx_in = pc.Vx, Vy_h = pc.Vyh, Vx_h = pc.Vxh;
@@ -270,7 +338,7 @@ __global__ void __launch_bounds__(BX* BY)
         __syncthreads();
 
         // ---- faces in the plane
-        const float wzc = a.wzc[k];
+        const float wzc = ldu(a.wzc, k);
         float Vy_new = 0.f, Vx_new = 0.f;
         if (HAS_Y) {
             const float S = wzc * wyx_vy;
@@ -297,7 +365,7 @@ __global__ void __launch_bounds__(BX* BY)
         {
             const float add = face_inj(k + 1);
             if (has_next) {
-                const float S = a.wzf[k + 1] * wyx_c;
+                const float S = ldu(a.wzf, k + 1) * wyx_c;
                 Vz_nx = face_new(S, Vz_nx_in, P_nx - P_cur, add);
                 Wz_nx = face_w(S, Vz_nx);
             }
@@ -322,19 +390,19 @@ __global__ void __launch_bounds__(BX* BY)
         }
         if (inside) {
 #if WV_NT_STORE
-            __builtin_nontemporal_store(A_new, &outA[offk]);
-            __builtin_nontemporal_store(Vz_cur, &outVz[offk]);
-            if (HAS_Y) __builtin_nontemporal_store(Vy_new, &outVy[offk]);
-            __builtin_nontemporal_store(Vx_new, &outVx[offk]);
+            st_plane_nt(A_new, outA + lk, pb4, o_c);
+            st_plane_nt(Vz_cur, outVz + lk, pb4, o_c);
+            if (HAS_Y) st_plane_nt(Vy_new, outVy + lk, pb4, o_c);
+            st_plane_nt(Vx_new, outVx + lk, pb4, o_c);
 #else
-            outA[offk] = A_new;
-            outVz[offk] = Vz_cur;
-            if (HAS_Y) outVy[offk] = Vy_new;
-            outVx[offk] = Vx_new;
+            st_plane(A_new, outA + lk, pb4, o_c);
+            st_plane(Vz_cur, outVz + lk, pb4, o_c);
+            if (HAS_Y) st_plane(Vy_new, outVy + lk, pb4, o_c);
+            st_plane(Vx_new, outVx + lk, pb4, o_c);
 #endif
             if (MODE == MODE_ADJ) {
-                acc[offk] = s_acc;
-                cmp[offk] = s_cmp;
+                st_plane(s_acc, acc + lk, pb4, o_c);
+                st_plane(s_cmp, cmp + lk, pb4, o_c);
             }
         }
         if constexpr (want_mm) {
@@ -377,13 +445,16 @@ __global__ void __launch_bounds__(BX* BY)
                 mx0 = mx1 = mx2 = mx3 = -INFINITY;
             }
         }
+        // traces: v_z of this level's new face at the receivers, through sRec
         if (MODE != MODE_ADJ && a.nrec > 0) {
-            while (tp < re && a.rec_ent[tp].x < k) ++tp;
-            for (int q = tp; q < re; ++q) {
-                const int4 e = a.rec_ent[q];
-                if (e.x != k) break;
-                if (e.y == local && inside)
-                    a.traces[((long long)s * a.nt + a.tidx) * a.nrec + e.z] = Vz_cur;
+            const int q0 = ldu(lp, k), q1 = ldu(lp, k + 1);
+            if (q1 > q0) {
+                sRec[local] = Vz_cur;
+                __syncthreads();
+                for (int q = q0 + tid; q < q1; q += BX * BY) {
+                    const int4 e = a.rec_ent[q];
+                    a.traces[trow + e.z] = sRec[e.y];
+                }
             }
         }
         P_cur = P_nx;
@@ -391,9 +462,18 @@ __global__ void __launch_bounds__(BX* BY)
         m_cur = cn.m;
         Vz_cur = Vz_nx;
         Wz_cur = Wz_nx;
-        cn = cnn;
-        pc = pn;
+    };
+    // level k0+u uses column slot (u+1) % NB, plane slot u % NB, and refills the
+    // slots of column k0+u (consumed one level earlier) and plane k0+u-1
+    int kb = k0;
+    for (; kb + NB <= k1; kb += NB) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            level(kb + u, cb[(u + 1) % NB], cb[u % NB], pb[u % NB], pb[(u + NB - 1) % NB]);
     }
+#pragma unroll
+    for (int u = 0; u < NB - 1; ++u)
+        if (kb + u < k1) level(kb + u, cb[(u + 1) % NB], cb[u % NB], pb[u % NB], pb[(u + NB - 1) % NB]);
 }
 
 template <int BX, int BY, bool HAS_Y>
@@ -422,7 +502,7 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
 }  // namespace
 
 #ifndef WV_TILE_BY
-#define WV_TILE_BY 4
+#define WV_TILE_BY 8
 #endif
 #ifndef WV_CHUNK_TARGET
 #define WV_CHUNK_TARGET 2048
@@ -464,6 +544,8 @@ Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji)
     chunking(WV_CHUNK_TARGET, &t.kc, &t.chunks_z);
     chunking(WV_CHUNK_TARGET_ADJ, &t.kc_adj, &t.chunks_adj);
 
+    // receivers bucketed by tile, then level, then local cell: one pointer per
+    // (tile, level) so a work-group finds the receivers of a level in O(1)
     auto bucket = [&](const std::vector<int>& kji, int** d_ptr, int4** d_ent) {
         const int n = (int)kji.size() / 3;
         std::vector<std::vector<int4>> per(tiles);
@@ -472,15 +554,20 @@ Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji)
             const int tl = (j / t.by) * t.tiles_x + (i / t.bx);
             per[tl].push_back(make_int4(k, (j % t.by) * t.bx + (i % t.bx), q, 0));
         }
-        std::vector<int> ptr(tiles + 1, 0);
+        std::vector<int> ptr((size_t)tiles * (nz + 1), 0);
         std::vector<int4> ent;
         for (int tl = 0; tl < tiles; ++tl) {
-            std::stable_sort(per[tl].begin(), per[tl].end(),
-                             [](const int4& x, const int4& y) { return x.x < y.x; });
-            ptr[tl] = (int)ent.size();
+            std::stable_sort(per[tl].begin(), per[tl].end(), [](const int4& x, const int4& y) {
+                return x.x != y.x ? x.x < y.x : x.y < y.y;
+            });
+            const int base = (int)ent.size();
+            size_t q = 0;
+            for (int k = 0; k <= nz; ++k) {
+                while (q < per[tl].size() && per[tl][q].x < k) ++q;
+                ptr[(size_t)tl * (nz + 1) + k] = base + (int)q;
+            }
             ent.insert(ent.end(), per[tl].begin(), per[tl].end());
         }
-        ptr[tiles] = (int)ent.size();
         WV_HIP(hipMalloc(d_ptr, sizeof(int) * ptr.size()));
         WV_HIP(hipMemcpy(*d_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice));
         const size_t ne = std::max<size_t>(ent.size(), 1);

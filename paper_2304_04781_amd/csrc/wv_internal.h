@@ -42,7 +42,9 @@ struct Tiling {
     int bx = 64, by = 8;
     int tiles_x = 0, tiles_y = 0, chunks_z = 0, kc = 0;  // forward / incremental chunks
     int chunks_adj = 0, kc_adj = 0;                       // adjoint chunks
-    int* rec_ptr = nullptr;   // [tiles + 1]
+    // receivers of tile t at level k: rec_ent[rec_ptr[t (nz + 1) + k] ..
+    // rec_ptr[t (nz + 1) + k + 1]), sorted by (local cell, receiver)
+    int* rec_ptr = nullptr;   // [tiles][nz + 1]
     int4* rec_ent = nullptr;  // (k, local, r, 0)
 };
 
