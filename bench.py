@@ -301,7 +301,12 @@ def main():
                         "effective_vs_float32_history": round(4.0 * 4 * N * (T - 1) / store_bytes, 1)},
         "train": dict(train_info, wall_s=round(t_train_total, 2)),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
-        "checkpoint_kernels": {k: {"us": round(us, 2), "timed_launches": n} for k, (us, n) in kt_ck.items() if n},
+        # the same stencil kernels with the GPU to themselves (no encode or decode beside them)
+        "checkpoint_kernels": {k: dict({"us": round(us, 2), "timed_launches": n},
+                                       **({"GB/s": round(per_launch[k][1] / (us * 1e-6) / 1e9, 1),
+                                           "frac_hbm": round(per_launch[k][1] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                                          if k in per_launch and per_launch[k][0] == "hbm" else {}))
+                               for k, (us, n) in kt_ck.items() if n},
         "first_gradient_s": round(t_train_total + t_ae, 3),
         "amortized_over_10_gradients_s": round((t_train_total + 10 * t_ae) / 10, 4),
         "setup_s": round(time.perf_counter() - t_setup, 1),
