@@ -359,9 +359,9 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
     }
 }
 
-// Decode: NW waves per work-group of BM patches; wave w owns hidden units and
-// field-f outputs [OPW w, OPW w + OPW). W4 fragments are read from L2 PFD k-steps
-// ahead of their use.
+// Decode: DEC_NW waves per work-group of DEC_BM patches; wave w owns hidden units
+// and field-f outputs [OPW w, OPW w + OPW). W4 fragments are read from L2 PFD
+// k-steps ahead of their use.
 #ifndef WV_DEC_WAVES
 #define WV_DEC_WAVES 16
 #endif
@@ -374,6 +374,8 @@ constexpr int DEC_NT = DEC_NW * 64;
 template <int L>
 __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
 {
+    constexpr int BM = DEC_BM;         // patches per work-group
+    constexpr int IT = BM / 16;        // 16-row tiles
     constexpr int OPW = HID / DEC_NW;  // hidden units / outputs per wave
     constexpr int JT = OPW / 16;       // 16-wide column tiles per wave
     constexpr int NK = HID / KB;       // k-steps of layer 4
@@ -418,9 +420,9 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
 
     // layer 3: H[BM][HID] = GELU(Z W3^T + b3) for this wave's hidden units
     {
-        f32x4 acc[8][JT];
+        f32x4 acc[IT][JT];
         #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < IT; ++i)
             #pragma unroll
             for (int j = 0; j < JT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -430,7 +432,7 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
             for (int j = 0; j < JT; ++j)
                 bw[j] = *reinterpret_cast<const bf16x8*>(a.w3t + (long long)(wave * OPW + j * 16 + fr) * L + kk * KB + fq);
             #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const long long p = m0 + i * 16 + fr;
                 bf16x8 az;
                 if (p < a.P) {
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
             const int n = wave * OPW + j * 16 + fr;
             const float bias = a.b3[n];
             #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < IT; ++i)
                 #pragma unroll
                 for (int r = 0; r < 4; ++r) sH[i * 16 + cr + r][n] = f2bf(gelu(acc[i][j][r] + bias));
         }
@@ -465,9 +467,9 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
     // layer 4, rows of field f. A row m of tile i is patch 16 i + 4 (m % 4) + m / 4, so that the C rows
     // held for one r by the four lane groups are four x-adjacent patches: each store then covers whole
     // 128-byte rows.
-    f32x4 acc[8][JT];
+    f32x4 acc[IT][JT];
     #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < IT; ++i)
         #pragma unroll
         for (int j = 0; j < JT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = 4 * (fr & 3) + (fr >> 2);
@@ -478,11 +480,11 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
             for (int j = 0; j < JT; ++j)
                 bq[(kk + PFD) % (PFD + 1)][j] =
                     *reinterpret_cast<const bf16x8*>(wb + (long long)(kk + PFD) * (128 * 512) + j * 512);
-        bf16x8 af[8];
+        bf16x8 af[IT];
         #pragma unroll
-        for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sH[i * 16 + arow][kk * KB + fq]);
+        for (int i = 0; i < IT; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&sH[i * 16 + arow][kk * KB + fq]);
         #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < IT; ++i)
             #pragma unroll
             for (int j = 0; j < JT; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bq[kk % (PFD + 1)][j], acc[i][j], 0, 0, 0);
@@ -499,7 +501,7 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
     float* out = a.state + a.f * a.N;
     if (has_exc) __syncthreads();  // sExc complete
     #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < IT; ++i)
         #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pl = i * 16 + 4 * r + q;
@@ -569,7 +571,7 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st, const ExcPatches* exc)
 {
-    static_assert(BM == DEC_BM, "exception ranges are built per decode work-group");
+    static_assert(DEC_BM % 16 == 0 && DEC_BM <= 512, "decode work-groups hold whole 16-patch tiles");
     DecArgs a{z, meta, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
               pg.ny / 8, pg.nx / 8, nullptr, nullptr, nullptr};
     if (exc && exc->K > 0) {
@@ -578,9 +580,9 @@ void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, con
         a.exc = exc->exc;
         a.erng = exc->rng;
     }
-    const size_t sm = (size_t)BM * (HID + HPAD) * 2 + (size_t)BM * 20;
+    const size_t sm = (size_t)DEC_BM * (HID + HPAD) * 2 + (size_t)DEC_BM * 20;
     allow_smem(decode_kernel<32>, sm);
-    hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(DEC_NT), sm, st, a);
+    hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)((pg.P + DEC_BM - 1) / DEC_BM)), dim3(DEC_NT), sm, st, a);
     WV_HIP(hipGetLastError());
 }
 

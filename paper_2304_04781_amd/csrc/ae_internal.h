@@ -35,7 +35,10 @@ struct ExcPatches {
     const float* exc;
     const int* rng;
 };
-constexpr int DEC_BM = 128;  // patches per decode work-group
+#ifndef WV_DEC_BM
+#define WV_DEC_BM 128
+#endif
+constexpr int DEC_BM = WV_DEC_BM;  // patches per decode work-group
 // Decompress the fields in field_mask into state [4][N]; with exc, the e values of
 // its patches are the exact ones.
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,

@@ -39,7 +39,20 @@ __device__ __forceinline__ float erf_as(float x)
     return copysignf(fmaf(-y, e, 1.0f), x);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) = max(x, 0) - |x| Phi(-|x|), with Phi(-a) = erfc(a / sqrt 2) / 2 from the
+// same approximation (argument scale and the 1/2 folded into its constants)
+__device__ __forceinline__ float gelu(float x)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, ax, 1.0f));
+    float y = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    y = fmaf(y, t, 0.5f * 1.421413741f);
+    y = fmaf(y, t, 0.5f * -0.284496736f);
+    y = fmaf(y, t, 0.5f * 0.254829592f);
+    y *= t;
+    const float e = __builtin_amdgcn_exp2f(x * (x * (-0.5f * 1.4426950408889634f)));
+    return fmaf(-ax, y * e, fmaxf(x, 0.0f));
+}
 __device__ __forceinline__ float gelu_prime(float x)
 {
     return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
