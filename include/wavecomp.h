@@ -275,20 +275,29 @@ int wv_revolve_schedule(int32_t nsteps, int32_t nslots, int32_t* h_actions, int6
 int wv_stats(const wv_ctx* ctx, int64_t* h_forward_steps, double* h_guard_err, int* h_degraded);
 
 /* Kernel timing. every > 0: every every-th launch of each timed class is
- * bracketed by HIP events recorded on the stream that runs it (the context's
- * stream; in the forward sweep of the autoencoder modes the exception selection
- * runs on the context's own side stream); every = 0 switches timing off. Either
- * call clears the totals. */
+ * bracketed by HIP events recorded on the stream that runs it: the context's
+ * stream for the stencil steps; in the autoencoder modes the context's own side
+ * streams for the compression (forward sweep), the exception selection and copy
+ * (forward sweep) and the decompressions of the reverse and incremental sweeps,
+ * which run beside the stencil steps. every = 0 switches timing off. Either call
+ * clears the totals. */
 int wv_set_timing(wv_ctx* ctx, int32_t every);
 
 /* Mean duration in microseconds and number of timed launches since the last
  * wv_set_timing, for one class: 0 forward stencil step, 1 adjoint stencil step,
  * 2 incremental-forward stencil step, 3 compression of one state (all sources),
- * 4 decompression of one e field, 5 selection of the exception patches of one
- * state, 6 exception restore of one e field, 7 copy of the exception patches of
- * one state. Waits for the timed work. NULL outputs are skipped; WV_EINVAL for an
- * unknown class. */
+ * 4 decompression of one e field (with its exception patches written exactly),
+ * 5 selection of the exception patches of one state, 6 a separate exception
+ * restore (not launched: the decompression writes those patches), 7 copy of the
+ * exception patches of one state. Waits for the timed work. NULL outputs are
+ * skipped; WV_EINVAL for an unknown class. */
 int wv_kernel_time(wv_ctx* ctx, int32_t cls, double* h_mean_us, int64_t* h_count);
+
+/* Number of consecutive adjoint steps whose gradient terms e^k q^k are summed in
+ * float32 before the sum is added to the compensated (Kahan) accumulator (Sec. 2,
+ * the time integral of the gradient): the adjoint step reads and writes the
+ * float32 partial every step and the compensated pair once per block. */
+int wv_accumulation_block(void);
 
 const char* wv_last_error(void);
 const char* wv_version(void);

@@ -78,6 +78,7 @@ EXPORTS = {
     "wv_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "wv_last_error": (C.c_char_p, []),
     "wv_version": (C.c_char_p, []),
+    "wv_accumulation_block": (C.c_int, []),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -328,3 +329,7 @@ def wv_last_error() -> str:
 
 def wv_version() -> str:
     return load().wv_version().decode()
+
+
+def wv_accumulation_block() -> int:
+    return int(load().wv_accumulation_block())

@@ -172,6 +172,7 @@ struct wv_ctx {
     float* adj[2] = {nullptr, nullptr};
     float* incb[2] = {nullptr, nullptr};
     float* acc = nullptr;
+    float* blk = nullptr;        // [S][N] float32 partial gradient of a block of adjoint steps
     float* ebuf = nullptr;       // [2][S][N]: decoded e, double-buffered
     float* dm = nullptr;
     float* traces = nullptr;
@@ -324,10 +325,24 @@ void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, floa
 }
 
 // adjoint launch k: (mu^{k+2}, eta^{k+1}) -> (mu^{k+1}, eta^k), consuming e^k
+// Adjoint steps sum their gradient terms per block of WV_ACC_BLOCK consecutive
+// steps in float32 and add each block to the compensated (Kahan) pair; the phase
+// of the step at sweep position j (0 = the sweep's first step), the sweep ending at k = 1.
+#ifndef WV_ACC_BLOCK
+#define WV_ACC_BLOCK 8
+#endif
+int acc_phase(long long j, int k)
+{
+    const bool first = j % WV_ACC_BLOCK == 0, last = j % WV_ACC_BLOCK == WV_ACC_BLOCK - 1 || k == 1;
+    return first ? (last ? ACC_EACH : ACC_FIRST) : (last ? ACC_LAST : ACC_MID);
+}
+
 void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid, const float* ek,
-              long long ekstride)
+              long long ekstride, int phase)
 {
     StepArgs a = base_args(c);
+    a.blk = c->blk;
+    a.acc_phase = phase;
     a.in = in;
     a.out = out;
     a.tidx = k;
@@ -526,6 +541,7 @@ void ensure_adj(wv_ctx* c)
         c->adj[0] = dev_alloc<float>(c->state_floats());
         c->adj[1] = dev_alloc<float>(c->state_floats());
         c->acc = dev_alloc<float>(2 * c->N * c->S);
+        c->blk = dev_alloc<float>(c->N * c->S);
         c->ebuf = dev_alloc<float>(2 * c->N * c->S);
     }
 }
@@ -676,8 +692,9 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
     launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
     float* ain = c->adj[0];
     float* aout = c->adj[1];
+    long long done = 0;  // adjoint steps of this sweep so far
     auto adjoint_k = [&](int k, const float* ek, long long stride) {
-        adj_step(c, ain, aout, k, resid, ek, stride);
+        adj_step(c, ain, aout, k, resid, ek, stride, acc_phase(done++, k));
         std::swap(ain, aout);
     };
     if (!acts && is_ae(c->mode)) {
@@ -846,7 +863,7 @@ int wv_destroy(wv_ctx* c)
     dev_free(c->src_kji);
     dev_free(c->src_w);
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
-                      &c->incb[0], &c->incb[1], &c->acc, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr})
+                      &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr})
         dev_free(*p);
     dev_free(c->partial);
     dev_free(c->dscal);
@@ -1223,5 +1240,7 @@ int wv_kernel_time(wv_ctx* c, int32_t cls, double* h_mean_us, int64_t* h_count)
 
 const char* wv_last_error(void) { return g_error.c_str(); }
 const char* wv_version(void) { return "wavecomp 0.1 gfx950"; }
+
+int wv_accumulation_block(void) { return WV_ACC_BLOCK; }
 
 }  // extern "C"

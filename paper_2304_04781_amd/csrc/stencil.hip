@@ -20,6 +20,10 @@
 //   mu_a' = S_va mu_a - dt G_a(S_e eta) + B^T r^{k+1},
 //   q = D(S_v mu'),  eta' = S_e eta - dt c^2 q,  acc += e^k q.
 // so dJ/d(c^2) = -dt sum_k e^k q^k (accumulated here without the 1/dx factor).
+// The time sum is compensated (Kahan) per block of consecutive adjoint steps: the
+// terms of a block are summed in a plain float32 partial (ACC_FIRST starts it,
+// ACC_MID adds to it), and its last step (ACC_LAST) adds the partial plus its own
+// term to the compensated pair; ACC_EACH adds every term to the pair directly.
 // Incremental forward: the forward step with c^2 e replaced by c^2 de + dm e^n.
 
 #include "wv_internal.h"
@@ -86,8 +90,9 @@ __device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, u
 #define WV_PF 1
 #endif
 
-// MM: also write the per-patch (min, max) partials of the new state (forward only)
-template <int BX, int BY, int MODE, bool HAS_Y, bool MM>
+// MM: also write the per-patch (min, max) partials of the new state (forward only);
+// ACC: the adjoint's gradient accumulation phase
+template <int BX, int BY, int MODE, bool HAS_Y, bool MM, int ACC = ACC_EACH>
 __global__ void __launch_bounds__(BX* BY)
     __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_ADJ ? WV_WAVES_ADJ : WV_WAVES_OTHER)))
     wave_step_kernel(const StepArgs a)
@@ -135,6 +140,9 @@ __global__ void __launch_bounds__(BX* BY)
     const float* __restrict__ ek = (MODE == MODE_ADJ) ? a.ek + s * a.ekstride : nullptr;
     float* __restrict__ acc = (MODE == MODE_ADJ) ? a.acc + s * 2 * N : nullptr;
     float* __restrict__ cmp = (MODE == MODE_ADJ) ? acc + N : nullptr;
+    float* __restrict__ blk = (MODE == MODE_ADJ) ? a.blk + s * N : nullptr;
+    constexpr bool rd_pair = MODE == MODE_ADJ && (ACC == ACC_EACH || ACC == ACC_LAST);
+    constexpr bool rd_blk = MODE == MODE_ADJ && (ACC == ACC_MID || ACC == ACC_LAST);
 
     // layer factors: S = wz * (wy * wx), the (y, x) product fixed per column
     const int jc = in_y ? j : 0, ic = in_x ? i : 0;
@@ -236,7 +244,7 @@ __global__ void __launch_bounds__(BX* BY)
         float A, m, Vz, dm, en;
     };
     struct Pln {  // in-plane operands of one level
-        float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp;
+        float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp, blk;
     };
     // Addresses are a level base (uniform, scalar registers) plus a 32-bit byte
     // offset within the plane (a plane holds fewer than 2^30 cells).
@@ -266,8 +274,11 @@ __global__ void __launch_bounds__(BX* BY)
         q.Vxh = ld(inVx, lo, o_hx);
         if (MODE == MODE_ADJ) {
             q.ek = ld(ek, lo, o_c);
-            q.acc = ld(acc, lo, o_c);
-            q.cmp = ld(cmp, lo, o_c);
+            if (rd_pair) {
+                q.acc = ld(acc, lo, o_c);
+                q.cmp = ld(cmp, lo, o_c);
+            }
+            if (rd_blk) q.blk = ld(blk, lo, o_c);
         }
         q.rA = ld(inA, lo, o_r);
         if (MODE != MODE_ADJ) q.rm = ld(mm, lo, o_r);
@@ -330,7 +341,8 @@ __global__ void __launch_bounds__(BX* BY)
         const float Vz_nx_in = cn.Vz;
         const float Vy_in = pc.Vy, Vx_in = pc.Vx, Vy_h = pc.Vyh, Vx_h = pc.Vxh;
         const float e_k = pc.ek;
-        float s_acc = pc.acc, s_cmp = pc.cmp;
+        float s_acc = rd_pair ? pc.acc : 0.f, s_cmp = rd_pair ? pc.cmp : 0.f;
+        const float s_blk = rd_blk ? pc.blk : 0.f;
         const float Pr = P_ring(k, pc);
 
         sP[ty + 1][tx + 1] = P_cur;
@@ -380,11 +392,18 @@ __global__ void __launch_bounds__(BX* BY)
         float A_new;
         if (MODE == MODE_ADJ) {
             A_new = Se * A_cur - a.dtdx * m_cur * dsum;
-            // Kahan: s_acc += e_k * dsum
-            const float y = e_k * dsum - s_cmp;
-            const float t = s_acc + y;
-            s_cmp = (t - s_acc) - y;
-            s_acc = t;
+            // the term of this step, plus the block's partial on its last step
+            float term = e_k * dsum;
+            if (ACC == ACC_MID || ACC == ACC_LAST) term = s_blk + term;
+            if (ACC == ACC_EACH || ACC == ACC_LAST) {
+                // Kahan: s_acc += term
+                const float y = term - s_cmp;
+                const float t = s_acc + y;
+                s_cmp = (t - s_acc) - y;
+                s_acc = t;
+            } else {
+                s_acc = term;  // the block partial
+            }
         } else {
             A_new = Se * (A_cur + a.dtdx * dsum);
         }
@@ -401,8 +420,12 @@ __global__ void __launch_bounds__(BX* BY)
             st_plane(Vx_new, outVx + lk, pb4, o_c);
 #endif
             if (MODE == MODE_ADJ) {
-                st_plane(s_acc, acc + lk, pb4, o_c);
-                st_plane(s_cmp, cmp + lk, pb4, o_c);
+                if (ACC == ACC_EACH || ACC == ACC_LAST) {
+                    st_plane(s_acc, acc + lk, pb4, o_c);
+                    st_plane(s_cmp, cmp + lk, pb4, o_c);
+                } else {
+                    st_plane(s_acc, blk + lk, pb4, o_c);
+                }
             }
         }
         if constexpr (want_mm) {
@@ -494,7 +517,14 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
         else
             hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, false>), grid, block, 0, st, a);
         break;
-    case MODE_ADJ: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false>), grid, block, 0, st, a); break;
+    case MODE_ADJ:
+        switch (a.acc_phase) {
+        case ACC_FIRST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_FIRST>), grid, block, 0, st, a); break;
+        case ACC_MID: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_MID>), grid, block, 0, st, a); break;
+        case ACC_LAST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_LAST>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_EACH>), grid, block, 0, st, a); break;
+        }
+        break;
     default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false>), grid, block, 0, st, a); break;
     }
 }

@@ -35,6 +35,8 @@ struct Error {
 // ---- stencil -----------------------------------------------------------------------
 
 enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2 };
+// gradient accumulation phase of an adjoint step within its block of steps
+enum AccPhase { ACC_EACH = 0, ACC_FIRST = 1, ACC_MID = 2, ACC_LAST = 3 };
 
 // Tiling of the (y, x) plane and of z into chunks, plus the receiver list
 // bucketed per (y, x) tile and sorted by depth.
@@ -74,6 +76,8 @@ struct StepArgs {
     const float* ek;       // [S][ekstride]
     long long ekstride;
     float* acc;            // [S][2][N]: sum, compensation
+    float* blk;            // [S][N]: float32 partial of the current block of steps
+    int acc_phase;         // AccPhase of this step
     // incremental forward: dm and forward e^n
     const float* dm;
     const float* en;

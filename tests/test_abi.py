@@ -73,3 +73,16 @@ def test_invalid_arguments_are_reported_on_host():
         L.wv_revolve_schedule(0, 4)
     assert e.value.code == -1
     assert "nsteps" in L.wv_last_error()
+
+
+def test_accumulation_block_and_adjoint_bytes():
+    """The adjoint's gradient sum is compensated per block of steps; the bench's
+    algorithmic bytes per cell follow the phases of those blocks."""
+    import bench
+    L.load()
+    B = L.wv_accumulation_block()
+    assert 1 <= B <= 64
+    assert bench.adjoint_bytes_per_cell(2000, 1) == 56.0          # the pair read and written every step
+    # 11 steps in blocks of 8: first 44, 6 middle 48, last 60; then 44, 48, 60
+    assert abs(bench.adjoint_bytes_per_cell(12, 8) - (44 + 6 * 48 + 60 + 44 + 48 + 60) / 11) < 1e-12
+    assert bench.adjoint_bytes_per_cell(2, 8) == 56.0             # a single step is its own block
