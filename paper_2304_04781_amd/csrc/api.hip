@@ -150,6 +150,9 @@ enum {
 
 using namespace wv;
 
+// decoded-e slots: the decode of a state runs up to NEB - 1 steps ahead of its use
+constexpr int NEB = 3;
+
 struct wv_ctx {
     KernelTimer tm;
     wv_grid g{};
@@ -173,7 +176,7 @@ struct wv_ctx {
     float* incb[2] = {nullptr, nullptr};
     float* acc = nullptr;
     float* blk = nullptr;        // [S][N] float32 partial gradient of a block of adjoint steps
-    float* ebuf = nullptr;       // [2][S][N]: decoded e, double-buffered
+    float* ebuf = nullptr;       // [NEB][S][N]: decoded e, one slot per state in flight
     float* dm = nullptr;
     float* traces = nullptr;
     float* resid = nullptr;
@@ -212,8 +215,8 @@ struct wv_ctx {
     hipEvent_t ev_step[3] = {};    // main: x_j written (j mod 3)
     hipEvent_t ev_enc[3] = {};     // side: x_j encoded
     hipEvent_t ev_stored[3] = {};  // x_j fully stored: its buffer and mmpart slot are free
-    hipEvent_t ev_ready[2] = {};   // side: e^k decoded into ebuf slot
-    hipEvent_t ev_free[2] = {};    // main: ebuf slot consumed
+    hipEvent_t ev_ready[NEB] = {};  // side: e^k decoded into ebuf slot
+    hipEvent_t ev_free[NEB] = {};   // main: ebuf slot consumed
     hipEvent_t ev_join = nullptr;
     long long P = 0;
     long long lat_bytes = 0;     // per patch
@@ -476,6 +479,16 @@ void store_state(wv_ctx* c, int n, const float* state)
     }
 }
 
+// Make stream st wait for event ev, unless the host already sees it complete
+// (then the wait packet, which costs the stream a few microseconds, is skipped).
+void wait_event(hipStream_t st, hipEvent_t ev)
+{
+    const hipError_t q = hipEventQuery(ev);
+    if (q == hipSuccess) return;
+    if (q != hipErrorNotReady) WV_HIP(q);
+    WV_HIP(hipStreamWaitEvent(st, ev, 0));
+}
+
 // 1: autoencoder stores and decodes run on the side streams, beside the stencil
 // steps; 2: only the exception selection and copy do; 0: everything on the main
 // stream in order
@@ -497,7 +510,7 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
     const int b = j % 3;
     hipStream_t s1 = side_stream(c, 0), s2 = side_stream(c, 1);
     WV_HIP(hipEventRecord(c->ev_step[b], c->st));
-    WV_HIP(hipStreamWaitEvent(s1, c->ev_step[b], 0));
+    wait_event(s1, c->ev_step[b]);
     const int te = c->tm.begin(TM_ENCODE, s1);
     for (int s = 0; s < c->S; ++s)
         ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
@@ -509,7 +522,7 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
         return;
     }
     WV_HIP(hipEventRecord(c->ev_enc[b], s1));
-    WV_HIP(hipStreamWaitEvent(s2, c->ev_enc[b], 0));
+    wait_event(s2, c->ev_enc[b]);
     const int tx = c->tm.begin(TM_EXC_SELECT, s2);
     for (int s = 0; s < c->S; ++s) {
         const long long q = (long long)(j - 1) * c->S + s;
@@ -542,7 +555,7 @@ void ensure_adj(wv_ctx* c)
         c->adj[1] = dev_alloc<float>(c->state_floats());
         c->acc = dev_alloc<float>(2 * c->N * c->S);
         c->blk = dev_alloc<float>(c->N * c->S);
-        c->ebuf = dev_alloc<float>(2 * c->N * c->S);
+        c->ebuf = dev_alloc<float>(NEB * c->N * c->S);
     }
 }
 
@@ -579,25 +592,25 @@ const float* load_e(wv_ctx* c, int n, long long* stride)
 }
 
 // Decode pipeline of the sweeps that read the AE store (adjoint, incremental
-// forward): e^n is decoded on `side` into one ebuf slot while the main stream
-// steps with the other. pipe_start marks both slots free; pipe_issue queues the
-// decode of e^n into slot b once its last reader is done; pipe_take makes the
-// main stream wait for it; pipe_release marks slot b read.
+// forward): e^n is decoded on `side` into slot n % NEB up to NEB - 1 steps before
+// the main stream's step reads it. pipe_start marks all slots free; pipe_issue
+// queues the decode of e^n once the slot's last reader is done; pipe_take makes
+// the main stream wait for it; pipe_release marks the slot read.
 void pipe_start(wv_ctx* c)
 {
     ensure_adj(c);
-    for (int b = 0; b < 2; ++b) WV_HIP(hipEventRecord(c->ev_free[b], c->st));
+    for (int b = 0; b < NEB; ++b) WV_HIP(hipEventRecord(c->ev_free[b], c->st));
 }
 void pipe_issue(wv_ctx* c, int n, int b)
 {
     hipStream_t s1 = side_stream(c, 0);
-    WV_HIP(hipStreamWaitEvent(s1, c->ev_free[b], 0));
+    wait_event(s1, c->ev_free[b]);
     decode_e(c, n, b, s1);
     WV_HIP(hipEventRecord(c->ev_ready[b], s1));
 }
 const float* pipe_take(wv_ctx* c, int b)
 {
-    WV_HIP(hipStreamWaitEvent(c->st, c->ev_ready[b], 0));
+    wait_event(c->st, c->ev_ready[b]);
     return ebuf_slot(c, b);
 }
 void pipe_release(wv_ctx* c, int b) { WV_HIP(hipEventRecord(c->ev_free[b], c->st)); }
@@ -625,7 +638,7 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
         if (ae) {
             out = c->work[j % 3];
             // the buffer and min/max slot held x_{j-3}: its store must be done
-            if (j - 3 >= 1 && j - 3 <= c->T - 1) WV_HIP(hipStreamWaitEvent(c->st, c->ev_stored[j % 3], 0));
+            if (j - 3 >= 1 && j - 3 <= c->T - 1) wait_event(c->st, c->ev_stored[j % 3]);
         } else {
             out = (snap && (*snap)[j] > 0) ? c->slot_ptr((*snap)[j]) : other_work(c, cur);
         }
@@ -698,14 +711,13 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
         std::swap(ain, aout);
     };
     if (!acts && is_ae(c->mode)) {
-        // e^{k-1} is decoded beside the adjoint step k
+        // e^{k-2} is decoded beside the adjoint steps k and k - 1
         pipe_start(c);
-        if (c->T - 1 >= 1) pipe_issue(c, c->T - 1, 0);
+        for (int n = c->T - 1; n >= std::max(1, c->T - NEB + 1); --n) pipe_issue(c, n, n % NEB);
         for (int k = c->T - 1; k >= 1; --k) {
-            const int b = (c->T - 1 - k) & 1;
-            if (k - 1 >= 1) pipe_issue(c, k - 1, b ^ 1);
-            adjoint_k(k, pipe_take(c, b), c->N);
-            pipe_release(c, b);
+            if (k - NEB + 1 >= 1) pipe_issue(c, k - NEB + 1, (k - NEB + 1) % NEB);
+            adjoint_k(k, pipe_take(c, k % NEB), c->N);
+            pipe_release(c, k % NEB);
         }
         return;
     }
@@ -831,7 +843,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
             WV_HIP(hipEventCreateWithFlags(&c->ev_enc[b], hipEventDisableTiming));
             WV_HIP(hipEventCreateWithFlags(&c->ev_stored[b], hipEventDisableTiming));
         }
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NEB; ++b) {
             WV_HIP(hipEventCreateWithFlags(&c->ev_ready[b], hipEventDisableTiming));
             WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
         }
@@ -854,9 +866,12 @@ int wv_destroy(wv_ctx* c)
     free_store(c);
     free_tiling(c->tl);
     for (hipEvent_t e : {c->ev_step[0], c->ev_step[1], c->ev_step[2], c->ev_enc[0], c->ev_enc[1], c->ev_enc[2],
-                         c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_ready[0], c->ev_ready[1],
-                         c->ev_free[0], c->ev_free[1], c->ev_join})
+                         c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_join})
         if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < NEB; ++b) {
+        if (c->ev_ready[b]) (void)hipEventDestroy(c->ev_ready[b]);
+        if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
+    }
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->side2) (void)hipStreamDestroy(c->side2);
     dev_free(c->tab);
@@ -1099,9 +1114,11 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
             en = cur;
             stride = 4 * c->N;
         } else if (pipe) {
-            // e^{n+1} is decoded beside the step n; slot n & 1 holds e^n
-            if (n + 1 <= c->T - 1) pipe_issue(c, n + 1, (n + 1) & 1);
-            en = n == 0 ? ebuf_slot(c, 0) : pipe_take(c, n & 1);
+            // e^{n+2} is decoded beside the steps n and n + 1; slot n % NEB holds e^n
+            if (n == 0)
+                for (int q = 1; q < NEB - 1 && q <= c->T - 1; ++q) pipe_issue(c, q, q % NEB);
+            if (n + NEB - 1 <= c->T - 1) pipe_issue(c, n + NEB - 1, (n + NEB - 1) % NEB);
+            en = n == 0 ? ebuf_slot(c, 0) : pipe_take(c, n % NEB);
             stride = c->N;
         } else if (n == 0) {
             en = ebuf_slot(c, 0);  // e^0 = 0
@@ -1110,7 +1127,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
             en = load_e(c, n, &stride);
         }
         inc_step(c, din, dout, n, en, stride, c->dtr);
-        if (pipe) pipe_release(c, n & 1);
+        if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
         if (ckpt) {
             float* out = (*snap)[n + 1] > 0 ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
