@@ -221,6 +221,28 @@ def main():
     ck_bytes = ck.storage_bytes()
     log(f"checkpointed gradient {t_ck:.3f} s, {fsteps} forward steps; kernel times {kt_ck}")
 
+    # ---- Gauss-Newton Hv at the same model: the AE path decodes the stored states, the
+    # checkpointed path recomputes the forward alongside the incremental forward and in
+    # the revolve reverse sweep (direction: c times a GRF of correlation length 12 cells)
+    dc = c0 * torch.tensor(0.01 * W.direction_grf((p.nz, p.ny, p.nx), 12.0, seed=2), dtype=torch.float32,
+                           device=dev)
+    hv = {}
+    for name, sol in (("ae", ae_solver), ("checkpoint", ck)):  # both hold the last gradient's c0
+        torch.cuda.synchronize()
+        ev0.record()
+        Hv = sol.hessvec(c0, dc)
+        ev1.record()
+        torch.cuda.synchronize()
+        hv[name] = (ev0.elapsed_time(ev1) / 1e3, Hv.double())
+    h_ae, h_ck = hv["ae"][1], hv["checkpoint"][1]
+    hessvec = {"ae_s": round(hv["ae"][0], 4), "checkpoint_s": round(hv["checkpoint"][0], 4),
+               "speedup_vs_checkpoint": round(hv["checkpoint"][0] / hv["ae"][0], 4),
+               "rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(h_ae - h_ck) / torch.linalg.norm(h_ck)), 5),
+               "cos_vs_checkpoint_fp32": round(float(torch.sum(h_ae * h_ck) / (torch.linalg.norm(h_ae) *
+                                                                              torch.linalg.norm(h_ck))), 6)}
+    del h_ae, h_ck, hv, dc
+    log(f"GN Hv: {hessvec}")
+
     ga = g_ae.double()
     gc = g_ck.double()
     rel_err = float(torch.linalg.norm(ga - gc) / torch.linalg.norm(gc))
@@ -295,6 +317,7 @@ def main():
         "checkpoint": {"gradients_per_hour": round(3600.0 / t_ck, 1), "ms_per_gradient": round(t_ck * 1e3, 2),
                        "forward_steps": fsteps, "store_GB": round(ck_bytes / 1e9, 2)},
         "speedup_vs_checkpoint": round(t_ck / t_ae, 4),
+        "gn_hessvec": hessvec,
         "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
         "grad_cos_vs_checkpoint_fp32": round(cos, 6),
         "misfit": {"ae": J_ae, "checkpoint": J_ck},
