@@ -151,7 +151,27 @@ int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
  * wv_set_storage. */
 int wv_set_ae_exceptions(wv_ctx* ctx, int32_t k_per_step);
 
-/* Bytes of history storage the current mode holds (after wv_set_storage). */
+/* Compression of the incremental forward states (AE modes). The paper notes
+ * that the incremental forward states can be compressed as well (Sec. 4); the
+ * 384^3 Hessian-vector configuration stores both histories. With enable = 1,
+ * every hessvec / wave_inc_forward of an AE mode also compresses each incremental
+ * state dx_n (n = 1..T-1, every source, all four fields) through the same
+ * autoencoder into a second latent store of the same format, with its own
+ * exception patches; it is allocated at the first such call, within the memory
+ * budget together with the forward store (WV_ENOMEM beyond it). The Gauss-Newton
+ * product itself does not read these states (wv_decode_delta returns them).
+ * enable = 0 frees the store. Other modes ignore the setting. */
+int wv_set_delta_storage(wv_ctx* ctx, int32_t enable);
+
+/* Decompress the stored incremental state dx_n (1 <= n <= T-1) of every source
+ * into state [S][4][N] (device): the fields whose bit is set in field_mask (bit f
+ * = field f: e, v_z, v_y, v_x; others untouched), the exception patches of e
+ * exact. WV_ESTATE when the last incremental forward stored none (or a forward
+ * solve ran since); WV_EINVAL for a bad mask or NULL state. */
+int wv_decode_delta(wv_ctx* ctx, int32_t n, uint32_t field_mask, float* state);
+
+/* Bytes of history storage the current mode holds (after wv_set_storage), plus
+ * the incremental store once allocated. */
 int wv_storage_bytes(const wv_ctx* ctx, int64_t* h_bytes);
 
 /* ---- wave solves (paper Sec. 2; Sec. 1 and 4 for the adjoint solves) ------------- */

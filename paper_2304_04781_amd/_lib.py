@@ -79,6 +79,8 @@ EXPORTS = {
     "wv_last_error": (C.c_char_p, []),
     "wv_version": (C.c_char_p, []),
     "wv_accumulation_block": (C.c_int, []),
+    "wv_set_delta_storage": (C.c_int, [C.c_void_p, C.c_int32]),
+    "wv_decode_delta": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -333,3 +335,11 @@ def wv_version() -> str:
 
 def wv_accumulation_block() -> int:
     return int(load().wv_accumulation_block())
+
+
+def wv_set_delta_storage(ctx, enable: bool) -> int:
+    return _check(load().wv_set_delta_storage(ctx, 1 if enable else 0))
+
+
+def wv_decode_delta(ctx, n: int, field_mask: int, state) -> int:
+    return _check(load().wv_decode_delta(ctx, int(n), int(field_mask), ptr(state)))

@@ -153,6 +153,17 @@ using namespace wv;
 // decoded-e slots: the decode of a state runs up to NEB - 1 steps ahead of its use
 constexpr int NEB = 3;
 
+// Latent store of the states x_1 .. x_{T-1} of every source (AE modes): latents,
+// per-patch metadata, FP8 scales and the exact e values of the exception patches
+struct LatStore {
+    uint8_t* lat = nullptr;   // [T-1][S][P][L]
+    float* meta = nullptr;    // [T-1][S][P][4][2]
+    float* qs = nullptr;      // [T-1][S][P]
+    int* exc_idx = nullptr;   // [T-1][S][K]
+    float* exc = nullptr;     // [T-1][S][K][512]
+    int* exc_rng = nullptr;   // [T-1][S][nbd + 1]: exceptions per decode work-group
+};
+
 struct wv_ctx {
     KernelTimer tm;
     wv_grid g{};
@@ -195,14 +206,13 @@ struct wv_ctx {
     int fallback = WV_FALLBACK_NONE;
     float* slots = nullptr;      // checkpoint slots 1..nslots-1
     float* ehist = nullptr;      // full storage of e^1..e^{T-1}
-    uint8_t* lat = nullptr;      // AE latents [T-1][S][P][L]
-    float* meta = nullptr;       // [T-1][S][P][4][2]
-    float* qs = nullptr;         // [T-1][S][P]
+    LatStore fs;                 // AE store of the forward states
+    LatStore ds;                 // AE store of the incremental forward states (optional)
+    bool store_delta = false;    // compress the incremental states in the AE modes
+    bool delta_ok = false;       // ds holds the incremental states of the last incremental forward
+    int64_t delta_bytes = 0;
     int exc_req = 0;             // requested exception patches per state
     int K = 0;                   // active exception patches per state
-    int* exc_idx = nullptr;      // [T-1][S][K]
-    float* exc = nullptr;        // [T-1][S][K][512]
-    int* exc_rng = nullptr;      // [T-1][S][nbd + 1]: exceptions per decode work-group
     int nbd = 0;                 // decode work-groups per state
     float* mmpart = nullptr;     // [3][S][P][H][4][2] (min, max) partials of the forward step
     int H = 1;                   // y sub-tiles per patch
@@ -384,16 +394,24 @@ void ensure_inc(wv_ctx* c)
     }
 }
 
+void free_latstore(LatStore& L)
+{
+    dev_free(L.lat);
+    dev_free(L.meta);
+    dev_free(L.qs);
+    dev_free(L.exc_idx);
+    dev_free(L.exc);
+    dev_free(L.exc_rng);
+}
+
 void free_store(wv_ctx* c)
 {
     dev_free(c->slots);
     dev_free(c->ehist);
-    dev_free(c->lat);
-    dev_free(c->meta);
-    dev_free(c->qs);
-    dev_free(c->exc_idx);
-    dev_free(c->exc);
-    dev_free(c->exc_rng);
+    free_latstore(c->fs);
+    free_latstore(c->ds);
+    c->delta_ok = false;
+    c->delta_bytes = 0;
     dev_free(c->mmpart);
     dev_free(c->work[2]);
     c->K = 0;
@@ -439,20 +457,42 @@ bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP
 int ae_fmt(int mode) { return mode == WV_STORE_AE_FP8 ? AE_LATENT_FP8 : AE_LATENT_BF16; }
 
 
-uint8_t* lat_slot(wv_ctx* c, int idx, int s)
+uint8_t* lat_slot(wv_ctx* c, const LatStore& L, int idx, int s)
 {
-    return c->lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
+    return L.lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
 }
-float* meta_slot(wv_ctx* c, int idx, int s) { return c->meta + ((long long)idx * c->S + s) * c->P * 8; }
-int* rng_slot(wv_ctx* c, long long q) { return c->exc_rng + q * (c->nbd + 1); }
-float* qs_slot(wv_ctx* c, int idx, int s)
+float* meta_slot(wv_ctx* c, const LatStore& L, int idx, int s) { return L.meta + ((long long)idx * c->S + s) * c->P * 8; }
+int* rng_slot(wv_ctx* c, const LatStore& L, long long q) { return L.exc_rng + q * (c->nbd + 1); }
+float* qs_slot(wv_ctx* c, const LatStore& L, int idx, int s)
 {
-    return c->qs ? c->qs + ((long long)idx * c->S + s) * c->P : nullptr;
+    return L.qs ? L.qs + ((long long)idx * c->S + s) * c->P : nullptr;
+}
+
+// bytes of one latent store for the current mode and exception count
+long long latstore_bytes(wv_ctx* c, int mode, int K)
+{
+    const long long slots = (long long)std::max(c->T - 1, 1) * c->S;
+    const long long nbd = (c->P + DEC_BM - 1) / DEC_BM;
+    return slots * (c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0)) + (long long)K * (512 * 4 + 4) +
+                    (K > 0 ? (nbd + 1) * 4 : 0));
+}
+
+void alloc_latstore(wv_ctx* c, LatStore& L, int mode, int K)
+{
+    const long long slots = (long long)std::max(c->T - 1, 1) * c->S;
+    L.lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
+    L.meta = dev_alloc<float>(slots * c->P * 8);
+    if (mode == WV_STORE_AE_FP8) L.qs = dev_alloc<float>(slots * c->P);
+    if (K > 0) {
+        L.exc_idx = dev_alloc<int>(slots * K);
+        L.exc = dev_alloc<float>(slots * K * 512);
+        L.exc_rng = dev_alloc<int>(slots * (c->nbd + 1));
+    }
 }
 
 // store x_n (n = 1..T-1) of every source on the main stream (full storage, or
-// an autoencoder store without the forward step's min/max)
-void store_state(wv_ctx* c, int n, const float* state)
+// the autoencoder store L without the forward step's min/max)
+void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
 {
     if (n < 1 || n > c->T - 1) return;
     if (c->mode == WV_STORE_FULL) {
@@ -463,16 +503,16 @@ void store_state(wv_ctx* c, int n, const float* state)
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
         const int te = c->tm.begin(TM_ENCODE, c->st);
         for (int s = 0; s < c->S; ++s)
-            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, n - 1, s),
-                            meta_slot(c, n - 1, s), qs_slot(c, n - 1, s), c->st);
+            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
+                            meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), c->st);
         c->tm.end(te, c->st);
         if (c->K > 0) {
             const int tx = c->tm.begin(TM_EXC_SELECT, c->st);
             for (int s = 0; s < c->S; ++s) {
                 const long long q = (long long)(n - 1) * c->S + s;
-                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, n - 1, s), c->K, c->exc_idx + q * c->K,
-                                 c->exc + q * c->K * 512, c->st);
-                exceptions_ranges(pg, c->K, c->exc_idx + q * c->K, DEC_BM, rng_slot(c, q), c->st);
+                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, L, n - 1, s), c->K, L.exc_idx + q * c->K,
+                                 L.exc + q * c->K * 512, c->st);
+                exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), c->st);
             }
             c->tm.end(tx, c->st);
         }
@@ -514,8 +554,8 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
     const int te = c->tm.begin(TM_ENCODE, s1);
     for (int s = 0; s < c->S; ++s)
         ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
-                           ae_fmt(c->mode), lat_slot(c, j - 1, s), meta_slot(c, j - 1, s), qs_slot(c, j - 1, s),
-                           s1);
+                           ae_fmt(c->mode), lat_slot(c, c->fs, j - 1, s), meta_slot(c, c->fs, j - 1, s),
+                           qs_slot(c, c->fs, j - 1, s), s1);
     c->tm.end(te, s1);
     if (c->K <= 0) {
         WV_HIP(hipEventRecord(c->ev_stored[b], s1));
@@ -526,14 +566,15 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
     const int tx = c->tm.begin(TM_EXC_SELECT, s2);
     for (int s = 0; s < c->S; ++s) {
         const long long q = (long long)(j - 1) * c->S + s;
-        exceptions_select(pg, meta_slot(c, j - 1, s), c->K, c->exc_idx + q * c->K, s2);
-        exceptions_ranges(pg, c->K, c->exc_idx + q * c->K, DEC_BM, rng_slot(c, q), s2);
+        exceptions_select(pg, meta_slot(c, c->fs, j - 1, s), c->K, c->fs.exc_idx + q * c->K, s2);
+        exceptions_ranges(pg, c->K, c->fs.exc_idx + q * c->K, DEC_BM, rng_slot(c, c->fs, q), s2);
     }
     c->tm.end(tx, s2);
     const int tg = c->tm.begin(TM_EXC_GATHER, s2);
     for (int s = 0; s < c->S; ++s) {
         const long long q = (long long)(j - 1) * c->S + s;
-        exceptions_gather(pg, state + s * 4 * c->N, c->K, c->exc_idx + q * c->K, c->exc + q * c->K * 512, s2);
+        exceptions_gather(pg, state + s * 4 * c->N, c->K, c->fs.exc_idx + q * c->K, c->fs.exc + q * c->K * 512,
+                          s2);
     }
     c->tm.end(tg, s2);
     WV_HIP(hipEventRecord(c->ev_stored[b], s2));
@@ -562,22 +603,27 @@ void ensure_adj(wv_ctx* c)
 // e^n of every source from the FULL or AE store: pointer + per-source stride
 float* ebuf_slot(wv_ctx* c, int b) { return c->ebuf + (long long)b * c->S * c->N; }
 
-// decode e^n of every source from the AE store into ebuf slot b on stream st
-void decode_e(wv_ctx* c, int n, int b, hipStream_t st)
+// decode the fields in mask of stored state n of every source from the AE store L
+// into out (per-source stride `stride` floats; field f at + f N) on stream st
+void decode_state(wv_ctx* c, const LatStore& L, int n, uint32_t mask, float* out, long long stride,
+                  hipStream_t st)
 {
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-    float* e = ebuf_slot(c, b);
     for (int s = 0; s < c->S; ++s) {
-        // the exception patches are written with their exact values by the decode
+        // the exception patches of e are written with their exact values by the decode
         const long long q = (long long)(n - 1) * c->S + s;
-        const ExcPatches ex{c->exc_idx + q * c->K, c->K, c->exc + q * c->K * 512, c->K > 0 ? rng_slot(c, q) : nullptr};
+        const ExcPatches ex{L.exc_idx + q * c->K, c->K, L.exc + q * c->K * 512,
+                            c->K > 0 ? rng_slot(c, L, q) : nullptr};
         const int td = c->tm.begin(TM_DECODE, st);
-        ae_decode_state(c->ae, pg, lat_slot(c, n - 1, s), meta_slot(c, n - 1, s), qs_slot(c, n - 1, s),
-                        ae_fmt(c->mode), 1u, e + s * c->N, st, c->K > 0 ? &ex : nullptr);
+        ae_decode_state(c->ae, pg, lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s),
+                        ae_fmt(c->mode), mask, out + s * stride, st, c->K > 0 ? &ex : nullptr);
         c->tm.end(td, st);
     }
 }
+
+// decode e^n of every source from the forward AE store into ebuf slot b on stream st
+void decode_e(wv_ctx* c, int n, int b, hipStream_t st) { decode_state(c, c->fs, n, 1u, ebuf_slot(c, b), c->N, st); }
 
 // e^n of every source from the FULL or AE store (decoded on the main stream into
 // ebuf slot 0): pointer + per-source stride
@@ -623,6 +669,7 @@ float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->w
 float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, float* capture, int every,
                      float** last)
 {
+    c->delta_ok = false;  // incremental states belong to the previous forward history
     // autoencoder stores run beside the steps (x_j in work[j % 3])
     const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
     if (ae && !c->work[2]) c->work[2] = dev_alloc<float>(c->state_floats());
@@ -648,7 +695,7 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
             if (ae)
                 store_state_async(c, j, out, mm);
             else
-                store_state(c, j, out);
+                store_state(c, c->fs, j, out);
         }
         if (ncap > 0 && j % every == 0 && j / every <= ncap)
             WV_HIP(hipMemcpyAsync(capture + (long long)(j / every - 1) * c->state_floats(), out,
@@ -922,23 +969,11 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
             c->P = pg.P;
             c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
-            const long long slots = (long long)std::max(T - 1, 1) * c->S;
             const int K = (int)std::min<long long>(c->exc_req, c->P);
-            const long long nbd = (c->P + DEC_BM - 1) / DEC_BM;
-            const long long bytes = slots * (c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0)) +
-                                             (long long)K * (512 * 4 + 4) + (K > 0 ? (nbd + 1) * 4 : 0));
+            c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
+            const long long bytes = latstore_bytes(c, mode, K);
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
-            c->lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
-            c->meta = dev_alloc<float>(slots * c->P * 8);
-            if (mode == WV_STORE_AE_FP8) c->qs = dev_alloc<float>(slots * c->P);
-            if (K > 0) {
-                c->exc_idx = dev_alloc<int>(slots * K);
-                WV_HIP(hipMemset(c->exc_idx, 0, sizeof(int) * slots * K));
-                c->exc = dev_alloc<float>(slots * K * 512);
-                c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
-                c->exc_rng = dev_alloc<int>(slots * (c->nbd + 1));
-                WV_HIP(hipMemset(c->exc_rng, 0, sizeof(int) * slots * (c->nbd + 1)));
-            }
+            alloc_latstore(c, c->fs, mode, K);
             c->K = K;
             c->H = 8 / c->tl.by;
             c->mmpart = dev_alloc<float>((size_t)3 * c->S * c->P * c->H * 8);
@@ -980,13 +1015,38 @@ int wv_set_ae_exceptions(wv_ctx* c, int32_t k_per_step)
     return WV_OK;
 }
 
+int wv_set_delta_storage(wv_ctx* c, int32_t enable)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && (enable == 0 || enable == 1), WV_EINVAL, "bad argument");
+        WV_HIP(hipStreamSynchronize(c->st));
+        c->store_delta = enable == 1;
+        if (!c->store_delta) {
+            free_latstore(c->ds);
+            c->delta_bytes = 0;
+            c->delta_ok = false;
+        }
+        return WV_OK;
+    });
+}
+
+int wv_decode_delta(wv_ctx* c, int32_t n, uint32_t field_mask, float* state)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && state && field_mask != 0 && field_mask < 16, WV_EINVAL, "bad argument");
+        WV_REQUIRE(is_ae(c->mode) && c->delta_ok, WV_ESTATE, "no incremental states stored");
+        decode_state(c, c->ds, n, field_mask, state, 4 * c->N, c->st);
+        return WV_OK;
+    });
+}
+
 int wv_storage_bytes(const wv_ctx* c, int64_t* h_bytes)
 {
     if (!c || !h_bytes) {
         set_error("null argument");
         return WV_EINVAL;
     }
-    *h_bytes = c->store_bytes;
+    *h_bytes = c->store_bytes + c->delta_bytes;
     return WV_OK;
 }
 
@@ -1096,6 +1156,16 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
     launch_dm(cdev, dc, c->dm, c->N, c->st);
     launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
     const bool pipe = !snap && is_ae(c->mode);
+    // optional AE store of the incremental states dx_1 .. dx_{T-1} (same network and format)
+    const bool keep_delta = pipe && c->store_delta;
+    c->delta_ok = false;
+    if (keep_delta && !c->ds.lat) {
+        const long long bytes = latstore_bytes(c, c->mode, c->K);
+        WV_REQUIRE(c->budget <= 0 || c->store_bytes + bytes <= c->budget, WV_ENOMEM,
+                   "incremental latent store exceeds the memory budget");
+        alloc_latstore(c, c->ds, c->mode, c->K);
+        c->delta_bytes = bytes;
+    }
     if (pipe) pipe_start(c);
     launch_fill(ebuf_slot(c, 0), c->N * c->S, 0.f, c->st);  // e^0 = 0
     float* din = c->incb[0];
@@ -1129,6 +1199,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         inc_step(c, din, dout, n, en, stride, c->dtr);
         if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
+        if (keep_delta) store_state(c, c->ds, n + 1, din);  // dx_{n+1}, read again only by the step after next
         if (ckpt) {
             float* out = (*snap)[n + 1] > 0 ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
             fwd_step(c, cur, out, n, nullptr);
@@ -1137,6 +1208,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         }
     }
     if (ckpt) c->last_fwd_steps = c->T;
+    if (keep_delta) c->delta_ok = true;
     return prev;
 }
 

@@ -66,6 +66,16 @@ class WaveSolver:
     def stats(self):
         return L.wv_stats(self.ctx)
 
+    def set_delta_storage(self, enable: bool = True) -> None:
+        """Also compress the incremental forward states (AE modes) in hessvec / inc_forward."""
+        L.wv_set_delta_storage(self.ctx, enable)
+
+    def decode_delta(self, n: int, field_mask: int = 0xF):
+        """Stored incremental state dx_n [S, 4, nz, ny, nx] (fields outside the mask zero)."""
+        out = torch.zeros((self.S, 4) + self.shape, dtype=torch.float32, device=self.device)
+        L.wv_decode_delta(self.ctx, n, field_mask, out)
+        return out
+
     def set_timing(self, every: int) -> None:
         """Time every `every`-th launch of each kernel class with HIP events (0: off)."""
         L.wv_set_timing(self.ctx, every)

@@ -268,6 +268,44 @@ def test_all_patches_exact_reproduces_full_storage():
         assert e2 < e3
 
 
+def test_incremental_states_stored_and_decoded():
+    """Optional AE store of the incremental forward states (the 384^3 Hv
+    configuration keeps both histories). With every patch exact (K = P) the
+    decoded e of dx_n equals the oracle's incremental e to float32 accuracy;
+    storing them leaves the Hv unchanged bit for bit and adds a second store of
+    the same size; a new forward solve makes them unavailable."""
+    p = ae_problem(nt=60, shape=(32, 32, 40))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    P = 4 * 4 * 5
+    dc = np.asarray(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2), np.float32).astype(np.float64)
+    Hs, bytes_ = [], []
+    for keep in (False, True):
+        s = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s.ctx, P)
+        s.set_storage(L.STORE_AE_BF16, ae=raw)
+        s.set_delta_storage(keep)
+        s.gradient(p.c_start, p.wavelet, d, sigma)
+        b0 = s.storage_bytes()
+        Hs.append(s.hessvec(p.c_start, dc))
+        bytes_.append((b0, s.storage_bytes()))
+    assert torch.equal(Hs[0], Hs[1])
+    assert bytes_[0][1] == bytes_[0][0] and bytes_[1][1] == 2 * bytes_[1][0]
+    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, src_w=p.src_w)
+    _, de_hist = ow.inc_forward(sol, p.c_start, dc, e_hist[0], p.rec, store_e=True)
+    assert not s.decode_delta(1, 1)[0, 0].any()          # dx_1 = 0 (the source dm e^0 vanishes)
+    for n in (p.nt // 3, p.nt // 2, p.nt - 1):
+        de = s.decode_delta(n, 1)[0, 0].cpu().numpy()
+        assert np.linalg.norm(de_hist[n]) > 0
+        print("dx", n, rel(de, de_hist[n]), flush=True)
+        assert rel(de, de_hist[n]) < 1e-5
+    assert bool(torch.isfinite(s.decode_delta(p.nt - 1)).all())
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    with pytest.raises(L.WvError):
+        s.decode_delta(1)
+
+
 def test_guard_falls_back_to_checkpointing():
     p = ae_problem(nt=120, shape=(32, 32, 32))
     sol = ow.solver_for(p)

@@ -176,6 +176,15 @@ def test_gn_hessvec_384_cube():
     cs = cosine(Hu_ae.cpu().numpy(), Hu.cpu().numpy())
     print("compressed Hv rel err", err, "cos", cs, flush=True)
     assert err < 0.1 and cs > 0.995
+    # the configuration stores the incremental forward states as latents too
+    ae.set_delta_storage(True)
+    b0 = ae.storage_bytes()
+    assert torch.equal(ae.hessvec(c, u), Hu_ae)      # storing them changes nothing
+    b1 = ae.storage_bytes()
+    print("stores: forward %.2f GB, incremental %.2f GB" % (b0 / 1e9, (b1 - b0) / 1e9), flush=True)
+    assert b1 == 2 * b0
+    dx = ae.decode_delta(p.nt - 1)
+    assert bool(torch.isfinite(dx).all()) and float(dx[:, 0].abs().max()) > 0
 
 
 # ----- 512 x 512 x 256, 8 sources ---------------------------------------------------------------
