@@ -37,7 +37,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--nt", type=int, default=2000)
@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--latent", choices=["bf16", "fp8"], default="bf16")
     ap.add_argument("--checkpoints", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--multisource", action="store_true",
+                    help="kernel rates of the 8-source 512 x 512 x 256 workload with FP8 latents (horizon --ms-nt); "
+                         "prints its own JSON line")
+    ap.add_argument("--ms-nt", type=int, default=120)
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc passes: a device copy of known size, then a few steps of "
                          "every hot-path kernel at the full grid")
@@ -110,10 +114,91 @@ def counters_pass():
                       "stencil_source_sha256": stencil_source_hash()}), flush=True)
 
 
+def copy_peak_gbs(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a 1 GiB buffer: the
+    measured reference next to the published 8 TB/s."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * nbytes / t / 1e9
+
+
+def multisource_pass(args):
+    """The 8-source 512 x 512 x 256 workload (one launch per step for all sources,
+    FP8 latents, 1 % exact patches) over a shortened horizon: mean kernel durations
+    and their HBM / MFMA rates. The network is untrained (rates do not depend on it)."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd.compressor import Autoencoder
+    from paper_2304_04781_amd.solver import WaveSolver
+    L.load()
+    dev = torch.device("cuda", 0)
+    T = args.ms_nt
+    p = W.problem_multisource(T)
+    S, N = len(p.src), p.n
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    d = torch.zeros((S, T, len(p.rec)), dtype=torch.float32, device=dev)
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    ae = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(ae.ctx, int(round(0.01 * P)))
+    ae.set_storage(L.STORE_AE_FP8, ae=net)
+    ae.gradient(c0, wav, d, 1.0)
+    torch.cuda.synchronize()
+    ae.set_timing(2)
+    t0 = time.perf_counter()
+    ae.gradient(c0, wav, d, 1.0)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    kt = ae.kernel_times()
+    ae.set_timing(0)
+    blk = L.wv_accumulation_block()
+    work = {  # per timed launch (the stencils launch all sources at once; encode/decode time one state)
+        "forward_stencil": ("hbm", (32.0 * S + 4.0) * N),
+        "adjoint_stencil": ("hbm", ((adjoint_bytes_per_cell(T, blk) - 4.0) * S + 4.0) * N),
+        "encode": ("mfma", S * 2.0 * P * (2048 * 512 + 512 * 32)),
+        "decode_e": ("mfma", 2.0 * P * (32 * 512 + 512 * 512)),
+    }
+    rows = {}
+    for name, (us, n) in kt.items():
+        if not n:
+            continue
+        row = {"us": round(us, 2), "timed_launches": n}
+        if name in work:
+            kind, w = work[name]
+            rate = w / (us * 1e-6)
+            if kind == "hbm":
+                row.update({"GB/s": round(rate / 1e9, 1), "frac_hbm": round(rate / 1e9 / HBM_PEAK_GBS, 4)})
+            else:
+                row.update({"TFLOP/s": round(rate / 1e12, 1),
+                            "frac_mfma_bf16": round(rate / 1e12 / BF16_PEAK_TFLOPS, 4)})
+        rows[name] = row
+    print(json.dumps({"workload": f"{p.name}: 8 sources, FP8 latents, 1 % exact patches, horizon {T} steps",
+                      "grid": [p.nz, p.ny, p.nx], "sources": S, "gradient_s": round(t_grad, 3),
+                      "store_GB": round(ae.storage_bytes() / 1e9, 2), "kernels": rows,
+                      "note": "with several sources the encode and decode run in order on the main stream; "
+                              "the exception selection and copy on a side stream"}), flush=True)
+
+
 def main():
     args = parse()
     if args.counters:
         counters_pass()
+        return
+    if args.multisource:
+        multisource_pass(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -249,6 +334,9 @@ def main():
     cos = float(torch.sum(ga * gc) / (torch.linalg.norm(ga) * torch.linalg.norm(gc)))
     log(f"grad rel err {rel_err:.4f} cos {cos:.5f}")
 
+    copy_gbs = copy_peak_gbs(torch, dev)
+    log(f"device copy {copy_gbs:.0f} GB/s")
+
     # ---- rooflines: algorithmic bytes (flops) per launch over the measured mean launch duration
     per_launch = {
         "forward_stencil": ("hbm", 36.0 * N),                          # read 4 fields + m, write 4 fields
@@ -280,6 +368,8 @@ def main():
     if bound == "hbm":
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(kernels[dom]["GB/s"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kernels[dom]["frac_hbm"], 4),
+                    "measured_copy_GBps": round(copy_gbs, 1),
+                    "frac_of_copy": round(kernels[dom]["GB/s"] / copy_gbs, 4),
                     "traffic": measured_traffic(dom), "mean_launch_us": round(kernels[dom]["us"], 2),
                     "algorithmic_bytes_per_launch": work}
     else:
@@ -317,6 +407,8 @@ def main():
         "checkpoint": {"gradients_per_hour": round(3600.0 / t_ck, 1), "ms_per_gradient": round(t_ck * 1e3, 2),
                        "forward_steps": fsteps, "store_GB": round(ck_bytes / 1e9, 2)},
         "speedup_vs_checkpoint": round(t_ck / t_ae, 4),
+        "gradient_runs_s": {"ae": [round(x, 4) for x in times], "ae_min": round(min(times), 4),
+                            "checkpoint": [round(x, 4) for x in times_ck], "checkpoint_min": round(min(times_ck), 4)},
         "gn_hessvec": hessvec,
         "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
         "grad_cos_vs_checkpoint_fp32": round(cos, 6),

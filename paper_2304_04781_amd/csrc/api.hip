@@ -531,14 +531,17 @@ void wait_event(hipStream_t st, hipEvent_t ev)
 
 // 1: autoencoder stores and decodes run on the side streams, beside the stencil
 // steps; 2: only the exception selection and copy do; 0: everything on the main
-// stream in order
+// stream in order. With several sources the stencil launch holds S times the
+// work-groups and the side-stream kernels starve beside it (an 8-source 512^2 x 256
+// decode ran 10x slower than alone), so such contexts use mode 2.
 #ifndef WV_OVERLAP
 #define WV_OVERLAP 1
 #endif
 hipStream_t side_stream(wv_ctx* c, int which)
 {
-    if (which) return WV_OVERLAP >= 1 ? c->side2 : c->st;
-    return WV_OVERLAP == 1 ? c->side : c->st;
+    const int mode = (WV_OVERLAP == 1 && c->S > 1) ? 2 : WV_OVERLAP;
+    if (which) return mode >= 1 ? c->side2 : c->st;
+    return mode == 1 ? c->side : c->st;
 }
 
 // Autoencoder store of x_j (1 <= j <= T-1) written by the forward step just
