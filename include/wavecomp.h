@@ -199,11 +199,18 @@ int wave_adjoint(wv_ctx* ctx, const float* c, const float* residual, float* g);
 int gradient(wv_ctx* ctx, const float* c, const float* wavelet, const float* d_obs,
              double sigma, float* g, double* h_misfit);
 
-/* Gauss-Newton Hessian-vector product Hdc = J_F^T (dt/sigma^2) J_F dc at the c of
- * the last gradient() (sigma taken from that call): incremental forward with
- * source dm e^n (dm = 2 c dc) and incremental adjoint, both reading the forward
- * history (decompressed again for the AE modes: compress once, decompress in
- * every Hv). gauss_newton must be 1 (the full-Newton term is not provided).
+/* Hessian-vector product at the c of the last gradient() (sigma taken from that
+ * call), reading the forward history (decompressed again for the AE modes:
+ * compress once, decompress in every Hv).
+ * gauss_newton = 1: Hdc = J_F^T (dt/sigma^2) J_F dc: incremental forward with
+ * source dm e^n (dm = 2 c dc), then the incremental adjoint (Sec. 4).
+ * gauss_newton = 0: the full-Newton product, the derivative of the gradient along
+ * dc, Hdc = -2 dt (dc * sum_n e^n q^n + c * sum_n (de^n q^n + e^n dq^n)): the
+ * incremental forward keeps de^n (full storage, or compressed into the incremental
+ * latent store in the AE modes), then the adjoint mu of the last gradient's
+ * residual and the incremental adjoint dmu (residual dt/sigma^2 dp, and -dt dm q
+ * in its eta equation) step together in reverse time. Needs the full or an AE
+ * store (WV_ESTATE for checkpointing or after a fallback).
  * WV_ESTATE when c differs from the last gradient's c or no store exists. */
 int hessvec(wv_ctx* ctx, const float* c, const float* dc, float* Hdc, int gauss_newton);
 

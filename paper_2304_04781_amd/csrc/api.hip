@@ -190,8 +190,17 @@ struct wv_ctx {
     float* ebuf = nullptr;       // [NEB][S][N]: decoded e, one slot per state in flight
     float* dm = nullptr;
     float* traces = nullptr;
-    float* resid = nullptr;
+    float* resid = nullptr;      // dt/sigma^2 (p - d) of the last gradient
     float* dtr = nullptr;
+    float* dresid = nullptr;     // dt/sigma^2 dp of the last Hessian action
+    // full-Newton Hessian action: second adjoint state, its sums, q of the mu step,
+    // de history (full storage) and a decoded de^k (AE modes)
+    float* adj2[2] = {nullptr, nullptr};
+    float* dacc = nullptr;
+    float* dblk = nullptr;
+    float* qbuf = nullptr;
+    float* dehist = nullptr;
+    float* dbuf = nullptr;
     double* partial = nullptr;
     double* dscal = nullptr;
     int* dflag = nullptr;
@@ -350,11 +359,13 @@ int acc_phase(long long j, int k)
     return first ? (last ? ACC_EACH : ACC_FIRST) : (last ? ACC_LAST : ACC_MID);
 }
 
-void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid, const float* ek,
-              long long ekstride, int phase)
+// One adjoint step of `mode` (MODE_ADJ; MODE_ADJQ / MODE_ADJD for the two sweeps
+// of the full-Newton Hessian action) accumulating into acc / blk.
+void adj_step_x(wv_ctx* c, int mode, const float* in, float* out, int k, const float* resid, const float* ek,
+                long long ekstride, int phase, float* acc, float* blk, const float* dek = nullptr)
 {
     StepArgs a = base_args(c);
-    a.blk = c->blk;
+    a.blk = blk;
     a.acc_phase = phase;
     a.in = in;
     a.out = out;
@@ -362,10 +373,20 @@ void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid,
     a.resid = resid;
     a.ek = ek;
     a.ekstride = ekstride;
-    a.acc = c->acc;
+    a.acc = acc;
+    a.qbuf = c->qbuf;
+    a.dek = dek;
+    a.dekstride = c->N;
+    a.dm = c->dm;
     const int t = c->tm.begin(TM_ADJ, c->st);
-    launch_step(MODE_ADJ, c->has_y, a, c->S, c->st);
+    launch_step(mode, c->has_y, a, c->S, c->st);
     c->tm.end(t, c->st);
+}
+
+void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid, const float* ek,
+              long long ekstride, int phase)
+{
+    adj_step_x(c, MODE_ADJ, in, out, k, resid, ek, ekstride, phase, c->acc, c->blk);
 }
 
 void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, long long enstride,
@@ -886,6 +907,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->traces = dev_alloc<float>(ntr);
         c->resid = dev_alloc<float>(ntr);
         c->dtr = dev_alloc<float>(ntr);
+        c->dresid = dev_alloc<float>(ntr);
         WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         WV_HIP(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
         for (int b = 0; b < 3; ++b) {
@@ -928,7 +950,8 @@ int wv_destroy(wv_ctx* c)
     dev_free(c->src_kji);
     dev_free(c->src_w);
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
-                      &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr})
+                      &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr,
+                      &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf})
         dev_free(*p);
     dev_free(c->partial);
     dev_free(c->dscal);
@@ -1152,15 +1175,20 @@ namespace {
 
 // incremental forward into c->dtr; CHECKPOINT runs the companion forward and
 // places snapshots for a following reverse sweep (returns x_{T-1} there).
-float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const std::vector<int>* snap)
+// keep_de: the full-Newton product needs de^n later (FULL: de history; AE: the
+// incremental latent store)
+float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const std::vector<int>* snap,
+                         bool keep_de = false)
 {
     ensure_inc(c);
     ensure_adj(c);
     launch_dm(cdev, dc, c->dm, c->N, c->st);
     launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
     const bool pipe = !snap && is_ae(c->mode);
+    const bool keep_full = keep_de && !snap && c->mode == WV_STORE_FULL;
+    if (keep_full && !c->dehist) c->dehist = dev_alloc<float>((size_t)std::max(c->T - 1, 1) * c->S * c->N);
     // optional AE store of the incremental states dx_1 .. dx_{T-1} (same network and format)
-    const bool keep_delta = pipe && c->store_delta;
+    const bool keep_delta = pipe && (c->store_delta || keep_de);
     c->delta_ok = false;
     if (keep_delta && !c->ds.lat) {
         const long long bytes = latstore_bytes(c, c->mode, c->K);
@@ -1203,6 +1231,10 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
         if (keep_delta) store_state(c, c->ds, n + 1, din);  // dx_{n+1}, read again only by the step after next
+        if (keep_full && n + 1 <= c->T - 1)
+            for (int s = 0; s < c->S; ++s)
+                WV_HIP(hipMemcpyAsync(c->dehist + ((long long)n * c->S + s) * c->N, din + s * 4 * c->N,
+                                      sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
         if (ckpt) {
             float* out = (*snap)[n + 1] > 0 ? c->slot_ptr((*snap)[n + 1]) : other_work(c, cur);
             fwd_step(c, cur, out, n, nullptr);
@@ -1236,11 +1268,53 @@ int wave_inc_forward(wv_ctx* c, const float* cdev, const float* dc, float* dtrac
     });
 }
 
+namespace {
+
+// Reverse sweep of the full-Newton Hessian action (FULL or AE store): per step k,
+// the mu step (residual of the last gradient) writes q and sums e^k q into acc;
+// the dmu step (residual dt/sigma^2 dp) takes -dt dm q into eta and sums
+// de^k q + e^k dq into dacc.
+void reverse_sweep_newton(wv_ctx* c)
+{
+    ensure_adj(c);
+    if (!c->adj2[0]) {
+        c->adj2[0] = dev_alloc<float>(c->state_floats());
+        c->adj2[1] = dev_alloc<float>(c->state_floats());
+        c->dacc = dev_alloc<float>(2 * c->N * c->S);
+        c->dblk = dev_alloc<float>(c->N * c->S);
+        c->qbuf = dev_alloc<float>(c->N * c->S);
+        c->dbuf = dev_alloc<float>(c->N * c->S);
+    }
+    for (float* p : {c->adj[0], c->adj2[0]}) launch_fill(p, c->state_floats(), 0.f, c->st);
+    launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
+    launch_fill(c->dacc, 2 * c->N * c->S, 0.f, c->st);
+    float *ain = c->adj[0], *aout = c->adj[1], *din = c->adj2[0], *dout = c->adj2[1];
+    long long done = 0;
+    for (int k = c->T - 1; k >= 1; --k) {
+        long long stride;
+        const float* e = load_e(c, k, &stride);
+        const float* de;
+        if (c->mode == WV_STORE_FULL) {
+            de = c->dehist + (long long)(k - 1) * c->S * c->N;
+        } else {
+            decode_state(c, c->ds, k, 1u, c->dbuf, c->N, c->st);
+            de = c->dbuf;
+        }
+        const int phase = acc_phase(done++, k);
+        adj_step_x(c, MODE_ADJQ, ain, aout, k, c->resid, e, stride, phase, c->acc, c->blk);
+        adj_step_x(c, MODE_ADJD, din, dout, k, c->dresid, e, stride, phase, c->dacc, c->dblk, de);
+        std::swap(ain, aout);
+        std::swap(din, dout);
+    }
+}
+
+}  // namespace
+
 int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss_newton)
 {
     return guarded([&]() -> int {
         WV_REQUIRE(c && cdev && dc && Hdc, WV_EINVAL, "null argument");
-        WV_REQUIRE(gauss_newton == 1, WV_EINVAL, "only the Gauss-Newton Hessian is provided");
+        WV_REQUIRE(gauss_newton == 0 || gauss_newton == 1, WV_EINVAL, "gauss_newton must be 0 or 1");
         WV_REQUIRE(c->have_grad, WV_ESTATE, "hessvec needs a preceding gradient() call");
         // the stored history must belong to this c
         WV_HIP(hipMemsetAsync(c->dflag, 0, sizeof(int), c->st));
@@ -1253,6 +1327,18 @@ int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss
         const long long ntr = (long long)c->S * c->T * c->R;
         int status = WV_OK;
         const bool use_ckpt = c->mode == WV_STORE_CHECKPOINT || (c->degraded && c->fallback == WV_FALLBACK_CHECKPOINT);
+        if (!gauss_newton) {
+            // full Newton: d/dc of the gradient along dc, -2 dt (dc acc + c dacc)
+            WV_REQUIRE(!use_ckpt && (c->mode == WV_STORE_FULL || is_ae(c->mode)), WV_ESTATE,
+                       "the full-Newton product needs a stored history (full or autoencoder)");
+            WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored");
+            inc_forward_sweep(c, cdev, dc, nullptr, true);
+            launch_scale_weights(c->dtr, c->dresid, ntr, w, c->st);
+            reverse_sweep_newton(c);
+            launch_newton_finish(cdev, dc, c->acc, c->dacc, c->N, c->S, -2.0 * c->g.dt / c->g.dx, Hdc, c->st);
+            WV_HIP(hipStreamSynchronize(c->st));
+            return WV_OK;
+        }
         if (use_ckpt) {
             if (!c->slots || c->nslots < 2) alloc_slots(c, std::max(c->nslots, 2));
             long long fs = 0;
@@ -1260,15 +1346,15 @@ int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss
             size_t first = 0;
             const auto snap = sweep_snapshots(acts, c->T, &first);
             float* xtm1 = inc_forward_sweep(c, cdev, dc, &snap);
-            launch_scale_weights(c->dtr, c->resid, ntr, w, c->st);
-            reverse_sweep(c, c->resid, &acts, first, xtm1);
+            launch_scale_weights(c->dtr, c->dresid, ntr, w, c->st);
+            reverse_sweep(c, c->dresid, &acts, first, xtm1);
             if (c->mode != WV_STORE_CHECKPOINT) status = WV_OK_FALLBACK;
             if (c->mode == WV_STORE_CHECKPOINT) c->store_ok = false;
         } else {
             WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored");
             inc_forward_sweep(c, cdev, dc, nullptr);
-            launch_scale_weights(c->dtr, c->resid, ntr, w, c->st);
-            reverse_sweep(c, c->resid, nullptr, 0, nullptr);
+            launch_scale_weights(c->dtr, c->dresid, ntr, w, c->st);
+            reverse_sweep(c, c->dresid, nullptr, 0, nullptr);
         }
         finish_grad(c, cdev, Hdc);
         WV_HIP(hipStreamSynchronize(c->st));

@@ -79,6 +79,22 @@ __global__ void grad_finish_kernel(const float* __restrict__ c, const float* __r
     }
 }
 
+// -2 dt (dc * sum_s acc_s + c * sum_s dacc_s), each sum as (sum - compensation) in float64
+__global__ void newton_finish_kernel(const float* __restrict__ c, const float* __restrict__ dc,
+                                     const float* __restrict__ acc, const float* __restrict__ dacc, long long N,
+                                     int nsrc, double scale, float* __restrict__ h)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N;
+         q += (long long)gridDim.x * blockDim.x) {
+        double s = 0.0, ds = 0.0;
+        for (int k = 0; k < nsrc; ++k) {
+            s += (double)acc[(long long)k * 2 * N + q] - (double)acc[(long long)k * 2 * N + N + q];
+            ds += (double)dacc[(long long)k * 2 * N + q] - (double)dacc[(long long)k * 2 * N + N + q];
+        }
+        h[q] = (float)(scale * ((double)dc[q] * s + (double)c[q] * ds));
+    }
+}
+
 __global__ void fill_kernel(float* __restrict__ p, long long n, float v)
 {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
@@ -240,6 +256,14 @@ void launch_misfit(const float* p, const float* d, float* resid, long long n, do
 void launch_scale_weights(const float* p, float* resid, long long n, double w, hipStream_t st)
 {
     hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, resid, n, w);
+    WV_HIP(hipGetLastError());
+}
+
+void launch_newton_finish(const float* c, const float* dc, const float* acc, const float* dacc, long long N,
+                          int nsrc, double scale, float* h, hipStream_t st)
+{
+    hipLaunchKernelGGL(newton_finish_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st, c, dc, acc, dacc, N, nsrc,
+                       scale, h);
     WV_HIP(hipGetLastError());
 }
 

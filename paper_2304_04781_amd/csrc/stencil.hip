@@ -25,6 +25,9 @@
 // ACC_MID adds to it), and its last step (ACC_LAST) adds the partial plus its own
 // term to the compensated pair; ACC_EACH adds every term to the pair directly.
 // Incremental forward: the forward step with c^2 e replaced by c^2 de + dm e^n.
+// Full-Newton Hessian action: the adjoint step of mu also writes its q (ADJQ); the
+// incremental adjoint step of dmu (ADJD) subtracts dt dm q from eta' and accumulates
+// de^k q + e^k dq, the derivative of e^k q along dc.
 
 #include "wv_internal.h"
 
@@ -94,7 +97,8 @@ __device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, u
 // ACC: the adjoint's gradient accumulation phase
 template <int BX, int BY, int MODE, bool HAS_Y, bool MM, int ACC = ACC_EACH>
 __global__ void __launch_bounds__(BX* BY)
-    __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_ADJ ? WV_WAVES_ADJ : WV_WAVES_OTHER)))
+    __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_INC || MODE == MODE_FWD ? WV_WAVES_OTHER
+                                                                                                  : WV_WAVES_ADJ)))
     wave_step_kernel(const StepArgs a)
 {
     __shared__ float sP[BY + 2][BX + 2];
@@ -137,12 +141,16 @@ __global__ void __launch_bounds__(BX* BY)
     float* __restrict__ outVx = outA + 3 * N;
     const float* __restrict__ mm = a.m;
     const float* __restrict__ en = (MODE == MODE_INC) ? a.en + s * a.enstride : nullptr;
-    const float* __restrict__ ek = (MODE == MODE_ADJ) ? a.ek + s * a.ekstride : nullptr;
-    float* __restrict__ acc = (MODE == MODE_ADJ) ? a.acc + s * 2 * N : nullptr;
-    float* __restrict__ cmp = (MODE == MODE_ADJ) ? acc + N : nullptr;
-    float* __restrict__ blk = (MODE == MODE_ADJ) ? a.blk + s * N : nullptr;
-    constexpr bool rd_pair = MODE == MODE_ADJ && (ACC == ACC_EACH || ACC == ACC_LAST);
-    constexpr bool rd_blk = MODE == MODE_ADJ && (ACC == ACC_MID || ACC == ACC_LAST);
+    constexpr bool ADJ = MODE == MODE_ADJ || MODE == MODE_ADJQ || MODE == MODE_ADJD;
+    const float* __restrict__ ek = ADJ ? a.ek + s * a.ekstride : nullptr;
+    float* __restrict__ acc = ADJ ? a.acc + s * 2 * N : nullptr;
+    float* __restrict__ cmp = ADJ ? acc + N : nullptr;
+    float* __restrict__ blk = ADJ ? a.blk + s * N : nullptr;
+    float* __restrict__ qout = (MODE == MODE_ADJQ) ? a.qbuf + s * N : nullptr;   // q of this mu step
+    const float* __restrict__ qin = (MODE == MODE_ADJD) ? a.qbuf + s * N : nullptr;
+    const float* __restrict__ dek = (MODE == MODE_ADJD) ? a.dek + s * a.dekstride : nullptr;
+    constexpr bool rd_pair = ADJ && (ACC == ACC_EACH || ACC == ACC_LAST);
+    constexpr bool rd_blk = ADJ && (ACC == ACC_MID || ACC == ACC_LAST);
 
     // layer factors: S = wz * (wy * wx), the (y, x) product fixed per column
     const int jc = in_y ? j : 0, ic = in_x ? i : 0;
@@ -201,7 +209,7 @@ __global__ void __launch_bounds__(BX* BY)
         if (MODE == MODE_FWD) {
             if (src_col && abs(kk - sk) <= R)
                 add = bsrc * a.src_w[(kk - sk + R) * wdj * (2 * R + 1) + src_col_off];
-        } else if (MODE == MODE_ADJ) {
+        } else if (ADJ) {
             if (a.nrec > 0 && kk < nz) {
                 const int q0 = ldu(lp, kk), q1 = ldu(lp, kk + 1);
                 if (q1 > q0) {
@@ -227,11 +235,11 @@ __global__ void __launch_bounds__(BX* BY)
     };
     // new face value from old value V, difference dP and extra term
     auto face_new = [&](float S, float V, float dP, float add) -> float {
-        if (MODE == MODE_ADJ) return S * V - a.dtdx * dP + add;
+        if (ADJ) return S * V - a.dtdx * dP + add;
         return S * (V + a.dtdx * dP + add);
     };
     // what enters the divergence: v' (forward) or S_v mu' (adjoint)
-    auto face_w = [&](float S, float Vn) -> float { return MODE == MODE_ADJ ? S * Vn : Vn; };
+    auto face_w = [&](float S, float Vn) -> float { return ADJ ? S * Vn : Vn; };
 
     // Software pipeline: the column data of level k+1+PF and the in-plane data of
     // level k+PF are loaded while level k is computed, into a ring of PF+1
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(BX* BY)
         float A, m, Vz, dm, en;
     };
     struct Pln {  // in-plane operands of one level
-        float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp, blk;
+        float Vy, Vx, Vyh, Vxh, rA, rm, rdm, ren, ek, acc, cmp, blk, dek, q;
     };
     // Addresses are a level base (uniform, scalar registers) plus a 32-bit byte
     // offset within the plane (a plane holds fewer than 2^30 cells).
@@ -263,6 +271,7 @@ __global__ void __launch_bounds__(BX* BY)
             c.dm = ld(a.dm, lo, o_c);
             c.en = ld(en, lo, o_c);
         }
+        if (MODE == MODE_ADJD) c.dm = ld(a.dm, lo, o_c);
     };
     auto load_pln = [&](int kk, Pln& q) {
         const long long lo = (long long)kk * plane;
@@ -272,7 +281,11 @@ __global__ void __launch_bounds__(BX* BY)
         }
         q.Vx = ld(inVx, lo, o_c);
         q.Vxh = ld(inVx, lo, o_hx);
-        if (MODE == MODE_ADJ) {
+        if (MODE == MODE_ADJD) {
+            q.dek = ld(dek, lo, o_c);
+            q.q = ld(qin, lo, o_c);
+        }
+        if (ADJ) {
             q.ek = ld(ek, lo, o_c);
             if (rd_pair) {
                 q.acc = ld(acc, lo, o_c);
@@ -281,7 +294,7 @@ __global__ void __launch_bounds__(BX* BY)
             if (rd_blk) q.blk = ld(blk, lo, o_c);
         }
         q.rA = ld(inA, lo, o_r);
-        if (MODE != MODE_ADJ) q.rm = ld(mm, lo, o_r);
+        if (!ADJ) q.rm = ld(mm, lo, o_r);
         if (MODE == MODE_INC) {
             q.rdm = ld(a.dm, lo, o_r);
             q.ren = ld(en, lo, o_r);
@@ -302,7 +315,7 @@ __global__ void __launch_bounds__(BX* BY)
     // ---- prologue: P(k0), cell value, v_z'(k0); first pipeline stages.
     // Ring slot u holds column level k0+u (mod NB) and plane level k0+u (mod NB).
     constexpr int NB = WV_PF + 1;
-    float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
+    float P_cur = 0.f, A_cur = 0.f, m_cur = 0.f, dm_cur = 0.f, Vz_cur = 0.f, Wz_cur = 0.f;
     Col cb[NB];
     Pln pb[NB];
     {
@@ -315,6 +328,7 @@ __global__ void __launch_bounds__(BX* BY)
         for (int u = 0; u < WV_PF; ++u) load_pln(min(k0 + u, k1 - 1), pb[u]);
         A_cur = c0.A;
         m_cur = c0.m;
+        if (MODE == MODE_ADJD) dm_cur = c0.dm;
         P_cur = inside ? P_col(k0, c0) : 0.f;
         const float P_lo = (inside && k0 > 0) ? P_col(k0 - 1, cl) : 0.f;
         const float add = face_inj(k0);
@@ -390,10 +404,15 @@ __global__ void __launch_bounds__(BX* BY)
         dsum += ((i + 1 < nx) ? sWx[ty][tx + 1] : 0.f) - sWx[ty][tx];
         const float Se = wzc * wyx_c;
         float A_new;
-        if (MODE == MODE_ADJ) {
+        if (ADJ) {
             A_new = Se * A_cur - a.dtdx * m_cur * dsum;
             // the term of this step, plus the block's partial on its last step
             float term = e_k * dsum;
+            if (MODE == MODE_ADJD) {
+                // coupling to the mu step: eta' -= dt dm q; the sum takes de^k q + e^k dq
+                A_new -= a.dtdx * dm_cur * pc.q;
+                term += pc.dek * pc.q;
+            }
             if (ACC == ACC_MID || ACC == ACC_LAST) term = s_blk + term;
             if (ACC == ACC_EACH || ACC == ACC_LAST) {
                 // Kahan: s_acc += term
@@ -419,13 +438,14 @@ __global__ void __launch_bounds__(BX* BY)
             if (HAS_Y) st_plane(Vy_new, outVy + lk, pb4, o_c);
             st_plane(Vx_new, outVx + lk, pb4, o_c);
 #endif
-            if (MODE == MODE_ADJ) {
+            if (ADJ) {
                 if (ACC == ACC_EACH || ACC == ACC_LAST) {
                     st_plane(s_acc, acc + lk, pb4, o_c);
                     st_plane(s_cmp, cmp + lk, pb4, o_c);
                 } else {
                     st_plane(s_acc, blk + lk, pb4, o_c);
                 }
+                if (MODE == MODE_ADJQ) st_plane(dsum, qout + lk, pb4, o_c);
             }
         }
         if constexpr (want_mm) {
@@ -469,7 +489,7 @@ __global__ void __launch_bounds__(BX* BY)
             }
         }
         // traces: v_z of this level's new face at the receivers, through sRec
-        if (MODE != MODE_ADJ && a.nrec > 0) {
+        if (!ADJ && a.nrec > 0) {
             const int q0 = ldu(lp, k), q1 = ldu(lp, k + 1);
             if (q1 > q0) {
                 sRec[local] = Vz_cur;
@@ -483,6 +503,7 @@ __global__ void __launch_bounds__(BX* BY)
         P_cur = P_nx;
         A_cur = cn.A;
         m_cur = cn.m;
+        if (MODE == MODE_ADJD) dm_cur = cn.dm;
         Vz_cur = Vz_nx;
         Wz_cur = Wz_nx;
     };
@@ -499,11 +520,22 @@ __global__ void __launch_bounds__(BX* BY)
         if (kb + u < k1) level(kb + u, cb[(u + 1) % NB], cb[u % NB], pb[u % NB], pb[(u + NB - 1) % NB]);
 }
 
+template <int BX, int BY, int MODE, bool HAS_Y>
+void launch_adj(const StepArgs& a, dim3 grid, dim3 block, hipStream_t st)
+{
+    switch (a.acc_phase) {
+    case ACC_FIRST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE, HAS_Y, false, ACC_FIRST>), grid, block, 0, st, a); break;
+    case ACC_MID: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE, HAS_Y, false, ACC_MID>), grid, block, 0, st, a); break;
+    case ACC_LAST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE, HAS_Y, false, ACC_LAST>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE, HAS_Y, false, ACC_EACH>), grid, block, 0, st, a); break;
+    }
+}
+
 template <int BX, int BY, bool HAS_Y>
 void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
 {
     StepArgs a = a0;
-    if (mode == MODE_ADJ) {
+    if (mode == MODE_ADJ || mode == MODE_ADJQ || mode == MODE_ADJD) {
         a.kc = a.kc_adj;
         a.chunks_z = a.chunks_adj;
     }
@@ -517,14 +549,9 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
         else
             hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, false>), grid, block, 0, st, a);
         break;
-    case MODE_ADJ:
-        switch (a.acc_phase) {
-        case ACC_FIRST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_FIRST>), grid, block, 0, st, a); break;
-        case ACC_MID: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_MID>), grid, block, 0, st, a); break;
-        case ACC_LAST: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_LAST>), grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_ADJ, HAS_Y, false, ACC_EACH>), grid, block, 0, st, a); break;
-        }
-        break;
+    case MODE_ADJ: launch_adj<BX, BY, MODE_ADJ, HAS_Y>(a, grid, block, st); break;
+    case MODE_ADJQ: launch_adj<BX, BY, MODE_ADJQ, HAS_Y>(a, grid, block, st); break;
+    case MODE_ADJD: launch_adj<BX, BY, MODE_ADJD, HAS_Y>(a, grid, block, st); break;
     default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false>), grid, block, 0, st, a); break;
     }
 }

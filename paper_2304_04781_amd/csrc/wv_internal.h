@@ -34,7 +34,7 @@ struct Error {
 
 // ---- stencil -----------------------------------------------------------------------
 
-enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2 };
+enum StepMode { MODE_FWD = 0, MODE_ADJ = 1, MODE_INC = 2, MODE_ADJQ = 3, MODE_ADJD = 4 };
 // gradient accumulation phase of an adjoint step within its block of steps
 enum AccPhase { ACC_EACH = 0, ACC_FIRST = 1, ACC_MID = 2, ACC_LAST = 3 };
 
@@ -78,6 +78,11 @@ struct StepArgs {
     float* acc;            // [S][2][N]: sum, compensation
     float* blk;            // [S][N]: float32 partial of the current block of steps
     int acc_phase;         // AccPhase of this step
+    // full-Newton Hessian action: q of the mu step [S][N] (written by ADJQ, read by
+    // ADJD), de^k of the dmu step
+    float* qbuf;
+    const float* dek;
+    long long dekstride;
     // incremental forward: dm and forward e^n
     const float* dm;
     const float* en;
@@ -103,6 +108,9 @@ void launch_scale_weights(const float* p, float* resid, long long n, double w, h
 void launch_grad_finish(const float* c, const float* acc, long long N, int nsrc, double scale,
                         float* g, hipStream_t st);
 void launch_fill(float* p, long long n, float v, hipStream_t st);
+// h = scale (dc * sum_s acc_s + c * sum_s dacc_s), acc/dacc [S][2][N] compensated pairs
+void launch_newton_finish(const float* c, const float* dc, const float* acc, const float* dacc, long long N,
+                          int nsrc, double scale, float* h, hipStream_t st);
 void launch_compare(const float* a, const float* b, long long n, int* flag, hipStream_t st);
 void launch_copy(float* dst, const float* src, long long n, hipStream_t st);
 void launch_rel_err(const float* a, const float* b, long long n, double* partial, int nblocks,

@@ -121,9 +121,10 @@ class WaveSolver:
         self.last_status = status
         return J, g
 
-    def hessvec(self, c, dc):
+    def hessvec(self, c, dc, gauss_newton: bool = True):
+        """Gauss-Newton (default) or full-Newton Hessian action at the last gradient's c."""
         H = torch.empty(self.shape, dtype=torch.float32, device=self.device)
-        self.last_status = L.hessvec(self.ctx, self._f32(c), self._f32(dc), H, 1)
+        self.last_status = L.hessvec(self.ctx, self._f32(c), self._f32(dc), H, 1 if gauss_newton else 0)
         return H
 
     def inc_forward(self, c, dc):

@@ -207,6 +207,36 @@ def test_gn_hessvec_matches_oracle(mode):
     assert np.array_equal(H, H2)
 
 
+def test_full_newton_hessvec_matches_oracle():
+    """Full-Newton Hessian action (derivative of the gradient along dc: the
+    incremental forward keeps de, then mu and dmu step together backwards) against
+    the oracle's, which is pinned to finite differences of the FP64 gradient; the
+    full Hessian is symmetric; it differs from the Gauss-Newton one."""
+    p = small3d(nt=160)
+    sol, d, sigma = oracle_data(p)
+    traces, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, src_w=p.src_w)
+    _, resid = ow.misfit(sol, traces, d, sigma)
+    u = f32(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2))
+    w = f32(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 9))
+    Hf_o = ow.hessvec_full(sol, p.c_start, u, e_hist, resid, p.rec, sigma)
+    s = solver_for(p, L.STORE_FULL)
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    Hu = s.hessvec(p.c_start, u, gauss_newton=False).cpu().numpy()
+    print("full Newton rel err", rel(Hu, Hf_o), flush=True)
+    assert rel(Hu, Hf_o) < 1e-4
+    Hw = s.hessvec(p.c_start, w, gauss_newton=False).cpu().numpy()
+    a, b = float(np.sum(w * Hu)), float(np.sum(u * Hw))
+    assert abs(a - b) / abs(a) < 1e-4
+    Hg = s.hessvec(p.c_start, u).cpu().numpy()
+    assert rel(Hg, Hf_o) > 1e-3
+    # the gradient residual survives the Gauss-Newton product
+    assert np.array_equal(s.hessvec(p.c_start, u, gauss_newton=False).cpu().numpy(), Hu)
+    ck = solver_for(p, L.STORE_CHECKPOINT, nslots=6)
+    ck.gradient(p.c_start, p.wavelet, d, sigma)
+    with pytest.raises(L.WvError):
+        ck.hessvec(p.c_start, u, gauss_newton=False)
+
+
 def test_autograd_gradient_and_double_backward():
     from paper_2304_04781_amd.autograd import WaveMisfit
     p = small3d(nt=150)
