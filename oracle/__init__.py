@@ -15,4 +15,6 @@ Modules
             the patch layout of the space compression scheme (Sec. 3.1)
   rounding  bfloat16 and OCP FP8 E4M3FN round-to-nearest-even
   revolve   optimal binomial checkpointing cost (closed form and DP)
+  inverse   BiLaplacian prior (Sec. 2) and the inexact Newton-CG loop for
+            the MAP point (Sec. 4)
 """
