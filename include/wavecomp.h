@@ -217,6 +217,76 @@ int hessvec(wv_ctx* ctx, const float* c, const float* dc, float* Hdc, int gauss_
 /* Incremental forward only: dp [S][T][R] = J_F dc (uses the stored history). */
 int wave_inc_forward(wv_ctx* ctx, const float* c, const float* dc, float* dtraces);
 
+/* ---- MAP point: BiLaplacian prior (paper Sec. 2) and Newton-CG (Sec. 4) ----------- */
+
+/* Prior term of the MAP objective, 1/2 ||c - c0||^2 weighted by the inverse prior
+ * covariance, with the BiLaplacian prior of Sec. 2: the inverse covariance is the
+ * square of the elliptic operator
+ *     A u = alpha (u - div(Theta grad u)),   zero normal flux of Theta grad u
+ * on the boundary, Theta = diag(theta_z, theta_y, theta_x) [m^2]. On the grid:
+ * (A u)_i = alpha (u_i - sum over the faces of cell i shared with a neighbour nb
+ * of theta_a (u_nb - u_i) / dx^2) (boundary faces carry no flux), and with the
+ * lumped mass dx^dims I (dims = 2 when ny == 1, whose y term vanishes)
+ *     R(c) = 1/2 dx^dims ||A (c - c0)||^2,   grad R = dx^dims A A (c - c0),
+ *     Hess R = dx^dims A A.
+ * wv_set_prior copies c0 [N] (device) into the context; alpha = 0 removes the
+ * prior (c0 may then be NULL). WV_EINVAL for negative or non-finite alpha or
+ * theta. */
+int wv_set_prior(wv_ctx* ctx, double alpha, const double* h_theta, const float* c0);
+
+/* R(c) into *h_cost (may be NULL), and g += grad R when g is non-NULL. Both are
+ * zero without a prior. Synchronises the context's stream when h_cost is set. */
+int wv_prior(wv_ctx* ctx, const float* c, float* g, double* h_cost);
+
+/* Hdc += dx^dims A A dc (nothing without a prior). */
+int wv_prior_hessvec(wv_ctx* ctx, const float* dc, float* Hdc);
+
+typedef struct wv_newton_cfg {
+    int32_t max_newton;     /* Newton iterations (>= 0) */
+    int32_t max_cg;         /* conjugate-gradient iterations per Newton step (>= 1) */
+    double eta_max;         /* cap of the forcing eta = min(eta_max, sqrt(|g| / |g_0|)), in (0, 1) */
+    double rel_tol;         /* stop once |g| <= rel_tol |g_0| (>= 0) */
+    double c_armijo;        /* sufficient decrease J(c + a p) <= J + c_armijo a g.p, in (0, 1) */
+    int32_t max_backtrack;  /* halvings of the step length before the line search fails (>= 0) */
+    int32_t gauss_newton;   /* 1: Gauss-Newton misfit Hessian, 0: full Newton (full or AE store) */
+} wv_newton_cfg;
+
+typedef struct wv_newton_rec {
+    double cost;        /* J = misfit + prior at the iterate */
+    double misfit;
+    double prior;
+    double gnorm;       /* |g|, g = gradient of J */
+    double step;        /* accepted step length (0 for the last iterate) */
+    double cg_rel_res;  /* |H p + g| / |g| of the CG recurrence when CG stopped */
+    int32_t cg_iters;   /* Hessian actions spent on the step from this iterate */
+    int32_t neg_curv;   /* CG stopped at non-positive curvature */
+    int32_t backtracks; /* step halvings (max_backtrack + 1: line search failed) */
+    int32_t status;     /* return code of the gradient at the iterate (WV_OK or WV_OK_FALLBACK) */
+} wv_newton_rec;
+
+/* Inexact Newton-CG for the MAP point (Sec. 4; the paper's references on
+ * Newton-CG for wave inversion): from c (device [N], updated in place), repeat
+ *   1. J, g at the iterate: gradient() plus the prior term (for later iterates
+ *      the accepted trial of the line search already computed them);
+ *   2. stop if |g| <= rel_tol |g_0|;
+ *   3. conjugate gradients on H p = -g from p = 0, H = hessvec() + prior Hessian
+ *      (each iteration one Hessian action, which decompresses the stored forward
+ *      history again in the AE modes), until |r| <= eta |g| with
+ *      eta = min(eta_max, sqrt(|g| / |g_0|)), max_cg iterations, or non-positive
+ *      curvature d.Hd <= 0 (then the iterate so far is kept, or p = -g at the
+ *      first iteration);
+ *   4. Armijo backtracking from the step length 1, halving; every trial runs a
+ *      gradient (forward with storage + adjoint), so an accepted trial leaves its
+ *      store for the next Hessian actions. A trial speed outside the stable,
+ *      positive range is rejected like an increase of J.
+ * Vector updates are float32, dot products float64.
+ * h_log: host array of max_newton + 1 records (iterates 0 .. *h_iters);
+ * *h_iters: Newton steps taken; *h_reason: 0 iteration limit, 1 gradient
+ * tolerance, 2 line search failed (c then holds the last accepted iterate and the
+ * store belongs to the last trial). Needs a storage mode other than WV_STORE_NONE. */
+int wv_newton_cg(wv_ctx* ctx, float* c, const float* wavelet, const float* d_obs, double sigma,
+                 const wv_newton_cfg* cfg, wv_newton_rec* h_log, int32_t* h_iters, int32_t* h_reason);
+
 /* ---- autoencoder (paper Sec. 3.3 architecture, Eq. (single_layer); Sec. 3.3.1) --- */
 
 /* Create a dense autoencoder in_dim -> hidden -> latent -> hidden -> in_dim with

@@ -39,6 +39,18 @@ class AeTrainCfg(C.Structure):
                 ("beta2", C.c_double), ("eps", C.c_double), ("weighting", C.c_int32)]
 
 
+class WvNewtonCfg(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("max_cg", C.c_int32), ("eta_max", C.c_double),
+                ("rel_tol", C.c_double), ("c_armijo", C.c_double), ("max_backtrack", C.c_int32),
+                ("gauss_newton", C.c_int32)]
+
+
+class WvNewtonRec(C.Structure):
+    _fields_ = [("cost", C.c_double), ("misfit", C.c_double), ("prior", C.c_double), ("gnorm", C.c_double),
+                ("step", C.c_double), ("cg_rel_res", C.c_double), ("cg_iters", C.c_int32),
+                ("neg_curv", C.c_int32), ("backtracks", C.c_int32), ("status", C.c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "wv_create": (C.c_int, [C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -81,6 +93,11 @@ EXPORTS = {
     "wv_accumulation_block": (C.c_int, []),
     "wv_set_delta_storage": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_decode_delta": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p]),
+    "wv_set_prior": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "wv_prior": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "wv_prior_hessvec": (C.c_int, [C.c_void_p] * 3),
+    "wv_newton_cg": (C.c_int, [C.c_void_p] * 4 + [C.c_double, C.POINTER(WvNewtonCfg), C.c_void_p,
+                                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -343,3 +360,36 @@ def wv_set_delta_storage(ctx, enable: bool) -> int:
 
 def wv_decode_delta(ctx, n: int, field_mask: int, state) -> int:
     return _check(load().wv_decode_delta(ctx, int(n), int(field_mask), ptr(state)))
+
+
+def wv_set_prior(ctx, alpha: float, theta: Sequence[float] = (0.0, 0.0, 0.0), c0=None) -> int:
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(3))
+    return _check(load().wv_set_prior(ctx, float(alpha), th.ctypes.data, ptr(c0, torch.float32)))
+
+
+def wv_prior(ctx, c, g=None, want_cost: bool = True):
+    """Returns R(c) (None when want_cost is False); g += grad R if g is given."""
+    R = C.c_double()
+    _check(load().wv_prior(ctx, ptr(c, torch.float32), ptr(g, torch.float32), C.byref(R) if want_cost else None))
+    return R.value if want_cost else None
+
+
+def wv_prior_hessvec(ctx, dc, Hdc) -> int:
+    return _check(load().wv_prior_hessvec(ctx, ptr(dc, torch.float32), ptr(Hdc, torch.float32)))
+
+
+NEWTON_FIELDS = [f for f, _ in WvNewtonRec._fields_]
+
+
+def wv_newton_cg(ctx, c, wavelet, d_obs, sigma, max_newton=5, max_cg=10, eta_max=0.5, rel_tol=1e-6,
+                 c_armijo=1e-4, max_backtrack=10, gauss_newton=1):
+    """Runs Newton-CG in place on c; returns (records as dicts, iterations, reason)."""
+    cfg = WvNewtonCfg(int(max_newton), int(max_cg), float(eta_max), float(rel_tol), float(c_armijo),
+                      int(max_backtrack), int(gauss_newton))
+    recs = (WvNewtonRec * (int(max_newton) + 1))()
+    it, reason = C.c_int32(), C.c_int32()
+    f32 = torch.float32
+    _check(load().wv_newton_cg(ctx, ptr(c, f32), ptr(wavelet, f32), ptr(d_obs, f32), float(sigma), C.byref(cfg),
+                               recs, C.byref(it), C.byref(reason)))
+    log = [{f: getattr(recs[i], f) for f in NEWTON_FIELDS} for i in range(it.value + 1)]
+    return log, it.value, reason.value

@@ -248,6 +248,13 @@ struct wv_ctx {
     double sigma = 1.0;
     long long last_fwd_steps = 0;
 
+    // MAP layer: BiLaplacian prior and the Newton-CG work vectors
+    double prior_alpha = 0.0;
+    double prior_theta[3] = {0.0, 0.0, 0.0};
+    float* prior_c0 = nullptr;
+    float* prior_w = nullptr;    // A (c - c0) or A dc
+    float* nvec = nullptr;       // [7][N]: g, trial g, trial c, p, r, d, H d
+
     long long state_floats() const { return 4LL * N * S; }
     float* slot_ptr(int b) const { return slots + (long long)(b - 1) * state_floats(); }
 };
@@ -951,7 +958,8 @@ int wv_destroy(wv_ctx* c)
     dev_free(c->src_w);
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
                       &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr,
-                      &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf})
+                      &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf,
+                      &c->prior_c0, &c->prior_w, &c->nvec})
         dev_free(*p);
     dev_free(c->partial);
     dev_free(c->dscal);
@@ -1359,6 +1367,218 @@ int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss
         finish_grad(c, cdev, Hdc);
         WV_HIP(hipStreamSynchronize(c->st));
         return status;
+    });
+}
+
+namespace {
+
+double dot_host(wv_ctx* c, const float* a, const float* b)
+{
+    launch_dot(a, b, c->N, c->partial, c->nblk_red, c->dscal, c->st);
+    double v = 0.0;
+    WV_HIP(hipMemcpyAsync(&v, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    WV_HIP(hipStreamSynchronize(c->st));
+    return v;
+}
+
+double cell_volume(const wv_ctx* c) { return c->has_y ? c->g.dx * c->g.dx * c->g.dx : c->g.dx * c->g.dx; }
+
+// out = scale A u' (+ out), u' = u - u0 (u0 may be null)
+void apply_prior(wv_ctx* c, const float* u, const float* u0, float* out, double scale, bool accumulate)
+{
+    const double h2 = c->g.dx * c->g.dx;
+    launch_prior(u, u0, out, c->g.nz, c->g.ny, c->g.nx, c->prior_alpha, c->prior_theta[0] / h2,
+                 c->prior_theta[1] / h2, c->prior_theta[2] / h2, scale, accumulate, c->st);
+}
+
+// R(c) = 1/2 dx^dims |A (c - c0)|^2 (when want_cost) and g += dx^dims A A (c - c0)
+double prior_cost_grad(wv_ctx* c, const float* cdev, float* g, bool want_cost)
+{
+    if (c->prior_alpha == 0.0) return 0.0;
+    apply_prior(c, cdev, c->prior_c0, c->prior_w, 1.0, false);
+    const double R = want_cost ? 0.5 * cell_volume(c) * dot_host(c, c->prior_w, c->prior_w) : 0.0;
+    if (g) apply_prior(c, c->prior_w, nullptr, g, cell_volume(c), true);
+    return R;
+}
+
+void prior_hv(wv_ctx* c, const float* dc, float* Hdc)
+{
+    if (c->prior_alpha == 0.0) return;
+    apply_prior(c, dc, nullptr, c->prior_w, 1.0, false);
+    apply_prior(c, c->prior_w, nullptr, Hdc, cell_volume(c), true);
+}
+
+// positive, finite and leapfrog-stable (the test of check_speed, without throwing)
+bool speed_ok(wv_ctx* c, const float* cdev)
+{
+    launch_range(cdev, c->N, c->partial, c->nblk_red, c->dscal, c->st);
+    double h[3];
+    WV_HIP(hipMemcpyAsync(h, c->dscal, sizeof(h), hipMemcpyDeviceToHost, c->st));
+    WV_HIP(hipStreamSynchronize(c->st));
+    const double dims = c->has_y ? 3.0 : 2.0;
+    return h[2] == 0.0 && h[0] > 0.0 && h[1] * c->g.dt / c->g.dx < 1.0 / std::sqrt(dims);
+}
+
+// a public entry point's failure, re-thrown inside a guarded call
+void check_rc(int rc)
+{
+    if (rc < 0) throw Error{rc, wv_last_error()};
+}
+
+}  // namespace
+
+int wv_set_prior(wv_ctx* c, double alpha, const double* h_theta, const float* c0)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c, WV_EINVAL, "null context");
+        WV_REQUIRE(std::isfinite(alpha) && alpha >= 0.0, WV_EINVAL, "alpha must be finite and >= 0");
+        if (alpha == 0.0) {
+            c->prior_alpha = 0.0;
+            return WV_OK;
+        }
+        WV_REQUIRE(h_theta && c0, WV_EINVAL, "null argument");
+        for (int a = 0; a < 3; ++a)
+            WV_REQUIRE(std::isfinite(h_theta[a]) && h_theta[a] >= 0.0, WV_EINVAL, "theta must be finite and >= 0");
+        if (!c->prior_c0) c->prior_c0 = dev_alloc<float>(c->N);
+        if (!c->prior_w) c->prior_w = dev_alloc<float>(c->N);
+        launch_copy(c->prior_c0, c0, c->N, c->st);
+        WV_HIP(hipStreamSynchronize(c->st));
+        c->prior_alpha = alpha;
+        for (int a = 0; a < 3; ++a) c->prior_theta[a] = h_theta[a];
+        return WV_OK;
+    });
+}
+
+int wv_prior(wv_ctx* c, const float* cdev, float* g, double* h_cost)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev, WV_EINVAL, "null argument");
+        const double R = prior_cost_grad(c, cdev, g, h_cost != nullptr);
+        if (h_cost) *h_cost = R;
+        return WV_OK;
+    });
+}
+
+int wv_prior_hessvec(wv_ctx* c, const float* dc, float* Hdc)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && dc && Hdc, WV_EINVAL, "null argument");
+        prior_hv(c, dc, Hdc);
+        return WV_OK;
+    });
+}
+
+int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_obs, double sigma,
+                 const wv_newton_cfg* cfg, wv_newton_rec* h_log, int32_t* h_iters, int32_t* h_reason)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cvec && wavelet && d_obs && cfg && h_log, WV_EINVAL, "null argument");
+        WV_REQUIRE(cfg->max_newton >= 0 && cfg->max_cg >= 1 && cfg->max_backtrack >= 0, WV_EINVAL,
+                   "max_newton >= 0, max_cg >= 1 and max_backtrack >= 0 required");
+        WV_REQUIRE(cfg->eta_max > 0.0 && cfg->eta_max < 1.0 && cfg->rel_tol >= 0.0 && cfg->c_armijo > 0.0 &&
+                       cfg->c_armijo < 1.0,
+                   WV_EINVAL, "eta_max and c_armijo must lie in (0, 1), rel_tol >= 0");
+        WV_REQUIRE(cfg->gauss_newton == 0 || cfg->gauss_newton == 1, WV_EINVAL, "gauss_newton must be 0 or 1");
+        WV_REQUIRE(c->mode != WV_STORE_NONE, WV_ESTATE, "Newton-CG needs a storage mode");
+        const long long N = c->N;
+        if (!c->nvec) c->nvec = dev_alloc<float>(7 * (size_t)N);
+        float* g = c->nvec;
+        float* gt = g + N;
+        float* ct = g + 2 * N;
+        float* p = g + 3 * N;
+        float* r = g + 4 * N;
+        float* d = g + 5 * N;
+        float* Hd = g + 6 * N;
+        auto record = [](double Jm, double R, double gn, int status) {
+            wv_newton_rec q{};
+            q.cost = Jm + R;
+            q.misfit = Jm;
+            q.prior = R;
+            q.gnorm = gn;
+            q.status = status;
+            return q;
+        };
+        // the iterate: J, g and the stored history that the Hessian actions read
+        double Jm = 0.0;
+        int status = gradient(c, cvec, wavelet, d_obs, sigma, g, &Jm);
+        check_rc(status);
+        double R = prior_cost_grad(c, cvec, g, true);
+        double J = Jm + R;
+        const double g0 = std::sqrt(dot_host(c, g, g));
+        h_log[0] = record(Jm, R, g0, status);
+        int it = 0, reason = 0;
+        for (; it < cfg->max_newton; ++it) {
+            wv_newton_rec& rec = h_log[it];
+            const double gn = rec.gnorm;
+            if (gn <= cfg->rel_tol * g0) {
+                reason = 1;
+                break;
+            }
+            const double eta = std::min(cfg->eta_max, std::sqrt(gn / g0));
+            // conjugate gradients on H p = -g from p = 0
+            launch_fill(p, N, 0.f, c->st);
+            launch_axpby(r, g, -1.0, 0.0, N, c->st);
+            launch_copy(d, r, N, c->st);
+            double rr = gn * gn;
+            const double r0 = gn;
+            int its = 0, neg = 0;
+            double rel = 1.0;
+            while (its < cfg->max_cg) {
+                check_rc(hessvec(c, cvec, d, Hd, cfg->gauss_newton));
+                prior_hv(c, d, Hd);
+                const double dHd = dot_host(c, d, Hd);
+                ++its;
+                if (!(dHd > 0.0)) {
+                    neg = 1;
+                    if (its == 1) launch_axpby(p, g, -1.0, 0.0, N, c->st);
+                    rel = std::sqrt(rr) / r0;
+                    break;
+                }
+                const double a = rr / dHd;
+                launch_axpby(p, d, a, 1.0, N, c->st);
+                launch_axpby(r, Hd, -a, 1.0, N, c->st);
+                const double rr_new = dot_host(c, r, r);
+                rel = std::sqrt(rr_new) / r0;
+                if (std::sqrt(rr_new) <= eta * r0) break;
+                launch_axpby(d, r, 1.0, rr_new / rr, N, c->st);
+                rr = rr_new;
+            }
+            const double gp = dot_host(c, g, p);
+            // Armijo backtracking; every trial is a full gradient evaluation
+            double a = 1.0, Jmt = 0.0, Rt = 0.0;
+            int bt = 0, st_t = WV_OK;
+            bool accepted = false;
+            for (; bt <= cfg->max_backtrack; ++bt, a *= 0.5) {
+                launch_lincomb(ct, cvec, a, p, N, c->st);
+                if (!speed_ok(c, ct)) continue;
+                st_t = gradient(c, ct, wavelet, d_obs, sigma, gt, &Jmt);
+                check_rc(st_t);
+                Rt = prior_cost_grad(c, ct, gt, true);
+                if (Jmt + Rt <= J + cfg->c_armijo * a * gp) {
+                    accepted = true;
+                    break;
+                }
+            }
+            rec.cg_iters = its;
+            rec.neg_curv = neg;
+            rec.cg_rel_res = rel;
+            rec.backtracks = bt;
+            if (!accepted) {
+                reason = 2;
+                break;
+            }
+            rec.step = a;
+            launch_copy(cvec, ct, N, c->st);
+            std::swap(g, gt);
+            Jm = Jmt;
+            R = Rt;
+            J = Jm + R;
+            h_log[it + 1] = record(Jm, R, std::sqrt(dot_host(c, g, g)), st_t);
+        }
+        WV_HIP(hipStreamSynchronize(c->st));
+        if (h_iters) *h_iters = it;
+        if (h_reason) *h_reason = reason;
+        return WV_OK;
     });
 }
 

@@ -122,6 +122,13 @@ void launch_range(const float* x, long long n, double* partial, int nblocks, dou
                   hipStream_t st);
 // dm = 2 c dc
 void launch_dm(const float* c, const float* dc, float* dm, long long n, hipStream_t st);
+// inverse-problem layer (inverse.hip)
+void launch_prior(const float* u, const float* u0, float* out, int nz, int ny, int nx, double alpha, double cz,
+                  double cy, double cx, double scale, bool accumulate, hipStream_t st);
+void launch_axpby(float* y, const float* x, double a, double b, long long n, hipStream_t st);
+void launch_lincomb(float* out, const float* x, double a, const float* y, long long n, hipStream_t st);
+void launch_dot(const float* a, const float* b, long long n, double* partial, int nblocks, double* d_out,
+                hipStream_t st);
 
 // ---- revolve --------------------------------------------------------------------------
 

@@ -131,3 +131,25 @@ class WaveSolver:
         dtr = self.empty_traces()
         L.wave_inc_forward(self.ctx, self._f32(c), self._f32(dc), dtr)
         return dtr
+
+    # ----- MAP point: BiLaplacian prior and Newton-CG --------------------------------------------
+    def set_prior(self, alpha: float, theta=(0.0, 0.0, 0.0), c0=None) -> None:
+        """BiLaplacian prior with mean c0 (copied); alpha = 0 removes it."""
+        L.wv_set_prior(self.ctx, alpha, theta, None if c0 is None else self._f32(c0))
+
+    def prior(self, c):
+        """(R(c), grad R(c))."""
+        g = torch.zeros(self.shape, dtype=torch.float32, device=self.device)
+        R = L.wv_prior(self.ctx, self._f32(c), g)
+        return R, g
+
+    def prior_hessvec(self, dc):
+        H = torch.zeros(self.shape, dtype=torch.float32, device=self.device)
+        L.wv_prior_hessvec(self.ctx, self._f32(dc), H)
+        return H
+
+    def newton_cg(self, c, wavelet, d_obs, sigma, **cfg):
+        """Newton-CG from c for the MAP point; returns (c, records, iterations, reason)."""
+        c = self._f32(c).clone()
+        log, it, reason = L.wv_newton_cg(self.ctx, c, self._f32(wavelet), self._f32(d_obs), sigma, **cfg)
+        return c, log, it, reason

@@ -394,3 +394,25 @@ def test_compressed_gradient_and_hessvec():
     err_u = rel(gu.cpu().numpy(), g0n)
     print("untrained rel err", err_u, flush=True)
     assert err_u > 5 * errs[(L.STORE_AE_BF16, 0)][0]
+
+
+def test_newton_cg_from_compressed_stores_equals_full_storage():
+    """Newton-CG on the AE store with every patch exact takes the full-storage path
+    bit for bit (the gradient and every Hessian action read identical states)."""
+    p = ae_problem(nt=60, shape=(32, 32, 40))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    cfg = dict(max_newton=2, max_cg=3, gauss_newton=0)
+    out = []
+    for mode in (L.STORE_FULL, L.STORE_AE_BF16):
+        s = WaveSolver.for_problem(p)
+        if mode != L.STORE_FULL:
+            L.wv_set_ae_exceptions(s.ctx, 4 * 4 * 5)
+        s.set_storage(mode, ae=raw if mode != L.STORE_FULL else None)
+        s.set_prior(1e-6, (1600.0, 1600.0, 1600.0), p.c_start)
+        out.append(s.newton_cg(p.c_start, p.wavelet, d, sigma, **cfg))
+    (c0, log0, it0, _), (c1, log1, it1, _) = out
+    assert it0 == it1 == 2
+    assert torch.equal(c0, c1)
+    assert [r["cost"] for r in log0] == [r["cost"] for r in log1]
