@@ -52,6 +52,9 @@ def parse():
                     help="kernel rates of the 8-source 512 x 512 x 256 workload with FP8 latents (horizon --ms-nt); "
                          "prints its own JSON line")
     ap.add_argument("--ms-nt", type=int, default=120)
+    ap.add_argument("--no-newton", action="store_true",
+                    help="skip the timed Newton-CG iteration (AE store vs checkpointing)")
+    ap.add_argument("--newton-cg", type=int, default=10, help="CG iterations of the timed Newton step")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc passes: a device copy of known size, then a few steps of "
                          "every hot-path kernel at the full grid")
@@ -328,6 +331,14 @@ def main():
     del h_ae, h_ck, hv, dc
     log(f"GN Hv: {hessvec}")
 
+    # ---- one Newton-CG iteration for the MAP point (BiLaplacian prior): a gradient, newton_cg Hv
+    # products in CG and the accepted trial's gradient; the AE store is written once per iterate
+    # and decompressed in every Hv, checkpointing recomputes the forward in each of them
+    newton = None
+    if not args.no_newton:
+        newton = newton_iteration(args, p, ae_solver, ck, c0, wav, d_obs, sigma)
+        log(f"Newton iteration: {newton}")
+
     ga = g_ae.double()
     gc = g_ck.double()
     rel_err = float(torch.linalg.norm(ga - gc) / torch.linalg.norm(gc))
@@ -410,6 +421,7 @@ def main():
         "gradient_runs_s": {"ae": [round(x, 4) for x in times], "ae_min": round(min(times), 4),
                             "checkpoint": [round(x, 4) for x in times_ck], "checkpoint_min": round(min(times_ck), 4)},
         "gn_hessvec": hessvec,
+        "newton_iteration": newton,
         "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
         "grad_cos_vs_checkpoint_fp32": round(cos, 6),
         "misfit": {"ae": J_ae, "checkpoint": J_ck},
@@ -430,6 +442,34 @@ def main():
         "setup_s": round(time.perf_counter() - t_setup, 1),
     }
     print(json.dumps(out), flush=True)
+
+
+def newton_iteration(args, p, ae_solver, ck, c0, wav, d_obs, sigma):
+    """Wall time of one Gauss-Newton CG iteration (eta tiny, so CG runs its
+    newton_cg iterations) with the AE store and with checkpointing, from the same
+    start model; the two updates are compared."""
+    import torch
+    alpha, theta = 2e-6, (4 * p.dx * p.dx,) * 3
+    res = {"max_cg": args.newton_cg, "prior": {"alpha": alpha, "theta_m2": theta[0]}}
+    upd = {}
+    for name, sol in (("ae", ae_solver), ("checkpoint", ck)):
+        sol.set_prior(alpha, theta, c0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c1, recs, it, reason = sol.newton_cg(c0, wav, d_obs, sigma, max_newton=1, max_cg=args.newton_cg,
+                                             eta_max=1e-6, gauss_newton=1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r0 = recs[0]
+        res[name] = {"wall_s": round(wall, 3), "hessvec": r0["cg_iters"], "gradients": 1 + 1 + r0["backtracks"],
+                     "step": r0["step"], "cost": [round(r["cost"], 4) for r in recs],
+                     "gnorm_ratio": round(recs[-1]["gnorm"] / r0["gnorm"], 5)}
+        upd[name] = (c1 - c0).double()
+        sol.set_prior(0.0)
+    res["speedup_vs_checkpoint"] = round(res["checkpoint"]["wall_s"] / res["ae"]["wall_s"], 4)
+    res["update_rel_err_vs_checkpoint"] = round(float(torch.linalg.norm(upd["ae"] - upd["checkpoint"]) /
+                                                      torch.linalg.norm(upd["checkpoint"])), 5)
+    return res
 
 
 def adjoint_bytes_per_cell(T, block):
