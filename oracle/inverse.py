@@ -19,6 +19,9 @@ theta_a (u_nb - u) / dx^2, where faces on the domain boundary carry zero flux
     R(c) = 1/2 dx^dims ||A (c - c0)||^2,  grad R = dx^dims A A (c - c0),
     Hess R = dx^dims A A    (A is symmetric).
 
+Prior draws (Sec. 3.3.1, Algorithm 1 trains the compressor on forward solves at
+draws from the prior): c = c0 + A^-1 w / sqrt(dx^dims), w white noise.
+
 Newton-CG (Sec. 4; the method of its references on inexact Newton-CG for
 wave inversion):
   * CG on H p = -g from p = 0, stopped when ||r|| <= eta ||g|| with the
@@ -79,6 +82,28 @@ def prior_hessvec(dc, alpha, theta, dx):
     """dx^dims A A dc."""
     vol = cell_volume(dc.shape, dx)
     return vol * prior_operator(prior_operator(dc, alpha, theta, dx), alpha, theta, dx)
+
+
+def prior_sample(w, c0, alpha, theta, dx):
+    """A draw from the prior N(c0, (dx^dims A A)^-1) for white noise w ~ N(0, I):
+    c = c0 + A^-1 w / sqrt(dx^dims) (covariance A^-1 A^-1 / dx^dims, A symmetric).
+    The solve is exact: the cell-centred cosine modes diagonalise A (the
+    orthonormal type-II DCT along each axis), with eigenvalues
+    alpha (1 + sum_a theta_a / dx^2 (2 - 2 cos(pi k_a / n_a)))."""
+    from scipy.fft import dctn, idctn
+
+    w = np.asarray(w, np.float64)
+    lam = np.full(w.shape, 1.0)
+    for axis, n in enumerate(w.shape):
+        if n == 1:
+            continue
+        sh = [1, 1, 1]
+        sh[axis] = n
+        k = np.arange(n).reshape(sh)
+        lam = lam + float(theta[axis]) / dx ** 2 * (2.0 - 2.0 * np.cos(np.pi * k / n))
+    lam = alpha * lam
+    b = w / np.sqrt(cell_volume(w.shape, dx))
+    return c0 + idctn(dctn(b, type=2, norm="ortho") / lam, type=2, norm="ortho")
 
 
 @dataclass

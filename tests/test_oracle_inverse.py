@@ -83,6 +83,34 @@ def test_prior_cost_constant_offset_and_derivatives():
     assert abs(R2 - 0.5 * dx ** 2 * alpha ** 2 * c2.size) < 1e-9 * R2
 
 
+@pytest.mark.parametrize("shape", [(6, 5, 7), (9, 1, 8)])
+def test_prior_sample_inverts_the_operator(shape):
+    """c = c0 + A^-1 w / sqrt(vol): applying A (the finite-volume stencil, not the
+    spectral form the sampler uses) to c - c0 returns w / sqrt(vol); and the
+    sample covariance over many draws on a tiny grid approaches (vol A A)^-1."""
+    rng = np.random.default_rng(8)
+    alpha, dx, theta = 0.05, 20.0, (1600.0, 900.0, 2500.0)
+    c0 = 2000.0 + 10 * rng.random(shape)
+    w = rng.standard_normal(shape)
+    vol = oi.cell_volume(shape, dx)
+    c = oi.prior_sample(w, c0, alpha, theta, dx)
+    np.testing.assert_allclose(oi.prior_operator(c - c0, alpha, theta, dx) * np.sqrt(vol), w, rtol=1e-10, atol=1e-10)
+    if shape[1] == 1:
+        return
+    small = (2, 2, 3)
+    n = int(np.prod(small))
+    M = np.zeros((n, n))
+    for col in range(n):
+        e = np.zeros(n)
+        e[col] = 1.0
+        M[:, col] = oi.prior_operator(e.reshape(small), alpha, theta, dx).ravel()
+    cov = np.linalg.inv(oi.cell_volume(small, dx) * M @ M)
+    draws = np.stack([oi.prior_sample(rng.standard_normal(small), np.zeros(small), alpha, theta, dx).ravel()
+                      for _ in range(20000)])
+    emp = draws.T @ draws / len(draws)
+    assert np.abs(emp - cov).max() < 0.05 * np.abs(cov).max()
+
+
 def test_cg_solves_spd_system_and_stops_on_negative_curvature():
     rng = np.random.default_rng(5)
     n = 12
