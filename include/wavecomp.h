@@ -241,6 +241,16 @@ int wv_prior(wv_ctx* ctx, const float* c, float* g, double* h_cost);
 /* Hdc += dx^dims A A dc (nothing without a prior). */
 int wv_prior_hessvec(wv_ctx* ctx, const float* dc, float* Hdc);
 
+/* A draw from the prior N(c0, (dx^dims A A)^-1) (Sec. 3.3.1, Algorithm 1: the
+ * compressor's training states come from forward solves at prior draws):
+ * out = c0 + x with A x = w / sqrt(dx^dims), for white noise w [N] (device, drawn
+ * by the caller). x is found by conjugate gradients from 0 (A is symmetric
+ * positive definite) until |r| <= rtol |w / sqrt(dx^dims)| or maxit iterations;
+ * *h_iters and *h_relres (may be NULL) report the iterations and the final
+ * relative residual. WV_ESTATE without a prior. Uses the Newton-CG work vectors. */
+int wv_prior_sample(wv_ctx* ctx, const float* w, float* out, double rtol, int32_t maxit, int32_t* h_iters,
+                    double* h_relres);
+
 typedef struct wv_newton_cfg {
     int32_t max_newton;     /* Newton iterations (>= 0) */
     int32_t max_cg;         /* conjugate-gradient iterations per Newton step (>= 1) */
@@ -322,6 +332,14 @@ int ae_load(const char* path, ae_net** out);
  * meta [P][4][2] = (min, r) per patch and field with r = max(max - min, beta_f). */
 int ae_normalize(const ae_net* net, const wv_grid* grid, const float* state, uint16_t* y,
                  float* meta, void* stream);
+
+/* The rows of ae_normalize for the listed patches only: row q of y [nrows][2048]
+ * and meta [nrows][4][2] is patch rows[q] (device int32, each in [0, P), checked
+ * before launch: WV_EINVAL otherwise). Keeping a random subset of the patch
+ * vectors of each state is the write-or-discard step of the training-data
+ * generation (Sec. 3.3.1, Algorithm 1). */
+int ae_normalize_rows(const ae_net* net, const wv_grid* grid, const float* state, const int32_t* rows,
+                      int32_t nrows, uint16_t* y, float* meta, void* stream);
 
 /* Compress one state [4][N]: per-patch normalisation, encoder, latent store.
  * latent: [P][latent] bfloat16 (AE_LATENT_BF16) or e4m3 bytes (AE_LATENT_FP8);

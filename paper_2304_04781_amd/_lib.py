@@ -94,6 +94,10 @@ EXPORTS = {
     "wv_set_delta_storage": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_decode_delta": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p]),
     "wv_set_prior": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "wv_prior_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "ae_normalize_rows": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
     "wv_prior": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "wv_prior_hessvec": (C.c_int, [C.c_void_p] * 3),
     "wv_newton_cg": (C.c_int, [C.c_void_p] * 4 + [C.c_double, C.POINTER(WvNewtonCfg), C.c_void_p,
@@ -393,3 +397,18 @@ def wv_newton_cg(ctx, c, wavelet, d_obs, sigma, max_newton=5, max_cg=10, eta_max
                                recs, C.byref(it), C.byref(reason)))
     log = [{f: getattr(recs[i], f) for f in NEWTON_FIELDS} for i in range(it.value + 1)]
     return log, it.value, reason.value
+
+
+def wv_prior_sample(ctx, w, out, rtol=1e-6, maxit=1000):
+    """out = c0 + A^-1 w / sqrt(vol); returns (CG iterations, final relative residual)."""
+    it, rr = C.c_int32(), C.c_double()
+    f32 = torch.float32
+    _check(load().wv_prior_sample(ctx, ptr(w, f32), ptr(out, f32), float(rtol), int(maxit), C.byref(it),
+                                  C.byref(rr)))
+    return it.value, rr.value
+
+
+def ae_normalize_rows(net, grid, state, rows, y, meta, stream=None) -> int:
+    n = 0 if rows is None else int(rows.numel())
+    return _check(load().ae_normalize_rows(net, C.byref(grid), ptr(state, torch.float32), ptr(rows, torch.int32), n,
+                                           ptr(y), ptr(meta, torch.float32), stream_handle(stream)))

@@ -1,6 +1,9 @@
-"""The learned compressor: an autoencoder handle and the training pipeline
-that feeds it snapshots of the solver's own forward solve (the paper's
-Algorithm 1 with the current model in place of prior draws, Sec. 3.3.1).
+"""The learned compressor: an autoencoder handle and the training pipelines
+of Sec. 3.3.1. train_from_forward feeds it snapshots of the solver's own
+forward solve (Algorithm 1 with the current model in place of prior draws);
+prior_draw_samples + train_samples follow Algorithm 1 itself: forward solves
+at draws from the prior, each state's patch vectors kept or discarded at
+random.
 
 Every step runs in libwavecomp.so: the forward solve captures raw states,
 ae_fit_beta sets the per-field floors, ae_normalize builds the bfloat16
@@ -58,6 +61,60 @@ class Autoencoder:
             self.close()
         except Exception:
             pass
+
+
+def prior_draw_samples(solver, ae: Autoencoder, draws, wavelet, every: int, rows, beta_rel: float = 1e-7):
+    """Training vectors from forward solves at the speed models `draws` (prior
+    draws, Sec. 3.3.1 Algorithm 1). Of every `every`-th state of draw i, the
+    patches rows[i][q] (int32 arrays, the random keep choice) are normalised into
+    y [n][2048] bfloat16 bits and meta [n][4][2]. The floors beta_f come from the
+    first draw's captured states. Returns (y, meta, capture seconds)."""
+    nz, ny, nx = solver.shape
+    total = sum(len(r) for rr in rows for r in rr)
+    dev = solver.device
+    y = torch.empty((total, 2048), dtype=torch.int16, device=dev)
+    meta = torch.empty((total, 4, 2), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    off = 0
+    for i, c in enumerate(draws):
+        _, _, cap = solver.forward(c, wavelet, capture_every=every)
+        ncap = cap.shape[0] * solver.S
+        cap = cap.reshape((ncap, 4) + solver.shape)
+        if len(rows[i]) != ncap:
+            raise ValueError(f"draw {i}: {len(rows[i])} row lists for {ncap} captured states")
+        if i == 0:
+            L.ae_fit_beta(ae.handle, solver.grid, cap, ncap, beta_rel)
+        for q in range(ncap):
+            n = len(rows[i][q])
+            r = torch.as_tensor(rows[i][q], dtype=torch.int32, device=dev)
+            L.ae_normalize_rows(ae.handle, solver.grid, cap[q], r, y[off:off + n], meta[off:off + n])
+            off += n
+        torch.cuda.synchronize()
+        del cap
+    torch.cuda.empty_cache()
+    return y, meta, time.perf_counter() - t0
+
+
+def train_samples(ae: Autoencoder, y, meta, epochs: int, batch: int, perms: Optional[np.ndarray] = None,
+                  weighting: int = 0, lr: float = 1e-3, decay_every: int = 5, decay_factor: float = 0.5):
+    """Adam on the training vectors y (with meta for the weighted loss).
+    Returns a dict with sizes, first/last epoch losses and timings."""
+    nsamp = int(y.shape[0])
+    perm_t = None
+    if perms is not None:
+        perm_t = torch.as_tensor(np.ascontiguousarray(perms, dtype=np.int32), device=y.device)
+    cfg = L.train_cfg(epochs=epochs, batch=batch, lr=lr, decay_every=decay_every, decay_factor=decay_factor,
+                      weighting=weighting)
+    t1 = time.perf_counter()
+    losses = L.ae_train(ae.handle, y, nsamp, cfg, perm_t, meta=meta)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    steps = epochs * (nsamp // batch)
+    flops = steps * batch * 6.0 * 2 * (2048 * 512 + 512 * 32 + 32 * 512 + 512 * 2048) / 2
+    return {"samples": nsamp, "epochs": int(epochs), "batch": int(batch), "adam_steps": int(steps),
+            "loss_first": float(losses[0]) if len(losses) else None,
+            "loss_last": float(losses[-1]) if len(losses) else None,
+            "train_s": round(t_train, 3), "train_TFLOP/s": round(flops / max(t_train, 1e-9) / 1e12, 1)}
 
 
 def train_from_forward(solver, ae: Autoencoder, c, wavelet, every: int, epochs: int, batch: int,

@@ -261,11 +261,14 @@ void gemm_auto(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, 
 // ------------------------------------------------------------------------------------
 // normalisation: one work-group per patch, one wave per field (8 values per lane)
 // ------------------------------------------------------------------------------------
+// one work-group per output row: patch p = rows ? rows[row] : row (rows checked on the host)
 __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict__ state, int ny, int nx,
                                                        long long N, int Py, int Px, const float* __restrict__ beta,
+                                                       const int32_t* __restrict__ rows,
                                                        uint16_t* __restrict__ y, float* __restrict__ meta)
 {
-    const long long p = blockIdx.x;
+    const long long row = blockIdx.x;
+    const long long p = rows ? (long long)rows[row] : row;
     const int f = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int px = p % Px, py = (p / Px) % Py, pz = p / ((long long)Px * Py);
     const int lz = l >> 3, ly = l & 7;
@@ -286,10 +289,10 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict_
     const float rinv = 1.0f / r;
     const uint4 o8 = make_uint4(f2bf2((v[0] - lo) * rinv, (v[1] - lo) * rinv), f2bf2((v[2] - lo) * rinv, (v[3] - lo) * rinv),
                                 f2bf2((v[4] - lo) * rinv, (v[5] - lo) * rinv), f2bf2((v[6] - lo) * rinv, (v[7] - lo) * rinv));
-    *reinterpret_cast<uint4*>(y + p * 2048 + f * 512 + l * 8) = o8;
+    *reinterpret_cast<uint4*>(y + row * 2048 + f * 512 + l * 8) = o8;
     if (l == 0) {
-        meta[p * 8 + 2 * f] = lo;
-        meta[p * 8 + 2 * f + 1] = r;
+        meta[row * 8 + 2 * f] = lo;
+        meta[row * 8 + 2 * f + 1] = r;
     }
 }
 
@@ -602,7 +605,16 @@ void normalize_state(const ae_net* a, const PatchGrid& pg, const float* state, u
 {
     const long long N = (long long)pg.nz * pg.ny * pg.nx;
     hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)pg.P), dim3(256), 0, st, state, pg.ny, pg.nx, N, pg.ny / 8,
-                       pg.nx / 8, a->beta_d, y, meta);
+                       pg.nx / 8, a->beta_d, (const int32_t*)nullptr, y, meta);
+    WV_HIP(hipGetLastError());
+}
+
+void normalize_rows(const ae_net* a, const PatchGrid& pg, const float* state, const int32_t* rows, int nrows,
+                    uint16_t* y, float* meta, hipStream_t st)
+{
+    const long long N = (long long)pg.nz * pg.ny * pg.nx;
+    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)nrows), dim3(256), 0, st, state, pg.ny, pg.nx, N, pg.ny / 8,
+                       pg.nx / 8, a->beta_d, rows, y, meta);
     WV_HIP(hipGetLastError());
 }
 
@@ -1067,6 +1079,26 @@ int ae_normalize(const ae_net* a, const wv_grid* g, const float* state, uint16_t
         WV_REQUIRE(a && state && y && meta, WV_EINVAL, "null argument");
         check_grid(g);
         normalize_state(a, patch_grid(g->nz, g->ny, g->nx), state, y, meta, (hipStream_t)stream);
+        return WV_OK;
+    });
+}
+
+int ae_normalize_rows(const ae_net* a, const wv_grid* g, const float* state, const int32_t* rows, int32_t nrows,
+                      uint16_t* y, float* meta, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && state && (nrows == 0 || (rows && y && meta)), WV_EINVAL, "null argument");
+        WV_REQUIRE(nrows >= 0, WV_EINVAL, "nrows must be >= 0");
+        check_grid(g);
+        const PatchGrid pg = patch_grid(g->nz, g->ny, g->nx);
+        if (nrows == 0) return WV_OK;
+        // every row must name a patch of the grid before the kernel reads it
+        std::vector<int32_t> h((size_t)nrows);
+        const hipStream_t st = (hipStream_t)stream;
+        WV_HIP(hipMemcpyAsync(h.data(), rows, sizeof(int32_t) * nrows, hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        for (int32_t v : h) WV_REQUIRE(v >= 0 && v < pg.P, WV_EINVAL, "row index outside the patch grid");
+        normalize_rows(a, pg, state, rows, nrows, y, meta, st);
         return WV_OK;
     });
 }

@@ -1468,6 +1468,46 @@ int wv_prior_hessvec(wv_ctx* c, const float* dc, float* Hdc)
     });
 }
 
+int wv_prior_sample(wv_ctx* c, const float* w, float* out, double rtol, int32_t maxit, int32_t* h_iters,
+                    double* h_relres)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && w && out, WV_EINVAL, "null argument");
+        WV_REQUIRE(c->prior_alpha > 0.0, WV_ESTATE, "no prior set (wv_set_prior with alpha > 0)");
+        WV_REQUIRE(rtol > 0.0 && rtol < 1.0 && maxit >= 1, WV_EINVAL, "rtol in (0, 1) and maxit >= 1 required");
+        const long long N = c->N;
+        if (!c->nvec) c->nvec = dev_alloc<float>(7 * (size_t)N);
+        float* x = c->nvec;
+        float* r = x + N;
+        float* d = x + 2 * N;
+        float* Ad = x + 3 * N;
+        // conjugate gradients on A x = w / sqrt(dx^dims) from x = 0 (A is symmetric positive definite)
+        launch_fill(x, N, 0.f, c->st);
+        launch_axpby(r, w, 1.0 / std::sqrt(cell_volume(c)), 0.0, N, c->st);
+        launch_copy(d, r, N, c->st);
+        double rr = dot_host(c, r, r);
+        const double b = std::sqrt(rr);
+        int it = 0;
+        double rel = b > 0.0 ? 1.0 : 0.0;
+        while (rel > rtol && it < maxit) {
+            apply_prior(c, d, nullptr, Ad, 1.0, false);
+            const double a = rr / dot_host(c, d, Ad);
+            launch_axpby(x, d, a, 1.0, N, c->st);
+            launch_axpby(r, Ad, -a, 1.0, N, c->st);
+            const double rr_new = dot_host(c, r, r);
+            ++it;
+            rel = std::sqrt(rr_new) / b;
+            launch_axpby(d, r, 1.0, rr_new / rr, N, c->st);
+            rr = rr_new;
+        }
+        launch_lincomb(out, c->prior_c0, 1.0, x, N, c->st);
+        WV_HIP(hipStreamSynchronize(c->st));
+        if (h_iters) *h_iters = it;
+        if (h_relres) *h_relres = rel;
+        return WV_OK;
+    });
+}
+
 int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_obs, double sigma,
                  const wv_newton_cfg* cfg, wv_newton_rec* h_log, int32_t* h_iters, int32_t* h_reason)
 {

@@ -137,6 +137,13 @@ class WaveSolver:
         """BiLaplacian prior with mean c0 (copied); alpha = 0 removes it."""
         L.wv_set_prior(self.ctx, alpha, theta, None if c0 is None else self._f32(c0))
 
+    def prior_sample(self, w, rtol: float = 1e-6, maxit: int = 2000):
+        """A prior draw c0 + A^-1 w / sqrt(vol) for white noise w; returns
+        (draw, CG iterations, final relative residual)."""
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        it, rr = L.wv_prior_sample(self.ctx, self._f32(w), out, rtol, maxit)
+        return out, it, rr
+
     def prior(self, c):
         """(R(c), grad R(c))."""
         g = torch.zeros(self.shape, dtype=torch.float32, device=self.device)

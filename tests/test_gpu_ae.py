@@ -236,6 +236,27 @@ def trained_net(p, every=4, epochs=40, weighting=0):
     return net, losses
 
 
+def test_normalize_rows_selects_rows_bitwise():
+    """ae_normalize_rows writes, row for row, the listed patches' rows of
+    ae_normalize (repeats allowed); indices outside the grid are refused."""
+    net = Net(W.ae_init(seed=4), beta=(1e-9, 2e-9, 3e-9, 4e-9))
+    _, ts = state_tensor(SHAPE, 2)
+    g = grid_of(SHAPE)
+    P = 30
+    y = torch.empty((P, 2048), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    L.ae_normalize(net.handle, g, ts, y, meta)
+    rows = torch.tensor([0, 29, 7, 7, 13], dtype=torch.int32, device="cuda")
+    yr = torch.empty((5, 2048), dtype=torch.int16, device="cuda")
+    mr = torch.empty((5, 4, 2), dtype=torch.float32, device="cuda")
+    L.ae_normalize_rows(net.handle, g, ts, rows, yr, mr)
+    assert torch.equal(yr, y[rows.long()]) and torch.equal(mr, meta[rows.long()])
+    for bad in ([30], [-1]):
+        with pytest.raises(L.WvError):
+            L.ae_normalize_rows(net.handle, g, ts, torch.tensor(bad, dtype=torch.int32, device="cuda"), yr[:1], mr[:1])
+    L.ae_normalize_rows(net.handle, g, ts, None, None, None)   # nothing to do
+
+
 def test_all_patches_exact_reproduces_full_storage():
     """With every patch kept exactly (K = P) the compressed store returns the
     true e, so gradient and Hv equal the full-storage ones bit for bit."""
@@ -416,3 +437,89 @@ def test_newton_cg_from_compressed_stores_equals_full_storage():
     assert it0 == it1 == 2
     assert torch.equal(c0, c1)
     assert [r["cost"] for r in log0] == [r["cost"] for r in log1]
+
+
+def state_error(p, net, c, every=8):
+    """Relative L2 error of the decoded e over every `every`-th state of the
+    forward solve at c (encode then decode, latents only)."""
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    _, _, cap = s.forward(c, p.wavelet, capture_every=every)
+    g = s.grid
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    lat = torch.empty((P, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    out = torch.zeros((4,) + s.shape, dtype=torch.float32, device="cuda")
+    num = den = 0.0
+    for q in range(cap.shape[0]):
+        L.ae_encode(net.handle, g, cap[q, 0], L.LATENT_BF16, lat, meta)
+        L.ae_decode(net.handle, g, lat, meta, None, L.LATENT_BF16, 1, out)
+        e = cap[q, 0, 0].double()
+        num += float(((out[0].double() - e) ** 2).sum())
+        den += float((e ** 2).sum())
+    return (num / den) ** 0.5
+
+
+def test_training_on_prior_draws():
+    """Algorithm 1 with draws from the BiLaplacian prior about the start model
+    (pointwise std about 100 m/s, correlation length about 10 cells): four forward
+    solves, each state's patches kept with probability 1/4, so the training set has
+    the size of the in-run set (every 4th state at c_start). Both networks are
+    judged by the compression error of e over the states of the start model, the
+    true model, the model halfway between and a held-out prior draw, and by the
+    compressed gradient (latents only) against full storage at the start and
+    halfway models (at the true model the gradient is noise only)."""
+    from paper_2304_04781_amd import compressor as C
+    p = ae_problem(nt=240, shape=(48, 48, 48))
+    p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    d = np.asarray(d, np.float32)
+    net_run, _ = trained_net(p)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    theta = (1e4, 1e4, 1e4)
+    s.set_prior(1.0, theta, p.c_start)
+    probe, _, _ = s.prior_sample(W.white_noise(p.c_start.shape, 100))
+    c0 = s._f32(p.c_start)
+    alpha = float((probe - c0).std()) / 100.0        # a draw scales as 1 / alpha
+    s.set_prior(alpha, theta, p.c_start)
+    draws = []
+    for i in range(5):
+        c, it, rr = s.prior_sample(W.white_noise(p.c_start.shape, 101 + i))
+        assert rr <= 1e-6
+        draws.append(c)
+    held_out = draws.pop()
+    std = float(torch.stack([c - c0 for c in draws]).std())
+    print("prior alpha", alpha, "draw std", std, flush=True)
+    assert 80.0 < std < 120.0
+    every, P = 4, 6 * 6 * 6
+    ncap = (p.nt - 1) // every
+    rows = W.keep_rows(4, ncap, P, 0.25, seed=6)
+    net_prior = Net(W.ae_init(seed=4))
+    y, meta, _ = C.prior_draw_samples(s, net_prior, draws, p.wavelet, every, rows)
+    n = int(y.shape[0])
+    assert n == sum(len(r) for rr in rows for r in rr)
+    info = C.train_samples(net_prior, y, meta, epochs=40, batch=64, perms=W.shuffles(n, 40, seed=5), decay_every=10)
+    print("prior-draw training", info, flush=True)
+    assert info["loss_last"] < 0.1 * info["loss_first"]
+    nets = (("in-run", net_run), ("prior draws", net_prior))
+    models = {"start": p.c_start, "true": p.c_true, "mid": 0.5 * (p.c_start + p.c_true), "held-out draw": held_out}
+    serr, gerr = {}, {}
+    for name, c in models.items():
+        for label, net in nets:
+            serr[(name, label)] = state_error(p, net, c)
+        if name in ("start", "mid"):
+            plain = WaveSolver.for_problem(p)
+            plain.set_storage(L.STORE_FULL)
+            _, g0 = plain.gradient(c, p.wavelet, d, sigma)
+            g0n = g0.cpu().numpy().astype(np.float64)
+            for label, net in nets:
+                a = WaveSolver.for_problem(p)
+                a.set_storage(L.STORE_AE_BF16, ae=net)
+                _, g = a.gradient(c, p.wavelet, d, sigma)
+                gerr[(name, label)] = rel(g.cpu().numpy(), g0n)
+    for k in serr:
+        print("model", k[0], "network", k[1], "e rel err", round(serr[k], 4),
+              "grad rel err", round(gerr[k], 4) if k in gerr else "-", flush=True)
+    assert all(np.isfinite(v) and v < 0.5 for v in list(serr.values()) + list(gerr.values()))

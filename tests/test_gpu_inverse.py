@@ -130,3 +130,22 @@ def test_newton_cg_argument_checks():
     c, log, it, reason = s.newton_cg(p.c_start, p.wavelet, d, sigma, max_newton=0)
     assert it == 0 and reason == 0 and len(log) == 1
     assert np.array_equal(c.cpu().numpy(), np.float32(p.c_start))
+
+
+@pytest.mark.parametrize("which", ["3d", "2d"])
+def test_prior_sample_matches_oracle(which):
+    """A prior draw by conjugate gradients on the GPU against the oracle's exact
+    cosine-mode solve for the same white noise (float32 CG to 1e-6 residual,
+    condition number of A about 1 + 12 theta / dx^2 = 49)."""
+    p = rounded(W.problem_3d(24, 20, 28, 10, sponge=3) if which == "3d" else W.problem_2d_small(nt=10))
+    print("case", which, p.name, flush=True)
+    w = f32(W.white_noise(p.c_start.shape, 7))
+    ref = oi.prior_sample(w, p.c_start, ALPHA, THETA, p.dx)
+    s = WaveSolver.for_problem(p)
+    with pytest.raises(L.WvError):   # no prior set
+        s.prior_sample(w)
+    s.set_prior(ALPHA, THETA, p.c_start)
+    c, it, rr = s.prior_sample(w, rtol=1e-6)
+    print("CG iterations", it, "relative residual", rr, flush=True)
+    assert rr <= 1e-6 and it < 2000
+    assert rel(c.cpu().numpy() - p.c_start, ref - p.c_start) < 1e-4

@@ -253,3 +253,17 @@ def smooth_random_state(nf: int, nz: int, ny: int, nx: int, seed: int,
     env = np.exp(rng.uniform(np.log(1e-6), 0.0, size=(1, nz // 8 + 1, ny // 8 + 1, nx // 8 + 1)))
     env = np.repeat(np.repeat(np.repeat(env, 8, axis=1), 8, axis=2), 8, axis=3)
     return out * env[:, :nz, :ny, :nx]
+
+
+def white_noise(shape, seed: int) -> np.ndarray:
+    """Standard normal draws (the noise of one prior draw), float64."""
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def keep_rows(ndraws: int, nstates: int, npatches: int, keep: float, seed: int) -> List[List[np.ndarray]]:
+    """For each draw and each captured state, the sorted patch indices kept
+    (each patch independently with probability `keep`): the random
+    write-or-discard choice of the training-data generation."""
+    rng = np.random.default_rng(seed)
+    return [[np.flatnonzero(rng.random(npatches) < keep).astype(np.int32) for _ in range(nstates)]
+            for _ in range(ndraws)]
