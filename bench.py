@@ -52,6 +52,10 @@ def parse():
                     help="kernel rates of the 8-source 512 x 512 x 256 workload with FP8 latents (horizon --ms-nt); "
                          "prints its own JSON line")
     ap.add_argument("--ms-nt", type=int, default=120)
+    ap.add_argument("--bayes", action="store_true",
+                    help="training on prior draws (Algorithm 1) against in-run snapshots at 256^3: "
+                         "compression and gradient errors on the start, true, midway and a held-out model")
+    ap.add_argument("--draws", type=int, default=4)
     ap.add_argument("--no-newton", action="store_true",
                     help="skip the timed Newton-CG iteration (AE store vs checkpointing)")
     ap.add_argument("--newton-cg", type=int, default=10, help="CG iterations of the timed Newton step")
@@ -195,6 +199,106 @@ def multisource_pass(args):
                               "the exception selection and copy on a side stream"}), flush=True)
 
 
+def bayes_pass(args):
+    """Algorithm 1 at 256^3 x 2000: the in-run network (every 10th state at c_start) against a
+    network trained on `draws` forward solves at BiLaplacian prior draws about c_start (pointwise
+    std 100 m/s, theta = 1e4 m^2), each state's patches kept with probability 1/draws, so both
+    training sets hold the same number of vectors; same epochs, batch and schedule."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd import compressor as C
+    from paper_2304_04781_amd.solver import WaveSolver
+    L.load()
+    dev = torch.device("cuda", 0)
+    T, every = args.nt, args.snapshot_every
+    p = W.problem_256(T)
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    K_exc = int(round(args.exceptions * P))
+    c_true = torch.tensor(p.c_true, dtype=torch.float32, device=dev)
+    c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    clean, _, _ = s.forward(c_true, wav)
+    clean_h = clean.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * float(np.abs(clean_h).max())
+    d_obs = torch.tensor((clean_h + sigma * p.noise).astype(np.float32), device=dev)
+    del clean
+    ncap = (T - 1) // every
+    nets, info = {}, {}
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    info["in-run"] = C.train_from_forward(s, net, c0, wav, every=every, epochs=args.epochs, batch=args.batch,
+                                          perms=W.shuffles(ncap * P, args.epochs, seed=5))
+    nets["in-run"] = net
+    log(f"in-run training {info['in-run']}")
+    theta = (1e4, 1e4, 1e4)
+    s.set_prior(1.0, theta, c0)
+    probe, _, _ = s.prior_sample(torch.tensor(W.white_noise(p.c_start.shape, 100), dtype=torch.float32, device=dev))
+    alpha = float((probe - c0).std()) / 100.0        # a draw scales as 1 / alpha
+    del probe
+    s.set_prior(alpha, theta, c0)
+    draws, cg = [], []
+    for i in range(args.draws + 1):
+        c, it, rr = s.prior_sample(torch.tensor(W.white_noise(p.c_start.shape, 101 + i), dtype=torch.float32,
+                                                device=dev))
+        draws.append(c)
+        cg.append(it)
+    held_out = draws.pop()
+    rows = W.keep_rows(args.draws, ncap, P, 1.0 / args.draws, seed=6)
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    y, meta, t_cap = C.prior_draw_samples(s, net, draws, wav, every, rows)
+    n = int(y.shape[0])
+    info["prior draws"] = dict(C.train_samples(net, y, meta, args.epochs, args.batch,
+                                               perms=W.shuffles(n, args.epochs, seed=5)), capture_s=round(t_cap, 2))
+    del y, meta
+    torch.cuda.empty_cache()
+    nets["prior draws"] = net
+    log(f"prior-draw training {info['prior draws']}")
+    models = {"start": c0, "true": c_true, "mid": 0.5 * (c0 + c_true), "held-out draw": held_out}
+    g = s.grid
+    lat = torch.empty((P, 32), dtype=torch.int16, device=dev)
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device=dev)
+    out = torch.zeros((4,) + s.shape, dtype=torch.float32, device=dev)
+    table = {}
+    for name, c in models.items():
+        _, _, cap = s.forward(c, wav, capture_every=4 * every)
+        row = {}
+        for label, nt_ in nets.items():
+            num = den = 0.0
+            for q in range(cap.shape[0]):
+                L.ae_encode(nt_.handle, g, cap[q, 0], L.LATENT_BF16, lat, meta)
+                L.ae_decode(nt_.handle, g, lat, meta, None, L.LATENT_BF16, 1, out)
+                e = cap[q, 0, 0].double()
+                num += float(((out[0].double() - e) ** 2).sum())
+                den += float((e ** 2).sum())
+            row[label] = {"e_rel_err": round((num / den) ** 0.5, 4)}
+        del cap
+        if name in ("start", "mid"):
+            ck = WaveSolver.for_problem(p)
+            ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
+            _, gc = ck.gradient(c, wav, d_obs, sigma)
+            gc = gc.double()
+            ck.close()
+            for label, nt_ in nets.items():
+                a = WaveSolver.for_problem(p)
+                L.wv_set_ae_exceptions(a.ctx, K_exc)
+                a.set_storage(L.STORE_AE_BF16, ae=nt_)
+                _, ga = a.gradient(c, wav, d_obs, sigma)
+                ga = ga.double()
+                row[label]["grad_rel_err"] = round(float(torch.linalg.norm(ga - gc) / torch.linalg.norm(gc)), 4)
+                row[label]["grad_cos"] = round(float(torch.sum(ga * gc) / torch.linalg.norm(ga) /
+                                                     torch.linalg.norm(gc)), 5)
+                a.close()
+        table[name] = row
+        log(f"model {name}: {row}")
+    print(json.dumps({"workload": f"{p.name}: compressor trained in-run vs on {args.draws} prior draws",
+                      "prior": {"alpha": alpha, "theta_m2": theta[0], "pointwise_std_target": 100.0,
+                                "cg_iterations": cg},
+                      "training": info, "exceptions": K_exc,
+                      "e_error_every_states": 4 * every, "errors": table}), flush=True)
+
+
 def main():
     args = parse()
     if args.counters:
@@ -202,6 +306,9 @@ def main():
         return
     if args.multisource:
         multisource_pass(args)
+        return
+    if args.bayes:
+        bayes_pass(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
