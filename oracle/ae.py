@@ -8,6 +8,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
     "compression data structure" of Sec. 3.3.1). Here a block is 8^3 cells
     of the 4 fields (e, v_z, v_y, v_x): x_p[f*512 + lz*64 + ly*8 + lx],
     patch p = (pz*Py + py)*Px + px.
+  * Time compression (Sec. 3.2): one field on a 4^3 block of cells over a
+    window of 32 consecutive time levels forms a vector (see time_vectors).
   * Normalisation (Sec. 3.3.1): r = max(max x - min x, beta),
     y = (x - min x) / r, applied per field slice of 512 values
     (the paper treats each state variable independently, Sec. 3);
@@ -62,6 +64,51 @@ def unpatchify(X: np.ndarray, nz: int, ny: int, nx: int) -> np.ndarray:
     x = X.reshape(nz // 8, ny // 8, nx // 8, nf, 8, 8, 8)
     x = x.transpose(3, 0, 4, 1, 5, 2, 6)
     return x.reshape(nf, nz, ny, nx).copy()
+
+
+# ----- time compression layout (Sec. 3.2) ---------------------------------------
+# Each vector holds one field (e, the only one the reverse solves read) on a
+# 4^3 block of cells over a window of TWIN consecutive time levels:
+# x_b[t*64 + lz*16 + ly*4 + lx], block b = (bz*By + by)*Bx + bx, t = 0..TWIN-1.
+TBLOCK = 4
+TWIN = 32
+
+
+def time_vectors(e_win: np.ndarray) -> np.ndarray:
+    """e_win [TWIN, nz, ny, nx] (consecutive levels) -> X [B, TWIN*64]."""
+    w, nz, ny, nx = e_win.shape
+    x = e_win.reshape(w, nz // 4, 4, ny // 4, 4, nx // 4, 4)
+    x = x.transpose(1, 3, 5, 0, 2, 4, 6)
+    return x.reshape(-1, w * 64).copy()
+
+
+def untime_vectors(X: np.ndarray, nz: int, ny: int, nx: int) -> np.ndarray:
+    w = X.shape[1] // 64
+    x = X.reshape(nz // 4, ny // 4, nx // 4, w, 4, 4, 4)
+    x = x.transpose(3, 0, 4, 1, 5, 2, 6)
+    return x.reshape(w, nz, ny, nx).copy()
+
+
+def pad_window(e_states: np.ndarray, w: int = TWIN) -> np.ndarray:
+    """A window with fewer than w levels (the last one of a solve) is filled by
+    repeating its last level."""
+    n = e_states.shape[0]
+    return np.concatenate([e_states, np.repeat(e_states[n - 1:n], w - n, axis=0)]) if n < w else e_states
+
+
+def normalize_vectors(X: np.ndarray, beta: float, emulate: bool = False):
+    """Min/range normalisation of each whole vector (Sec. 3.3.1): lo [B], r [B],
+    Y = (X - lo) / r with r = max(max - min, beta); emulate as in normalize."""
+    lo = X.min(axis=1)
+    hi = X.max(axis=1)
+    if emulate:
+        r = np.maximum(rd.f32(hi - lo), rd.f32(np.float64(beta)))
+        rinv = rd.f32(1.0 / r)
+        Y = rd.f32(rd.f32(X - lo[:, None]) * rinv[:, None])
+    else:
+        r = np.maximum(hi - lo, beta)
+        Y = (X - lo[:, None]) / r[:, None]
+    return Y, lo, r
 
 
 # ----- normalisation ----------------------------------------------------------

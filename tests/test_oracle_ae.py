@@ -31,6 +31,47 @@ def test_patch_layout_brute_force():
     assert np.array_equal(oae.unpatchify(X, 16, 8, 24), st)
 
 
+def test_time_layout_brute_force():
+    """Time vectors by explicit loops over the definition: e on block (bz, by, bx)
+    at level t, cell (lz, ly, lx) sits at entry t*64 + lz*16 + ly*4 + lx of vector
+    (bz*By + by)*Bx + bx; the inverse layout returns the window."""
+    rng = np.random.default_rng(3)
+    nz, ny, nx, w = 8, 4, 12, 32
+    e = rng.standard_normal((w, nz, ny, nx))
+    X = oae.time_vectors(e)
+    By, Bx = ny // 4, nx // 4
+    ref = np.zeros(((nz // 4) * By * Bx, w * 64))
+    for t in range(w):
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    b = ((k // 4) * By + j // 4) * Bx + i // 4
+                    ref[b, t * 64 + (k % 4) * 16 + (j % 4) * 4 + i % 4] = e[t, k, j, i]
+    assert np.array_equal(X, ref)
+    assert np.array_equal(oae.untime_vectors(X, nz, ny, nx), e)
+    # a short last window repeats its last level
+    part = oae.pad_window(e[:5])
+    assert part.shape == e.shape and np.array_equal(part[:5], e[:5])
+    assert all(np.array_equal(part[t], e[4]) for t in range(5, w))
+    assert oae.pad_window(e) is e
+
+
+def test_vector_normalisation_special_cases():
+    """Whole-vector min/range: a constant vector maps to 0 with r = beta; the
+    minimum maps to 0 and the maximum to 1; x = lo + r y within FP32 rounding."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((6, 2048)) * 1e-6
+    X[2] = 3.0e-7
+    Y, lo, r = oae.normalize_vectors(X, 1e-12, emulate=True)
+    assert np.all(Y[2] == 0.0) and r[2] == rd.f32(np.float64(1e-12))
+    for q in (0, 1, 3):
+        assert Y[q, np.argmin(X[q])] == 0.0
+        assert abs(Y[q, np.argmax(X[q])] - 1.0) < 1e-6
+        assert np.max(np.abs(lo[q] + r[q] * Y[q] - X[q])) < 1e-6 * r[q]
+    Y64, lo64, r64 = oae.normalize_vectors(X, 1e-12)
+    assert np.max(np.abs(Y64 - Y)) < 1e-6
+
+
 def test_normalisation_special_cases():
     rng = np.random.default_rng(1)
     X = rng.standard_normal((6, 2048)) * 10.0 ** rng.uniform(-12, 3, size=(6, 1))
