@@ -70,6 +70,11 @@ extern "C" {
                                    compression, 8^3-cell x 4-field patches) */
 #define WV_STORE_AE_FP8      4  /* autoencoder latents in OCP FP8 E4M3FN with one
                                    float32 scale per patch */
+#define WV_STORE_AE_TIME     5  /* time compression (Sec. 3.2): e only, 4^3 cells x 32
+                                   consecutive levels per vector, bfloat16 latents;
+                                   the reverse solves decode a whole window at once.
+                                   Needs nz, ny, nx divisible by 4; no exception
+                                   patches, guard or fallback (space modes only) */
 
 /* Latent formats of ae_encode / ae_decode. */
 #define AE_LATENT_BF16  0
@@ -185,6 +190,18 @@ int wv_storage_bytes(const wv_ctx* ctx, int64_t* h_bytes);
  * the training snapshots of the learned compressor. */
 int wave_forward(wv_ctx* ctx, const float* c, const float* wavelet, float* traces,
                  float* final_state, float* capture, int32_t capture_every);
+
+/* wave_forward that also copies e^n of every source at the nsteps listed levels
+ * h_steps[q] (host, distinct, each in [1, T]) into e_out [nsteps][S][N] in list
+ * order (the training levels of the time-compression network); no traces out. */
+int wave_forward_e(wv_ctx* ctx, const float* c, const float* wavelet, const int32_t* h_steps,
+                   int32_t nsteps, float* e_out);
+
+/* e^n [S][N] (1 <= n <= T-1) as the reverse solves read it from the store of the
+ * last forward solve: the float32 copy (full storage), the decoded state with its
+ * exact patches (AE modes) or the decoded window level (time compression).
+ * WV_ESTATE without such a store (checkpointing included). Synchronises. */
+int wv_load_e(wv_ctx* ctx, int32_t n, float* out);
 
 /* Reverse-time adjoint solve consuming the store of the last wave_forward at the
  * same c: returns g = J_F^T w, i.e. g = -2 dt c * sum_n e^n * q^n for the adjoint
@@ -340,6 +357,32 @@ int ae_normalize(const ae_net* net, const wv_grid* grid, const float* state, uin
  * generation (Sec. 3.3.1, Algorithm 1). */
 int ae_normalize_rows(const ae_net* net, const wv_grid* grid, const float* state, const int32_t* rows,
                       int32_t nrows, uint16_t* y, float* meta, void* stream);
+
+/* ---- time compression (paper Sec. 3.2) ---------------------------------------------
+ * A vector holds one field, e (the only one the reverse solves read), on a 4^3
+ * block of cells over a window of 32 consecutive time levels: entry
+ * t*64 + lz*16 + ly*4 + lx, vector s*B + b for source s (grid->nsrc sources) and
+ * block b = (bz*By + by)*Bx + bx, B = (nz/4)(ny/4)(nx/4). A window buffer e_win
+ * holds levels [32][S][N] (or [nvalid][S][N]); a window of nvalid < 32 levels
+ * (the last of a solve) is completed by repeating its last level. Each vector is
+ * normalised as a whole, r = max(max - min, beta_e) (Sec. 3.3.1, beta_e = the
+ * net's first floor). The net must have in_dim 2048. WV_ESHAPE unless the grid is
+ * 3D with nz, ny, nx divisible by 4; WV_EINVAL for nvalid outside [1, 32]. */
+
+/* beta_e = rel * max |e| over nlevels levels e [nlevels][S][N]. */
+int ae_time_fit_beta(ae_net* net, const wv_grid* grid, const float* e, int64_t nlevels, double rel,
+                     void* stream);
+/* Normalised vectors y [n][2048] (bfloat16 bits) and meta [n][2] = (lo, r) of the
+ * vectors rows[0..nrows) (device int32 in [0, S*B), checked before launch), or of
+ * all S*B vectors in order when rows is NULL (n = S*B). */
+int ae_time_normalize(const ae_net* net, const wv_grid* grid, const float* e_win, int32_t nvalid,
+                      const int32_t* rows, int32_t nrows, uint16_t* y, float* meta, void* stream);
+/* Compress a window: latent [S*B][latent] bfloat16, meta [S*B][2]. */
+int ae_time_encode(const ae_net* net, const wv_grid* grid, const float* e_win, int32_t nvalid,
+                   uint16_t* latent, float* meta, void* stream);
+/* Decompress into levels 0..nvalid-1 of the window buffer e_win. */
+int ae_time_decode(const ae_net* net, const wv_grid* grid, const uint16_t* latent, const float* meta,
+                   int32_t nvalid, float* e_win, void* stream);
 
 /* Compress one state [4][N]: per-patch normalisation, encoder, latent store.
  * latent: [P][latent] bfloat16 (AE_LATENT_BF16) or e4m3 bytes (AE_LATENT_FP8);

@@ -14,7 +14,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwavecomp.so")
 
-STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AE_BF16, STORE_AE_FP8 = range(5)
+STORE_NONE, STORE_FULL, STORE_CHECKPOINT, STORE_AE_BF16, STORE_AE_FP8, STORE_AE_TIME = range(6)
+TWIN = 32   # levels per time-compression window
 LATENT_BF16, LATENT_FP8 = 0, 1
 FALLBACK_NONE, FALLBACK_CHECKPOINT = 0, 1
 OK, OK_FALLBACK = 0, 1
@@ -94,6 +95,15 @@ EXPORTS = {
     "wv_set_delta_storage": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_decode_delta": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p]),
     "wv_set_prior": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "wave_forward_e": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_void_p]),
+    "wv_load_e": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ae_time_fit_beta": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
+    "ae_time_normalize": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ae_time_encode": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    "ae_time_decode": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                 C.c_void_p]),
     "wv_prior_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "ae_normalize_rows": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
@@ -412,3 +422,35 @@ def ae_normalize_rows(net, grid, state, rows, y, meta, stream=None) -> int:
     n = 0 if rows is None else int(rows.numel())
     return _check(load().ae_normalize_rows(net, C.byref(grid), ptr(state, torch.float32), ptr(rows, torch.int32), n,
                                            ptr(y), ptr(meta, torch.float32), stream_handle(stream)))
+
+
+def wave_forward_e(ctx, c, wavelet, steps, e_out) -> int:
+    st = np.ascontiguousarray(np.asarray(steps, dtype=np.int32).reshape(-1))
+    return _check(load().wave_forward_e(ctx, ptr(c, torch.float32), ptr(wavelet, torch.float32),
+                                        st.ctypes.data if st.size else None, int(st.size), ptr(e_out, torch.float32)))
+
+
+def wv_load_e(ctx, n: int, out) -> int:
+    return _check(load().wv_load_e(ctx, int(n), ptr(out, torch.float32)))
+
+
+def ae_time_fit_beta(net, grid, e, nlevels: int, rel: float, stream=None) -> int:
+    return _check(load().ae_time_fit_beta(net, C.byref(grid), ptr(e, torch.float32), int(nlevels), float(rel),
+                                          stream_handle(stream)))
+
+
+def ae_time_normalize(net, grid, e_win, nvalid: int, y, meta, rows=None, stream=None) -> int:
+    n = 0 if rows is None else int(rows.numel())
+    return _check(load().ae_time_normalize(net, C.byref(grid), ptr(e_win, torch.float32), int(nvalid),
+                                           ptr(rows, torch.int32), n, ptr(y), ptr(meta, torch.float32),
+                                           stream_handle(stream)))
+
+
+def ae_time_encode(net, grid, e_win, nvalid: int, latent, meta, stream=None) -> int:
+    return _check(load().ae_time_encode(net, C.byref(grid), ptr(e_win, torch.float32), int(nvalid), ptr(latent),
+                                        ptr(meta, torch.float32), stream_handle(stream)))
+
+
+def ae_time_decode(net, grid, latent, meta, nvalid: int, e_win, stream=None) -> int:
+    return _check(load().ae_time_decode(net, C.byref(grid), ptr(latent), ptr(meta, torch.float32), int(nvalid),
+                                        ptr(e_win, torch.float32), stream_handle(stream)))

@@ -95,6 +95,40 @@ def prior_draw_samples(solver, ae: Autoencoder, draws, wavelet, every: int, rows
     return y, meta, time.perf_counter() - t0
 
 
+def time_window_samples(solver, ae: Autoencoder, c, wavelet, windows, rows=None, beta_rel: float = 1e-7):
+    """Training vectors of the time-compression scheme (Sec. 3.2): e over the
+    listed windows (window w holds levels 32 w + 1 .. 32 w + 32, the last one
+    possibly short) of one forward solve at c, normalised per vector; rows[i]
+    (int32 arrays, optional) keeps only those vectors of window i. The floor
+    beta_e comes from the captured levels. Returns (y, meta, capture seconds)."""
+    T1 = solver.nt - 1
+    nv = [min(L.TWIN, T1 - L.TWIN * w) for w in windows]
+    if min(nv) < 1:
+        raise ValueError("window beyond the stored levels")
+    steps = [L.TWIN * w + 1 + t for w, n in zip(windows, nv) for t in range(n)]
+    t0 = time.perf_counter()
+    e = solver.forward_e(c, wavelet, steps)
+    torch.cuda.synchronize()
+    t_cap = time.perf_counter() - t0
+    L.ae_time_fit_beta(ae.handle, solver.grid, e, len(steps), beta_rel)
+    nz, ny, nx = solver.shape
+    M = solver.S * (nz // 4) * (ny // 4) * (nx // 4)
+    counts = [M if rows is None else len(rows[i]) for i in range(len(windows))]
+    y = torch.empty((sum(counts), 2048), dtype=torch.int16, device=solver.device)
+    meta = torch.empty((sum(counts), 2), dtype=torch.float32, device=solver.device)
+    off = lvl = 0
+    for i, n in enumerate(nv):
+        r = None if rows is None else torch.as_tensor(rows[i], dtype=torch.int32, device=solver.device)
+        L.ae_time_normalize(ae.handle, solver.grid, e[lvl:lvl + n], n, y[off:off + counts[i]],
+                            meta[off:off + counts[i]], rows=r)
+        off += counts[i]
+        lvl += n
+    torch.cuda.synchronize()
+    del e
+    torch.cuda.empty_cache()
+    return y, meta, t_cap
+
+
 def train_samples(ae: Autoencoder, y, meta, epochs: int, batch: int, perms: Optional[np.ndarray] = None,
                   weighting: int = 0, lr: float = 1e-3, decay_every: int = 5, decay_factor: float = 0.5):
     """Adam on the training vectors y (with meta for the weighted loss).

@@ -249,6 +249,27 @@ void gemm(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipSt
 }
 
 // wide N (>= 128) and narrow N (<= 32) tile shapes
+struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) into levels t < nvalid
+    float* e_win;
+    const float* meta;  // [S*B][2]
+    const float* bias;  // b4
+    int S, ny, nx, By, Bx, nvalid;
+    long long B, N;
+    __device__ __forceinline__ void operator()(int row, int c, float v, int) const
+    {
+        const int t = c >> 6;
+        if (t >= nvalid) return;
+        const float yv = v + bias[c];
+        const float lo = meta[(long long)row * 2], rr = meta[(long long)row * 2 + 1];
+        const int s = (int)(row / B);
+        const long long b = row % B;
+        const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+        const int cell = c & 63, lz = cell >> 4, ly = (cell >> 2) & 3, lx = cell & 3;
+        e_win[((long long)t * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly) * nx + bx * 4 + lx] =
+            lo + rr * yv;
+    }
+};
+
 template <class LA, class LB, class EPI>
 void gemm_auto(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
 {
@@ -293,6 +314,56 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict_
     if (l == 0) {
         meta[row * 8 + 2 * f] = lo;
         meta[row * 8 + 2 * f + 1] = r;
+    }
+}
+
+// time vectors: one work-group per vector; thread i holds level t = i / 8 (the
+// last valid level for t >= nvalid) and cells 8 (i % 8) .. + 7 of the block, i.e.
+// the x-rows (lz, ly0) and (lz, ly0 + 1) with lz = (i % 8) / 2, ly0 = 2 (i % 2)
+__global__ void __launch_bounds__(256) time_normalize_kernel(const float* __restrict__ e_win, int S, int ny, int nx,
+                                                            long long N, int By, int Bx, long long B, int nvalid,
+                                                            const float* __restrict__ beta,
+                                                            const int32_t* __restrict__ rows,
+                                                            uint16_t* __restrict__ y, float* __restrict__ meta)
+{
+    const long long row = blockIdx.x;
+    const long long vix = rows ? (long long)rows[row] : row;
+    const int s = (int)(vix / B);
+    const long long b = vix % B;
+    const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+    const int t = threadIdx.x >> 3, q = threadIdx.x & 7;
+    const int tl = t < nvalid ? t : nvalid - 1;
+    const int lz = q >> 1, ly0 = (q & 1) * 2;
+    const float* src =
+        e_win + ((long long)tl * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly0) * nx + bx * 4;
+    const float4 a = *reinterpret_cast<const float4*>(src);
+    const float4 c = *reinterpret_cast<const float4*>(src + nx);
+    const float v[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+    float lo = v[0], hi = v[0];
+    for (int k = 1; k < 8; ++k) {
+        lo = fminf(lo, v[k]);
+        hi = fmaxf(hi, v[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    __shared__ float slo[4], shi[4];
+    if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    lo = fminf(fminf(slo[0], slo[1]), fminf(slo[2], slo[3]));
+    hi = fmaxf(fmaxf(shi[0], shi[1]), fmaxf(shi[2], shi[3]));
+    const float r = fmaxf(hi - lo, beta[0]);
+    const float rinv = 1.0f / r;
+    const uint4 o8 = make_uint4(f2bf2((v[0] - lo) * rinv, (v[1] - lo) * rinv), f2bf2((v[2] - lo) * rinv, (v[3] - lo) * rinv),
+                                f2bf2((v[4] - lo) * rinv, (v[5] - lo) * rinv), f2bf2((v[6] - lo) * rinv, (v[7] - lo) * rinv));
+    *reinterpret_cast<uint4*>(y + row * (TWIN * 64) + t * 64 + q * 8) = o8;
+    if (threadIdx.x == 0) {
+        meta[row * 2] = lo;
+        meta[row * 2 + 1] = r;
     }
 }
 
@@ -618,6 +689,14 @@ void normalize_rows(const ae_net* a, const PatchGrid& pg, const float* state, co
     WV_HIP(hipGetLastError());
 }
 
+void check_time_grid(const wv_grid* g)
+{
+    WV_REQUIRE(g, WV_EINVAL, "null grid");
+    WV_REQUIRE(g->ny > 1 && g->nz % 4 == 0 && g->ny % 4 == 0 && g->nx % 4 == 0 && g->nsrc >= 1, WV_ESHAPE,
+               "time compression needs a 3D grid divisible into 4^3 blocks");
+}
+
+
 template <class F>
 int guarded_ae(F&& f)
 {
@@ -635,6 +714,7 @@ int guarded_ae(F&& f)
 }  // namespace
 
 int ae_latent_dim(const ae_net* net) { return net->lat; }
+int ae_input_dim(const ae_net* net) { return net->in; }
 
 long long ae_latent_bytes_per_patch(const ae_net* net, int fmt)
 {
@@ -706,6 +786,48 @@ void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state
                            qscale);
         WV_HIP(hipGetLastError());
     }
+}
+
+void ae_time_normalize_rows(const ae_net* a, const TimeGrid& tg, const float* e_win, int nvalid,
+                            const int32_t* rows, long long nrows, uint16_t* y, float* meta, hipStream_t st)
+{
+    WV_REQUIRE(a->in == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
+    WV_REQUIRE(nvalid >= 1 && nvalid <= TWIN, WV_EINVAL, "nvalid must lie in [1, 32]");
+    if (nrows == 0) return;
+    const long long N = (long long)tg.nz * tg.ny * tg.nx;
+    hipLaunchKernelGGL(time_normalize_kernel, dim3((unsigned)nrows), dim3(256), 0, st, e_win, tg.S, tg.ny, tg.nx, N,
+                       tg.ny / 4, tg.nx / 4, tg.B, nvalid, a->beta_d, rows, y, meta);
+    WV_HIP(hipGetLastError());
+}
+
+void ae_time_encode(const ae_net* a, const TimeGrid& tg, const float* e_win, int nvalid, uint16_t* latent,
+                    float* meta, hipStream_t st)
+{
+    const long long M = tg.B * tg.S;
+    const size_t oh = align256(M * (size_t)a->in * 2);
+    uint8_t* ws = (uint8_t*)workspace(a, align256(oh + M * (size_t)a->hid * 2));
+    uint16_t* y = (uint16_t*)ws;
+    uint16_t* h = (uint16_t*)(ws + oh);
+    ae_time_normalize_rows(a, tg, e_win, nvalid, nullptr, M, y, meta, st);
+    gemm_auto((int)M, a->hid, a->in, LoadK{y, a->in, nullptr, (int)M, a->in},
+              LoadK{a->wt[0], a->in, nullptr, a->hid, a->in}, EpiGelu{h, a->hid, a->bias(0), nullptr}, st);
+    gemm_auto((int)M, a->lat, a->hid, LoadK{h, a->hid, nullptr, (int)M, a->hid},
+              LoadK{a->wt[1], a->hid, nullptr, a->lat, a->hid}, EpiBF16{latent, a->lat, a->bias(1), nullptr}, st);
+}
+
+void ae_time_decode(const ae_net* a, const TimeGrid& tg, const uint16_t* latent, const float* meta, int nvalid,
+                    float* e_win, hipStream_t st)
+{
+    WV_REQUIRE(a->in == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
+    WV_REQUIRE(nvalid >= 1 && nvalid <= TWIN, WV_EINVAL, "nvalid must lie in [1, 32]");
+    const long long M = tg.B * tg.S;
+    uint16_t* h = (uint16_t*)workspace(a, align256(M * (size_t)a->hid * 2));
+    gemm_auto((int)M, a->hid, a->lat, LoadK{latent, a->lat, nullptr, (int)M, a->lat},
+              LoadK{a->wt[2], a->lat, nullptr, a->hid, a->lat}, EpiGelu{h, a->hid, a->bias(2), nullptr}, st);
+    const long long N = (long long)tg.nz * tg.ny * tg.nx;
+    gemm_auto((int)M, a->in, a->hid, LoadK{h, a->hid, nullptr, (int)M, a->hid},
+              LoadK{a->wt[3], a->hid, nullptr, a->in, a->hid},
+              EpiTimeDenorm{e_win, meta, a->bias(3), tg.S, tg.ny, tg.nx, tg.ny / 4, tg.nx / 4, nvalid, tg.B, N}, st);
 }
 
 void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
@@ -1099,6 +1221,76 @@ int ae_normalize_rows(const ae_net* a, const wv_grid* g, const float* state, con
         WV_HIP(hipStreamSynchronize(st));
         for (int32_t v : h) WV_REQUIRE(v >= 0 && v < pg.P, WV_EINVAL, "row index outside the patch grid");
         normalize_rows(a, pg, state, rows, nrows, y, meta, st);
+        return WV_OK;
+    });
+}
+
+int ae_time_fit_beta(ae_net* a, const wv_grid* g, const float* e, int64_t nlevels, double rel, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && g && e && nlevels > 0 && rel > 0, WV_EINVAL, "bad argument");
+        check_time_grid(g);
+        hipStream_t st = (hipStream_t)stream;
+        const long long n = nlevels * g->nsrc * (long long)g->nz * g->ny * g->nx;
+        constexpr int NB = 1024;
+        double* d = dalloc<double>(3 * NB + 3);
+        launch_range(e, n, d, NB, d + 3 * NB, st);
+        double h[3];
+        WV_HIP(hipMemcpyAsync(h, d + 3 * NB, sizeof(h), hipMemcpyDeviceToHost, st));
+        WV_HIP(hipStreamSynchronize(st));
+        (void)hipFree(d);
+        WV_REQUIRE(h[2] == 0.0, WV_EINVAL, "e contains NaN");
+        const double m = std::max(std::fabs(h[0]), std::fabs(h[1]));
+        a->beta[0] = m > 0 ? rel * m : rel;
+        upload_beta(a);
+        return WV_OK;
+    });
+}
+
+int ae_time_normalize(const ae_net* a, const wv_grid* g, const float* e_win, int32_t nvalid, const int32_t* rows,
+                      int32_t nrows, uint16_t* y, float* meta, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && e_win && y && meta, WV_EINVAL, "null argument");
+        check_time_grid(g);
+        const TimeGrid tg = time_grid(g->nz, g->ny, g->nx, g->nsrc);
+        const hipStream_t st = (hipStream_t)stream;
+        long long n = tg.B * tg.S;
+        if (rows) {
+            WV_REQUIRE(nrows >= 0, WV_EINVAL, "nrows must be >= 0");
+            std::vector<int32_t> h((size_t)nrows);
+            if (nrows) {
+                WV_HIP(hipMemcpyAsync(h.data(), rows, sizeof(int32_t) * nrows, hipMemcpyDeviceToHost, st));
+                WV_HIP(hipStreamSynchronize(st));
+            }
+            for (int32_t v : h) WV_REQUIRE(v >= 0 && v < n, WV_EINVAL, "row index outside the block grid");
+            n = nrows;
+        }
+        ae_time_normalize_rows(a, tg, e_win, nvalid, rows, n, y, meta, st);
+        return WV_OK;
+    });
+}
+
+int ae_time_encode(const ae_net* a, const wv_grid* g, const float* e_win, int32_t nvalid, uint16_t* latent,
+                   float* meta, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && e_win && latent && meta, WV_EINVAL, "null argument");
+        check_time_grid(g);
+        wv::ae_time_encode(a, time_grid(g->nz, g->ny, g->nx, g->nsrc), e_win, nvalid, latent, meta,
+                           (hipStream_t)stream);
+        return WV_OK;
+    });
+}
+
+int ae_time_decode(const ae_net* a, const wv_grid* g, const uint16_t* latent, const float* meta, int32_t nvalid,
+                   float* e_win, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && latent && meta && e_win, WV_EINVAL, "null argument");
+        check_time_grid(g);
+        wv::ae_time_decode(a, time_grid(g->nz, g->ny, g->nx, g->nsrc), latent, meta, nvalid, e_win,
+                           (hipStream_t)stream);
         return WV_OK;
     });
 }

@@ -15,7 +15,32 @@ inline PatchGrid patch_grid(int nz, int ny, int nx)
     return PatchGrid{nz, ny, nx, (long long)(nz / 8) * (ny / 8) * (nx / 8)};
 }
 
+// Time compression (paper Sec. 3.2): one vector holds e on a 4^3 block of cells
+// over TWIN consecutive time levels, entry t*64 + lz*16 + ly*4 + lx, vector
+// s*B + b for source s and block b = (bz*By + by)*Bx + bx. A window buffer holds
+// levels [TWIN][S][N]; a window of nvalid < TWIN levels repeats its last level.
+constexpr int TWIN = 32;
+struct TimeGrid {
+    int nz, ny, nx, S;
+    long long B;  // blocks per source
+};
+inline TimeGrid time_grid(int nz, int ny, int nx, int S)
+{
+    return TimeGrid{nz, ny, nx, S, (long long)(nz / 4) * (ny / 4) * (nx / 4)};
+}
+// normalised bf16 vectors y [nrows][TWIN*64] and (lo, r) meta [nrows][2] of the
+// vectors rows[0..nrows) (rows == nullptr: all S*B in order)
+void ae_time_normalize_rows(const ae_net* net, const TimeGrid& tg, const float* e_win, int nvalid,
+                            const int32_t* rows, long long nrows, uint16_t* y, float* meta, hipStream_t st);
+// compress a window into bf16 latents [S*B][L] and meta [S*B][2]
+void ae_time_encode(const ae_net* net, const TimeGrid& tg, const float* e_win, int nvalid, uint16_t* latent,
+                    float* meta, hipStream_t st);
+// decompress into the first nvalid levels of the window buffer
+void ae_time_decode(const ae_net* net, const TimeGrid& tg, const uint16_t* latent, const float* meta, int nvalid,
+                    float* e_win, hipStream_t st);
+
 int ae_latent_dim(const ae_net* net);
+int ae_input_dim(const ae_net* net);
 // bytes per patch of the latent store (latent codes only)
 long long ae_latent_bytes_per_patch(const ae_net* net, int fmt);
 

@@ -248,6 +248,17 @@ struct wv_ctx {
     double sigma = 1.0;
     long long last_fwd_steps = 0;
 
+    // time compression store: latents [nwin][S B][L] bf16, meta [nwin][S B][2] (lo, r),
+    // one window buffer [TWIN][S][N] (filled by the forward sweep, decoded into by the
+    // reverse sweeps)
+    uint16_t* tlat = nullptr;
+    float* tmeta = nullptr;
+    float* twin = nullptr;
+    int tdec_w = -1;             // window held decoded in twin (-1: none)
+    long long TB = 0;            // 4^3 blocks per source
+    int nwin = 0;
+    int tlat_dim = 0;
+
     // MAP layer: BiLaplacian prior and the Newton-CG work vectors
     double prior_alpha = 0.0;
     double prior_theta[3] = {0.0, 0.0, 0.0};
@@ -442,6 +453,10 @@ void free_store(wv_ctx* c)
     c->delta_bytes = 0;
     dev_free(c->mmpart);
     dev_free(c->work[2]);
+    dev_free(c->tlat);
+    dev_free(c->tmeta);
+    dev_free(c->twin);
+    c->tdec_w = -1;
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -482,6 +497,10 @@ void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
 }
 
 bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
+bool is_time(int mode) { return mode == WV_STORE_AE_TIME; }
+TimeGrid ctx_time_grid(const wv_ctx* c) { return time_grid(c->g.nz, c->g.ny, c->g.nx, c->S); }
+uint16_t* tlat_slot(wv_ctx* c, int w) { return c->tlat + (long long)w * c->TB * c->S * c->tlat_dim; }
+float* tmeta_slot(wv_ctx* c, int w) { return c->tmeta + (long long)w * c->TB * c->S * 2; }
 int ae_fmt(int mode) { return mode == WV_STORE_AE_FP8 ? AE_LATENT_FP8 : AE_LATENT_BF16; }
 
 
@@ -527,6 +546,17 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
         for (int s = 0; s < c->S; ++s)
             WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
+    } else if (is_time(c->mode)) {
+        // e^n joins its window; a full window (or the last, short one) is compressed
+        const int t = (n - 1) % TWIN, w = (n - 1) / TWIN;
+        for (int s = 0; s < c->S; ++s)
+            launch_copy(c->twin + ((long long)t * c->S + s) * c->N, state + s * 4 * c->N, c->N, c->st);
+        if (t == TWIN - 1 || n == c->T - 1) {
+            const int te = c->tm.begin(TM_ENCODE, c->st);
+            ae_time_encode(c->ae, ctx_time_grid(c), c->twin, t + 1, tlat_slot(c, w), tmeta_slot(c, w), c->st);
+            c->tm.end(te, c->st);
+            c->tdec_w = -1;
+        }
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
         const int te = c->tm.begin(TM_ENCODE, c->st);
@@ -663,6 +693,18 @@ const float* load_e(wv_ctx* c, int n, long long* stride)
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     *stride = c->N;
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
+    if (is_time(c->mode)) {
+        // the window of e^n, decoded once for all its levels
+        const int w = (n - 1) / TWIN;
+        if (w != c->tdec_w) {
+            const int nvalid = std::min(TWIN, c->T - 1 - w * TWIN);
+            const int td = c->tm.begin(TM_DECODE, c->st);
+            ae_time_decode(c->ae, ctx_time_grid(c), tlat_slot(c, w), tmeta_slot(c, w), nvalid, c->twin, c->st);
+            c->tm.end(td, c->st);
+            c->tdec_w = w;
+        }
+        return c->twin + (long long)((n - 1) % TWIN) * c->S * c->N;
+    }
     ensure_adj(c);  // owns the decode target ebuf
     decode_e(c, n, 0, c->st);
     return ebuf_slot(c, 0);
@@ -698,9 +740,10 @@ float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->w
 // store, writes checkpoint snapshots (snap[n] = slot of x_n or 0), captures.
 // Returns the buffer holding x_{T-1}; *last receives the one holding x_T.
 float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, float* capture, int every,
-                     float** last)
+                     float** last, const std::vector<int>* ecap_idx = nullptr, float* ecap = nullptr)
 {
     c->delta_ok = false;  // incremental states belong to the previous forward history
+    c->tdec_w = -1;
     // autoencoder stores run beside the steps (x_j in work[j % 3])
     const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
     if (ae && !c->work[2]) c->work[2] = dev_alloc<float>(c->state_floats());
@@ -731,6 +774,9 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
         if (ncap > 0 && j % every == 0 && j / every <= ncap)
             WV_HIP(hipMemcpyAsync(capture + (long long)(j / every - 1) * c->state_floats(), out,
                                   sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice, c->st));
+        if (ecap_idx && (*ecap_idx)[j] >= 0)
+            for (int s = 0; s < c->S; ++s)
+                launch_copy(ecap + ((long long)(*ecap_idx)[j] * c->S + s) * c->N, out + s * 4 * c->N, c->N, c->st);
         prev = cur;
         cur = out;
     }
@@ -973,7 +1019,7 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
 {
     return guarded([&]() -> int {
         WV_REQUIRE(c, WV_EINVAL, "null context");
-        WV_REQUIRE(mode >= WV_STORE_NONE && mode <= WV_STORE_AE_FP8, WV_EINVAL, "unknown storage mode");
+        WV_REQUIRE(mode >= WV_STORE_NONE && mode <= WV_STORE_AE_TIME, WV_EINVAL, "unknown storage mode");
         WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE || fallback_policy == WV_FALLBACK_CHECKPOINT, WV_EINVAL,
                    "unknown fallback policy");
         WV_HIP(hipStreamSynchronize(c->st));
@@ -996,6 +1042,23 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
         } else if (mode == WV_STORE_CHECKPOINT) {
             alloc_slots(c, n_checkpoints);
             c->store_bytes = (int64_t)(n_checkpoints - 1) * c->state_floats() * 4;
+        } else if (is_time(mode)) {
+            WV_REQUIRE(ae, WV_EINVAL, "time compression needs an ae_net");
+            WV_REQUIRE(ae_input_dim(ae) == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
+            WV_REQUIRE(c->has_y && c->g.nz % 4 == 0 && c->g.ny % 4 == 0 && c->g.nx % 4 == 0, WV_ESHAPE,
+                       "time compression needs a 3D grid divisible into 4^3 blocks");
+            WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE, WV_EINVAL,
+                       "the accuracy guard and its fallback apply to the space modes");
+            c->TB = ctx_time_grid(c).B;
+            c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
+            c->tlat_dim = ae_latent_dim(ae);
+            const long long rows = (long long)c->nwin * c->TB * c->S;
+            const long long bytes = rows * (c->tlat_dim * 2 + 8);
+            WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
+            c->tlat = dev_alloc<uint16_t>(rows * c->tlat_dim);
+            c->tmeta = dev_alloc<float>(rows * 2);
+            c->twin = dev_alloc<float>((size_t)TWIN * c->S * c->N);
+            c->store_bytes = bytes;
         } else if (is_ae(mode)) {
             WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
             WV_REQUIRE(c->has_y && c->g.nz % 8 == 0 && c->g.ny % 8 == 0 && c->g.nx % 8 == 0, WV_ESHAPE,
@@ -1084,38 +1147,90 @@ int wv_storage_bytes(const wv_ctx* c, int64_t* h_bytes)
     return WV_OK;
 }
 
+namespace {
+
+// forward solve filling the store of the current mode, with optional captures:
+// whole states every `every` steps, and e of the levels marked in ecap_idx
+void forward_solve(wv_ctx* c, const float* cdev, const float* wavelet, float* traces, float* final_state,
+                   float* capture, int every, const std::vector<int>* ecap_idx, float* ecap);
+
+}  // namespace
+
+int wave_forward_e(wv_ctx* c, const float* cdev, const float* wavelet, const int32_t* h_steps, int32_t nsteps,
+                   float* e_out)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && cdev && wavelet && nsteps >= 0 && (nsteps == 0 || (h_steps && e_out)), WV_EINVAL,
+                   "null argument or negative count");
+        std::vector<int> idx((size_t)c->T + 1, -1);
+        for (int q = 0; q < nsteps; ++q) {
+            const int n = h_steps[q];
+            WV_REQUIRE(n >= 1 && n <= c->T, WV_EINVAL, "capture level outside [1, T]");
+            WV_REQUIRE(idx[n] < 0, WV_EINVAL, "capture level listed twice");
+            idx[n] = q;
+        }
+        forward_solve(c, cdev, wavelet, nullptr, nullptr, nullptr, 0, &idx, e_out);
+        return WV_OK;
+    });
+}
+
+int wv_load_e(wv_ctx* c, int32_t n, float* out)
+{
+    return guarded([&]() -> int {
+        WV_REQUIRE(c && out, WV_EINVAL, "null argument");
+        WV_REQUIRE(c->store_ok && (c->mode == WV_STORE_FULL || is_ae(c->mode) || is_time(c->mode)), WV_ESTATE,
+                   "no stored forward history (full, autoencoder or time-compressed)");
+        WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_EINVAL, "level outside [1, T-1]");
+        long long stride;
+        const float* e = load_e(c, n, &stride);
+        for (int s = 0; s < c->S; ++s) launch_copy(out + (long long)s * c->N, e + s * stride, c->N, c->st);
+        WV_HIP(hipStreamSynchronize(c->st));
+        return WV_OK;
+    });
+}
+
 int wave_forward(wv_ctx* c, const float* cdev, const float* wavelet, float* traces, float* final_state,
                  float* capture, int32_t capture_every)
 {
     return guarded([&]() -> int {
         WV_REQUIRE(c && cdev && wavelet, WV_EINVAL, "null argument");
         WV_REQUIRE(!capture || capture_every >= 1, WV_EINVAL, "capture_every must be >= 1");
-        prepare_model(c, cdev, wavelet);
-        c->store_ok = false;
-        c->have_grad = false;
-        float* last = nullptr;
-        float* xtm1;
-        std::vector<RevAction> acts;
-        if (c->mode == WV_STORE_CHECKPOINT) {
-            long long fs = 0;
-            acts = revolve_schedule(c->T, c->nslots, &fs);
-            size_t first = 0;
-            const auto snap = sweep_snapshots(acts, c->T, &first);
-            xtm1 = forward_sweep(c, c->traces, &snap, capture, capture_every, &last);
-        } else {
-            xtm1 = forward_sweep(c, c->traces, nullptr, capture, capture_every, &last);
-        }
-        if (traces)
-            WV_HIP(hipMemcpyAsync(traces, c->traces, sizeof(float) * c->S * c->T * c->R, hipMemcpyDeviceToDevice,
-                                  c->st));
-        if (final_state)
-            WV_HIP(hipMemcpyAsync(final_state, last, sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice,
-                                  c->st));
-        run_guard(c, xtm1);
-        c->store_ok = c->mode != WV_STORE_NONE;
+        forward_solve(c, cdev, wavelet, traces, final_state, capture, capture_every, nullptr, nullptr);
         return WV_OK;
     });
 }
+
+namespace {
+
+void forward_solve(wv_ctx* c, const float* cdev, const float* wavelet, float* traces, float* final_state,
+               float* capture, int capture_every, const std::vector<int>* ecap_idx, float* ecap)
+{
+    prepare_model(c, cdev, wavelet);
+    c->store_ok = false;
+    c->have_grad = false;
+    float* last = nullptr;
+    float* xtm1;
+    std::vector<RevAction> acts;
+    if (c->mode == WV_STORE_CHECKPOINT) {
+        long long fs = 0;
+        acts = revolve_schedule(c->T, c->nslots, &fs);
+        size_t first = 0;
+        const auto snap = sweep_snapshots(acts, c->T, &first);
+        xtm1 = forward_sweep(c, c->traces, &snap, capture, capture_every, &last, ecap_idx, ecap);
+    } else {
+        xtm1 = forward_sweep(c, c->traces, nullptr, capture, capture_every, &last, ecap_idx, ecap);
+    }
+    if (traces)
+        WV_HIP(hipMemcpyAsync(traces, c->traces, sizeof(float) * c->S * c->T * c->R, hipMemcpyDeviceToDevice,
+                              c->st));
+    if (final_state)
+        WV_HIP(hipMemcpyAsync(final_state, last, sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice,
+                              c->st));
+    run_guard(c, xtm1);
+    c->store_ok = c->mode != WV_STORE_NONE;
+}
+
+}  // namespace
 
 int wave_adjoint(wv_ctx* c, const float* cdev, const float* residual, float* g)
 {

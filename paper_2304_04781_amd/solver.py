@@ -132,6 +132,18 @@ class WaveSolver:
         L.wave_inc_forward(self.ctx, self._f32(c), self._f32(dc), dtr)
         return dtr
 
+    def forward_e(self, c, wavelet, steps):
+        """Forward solve returning e^n of every source at the listed levels [len][S][nz][ny][nx]."""
+        e = torch.empty((len(steps), self.S) + self.shape, dtype=torch.float32, device=self.device)
+        L.wave_forward_e(self.ctx, self._f32(c), self._f32(wavelet), steps, e)
+        return e
+
+    def load_e(self, n: int):
+        """e^n [S][nz][ny][nx] as the reverse solves read it from the store."""
+        out = torch.empty((self.S,) + self.shape, dtype=torch.float32, device=self.device)
+        L.wv_load_e(self.ctx, n, out)
+        return out
+
     # ----- MAP point: BiLaplacian prior and Newton-CG --------------------------------------------
     def set_prior(self, alpha: float, theta=(0.0, 0.0, 0.0), c0=None) -> None:
         """BiLaplacian prior with mean c0 (copied); alpha = 0 removes it."""

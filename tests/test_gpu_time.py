@@ -1,0 +1,160 @@
+"""GPU parity of the time-compression scheme (paper Sec. 3.2): e on 4^3 blocks
+over 32 consecutive levels per vector.
+
+Normalisation is compared bit for bit with the oracle's emulated FP32
+arithmetic. Encoder and decoder are compared with the oracle network under
+bf16 rounding emulation (5e-3 relative, as for the space scheme). The solver's
+store is checked end to end: every level the reverse solves read equals, bit
+for bit, encode followed by decode of the exact window captured from the same
+forward solve."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ae as oae
+from oracle import rounding as rd
+from oracle import wave as ow
+from paper_2304_04781_amd import _lib as L
+from paper_2304_04781_amd.solver import WaveSolver
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (8, 12, 16)        # 2 x 3 x 4 = 24 blocks per source
+BETA_E = 1e-9
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+class Net:
+    def __init__(self, prm, beta=(BETA_E, 1e-7, 1e-7, 1e-7)):
+        self.prm32 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in prm.items()}
+        flat = np.concatenate([self.prm32[k].ravel() for k in oae.NAMES]).astype(np.float32)
+        self.handle = L.ae_create(2048, 512, 32, flat, np.asarray(beta, np.float64))
+
+    def __del__(self):
+        L.ae_destroy(self.handle)
+
+
+def grid_of(shape, nsrc):
+    nz, ny, nx = shape
+    return L.make_grid(nz, ny, nx, 20.0, 1e-3, 10, 0, 1.0, nsrc, 0)
+
+
+def window(seed, nsrc, shape=SHAPE):
+    """[32][S][nz][ny][nx] float32: smooth in time and space, amplitudes spanning decades."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(32)[:, None, None, None, None]
+    base = W.smooth_random_state(nsrc, *shape, seed=seed)[None]
+    scale = 10.0 ** rng.uniform(-9, -6, (1, nsrc, 1, 1, 1))
+    return (scale * (base * np.cos(0.1 * t) + 0.1 * rng.standard_normal((32, nsrc) + shape))).astype(np.float32)
+
+
+@pytest.mark.parametrize("nvalid", [32, 13])
+def test_time_normalize_bitwise(nvalid):
+    S = 2
+    net = Net(W.ae_init(seed=4))
+    e = window(1, S)
+    e[:, 0, :4, :4, :4] = 2.5e-8              # block 0 of source 0 constant in space and time: r = beta
+    g = grid_of(SHAPE, S)
+    B = 24
+    te = torch.tensor(e[:nvalid], device="cuda")
+    y = torch.empty((S * B, 2048), dtype=torch.int16, device="cuda")
+    meta = torch.empty((S * B, 2), dtype=torch.float32, device="cuda")
+    L.ae_time_normalize(net.handle, g, te, nvalid, y, meta)
+    yb = y.cpu().numpy().view(np.uint16)
+    m = meta.cpu().numpy()
+    for s in range(S):
+        X = oae.time_vectors(oae.pad_window(e[:nvalid, s].astype(np.float64)))
+        Y, lo, r = oae.normalize_vectors(X, np.float64(np.float32(BETA_E)), emulate=True)
+        assert np.array_equal(m[s * B:(s + 1) * B, 0], lo) and np.array_equal(m[s * B:(s + 1) * B, 1], r)
+        assert np.array_equal(yb[s * B:(s + 1) * B], rd.bf16_bits(Y))
+    assert np.all(yb[0] == 0)
+    # a subset of rows (any order, repeats), and refused indices
+    rows = torch.tensor([47, 0, 5, 5, 30], dtype=torch.int32, device="cuda")
+    yr = torch.empty((5, 2048), dtype=torch.int16, device="cuda")
+    mr = torch.empty((5, 2), dtype=torch.float32, device="cuda")
+    L.ae_time_normalize(net.handle, g, te, nvalid, yr, mr, rows=rows)
+    assert torch.equal(yr, y[rows.long()]) and torch.equal(mr, meta[rows.long()])
+    with pytest.raises(L.WvError):
+        L.ae_time_normalize(net.handle, g, te, nvalid, yr[:1], mr[:1],
+                            rows=torch.tensor([48], dtype=torch.int32, device="cuda"))
+    with pytest.raises(L.WvError):
+        L.ae_time_normalize(net.handle, g, te, 33, y, meta)
+
+
+def test_time_encode_decode_against_oracle():
+    S, B, nvalid = 2, 24, 20
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    e = window(2, S)
+    g = grid_of(SHAPE, S)
+    lat = torch.empty((S * B, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((S * B, 2), dtype=torch.float32, device="cuda")
+    L.ae_time_encode(net.handle, g, torch.tensor(e[:nvalid], device="cuda"), nvalid, lat, meta)
+    ae = oae.AE(net.prm32)
+    X = np.concatenate([oae.time_vectors(oae.pad_window(e[:nvalid, s].astype(np.float64))) for s in range(S)])
+    Y, lo, r = oae.normalize_vectors(X, np.float64(np.float32(BETA_E)), emulate=True)
+    z_o = ae.encode(Y, emulate=True)
+    z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16))
+    assert rel(z_gpu, rd.bf16(z_o)) < 5e-3
+    # decoder on seeded latents and metadata; levels >= nvalid are left alone
+    rng = np.random.default_rng(17)
+    zs = rd.bf16(0.5 * rng.standard_normal((S * B, 32)))
+    ms = np.stack([rng.uniform(-1.0, 1.0, S * B), rng.uniform(0.5, 2.0, S * B)], axis=1).astype(np.float32)
+    out = torch.full((32, S) + SHAPE, 7.0, dtype=torch.float32, device="cuda")
+    L.ae_time_decode(net.handle, g, torch.tensor(rd.bf16_bits(zs).view(np.int16), device="cuda"),
+                     torch.tensor(ms, device="cuda"), nvalid, out)
+    o = out.cpu().numpy()
+    dec = ae.decode(zs, emulate=True)
+    x = ms[:, :1].astype(np.float64) + ms[:, 1:].astype(np.float64) * dec
+    for s in range(S):
+        ref = oae.untime_vectors(x[s * B:(s + 1) * B], *SHAPE)
+        assert rel(o[:nvalid, s], ref[:nvalid]) < 5e-3
+    assert np.all(o[nvalid:] == 7.0)
+
+
+def time_problem(nt, shape=(32, 32, 40)):
+    p = W.problem_3d(*shape, nt, f0=15.0, sponge=8, name="time3d")
+    for k in ("c_true", "c_start", "wavelet"):
+        setattr(p, k, np.asarray(getattr(p, k), np.float32).astype(np.float64))
+    return p
+
+
+def test_time_store_levels_equal_window_roundtrip():
+    """T - 1 = 74 stored levels: two full windows and a short one of 10. Every level
+    the reverse solves read is the encode-decode round trip of the exact window
+    from the same forward solve; the store holds 3 windows of latents and (lo, r);
+    gradient and Gauss-Newton Hv run, the full-Newton product is refused."""
+    p = time_problem(75)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    net = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    e_all = s.forward_e(p.c_start, p.wavelet, list(range(1, 75)))
+    L.ae_time_fit_beta(net.handle, s.grid, e_all, 74, 1e-7)
+    t = WaveSolver.for_problem(p)
+    t.set_storage(L.STORE_AE_TIME, ae=net)
+    B = 8 * 8 * 10
+    assert t.storage_bytes() == 3 * B * (32 * 2 + 8)
+    J, g = t.gradient(p.c_start, p.wavelet, d, sigma)
+    assert torch.isfinite(g).all()
+    lat = torch.empty((B, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    dec = torch.empty((32, 1) + t.shape, dtype=torch.float32, device="cuda")
+    for w, nvalid in ((0, 32), (1, 32), (2, 10)):
+        win = e_all[32 * w:32 * w + nvalid]
+        L.ae_time_encode(net.handle, t.grid, win, nvalid, lat, meta)
+        L.ae_time_decode(net.handle, t.grid, lat, meta, nvalid, dec)
+        for lvl in sorted({0, nvalid // 2, nvalid - 1}):
+            n = 32 * w + 1 + lvl
+            assert torch.equal(t.load_e(n), dec[lvl]), n
+    H = t.hessvec(p.c_start, p.c_start * 0.01)
+    assert torch.isfinite(H).all()
+    with pytest.raises(L.WvError):
+        t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False)
