@@ -158,3 +158,50 @@ def test_time_store_levels_equal_window_roundtrip():
     assert torch.isfinite(H).all()
     with pytest.raises(L.WvError):
         t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False)
+
+
+def test_time_compressed_gradient_with_trained_network():
+    """The 48^3, 240-step problem of the space-scheme accuracy test (8 Hz): the
+    time network is trained on all 8 windows of the forward solve at the start
+    model; the compressed gradient and Gauss-Newton Hv are judged against full
+    storage. An untrained network is far worse."""
+    from paper_2304_04781_amd import compressor as C
+    p = time_problem(240, shape=(48, 48, 48))
+    p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    d = np.asarray(d, np.float32)
+    net = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    y, meta, _ = C.time_window_samples(s, net, p.c_start, p.wavelet, list(range(8)))
+    n = int(y.shape[0])
+    assert n == 8 * 12 ** 3
+    info = C.train_samples(net, y, None, epochs=40, batch=64, perms=W.shuffles(n, 40, seed=5), decay_every=10)
+    print("time-network training", info, flush=True)
+    assert info["loss_last"] < 0.1 * info["loss_first"]
+    plain = WaveSolver.for_problem(p)
+    plain.set_storage(L.STORE_FULL)
+    J0, g0 = plain.gradient(p.c_start, p.wavelet, d, sigma)
+    dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
+    H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+    g0n = g0.cpu().numpy().astype(np.float64)
+    t = WaveSolver.for_problem(p)
+    t.set_storage(L.STORE_AE_TIME, ae=net)
+    J, g = t.gradient(p.c_start, p.wavelet, d, sigma)
+    gn = g.cpu().numpy().astype(np.float64)
+    err = rel(gn, g0n)
+    cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
+    herr = rel(t.hessvec(p.c_start, dc).cpu().numpy(), H0)
+    print("time scheme: grad rel err", err, "cos", cos, "Hv rel err", herr,
+          "store bytes", t.storage_bytes(), "vs full", plain.storage_bytes(), flush=True)
+    assert J == J0
+    assert err < 0.2 and cos > 0.98 and herr < 0.2
+    raw = Net(W.ae_init(seed=4))
+    L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
+    u = WaveSolver.for_problem(p)
+    u.set_storage(L.STORE_AE_TIME, ae=raw)
+    _, gu = u.gradient(p.c_start, p.wavelet, d, sigma)
+    err_u = rel(gu.cpu().numpy(), g0n)
+    print("untrained rel err", err_u, flush=True)
+    assert err_u > 3 * err
