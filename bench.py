@@ -56,6 +56,9 @@ def parse():
                     help="training on prior draws (Algorithm 1) against in-run snapshots at 256^3: "
                          "compression and gradient errors on the start, true, midway and a held-out model")
     ap.add_argument("--draws", type=int, default=4)
+    ap.add_argument("--time", action="store_true",
+                    help="time-compression scheme at 256^3 x 2000: gradient and Gauss-Newton Hv against "
+                         "checkpointing (network trained on every 4th window of the start model's solve)")
     ap.add_argument("--no-newton", action="store_true",
                     help="skip the timed Newton-CG iteration (AE store vs checkpointing)")
     ap.add_argument("--newton-cg", type=int, default=10, help="CG iterations of the timed Newton step")
@@ -299,6 +302,89 @@ def bayes_pass(args):
                       "e_error_every_states": 4 * every, "errors": table}), flush=True)
 
 
+def time_pass(args):
+    """The time-compression scheme (e on 4^3 blocks x 32 levels) on the 256^3 x 2000 gradient workload."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd import compressor as C
+    from paper_2304_04781_amd.solver import WaveSolver
+    L.load()
+    dev = torch.device("cuda", 0)
+    T = args.nt
+    p = W.problem_256(T)
+    c_true = torch.tensor(p.c_true, dtype=torch.float32, device=dev)
+    c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    clean, _, _ = s.forward(c_true, wav)
+    clean_h = clean.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * float(np.abs(clean_h).max())
+    d_obs = torch.tensor((clean_h + sigma * p.noise).astype(np.float32), device=dev)
+    del clean
+    nwin = (T - 1 + L.TWIN - 1) // L.TWIN
+    windows = list(range(0, nwin, 4))
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    y, meta, t_cap = C.time_window_samples(s, net, c0, wav, windows)
+    n = int(y.shape[0])
+    info = dict(C.train_samples(net, y, None, args.epochs, args.batch, perms=W.shuffles(n, args.epochs, seed=5)),
+                windows=len(windows), capture_s=round(t_cap, 2))
+    del y, meta
+    torch.cuda.empty_cache()
+    log(f"time-network training {info}")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tm = WaveSolver.for_problem(p)
+    tm.set_storage(L.STORE_AE_TIME, ae=net)
+    tm.gradient(c0, wav, d_obs, sigma)
+    torch.cuda.synchronize()
+    tm.set_timing(1)
+    times = []
+    for _ in range(3):
+        ev0.record()
+        _, g_t = tm.gradient(c0, wav, d_obs, sigma)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / 1e3)
+    kt = {k: (round(us, 1), n) for k, (us, n) in tm.kernel_times().items() if n}
+    tm.set_timing(0)
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
+    ck.gradient(c0, wav, d_obs, sigma)
+    torch.cuda.synchronize()
+    ev0.record()
+    _, g_c = ck.gradient(c0, wav, d_obs, sigma)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_ck = ev0.elapsed_time(ev1) / 1e3
+    gt, gc = g_t.double(), g_c.double()
+    dc = c0 * torch.tensor(0.01 * W.direction_grf((p.nz, p.ny, p.nx), 12.0, seed=2), dtype=torch.float32, device=dev)
+    hv = {}
+    for name, sol in (("time", tm), ("checkpoint", ck)):
+        torch.cuda.synchronize()
+        ev0.record()
+        H = sol.hessvec(c0, dc)
+        ev1.record()
+        torch.cuda.synchronize()
+        hv[name] = (ev0.elapsed_time(ev1) / 1e3, H.double())
+    ht, hc = hv["time"][1], hv["checkpoint"][1]
+    out = {"workload": f"{p.name}: time compression (e on 4^3 blocks x {L.TWIN} levels, bf16 latents) "
+                       f"vs revolve checkpointing ({args.checkpoints} slots)",
+           "training": info,
+           "gradient_s": {"time": round(float(np.median(times)), 4), "runs": [round(x, 4) for x in times],
+                          "checkpoint": round(t_ck, 4)},
+           "speedup_vs_checkpoint": round(t_ck / float(np.median(times)), 4),
+           "grad_rel_err_vs_checkpoint": round(float(torch.linalg.norm(gt - gc) / torch.linalg.norm(gc)), 5),
+           "grad_cos": round(float(torch.sum(gt * gc) / torch.linalg.norm(gt) / torch.linalg.norm(gc)), 6),
+           "gn_hessvec_s": {"time": round(hv["time"][0], 4), "checkpoint": round(hv["checkpoint"][0], 4)},
+           "hessvec_speedup_vs_checkpoint": round(hv["checkpoint"][0] / hv["time"][0], 4),
+           "hv_rel_err_vs_checkpoint": round(float(torch.linalg.norm(ht - hc) / torch.linalg.norm(hc)), 5),
+           "store_GB": round(tm.storage_bytes() / 1e9, 3),
+           "kernel_times_us": kt,
+           "note": "encode per window of 32 levels (timing class 3), decode per window (class 4)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.counters:
@@ -309,6 +395,9 @@ def main():
         return
     if args.bayes:
         bayes_pass(args)
+        return
+    if args.time:
+        time_pass(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
