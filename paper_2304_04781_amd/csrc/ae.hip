@@ -66,6 +66,14 @@ __device__ __forceinline__ float e4m32f(uint8_t c)
 constexpr int BK = 32;
 constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row
 
+// registers holding one BR x BK tile between its global load and its LDS store:
+// chunk c = tid + 256 i of 8 bf16 in v[i]
+template <int BR>
+struct Frag {
+    static constexpr int NC = (BR * (BK / 8) + 255) / 256;
+    uint4 v[NC];
+};
+
 // source stored [rows][ld] with k contiguous; optional row gather
 struct LoadK {
     const uint16_t* p;
@@ -73,18 +81,29 @@ struct LoadK {
     const int* rows;  // nullable: logical row r reads source row rows[r]
     int nrows;        // logical rows
     int k_total;
-    __device__ __forceinline__ void load(int r0, int k0, int tid, int BR, uint16_t (*lds)[BK + LDS_PAD]) const
+    template <int BR>
+    __device__ __forceinline__ void fetch(int r0, int k0, int tid, Frag<BR>& f) const
     {
-        // BR x BK tile = BR*4 chunks of 8 bf16
-        for (int c = tid; c < BR * (BK / 8); c += 256) {
+#pragma unroll
+        for (int i = 0; i < Frag<BR>::NC; ++i) {
+            const int c = tid + 256 * i;
             const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kc;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (gr < nrows && gk < k_total) {
+            if (c < BR * (BK / 8) && gr < nrows && gk < k_total) {
                 const long long src = rows ? rows[gr] : gr;
                 v = *reinterpret_cast<const uint4*>(p + src * ld + gk);
             }
-            *reinterpret_cast<uint4*>(&lds[r][kc]) = v;
+            f.v[i] = v;
+        }
+    }
+    template <int BR>
+    __device__ __forceinline__ void store(const Frag<BR>& f, int tid, uint16_t (*lds)[BK + LDS_PAD]) const
+    {
+#pragma unroll
+        for (int i = 0; i < Frag<BR>::NC; ++i) {
+            const int c = tid + 256 * i;
+            if (c < BR * (BK / 8)) *reinterpret_cast<uint4*>(&lds[c / (BK / 8)][(c % (BK / 8)) * 8]) = f.v[i];
         }
     }
 };
@@ -96,24 +115,40 @@ struct LoadT {
     const int* kidx;  // nullable: logical k reads source row kidx[k]
     int nrows;
     int k_total;
-    __device__ __forceinline__ void load(int r0, int k0, int tid, int BR, uint16_t (*lds)[BK + LDS_PAD]) const
+    template <int BR>
+    __device__ __forceinline__ void fetch(int r0, int k0, int tid, Frag<BR>& f) const
     {
-        // each chunk: 8 consecutive rows at one k
-        for (int c = tid; c < BK * (BR / 8); c += 256) {
+#pragma unroll
+        for (int i = 0; i < Frag<BR>::NC; ++i) {
+            const int c = tid + 256 * i;
             const int kk = c / (BR / 8), rc = (c % (BR / 8)) * 8;
             const int gk = k0 + kk, gr = r0 + rc;
-            uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (gk < k_total) {
+            uint4 w = make_uint4(0, 0, 0, 0);
+            if (c < BK * (BR / 8) && gk < k_total) {
                 const long long src = kidx ? kidx[gk] : gk;
                 const uint16_t* q = p + src * ld + gr;
                 if (gr + 8 <= nrows) {
-                    const uint4 w = *reinterpret_cast<const uint4*>(q);
-                    memcpy(v, &w, 16);
+                    w = *reinterpret_cast<const uint4*>(q);
                 } else {
+                    uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                     for (int t = 0; t < 8; ++t)
                         if (gr + t < nrows) v[t] = q[t];
+                    memcpy(&w, v, 16);
                 }
             }
+            f.v[i] = w;
+        }
+    }
+    template <int BR>
+    __device__ __forceinline__ void store(const Frag<BR>& f, int tid, uint16_t (*lds)[BK + LDS_PAD]) const
+    {
+#pragma unroll
+        for (int i = 0; i < Frag<BR>::NC; ++i) {
+            const int c = tid + 256 * i;
+            if (c >= BK * (BR / 8)) continue;
+            const int kk = c / (BR / 8), rc = (c % (BR / 8)) * 8;
+            uint16_t v[8];
+            memcpy(v, &f.v[i], 16);
             for (int t = 0; t < 8; ++t) lds[rc + t][kk] = v[t];
         }
     }
@@ -124,8 +159,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
 {
     static_assert((BM / WM) * (BN / WN) == 4, "4 waves");
     constexpr int TM = WM / 16, TN = WN / 16;
-    __shared__ __attribute__((aligned(16))) uint16_t sA[BM][BK + LDS_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[BN][BK + LDS_PAD];
+    // two LDS stages: the next k-tile is loaded into registers while the MFMAs of the
+    // current one run, and stored to the other stage after them
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM][BK + LDS_PAD];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN][BK + LDS_PAD];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -141,23 +178,40 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
         for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    Frag<BM> fa;
+    Frag<BN> fb;
+    if (kb < ke) {
+        la.template fetch<BM>(m0, kb, tid, fa);
+        lb.template fetch<BN>(n0, kb, tid, fb);
+        la.template store<BM>(fa, tid, sA[0]);
+        lb.template store<BN>(fb, tid, sB[0]);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
-        la.load(m0, k0, tid, BM, sA);
-        lb.load(n0, k0, tid, BN, sB);
-        __syncthreads();
+        const bool more = k0 + BK < ke;
+        if (more) {
+            la.template fetch<BM>(m0, k0 + BK, tid, fa);
+            lb.template fetch<BN>(n0, k0 + BK, tid, fb);
+        }
         bf16x8 af[TM], bfr[TN];
 #pragma unroll
         for (int a = 0; a < TM; ++a)
-            af[a] = *reinterpret_cast<const bf16x8*>(&sA[wm0 + a * 16 + fr][fk]);
+            af[a] = *reinterpret_cast<const bf16x8*>(&sA[cur][wm0 + a * 16 + fr][fk]);
 #pragma unroll
         for (int b = 0; b < TN; ++b)
-            bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[wn0 + b * 16 + fr][fk]);
+            bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[cur][wn0 + b * 16 + fr][fk]);
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
             for (int b = 0; b < TN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        if (more) {
+            la.template store<BM>(fa, tid, sA[cur ^ 1]);
+            lb.template store<BN>(fb, tid, sB[cur ^ 1]);
+        }
         __syncthreads();
+        cur ^= 1;
     }
     // C layout of a 16x16 tile: lane holds column lane%16, rows 4*(lane/16) + r
     const int cc = lane & 15, cr = (lane >> 4) * 4;
