@@ -447,8 +447,10 @@ int wv_set_timing(wv_ctx* ctx, int32_t every);
  * 4 decompression of one e field (with its exception patches written exactly),
  * 5 selection of the exception patches of one state, 6 a separate exception
  * restore (not launched: the decompression writes those patches), 7 copy of the
- * exception patches of one state. Waits for the timed work. NULL outputs are
- * skipped; WV_EINVAL for an unknown class. */
+ * exception patches of one state. In the time-compression mode classes 3 and 4
+ * time the compression and decompression of one window of 32 levels, on the
+ * context's stream. Waits for the timed work. NULL outputs are skipped;
+ * WV_EINVAL for an unknown class. */
 int wv_kernel_time(wv_ctx* ctx, int32_t cls, double* h_mean_us, int64_t* h_count);
 
 /* Number of consecutive adjoint steps whose gradient terms e^k q^k are summed in
