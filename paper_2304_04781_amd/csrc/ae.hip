@@ -19,6 +19,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ae_internal.h"
@@ -63,7 +64,7 @@ __device__ __forceinline__ float e4m32f(uint8_t c)
 // A and B tiles (BM x BK, BN x BK, k fastest) are staged through LDS by loaders
 // that know the source layout; epilogues consume (row, col, value).
 // ------------------------------------------------------------------------------------
-constexpr int BK = 32;
+constexpr int BK = 64;  // k per LDS stage: two 32-deep MFMA steps; depths below a multiple are zero-filled
 constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row
 
 // registers holding one BR x BK tile between its global load and its LDS store:
@@ -72,6 +73,16 @@ template <int BR>
 struct Frag {
     static constexpr int NC = (BR * (BK / 8) + 255) / 256;
     uint4 v[NC];
+};
+
+// an epilogue with kTile = true takes the whole C tile from LDS: tile(m0, n0, rows, cols, C, ldc)
+template <class E, class = void>
+struct EpiHasTile {
+    static constexpr bool value = false;
+};
+template <class E>
+struct EpiHasTile<E, std::void_t<decltype(E::kTile)>> {
+    static constexpr bool value = E::kTile;
 };
 
 // source stored [rows][ld] with k contiguous; optional row gather
@@ -160,9 +171,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     static_assert((BM / WM) * (BN / WN) == 4, "4 waves");
     constexpr int TM = WM / 16, TN = WN / 16;
     // two LDS stages: the next k-tile is loaded into registers while the MFMAs of the
-    // current one run, and stored to the other stage after them
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM][BK + LDS_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN][BK + LDS_PAD];
+    // current one run, and stored to the other stage after them. An epilogue that
+    // writes whole tiles gets the C tile staged in the same memory afterwards.
+    __shared__ __attribute__((aligned(16))) uint16_t smem[2 * (BM + BN) * (BK + LDS_PAD)];
+    auto sA = reinterpret_cast<uint16_t(*)[BM][BK + LDS_PAD]>(smem);
+    auto sB = reinterpret_cast<uint16_t(*)[BN][BK + LDS_PAD]>(smem + 2 * BM * (BK + LDS_PAD));
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -194,18 +207,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
             la.template fetch<BM>(m0, k0 + BK, tid, fa);
             lb.template fetch<BN>(n0, k0 + BK, tid, fb);
         }
-        bf16x8 af[TM], bfr[TN];
 #pragma unroll
-        for (int a = 0; a < TM; ++a)
-            af[a] = *reinterpret_cast<const bf16x8*>(&sA[cur][wm0 + a * 16 + fr][fk]);
+        for (int ks = 0; ks < BK; ks += 32) {
+            bf16x8 af[TM], bfr[TN];
 #pragma unroll
-        for (int b = 0; b < TN; ++b)
-            bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[cur][wn0 + b * 16 + fr][fk]);
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
+            for (int a = 0; a < TM; ++a)
+                af[a] = *reinterpret_cast<const bf16x8*>(&sA[cur][wm0 + a * 16 + fr][ks + fk]);
 #pragma unroll
             for (int b = 0; b < TN; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+                bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[cur][wn0 + b * 16 + fr][ks + fk]);
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        }
         if (more) {
             la.template store<BM>(fa, tid, sA[cur ^ 1]);
             lb.template store<BN>(fb, tid, sB[cur ^ 1]);
@@ -215,6 +231,20 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     }
     // C layout of a 16x16 tile: lane holds column lane%16, rows 4*(lane/16) + r
     const int cc = lane & 15, cr = (lane >> 4) * 4;
+    if constexpr (EpiHasTile<EPI>::value) {
+        constexpr int LDC = BN + 4;
+        static_assert(BM * LDC * 4 <= (int)sizeof(smem), "the C tile fits in the operand stages");
+        float* C = reinterpret_cast<float*>(smem);  // the loop ended with a barrier: the stages are free
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) C[(wm0 + a * 16 + cr + r) * LDC + wn0 + b * 16 + cc] = acc[a][b][r];
+        __syncthreads();
+        epi.tile(m0, n0, min(BM, M - m0), min(BN, N - n0), C, LDC);
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -295,8 +325,8 @@ struct EpiDenorm {  // decoder output of field f -> lo + r (v + b) scattered int
 template <int BM, int BN, int WM, int WN, class LA, class LB, class EPI>
 void gemm(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
 {
-    WV_REQUIRE(K % BK == 0, WV_EINVAL, "GEMM depth must be a multiple of 32");
-    const int kps = ((K / BK + splits - 1) / splits) * BK;
+    WV_REQUIRE(K % 32 == 0, WV_EINVAL, "GEMM depth must be a multiple of 32");
+    const int kps = (((K + BK - 1) / BK + splits - 1) / splits) * BK;
     dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
     hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, LA, LB, EPI>), grid, dim3(256), 0, st, M, N, K, kps, la, lb, epi);
     WV_HIP(hipGetLastError());
@@ -304,6 +334,7 @@ void gemm(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipSt
 
 // wide N (>= 128) and narrow N (<= 32) tile shapes
 struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) into levels t < nvalid
+    static constexpr bool kTile = true;
     float* e_win;
     const float* meta;  // [S*B][2]
     const float* bias;  // b4
@@ -321,6 +352,30 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
         const int cell = c & 63, lz = cell >> 4, ly = (cell >> 2) & 3, lx = cell & 3;
         e_win[((long long)t * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly) * nx + bx * 4 + lx] =
             lo + rr * yv;
+    }
+    // The tile's rows are consecutive vectors, i.e. blocks along x. Thread i takes
+    // lx = i % 4 and the rows i / 4 + 64 j, resolves each row's block and (lo, r)
+    // once, then walks the tile's columns: at every store the 64 lanes of a wave
+    // cover 16 blocks x 4 cells, one contiguous run of x (cols is a multiple of 4).
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    {
+        const int lx = threadIdx.x & 3;
+        for (int rr = threadIdx.x >> 2; rr < rows; rr += 64) {
+            const long long row = (long long)m0 + rr;
+            const int s = (int)(row / B);
+            const long long b = row % B;
+            const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+            const float lo = meta[row * 2], rg = meta[row * 2 + 1];
+            float* base = e_win + (long long)s * N + ((long long)bz * 4 * ny + by * 4) * nx + bx * 4 + lx;
+            const float* crow = C + rr * ldc + lx;
+            for (int cq = 0; cq < cols / 4; ++cq) {
+                const int c = n0 + cq * 4 + lx;
+                const int t = c >> 6;
+                if (t >= nvalid) break;  // columns ascend, so do the levels
+                const int cell = c & 63, lz = cell >> 4, ly = (cell >> 2) & 3;
+                base[(long long)t * S * N + ((long long)lz * ny + ly) * nx] = lo + rg * (crow[cq * 4] + bias[c]);
+            }
+        }
     }
 };
 
@@ -368,6 +423,65 @@ __global__ void __launch_bounds__(256) normalize_kernel(const float* __restrict_
     if (l == 0) {
         meta[row * 8 + 2 * f] = lo;
         meta[row * 8 + 2 * f + 1] = r;
+    }
+}
+
+// time vectors of G x-adjacent blocks per work-group (all vectors of a window in
+// order): the 512 rows (t, lz, ly) of the window are read as G float4 runs each,
+// G * 16 bytes contiguous, so a row of blocks is fetched in whole cache lines.
+// Thread i holds block i % G and rows i / G + (256 / G) m, m < 2 G.
+template <int G>
+__global__ void __launch_bounds__(256) time_normalize_group_kernel(const float* __restrict__ e_win, int S, int ny,
+                                                                  int nx, long long N, int By, int Bx, long long B,
+                                                                  int nvalid, const float* __restrict__ beta,
+                                                                  uint16_t* __restrict__ y, float* __restrict__ meta)
+{
+    constexpr int NR = 2 * G;             // rows per thread
+    constexpr int RS = 256 / G;           // row stride between a thread's rows
+    const long long v0 = (long long)blockIdx.x * G;  // first vector of the group
+    const int s = (int)(v0 / B);
+    const long long b0 = v0 % B;
+    const int bx0 = (int)(b0 % Bx), by = (int)((b0 / Bx) % By), bz = (int)(b0 / ((long long)Bx * By));
+    const int g = threadIdx.x % G, r0 = threadIdx.x / G;
+    float4 v[NR];
+    float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+        const int r = r0 + RS * m;        // row = t * 16 + lz * 4 + ly
+        const int t = r >> 4, lz = (r >> 2) & 3, ly = r & 3;
+        const int tl = t < nvalid ? t : nvalid - 1;
+        v[m] = *reinterpret_cast<const float4*>(e_win + ((long long)tl * S + s) * N +
+                                                ((long long)(bz * 4 + lz) * ny + by * 4 + ly) * nx + (bx0 + g) * 4);
+        lo = fminf(lo, fminf(fminf(v[m].x, v[m].y), fminf(v[m].z, v[m].w)));
+        hi = fmaxf(hi, fmaxf(fmaxf(v[m].x, v[m].y), fmaxf(v[m].z, v[m].w)));
+    }
+    // lanes of one block differ by multiples of G
+    for (int o = G; o < 64; o <<= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    }
+    __shared__ float slo[4][G], shi[4][G];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) < G) {
+        slo[w][g] = lo;
+        shi[w][g] = hi;
+    }
+    __syncthreads();
+    lo = fminf(fminf(slo[0][g], slo[1][g]), fminf(slo[2][g], slo[3][g]));
+    hi = fmaxf(fmaxf(shi[0][g], shi[1][g]), fmaxf(shi[2][g], shi[3][g]));
+    const float rr = fmaxf(hi - lo, beta[0]);
+    const float rinv = 1.0f / rr;
+    uint16_t* yv = y + (v0 + g) * (TWIN * 64);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+        const int r = r0 + RS * m;
+        const uint2 o = make_uint2(f2bf2((v[m].x - lo) * rinv, (v[m].y - lo) * rinv),
+                                   f2bf2((v[m].z - lo) * rinv, (v[m].w - lo) * rinv));
+        *reinterpret_cast<uint2*>(yv + r * 4) = o;
+    }
+    if (threadIdx.x < G) {
+        meta[(v0 + g) * 2] = lo;
+        meta[(v0 + g) * 2 + 1] = rr;
     }
 }
 
@@ -849,6 +963,21 @@ void ae_time_normalize_rows(const ae_net* a, const TimeGrid& tg, const float* e_
     WV_REQUIRE(nvalid >= 1 && nvalid <= TWIN, WV_EINVAL, "nvalid must lie in [1, 32]");
     if (nrows == 0) return;
     const long long N = (long long)tg.nz * tg.ny * tg.nx;
+    const int Bx = tg.nx / 4;
+    if (!rows) {
+        // whole window: groups of x-adjacent blocks (a group never crosses a row of blocks)
+        const long long M = nrows;
+        auto launch = [&](auto kern, int G) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)(M / G)), dim3(256), 0, st, e_win, tg.S, tg.ny, tg.nx, N,
+                               tg.ny / 4, Bx, tg.B, nvalid, a->beta_d, y, meta);
+        };
+        if (Bx % 8 == 0) launch(time_normalize_group_kernel<8>, 8);
+        else if (Bx % 4 == 0) launch(time_normalize_group_kernel<4>, 4);
+        else if (Bx % 2 == 0) launch(time_normalize_group_kernel<2>, 2);
+        else launch(time_normalize_group_kernel<1>, 1);
+        WV_HIP(hipGetLastError());
+        return;
+    }
     hipLaunchKernelGGL(time_normalize_kernel, dim3((unsigned)nrows), dim3(256), 0, st, e_win, tg.S, tg.ny, tg.nx, N,
                        tg.ny / 4, tg.nx / 4, tg.B, nvalid, a->beta_d, rows, y, meta);
     WV_HIP(hipGetLastError());

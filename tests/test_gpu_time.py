@@ -54,14 +54,18 @@ def window(seed, nsrc, shape=SHAPE):
     return (scale * (base * np.cos(0.1 * t) + 0.1 * rng.standard_normal((32, nsrc) + shape))).astype(np.float32)
 
 
-@pytest.mark.parametrize("nvalid", [32, 13])
-def test_time_normalize_bitwise(nvalid):
+@pytest.mark.parametrize("nvalid,shape", [(32, SHAPE), (13, SHAPE), (32, (8, 8, 32)), (7, (4, 8, 12)),
+                                          (32, (8, 4, 40))])
+def test_time_normalize_bitwise(nvalid, shape):
+    """Whole windows are read by groups of 8, 4, 2 or 1 x-adjacent blocks (the
+    largest that divides the blocks along x: 32, 16, 12 and 40 cells here), row
+    subsets one vector per work-group; both against the oracle bit for bit."""
     S = 2
     net = Net(W.ae_init(seed=4))
-    e = window(1, S)
+    e = window(1, S, shape)
     e[:, 0, :4, :4, :4] = 2.5e-8              # block 0 of source 0 constant in space and time: r = beta
-    g = grid_of(SHAPE, S)
-    B = 24
+    g = grid_of(shape, S)
+    B = (shape[0] // 4) * (shape[1] // 4) * (shape[2] // 4)
     te = torch.tensor(e[:nvalid], device="cuda")
     y = torch.empty((S * B, 2048), dtype=torch.int16, device="cuda")
     meta = torch.empty((S * B, 2), dtype=torch.float32, device="cuda")
@@ -75,14 +79,14 @@ def test_time_normalize_bitwise(nvalid):
         assert np.array_equal(yb[s * B:(s + 1) * B], rd.bf16_bits(Y))
     assert np.all(yb[0] == 0)
     # a subset of rows (any order, repeats), and refused indices
-    rows = torch.tensor([47, 0, 5, 5, 30], dtype=torch.int32, device="cuda")
+    rows = torch.tensor([2 * B - 1, 0, 5, 5, B + 3], dtype=torch.int32, device="cuda")
     yr = torch.empty((5, 2048), dtype=torch.int16, device="cuda")
     mr = torch.empty((5, 2), dtype=torch.float32, device="cuda")
     L.ae_time_normalize(net.handle, g, te, nvalid, yr, mr, rows=rows)
     assert torch.equal(yr, y[rows.long()]) and torch.equal(mr, meta[rows.long()])
     with pytest.raises(L.WvError):
         L.ae_time_normalize(net.handle, g, te, nvalid, yr[:1], mr[:1],
-                            rows=torch.tensor([48], dtype=torch.int32, device="cuda"))
+                            rows=torch.tensor([2 * B], dtype=torch.int32, device="cuda"))
     with pytest.raises(L.WvError):
         L.ae_time_normalize(net.handle, g, te, 33, y, meta)
 
