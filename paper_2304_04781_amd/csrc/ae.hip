@@ -382,8 +382,13 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
 template <class LA, class LB, class EPI>
 void gemm_auto(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
 {
+    // 128 x 128 tiles when they give at least two work-groups per CU, else 64 x 64
+    // (training batches of a few thousand rows)
+    const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
     if (N <= 32)
         gemm<128, 32, 32, 32>(M, N, K, la, lb, epi, st, splits);
+    else if (wg128 < 512)
+        gemm<64, 64, 32, 32>(M, N, K, la, lb, epi, st, splits);
     else
         gemm<128, 128, 64, 64>(M, N, K, la, lb, epi, st, splits);
 }
