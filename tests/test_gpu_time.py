@@ -122,19 +122,26 @@ def test_time_encode_decode_against_oracle():
     assert np.all(o[nvalid:] == 7.0)
 
 
-def time_problem(nt, shape=(32, 32, 40)):
+def time_problem(nt, shape=(32, 32, 40), nsrc=1):
     p = W.problem_3d(*shape, nt, f0=15.0, sponge=8, name="time3d")
+    if nsrc == 2:
+        p.src = np.array([[4, 16, 20], [6, 12, 28]], dtype=np.int32)
+        p.wavelet = np.stack([p.wavelet[0], 0.6 * W.ricker(11.0, p.dt, nt) / p.dx ** 3])
+        p.noise = np.random.default_rng(1).standard_normal((2, nt, len(p.rec)))
     for k in ("c_true", "c_start", "wavelet"):
         setattr(p, k, np.asarray(getattr(p, k), np.float32).astype(np.float64))
     return p
 
 
-def test_time_store_levels_equal_window_roundtrip():
+@pytest.mark.parametrize("nsrc", [1, 2])
+def test_time_store_levels_equal_window_roundtrip(nsrc):
     """T - 1 = 74 stored levels: two full windows and a short one of 10. Every level
-    the reverse solves read is the encode-decode round trip of the exact window
-    from the same forward solve; the store holds 3 windows of latents and (lo, r);
-    gradient and Gauss-Newton Hv run, the full-Newton product is refused."""
-    p = time_problem(75)
+    the reverse solves read (each source's) is the encode-decode round trip of the
+    exact window from the same forward solve; the store holds 3 windows of latents
+    and (lo, r) per source; gradient and Gauss-Newton Hv run, the full-Newton
+    product is refused."""
+    p = time_problem(75, nsrc=nsrc)
+    print("case sources", nsrc, flush=True)
     sol = ow.solver_for(p)
     d, sigma, _ = ow.observed_data(sol, p)
     net = Net(W.ae_init(seed=4))
@@ -145,12 +152,12 @@ def test_time_store_levels_equal_window_roundtrip():
     t = WaveSolver.for_problem(p)
     t.set_storage(L.STORE_AE_TIME, ae=net)
     B = 8 * 8 * 10
-    assert t.storage_bytes() == 3 * B * (32 * 2 + 8)
+    assert t.storage_bytes() == 3 * nsrc * B * (32 * 2 + 8)
     J, g = t.gradient(p.c_start, p.wavelet, d, sigma)
     assert torch.isfinite(g).all()
-    lat = torch.empty((B, 32), dtype=torch.int16, device="cuda")
-    meta = torch.empty((B, 2), dtype=torch.float32, device="cuda")
-    dec = torch.empty((32, 1) + t.shape, dtype=torch.float32, device="cuda")
+    lat = torch.empty((nsrc * B, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((nsrc * B, 2), dtype=torch.float32, device="cuda")
+    dec = torch.empty((32, nsrc) + t.shape, dtype=torch.float32, device="cuda")
     for w, nvalid in ((0, 32), (1, 32), (2, 10)):
         win = e_all[32 * w:32 * w + nvalid]
         L.ae_time_encode(net.handle, t.grid, win, nvalid, lat, meta)
