@@ -249,12 +249,15 @@ struct wv_ctx {
     long long last_fwd_steps = 0;
 
     // time compression store: latents [nwin][S B][L] bf16, meta [nwin][S B][2] (lo, r),
-    // one window buffer [TWIN][S][N] (filled by the forward sweep, decoded into by the
-    // reverse sweeps)
+    // two window buffers [2][TWIN][S][N]: the forward fills one while the other is
+    // compressed on `side`; the reverse-time sweeps read one while the next window
+    // is decompressed into the other on `side`
     uint16_t* tlat = nullptr;
     float* tmeta = nullptr;
     float* twin = nullptr;
-    int tdec_w = -1;             // window held decoded in twin (-1: none)
+    int tbuf_w[2] = {-1, -1};    // window held decoded in each buffer (-1: none)
+    int tcur_w = -1;             // window the main stream reads now
+    hipEvent_t ev_tfill[2] = {}, ev_tenc[2] = {}, ev_tready[2] = {}, ev_tfree[2] = {};
     long long TB = 0;            // 4^3 blocks per source
     int nwin = 0;
     int tlat_dim = 0;
@@ -456,7 +459,8 @@ void free_store(wv_ctx* c)
     dev_free(c->tlat);
     dev_free(c->tmeta);
     dev_free(c->twin);
-    c->tdec_w = -1;
+    c->tbuf_w[0] = c->tbuf_w[1] = -1;
+    c->tcur_w = -1;
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -498,6 +502,7 @@ void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
 
 bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
 bool is_time(int mode) { return mode == WV_STORE_AE_TIME; }
+float* twin_buf(wv_ctx* c, int b) { return c->twin + (long long)b * TWIN * c->S * c->N; }
 TimeGrid ctx_time_grid(const wv_ctx* c) { return time_grid(c->g.nz, c->g.ny, c->g.nx, c->S); }
 uint16_t* tlat_slot(wv_ctx* c, int w) { return c->tlat + (long long)w * c->TB * c->S * c->tlat_dim; }
 float* tmeta_slot(wv_ctx* c, int w) { return c->tmeta + (long long)w * c->TB * c->S * 2; }
@@ -537,6 +542,9 @@ void alloc_latstore(wv_ctx* c, LatStore& L, int mode, int K)
     }
 }
 
+void wait_event(hipStream_t st, hipEvent_t ev);
+hipStream_t side_stream(wv_ctx* c, int which);
+
 // store x_n (n = 1..T-1) of every source on the main stream (full storage, or
 // the autoencoder store L without the forward step's min/max)
 void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
@@ -547,15 +555,21 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
             WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
     } else if (is_time(c->mode)) {
-        // e^n joins its window; a full window (or the last, short one) is compressed
-        const int t = (n - 1) % TWIN, w = (n - 1) / TWIN;
+        // e^n joins its window in buffer w % 2; a full window (or the last, short one)
+        // is compressed on `side` while the steps go on into the other buffer
+        const int t = (n - 1) % TWIN, w = (n - 1) / TWIN, b = w & 1;
+        float* buf = twin_buf(c, b);
+        if (t == 0 && w >= 2) wait_event(c->st, c->ev_tenc[b]);  // window w - 2 has been read
         for (int s = 0; s < c->S; ++s)
-            launch_copy(c->twin + ((long long)t * c->S + s) * c->N, state + s * 4 * c->N, c->N, c->st);
+            launch_copy(buf + ((long long)t * c->S + s) * c->N, state + s * 4 * c->N, c->N, c->st);
         if (t == TWIN - 1 || n == c->T - 1) {
-            const int te = c->tm.begin(TM_ENCODE, c->st);
-            ae_time_encode(c->ae, ctx_time_grid(c), c->twin, t + 1, tlat_slot(c, w), tmeta_slot(c, w), c->st);
-            c->tm.end(te, c->st);
-            c->tdec_w = -1;
+            hipStream_t s1 = side_stream(c, 0);
+            WV_HIP(hipEventRecord(c->ev_tfill[b], c->st));
+            wait_event(s1, c->ev_tfill[b]);
+            const int te = c->tm.begin(TM_ENCODE, s1);
+            ae_time_encode(c->ae, ctx_time_grid(c), buf, t + 1, tlat_slot(c, w), tmeta_slot(c, w), s1);
+            c->tm.end(te, s1);
+            WV_HIP(hipEventRecord(c->ev_tenc[b], s1));
         }
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
@@ -688,23 +702,47 @@ void decode_e(wv_ctx* c, int n, int b, hipStream_t st) { decode_state(c, c->fs, 
 
 // e^n of every source from the FULL or AE store (decoded on the main stream into
 // ebuf slot 0): pointer + per-source stride
-const float* load_e(wv_ctx* c, int n, long long* stride)
+// queue the decompression of window w into buffer b on `side`, after the main
+// stream's reads of b enqueued so far
+void time_issue(wv_ctx* c, int w, int b)
+{
+    hipStream_t s1 = side_stream(c, 0);
+    WV_HIP(hipEventRecord(c->ev_tfree[b], c->st));
+    wait_event(s1, c->ev_tfree[b]);
+    const int nvalid = std::min(TWIN, c->T - 1 - w * TWIN);
+    const int td = c->tm.begin(TM_DECODE, s1);
+    ae_time_decode(c->ae, ctx_time_grid(c), tlat_slot(c, w), tmeta_slot(c, w), nvalid, twin_buf(c, b), s1);
+    c->tm.end(td, s1);
+    WV_HIP(hipEventRecord(c->ev_tready[b], s1));
+    c->tbuf_w[b] = w;
+}
+
+// e^n of the time-compressed store: its window is decompressed whole; at the first
+// read of a window the next one in the direction of travel (dir = -1 reverse time,
+// +1 forward) is queued into the other buffer
+const float* time_e(wv_ctx* c, int n, int dir)
+{
+    const int w = (n - 1) / TWIN;
+    int b = c->tbuf_w[0] == w ? 0 : (c->tbuf_w[1] == w ? 1 : -1);
+    if (b < 0) {
+        b = c->tbuf_w[0] == c->tcur_w && c->tcur_w >= 0 ? 1 : 0;
+        time_issue(c, w, b);
+    }
+    if (c->tcur_w != w) {
+        wait_event(c->st, c->ev_tready[b]);
+        c->tcur_w = w;
+        const int wn = w + dir;
+        if (wn >= 0 && wn < c->nwin && c->tbuf_w[0] != wn && c->tbuf_w[1] != wn) time_issue(c, wn, 1 - b);
+    }
+    return twin_buf(c, b) + (long long)((n - 1) % TWIN) * c->S * c->N;
+}
+
+const float* load_e(wv_ctx* c, int n, long long* stride, int dir = -1)
 {
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     *stride = c->N;
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
-    if (is_time(c->mode)) {
-        // the window of e^n, decoded once for all its levels
-        const int w = (n - 1) / TWIN;
-        if (w != c->tdec_w) {
-            const int nvalid = std::min(TWIN, c->T - 1 - w * TWIN);
-            const int td = c->tm.begin(TM_DECODE, c->st);
-            ae_time_decode(c->ae, ctx_time_grid(c), tlat_slot(c, w), tmeta_slot(c, w), nvalid, c->twin, c->st);
-            c->tm.end(td, c->st);
-            c->tdec_w = w;
-        }
-        return c->twin + (long long)((n - 1) % TWIN) * c->S * c->N;
-    }
+    if (is_time(c->mode)) return time_e(c, n, dir);
     ensure_adj(c);  // owns the decode target ebuf
     decode_e(c, n, 0, c->st);
     return ebuf_slot(c, 0);
@@ -743,7 +781,12 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
                      float** last, const std::vector<int>* ecap_idx = nullptr, float* ecap = nullptr)
 {
     c->delta_ok = false;  // incremental states belong to the previous forward history
-    c->tdec_w = -1;
+    if (is_time(c->mode)) {
+        // the window buffers are refilled: nothing queued on `side` may still use them
+        join_side(c);
+        c->tbuf_w[0] = c->tbuf_w[1] = -1;
+        c->tcur_w = -1;
+    }
     // autoencoder stores run beside the steps (x_j in work[j % 3])
     const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
     if (ae && !c->work[2]) c->work[2] = dev_alloc<float>(c->state_floats());
@@ -825,6 +868,7 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
                    float* xtm1)
 {
     ensure_adj(c);
+    c->tcur_w = -1;
     launch_fill(c->adj[0], c->state_floats(), 0.f, c->st);
     launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
     float* ain = c->adj[0];
@@ -973,6 +1017,9 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
             WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
         }
         WV_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        for (int b = 0; b < 2; ++b)
+            for (hipEvent_t* e : {&c->ev_tfill[b], &c->ev_tenc[b], &c->ev_tready[b], &c->ev_tfree[b]})
+                WV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
         c->dscal = dev_alloc<double>(8);
         c->dflag = dev_alloc<int>(1);
@@ -997,6 +1044,9 @@ int wv_destroy(wv_ctx* c)
         if (c->ev_ready[b]) (void)hipEventDestroy(c->ev_ready[b]);
         if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
     }
+    for (int b = 0; b < 2; ++b)
+        for (hipEvent_t e : {c->ev_tfill[b], c->ev_tenc[b], c->ev_tready[b], c->ev_tfree[b]})
+            if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->side2) (void)hipStreamDestroy(c->side2);
     dev_free(c->tab);
@@ -1057,7 +1107,7 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
             c->tlat = dev_alloc<uint16_t>(rows * c->tlat_dim);
             c->tmeta = dev_alloc<float>(rows * 2);
-            c->twin = dev_alloc<float>((size_t)TWIN * c->S * c->N);
+            c->twin = dev_alloc<float>((size_t)2 * TWIN * c->S * c->N);
             c->store_bytes = bytes;
         } else if (is_ae(mode)) {
             WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
@@ -1305,6 +1355,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
 {
     ensure_inc(c);
     ensure_adj(c);
+    c->tcur_w = -1;
     launch_dm(cdev, dc, c->dm, c->N, c->st);
     launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
     const bool pipe = !snap && is_ae(c->mode);
@@ -1348,7 +1399,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
             en = ebuf_slot(c, 0);  // e^0 = 0
             stride = c->N;
         } else {
-            en = load_e(c, n, &stride);
+            en = load_e(c, n, &stride, +1);
         }
         inc_step(c, din, dout, n, en, stride, c->dtr);
         if (pipe) pipe_release(c, n % NEB);
