@@ -226,3 +226,85 @@ def test_multisource_fp8_gradient_full_grid():
         ae.close()
     err, cs = errs[int(round(0.01 * P))]
     assert err < 0.1 and cs > 0.995
+
+
+# ----- 256^3: MAP layer and time compression ---------------------------------------------------------
+def test_prior_and_prior_draw_256_cube():
+    """BiLaplacian prior on the full 256^3 grid: cost, gradient and Hessian action
+    against the FP64 oracle (1e-5), and a prior draw by CG against the oracle's
+    exact cosine-mode solve (1e-4)."""
+    from oracle import inverse as oi
+    p = rounded(W.problem_256(10))
+    print("case", p.name, flush=True)
+    alpha, theta = 2.2e-6, (1e4, 1e4, 1e4)
+    u = f32(p.c_start * (1.0 + 0.02 * W.direction_grf(p.c_start.shape, 12.0, 5)))
+    R_o, g_o = oi.prior_cost_grad(u, p.c_start, alpha, theta, p.dx)
+    s = WaveSolver.for_problem(p)
+    s.set_prior(alpha, theta, p.c_start)
+    R, g = s.prior(u)
+    assert abs(R - R_o) < 1e-5 * R_o
+    assert rel(g.cpu().numpy(), g_o) < 1e-5
+    del g, g_o
+    H_o = oi.prior_hessvec(u - p.c_start, alpha, theta, p.dx)
+    assert rel(s.prior_hessvec(u - p.c_start).cpu().numpy(), H_o) < 1e-5
+    del H_o
+    w = f32(W.white_noise(p.c_start.shape, 101))
+    c, it, rr = s.prior_sample(w, rtol=1e-6)
+    print("CG iterations", it, "residual", rr, flush=True)
+    ref = oi.prior_sample(w, p.c_start, alpha, theta, p.dx)
+    assert rr <= 1e-6 and rel(c.cpu().numpy() - p.c_start, ref - p.c_start) < 1e-4
+
+
+def test_time_store_256_cube():
+    """Time compression on the full 256^3 grid (69 stored levels: two full windows
+    and a short one of 5): the levels the reverse solves read equal the encode-decode
+    round trip of the exact windows bit for bit, and the store is 3 windows of
+    262,144 vectors."""
+    p = rounded(W.problem_256(70))
+    print("case", p.name, flush=True)
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    e_all = s.forward_e(p.c_start, p.wavelet, list(range(1, 70)))
+    L.ae_time_fit_beta(net.handle, s.grid, e_all, 69, 1e-7)
+    t = WaveSolver.for_problem(p)
+    t.set_storage(L.STORE_AE_TIME, ae=net)
+    B = 64 ** 3
+    assert t.storage_bytes() == 3 * B * (32 * 2 + 8)
+    d = torch.zeros((1, p.nt, len(p.rec)), dtype=torch.float32, device="cuda")
+    J, g = t.gradient(p.c_start, p.wavelet, d, 1.0)
+    assert torch.isfinite(g).all()
+    lat = torch.empty((B, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    dec = torch.empty((32, 1) + t.shape, dtype=torch.float32, device="cuda")
+    for w, nvalid in ((0, 32), (1, 32), (2, 5)):
+        L.ae_time_encode(net.handle, t.grid, e_all[32 * w:32 * w + nvalid], nvalid, lat, meta)
+        L.ae_time_decode(net.handle, t.grid, lat, meta, nvalid, dec)
+        for lvl in sorted({0, nvalid // 2, nvalid - 1}):
+            n = 32 * w + 1 + lvl
+            assert torch.equal(t.load_e(n), dec[lvl]), n
+
+
+def test_newton_cg_256_cube_checkpointing_equals_full_storage():
+    """One Gauss-Newton CG iteration (two Hv) with the BiLaplacian prior on the full
+    256^3 grid over 40 steps: revolve checkpointing takes the full-storage path bit
+    for bit, and the cost falls."""
+    p = rounded(W.problem_256(40))
+    print("case", p.name, flush=True)
+    s0 = WaveSolver.for_problem(p)
+    s0.set_storage(L.STORE_NONE)
+    clean, _, _ = s0.forward(p.c_true, p.wavelet)
+    sigma = 0.01 * float(clean.abs().max())
+    d = clean + sigma * torch.tensor(p.noise, dtype=torch.float32, device="cuda")
+    del s0
+    out = []
+    for mode in (L.STORE_FULL, L.STORE_CHECKPOINT):
+        s = WaveSolver.for_problem(p)
+        s.set_storage(mode, n_checkpoints=8)
+        s.set_prior(2.2e-6, (1e4, 1e4, 1e4), p.c_start)
+        out.append(s.newton_cg(p.c_start, p.wavelet, d, sigma, max_newton=1, max_cg=2))
+        del s
+    (c0, log0, _, _), (c1, log1, _, _) = out
+    assert torch.equal(c0, c1)
+    assert [r["cost"] for r in log0] == [r["cost"] for r in log1]
+    assert log0[1]["cost"] < log0[0]["cost"]
