@@ -24,11 +24,12 @@ draws from the prior): c = c0 + A^-1 w / sqrt(dx^dims), w white noise.
 
 Newton-CG (Sec. 4; the method of its references on inexact Newton-CG for
 wave inversion):
-  * CG on H p = -g from p = 0, stopped when ||r|| <= eta ||g|| with the
+  * CG on H p = -g from p = 0, optionally preconditioned by the prior
+    covariance (dx^dims A A)^-1, stopped when ||r||_M <= eta ||g||_M with the
     Eisenstat-Walker forcing eta = min(eta_max, sqrt(||g|| / ||g_0||)), after
     max_cg iterations, or at the first direction of non-positive curvature
-    (then the iterate so far is kept; at the first iteration the steepest-
-    descent direction -g is taken);
+    (then the iterate so far is kept; at the first iteration the
+    (preconditioned) steepest-descent direction -M g is taken);
   * Armijo backtracking: the step length starts at 1 and halves until
     J(c + a p) <= J(c) + c_armijo a g.p;
   * stop when ||g|| <= rel_tol ||g_0|| or after max_newton iterations.
@@ -84,26 +85,35 @@ def prior_hessvec(dc, alpha, theta, dx):
     return vol * prior_operator(prior_operator(dc, alpha, theta, dx), alpha, theta, dx)
 
 
-def prior_sample(w, c0, alpha, theta, dx):
-    """A draw from the prior N(c0, (dx^dims A A)^-1) for white noise w ~ N(0, I):
-    c = c0 + A^-1 w / sqrt(dx^dims) (covariance A^-1 A^-1 / dx^dims, A symmetric).
-    The solve is exact: the cell-centred cosine modes diagonalise A (the
+def prior_solve(b, alpha, theta, dx):
+    """A^-1 b, exactly: the cell-centred cosine modes diagonalise A (the
     orthonormal type-II DCT along each axis), with eigenvalues
     alpha (1 + sum_a theta_a / dx^2 (2 - 2 cos(pi k_a / n_a)))."""
     from scipy.fft import dctn, idctn
 
-    w = np.asarray(w, np.float64)
-    lam = np.full(w.shape, 1.0)
-    for axis, n in enumerate(w.shape):
+    b = np.asarray(b, np.float64)
+    lam = np.full(b.shape, 1.0)
+    for axis, n in enumerate(b.shape):
         if n == 1:
             continue
         sh = [1, 1, 1]
         sh[axis] = n
         k = np.arange(n).reshape(sh)
         lam = lam + float(theta[axis]) / dx ** 2 * (2.0 - 2.0 * np.cos(np.pi * k / n))
-    lam = alpha * lam
-    b = w / np.sqrt(cell_volume(w.shape, dx))
-    return c0 + idctn(dctn(b, type=2, norm="ortho") / lam, type=2, norm="ortho")
+    return idctn(dctn(b, type=2, norm="ortho") / (alpha * lam), type=2, norm="ortho")
+
+
+def prior_covariance(r, alpha, theta, dx):
+    """The prior covariance applied to r: (dx^dims A A)^-1 r, the preconditioner
+    of the Newton system."""
+    return prior_solve(prior_solve(r, alpha, theta, dx), alpha, theta, dx) / cell_volume(r.shape, dx)
+
+
+def prior_sample(w, c0, alpha, theta, dx):
+    """A draw from the prior N(c0, (dx^dims A A)^-1) for white noise w ~ N(0, I):
+    c = c0 + A^-1 w / sqrt(dx^dims) (covariance A^-1 A^-1 / dx^dims, A symmetric)."""
+    w = np.asarray(w, np.float64)
+    return c0 + prior_solve(w / np.sqrt(cell_volume(w.shape, dx)), alpha, theta, dx)
 
 
 @dataclass
@@ -127,15 +137,21 @@ class NewtonRecord:
     cg_rel_res: float = 0.0
 
 
-def cg_steihaug(hv: Callable[[np.ndarray], np.ndarray], g: np.ndarray, eta: float, max_cg: int):
-    """Approximate solve of H p = -g from p = 0 (conjugate gradients with the
-    forcing eta and the negative-curvature stop). Returns p, iterations,
-    whether non-positive curvature ended it, and ||r|| / ||g||."""
+def cg_steihaug(hv: Callable[[np.ndarray], np.ndarray], g: np.ndarray, eta: float, max_cg: int,
+                prec: Callable[[np.ndarray], np.ndarray] = None):
+    """Approximate solve of H p = -g from p = 0: conjugate gradients, preconditioned
+    by prec (symmetric positive definite, M ~ H^-1; None: M = I), with the forcing
+    eta on the M-norm of the residual, ||r||_M = sqrt(r.Mr), and the
+    negative-curvature stop (at the first iteration the direction d = -M g itself
+    is taken). Returns p, iterations, whether non-positive curvature ended it, and
+    ||r||_M / ||g||_M."""
+    M = prec if prec is not None else (lambda v: v)
     p = np.zeros_like(g)
     r = -g
-    d = r.copy()
-    rr = float(np.sum(r * r))
-    r0 = np.sqrt(rr)
+    z = M(r)
+    d = z.copy()
+    rz = float(np.sum(r * z))
+    r0 = np.sqrt(rz)
     if r0 == 0.0:
         return p, 0, False, 0.0
     it = 0
@@ -145,24 +161,27 @@ def cg_steihaug(hv: Callable[[np.ndarray], np.ndarray], g: np.ndarray, eta: floa
         it += 1
         if dHd <= 0.0:
             if it == 1:
-                p = -g.copy()
-            return p, it, True, np.sqrt(rr) / r0
-        a = rr / dHd
+                p = d.copy()
+            return p, it, True, np.sqrt(rz) / r0
+        a = rz / dHd
         p = p + a * d
         r = r - a * Hd
-        rr_new = float(np.sum(r * r))
-        if np.sqrt(rr_new) <= eta * r0:
-            return p, it, False, np.sqrt(rr_new) / r0
-        d = r + (rr_new / rr) * d
-        rr = rr_new
-    return p, it, False, np.sqrt(rr) / r0
+        z = M(r)
+        rz_new = float(np.sum(r * z))
+        if np.sqrt(rz_new) <= eta * r0:
+            return p, it, False, np.sqrt(rz_new) / r0
+        d = z + (rz_new / rz) * d
+        rz = rz_new
+    return p, it, False, np.sqrt(rz) / r0
 
 
-def newton_cg(cost_grad: Callable, hessvec: Callable, c: np.ndarray, cfg: NewtonConfig):
+def newton_cg(cost_grad: Callable, hessvec: Callable, c: np.ndarray, cfg: NewtonConfig,
+              prec: Callable[[np.ndarray], np.ndarray] = None):
     """Inexact Newton-CG with Armijo backtracking. cost_grad(c) -> (J, g, state);
-    hessvec(state, v) -> H v at the point whose state it is. Returns the final
-    c, the per-iteration records and the reason it stopped (0: iteration limit,
-    1: gradient tolerance, 2: line search failed)."""
+    hessvec(state, v) -> H v at the point whose state it is; prec: the CG
+    preconditioner (None: none). Returns the final c, the per-iteration records
+    and the reason it stopped (0: iteration limit, 1: gradient tolerance, 2: line
+    search failed)."""
     c = np.asarray(c, np.float64).copy()
     J, g, st = cost_grad(c)
     g0 = np.sqrt(float(np.sum(g * g)))
@@ -172,7 +191,7 @@ def newton_cg(cost_grad: Callable, hessvec: Callable, c: np.ndarray, cfg: Newton
         if gn <= cfg.rel_tol * g0:
             return c, log, 1
         eta = min(cfg.eta_max, np.sqrt(gn / g0))
-        p, its, neg, rel = cg_steihaug(lambda v: hessvec(st, v), g, eta, cfg.max_cg)
+        p, its, neg, rel = cg_steihaug(lambda v: hessvec(st, v), g, eta, cfg.max_cg, prec)
         gp = float(np.sum(g * p))
         a = 1.0
         for bt in range(cfg.max_backtrack + 1):

@@ -137,6 +137,33 @@ def test_cg_solves_spd_system_and_stops_on_negative_curvature():
     np.testing.assert_allclose(p, [-a, -0.5 * a], rtol=1e-14)
 
 
+def test_preconditioned_cg():
+    """With any SPD preconditioner CG still solves the SPD system exactly; with
+    M = H^-1 it needs one iteration; the prior covariance (spectral solve) is the
+    inverse of dx^dims A A (finite-volume stencil)."""
+    rng = np.random.default_rng(9)
+    n = 12
+    Q = rng.standard_normal((n, n))
+    H = Q @ Q.T + n * np.eye(n)
+    g = rng.standard_normal(n)
+    Md = rng.uniform(0.1, 3.0, n)
+    p, its, neg, rel = oi.cg_steihaug(lambda v: H @ v, g, 1e-14, 4 * n, prec=lambda v: Md * v)
+    np.testing.assert_allclose(p, np.linalg.solve(H, -g), rtol=1e-10, atol=1e-12)
+    Hinv = np.linalg.inv(H)
+    p, its, neg, rel = oi.cg_steihaug(lambda v: H @ v, g, 1e-8, 10, prec=lambda v: Hinv @ v)
+    assert its == 1 and rel < 1e-10
+    np.testing.assert_allclose(p, -Hinv @ g, rtol=1e-10)
+    # first-iteration negative curvature returns the preconditioned direction -M g
+    Hn = np.diag([-1.0, 2.0])
+    p, its, neg, _ = oi.cg_steihaug(lambda v: Hn @ v, np.array([1.0, 0.0]), 1e-8, 5, prec=lambda v: 2.0 * v)
+    assert neg and its == 1 and np.array_equal(p, [-2.0, 0.0])
+    shape, alpha, dx, theta = (6, 5, 7), 0.03, 20.0, (1600.0, 900.0, 2500.0)
+    r = rng.standard_normal(shape)
+    z = oi.prior_covariance(r, alpha, theta, dx)
+    back = oi.cell_volume(shape, dx) * oi.prior_operator(oi.prior_operator(z, alpha, theta, dx), alpha, theta, dx)
+    np.testing.assert_allclose(back, r, rtol=1e-9, atol=1e-9)
+
+
 def test_newton_one_step_on_a_quadratic():
     """J = 1/2 x.Qx - b.x: one Newton step with CG to high accuracy lands on
     Q^-1 b with the full step accepted; the next test of the gradient stops."""
@@ -152,6 +179,10 @@ def test_newton_one_step_on_a_quadratic():
     x, log, reason = oi.newton_cg(cg, hv, np.zeros(n), cfg)
     np.testing.assert_allclose(x, np.linalg.solve(Q, b), rtol=1e-9, atol=1e-10)
     assert log[0].step == 1.0 and log[0].backtracks == 0
+    assert reason == 1 and len(log) == 2
+    # the same with a diagonal preconditioner
+    x, log, reason = oi.newton_cg(cg, hv, np.zeros(n), cfg, prec=lambda v: v / np.diag(Q))
+    np.testing.assert_allclose(x, np.linalg.solve(Q, b), rtol=1e-9, atol=1e-10)
     assert reason == 1 and len(log) == 2
 
 
