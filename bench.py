@@ -124,6 +124,25 @@ def counters_pass():
                       "stencil_source_sha256": stencil_source_hash()}), flush=True)
 
 
+def gemm_peak_tflops(torch, dev, n=8192, reps=10):
+    """Dense bf16 GEMM rate of the vendor library (torch.matmul, n x n x n, contiguous
+    operands): the measured MFMA reference next to the published 2.5 PFLOP/s."""
+    a = torch.randn((n, n), dtype=torch.bfloat16, device=dev)
+    b = torch.randn((n, n), dtype=torch.bfloat16, device=dev)
+    for _ in range(3):
+        c = torch.matmul(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        c = torch.matmul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b, c
+    return 2.0 * n ** 3 / t / 1e12
+
+
 def copy_peak_gbs(torch, dev, nbytes=1 << 30, reps=10):
     """Device-to-device copy rate (read + write bytes per second) of a 1 GiB buffer: the
     measured reference next to the published 8 TB/s."""
@@ -542,6 +561,8 @@ def main():
     log(f"grad rel err {rel_err:.4f} cos {cos:.5f}")
 
     copy_gbs = copy_peak_gbs(torch, dev)
+    gemm_tf = gemm_peak_tflops(torch, dev)
+    log(f"library bf16 GEMM {gemm_tf:.0f} TFLOP/s")
     log(f"device copy {copy_gbs:.0f} GB/s")
 
     # ---- rooflines: algorithmic bytes (flops) per launch over the measured mean launch duration
@@ -566,6 +587,7 @@ def main():
             else:
                 row["TFLOP/s"] = work / (us * 1e-6) / 1e12
                 row["frac_mfma_bf16"] = row["TFLOP/s"] / BF16_PEAK_TFLOPS
+                row["frac_of_library_gemm"] = row["TFLOP/s"] / gemm_tf
         kernels[name] = row
     # dominant kernel: the main-stream (critical-path) kernel with the most time per gradient; the
     # encode and decode run on side streams beside the stencil steps, so their event time overlaps
@@ -627,6 +649,7 @@ def main():
                         "effective_vs_float32_history": round(4.0 * 4 * N * (T - 1) / store_bytes, 1)},
         "train": dict(train_info, wall_s=round(t_train_total, 2)),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
+        "measured_peaks": {"device_copy_GBps": round(copy_gbs, 1), "library_bf16_gemm_TFLOPs": round(gemm_tf, 1)},
         # the same stencil kernels with the GPU to themselves (no encode or decode beside them)
         "checkpoint_kernels": {k: dict({"us": round(us, 2), "timed_launches": n},
                                        **({"GB/s": round(per_launch[k][1] / (us * 1e-6) / 1e9, 1),
@@ -641,19 +664,20 @@ def main():
 
 
 def newton_iteration(args, p, ae_solver, ck, c0, wav, d_obs, sigma):
-    """Wall time of one Gauss-Newton CG iteration (eta tiny, so CG runs its
-    newton_cg iterations) with the AE store and with checkpointing, from the same
-    start model; the two updates are compared."""
+    """Wall time of one Gauss-Newton CG iteration (prior-preconditioned, eta tiny, so
+    CG runs its newton_cg iterations) with the AE store and with checkpointing, from
+    the same start model; the two updates are compared."""
     import torch
     alpha, theta = 2e-6, (4 * p.dx * p.dx,) * 3
-    res = {"max_cg": args.newton_cg, "prior": {"alpha": alpha, "theta_m2": theta[0]}}
+    res = {"max_cg": args.newton_cg, "preconditioner": "prior covariance",
+           "prior": {"alpha": alpha, "theta_m2": theta[0]}}
     upd = {}
     for name, sol in (("ae", ae_solver), ("checkpoint", ck)):
         sol.set_prior(alpha, theta, c0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         c1, recs, it, reason = sol.newton_cg(c0, wav, d_obs, sigma, max_newton=1, max_cg=args.newton_cg,
-                                             eta_max=1e-6, gauss_newton=1)
+                                             eta_max=1e-6, gauss_newton=1, precondition=1)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         r0 = recs[0]

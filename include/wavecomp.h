@@ -276,6 +276,9 @@ typedef struct wv_newton_cfg {
     double c_armijo;        /* sufficient decrease J(c + a p) <= J + c_armijo a g.p, in (0, 1) */
     int32_t max_backtrack;  /* halvings of the step length before the line search fails (>= 0) */
     int32_t gauss_newton;   /* 1: Gauss-Newton misfit Hessian, 0: full Newton (full or AE store) */
+    int32_t precondition;   /* 1: CG preconditioned by the prior covariance (dx^dims A A)^-1, each
+                               application two elliptic solves by CG to 1e-6 relative residual;
+                               0: none. 1 needs a prior (WV_ESTATE otherwise) */
 } wv_newton_cfg;
 
 typedef struct wv_newton_rec {
@@ -284,7 +287,7 @@ typedef struct wv_newton_rec {
     double prior;
     double gnorm;       /* |g|, g = gradient of J */
     double step;        /* accepted step length (0 for the last iterate) */
-    double cg_rel_res;  /* |H p + g| / |g| of the CG recurrence when CG stopped */
+    double cg_rel_res;  /* |r|_M / |g|_M of the CG recurrence when CG stopped (r = -g - H p) */
     int32_t cg_iters;   /* Hessian actions spent on the step from this iterate */
     int32_t neg_curv;   /* CG stopped at non-positive curvature */
     int32_t backtracks; /* step halvings (max_backtrack + 1: line search failed) */
@@ -298,10 +301,11 @@ typedef struct wv_newton_rec {
  *   2. stop if |g| <= rel_tol |g_0|;
  *   3. conjugate gradients on H p = -g from p = 0, H = hessvec() + prior Hessian
  *      (each iteration one Hessian action, which decompresses the stored forward
- *      history again in the AE modes), until |r| <= eta |g| with
- *      eta = min(eta_max, sqrt(|g| / |g_0|)), max_cg iterations, or non-positive
- *      curvature d.Hd <= 0 (then the iterate so far is kept, or p = -g at the
- *      first iteration);
+ *      history again in the AE modes), optionally preconditioned by the prior
+ *      covariance M, until |r|_M <= eta |g|_M (|r|_M = sqrt(r.Mr), M = I without
+ *      preconditioning) with eta = min(eta_max, sqrt(|g| / |g_0|)), max_cg
+ *      iterations, or non-positive curvature d.Hd <= 0 (then the iterate so far
+ *      is kept, or p = d = -M g at the first iteration);
  *   4. Armijo backtracking from the step length 1, halving; every trial runs a
  *      gradient (forward with storage + adjoint), so an accepted trial leaves its
  *      store for the next Hessian actions. A trial speed outside the stable,

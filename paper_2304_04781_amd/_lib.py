@@ -43,7 +43,7 @@ class AeTrainCfg(C.Structure):
 class WvNewtonCfg(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_cg", C.c_int32), ("eta_max", C.c_double),
                 ("rel_tol", C.c_double), ("c_armijo", C.c_double), ("max_backtrack", C.c_int32),
-                ("gauss_newton", C.c_int32)]
+                ("gauss_newton", C.c_int32), ("precondition", C.c_int32)]
 
 
 class WvNewtonRec(C.Structure):
@@ -396,10 +396,10 @@ NEWTON_FIELDS = [f for f, _ in WvNewtonRec._fields_]
 
 
 def wv_newton_cg(ctx, c, wavelet, d_obs, sigma, max_newton=5, max_cg=10, eta_max=0.5, rel_tol=1e-6,
-                 c_armijo=1e-4, max_backtrack=10, gauss_newton=1):
+                 c_armijo=1e-4, max_backtrack=10, gauss_newton=1, precondition=0):
     """Runs Newton-CG in place on c; returns (records as dicts, iterations, reason)."""
     cfg = WvNewtonCfg(int(max_newton), int(max_cg), float(eta_max), float(rel_tol), float(c_armijo),
-                      int(max_backtrack), int(gauss_newton))
+                      int(max_backtrack), int(gauss_newton), int(precondition))
     recs = (WvNewtonRec * (int(max_newton) + 1))()
     it, reason = C.c_int32(), C.c_int32()
     f32 = torch.float32

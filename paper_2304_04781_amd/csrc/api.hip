@@ -267,7 +267,8 @@ struct wv_ctx {
     double prior_theta[3] = {0.0, 0.0, 0.0};
     float* prior_c0 = nullptr;
     float* prior_w = nullptr;    // A (c - c0) or A dc
-    float* nvec = nullptr;       // [7][N]: g, trial g, trial c, p, r, d, H d
+    float* nvec = nullptr;       // [8][N]: g, trial g, trial c, p, r, d, H d, M r
+    float* pvec = nullptr;       // [4][N]: the inner CG of the elliptic solves
 
     long long state_floats() const { return 4LL * N * S; }
     float* slot_ptr(int b) const { return slots + (long long)(b - 1) * state_floats(); }
@@ -1055,7 +1056,7 @@ int wv_destroy(wv_ctx* c)
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
                       &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr,
                       &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf,
-                      &c->prior_c0, &c->prior_w, &c->nvec})
+                      &c->prior_c0, &c->prior_w, &c->nvec, &c->pvec})
         dev_free(*p);
     dev_free(c->partial);
     dev_free(c->dscal);
@@ -1574,6 +1575,50 @@ void prior_hv(wv_ctx* c, const float* dc, float* Hdc)
     apply_prior(c, c->prior_w, nullptr, Hdc, cell_volume(c), true);
 }
 
+// conjugate gradients on A x = b from x = 0 (A symmetric positive definite) until
+// |r| <= rtol |b| or maxit iterations, with the inner work vectors pvec[1..3];
+// returns the iterations, *rel the final relative residual
+int prior_solve(wv_ctx* c, const float* b, float* x, double rtol, int maxit, double* rel_out)
+{
+    const long long N = c->N;
+    if (!c->pvec) c->pvec = dev_alloc<float>(4 * (size_t)N);
+    float* r = c->pvec + N;
+    float* d = c->pvec + 2 * N;
+    float* Ad = c->pvec + 3 * N;
+    launch_fill(x, N, 0.f, c->st);
+    launch_copy(r, b, N, c->st);
+    launch_copy(d, r, N, c->st);
+    double rr = dot_host(c, r, r);
+    const double bn = std::sqrt(rr);
+    int it = 0;
+    double rel = bn > 0.0 ? 1.0 : 0.0;
+    while (rel > rtol && it < maxit) {
+        apply_prior(c, d, nullptr, Ad, 1.0, false);
+        const double a = rr / dot_host(c, d, Ad);
+        launch_axpby(x, d, a, 1.0, N, c->st);
+        launch_axpby(r, Ad, -a, 1.0, N, c->st);
+        const double rr_new = dot_host(c, r, r);
+        ++it;
+        rel = std::sqrt(rr_new) / bn;
+        launch_axpby(d, r, 1.0, rr_new / rr, N, c->st);
+        rr = rr_new;
+    }
+    if (rel_out) *rel_out = rel;
+    return it;
+}
+
+// z = (dx^dims A A)^-1 r, the prior covariance (two elliptic solves)
+constexpr double PREC_RTOL = 1e-6;
+constexpr int PREC_MAXIT = 1000;
+void prior_covariance(wv_ctx* c, const float* r, float* z)
+{
+    if (!c->pvec) c->pvec = dev_alloc<float>(4 * (size_t)c->N);
+    float* y = c->pvec;
+    prior_solve(c, r, y, PREC_RTOL, PREC_MAXIT, nullptr);
+    launch_axpby(y, y, 1.0 / cell_volume(c), 0.0, c->N, c->st);
+    prior_solve(c, y, z, PREC_RTOL, PREC_MAXIT, nullptr);
+}
+
 // positive, finite and leapfrog-stable (the test of check_speed, without throwing)
 bool speed_ok(wv_ctx* c, const float* cdev)
 {
@@ -1642,30 +1687,12 @@ int wv_prior_sample(wv_ctx* c, const float* w, float* out, double rtol, int32_t 
         WV_REQUIRE(c->prior_alpha > 0.0, WV_ESTATE, "no prior set (wv_set_prior with alpha > 0)");
         WV_REQUIRE(rtol > 0.0 && rtol < 1.0 && maxit >= 1, WV_EINVAL, "rtol in (0, 1) and maxit >= 1 required");
         const long long N = c->N;
-        if (!c->nvec) c->nvec = dev_alloc<float>(7 * (size_t)N);
-        float* x = c->nvec;
-        float* r = x + N;
-        float* d = x + 2 * N;
-        float* Ad = x + 3 * N;
-        // conjugate gradients on A x = w / sqrt(dx^dims) from x = 0 (A is symmetric positive definite)
-        launch_fill(x, N, 0.f, c->st);
-        launch_axpby(r, w, 1.0 / std::sqrt(cell_volume(c)), 0.0, N, c->st);
-        launch_copy(d, r, N, c->st);
-        double rr = dot_host(c, r, r);
-        const double b = std::sqrt(rr);
-        int it = 0;
-        double rel = b > 0.0 ? 1.0 : 0.0;
-        while (rel > rtol && it < maxit) {
-            apply_prior(c, d, nullptr, Ad, 1.0, false);
-            const double a = rr / dot_host(c, d, Ad);
-            launch_axpby(x, d, a, 1.0, N, c->st);
-            launch_axpby(r, Ad, -a, 1.0, N, c->st);
-            const double rr_new = dot_host(c, r, r);
-            ++it;
-            rel = std::sqrt(rr_new) / b;
-            launch_axpby(d, r, 1.0, rr_new / rr, N, c->st);
-            rr = rr_new;
-        }
+        if (!c->nvec) c->nvec = dev_alloc<float>(8 * (size_t)N);
+        float* b = c->nvec;
+        float* x = c->nvec + N;
+        launch_axpby(b, w, 1.0 / std::sqrt(cell_volume(c)), 0.0, N, c->st);
+        double rel = 0.0;
+        const int it = prior_solve(c, b, x, rtol, maxit, &rel);
         launch_lincomb(out, c->prior_c0, 1.0, x, N, c->st);
         WV_HIP(hipStreamSynchronize(c->st));
         if (h_iters) *h_iters = it;
@@ -1685,9 +1712,12 @@ int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_ob
                        cfg->c_armijo < 1.0,
                    WV_EINVAL, "eta_max and c_armijo must lie in (0, 1), rel_tol >= 0");
         WV_REQUIRE(cfg->gauss_newton == 0 || cfg->gauss_newton == 1, WV_EINVAL, "gauss_newton must be 0 or 1");
+        WV_REQUIRE(cfg->precondition == 0 || cfg->precondition == 1, WV_EINVAL, "precondition must be 0 or 1");
+        WV_REQUIRE(!cfg->precondition || c->prior_alpha > 0.0, WV_ESTATE,
+                   "prior preconditioning needs a prior (wv_set_prior with alpha > 0)");
         WV_REQUIRE(c->mode != WV_STORE_NONE, WV_ESTATE, "Newton-CG needs a storage mode");
         const long long N = c->N;
-        if (!c->nvec) c->nvec = dev_alloc<float>(7 * (size_t)N);
+        if (!c->nvec) c->nvec = dev_alloc<float>(8 * (size_t)N);
         float* g = c->nvec;
         float* gt = g + N;
         float* ct = g + 2 * N;
@@ -1695,6 +1725,8 @@ int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_ob
         float* r = g + 4 * N;
         float* d = g + 5 * N;
         float* Hd = g + 6 * N;
+        // z = M r: the prior covariance, or r itself without preconditioning
+        float* z = cfg->precondition ? g + 7 * N : r;
         auto record = [](double Jm, double R, double gn, int status) {
             wv_newton_rec q{};
             q.cost = Jm + R;
@@ -1721,12 +1753,14 @@ int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_ob
                 break;
             }
             const double eta = std::min(cfg->eta_max, std::sqrt(gn / g0));
-            // conjugate gradients on H p = -g from p = 0
+            // conjugate gradients on H p = -g from p = 0, preconditioned by M, the
+            // forcing applied to the M-norm of the residual sqrt(r.Mr)
             launch_fill(p, N, 0.f, c->st);
             launch_axpby(r, g, -1.0, 0.0, N, c->st);
-            launch_copy(d, r, N, c->st);
-            double rr = gn * gn;
-            const double r0 = gn;
+            if (cfg->precondition) prior_covariance(c, r, z);
+            launch_copy(d, z, N, c->st);
+            double rz = dot_host(c, r, z);
+            const double r0 = std::sqrt(rz);
             int its = 0, neg = 0;
             double rel = 1.0;
             while (its < cfg->max_cg) {
@@ -1736,18 +1770,19 @@ int wv_newton_cg(wv_ctx* c, float* cvec, const float* wavelet, const float* d_ob
                 ++its;
                 if (!(dHd > 0.0)) {
                     neg = 1;
-                    if (its == 1) launch_axpby(p, g, -1.0, 0.0, N, c->st);
-                    rel = std::sqrt(rr) / r0;
+                    if (its == 1) launch_copy(p, d, N, c->st);
+                    rel = std::sqrt(rz) / r0;
                     break;
                 }
-                const double a = rr / dHd;
+                const double a = rz / dHd;
                 launch_axpby(p, d, a, 1.0, N, c->st);
                 launch_axpby(r, Hd, -a, 1.0, N, c->st);
-                const double rr_new = dot_host(c, r, r);
-                rel = std::sqrt(rr_new) / r0;
-                if (std::sqrt(rr_new) <= eta * r0) break;
-                launch_axpby(d, r, 1.0, rr_new / rr, N, c->st);
-                rr = rr_new;
+                if (cfg->precondition) prior_covariance(c, r, z);
+                const double rz_new = dot_host(c, r, z);
+                rel = std::sqrt(rz_new) / r0;
+                if (std::sqrt(rz_new) <= eta * r0) break;
+                launch_axpby(d, z, 1.0, rz_new / rz, N, c->st);
+                rz = rz_new;
             }
             const double gp = dot_host(c, g, p);
             // Armijo backtracking; every trial is a full gradient evaluation

@@ -71,21 +71,25 @@ def newton_case():
     return p, sol, f32(d), sigma
 
 
-@pytest.mark.parametrize("gauss_newton", [1, 0])
-def test_newton_cg_matches_oracle(gauss_newton):
-    """Three Newton iterations with at most 4 CG iterations each (full storage):
+@pytest.mark.parametrize("gauss_newton,precondition", [(1, 0), (0, 0), (1, 1), (0, 1)])
+def test_newton_cg_matches_oracle(gauss_newton, precondition):
+    """Three Newton iterations with at most 4 CG iterations each (full storage),
+    without and with the prior-covariance preconditioner (on the GPU two CG solves
+    of the elliptic operator to 1e-6, in the oracle the exact cosine-mode solve):
     iteration records, costs, gradient norms and the final model against the
     oracle's Newton-CG on the same problem."""
     p, sol, d, sigma = newton_case()
-    print("case", p.name, "gauss_newton", gauss_newton, flush=True)
+    print("case", p.name, "gauss_newton", gauss_newton, "precondition", precondition, flush=True)
     cfg = dict(max_newton=3, max_cg=4, eta_max=0.5, rel_tol=1e-8, c_armijo=1e-4, max_backtrack=10)
     cost_grad, hv = oi.wave_map_problem(sol, p.wavelet, p.src, p.rec, d, sigma, p.c_start, ALPHA, THETA,
                                         gauss_newton=bool(gauss_newton), src_w=p.src_w)
-    c_o, log_o, reason_o = oi.newton_cg(cost_grad, hv, p.c_start, oi.NewtonConfig(**cfg))
+    prec = (lambda r: oi.prior_covariance(r, ALPHA, THETA, p.dx)) if precondition else None
+    c_o, log_o, reason_o = oi.newton_cg(cost_grad, hv, p.c_start, oi.NewtonConfig(**cfg), prec=prec)
     s = WaveSolver.for_problem(p)
     s.set_storage(L.STORE_FULL)
     s.set_prior(ALPHA, THETA, p.c_start)
-    c, log, it, reason = s.newton_cg(p.c_start, p.wavelet, d, sigma, gauss_newton=gauss_newton, **cfg)
+    c, log, it, reason = s.newton_cg(p.c_start, p.wavelet, d, sigma, gauss_newton=gauss_newton,
+                                     precondition=precondition, **cfg)
     for r_o, r in zip(log_o, log):
         print("oracle", r_o, "\ngpu   ", r, flush=True)
     assert reason == reason_o and it == len(log_o) - 1
@@ -121,7 +125,8 @@ def test_newton_cg_argument_checks():
     with pytest.raises(L.WvError):   # no storage mode
         s.newton_cg(p.c_start, p.wavelet, d, sigma)
     s.set_storage(L.STORE_FULL)
-    for bad in (dict(max_cg=0), dict(eta_max=1.0), dict(c_armijo=0.0), dict(gauss_newton=2), dict(max_newton=-1)):
+    for bad in (dict(max_cg=0), dict(eta_max=1.0), dict(c_armijo=0.0), dict(gauss_newton=2), dict(max_newton=-1),
+                dict(precondition=2), dict(precondition=1)):   # the last: no prior set
         with pytest.raises(L.WvError):
             s.newton_cg(p.c_start, p.wavelet, d, sigma, **bad)
     with pytest.raises(L.WvError):
