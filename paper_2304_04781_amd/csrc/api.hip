@@ -1098,7 +1098,7 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             WV_REQUIRE(ae_input_dim(ae) == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
             WV_REQUIRE(c->has_y && c->g.nz % 4 == 0 && c->g.ny % 4 == 0 && c->g.nx % 4 == 0, WV_ESHAPE,
                        "time compression needs a 3D grid divisible into 4^3 blocks");
-            WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE, WV_EINVAL,
+            WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE && guard_tol <= 0.0, WV_EINVAL,
                        "the accuracy guard and its fallback apply to the space modes");
             c->TB = ctx_time_grid(c).B;
             c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
