@@ -216,3 +216,37 @@ def test_time_compressed_gradient_with_trained_network():
     err_u = rel(gu.cpu().numpy(), g0n)
     print("untrained rel err", err_u, flush=True)
     assert err_u > 3 * err
+
+
+@pytest.mark.parametrize("nt", [2, 33, 65])
+def test_time_store_window_edges(nt):
+    """Horizons at the window edges: one stored level (a window of 1), exactly one
+    full window, exactly two. Every level the reverse solves read equals the
+    window round trip; gradient and Gauss-Newton Hv run; store size by windows."""
+    p = time_problem(nt)
+    print("case nt", nt, flush=True)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    net = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    T1 = nt - 1
+    e_all = s.forward_e(p.c_start, p.wavelet, list(range(1, nt)))
+    L.ae_time_fit_beta(net.handle, s.grid, e_all, T1, 1e-7)
+    t = WaveSolver.for_problem(p)
+    t.set_storage(L.STORE_AE_TIME, ae=net)
+    B = 8 * 8 * 10
+    nwin = (T1 + 31) // 32
+    assert t.storage_bytes() == nwin * B * (32 * 2 + 8)
+    J, g = t.gradient(p.c_start, p.wavelet, d, sigma)
+    assert torch.isfinite(g).all() and torch.any(g != 0)
+    lat = torch.empty((B, 32), dtype=torch.int16, device="cuda")
+    meta = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    dec = torch.empty((32, 1) + t.shape, dtype=torch.float32, device="cuda")
+    for w in range(nwin):
+        nvalid = min(32, T1 - 32 * w)
+        L.ae_time_encode(net.handle, t.grid, e_all[32 * w:32 * w + nvalid], nvalid, lat, meta)
+        L.ae_time_decode(net.handle, t.grid, lat, meta, nvalid, dec)
+        for lvl in range(nvalid):
+            assert torch.equal(t.load_e(32 * w + 1 + lvl), dec[lvl]), (w, lvl)
+    assert torch.isfinite(t.hessvec(p.c_start, p.c_start * 0.01)).all()
