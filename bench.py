@@ -420,8 +420,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the compressed gradient on a single "
-              "MI355X; sharding by source or by domain is not implemented",
+        print("bench.py measures one GPU only: the compressed gradient runs on a single MI355X; "
+              "sharding by source or by domain is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
