@@ -65,7 +65,10 @@ __device__ __forceinline__ float e4m32f(uint8_t c)
 // that know the source layout; epilogues consume (row, col, value).
 // ------------------------------------------------------------------------------------
 constexpr int BK = 64;  // k per LDS stage: two 32-deep MFMA steps; depths below a multiple are zero-filled
-constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row
+#ifndef WV_LDS_PAD
+#define WV_LDS_PAD 8
+#endif
+constexpr int LDS_PAD = WV_LDS_PAD;  // bf16 elements of padding per LDS row
 
 // registers holding one BR x BK tile between its global load and its LDS store:
 // chunk c = tid + 256 i of 8 bf16 in v[i]
