@@ -56,6 +56,10 @@ def parse():
                     help="training on prior draws (Algorithm 1) against in-run snapshots at 256^3: "
                          "compression and gradient errors on the start, true, midway and a held-out model")
     ap.add_argument("--draws", type=int, default=4)
+    ap.add_argument("--inversion", action="store_true",
+                    help="a short MAP inversion at 256^3 x 2000 (prior-preconditioned Gauss-Newton CG) with the "
+                         "AE store and with checkpointing: wall time, Hv count, cost and model error")
+    ap.add_argument("--inv-iters", type=int, default=5)
     ap.add_argument("--time", action="store_true",
                     help="time-compression scheme at 256^3 x 2000: gradient and Gauss-Newton Hv against "
                          "checkpointing (network trained on every 4th window of the start model's solve)")
@@ -321,6 +325,80 @@ def bayes_pass(args):
                       "e_error_every_states": 4 * every, "errors": table}), flush=True)
 
 
+def inversion_pass(args):
+    """The analogue of the paper's inversion experiment (speedup and inverse-solution error of
+    the compressed path against the uncompressed one): Newton-CG from c_start with the
+    BiLaplacian prior (mean c_start), CG preconditioned by the prior covariance, Eisenstat-Walker
+    forcing with eta_max 0.5, at most 10 CG iterations per step. The network is trained once on
+    snapshots of the forward solve at c_start and kept for every iterate."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd import compressor as C
+    from paper_2304_04781_amd.solver import WaveSolver
+    L.load()
+    dev = torch.device("cuda", 0)
+    T = args.nt
+    p = W.problem_256(T)
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    K_exc = int(round(args.exceptions * P))
+    c_true = torch.tensor(p.c_true, dtype=torch.float32, device=dev)
+    c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    clean, _, _ = s.forward(c_true, wav)
+    clean_h = clean.cpu().numpy().astype(np.float64)
+    sigma = 0.01 * float(np.abs(clean_h).max())
+    d_obs = torch.tensor((clean_h + sigma * p.noise).astype(np.float32), device=dev)
+    del clean
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    ncap = (T - 1) // args.snapshot_every
+    t0 = time.perf_counter()
+    info = C.train_from_forward(s, net, c0, wav, every=args.snapshot_every, epochs=args.epochs, batch=args.batch,
+                                perms=W.shuffles(ncap * P, args.epochs, seed=5))
+    t_train = time.perf_counter() - t0
+    log(f"training {info}")
+    alpha, theta = 2e-6, (4 * p.dx * p.dx,) * 3
+    e_start = float(torch.linalg.norm(c0 - c_true))
+    top = p.nz // 3
+    e_start_top = float(torch.linalg.norm((c0 - c_true)[:top]))
+    res, models = {}, {}
+    for name in ("ae", "checkpoint"):
+        sol = WaveSolver.for_problem(p)
+        if name == "ae":
+            L.wv_set_ae_exceptions(sol.ctx, K_exc)
+            sol.set_storage(L.STORE_AE_BF16, ae=net)
+        else:
+            sol.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
+        sol.set_prior(alpha, theta, c0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, recs, it, reason = sol.newton_cg(c0, wav, d_obs, sigma, max_newton=args.inv_iters, max_cg=10,
+                                            eta_max=0.5, gauss_newton=1, precondition=1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        models[name] = c
+        res[name] = {"wall_s": round(wall, 2), "newton_iterations": it, "stop_reason": reason,
+                     "hessvec": sum(r["cg_iters"] for r in recs),
+                     "gradients": 1 + sum(1 + r["backtracks"] for r in recs[:it]),
+                     "cost": [round(r["cost"], 3) for r in recs],
+                     "gnorm_ratio": round(recs[-1]["gnorm"] / recs[0]["gnorm"], 5),
+                     "model_err_rel": round(float(torch.linalg.norm(c - c_true)) / e_start, 5),
+                     "model_err_rel_top_third": round(float(torch.linalg.norm((c - c_true)[:top])) / e_start_top, 5)}
+        log(f"{name}: {res[name]}")
+        sol.close()
+    ca, cc = models["ae"].double(), models["checkpoint"].double()
+    out = {"workload": f"{p.name}: MAP inversion, {args.inv_iters} prior-preconditioned Gauss-Newton CG iterations, "
+                       f"AE store (bf16, {K_exc} exact patches per state) vs revolve checkpointing",
+           "prior": {"alpha": alpha, "theta_m2": theta[0], "mean": "c_start"},
+           "train_s": round(t_train, 2), "results": res,
+           "speedup_vs_checkpoint": round(res["checkpoint"]["wall_s"] / res["ae"]["wall_s"], 4),
+           "speedup_incl_training": round(res["checkpoint"]["wall_s"] / (res["ae"]["wall_s"] + t_train), 4),
+           "model_update_rel_diff": round(float(torch.linalg.norm(ca - cc) / torch.linalg.norm(cc - c0.double())), 5)}
+    print(json.dumps(out), flush=True)
+
+
 def time_pass(args):
     """The time-compression scheme (e on 4^3 blocks x 32 levels) on the 256^3 x 2000 gradient workload."""
     import torch
@@ -417,6 +495,9 @@ def main():
         return
     if args.time:
         time_pass(args)
+        return
+    if args.inversion:
+        inversion_pass(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
