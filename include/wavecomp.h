@@ -73,8 +73,10 @@ extern "C" {
 #define WV_STORE_AE_TIME     5  /* time compression (Sec. 3.2): e only, 4^3 cells x 32
                                    consecutive levels per vector, bfloat16 latents;
                                    the reverse solves decode a whole window at once.
-                                   Needs nz, ny, nx divisible by 4; no exception
-                                   patches, guard or fallback (space modes only) */
+                                   Needs nz, ny, nx divisible by 4. Exception vectors:
+                                   the K (wv_set_ae_exceptions) largest-range vectors
+                                   of each window and source are kept exactly. No
+                                   guard or fallback (space modes only) */
 
 /* Latent formats of ae_encode / ae_decode. */
 #define AE_LATENT_BF16  0
@@ -151,6 +153,8 @@ int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
  * (float32), and decompression of e restores them. Ranges are compared at a
  * resolution of 2^-5 relative (the top 14 bits of the float); within the bin of
  * the k-th largest range, lower patch indices come first.
+ * In the time-compression mode k_per_step counts e-only vectors (4^3 cells x 32
+ * levels) kept per window and source, chosen the same way.
  * 0 (default) stores latents only, as in the paper; the paper mentions storing
  * residuals to bound the error (Sec. 1, Sec. 3.3). Takes effect at the next
  * wv_set_storage. */

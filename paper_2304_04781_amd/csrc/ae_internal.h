@@ -39,6 +39,16 @@ void ae_time_encode(const ae_net* net, const TimeGrid& tg, const float* e_win, i
 void ae_time_decode(const ae_net* net, const TimeGrid& tg, const uint16_t* latent, const float* meta, int nvalid,
                     float* e_win, hipStream_t st);
 
+// exception vectors of the time scheme, per window and source s: the K vectors with
+// the largest range r (meta [B][2] of source s, the same key and tie rule as the
+// patches) in increasing block order into idx [K], their values [K][2048] into exc
+// (gathered from the window buffer before it is refilled); restore writes levels
+// t < nvalid of them back over a decoded window
+void time_exceptions_store(const TimeGrid& tg, const float* e_win, int s, int nvalid, const float* meta, int K,
+                           int* idx, float* exc, hipStream_t st);
+void time_exceptions_restore(const TimeGrid& tg, float* e_win, int s, int nvalid, int K, const int* idx,
+                             const float* exc, hipStream_t st);
+
 int ae_latent_dim(const ae_net* net);
 int ae_input_dim(const ae_net* net);
 // bytes per patch of the latent store (latent codes only)

@@ -261,6 +261,9 @@ struct wv_ctx {
     long long TB = 0;            // 4^3 blocks per source
     int nwin = 0;
     int tlat_dim = 0;
+    int tK = 0;                  // exception vectors per window and source
+    int* texc_idx = nullptr;     // [nwin][S][tK] block indices, increasing
+    float* texc = nullptr;       // [nwin][S][tK][2048] their exact values
 
     // MAP layer: BiLaplacian prior and the Newton-CG work vectors
     double prior_alpha = 0.0;
@@ -460,6 +463,9 @@ void free_store(wv_ctx* c)
     dev_free(c->tlat);
     dev_free(c->tmeta);
     dev_free(c->twin);
+    dev_free(c->texc_idx);
+    dev_free(c->texc);
+    c->tK = 0;
     c->tbuf_w[0] = c->tbuf_w[1] = -1;
     c->tcur_w = -1;
     c->K = 0;
@@ -504,6 +510,8 @@ void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
 bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
 bool is_time(int mode) { return mode == WV_STORE_AE_TIME; }
 float* twin_buf(wv_ctx* c, int b) { return c->twin + (long long)b * TWIN * c->S * c->N; }
+int* texc_idx_slot(wv_ctx* c, int w, int s) { return c->texc_idx + ((long long)w * c->S + s) * c->tK; }
+float* texc_slot(wv_ctx* c, int w, int s) { return c->texc + ((long long)w * c->S + s) * c->tK * 2048; }
 TimeGrid ctx_time_grid(const wv_ctx* c) { return time_grid(c->g.nz, c->g.ny, c->g.nx, c->S); }
 uint16_t* tlat_slot(wv_ctx* c, int w) { return c->tlat + (long long)w * c->TB * c->S * c->tlat_dim; }
 float* tmeta_slot(wv_ctx* c, int w) { return c->tmeta + (long long)w * c->TB * c->S * 2; }
@@ -567,8 +575,12 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
             hipStream_t s1 = side_stream(c, 0);
             WV_HIP(hipEventRecord(c->ev_tfill[b], c->st));
             wait_event(s1, c->ev_tfill[b]);
+            const TimeGrid tg = ctx_time_grid(c);
             const int te = c->tm.begin(TM_ENCODE, s1);
-            ae_time_encode(c->ae, ctx_time_grid(c), buf, t + 1, tlat_slot(c, w), tmeta_slot(c, w), s1);
+            ae_time_encode(c->ae, tg, buf, t + 1, tlat_slot(c, w), tmeta_slot(c, w), s1);
+            for (int s = 0; s < c->S && c->tK > 0; ++s)
+                time_exceptions_store(tg, buf, s, t + 1, tmeta_slot(c, w) + (long long)s * c->TB * 2, c->tK,
+                                      texc_idx_slot(c, w, s), texc_slot(c, w, s), s1);
             c->tm.end(te, s1);
             WV_HIP(hipEventRecord(c->ev_tenc[b], s1));
         }
@@ -711,8 +723,11 @@ void time_issue(wv_ctx* c, int w, int b)
     WV_HIP(hipEventRecord(c->ev_tfree[b], c->st));
     wait_event(s1, c->ev_tfree[b]);
     const int nvalid = std::min(TWIN, c->T - 1 - w * TWIN);
+    const TimeGrid tg = ctx_time_grid(c);
     const int td = c->tm.begin(TM_DECODE, s1);
-    ae_time_decode(c->ae, ctx_time_grid(c), tlat_slot(c, w), tmeta_slot(c, w), nvalid, twin_buf(c, b), s1);
+    ae_time_decode(c->ae, tg, tlat_slot(c, w), tmeta_slot(c, w), nvalid, twin_buf(c, b), s1);
+    for (int s = 0; s < c->S && c->tK > 0; ++s)
+        time_exceptions_restore(tg, twin_buf(c, b), s, nvalid, c->tK, texc_idx_slot(c, w, s), texc_slot(c, w, s), s1);
     c->tm.end(td, s1);
     WV_HIP(hipEventRecord(c->ev_tready[b], s1));
     c->tbuf_w[b] = w;
@@ -1104,10 +1119,17 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
             c->tlat_dim = ae_latent_dim(ae);
             const long long rows = (long long)c->nwin * c->TB * c->S;
-            const long long bytes = rows * (c->tlat_dim * 2 + 8);
+            const int K = (int)std::min<long long>(c->exc_req, c->TB);
+            const long long kslots = (long long)c->nwin * c->S * K;
+            const long long bytes = rows * (c->tlat_dim * 2 + 8) + kslots * (4 + 2048 * 4);
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
             c->tlat = dev_alloc<uint16_t>(rows * c->tlat_dim);
             c->tmeta = dev_alloc<float>(rows * 2);
+            c->tK = K;
+            if (K > 0) {
+                c->texc_idx = dev_alloc<int>(kslots);
+                c->texc = dev_alloc<float>(kslots * 2048);
+            }
             c->twin = dev_alloc<float>((size_t)2 * TWIN * c->S * c->N);
             c->store_bytes = bytes;
         } else if (is_ae(mode)) {

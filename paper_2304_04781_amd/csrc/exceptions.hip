@@ -1,8 +1,9 @@
 // Exact storage of the largest-range patches alongside the autoencoder latents
 // (error bounding): per compressed state, select the K patches with the largest
-// e-field range r (resolved to bins 2^-7 wide in relative terms; within the bin
+// e-field range r (resolved to bins 2^-5 wide in relative terms; within the bin
 // that holds the K-th largest range, lower patch indices first), keep their e
-// values, and restore them after decompression.
+// values, and restore them after decompression. The time scheme does the same
+// per window and source with its e-only vectors (4^3 cells x 32 levels).
 
 #include "ae_internal.h"
 
@@ -50,12 +51,14 @@ __device__ int block_scan_incl(int v, int* ws)
 constexpr int BIN_SHIFT = EXC_BIN_SHIFT;
 constexpr int NBIN = EXC_NBIN;
 
-__device__ __forceinline__ unsigned bin_of(const float* meta, int p)
+// r of row p sits at meta[p * ms + 1]: ms = 8 for patches ((lo, r) of 4 fields, e
+// first), 2 for the e-only vectors of the time scheme
+__device__ __forceinline__ unsigned bin_of(const float* meta, int ms, int p)
 {
-    return __float_as_uint(meta[(long long)p * 8 + 1]) >> BIN_SHIFT;
+    return __float_as_uint(meta[(long long)p * ms + 1]) >> BIN_SHIFT;
 }
 
-__global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __restrict__ meta, int P, int K,
+__global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __restrict__ meta, int ms, int P, int K,
                                                              int* __restrict__ out)
 {
     constexpr int BPT = NBIN / SEL_THREADS;  // bins per thread, highest bins to thread 0
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __rest
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int p = c0 + q * SEL_THREADS + tid;
-            key[q] = p < P ? bin_of(meta, p) : 0xFFFFFFFFu;
+            key[q] = p < P ? bin_of(meta, ms, p) : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __rest
         for (int q = 0; q < KPT; ++q) {
             const int i = q * SEL_THREADS + tid;  // coalesced
             const int p = c0 + i;
-            skey[(i / KPT) * (KPT + 1) + i % KPT] = p < P ? bin_of(meta, p) : 0u;
+            skey[(i / KPT) * (KPT + 1) + i % KPT] = p < P ? bin_of(meta, ms, p) : 0u;
         }
         __syncthreads();
         const int r0 = tid * KPT;  // run of this thread within the chunk
@@ -187,6 +190,43 @@ __global__ void scatter_kernel(float* __restrict__ e, int ny, int nx, int Py, in
     e[(z * ny + y) * nx + x] = exc[(long long)k * 512 + l];
 }
 
+// time scheme: exc[k][t*64 + cell] = e of block idx[k] of source s at level t (the
+// last valid level for t >= nvalid), one work-group of 256 per vector, thread i
+// holding level i / 8 and cells 8 (i % 8) .. + 7 (the layout of the vectors)
+__global__ void time_gather_kernel(const float* __restrict__ e_win, int S, int s, int ny, int nx, long long N,
+                                   int By, int Bx, long long B, int nvalid, const int* __restrict__ idx,
+                                   float* __restrict__ exc)
+{
+    const long long b = idx[blockIdx.x];
+    if (b < 0 || b >= B) return;
+    const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+    const int t = threadIdx.x >> 3, q = threadIdx.x & 7;
+    const int tl = t < nvalid ? t : nvalid - 1;
+    const int lz = q >> 1, ly0 = (q & 1) * 2;
+    const float* src =
+        e_win + ((long long)tl * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly0) * nx + bx * 4;
+    float* dst = exc + (long long)blockIdx.x * 2048 + t * 64 + q * 8;
+    *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
+    *reinterpret_cast<float4*>(dst + 4) = *reinterpret_cast<const float4*>(src + nx);
+}
+
+// the inverse for levels t < nvalid: the exact values over the decoded window
+__global__ void time_scatter_kernel(float* __restrict__ e_win, int S, int s, int ny, int nx, long long N, int By,
+                                    int Bx, long long B, int nvalid, const int* __restrict__ idx,
+                                    const float* __restrict__ exc)
+{
+    const long long b = idx[blockIdx.x];
+    if (b < 0 || b >= B) return;
+    const int t = threadIdx.x >> 3, q = threadIdx.x & 7;
+    if (t >= nvalid) return;
+    const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+    const int lz = q >> 1, ly0 = (q & 1) * 2;
+    float* dst = e_win + ((long long)t * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly0) * nx + bx * 4;
+    const float* src = exc + (long long)blockIdx.x * 2048 + t * 64 + q * 8;
+    *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(src);
+    *reinterpret_cast<float4*>(dst + nx) = *reinterpret_cast<const float4*>(src + 4);
+}
+
 // rng[b] = lower bound of patch bm b in the increasing list idx [K]
 __global__ void ranges_kernel(const int* __restrict__ idx, int K, int bm, int nb, int* __restrict__ rng)
 {
@@ -209,7 +249,7 @@ void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, 
     if (K <= 0) return;
     WV_REQUIRE(K <= pg.P, WV_EINVAL, "more exception patches than patches");
     WV_REQUIRE(pg.P < (1LL << 31), WV_EINVAL, "too many patches for the exception selector");
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, (int)pg.P, K, idx);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, 8, (int)pg.P, K, idx);
     WV_HIP(hipGetLastError());
 }
 
@@ -241,6 +281,29 @@ void exceptions_restore(const PatchGrid& pg, float* e, int K, const int* idx, co
     if (K <= 0) return;
     hipLaunchKernelGGL(scatter_kernel, dim3(K), dim3(512), 0, st, e, pg.ny, pg.nx, pg.ny / 8, pg.nx / 8, (int)pg.P,
                        idx, exc);
+    WV_HIP(hipGetLastError());
+}
+
+void time_exceptions_store(const TimeGrid& tg, const float* e_win, int s, int nvalid, const float* meta, int K,
+                           int* idx, float* exc, hipStream_t st)
+{
+    if (K <= 0) return;
+    WV_REQUIRE(K <= tg.B, WV_EINVAL, "more exception vectors than blocks");
+    WV_REQUIRE(tg.B < (1LL << 31), WV_EINVAL, "too many blocks for the exception selector");
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, 2, (int)tg.B, K, idx);
+    const long long N = (long long)tg.nz * tg.ny * tg.nx;
+    hipLaunchKernelGGL(time_gather_kernel, dim3(K), dim3(256), 0, st, e_win, tg.S, s, tg.ny, tg.nx, N, tg.ny / 4,
+                       tg.nx / 4, tg.B, nvalid, idx, exc);
+    WV_HIP(hipGetLastError());
+}
+
+void time_exceptions_restore(const TimeGrid& tg, float* e_win, int s, int nvalid, int K, const int* idx,
+                             const float* exc, hipStream_t st)
+{
+    if (K <= 0) return;
+    const long long N = (long long)tg.nz * tg.ny * tg.nx;
+    hipLaunchKernelGGL(time_scatter_kernel, dim3(K), dim3(256), 0, st, e_win, tg.S, s, tg.ny, tg.nx, N, tg.ny / 4,
+                       tg.nx / 4, tg.B, nvalid, idx, exc);
     WV_HIP(hipGetLastError());
 }
 

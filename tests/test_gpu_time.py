@@ -208,6 +208,14 @@ def test_time_compressed_gradient_with_trained_network():
           "store bytes", t.storage_bytes(), "vs full", plain.storage_bytes(), flush=True)
     assert J == J0
     assert err < 0.2 and cos > 0.98 and herr < 0.2
+    # exception vectors: the 1 % largest-range vectors of every window kept exactly
+    k = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(k.ctx, 17)                       # 1 % of the 1728 blocks
+    k.set_storage(L.STORE_AE_TIME, ae=net)
+    _, gk = k.gradient(p.c_start, p.wavelet, d, sigma)
+    err_k = rel(gk.cpu().numpy(), g0n)
+    print("with 17 exact vectors per window: grad rel err", err_k, flush=True)
+    assert err_k < err
     raw = Net(W.ae_init(seed=4))
     L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
     u = WaveSolver.for_problem(p)
@@ -250,3 +258,31 @@ def test_time_store_window_edges(nt):
         for lvl in range(nvalid):
             assert torch.equal(t.load_e(32 * w + 1 + lvl), dec[lvl]), (w, lvl)
     assert torch.isfinite(t.hessvec(p.c_start, p.c_start * 0.01)).all()
+
+
+@pytest.mark.parametrize("nsrc", [1, 2])
+def test_time_all_vectors_exact_reproduce_full_storage(nsrc):
+    """Exception vectors at K = B (every vector of every window kept exactly): each
+    level the reverse solves read is the exact e, so gradient and Gauss-Newton Hv
+    equal the full-storage ones bit for bit; the store counts the exact values."""
+    p = time_problem(75, nsrc=nsrc)
+    print("case sources", nsrc, flush=True)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    net = Net(W.ae_init(seed=4))
+    B = 8 * 8 * 10
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    J0, g0 = full.gradient(p.c_start, p.wavelet, d, sigma)
+    dc = p.c_start * 0.01
+    H0 = full.hessvec(p.c_start, dc)
+    e_all = full.forward_e(p.c_start, p.wavelet, list(range(1, 75)))
+    t = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(t.ctx, B)
+    t.set_storage(L.STORE_AE_TIME, ae=net)
+    assert t.storage_bytes() == 3 * nsrc * (B * (32 * 2 + 8) + B * (4 + 2048 * 4))
+    J, g = t.gradient(p.c_start, p.wavelet, d, sigma)
+    for n in (1, 17, 32, 33, 64, 65, 70, 74):
+        assert torch.equal(t.load_e(n), e_all[n - 1]), n
+    assert J == J0 and torch.equal(g, g0)
+    assert torch.equal(t.hessvec(p.c_start, dc), H0)
