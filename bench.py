@@ -431,7 +431,10 @@ def time_pass(args):
     torch.cuda.empty_cache()
     log(f"time-network training {info}")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    B = (p.nz // 4) * (p.ny // 4) * (p.nx // 4)
+    K_exc = int(round(args.exceptions * B))
     tm = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(tm.ctx, K_exc)
     tm.set_storage(L.STORE_AE_TIME, ae=net)
     tm.gradient(c0, wav, d_obs, sigma)
     torch.cuda.synchronize()
@@ -465,8 +468,8 @@ def time_pass(args):
         torch.cuda.synchronize()
         hv[name] = (ev0.elapsed_time(ev1) / 1e3, H.double())
     ht, hc = hv["time"][1], hv["checkpoint"][1]
-    out = {"workload": f"{p.name}: time compression (e on 4^3 blocks x {L.TWIN} levels, bf16 latents) "
-                       f"vs revolve checkpointing ({args.checkpoints} slots)",
+    out = {"workload": f"{p.name}: time compression (e on 4^3 blocks x {L.TWIN} levels, bf16 latents, "
+                       f"{K_exc} exact vectors per window) vs revolve checkpointing ({args.checkpoints} slots)",
            "training": info,
            "gradient_s": {"time": round(float(np.median(times)), 4), "runs": [round(x, 4) for x in times],
                           "checkpoint": round(t_ck, 4)},
