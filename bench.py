@@ -60,6 +60,8 @@ def parse():
                     help="a short MAP inversion at 256^3 x 2000 (prior-preconditioned Gauss-Newton CG) with the "
                          "AE store and with checkpointing: wall time, Hv count, cost and model error")
     ap.add_argument("--inv-iters", type=int, default=5)
+    ap.add_argument("--inv-store", choices=["space", "time"], default="space",
+                    help="compressed store of the inversion: space patches (bf16) or time windows")
     ap.add_argument("--time", action="store_true",
                     help="time-compression scheme at 256^3 x 2000: gradient and Gauss-Newton Hv against "
                          "checkpointing (network trained on every 4th window of the start model's solve)")
@@ -353,10 +355,20 @@ def inversion_pass(args):
     d_obs = torch.tensor((clean_h + sigma * p.noise).astype(np.float32), device=dev)
     del clean
     net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
-    ncap = (T - 1) // args.snapshot_every
     t0 = time.perf_counter()
-    info = C.train_from_forward(s, net, c0, wav, every=args.snapshot_every, epochs=args.epochs, batch=args.batch,
-                                perms=W.shuffles(ncap * P, args.epochs, seed=5))
+    if args.inv_store == "space":
+        ncap = (T - 1) // args.snapshot_every
+        info = C.train_from_forward(s, net, c0, wav, every=args.snapshot_every, epochs=args.epochs,
+                                    batch=args.batch, perms=W.shuffles(ncap * P, args.epochs, seed=5))
+    else:
+        nwin = (T - 1 + L.TWIN - 1) // L.TWIN
+        y, meta, _ = C.time_window_samples(s, net, c0, wav, list(range(0, nwin, 4)))
+        info = C.train_samples(net, y, None, args.epochs, args.batch,
+                               perms=W.shuffles(int(y.shape[0]), args.epochs, seed=5))
+        del y, meta
+        torch.cuda.empty_cache()
+        P = (p.nz // 4) * (p.ny // 4) * (p.nx // 4)    # exception vectors count 4^3 blocks
+        K_exc = int(round(args.exceptions * P))
     t_train = time.perf_counter() - t0
     log(f"training {info}")
     alpha, theta = 2e-6, (4 * p.dx * p.dx,) * 3
@@ -368,7 +380,7 @@ def inversion_pass(args):
         sol = WaveSolver.for_problem(p)
         if name == "ae":
             L.wv_set_ae_exceptions(sol.ctx, K_exc)
-            sol.set_storage(L.STORE_AE_BF16, ae=net)
+            sol.set_storage(L.STORE_AE_BF16 if args.inv_store == "space" else L.STORE_AE_TIME, ae=net)
         else:
             sol.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
         sol.set_prior(alpha, theta, c0)
@@ -389,8 +401,10 @@ def inversion_pass(args):
         log(f"{name}: {res[name]}")
         sol.close()
     ca, cc = models["ae"].double(), models["checkpoint"].double()
+    store = (f"AE space store (bf16, {K_exc} exact patches per state)" if args.inv_store == "space" else
+             f"AE time store (bf16, {K_exc} exact vectors per window)")
     out = {"workload": f"{p.name}: MAP inversion, {args.inv_iters} prior-preconditioned Gauss-Newton CG iterations, "
-                       f"AE store (bf16, {K_exc} exact patches per state) vs revolve checkpointing",
+                       f"{store} vs revolve checkpointing",
            "prior": {"alpha": alpha, "theta_m2": theta[0], "mean": "c_start"},
            "train_s": round(t_train, 2), "results": res,
            "speedup_vs_checkpoint": round(res["checkpoint"]["wall_s"] / res["ae"]["wall_s"], 4),
