@@ -154,3 +154,28 @@ def test_prior_sample_matches_oracle(which):
     print("CG iterations", it, "relative residual", rr, flush=True)
     assert rr <= 1e-6 and it < 2000
     assert rel(c.cpu().numpy() - p.c_start, ref - p.c_start) < 1e-4
+
+
+@pytest.mark.parametrize("gauss_newton", [True, False])
+def test_autograd_map_objective(gauss_newton):
+    """The MAP objective through torch.autograd (misfit + BiLaplacian prior): value,
+    gradient and the double-backward Hessian action against the oracle's (Gauss-
+    Newton or full-Newton misfit Hessian plus the exact prior Hessian)."""
+    from paper_2304_04781_amd.autograd import BiLaplacianPrior, WaveMisfit
+    p, sol, d, sigma = newton_case()
+    cost_grad, hv = oi.wave_map_problem(sol, p.wavelet, p.src, p.rec, d, sigma, p.c_start, ALPHA, THETA,
+                                        gauss_newton=gauss_newton, src_w=p.src_w)
+    cm = f32(p.c_start * (1.0 + 0.01 * W.direction_grf(p.c_start.shape, 3.0, 4)))
+    J_o, g_o, st = cost_grad(cm)
+    v = f32(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 3.0, 8))
+    H_o = hv(st, v)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_FULL)
+    s.set_prior(ALPHA, THETA, p.c_start)
+    c = torch.tensor(cm, dtype=torch.float32, device="cuda", requires_grad=True)
+    J = WaveMisfit.apply(c, s, s._f32(p.wavelet), s._f32(d), sigma, gauss_newton) + BiLaplacianPrior.apply(c, s)
+    assert abs(float(J) - J_o) < 1e-5 * J_o
+    (g,) = torch.autograd.grad(J, c, create_graph=True)
+    assert rel(g.detach().cpu().numpy(), g_o) < 1e-4
+    (Hv,) = torch.autograd.grad(g, c, grad_outputs=torch.tensor(v, dtype=torch.float32, device="cuda"))
+    assert rel(Hv.cpu().numpy(), H_o) < 1e-4
