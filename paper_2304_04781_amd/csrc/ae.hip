@@ -88,6 +88,15 @@ struct EpiHasTile<E, std::void_t<decltype(E::kTile)>> {
     static constexpr bool value = E::kTile;
 };
 
+// per-thread loader state of one work-group's tile rows, set before the k loop:
+// LoadK keeps the source address of each of its chunks (null: past the last row),
+// so a stage only adds its k offset; LoadT keeps the first row
+template <int BR>
+struct LoadState {
+    const uint16_t* row[Frag<BR>::NC];
+    int r0;
+};
+
 // source stored [rows][ld] with k contiguous; optional row gather
 struct LoadK {
     const uint16_t* p;
@@ -96,18 +105,25 @@ struct LoadK {
     int nrows;        // logical rows
     int k_total;
     template <int BR>
-    __device__ __forceinline__ void fetch(int r0, int k0, int tid, Frag<BR>& f) const
+    __device__ __forceinline__ void prepare(int r0, int tid, LoadState<BR>& s) const
     {
 #pragma unroll
         for (int i = 0; i < Frag<BR>::NC; ++i) {
             const int c = tid + 256 * i;
             const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-            const int gr = r0 + r, gk = k0 + kc;
+            const int gr = r0 + r;
+            s.row[i] = (c < BR * (BK / 8) && gr < nrows) ? p + (long long)(rows ? rows[gr] : gr) * ld + kc : nullptr;
+        }
+        s.r0 = r0;
+    }
+    template <int BR>
+    __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int tid, Frag<BR>& f) const
+    {
+#pragma unroll
+        for (int i = 0; i < Frag<BR>::NC; ++i) {
+            const int kc = ((tid + 256 * i) % (BK / 8)) * 8;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (c < BR * (BK / 8) && gr < nrows && gk < k_total) {
-                const long long src = rows ? rows[gr] : gr;
-                v = *reinterpret_cast<const uint4*>(p + src * ld + gk);
-            }
+            if (s.row[i] && k0 + kc < k_total) v = *reinterpret_cast<const uint4*>(s.row[i] + k0);
             f.v[i] = v;
         }
     }
@@ -130,8 +146,14 @@ struct LoadT {
     int nrows;
     int k_total;
     template <int BR>
-    __device__ __forceinline__ void fetch(int r0, int k0, int tid, Frag<BR>& f) const
+    __device__ __forceinline__ void prepare(int r0, int, LoadState<BR>& s) const
     {
+        s.r0 = r0;
+    }
+    template <int BR>
+    __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int tid, Frag<BR>& f) const
+    {
+        const int r0 = s.r0;
 #pragma unroll
         for (int i = 0; i < Frag<BR>::NC; ++i) {
             const int c = tid + 256 * i;
@@ -196,9 +218,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     Frag<BM> fa;
     Frag<BN> fb;
+    LoadState<BM> sla;
+    LoadState<BN> slb;
+    la.template prepare<BM>(m0, tid, sla);
+    lb.template prepare<BN>(n0, tid, slb);
     if (kb < ke) {
-        la.template fetch<BM>(m0, kb, tid, fa);
-        lb.template fetch<BN>(n0, kb, tid, fb);
+        la.template fetch<BM>(sla, kb, tid, fa);
+        lb.template fetch<BN>(slb, kb, tid, fb);
         la.template store<BM>(fa, tid, sA[0]);
         lb.template store<BN>(fb, tid, sB[0]);
     }
@@ -207,8 +233,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     for (int k0 = kb; k0 < ke; k0 += BK) {
         const bool more = k0 + BK < ke;
         if (more) {
-            la.template fetch<BM>(m0, k0 + BK, tid, fa);
-            lb.template fetch<BN>(n0, k0 + BK, tid, fb);
+            la.template fetch<BM>(sla, k0 + BK, tid, fa);
+            lb.template fetch<BN>(slb, k0 + BK, tid, fb);
         }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 32) {
