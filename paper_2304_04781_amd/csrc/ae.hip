@@ -205,7 +205,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm0 = (wave / (BN / WN)) * WM, wn0 = (wave % (BN / WN)) * WN;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    // tiles in a 1D grid, column tiles fastest so the row tile of A is reused from L2 by
+    // the work-groups that follow; with a multiple of 8 tiles each XCD (work-group id
+    // mod 8) takes a contiguous run of tiles, so that reuse stays within one L2
+    const int ntn = (N + BN - 1) / BN;
+    const int ntiles = ntn * ((M + BM - 1) / BM);
+    int bid = blockIdx.x;
+    if (ntiles % 8 == 0) bid = (bid % 8) * (ntiles / 8) + bid / 8;
+    const int m0 = (bid / ntn) * BM, n0 = (bid % ntn) * BN;
     const int kb = blockIdx.z * k_per_split;
     const int ke = min(K, kb + k_per_split);
 
@@ -356,7 +363,7 @@ void gemm(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipSt
 {
     WV_REQUIRE(K % 32 == 0, WV_EINVAL, "GEMM depth must be a multiple of 32");
     const int kps = (((K + BK - 1) / BK + splits - 1) / splits) * BK;
-    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+    dim3 grid(((M + BM - 1) / BM) * ((N + BN - 1) / BN), 1, splits);
     hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, LA, LB, EPI>), grid, dim3(256), 0, st, M, N, K, kps, la, lb, epi);
     WV_HIP(hipGetLastError());
 }
