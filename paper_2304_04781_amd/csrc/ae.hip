@@ -389,28 +389,32 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
         e_win[((long long)t * S + s) * N + ((long long)(bz * 4 + lz) * ny + by * 4 + ly) * nx + bx * 4 + lx] =
             lo + rr * yv;
     }
-    // The tile's rows are consecutive vectors, i.e. blocks along x. Thread i takes
-    // lx = i % 4 and the rows i / 4 + 64 j, resolves each row's block and (lo, r)
-    // once, then walks the tile's columns: at every store the 64 lanes of a wave
-    // cover 16 blocks x 4 cells, one contiguous run of x (cols is a multiple of 4).
+    // The tile's rows are consecutive vectors, i.e. blocks along x. Thread i takes row
+    // i % 128 and every other group of 4 columns from i / 128 on: 4 columns are the
+    // 4 x-cells of one (t, lz, ly) row of the block, so each thread moves float4s
+    // (one LDS read, one store), and a wave's store covers 64 consecutive blocks
+    // (a contiguous run of x). The row's block and (lo, r) are resolved once.
     __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
     {
-        const int lx = threadIdx.x & 3;
-        for (int rr = threadIdx.x >> 2; rr < rows; rr += 64) {
-            const long long row = (long long)m0 + rr;
-            const int s = (int)(row / B);
-            const long long b = row % B;
-            const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
-            const float lo = meta[row * 2], rg = meta[row * 2 + 1];
-            float* base = e_win + (long long)s * N + ((long long)bz * 4 * ny + by * 4) * nx + bx * 4 + lx;
-            const float* crow = C + rr * ldc + lx;
-            for (int cq = 0; cq < cols / 4; ++cq) {
-                const int c = n0 + cq * 4 + lx;
-                const int t = c >> 6;
-                if (t >= nvalid) break;  // columns ascend, so do the levels
-                const int cell = c & 63, lz = cell >> 4, ly = (cell >> 2) & 3;
-                base[(long long)t * S * N + ((long long)lz * ny + ly) * nx] = lo + rg * (crow[cq * 4] + bias[c]);
-            }
+        const int rr = threadIdx.x & 127;
+        if (rr >= rows) return;
+        const long long row = (long long)m0 + rr;
+        const int s = (int)(row / B);
+        const long long b = row % B;
+        const int bx = (int)(b % Bx), by = (int)((b / Bx) % By), bz = (int)(b / ((long long)Bx * By));
+        const float lo = meta[row * 2], rg = meta[row * 2 + 1];
+        float* base = e_win + (long long)s * N + ((long long)bz * 4 * ny + by * 4) * nx + bx * 4;
+        const float* crow = C + rr * ldc;
+        for (int cq = threadIdx.x >> 7; cq < cols / 4; cq += 2) {
+            const int c = n0 + cq * 4;
+            const int t = c >> 6;
+            if (t >= nvalid) break;  // columns ascend, so do the levels
+            const int cell = c & 63, lz = cell >> 4, ly = (cell >> 2) & 3;
+            const float4 v = *reinterpret_cast<const float4*>(crow + cq * 4);
+            const float4 bb = *reinterpret_cast<const float4*>(bias + c);
+            *reinterpret_cast<float4*>(base + (long long)t * S * N + ((long long)lz * ny + ly) * nx) =
+                make_float4(lo + rg * (v.x + bb.x), lo + rg * (v.y + bb.y), lo + rg * (v.z + bb.z),
+                            lo + rg * (v.w + bb.w));
         }
     }
 };
