@@ -317,6 +317,7 @@ struct EpiBF16 {  // bf16(v + bias), optional fp32 copy
     }
 };
 struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
+    static constexpr bool kTile = true;
     uint16_t* out;
     long long ld;
     const float* bias;
@@ -326,6 +327,31 @@ struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
         const float a = v + bias[c];
         if (pre) pre[(long long)r * ld + c] = a;
         out[(long long)r * ld + c] = f2bf(gelu(a));
+    }
+    // 8 consecutive columns per thread (cols is a multiple of 8): one 16-byte store of
+    // bf16 activations, two float4 stores of the pre-activation; 16 threads write one
+    // 128-column row segment in 256 contiguous bytes
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    {
+        const int nq = cols / 8;
+        for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
+            const int rr = idx / nq, q = idx % nq;
+            const int c = n0 + q * 8;
+            const float4 v0 = *reinterpret_cast<const float4*>(C + rr * ldc + q * 8);
+            const float4 v1 = *reinterpret_cast<const float4*>(C + rr * ldc + q * 8 + 4);
+            const float4 b0 = *reinterpret_cast<const float4*>(bias + c);
+            const float4 b1 = *reinterpret_cast<const float4*>(bias + c + 4);
+            const float4 a0 = make_float4(v0.x + b0.x, v0.y + b0.y, v0.z + b0.z, v0.w + b0.w);
+            const float4 a1 = make_float4(v1.x + b1.x, v1.y + b1.y, v1.z + b1.z, v1.w + b1.w);
+            const long long o = (long long)(m0 + rr) * ld + c;
+            if (pre) {
+                *reinterpret_cast<float4*>(pre + o) = a0;
+                *reinterpret_cast<float4*>(pre + o + 4) = a1;
+            }
+            *reinterpret_cast<uint4*>(out + o) =
+                make_uint4(f2bf2(gelu(a0.x), gelu(a0.y)), f2bf2(gelu(a0.z), gelu(a0.w)),
+                           f2bf2(gelu(a1.x), gelu(a1.y)), f2bf2(gelu(a1.z), gelu(a1.w)));
+        }
     }
 };
 struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
