@@ -296,12 +296,36 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
 
 // ---- epilogues ----------------------------------------------------------------------
 struct EpiF32 {  // out[z][row][col] = v (+ bias[col])
+    static constexpr bool kTile = true;
     float* out;
     long long ld, zstride;
     const float* bias;
     __device__ __forceinline__ void operator()(int r, int c, float v, int z) const
     {
         out[z * zstride + (long long)r * ld + c] = v + (bias ? bias[c] : 0.f);
+    }
+    // 4 consecutive columns per thread, one float4 store (cols and ld are multiples of 4)
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    {
+        const int nq = cols / 4;
+        float* o = out + blockIdx.z * zstride;
+        for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
+            const int rr = idx / nq, q = idx % nq;
+            const int c = n0 + q * 4;
+            float4 v = *reinterpret_cast<const float4*>(C + rr * ldc + q * 4);
+            if (bias) {
+                v.x += bias[c];
+                v.y += bias[c + 1];
+                v.z += bias[c + 2];
+                v.w += bias[c + 3];
+            } else {
+                v.x += 0.f;
+                v.y += 0.f;
+                v.z += 0.f;
+                v.w += 0.f;
+            }
+            *reinterpret_cast<float4*>(o + (long long)(m0 + rr) * ld + c) = v;
+        }
     }
 };
 struct EpiBF16 {  // bf16(v + bias), optional fp32 copy
@@ -355,6 +379,7 @@ struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
     }
 };
 struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
+    static constexpr bool kTile = true;
     uint16_t* out;
     float* f32out;
     const float* pre;
@@ -365,6 +390,28 @@ struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
         const float d = v * gelu_prime(pre[o]);
         out[o] = f2bf(d);
         f32out[o] = d;
+    }
+    // 8 consecutive columns per thread: vector loads of pre, one 16-byte bf16 store,
+    // two float4 stores (cols and ld are multiples of 8)
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    {
+        const int nq = cols / 8;
+        for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
+            const int rr = idx / nq, q = idx % nq;
+            const long long o = (long long)(m0 + rr) * ld + n0 + q * 8;
+            const float4 v0 = *reinterpret_cast<const float4*>(C + rr * ldc + q * 8);
+            const float4 v1 = *reinterpret_cast<const float4*>(C + rr * ldc + q * 8 + 4);
+            const float4 p0 = *reinterpret_cast<const float4*>(pre + o);
+            const float4 p1 = *reinterpret_cast<const float4*>(pre + o + 4);
+            const float4 d0 = make_float4(v0.x * gelu_prime(p0.x), v0.y * gelu_prime(p0.y), v0.z * gelu_prime(p0.z),
+                                          v0.w * gelu_prime(p0.w));
+            const float4 d1 = make_float4(v1.x * gelu_prime(p1.x), v1.y * gelu_prime(p1.y), v1.z * gelu_prime(p1.z),
+                                          v1.w * gelu_prime(p1.w));
+            *reinterpret_cast<float4*>(f32out + o) = d0;
+            *reinterpret_cast<float4*>(f32out + o + 4) = d1;
+            *reinterpret_cast<uint4*>(out + o) = make_uint4(f2bf2(d0.x, d0.y), f2bf2(d0.z, d0.w), f2bf2(d1.x, d1.y),
+                                                            f2bf2(d1.z, d1.w));
+        }
     }
 };
 struct EpiDenorm {  // decoder output of field f -> lo + r (v + b) scattered into the state
