@@ -356,7 +356,9 @@ StepArgs base_args(const wv_ctx* c)
 
 // one forward step n: state in -> out; traces (nullptr: not recorded); mm: per-patch
 // (min, max) partials of the new state (nullptr: not computed)
-void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, float* mm = nullptr)
+// e_extra: the new e is also written there ([S][N]), the time-compression window slot
+void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, float* mm = nullptr,
+              float* e_extra = nullptr)
 {
     StepArgs a = base_args(c);
     a.in = in;
@@ -365,6 +367,7 @@ void fwd_step(wv_ctx* c, const float* in, float* out, int n, float* traces, floa
     a.tidx = n;
     a.traces = traces;
     a.mm_out = mm;
+    a.e_extra = e_extra;
     if (!traces) a.nrec = 0;
     const int t = c->tm.begin(TM_FWD, c->st);
     launch_step(MODE_FWD, c->has_y, a, c->S, c->st);
@@ -564,13 +567,12 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
             WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
     } else if (is_time(c->mode)) {
-        // e^n joins its window in buffer w % 2; a full window (or the last, short one)
-        // is compressed on `side` while the steps go on into the other buffer
+        // the forward step wrote e^n into its window (buffer w % 2, see forward_sweep);
+        // a full window (or the last, short one) is compressed on `side` while the
+        // steps go on into the other buffer
+        (void)state;
         const int t = (n - 1) % TWIN, w = (n - 1) / TWIN, b = w & 1;
         float* buf = twin_buf(c, b);
-        if (t == 0 && w >= 2) wait_event(c->st, c->ev_tenc[b]);  // window w - 2 has been read
-        for (int s = 0; s < c->S; ++s)
-            launch_copy(buf + ((long long)t * c->S + s) * c->N, state + s * 4 * c->N, c->N, c->st);
         if (t == TWIN - 1 || n == c->T - 1) {
             hipStream_t s1 = side_stream(c, 0);
             WV_HIP(hipEventRecord(c->ev_tfill[b], c->st));
@@ -823,7 +825,15 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
             out = (snap && (*snap)[j] > 0) ? c->slot_ptr((*snap)[j]) : other_work(c, cur);
         }
         float* mm = (ae && store) ? c->mmpart + (j % 3) * mm_stride : nullptr;
-        fwd_step(c, cur, out, n, traces, mm);
+        // time compression: the step writes e^j straight into its window slot; the
+        // buffer held window w - 2, whose compression must have read it
+        float* ew = nullptr;
+        if (is_time(c->mode) && store) {
+            const int t = (j - 1) % TWIN, w = (j - 1) / TWIN, b = w & 1;
+            if (t == 0 && w >= 2) wait_event(c->st, c->ev_tenc[b]);
+            ew = twin_buf(c, b) + (long long)t * c->S * c->N;
+        }
+        fwd_step(c, cur, out, n, traces, mm, ew);
         if (store) {
             if (ae)
                 store_state_async(c, j, out, mm);

@@ -94,8 +94,9 @@ __device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, u
 #endif
 
 // MM: also write the per-patch (min, max) partials of the new state (forward only);
-// ACC: the adjoint's gradient accumulation phase
-template <int BX, int BY, int MODE, bool HAS_Y, bool MM, int ACC = ACC_EACH>
+// ACC: the adjoint's gradient accumulation phase; EX: also write the new e to
+// a.e_extra (forward only: the time-compression window slot of this level)
+template <int BX, int BY, int MODE, bool HAS_Y, bool MM, int ACC = ACC_EACH, bool EX = false>
 __global__ void __launch_bounds__(BX* BY)
     __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_INC || MODE == MODE_FWD ? WV_WAVES_OTHER
                                                                                                   : WV_WAVES_ADJ)))
@@ -139,6 +140,7 @@ __global__ void __launch_bounds__(BX* BY)
     float* __restrict__ outVz = outA + N;
     float* __restrict__ outVy = outA + 2 * N;
     float* __restrict__ outVx = outA + 3 * N;
+    float* __restrict__ outE = EX ? a.e_extra + s * N : nullptr;
     const float* __restrict__ mm = a.m;
     const float* __restrict__ en = (MODE == MODE_INC) ? a.en + s * a.enstride : nullptr;
     constexpr bool ADJ = MODE == MODE_ADJ || MODE == MODE_ADJQ || MODE == MODE_ADJD;
@@ -432,11 +434,13 @@ __global__ void __launch_bounds__(BX* BY)
             st_plane_nt(Vz_cur, outVz + lk, pb4, o_c);
             if (HAS_Y) st_plane_nt(Vy_new, outVy + lk, pb4, o_c);
             st_plane_nt(Vx_new, outVx + lk, pb4, o_c);
+            if (EX) st_plane_nt(A_new, outE + lk, pb4, o_c);
 #else
             st_plane(A_new, outA + lk, pb4, o_c);
             st_plane(Vz_cur, outVz + lk, pb4, o_c);
             if (HAS_Y) st_plane(Vy_new, outVy + lk, pb4, o_c);
             st_plane(Vx_new, outVx + lk, pb4, o_c);
+            if (EX) st_plane(A_new, outE + lk, pb4, o_c);
 #endif
             if (ADJ) {
                 if (ACC == ACC_EACH || ACC == ACC_LAST) {
@@ -540,12 +544,16 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
         a.chunks_z = a.chunks_adj;
     }
     if (mode != MODE_FWD || !HAS_Y) a.mm_out = nullptr;
+    if (mode != MODE_FWD) a.e_extra = nullptr;
     dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
     dim3 block(BX * BY);
     switch (mode) {
     case MODE_FWD:
         if (HAS_Y && a.mm_out)
             hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, HAS_Y>), grid, block, 0, st, a);
+        else if (a.e_extra)
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, false, ACC_EACH, true>), grid, block, 0,
+                               st, a);
         else
             hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_FWD, HAS_Y, false>), grid, block, 0, st, a);
         break;
