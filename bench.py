@@ -56,6 +56,8 @@ def parse():
                     help="training on prior draws (Algorithm 1) against in-run snapshots at 256^3: "
                          "compression and gradient errors on the start, true, midway and a held-out model")
     ap.add_argument("--draws", type=int, default=4)
+    ap.add_argument("--no-time", action="store_true",
+                    help="skip the time-compression leg of the default run")
     ap.add_argument("--inversion", action="store_true",
                     help="a short MAP inversion at 256^3 x 2000 (prior-preconditioned Gauss-Newton CG) with the "
                          "AE store and with checkpointing: wall time, Hv count, cost and model error")
@@ -653,8 +655,16 @@ def main():
     hessvec["full_newton_vs_gn_rel_diff"] = round(float(torch.linalg.norm(Hf.double() - h_ae) /
                                                         torch.linalg.norm(h_ae)), 5)
     hessvec["store_with_incremental_GB"] = round(ae_solver.storage_bytes() / 1e9, 3)
-    del h_ae, h_ck, hv, dc, Hf
+    del h_ae, hv, Hf
     log(f"GN Hv: {hessvec}")
+
+    # ---- the time-compression scheme on the same workload (e on 4^3 blocks x 32 levels,
+    # 1 % exact vectors per window), against the same checkpointed gradient and Hv
+    time_scheme = None
+    if not args.no_time:
+        time_scheme = time_leg(args, p, solver, c0, wav, d_obs, sigma, g_ck, h_ck, dc, t_ck, hessvec["checkpoint_s"])
+        log(f"time compression: {time_scheme}")
+    del h_ck, dc
 
     # ---- one Newton-CG iteration for the MAP point (BiLaplacian prior): a gradient, newton_cg Hv
     # products in CG and the accepted trial's gradient; the AE store is written once per iterate
@@ -749,6 +759,7 @@ def main():
         "gradient_runs_s": {"ae": [round(x, 4) for x in times], "ae_min": round(min(times), 4),
                             "checkpoint": [round(x, 4) for x in times_ck], "checkpoint_min": round(min(times_ck), 4)},
         "gn_hessvec": hessvec,
+        "time_compression": time_scheme,
         "newton_iteration": newton,
         "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
         "grad_cos_vs_checkpoint_fp32": round(cos, 6),
@@ -771,6 +782,58 @@ def main():
         "setup_s": round(time.perf_counter() - t_setup, 1),
     }
     print(json.dumps(out), flush=True)
+
+
+def time_leg(args, p, solver, c0, wav, d_obs, sigma, g_ck, h_ck, dc, t_ck, hv_ck_s):
+    """Time-compression scheme: network trained on every 4th window of the forward solve at
+    c0 (the solver's own states), then timed gradients and one Gauss-Newton Hv."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd import compressor as C
+    from paper_2304_04781_amd.solver import WaveSolver
+    T = p.nt
+    nwin = (T - 1 + L.TWIN - 1) // L.TWIN
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    y, meta, _ = C.time_window_samples(solver, net, c0, wav, list(range(0, nwin, 4)))
+    info = C.train_samples(net, y, None, args.epochs, args.batch, perms=W.shuffles(int(y.shape[0]), args.epochs, seed=5))
+    del y, meta
+    torch.cuda.empty_cache()
+    B = (p.nz // 4) * (p.ny // 4) * (p.nx // 4)
+    K = int(round(args.exceptions * B))
+    tm = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(tm.ctx, K)
+    tm.set_storage(L.STORE_AE_TIME, ae=net)
+    tm.gradient(c0, wav, d_obs, sigma)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        ev0.record()
+        _, g = tm.gradient(c0, wav, d_obs, sigma)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / 1e3)
+    gt, gc = g.double(), g_ck.double()
+    torch.cuda.synchronize()
+    ev0.record()
+    H = tm.hessvec(c0, dc)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_hv = ev0.elapsed_time(ev1) / 1e3
+    ht, hc = H.double(), h_ck
+    t_g = min(times)
+    out = {"exact_vectors_per_window": K, "train_s": info["train_s"],
+           "gradient_s": round(t_g, 4), "gradient_runs_s": [round(x, 4) for x in times],
+           "gradients_per_hour": round(3600.0 / t_g, 1), "speedup_vs_checkpoint": round(t_ck / t_g, 4),
+           "grad_rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(gt - gc) / torch.linalg.norm(gc)), 5),
+           "grad_cos_vs_checkpoint_fp32": round(float(torch.sum(gt * gc) / torch.linalg.norm(gt) /
+                                                      torch.linalg.norm(gc)), 6),
+           "gn_hessvec_s": round(t_hv, 4), "hessvec_speedup_vs_checkpoint": round(hv_ck_s / t_hv, 4),
+           "hv_rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(ht - hc) / torch.linalg.norm(hc)), 5),
+           "store_GB": round(tm.storage_bytes() / 1e9, 3)}
+    tm.close()
+    return out
 
 
 def newton_iteration(args, p, ae_solver, ck, c0, wav, d_obs, sigma):
