@@ -89,12 +89,11 @@ struct EpiHasTile<E, std::void_t<decltype(E::kTile)>> {
 };
 
 // per-thread loader state of one work-group's tile rows, set before the k loop:
-// LoadK keeps the source address of each of its chunks (null: past the last row),
-// so a stage only adds its k offset; LoadT keeps the first row
+// the source address of each of its chunks (null: past the last row), so a stage
+// only adds its k offset
 template <int BR>
 struct LoadState {
     const uint16_t* row[Frag<BR>::NC];
-    int r0;
 };
 
 // source stored [rows][ld] with k contiguous; optional row gather
@@ -114,7 +113,6 @@ struct LoadK {
             const int gr = r0 + r;
             s.row[i] = (c < BR * (BK / 8) && gr < nrows) ? p + (long long)(rows ? rows[gr] : gr) * ld + kc : nullptr;
         }
-        s.r0 = r0;
     }
     template <int BR>
     __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int tid, Frag<BR>& f) const
@@ -138,57 +136,6 @@ struct LoadK {
     }
 };
 
-// source stored [k][ld] with rows contiguous (a transposed operand); optional k gather
-struct LoadT {
-    const uint16_t* p;
-    long long ld;
-    const int* kidx;  // nullable: logical k reads source row kidx[k]
-    int nrows;
-    int k_total;
-    template <int BR>
-    __device__ __forceinline__ void prepare(int r0, int, LoadState<BR>& s) const
-    {
-        s.r0 = r0;
-    }
-    template <int BR>
-    __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int tid, Frag<BR>& f) const
-    {
-        const int r0 = s.r0;
-#pragma unroll
-        for (int i = 0; i < Frag<BR>::NC; ++i) {
-            const int c = tid + 256 * i;
-            const int kk = c / (BR / 8), rc = (c % (BR / 8)) * 8;
-            const int gk = k0 + kk, gr = r0 + rc;
-            uint4 w = make_uint4(0, 0, 0, 0);
-            if (c < BK * (BR / 8) && gk < k_total) {
-                const long long src = kidx ? kidx[gk] : gk;
-                const uint16_t* q = p + src * ld + gr;
-                if (gr + 8 <= nrows) {
-                    w = *reinterpret_cast<const uint4*>(q);
-                } else {
-                    uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                    for (int t = 0; t < 8; ++t)
-                        if (gr + t < nrows) v[t] = q[t];
-                    memcpy(&w, v, 16);
-                }
-            }
-            f.v[i] = w;
-        }
-    }
-    template <int BR>
-    __device__ __forceinline__ void store(const Frag<BR>& f, int tid, uint16_t (*lds)[BK + LDS_PAD]) const
-    {
-#pragma unroll
-        for (int i = 0; i < Frag<BR>::NC; ++i) {
-            const int c = tid + 256 * i;
-            if (c >= BK * (BR / 8)) continue;
-            const int kk = c / (BR / 8), rc = (c % (BR / 8)) * 8;
-            uint16_t v[8];
-            memcpy(v, &f.v[i], 16);
-            for (int t = 0; t < 8; ++t) lds[rc + t][kk] = v[t];
-        }
-    }
-};
 
 template <int BM, int BN, int WM, int WN, class LA, class LB, class EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_per_split, LA la, LB lb, EPI epi)
@@ -1182,6 +1129,7 @@ namespace {
 struct TrainBufs {
     float *a1, *a3, *yhat, *d4f, *d3f, *dzf, *d1f, *zf, *part, *w;
     uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
+    uint16_t *xt, *dt;  // transposed operands of a weight gradient, [width][batch]
     double *lpart, *wsum;
 };
 
@@ -1199,7 +1147,7 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
                  o_zf = take(B * lat * 4), o_part = take((size_t)splits * in * hid * 4), o_h1 = take(B * hid * 2),
                  o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
                  o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8), o_w = take(B * 16),
-                 o_ws = take(8);
+                 o_ws = take(8), o_xt = take(B * std::max(in, hid) * 2), o_dt = take(B * std::max(in, hid) * 2);
     uint8_t* w = (uint8_t*)workspace(a, o);
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
@@ -1218,6 +1166,8 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
     t.d3 = (uint16_t*)(w + o_d3);
     t.dz = (uint16_t*)(w + o_dz);
     t.d1 = (uint16_t*)(w + o_d1);
+    t.xt = (uint16_t*)(w + o_xt);
+    t.dt = (uint16_t*)(w + o_dt);
     t.lpart = (double*)(w + o_lp);
     t.w = (float*)(w + o_w);
     t.wsum = (double*)(w + o_ws);
@@ -1225,13 +1175,61 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
 }
 
 // weight gradient dW[fi][fo] = X^T D with split-K over the batch
-template <class LX, class LD>
-void weight_grad(ae_net* a, int l, int B, const LX& lx, const LD& ld, float* part, int splits, hipStream_t st)
+// dst [C][R] = src rows transposed: dst[c][r] = src[rows ? rows[r] : r][c] for a bf16
+// matrix of R rows (R % 8 == 0) and C columns (C % 8 == 0) with row stride ld; 64 x 64
+// tiles through LDS, 16-byte loads and stores
+__global__ void __launch_bounds__(256) transpose_kernel(const uint16_t* __restrict__ src, long long ld,
+                                                        const int* __restrict__ rows, int R, int C,
+                                                        uint16_t* __restrict__ dst)
+{
+    __shared__ uint16_t tile[64][64 + 2];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = threadIdx.x + 256 * q;
+        const int r = k >> 3, c8 = (k & 7) * 8;
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r0 + r < R && c0 + c8 < C) {
+            const long long sr = rows ? rows[r0 + r] : r0 + r;
+            const uint4 w = *reinterpret_cast<const uint4*>(src + sr * ld + c0 + c8);
+            memcpy(v, &w, 16);
+        }
+        for (int i = 0; i < 8; ++i) tile[r][c8 + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = threadIdx.x + 256 * q;
+        const int c = k >> 3, r8 = (k & 7) * 8;
+        if (c0 + c < C && r0 + r8 < R) {
+            uint16_t v[8];
+            for (int i = 0; i < 8; ++i) v[i] = tile[r8 + i][c];
+            uint4 w;
+            memcpy(&w, v, 16);
+            *reinterpret_cast<uint4*>(dst + (long long)(c0 + c) * R + r0 + r8) = w;
+        }
+    }
+}
+
+void transpose_rows(const uint16_t* src, long long ld, const int* rows, int R, int C, uint16_t* dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(transpose_kernel, dim3((C + 63) / 64, (R + 63) / 64), dim3(256), 0, st, src, ld, rows, R, C,
+                       dst);
+    WV_HIP(hipGetLastError());
+}
+
+// dW_l = X^T D summed over the batch: both operands are transposed into k-contiguous
+// rows first (the batch rows of X gathered by xrows), so the GEMM streams whole rows
+void weight_grad(ae_net* a, int l, int B, const uint16_t* X, const int* xrows, const uint16_t* D, TrainBufs& t,
+                 int splits, hipStream_t st)
 {
     const int fi = a->fi[l], fo = a->fo[l];
     const long long n = (long long)fi * fo;
-    gemm_auto(fi, fo, B, lx, ld, EpiF32{part, fo, n, nullptr}, st, splits);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, part, splits, n, a->grad + a->oW[l]);
+    transpose_rows(X, fi, xrows, B, fi, t.xt, st);
+    transpose_rows(D, fo, nullptr, B, fo, t.dt, st);
+    gemm_auto(fi, fo, B, LoadK{t.xt, B, nullptr, fi, B}, LoadK{t.dt, B, nullptr, fo, B},
+              EpiF32{t.part, fo, n, nullptr}, st, splits);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, t.part, splits, n, a->grad + a->oW[l]);
 }
 
 void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting, const int* idx, int B,
@@ -1253,22 +1251,22 @@ void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting,
                        t.lpart);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lpart, B, 1.0, dloss, accumulate);
     // backward: layer 4
-    weight_grad(a, 3, B, LoadT{t.h3, hid, nullptr, hid, B}, LoadT{t.d4, in, nullptr, in, B}, t.part, splits, st);
+    weight_grad(a, 3, B, t.h3, nullptr, t.d4, t, splits, st);
     colsum(t.d4f, B, in, t.part, a->grad + a->ob[3], st);
     gemm_auto(B, hid, in, LoadK{t.d4, in, nullptr, B, in}, LoadK{a->wb[3], in, nullptr, hid, in},
               EpiGeluBack{t.d3, t.d3f, t.a3, hid}, st);
     // layer 3
-    weight_grad(a, 2, B, LoadT{t.zb, lat, nullptr, lat, B}, LoadT{t.d3, hid, nullptr, hid, B}, t.part, splits, st);
+    weight_grad(a, 2, B, t.zb, nullptr, t.d3, t, splits, st);
     colsum(t.d3f, B, hid, t.part, a->grad + a->ob[2], st);
     gemm_auto(B, lat, hid, LoadK{t.d3, hid, nullptr, B, hid}, LoadK{a->wb[2], hid, nullptr, lat, hid},
               EpiBF16{t.dz, lat, nullptr, t.dzf}, st);
     // layer 2
-    weight_grad(a, 1, B, LoadT{t.h1, hid, nullptr, hid, B}, LoadT{t.dz, lat, nullptr, lat, B}, t.part, splits, st);
+    weight_grad(a, 1, B, t.h1, nullptr, t.dz, t, splits, st);
     colsum(t.dzf, B, lat, t.part, a->grad + a->ob[1], st);
     gemm_auto(B, hid, lat, LoadK{t.dz, lat, nullptr, B, lat}, LoadK{a->wb[1], lat, nullptr, hid, lat},
               EpiGeluBack{t.d1, t.d1f, t.a1, hid}, st);
     // layer 1
-    weight_grad(a, 0, B, LoadT{y, in, idx, in, B}, LoadT{t.d1, hid, nullptr, hid, B}, t.part, splits, st);
+    weight_grad(a, 0, B, y, idx, t.d1, t, splits, st);
     colsum(t.d1f, B, hid, t.part, a->grad + a->ob[0], st);
     WV_HIP(hipGetLastError());
 }
