@@ -169,7 +169,9 @@ int wv_set_ae_exceptions(wv_ctx* ctx, int32_t k_per_step);
  * exception patches; it is allocated at the first such call, within the memory
  * budget together with the forward store (WV_ENOMEM beyond it). The Gauss-Newton
  * product itself does not read these states (wv_decode_delta returns them).
- * enable = 0 frees the store. Other modes ignore the setting. */
+ * enable = 0 frees the store, and also the incremental time store that the
+ * full-Newton product of WV_STORE_AE_TIME allocates. Other modes ignore the
+ * setting. */
 int wv_set_delta_storage(wv_ctx* ctx, int32_t enable);
 
 /* Decompress the stored incremental state dx_n (1 <= n <= T-1) of every source
@@ -227,11 +229,13 @@ int gradient(wv_ctx* ctx, const float* c, const float* wavelet, const float* d_o
  * source dm e^n (dm = 2 c dc), then the incremental adjoint (Sec. 4).
  * gauss_newton = 0: the full-Newton product, the derivative of the gradient along
  * dc, Hdc = -2 dt (dc * sum_n e^n q^n + c * sum_n (de^n q^n + e^n dq^n)): the
- * incremental forward keeps de^n (full storage, or compressed into the incremental
- * latent store in the AE modes), then the adjoint mu of the last gradient's
- * residual and the incremental adjoint dmu (residual dt/sigma^2 dp, and -dt dm q
- * in its eta equation) step together in reverse time. Needs the full or an AE
- * store (WV_ESTATE for checkpointing or after a fallback).
+ * incremental forward keeps de^n (full storage; compressed into the incremental
+ * latent store in the AE modes; in WV_STORE_AE_TIME into a second time store of
+ * the same layout and exception count, allocated at the first such call within
+ * the memory budget together with the forward store), then the adjoint mu of the
+ * last gradient's residual and the incremental adjoint dmu (residual dt/sigma^2
+ * dp, and -dt dm q in its eta equation) step together in reverse time. Needs the
+ * full, an AE or the time store (WV_ESTATE for checkpointing or after a fallback).
  * WV_ESTATE when c differs from the last gradient's c or no store exists. */
 int hessvec(wv_ctx* ctx, const float* c, const float* dc, float* Hdc, int gauss_newton);
 
@@ -279,7 +283,7 @@ typedef struct wv_newton_cfg {
     double rel_tol;         /* stop once |g| <= rel_tol |g_0| (>= 0) */
     double c_armijo;        /* sufficient decrease J(c + a p) <= J + c_armijo a g.p, in (0, 1) */
     int32_t max_backtrack;  /* halvings of the step length before the line search fails (>= 0) */
-    int32_t gauss_newton;   /* 1: Gauss-Newton misfit Hessian, 0: full Newton (full or AE store) */
+    int32_t gauss_newton;   /* 1: Gauss-Newton misfit Hessian, 0: full Newton (full, AE or time store) */
     int32_t precondition;   /* 1: CG preconditioned by the prior covariance (dx^dims A A)^-1, each
                                application two elliptic solves by CG to 1e-6 relative residual;
                                0: none. 1 needs a prior (WV_ESTATE otherwise) */

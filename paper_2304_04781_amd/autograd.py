@@ -11,7 +11,7 @@ prior term R(c).
 By default the misfit's second derivative is the Gauss-Newton Hessian
 (J_F^T Gamma^-1 J_F, the operator Newton-CG applies in the paper's Sec. 4),
 which omits the term weighted by the data residual. Passing False selects the
-full-Newton product, which needs a full or autoencoder store. The prior's is exact
+full-Newton product, which needs a full, autoencoder or time store. The prior's is exact
 (dx^dims A A). All arithmetic runs in the HIP library. The gradient is computed
 together with J (one forward and one adjoint solve), and the forward history
 (checkpoints or autoencoder latents) is reused by every Hv at the same c."""

@@ -822,9 +822,14 @@ struct ae_net {
     double* loss_d = nullptr;
     double beta[4] = {1e-7, 1e-7, 1e-7, 1e-7};
     long long step = 0;
-    // workspace (grown on demand)
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
+    // workspaces, one per stream (grown on demand): codec calls queued on different
+    // streams (the forward and the incremental history) may run at the same time
+    struct Workspace {
+        hipStream_t st;
+        void* p;
+        size_t bytes;
+    };
+    std::vector<Workspace> ws;
 
     const float* bias(int l) const { return master + ob[l]; }
 };
@@ -881,18 +886,27 @@ void upload_beta(ae_net* a)
     WV_HIP(hipMemcpy(a->beta_d, b, sizeof(b), hipMemcpyHostToDevice));
 }
 
-void* workspace(const ae_net* ac, size_t bytes)
+// the work buffer of the calls queued on stream st; calls on one stream run in
+// order, so they share it
+void* workspace(const ae_net* ac, size_t bytes, hipStream_t st)
 {
     ae_net* a = const_cast<ae_net*>(ac);
-    if (bytes > a->ws_bytes) {
-        WV_HIP(hipDeviceSynchronize());
-        if (a->ws) (void)hipFree(a->ws);
-        a->ws = nullptr;
-        a->ws_bytes = 0;
-        a->ws = dalloc<uint8_t>(bytes);
-        a->ws_bytes = bytes;
+    ae_net::Workspace* w = nullptr;
+    for (auto& q : a->ws)
+        if (q.st == st) w = &q;
+    if (!w) {
+        a->ws.push_back({st, nullptr, 0});
+        w = &a->ws.back();
     }
-    return a->ws;
+    if (bytes > w->bytes) {
+        WV_HIP(hipDeviceSynchronize());
+        if (w->p) (void)hipFree(w->p);
+        w->p = nullptr;
+        w->bytes = 0;
+        w->p = dalloc<uint8_t>(bytes);
+        w->bytes = bytes;
+    }
+    return w->p;
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -970,7 +984,7 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
             fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
                          (uint16_t*)latent, nullptr, st);
         } else {
-            float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
+            float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4), st);
             fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr,
                          z, st);
             hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
@@ -980,7 +994,7 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
         return;
     }
     const size_t oy = 0, oh = align256(oy + P * 2048 * 2), oz = align256(oh + P * (size_t)a->hid * 2);
-    uint8_t* ws = (uint8_t*)workspace(a, align256(oz + P * (size_t)a->lat * 4));
+    uint8_t* ws = (uint8_t*)workspace(a, align256(oz + P * (size_t)a->lat * 4), st);
     uint16_t* y = (uint16_t*)(ws + oy);
     uint16_t* h = (uint16_t*)(ws + oh);
     float* z = (float*)(ws + oz);
@@ -1013,7 +1027,7 @@ void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state
         fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
                      (uint16_t*)latent, nullptr, st);
     } else {
-        float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4));
+        float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4), st);
         fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
         hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                            qscale);
@@ -1053,7 +1067,7 @@ void ae_time_encode(const ae_net* a, const TimeGrid& tg, const float* e_win, int
 {
     const long long M = tg.B * tg.S;
     const size_t oh = align256(M * (size_t)a->in * 2);
-    uint8_t* ws = (uint8_t*)workspace(a, align256(oh + M * (size_t)a->hid * 2));
+    uint8_t* ws = (uint8_t*)workspace(a, align256(oh + M * (size_t)a->hid * 2), st);
     uint16_t* y = (uint16_t*)ws;
     uint16_t* h = (uint16_t*)(ws + oh);
     ae_time_normalize_rows(a, tg, e_win, nvalid, nullptr, M, y, meta, st);
@@ -1069,7 +1083,7 @@ void ae_time_decode(const ae_net* a, const TimeGrid& tg, const uint16_t* latent,
     WV_REQUIRE(a->in == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
     WV_REQUIRE(nvalid >= 1 && nvalid <= TWIN, WV_EINVAL, "nvalid must lie in [1, 32]");
     const long long M = tg.B * tg.S;
-    uint16_t* h = (uint16_t*)workspace(a, align256(M * (size_t)a->hid * 2));
+    uint16_t* h = (uint16_t*)workspace(a, align256(M * (size_t)a->hid * 2), st);
     gemm_auto((int)M, a->hid, a->lat, LoadK{latent, a->lat, nullptr, (int)M, a->lat},
               LoadK{a->wt[2], a->lat, nullptr, a->hid, a->lat}, EpiGelu{h, a->hid, a->bias(2), nullptr}, st);
     const long long N = (long long)tg.nz * tg.ny * tg.nx;
@@ -1088,7 +1102,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
     if (fused_supported(a->hid, a->lat)) {
         const uint16_t* zb = (const uint16_t*)latent;
         if (fmt == AE_LATENT_FP8) {
-            uint16_t* zq = (uint16_t*)workspace(a, align256(P * (size_t)a->lat * 2));
+            uint16_t* zq = (uint16_t*)workspace(a, align256(P * (size_t)a->lat * 2), st);
             hipLaunchKernelGGL(dequantize_kernel, dim3(blocks(P * a->lat, 256)), dim3(256), 0, st,
                                (const uint8_t*)latent, qscale, P, a->lat, zq);
             WV_HIP(hipGetLastError());
@@ -1101,7 +1115,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
         return;
     }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);
-    uint8_t* ws = (uint8_t*)workspace(a, align256(ozb + P * (size_t)a->lat * 2));
+    uint8_t* ws = (uint8_t*)workspace(a, align256(ozb + P * (size_t)a->lat * 2), st);
     uint16_t* h = (uint16_t*)(ws + oh);
     const uint16_t* zb = (const uint16_t*)latent;
     if (fmt == AE_LATENT_FP8) {
@@ -1133,7 +1147,7 @@ struct TrainBufs {
     double *lpart, *wsum;
 };
 
-TrainBufs train_buffers(const ae_net* a, int B, int splits)
+TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
 {
     const size_t in = a->in, hid = a->hid, lat = a->lat;
     size_t o = 0;
@@ -1148,7 +1162,7 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits)
                  o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
                  o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8), o_w = take(B * 16),
                  o_ws = take(8), o_xt = take(B * std::max(in, hid) * 2), o_dt = take(B * std::max(in, hid) * 2);
-    uint8_t* w = (uint8_t*)workspace(a, o);
+    uint8_t* w = (uint8_t*)workspace(a, o, st);
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
     t.a3 = (float*)(w + o_a3);
@@ -1326,7 +1340,8 @@ void free_net(ae_net* a)
     }
     if (a->wp1) (void)hipFree(a->wp1);
     if (a->wp4) (void)hipFree(a->wp4);
-    if (a->ws) (void)hipFree(a->ws);
+    for (auto& q : a->ws)
+        if (q.p) (void)hipFree(q.p);
     delete a;
 }
 
@@ -1629,7 +1644,7 @@ int ae_train_step(ae_net* a, const uint16_t* y, const float* meta, const int32_t
         WV_REQUIRE(B % 32 == 0, WV_EINVAL, "batch must be a multiple of 32");
         hipStream_t st = (hipStream_t)stream;
         const int splits = std::max(1, std::min(8, B / 512));
-        TrainBufs t = train_buffers(a, B, splits);
+        TrainBufs t = train_buffers(a, B, splits, st);
         double* dloss = a->loss_d;
         train_batch(a, y, meta, cfg->weighting, idx, B, t, splits, dloss, 0, st);
         if (h_grads) WV_HIP(hipMemcpyAsync(h_grads, a->grad, a->nparam * 4, hipMemcpyDeviceToHost, st));
@@ -1653,7 +1668,7 @@ int ae_train(ae_net* a, const uint16_t* y, const float* meta, int64_t nsamples, 
         hipStream_t st = (hipStream_t)stream;
         const int B = cfg->batch;
         const int splits = std::max(1, std::min(8, B / 512));
-        TrainBufs t = train_buffers(a, B, splits);
+        TrainBufs t = train_buffers(a, B, splits, st);
         double* dloss = a->loss_d;
         const long long nb = nsamples / B;
         std::vector<int> seq;

@@ -164,6 +164,25 @@ struct LatStore {
     int* exc_rng = nullptr;   // [T-1][S][nbd + 1]: exceptions per decode work-group
 };
 
+// One time-compressed history (e^1..e^{T-1} of the forward solve, or de^1..de^{T-1}
+// of the incremental forward): latents [nwin][S B][L] bf16, meta [nwin][S B][2]
+// (lo, r), the K exact vectors per window and source, and two window buffers
+// [2][TWIN][S][N]. The forward fills one buffer while the other is compressed on
+// the store's side stream; the reverse-time sweeps read one while the next window
+// is decompressed into the other.
+struct TimeStore {
+    uint16_t* lat = nullptr;
+    float* meta = nullptr;
+    float* win = nullptr;
+    int* exc_idx = nullptr;      // [nwin][S][K] block indices, increasing
+    float* exc = nullptr;        // [nwin][S][K][2048] their exact values
+    int K = 0;
+    int side = 0;                // side stream index of its codec work
+    int buf_w[2] = {-1, -1};     // window held decoded in each buffer (-1: none)
+    int cur_w = -1;              // window the main stream reads now
+    hipEvent_t ev_fill[2] = {}, ev_enc[2] = {}, ev_ready[2] = {}, ev_free[2] = {};
+};
+
 struct wv_ctx {
     KernelTimer tm;
     wv_grid g{};
@@ -248,22 +267,14 @@ struct wv_ctx {
     double sigma = 1.0;
     long long last_fwd_steps = 0;
 
-    // time compression store: latents [nwin][S B][L] bf16, meta [nwin][S B][2] (lo, r),
-    // two window buffers [2][TWIN][S][N]: the forward fills one while the other is
-    // compressed on `side`; the reverse-time sweeps read one while the next window
-    // is decompressed into the other on `side`
-    uint16_t* tlat = nullptr;
-    float* tmeta = nullptr;
-    float* twin = nullptr;
-    int tbuf_w[2] = {-1, -1};    // window held decoded in each buffer (-1: none)
-    int tcur_w = -1;             // window the main stream reads now
-    hipEvent_t ev_tfill[2] = {}, ev_tenc[2] = {}, ev_tready[2] = {}, ev_tfree[2] = {};
+    // time compression: the forward history ts and (full-Newton products) the
+    // incremental history tds, on one block layout
+    TimeStore ts;
+    TimeStore tds;
     long long TB = 0;            // 4^3 blocks per source
     int nwin = 0;
     int tlat_dim = 0;
-    int tK = 0;                  // exception vectors per window and source
-    int* texc_idx = nullptr;     // [nwin][S][tK] block indices, increasing
-    float* texc = nullptr;       // [nwin][S][tK][2048] their exact values
+    bool tdelta_ok = false;      // tds holds the incremental states of the last incremental forward
 
     // MAP layer: BiLaplacian prior and the Newton-CG work vectors
     double prior_alpha = 0.0;
@@ -418,9 +429,10 @@ void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid,
 }
 
 void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, long long enstride,
-              float* dtraces)
+              float* dtraces, float* e_extra = nullptr)
 {
     StepArgs a = base_args(c);
+    a.e_extra = e_extra;
     a.in = in;
     a.out = out;
     a.tidx = n;
@@ -453,6 +465,19 @@ void free_latstore(LatStore& L)
     dev_free(L.exc_rng);
 }
 
+// frees the buffers of a time store; its events live as long as the context
+void free_timestore(TimeStore& T)
+{
+    dev_free(T.lat);
+    dev_free(T.meta);
+    dev_free(T.win);
+    dev_free(T.exc_idx);
+    dev_free(T.exc);
+    T.K = 0;
+    T.buf_w[0] = T.buf_w[1] = -1;
+    T.cur_w = -1;
+}
+
 void free_store(wv_ctx* c)
 {
     dev_free(c->slots);
@@ -463,14 +488,9 @@ void free_store(wv_ctx* c)
     c->delta_bytes = 0;
     dev_free(c->mmpart);
     dev_free(c->work[2]);
-    dev_free(c->tlat);
-    dev_free(c->tmeta);
-    dev_free(c->twin);
-    dev_free(c->texc_idx);
-    dev_free(c->texc);
-    c->tK = 0;
-    c->tbuf_w[0] = c->tbuf_w[1] = -1;
-    c->tcur_w = -1;
+    free_timestore(c->ts);
+    free_timestore(c->tds);
+    c->tdelta_ok = false;
     c->K = 0;
     c->store_bytes = 0;
     c->store_ok = false;
@@ -512,12 +532,46 @@ void prepare_model(wv_ctx* c, const float* cdev, const float* wavelet)
 
 bool is_ae(int mode) { return mode == WV_STORE_AE_BF16 || mode == WV_STORE_AE_FP8; }
 bool is_time(int mode) { return mode == WV_STORE_AE_TIME; }
-float* twin_buf(wv_ctx* c, int b) { return c->twin + (long long)b * TWIN * c->S * c->N; }
-int* texc_idx_slot(wv_ctx* c, int w, int s) { return c->texc_idx + ((long long)w * c->S + s) * c->tK; }
-float* texc_slot(wv_ctx* c, int w, int s) { return c->texc + ((long long)w * c->S + s) * c->tK * 2048; }
+float* twin_buf(const wv_ctx* c, const TimeStore& T, int b) { return T.win + (long long)b * TWIN * c->S * c->N; }
+int* texc_idx_slot(const wv_ctx* c, const TimeStore& T, int w, int s)
+{
+    return T.exc_idx + ((long long)w * c->S + s) * T.K;
+}
+float* texc_slot(const wv_ctx* c, const TimeStore& T, int w, int s)
+{
+    return T.exc + ((long long)w * c->S + s) * T.K * 2048;
+}
 TimeGrid ctx_time_grid(const wv_ctx* c) { return time_grid(c->g.nz, c->g.ny, c->g.nx, c->S); }
-uint16_t* tlat_slot(wv_ctx* c, int w) { return c->tlat + (long long)w * c->TB * c->S * c->tlat_dim; }
-float* tmeta_slot(wv_ctx* c, int w) { return c->tmeta + (long long)w * c->TB * c->S * 2; }
+uint16_t* tlat_slot(const wv_ctx* c, const TimeStore& T, int w)
+{
+    return T.lat + (long long)w * c->TB * c->S * c->tlat_dim;
+}
+float* tmeta_slot(const wv_ctx* c, const TimeStore& T, int w) { return T.meta + (long long)w * c->TB * c->S * 2; }
+
+// bytes of a time store with K exact vectors per window and source (its two
+// window buffers are work space and not counted)
+long long timestore_bytes(const wv_ctx* c, int K)
+{
+    const long long rows = (long long)c->nwin * c->TB * c->S;
+    const long long kslots = (long long)c->nwin * c->S * K;
+    return rows * (c->tlat_dim * 2 + 8) + kslots * (4 + 2048 * 4);
+}
+
+void alloc_timestore(wv_ctx* c, TimeStore& T, int K)
+{
+    const long long rows = (long long)c->nwin * c->TB * c->S;
+    const long long kslots = (long long)c->nwin * c->S * K;
+    T.lat = dev_alloc<uint16_t>(rows * c->tlat_dim);
+    T.meta = dev_alloc<float>(rows * 2);
+    T.K = K;
+    if (K > 0) {
+        T.exc_idx = dev_alloc<int>(kslots);
+        T.exc = dev_alloc<float>(kslots * 2048);
+    }
+    T.win = dev_alloc<float>((size_t)2 * TWIN * c->S * c->N);
+    T.buf_w[0] = T.buf_w[1] = -1;
+    T.cur_w = -1;
+}
 int ae_fmt(int mode) { return mode == WV_STORE_AE_FP8 ? AE_LATENT_FP8 : AE_LATENT_BF16; }
 
 
@@ -557,6 +611,37 @@ void alloc_latstore(wv_ctx* c, LatStore& L, int mode, int K)
 void wait_event(hipStream_t st, hipEvent_t ev);
 hipStream_t side_stream(wv_ctx* c, int which);
 
+// Window slot of level j (1..T-1) in store T, for the step about to write it.
+// The buffer held window w - 2, whose compression must have read it first.
+float* time_slot(wv_ctx* c, TimeStore& T, int j)
+{
+    const int t = (j - 1) % TWIN, w = (j - 1) / TWIN, b = w & 1;
+    if (t == 0 && w >= 2) wait_event(c->st, T.ev_enc[b]);
+    return twin_buf(c, T, b) + (long long)t * c->S * c->N;
+}
+
+// After the step that wrote level n into its slot: a full window (or the last,
+// short one) is compressed on the store's side stream while the steps go on into
+// the other buffer.
+void time_store_level(wv_ctx* c, TimeStore& T, int n)
+{
+    if (n < 1 || n > c->T - 1) return;
+    const int t = (n - 1) % TWIN, w = (n - 1) / TWIN, b = w & 1;
+    if (t != TWIN - 1 && n != c->T - 1) return;
+    float* buf = twin_buf(c, T, b);
+    hipStream_t s1 = side_stream(c, T.side);
+    WV_HIP(hipEventRecord(T.ev_fill[b], c->st));
+    wait_event(s1, T.ev_fill[b]);
+    const TimeGrid tg = ctx_time_grid(c);
+    const int te = c->tm.begin(TM_ENCODE, s1);
+    ae_time_encode(c->ae, tg, buf, t + 1, tlat_slot(c, T, w), tmeta_slot(c, T, w), s1);
+    for (int s = 0; s < c->S && T.K > 0; ++s)
+        time_exceptions_store(tg, buf, s, t + 1, tmeta_slot(c, T, w) + (long long)s * c->TB * 2, T.K,
+                              texc_idx_slot(c, T, w, s), texc_slot(c, T, w, s), s1);
+    c->tm.end(te, s1);
+    WV_HIP(hipEventRecord(T.ev_enc[b], s1));
+}
+
 // store x_n (n = 1..T-1) of every source on the main stream (full storage, or
 // the autoencoder store L without the forward step's min/max)
 void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
@@ -567,25 +652,8 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
             WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
                                   sizeof(float) * c->N, hipMemcpyDeviceToDevice, c->st));
     } else if (is_time(c->mode)) {
-        // the forward step wrote e^n into its window (buffer w % 2, see forward_sweep);
-        // a full window (or the last, short one) is compressed on `side` while the
-        // steps go on into the other buffer
-        (void)state;
-        const int t = (n - 1) % TWIN, w = (n - 1) / TWIN, b = w & 1;
-        float* buf = twin_buf(c, b);
-        if (t == TWIN - 1 || n == c->T - 1) {
-            hipStream_t s1 = side_stream(c, 0);
-            WV_HIP(hipEventRecord(c->ev_tfill[b], c->st));
-            wait_event(s1, c->ev_tfill[b]);
-            const TimeGrid tg = ctx_time_grid(c);
-            const int te = c->tm.begin(TM_ENCODE, s1);
-            ae_time_encode(c->ae, tg, buf, t + 1, tlat_slot(c, w), tmeta_slot(c, w), s1);
-            for (int s = 0; s < c->S && c->tK > 0; ++s)
-                time_exceptions_store(tg, buf, s, t + 1, tmeta_slot(c, w) + (long long)s * c->TB * 2, c->tK,
-                                      texc_idx_slot(c, w, s), texc_slot(c, w, s), s1);
-            c->tm.end(te, s1);
-            WV_HIP(hipEventRecord(c->ev_tenc[b], s1));
-        }
+        (void)state;  // the forward step wrote e^n into its window slot
+        time_store_level(c, c->ts, n);
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
         const int te = c->tm.begin(TM_ENCODE, c->st);
@@ -719,40 +787,41 @@ void decode_e(wv_ctx* c, int n, int b, hipStream_t st) { decode_state(c, c->fs, 
 // ebuf slot 0): pointer + per-source stride
 // queue the decompression of window w into buffer b on `side`, after the main
 // stream's reads of b enqueued so far
-void time_issue(wv_ctx* c, int w, int b)
+void time_issue(wv_ctx* c, TimeStore& T, int w, int b)
 {
-    hipStream_t s1 = side_stream(c, 0);
-    WV_HIP(hipEventRecord(c->ev_tfree[b], c->st));
-    wait_event(s1, c->ev_tfree[b]);
+    hipStream_t s1 = side_stream(c, T.side);
+    WV_HIP(hipEventRecord(T.ev_free[b], c->st));
+    wait_event(s1, T.ev_free[b]);
     const int nvalid = std::min(TWIN, c->T - 1 - w * TWIN);
     const TimeGrid tg = ctx_time_grid(c);
     const int td = c->tm.begin(TM_DECODE, s1);
-    ae_time_decode(c->ae, tg, tlat_slot(c, w), tmeta_slot(c, w), nvalid, twin_buf(c, b), s1);
-    for (int s = 0; s < c->S && c->tK > 0; ++s)
-        time_exceptions_restore(tg, twin_buf(c, b), s, nvalid, c->tK, texc_idx_slot(c, w, s), texc_slot(c, w, s), s1);
+    ae_time_decode(c->ae, tg, tlat_slot(c, T, w), tmeta_slot(c, T, w), nvalid, twin_buf(c, T, b), s1);
+    for (int s = 0; s < c->S && T.K > 0; ++s)
+        time_exceptions_restore(tg, twin_buf(c, T, b), s, nvalid, T.K, texc_idx_slot(c, T, w, s),
+                                texc_slot(c, T, w, s), s1);
     c->tm.end(td, s1);
-    WV_HIP(hipEventRecord(c->ev_tready[b], s1));
-    c->tbuf_w[b] = w;
+    WV_HIP(hipEventRecord(T.ev_ready[b], s1));
+    T.buf_w[b] = w;
 }
 
-// e^n of the time-compressed store: its window is decompressed whole; at the first
-// read of a window the next one in the direction of travel (dir = -1 reverse time,
-// +1 forward) is queued into the other buffer
-const float* time_e(wv_ctx* c, int n, int dir)
+// Level n of the time-compressed store T: its window is decompressed whole; at the
+// first read of a window the next one in the direction of travel (dir = -1 reverse
+// time, +1 forward) is queued into the other buffer
+const float* time_e(wv_ctx* c, TimeStore& T, int n, int dir)
 {
     const int w = (n - 1) / TWIN;
-    int b = c->tbuf_w[0] == w ? 0 : (c->tbuf_w[1] == w ? 1 : -1);
+    int b = T.buf_w[0] == w ? 0 : (T.buf_w[1] == w ? 1 : -1);
     if (b < 0) {
-        b = c->tbuf_w[0] == c->tcur_w && c->tcur_w >= 0 ? 1 : 0;
-        time_issue(c, w, b);
+        b = T.buf_w[0] == T.cur_w && T.cur_w >= 0 ? 1 : 0;
+        time_issue(c, T, w, b);
     }
-    if (c->tcur_w != w) {
-        wait_event(c->st, c->ev_tready[b]);
-        c->tcur_w = w;
+    if (T.cur_w != w) {
+        wait_event(c->st, T.ev_ready[b]);
+        T.cur_w = w;
         const int wn = w + dir;
-        if (wn >= 0 && wn < c->nwin && c->tbuf_w[0] != wn && c->tbuf_w[1] != wn) time_issue(c, wn, 1 - b);
+        if (wn >= 0 && wn < c->nwin && T.buf_w[0] != wn && T.buf_w[1] != wn) time_issue(c, T, wn, 1 - b);
     }
-    return twin_buf(c, b) + (long long)((n - 1) % TWIN) * c->S * c->N;
+    return twin_buf(c, T, b) + (long long)((n - 1) % TWIN) * c->S * c->N;
 }
 
 const float* load_e(wv_ctx* c, int n, long long* stride, int dir = -1)
@@ -760,7 +829,7 @@ const float* load_e(wv_ctx* c, int n, long long* stride, int dir = -1)
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     *stride = c->N;
     if (c->mode == WV_STORE_FULL) return c->ehist + (long long)(n - 1) * c->S * c->N;
-    if (is_time(c->mode)) return time_e(c, n, dir);
+    if (is_time(c->mode)) return time_e(c, c->ts, n, dir);
     ensure_adj(c);  // owns the decode target ebuf
     decode_e(c, n, 0, c->st);
     return ebuf_slot(c, 0);
@@ -802,8 +871,9 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
     if (is_time(c->mode)) {
         // the window buffers are refilled: nothing queued on `side` may still use them
         join_side(c);
-        c->tbuf_w[0] = c->tbuf_w[1] = -1;
-        c->tcur_w = -1;
+        c->ts.buf_w[0] = c->ts.buf_w[1] = -1;
+        c->ts.cur_w = -1;
+        c->tdelta_ok = false;
     }
     // autoencoder stores run beside the steps (x_j in work[j % 3])
     const bool ae = is_ae(c->mode) && c->mmpart && c->has_y;
@@ -827,12 +897,7 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
         float* mm = (ae && store) ? c->mmpart + (j % 3) * mm_stride : nullptr;
         // time compression: the step writes e^j straight into its window slot; the
         // buffer held window w - 2, whose compression must have read it
-        float* ew = nullptr;
-        if (is_time(c->mode) && store) {
-            const int t = (j - 1) % TWIN, w = (j - 1) / TWIN, b = w & 1;
-            if (t == 0 && w >= 2) wait_event(c->st, c->ev_tenc[b]);
-            ew = twin_buf(c, b) + (long long)t * c->S * c->N;
-        }
+        float* ew = is_time(c->mode) && store ? time_slot(c, c->ts, j) : nullptr;
         fwd_step(c, cur, out, n, traces, mm, ew);
         if (store) {
             if (ae)
@@ -894,7 +959,7 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
                    float* xtm1)
 {
     ensure_adj(c);
-    c->tcur_w = -1;
+    c->ts.cur_w = -1;
     launch_fill(c->adj[0], c->state_floats(), 0.f, c->st);
     launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
     float* ain = c->adj[0];
@@ -1043,9 +1108,11 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
             WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
         }
         WV_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        for (int b = 0; b < 2; ++b)
-            for (hipEvent_t* e : {&c->ev_tfill[b], &c->ev_tenc[b], &c->ev_tready[b], &c->ev_tfree[b]})
-                WV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        c->tds.side = 1;
+        for (TimeStore* T : {&c->ts, &c->tds})
+            for (int b = 0; b < 2; ++b)
+                for (hipEvent_t* e : {&T->ev_fill[b], &T->ev_enc[b], &T->ev_ready[b], &T->ev_free[b]})
+                    WV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         c->partial = dev_alloc<double>(3 * (size_t)c->nblk_red);
         c->dscal = dev_alloc<double>(8);
         c->dflag = dev_alloc<int>(1);
@@ -1070,9 +1137,10 @@ int wv_destroy(wv_ctx* c)
         if (c->ev_ready[b]) (void)hipEventDestroy(c->ev_ready[b]);
         if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
     }
-    for (int b = 0; b < 2; ++b)
-        for (hipEvent_t e : {c->ev_tfill[b], c->ev_tenc[b], c->ev_tready[b], c->ev_tfree[b]})
-            if (e) (void)hipEventDestroy(e);
+    for (TimeStore* T : {&c->ts, &c->tds})
+        for (int b = 0; b < 2; ++b)
+            for (hipEvent_t e : {T->ev_fill[b], T->ev_enc[b], T->ev_ready[b], T->ev_free[b]})
+                if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->side2) (void)hipStreamDestroy(c->side2);
     dev_free(c->tab);
@@ -1128,19 +1196,10 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             c->TB = ctx_time_grid(c).B;
             c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
             c->tlat_dim = ae_latent_dim(ae);
-            const long long rows = (long long)c->nwin * c->TB * c->S;
             const int K = (int)std::min<long long>(c->exc_req, c->TB);
-            const long long kslots = (long long)c->nwin * c->S * K;
-            const long long bytes = rows * (c->tlat_dim * 2 + 8) + kslots * (4 + 2048 * 4);
+            const long long bytes = timestore_bytes(c, K);
             WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
-            c->tlat = dev_alloc<uint16_t>(rows * c->tlat_dim);
-            c->tmeta = dev_alloc<float>(rows * 2);
-            c->tK = K;
-            if (K > 0) {
-                c->texc_idx = dev_alloc<int>(kslots);
-                c->texc = dev_alloc<float>(kslots * 2048);
-            }
-            c->twin = dev_alloc<float>((size_t)2 * TWIN * c->S * c->N);
+            alloc_timestore(c, c->ts, K);
             c->store_bytes = bytes;
         } else if (is_ae(mode)) {
             WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
@@ -1203,8 +1262,10 @@ int wv_set_delta_storage(wv_ctx* c, int32_t enable)
         c->store_delta = enable == 1;
         if (!c->store_delta) {
             free_latstore(c->ds);
+            free_timestore(c->tds);
             c->delta_bytes = 0;
             c->delta_ok = false;
+            c->tdelta_ok = false;
         }
         return WV_OK;
     });
@@ -1382,13 +1443,13 @@ namespace {
 // incremental forward into c->dtr; CHECKPOINT runs the companion forward and
 // places snapshots for a following reverse sweep (returns x_{T-1} there).
 // keep_de: the full-Newton product needs de^n later (FULL: de history; AE: the
-// incremental latent store)
+// incremental latent store; time compression: the incremental time store)
 float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const std::vector<int>* snap,
                          bool keep_de = false)
 {
     ensure_inc(c);
     ensure_adj(c);
-    c->tcur_w = -1;
+    c->ts.cur_w = -1;
     launch_dm(cdev, dc, c->dm, c->N, c->st);
     launch_fill(c->incb[0], c->state_floats(), 0.f, c->st);
     const bool pipe = !snap && is_ae(c->mode);
@@ -1403,6 +1464,22 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
                    "incremental latent store exceeds the memory budget");
         alloc_latstore(c, c->ds, c->mode, c->K);
         c->delta_bytes = bytes;
+    }
+    // time store of de^1 .. de^{T-1}: same network, block layout and exception count
+    const bool keep_time = keep_de && !snap && is_time(c->mode);
+    c->tdelta_ok = false;
+    if (keep_time) {
+        if (!c->tds.lat) {
+            const long long bytes = timestore_bytes(c, c->ts.K);
+            WV_REQUIRE(c->budget <= 0 || c->store_bytes + bytes <= c->budget, WV_ENOMEM,
+                       "incremental latent store exceeds the memory budget");
+            alloc_timestore(c, c->tds, c->ts.K);
+            c->delta_bytes = bytes;
+        }
+        // its window buffers are refilled: nothing queued on the side streams may still use them
+        join_side(c);
+        c->tds.buf_w[0] = c->tds.buf_w[1] = -1;
+        c->tds.cur_w = -1;
     }
     if (pipe) pipe_start(c);
     launch_fill(ebuf_slot(c, 0), c->N * c->S, 0.f, c->st);  // e^0 = 0
@@ -1434,9 +1511,11 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         } else {
             en = load_e(c, n, &stride, +1);
         }
-        inc_step(c, din, dout, n, en, stride, c->dtr);
+        float* dew = keep_time && n + 1 <= c->T - 1 ? time_slot(c, c->tds, n + 1) : nullptr;
+        inc_step(c, din, dout, n, en, stride, c->dtr, dew);
         if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
+        if (keep_time) time_store_level(c, c->tds, n + 1);
         if (keep_delta) store_state(c, c->ds, n + 1, din);  // dx_{n+1}, read again only by the step after next
         if (keep_full && n + 1 <= c->T - 1)
             for (int s = 0; s < c->S; ++s)
@@ -1451,6 +1530,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
     }
     if (ckpt) c->last_fwd_steps = c->T;
     if (keep_delta) c->delta_ok = true;
+    if (keep_time) c->tdelta_ok = true;
     return prev;
 }
 
@@ -1460,8 +1540,8 @@ int wave_inc_forward(wv_ctx* c, const float* cdev, const float* dc, float* dtrac
 {
     return guarded([&]() -> int {
         WV_REQUIRE(c && cdev && dc && dtraces, WV_EINVAL, "null argument");
-        WV_REQUIRE(c->mode == WV_STORE_FULL || is_ae(c->mode) || c->mode == WV_STORE_CHECKPOINT, WV_ESTATE,
-                   "incremental forward needs a storage mode");
+        WV_REQUIRE(c->mode == WV_STORE_FULL || is_ae(c->mode) || is_time(c->mode) || c->mode == WV_STORE_CHECKPOINT,
+                   WV_ESTATE, "incremental forward needs a storage mode");
         if (c->mode == WV_STORE_CHECKPOINT) {
             prepare_model(c, cdev, nullptr);
             std::vector<int> snap(c->T + 1, 0);
@@ -1477,7 +1557,7 @@ int wave_inc_forward(wv_ctx* c, const float* cdev, const float* dc, float* dtrac
 
 namespace {
 
-// Reverse sweep of the full-Newton Hessian action (FULL or AE store): per step k,
+// Reverse sweep of the full-Newton Hessian action (FULL, AE or time store): per step k,
 // the mu step (residual of the last gradient) writes q and sums e^k q into acc;
 // the dmu step (residual dt/sigma^2 dp) takes -dt dm q into eta and sums
 // de^k q + e^k dq into dacc.
@@ -1496,6 +1576,8 @@ void reverse_sweep_newton(wv_ctx* c)
     launch_fill(c->acc, 2 * c->N * c->S, 0.f, c->st);
     launch_fill(c->dacc, 2 * c->N * c->S, 0.f, c->st);
     float *ain = c->adj[0], *aout = c->adj[1], *din = c->adj2[0], *dout = c->adj2[1];
+    c->ts.cur_w = -1;
+    c->tds.cur_w = -1;
     long long done = 0;
     for (int k = c->T - 1; k >= 1; --k) {
         long long stride;
@@ -1503,6 +1585,9 @@ void reverse_sweep_newton(wv_ctx* c)
         const float* de;
         if (c->mode == WV_STORE_FULL) {
             de = c->dehist + (long long)(k - 1) * c->S * c->N;
+        } else if (is_time(c->mode)) {
+            WV_REQUIRE(c->tdelta_ok, WV_ESTATE, "no incremental states stored");
+            de = time_e(c, c->tds, k, -1);
         } else {
             decode_state(c, c->ds, k, 1u, c->dbuf, c->N, c->st);
             de = c->dbuf;
@@ -1536,8 +1621,8 @@ int hessvec(wv_ctx* c, const float* cdev, const float* dc, float* Hdc, int gauss
         const bool use_ckpt = c->mode == WV_STORE_CHECKPOINT || (c->degraded && c->fallback == WV_FALLBACK_CHECKPOINT);
         if (!gauss_newton) {
             // full Newton: d/dc of the gradient along dc, -2 dt (dc acc + c dacc)
-            WV_REQUIRE(!use_ckpt && (c->mode == WV_STORE_FULL || is_ae(c->mode)), WV_ESTATE,
-                       "the full-Newton product needs a stored history (full or autoencoder)");
+            WV_REQUIRE(!use_ckpt && (c->mode == WV_STORE_FULL || is_ae(c->mode) || is_time(c->mode)), WV_ESTATE,
+                       "the full-Newton product needs a stored history (full, autoencoder or time)");
             WV_REQUIRE(c->store_ok, WV_ESTATE, "no forward history stored");
             inc_forward_sweep(c, cdev, dc, nullptr, true);
             launch_scale_weights(c->dtr, c->dresid, ntr, w, c->st);

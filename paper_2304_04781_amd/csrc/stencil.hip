@@ -95,7 +95,8 @@ __device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, u
 
 // MM: also write the per-patch (min, max) partials of the new state (forward only);
 // ACC: the adjoint's gradient accumulation phase; EX: also write the new e to
-// a.e_extra (forward only: the time-compression window slot of this level)
+// a.e_extra (forward and incremental forward: the time-compression window slot
+// of this level)
 template <int BX, int BY, int MODE, bool HAS_Y, bool MM, int ACC = ACC_EACH, bool EX = false>
 __global__ void __launch_bounds__(BX* BY)
     __attribute__((amdgpu_waves_per_eu(MM ? WV_WAVES_FWD_MM : MODE == MODE_INC || MODE == MODE_FWD ? WV_WAVES_OTHER
@@ -544,7 +545,7 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
         a.chunks_z = a.chunks_adj;
     }
     if (mode != MODE_FWD || !HAS_Y) a.mm_out = nullptr;
-    if (mode != MODE_FWD) a.e_extra = nullptr;
+    if (mode != MODE_FWD && mode != MODE_INC) a.e_extra = nullptr;
     dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
     dim3 block(BX * BY);
     switch (mode) {
@@ -560,7 +561,13 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
     case MODE_ADJ: launch_adj<BX, BY, MODE_ADJ, HAS_Y>(a, grid, block, st); break;
     case MODE_ADJQ: launch_adj<BX, BY, MODE_ADJQ, HAS_Y>(a, grid, block, st); break;
     case MODE_ADJD: launch_adj<BX, BY, MODE_ADJD, HAS_Y>(a, grid, block, st); break;
-    default: hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false>), grid, block, 0, st, a); break;
+    default:
+        if (a.e_extra)
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false, ACC_EACH, true>), grid, block, 0,
+                               st, a);
+        else
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false>), grid, block, 0, st, a);
+        break;
     }
 }
 

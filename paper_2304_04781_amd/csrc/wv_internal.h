@@ -83,8 +83,8 @@ struct StepArgs {
     float* qbuf;
     const float* dek;
     long long dekstride;
-    // forward only: e of the new state also written here ([S][N], per-source stride
-    // N), the time-compression window slot of this level; null for none
+    // forward and incremental forward: e of the new state also written here ([S][N],
+    // per-source stride N), the time-compression window slot of this level; null for none
     float* e_extra;
     // incremental forward: dm and forward e^n
     const float* dm;

@@ -347,6 +347,27 @@ def test_full_newton_hessvec_from_compressed_stores():
     assert torch.equal(H, H0)
 
 
+def test_full_newton_fp8_stores_reproducible():
+    """FP8 latents without exception patches: the incremental forward decodes e on
+    a side stream while it encodes the incremental states on the main stream, each
+    codec call with the work buffer of its own stream. Repeated full-Newton
+    products, alternating with Gauss-Newton ones, agree bit for bit."""
+    p = ae_problem(nt=60, shape=(32, 32, 40))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    dc = np.asarray(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2), np.float32).astype(np.float64)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_AE_FP8, ae=raw)
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    H1 = s.hessvec(p.c_start, dc, gauss_newton=False)
+    G1 = s.hessvec(p.c_start, dc)
+    assert torch.isfinite(H1).all() and not torch.equal(H1, G1)
+    for _ in range(2):
+        assert torch.equal(s.hessvec(p.c_start, dc, gauss_newton=False), H1)
+        assert torch.equal(s.hessvec(p.c_start, dc), G1)
+
+
 def test_guard_falls_back_to_checkpointing():
     p = ae_problem(nt=120, shape=(32, 32, 32))
     sol = ow.solver_for(p)

@@ -138,8 +138,8 @@ def test_time_store_levels_equal_window_roundtrip(nsrc):
     """T - 1 = 74 stored levels: two full windows and a short one of 10. Every level
     the reverse solves read (each source's) is the encode-decode round trip of the
     exact window from the same forward solve; the store holds 3 windows of latents
-    and (lo, r) per source; gradient and Gauss-Newton Hv run, the full-Newton
-    product is refused."""
+    and (lo, r) per source; gradient and Gauss-Newton Hv run; the full-Newton
+    product adds an incremental store of the same size."""
     p = time_problem(75, nsrc=nsrc)
     print("case sources", nsrc, flush=True)
     sol = ow.solver_for(p)
@@ -167,15 +167,21 @@ def test_time_store_levels_equal_window_roundtrip(nsrc):
             assert torch.equal(t.load_e(n), dec[lvl]), n
     H = t.hessvec(p.c_start, p.c_start * 0.01)
     assert torch.isfinite(H).all()
-    with pytest.raises(L.WvError):
-        t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False)
+    assert t.storage_bytes() == 3 * nsrc * B * (32 * 2 + 8)
+    Hf = t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False)
+    assert torch.isfinite(Hf).all() and not torch.equal(Hf, H)
+    assert t.storage_bytes() == 2 * 3 * nsrc * B * (32 * 2 + 8)
+    L.wv_set_delta_storage(t.ctx, 0)
+    assert t.storage_bytes() == 3 * nsrc * B * (32 * 2 + 8)
+    assert torch.equal(t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False), Hf)
 
 
 def test_time_compressed_gradient_with_trained_network():
     """The 48^3, 240-step problem of the space-scheme accuracy test (8 Hz): the
     time network is trained on all 8 windows of the forward solve at the start
     model; the compressed gradient and Gauss-Newton Hv are judged against full
-    storage. An untrained network is far worse."""
+    storage. An untrained network is far worse. The full-Newton product compresses the incremental
+    states de with the same network."""
     from paper_2304_04781_amd import compressor as C
     p = time_problem(240, shape=(48, 48, 48))
     p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
@@ -196,6 +202,7 @@ def test_time_compressed_gradient_with_trained_network():
     J0, g0 = plain.gradient(p.c_start, p.wavelet, d, sigma)
     dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
     H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+    F0 = plain.hessvec(p.c_start, dc, gauss_newton=False).cpu().numpy()
     g0n = g0.cpu().numpy().astype(np.float64)
     t = WaveSolver.for_problem(p)
     t.set_storage(L.STORE_AE_TIME, ae=net)
@@ -204,18 +211,21 @@ def test_time_compressed_gradient_with_trained_network():
     err = rel(gn, g0n)
     cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
     herr = rel(t.hessvec(p.c_start, dc).cpu().numpy(), H0)
-    print("time scheme: grad rel err", err, "cos", cos, "Hv rel err", herr,
+    ferr = rel(t.hessvec(p.c_start, dc, gauss_newton=False).cpu().numpy(), F0)
+    print("time scheme: grad rel err", err, "cos", cos, "Hv rel err", herr, "full-Newton Hv rel err", ferr,
           "store bytes", t.storage_bytes(), "vs full", plain.storage_bytes(), flush=True)
     assert J == J0
-    assert err < 0.2 and cos > 0.98 and herr < 0.2
+    # the full-Newton product also reads de through the network trained on e
+    assert err < 0.2 and cos > 0.98 and herr < 0.2 and ferr < 0.3
     # exception vectors: the 1 % largest-range vectors of every window kept exactly
     k = WaveSolver.for_problem(p)
     L.wv_set_ae_exceptions(k.ctx, 17)                       # 1 % of the 1728 blocks
     k.set_storage(L.STORE_AE_TIME, ae=net)
     _, gk = k.gradient(p.c_start, p.wavelet, d, sigma)
     err_k = rel(gk.cpu().numpy(), g0n)
-    print("with 17 exact vectors per window: grad rel err", err_k, flush=True)
-    assert err_k < err
+    ferr_k = rel(k.hessvec(p.c_start, dc, gauss_newton=False).cpu().numpy(), F0)
+    print("with 17 exact vectors per window: grad rel err", err_k, "full-Newton Hv rel err", ferr_k, flush=True)
+    assert err_k < err and ferr_k < ferr
     raw = Net(W.ae_init(seed=4))
     L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
     u = WaveSolver.for_problem(p)
@@ -258,13 +268,15 @@ def test_time_store_window_edges(nt):
         for lvl in range(nvalid):
             assert torch.equal(t.load_e(32 * w + 1 + lvl), dec[lvl]), (w, lvl)
     assert torch.isfinite(t.hessvec(p.c_start, p.c_start * 0.01)).all()
+    assert torch.isfinite(t.hessvec(p.c_start, p.c_start * 0.01, gauss_newton=False)).all()
 
 
 @pytest.mark.parametrize("nsrc", [1, 2])
 def test_time_all_vectors_exact_reproduce_full_storage(nsrc):
     """Exception vectors at K = B (every vector of every window kept exactly): each
-    level the reverse solves read is the exact e, so gradient and Gauss-Newton Hv
-    equal the full-storage ones bit for bit; the store counts the exact values."""
+    level the reverse solves read is the exact e (and de), so gradient,
+    Gauss-Newton and full-Newton Hv equal the full-storage ones bit for bit, also
+    when the products alternate; the store counts the exact values."""
     p = time_problem(75, nsrc=nsrc)
     print("case sources", nsrc, flush=True)
     sol = ow.solver_for(p)
@@ -274,8 +286,10 @@ def test_time_all_vectors_exact_reproduce_full_storage(nsrc):
     full = WaveSolver.for_problem(p)
     full.set_storage(L.STORE_FULL)
     J0, g0 = full.gradient(p.c_start, p.wavelet, d, sigma)
-    dc = p.c_start * 0.01
+    dc = p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 4.0, 3)
     H0 = full.hessvec(p.c_start, dc)
+    F0 = full.hessvec(p.c_start, dc, gauss_newton=False)
+    assert not torch.equal(F0, H0)
     e_all = full.forward_e(p.c_start, p.wavelet, list(range(1, 75)))
     t = WaveSolver.for_problem(p)
     L.wv_set_ae_exceptions(t.ctx, B)
@@ -286,3 +300,6 @@ def test_time_all_vectors_exact_reproduce_full_storage(nsrc):
         assert torch.equal(t.load_e(n), e_all[n - 1]), n
     assert J == J0 and torch.equal(g, g0)
     assert torch.equal(t.hessvec(p.c_start, dc), H0)
+    assert torch.equal(t.hessvec(p.c_start, dc, gauss_newton=False), F0)
+    assert torch.equal(t.hessvec(p.c_start, dc), H0)
+    assert torch.equal(t.hessvec(p.c_start, dc, gauss_newton=False), F0)
