@@ -303,3 +303,26 @@ def test_time_all_vectors_exact_reproduce_full_storage(nsrc):
     assert torch.equal(t.hessvec(p.c_start, dc, gauss_newton=False), F0)
     assert torch.equal(t.hessvec(p.c_start, dc), H0)
     assert torch.equal(t.hessvec(p.c_start, dc, gauss_newton=False), F0)
+
+
+def test_time_newton_cg_full_newton_equals_full_storage():
+    """Full-Newton Newton-CG on the time store with every vector exact takes the
+    full-storage path bit for bit: each gradient reads identical e, each Hessian
+    action identical e and de (the incremental store rewritten per action)."""
+    p = time_problem(75)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    net = Net(W.ae_init(seed=4))
+    cfg = dict(max_newton=2, max_cg=3, gauss_newton=0)
+    out = []
+    for mode in (L.STORE_FULL, L.STORE_AE_TIME):
+        s = WaveSolver.for_problem(p)
+        if mode != L.STORE_FULL:
+            L.wv_set_ae_exceptions(s.ctx, 8 * 8 * 10)
+        s.set_storage(mode, ae=net if mode != L.STORE_FULL else None)
+        s.set_prior(1e-6, (1600.0, 1600.0, 1600.0), p.c_start)
+        out.append(s.newton_cg(p.c_start, p.wavelet, d, sigma, **cfg))
+    (c0, log0, it0, _), (c1, log1, it1, _) = out
+    assert it0 == it1 == 2
+    assert torch.equal(c0, c1)
+    assert [r["cost"] for r in log0] == [r["cost"] for r in log1]
