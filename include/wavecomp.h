@@ -169,16 +169,19 @@ int wv_set_ae_exceptions(wv_ctx* ctx, int32_t k_per_step);
  * exception patches; it is allocated at the first such call, within the memory
  * budget together with the forward store (WV_ENOMEM beyond it). The Gauss-Newton
  * product itself does not read these states (wv_decode_delta returns them).
- * enable = 0 frees the store, and also the incremental time store that the
- * full-Newton product of WV_STORE_AE_TIME allocates. Other modes ignore the
- * setting. */
+ * enable = 0 frees the store. In WV_STORE_AE_TIME the same setting keeps de_n
+ * (e only) in an incremental time store of the forward store's layout; the
+ * full-Newton product fills that store in any case, and enable = 0 frees it too.
+ * Other modes ignore the setting. */
 int wv_set_delta_storage(wv_ctx* ctx, int32_t enable);
 
 /* Decompress the stored incremental state dx_n (1 <= n <= T-1) of every source
  * into state [S][4][N] (device): the fields whose bit is set in field_mask (bit f
  * = field f: e, v_z, v_y, v_x; others untouched), the exception patches of e
- * exact. WV_ESTATE when the last incremental forward stored none (or a forward
- * solve ran since); WV_EINVAL for a bad mask or NULL state. */
+ * exact. In WV_STORE_AE_TIME only e is stored (field_mask must be 1): its window
+ * is decompressed whole, the exception vectors exact. WV_ESTATE when the last
+ * incremental forward stored none (or a forward solve ran since); WV_EINVAL for a
+ * bad mask, a level outside [1, T-1] (time store) or NULL state. */
 int wv_decode_delta(wv_ctx* ctx, int32_t n, uint32_t field_mask, float* state);
 
 /* Bytes of history storage the current mode holds (after wv_set_storage), plus

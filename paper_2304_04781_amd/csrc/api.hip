@@ -1275,7 +1275,15 @@ int wv_decode_delta(wv_ctx* c, int32_t n, uint32_t field_mask, float* state)
 {
     return guarded([&]() -> int {
         WV_REQUIRE(c && state && field_mask != 0 && field_mask < 16, WV_EINVAL, "bad argument");
-        WV_REQUIRE(is_ae(c->mode) && c->delta_ok, WV_ESTATE, "no incremental states stored");
+        WV_REQUIRE((is_ae(c->mode) && c->delta_ok) || (is_time(c->mode) && c->tdelta_ok), WV_ESTATE,
+                   "no incremental states stored");
+        if (is_time(c->mode)) {
+            WV_REQUIRE(field_mask == 1u, WV_EINVAL, "the time store holds e only (field mask 1)");
+            WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_EINVAL, "level outside [1, T-1]");
+            const float* de = time_e(c, c->tds, n, -1);
+            for (int s = 0; s < c->S; ++s) launch_copy(state + (long long)s * 4 * c->N, de + s * c->N, c->N, c->st);
+            return WV_OK;
+        }
         decode_state(c, c->ds, n, field_mask, state, 4 * c->N, c->st);
         return WV_OK;
     });
@@ -1466,7 +1474,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         c->delta_bytes = bytes;
     }
     // time store of de^1 .. de^{T-1}: same network, block layout and exception count
-    const bool keep_time = keep_de && !snap && is_time(c->mode);
+    const bool keep_time = (keep_de || c->store_delta) && !snap && is_time(c->mode);
     c->tdelta_ok = false;
     if (keep_time) {
         if (!c->tds.lat) {

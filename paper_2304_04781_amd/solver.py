@@ -67,7 +67,7 @@ class WaveSolver:
         return L.wv_stats(self.ctx)
 
     def set_delta_storage(self, enable: bool = True) -> None:
-        """Also compress the incremental forward states (AE modes) in hessvec / inc_forward."""
+        """Also compress the incremental forward states (AE modes; e only in the time mode) in hessvec / inc_forward."""
         L.wv_set_delta_storage(self.ctx, enable)
 
     def decode_delta(self, n: int, field_mask: int = 0xF):

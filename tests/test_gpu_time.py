@@ -326,3 +326,40 @@ def test_time_newton_cg_full_newton_equals_full_storage():
     assert it0 == it1 == 2
     assert torch.equal(c0, c1)
     assert [r["cost"] for r in log0] == [r["cost"] for r in log1]
+
+
+def test_time_incremental_store_matches_oracle():
+    """wv_set_delta_storage in the time mode: the Gauss-Newton product also keeps de
+    in an incremental time store (the product itself unchanged bit for bit, the
+    store doubled). With every vector exact each decoded de_n equals the oracle's
+    incremental e to float32 accuracy, at window edges and in the short last
+    window; de_1 = 0; only field mask 1 is accepted."""
+    p = time_problem(75)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    net = Net(W.ae_init(seed=4))
+    B = 8 * 8 * 10
+    dc = np.asarray(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 4.0, 3), np.float32).astype(np.float64)
+    Hs, bytes_ = [], []
+    for keep in (False, True):
+        s = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s.ctx, B)
+        s.set_storage(L.STORE_AE_TIME, ae=net)
+        s.set_delta_storage(keep)
+        s.gradient(p.c_start, p.wavelet, d, sigma)
+        b0 = s.storage_bytes()
+        Hs.append(s.hessvec(p.c_start, dc))
+        bytes_.append((b0, s.storage_bytes()))
+    assert torch.equal(Hs[0], Hs[1])
+    assert bytes_[0][1] == bytes_[0][0] and bytes_[1][1] == 2 * bytes_[1][0]
+    _, e_hist, _, _ = ow.forward(sol, p.c_start, p.wavelet, p.src, p.rec, src_w=p.src_w)
+    _, de_hist = ow.inc_forward(sol, p.c_start, dc, e_hist[0], p.rec, store_e=True)
+    assert not s.decode_delta(1, 1)[0, 0].any()
+    for n in (2, 32, 33, 64, 65, 74):
+        de = s.decode_delta(n, 1)[0, 0].cpu().numpy()
+        assert np.linalg.norm(de_hist[n]) > 0
+        err = rel(de, de_hist[n])
+        print("de", n, err, flush=True)
+        assert err < 1e-5, n
+    with pytest.raises(L.WvError):
+        s.decode_delta(10, 3)
