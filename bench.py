@@ -722,6 +722,17 @@ def main():
                     "frac_of_copy": round(kernels[dom]["GB/s"] / copy_gbs, 4),
                     "traffic": measured_traffic(dom), "mean_launch_us": round(kernels[dom]["us"], 2),
                     "algorithmic_bytes_per_launch": work}
+        if dom == "forward_stencil" and "encode" in kernels:
+            # context: during each forward step the side stream's encode reads the state the previous
+            # step wrote and writes its latents and (lo, r) pairs, so the HBM moved in the step's
+            # interval is both kernels' bytes (the exception selection and copy are small beside them)
+            enc = 16.0 * N + P * (32 * 2 + 8 * 4)
+            step = work + enc
+            gbs = step / (kernels[dom]["us"] * 1e-6) / 1e9
+            roofline["with_side_stream"] = {"kernels": "forward_stencil + encode (side stream)",
+                                            "bytes_per_step": step, "achieved": round(gbs, 1),
+                                            "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                            "frac_of_copy": round(gbs / copy_gbs, 4)}
     else:
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(kernels[dom]["TFLOP/s"], 1),
                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(kernels[dom]["frac_mfma_bf16"], 4),
