@@ -62,6 +62,10 @@ def parse():
                     help="a short MAP inversion at 256^3 x 2000 (prior-preconditioned Gauss-Newton CG) with the "
                          "AE store and with checkpointing: wall time, Hv count, cost and model error")
     ap.add_argument("--inv-iters", type=int, default=5)
+    ap.add_argument("--hv384", action="store_true",
+                    help="the 384^3 x 3000 Gauss-Newton Hv with both histories compressed vs checkpointing")
+    ap.add_argument("--hv-nt", type=int, default=3000)
+    ap.add_argument("--hv-epochs", type=int, default=10)
     ap.add_argument("--inv-store", choices=["space", "time"], default="space",
                     help="compressed store of the inversion: space patches (bf16) or time windows")
     ap.add_argument("--time", action="store_true",
@@ -415,6 +419,86 @@ def inversion_pass(args):
     print(json.dumps(out), flush=True)
 
 
+def hv384_pass(args):
+    """The Gauss-Newton workload: 384^3 x 3000 steps, direction c * GRF(12 cells). Hv with the
+    forward and incremental forward states both stored as bf16 latents (1 % exact patches) against
+    the checkpointed Hv (64 slots, incremental forward recomputed beside the companion forward).
+    The network is trained on every 60th state of the forward solve at c_start."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd import compressor as C
+    from paper_2304_04781_amd.solver import WaveSolver
+    L.load()
+    dev = torch.device("cuda", 0)
+    p = W.problem_384(args.hv_nt)
+    T = p.nt
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    c = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    u = torch.tensor(p.c_start * W.direction_grf(p.c_start.shape, 12.0, 2), dtype=torch.float32, device=dev)
+    d = torch.zeros((len(p.src), T, len(p.rec)), dtype=torch.float32, device=dev)
+    sigma = 1.0  # the GN Hv depends on the data only through the weight dt / sigma^2
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    every = 60
+    ncap = (T - 1) // every
+    info = C.train_from_forward(s, net, c, wav, every=every, epochs=args.hv_epochs, batch=args.batch,
+                                perms=W.shuffles(ncap * P, args.hv_epochs, seed=5))
+    s.close()
+    torch.cuda.empty_cache()
+    log(f"training {info}")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed_hv(sol):
+        runs, H = [], None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            ev0.record()
+            H = sol.hessvec(c, u)
+            ev1.record()
+            torch.cuda.synchronize()
+            runs.append(ev0.elapsed_time(ev1) / 1e3)
+        return H, runs
+
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
+    ck.gradient(c, wav, d, sigma)
+    H_ck, runs_ck = timed_hv(ck)
+    ck_bytes = ck.storage_bytes()
+    ck.close()
+    log(f"checkpointed Hv {runs_ck}")
+    ae = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(ae.ctx, int(round(args.exceptions * P)))
+    ae.set_storage(L.STORE_AE_BF16, ae=net)
+    ae.set_delta_storage(True)
+    ae.gradient(c, wav, d, sigma)
+    fwd_bytes = ae.storage_bytes()
+    H_ae, runs_ae = timed_hv(ae)
+    both_bytes = ae.storage_bytes()
+    ae.set_timing(2)
+    ae.hessvec(c, u)
+    torch.cuda.synchronize()
+    kt = {k: (round(us, 1), n) for k, (us, n) in ae.kernel_times().items() if n}
+    ae.set_timing(0)
+    log(f"AE Hv kernel times (us, launches timed): {kt}")
+    ha, hc = H_ae.double(), H_ck.double()
+    out = {"workload": f"{p.name}: Gauss-Newton Hv, forward and incremental states as bf16 latents "
+                       f"({int(round(args.exceptions * P))} exact patches per state) vs revolve checkpointing "
+                       f"({args.checkpoints} slots)",
+           "train_s": info["train_s"], "hessvec_ae_s": round(min(runs_ae), 4), "runs_ae_s": [round(x, 4) for x in runs_ae],
+           "hessvec_checkpoint_s": round(min(runs_ck), 4), "runs_checkpoint_s": [round(x, 4) for x in runs_ck],
+           "speedup_vs_checkpoint": round(min(runs_ck) / min(runs_ae), 4),
+           "hv_rel_err_vs_checkpoint": round(float(torch.linalg.norm(ha - hc) / torch.linalg.norm(hc)), 5),
+           "hv_cos_vs_checkpoint": round(float(torch.sum(ha * hc) / torch.linalg.norm(ha) / torch.linalg.norm(hc)), 6),
+           "store_GB": {"forward": round(fwd_bytes / 1e9, 2), "incremental": round((both_bytes - fwd_bytes) / 1e9, 2),
+                        "checkpoints": round(ck_bytes / 1e9, 2)},
+           "ae_kernel_us": kt}
+    ae.close()
+    print(json.dumps(out), flush=True)
+
+
 def time_pass(args):
     """The time-compression scheme (e on 4^3 blocks x 32 levels) on the 256^3 x 2000 gradient workload."""
     import torch
@@ -517,6 +601,9 @@ def main():
         return
     if args.inversion:
         inversion_pass(args)
+        return
+    if args.hv384:
+        hv384_pass(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

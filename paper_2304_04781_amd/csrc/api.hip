@@ -256,6 +256,8 @@ struct wv_ctx {
     hipEvent_t ev_ready[NEB] = {};  // side: e^k decoded into ebuf slot
     hipEvent_t ev_free[NEB] = {};   // main: ebuf slot consumed
     hipEvent_t ev_join = nullptr;
+    hipEvent_t ev_dstep[2] = {};    // main: dx_n written (n mod 2), incremental forward
+    hipEvent_t ev_dstored[2] = {};  // dx_n stored on the side stream: its buffer is free
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -429,10 +431,11 @@ void adj_step(wv_ctx* c, const float* in, float* out, int k, const float* resid,
 }
 
 void inc_step(wv_ctx* c, const float* in, float* out, int n, const float* en, long long enstride,
-              float* dtraces, float* e_extra = nullptr)
+              float* dtraces, float* e_extra = nullptr, float* mm = nullptr)
 {
     StepArgs a = base_args(c);
     a.e_extra = e_extra;
+    a.mm_out = mm;
     a.in = in;
     a.out = out;
     a.tidx = n;
@@ -642,11 +645,15 @@ void time_store_level(wv_ctx* c, TimeStore& T, int n)
     WV_HIP(hipEventRecord(T.ev_enc[b], s1));
 }
 
-// store x_n (n = 1..T-1) of every source on the main stream (full storage, or
-// the autoencoder store L without the forward step's min/max)
-void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
+// store x_n (n = 1..T-1) of every source on the main stream (full storage), or
+// into the autoencoder store L on stream st when given, with the per-patch
+// (min, max) partials mm of the step that wrote it when given
+// (else the encode computes them)
+void store_state(wv_ctx* c, LatStore& L, int n, const float* state, hipStream_t st = nullptr,
+                 const float* mm = nullptr)
 {
     if (n < 1 || n > c->T - 1) return;
+    if (!st) st = c->st;
     if (c->mode == WV_STORE_FULL) {
         for (int s = 0; s < c->S; ++s)
             WV_HIP(hipMemcpyAsync(c->ehist + ((long long)(n - 1) * c->S + s) * c->N, state + s * 4 * c->N,
@@ -656,20 +663,26 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state)
         time_store_level(c, c->ts, n);
     } else if (is_ae(c->mode)) {
         const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-        const int te = c->tm.begin(TM_ENCODE, c->st);
-        for (int s = 0; s < c->S; ++s)
-            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
-                            meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), c->st);
-        c->tm.end(te, c->st);
+        const int te = c->tm.begin(TM_ENCODE, st);
+        for (int s = 0; s < c->S; ++s) {
+            if (mm)
+                ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
+                                   ae_fmt(c->mode), lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s),
+                                   qs_slot(c, L, n - 1, s), st);
+            else
+                ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
+                                meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), st);
+        }
+        c->tm.end(te, st);
         if (c->K > 0) {
-            const int tx = c->tm.begin(TM_EXC_SELECT, c->st);
+            const int tx = c->tm.begin(TM_EXC_SELECT, st);
             for (int s = 0; s < c->S; ++s) {
                 const long long q = (long long)(n - 1) * c->S + s;
                 exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, L, n - 1, s), c->K, L.exc_idx + q * c->K,
-                                 L.exc + q * c->K * 512, c->st);
-                exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), c->st);
+                                 L.exc + q * c->K * 512, st);
+                exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), st);
             }
-            c->tm.end(tx, c->st);
+            c->tm.end(tx, st);
         }
     }
 }
@@ -1108,6 +1121,10 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
             WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
         }
         WV_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        for (int b = 0; b < 2; ++b) {
+            WV_HIP(hipEventCreateWithFlags(&c->ev_dstep[b], hipEventDisableTiming));
+            WV_HIP(hipEventCreateWithFlags(&c->ev_dstored[b], hipEventDisableTiming));
+        }
         c->tds.side = 1;
         for (TimeStore* T : {&c->ts, &c->tds})
             for (int b = 0; b < 2; ++b)
@@ -1131,7 +1148,8 @@ int wv_destroy(wv_ctx* c)
     free_store(c);
     free_tiling(c->tl);
     for (hipEvent_t e : {c->ev_step[0], c->ev_step[1], c->ev_step[2], c->ev_enc[0], c->ev_enc[1], c->ev_enc[2],
-                         c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_join})
+                         c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_join, c->ev_dstep[0],
+                         c->ev_dstep[1], c->ev_dstored[0], c->ev_dstored[1]})
         if (e) (void)hipEventDestroy(e);
     for (int b = 0; b < NEB; ++b) {
         if (c->ev_ready[b]) (void)hipEventDestroy(c->ev_ready[b]);
@@ -1489,6 +1507,15 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         c->tds.buf_w[0] = c->tds.buf_w[1] = -1;
         c->tds.cur_w = -1;
     }
+    // the incremental latent store is written on the second side stream, beside the
+    // steps and the decodes of e on the first: dx_{n+1} (in the buffer step n wrote)
+    // is encoded while step n + 1 runs, and step n + 2, which overwrites it, waits
+    const hipStream_t sd = keep_delta ? side_stream(c, 1) : c->st;
+    const bool dasync = sd != c->st;
+    // the step writing dx_{n+1} also writes its per-patch (min, max) partials into
+    // slot (n + 1) % 2 of the forward store's partial buffer, for the encode
+    const bool dmm = keep_delta && c->mmpart && c->has_y;
+    const long long mm_stride = (long long)c->S * c->P * c->H * 8;
     if (pipe) pipe_start(c);
     launch_fill(ebuf_slot(c, 0), c->N * c->S, 0.f, c->st);  // e^0 = 0
     float* din = c->incb[0];
@@ -1520,11 +1547,20 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
             en = load_e(c, n, &stride, +1);
         }
         float* dew = keep_time && n + 1 <= c->T - 1 ? time_slot(c, c->tds, n + 1) : nullptr;
-        inc_step(c, din, dout, n, en, stride, c->dtr, dew);
+        if (dasync && n >= 2) wait_event(c->st, c->ev_dstored[(n - 1) & 1]);  // dout held dx_{n-1}
+        float* dmmp = dmm && n + 1 <= c->T - 1 ? c->mmpart + ((n + 1) & 1) * mm_stride : nullptr;
+        inc_step(c, din, dout, n, en, stride, c->dtr, dew, dmmp);
         if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
         if (keep_time) time_store_level(c, c->tds, n + 1);
-        if (keep_delta) store_state(c, c->ds, n + 1, din);  // dx_{n+1}, read again only by the step after next
+        if (keep_delta && n + 1 <= c->T - 1) {
+            if (dasync) {
+                WV_HIP(hipEventRecord(c->ev_dstep[(n + 1) & 1], c->st));
+                wait_event(sd, c->ev_dstep[(n + 1) & 1]);
+            }
+            store_state(c, c->ds, n + 1, din, sd, dmmp);
+            if (dasync) WV_HIP(hipEventRecord(c->ev_dstored[(n + 1) & 1], sd));
+        }
         if (keep_full && n + 1 <= c->T - 1)
             for (int s = 0; s < c->S; ++s)
                 WV_HIP(hipMemcpyAsync(c->dehist + ((long long)n * c->S + s) * c->N, din + s * 4 * c->N,
@@ -1537,6 +1573,7 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         }
     }
     if (ckpt) c->last_fwd_steps = c->T;
+    if (dasync) join_side(c);  // the reverse sweep decodes the incremental store on the main stream
     if (keep_delta) c->delta_ok = true;
     if (keep_time) c->tdelta_ok = true;
     return prev;

@@ -93,7 +93,8 @@ __device__ __forceinline__ void st_plane(float v, float* base, unsigned bytes, u
 #define WV_PF 1
 #endif
 
-// MM: also write the per-patch (min, max) partials of the new state (forward only);
+// MM: also write the per-patch (min, max) partials of the new state (forward and
+// incremental forward);
 // ACC: the adjoint's gradient accumulation phase; EX: also write the new e to
 // a.e_extra (forward and incremental forward: the time-compression window slot
 // of this level)
@@ -341,7 +342,7 @@ __global__ void __launch_bounds__(BX* BY)
     }
 
     // running (min, max) of the 4 new fields over the current patch layer
-    constexpr bool want_mm = MM && MODE == MODE_FWD && HAS_Y;
+    constexpr bool want_mm = MM && (MODE == MODE_FWD || MODE == MODE_INC) && HAS_Y;
     float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mn3 = INFINITY;
     float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY, mx3 = -INFINITY;
 
@@ -544,7 +545,7 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
         a.kc = a.kc_adj;
         a.chunks_z = a.chunks_adj;
     }
-    if (mode != MODE_FWD || !HAS_Y) a.mm_out = nullptr;
+    if ((mode != MODE_FWD && mode != MODE_INC) || !HAS_Y) a.mm_out = nullptr;
     if (mode != MODE_FWD && mode != MODE_INC) a.e_extra = nullptr;
     dim3 grid(a.tiles_x * a.tiles_y * a.chunks_z, nsrc);
     dim3 block(BX * BY);
@@ -562,7 +563,9 @@ void launch_mode(int mode, const StepArgs& a0, int nsrc, hipStream_t st)
     case MODE_ADJQ: launch_adj<BX, BY, MODE_ADJQ, HAS_Y>(a, grid, block, st); break;
     case MODE_ADJD: launch_adj<BX, BY, MODE_ADJD, HAS_Y>(a, grid, block, st); break;
     default:
-        if (a.e_extra)
+        if (HAS_Y && a.mm_out)
+            hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, HAS_Y>), grid, block, 0, st, a);
+        else if (a.e_extra)
             hipLaunchKernelGGL((wave_step_kernel<BX, BY, MODE_INC, HAS_Y, false, ACC_EACH, true>), grid, block, 0,
                                st, a);
         else
