@@ -203,7 +203,7 @@ struct wv_ctx {
     float* wavelet = nullptr;
     float* work[3] = {nullptr, nullptr, nullptr};  // [2]: only for autoencoder stores
     float* adj[2] = {nullptr, nullptr};
-    float* incb[2] = {nullptr, nullptr};
+    float* incb[3] = {nullptr, nullptr, nullptr};  // the third only while an incremental store runs beside
     float* acc = nullptr;
     float* blk = nullptr;        // [S][N] float32 partial gradient of a block of adjoint steps
     float* ebuf = nullptr;       // [NEB][S][N]: decoded e, one slot per state in flight
@@ -248,16 +248,20 @@ struct wv_ctx {
     // x_j (and decodes e^k for the reverse sweeps), `side2` selects and copies the
     // exception patches of x_j. Forward states rotate through three buffers, so
     // the store of x_j may take until the step that overwrites x_j, two later.
+    // The incremental forward's latent store encodes dx_n on `side3` (the decodes of
+    // e^n are on `side`) and selects and copies its exception patches on `side2`.
     hipStream_t side = nullptr;
     hipStream_t side2 = nullptr;
+    hipStream_t side3 = nullptr;
     hipEvent_t ev_step[3] = {};    // main: x_j written (j mod 3)
     hipEvent_t ev_enc[3] = {};     // side: x_j encoded
     hipEvent_t ev_stored[3] = {};  // x_j fully stored: its buffer and mmpart slot are free
     hipEvent_t ev_ready[NEB] = {};  // side: e^k decoded into ebuf slot
     hipEvent_t ev_free[NEB] = {};   // main: ebuf slot consumed
     hipEvent_t ev_join = nullptr;
-    hipEvent_t ev_dstep[2] = {};    // main: dx_n written (n mod 2), incremental forward
-    hipEvent_t ev_dstored[2] = {};  // dx_n stored on the side stream: its buffer is free
+    hipEvent_t ev_dstep[3] = {};    // main: dx_n written (n mod 3), incremental forward
+    hipEvent_t ev_denc[3] = {};     // dx_n encoded
+    hipEvent_t ev_dstored[3] = {};  // dx_n fully stored: its buffer and partial slot are free
     long long P = 0;
     long long lat_bytes = 0;     // per patch
     int64_t store_bytes = 0;
@@ -614,6 +618,40 @@ void alloc_latstore(wv_ctx* c, LatStore& L, int mode, int K)
 void wait_event(hipStream_t st, hipEvent_t ev);
 hipStream_t side_stream(wv_ctx* c, int which);
 
+// encode x_n of every source into the autoencoder store L on stream st, with the
+// per-patch (min, max) partials mm of the step that wrote it when given (else the
+// encode computes them)
+void encode_state_into(wv_ctx* c, LatStore& L, int n, const float* state, hipStream_t st, const float* mm)
+{
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    const int te = c->tm.begin(TM_ENCODE, st);
+    for (int s = 0; s < c->S; ++s) {
+        if (mm)
+            ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
+                               ae_fmt(c->mode), lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s),
+                               qs_slot(c, L, n - 1, s), st);
+        else
+            ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
+                            meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), st);
+    }
+    c->tm.end(te, st);
+}
+
+// select and copy the exception patches of x_n (after its encode wrote the ranges)
+void exceptions_into(wv_ctx* c, LatStore& L, int n, const float* state, hipStream_t st)
+{
+    if (c->K <= 0) return;
+    const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+    const int tx = c->tm.begin(TM_EXC_SELECT, st);
+    for (int s = 0; s < c->S; ++s) {
+        const long long q = (long long)(n - 1) * c->S + s;
+        exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, L, n - 1, s), c->K, L.exc_idx + q * c->K,
+                         L.exc + q * c->K * 512, st);
+        exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), st);
+    }
+    c->tm.end(tx, st);
+}
+
 // Window slot of level j (1..T-1) in store T, for the step about to write it.
 // The buffer held window w - 2, whose compression must have read it first.
 float* time_slot(wv_ctx* c, TimeStore& T, int j)
@@ -662,28 +700,8 @@ void store_state(wv_ctx* c, LatStore& L, int n, const float* state, hipStream_t 
         (void)state;  // the forward step wrote e^n into its window slot
         time_store_level(c, c->ts, n);
     } else if (is_ae(c->mode)) {
-        const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-        const int te = c->tm.begin(TM_ENCODE, st);
-        for (int s = 0; s < c->S; ++s) {
-            if (mm)
-                ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
-                                   ae_fmt(c->mode), lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s),
-                                   qs_slot(c, L, n - 1, s), st);
-            else
-                ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
-                                meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), st);
-        }
-        c->tm.end(te, st);
-        if (c->K > 0) {
-            const int tx = c->tm.begin(TM_EXC_SELECT, st);
-            for (int s = 0; s < c->S; ++s) {
-                const long long q = (long long)(n - 1) * c->S + s;
-                exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, L, n - 1, s), c->K, L.exc_idx + q * c->K,
-                                 L.exc + q * c->K * 512, st);
-                exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), st);
-            }
-            c->tm.end(tx, st);
-        }
+        encode_state_into(c, L, n, state, st, mm);
+        exceptions_into(c, L, n, state, st);
     }
 }
 
@@ -708,6 +726,7 @@ void wait_event(hipStream_t st, hipEvent_t ev)
 hipStream_t side_stream(wv_ctx* c, int which)
 {
     const int mode = (WV_OVERLAP == 1 && c->S > 1) ? 2 : WV_OVERLAP;
+    if (which == 2) return mode == 1 ? c->side3 : c->st;
     if (which) return mode >= 1 ? c->side2 : c->st;
     return mode == 1 ? c->side : c->st;
 }
@@ -754,7 +773,7 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
 // make the main stream wait for everything queued on the side streams
 void join_side(wv_ctx* c)
 {
-    for (hipStream_t st : {c->side, c->side2}) {
+    for (hipStream_t st : {c->side, c->side2, c->side3}) {
         WV_HIP(hipEventRecord(c->ev_join, st));
         WV_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
     }
@@ -1111,6 +1130,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->dresid = dev_alloc<float>(ntr);
         WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         WV_HIP(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
+        WV_HIP(hipStreamCreateWithFlags(&c->side3, hipStreamNonBlocking));
         for (int b = 0; b < 3; ++b) {
             WV_HIP(hipEventCreateWithFlags(&c->ev_step[b], hipEventDisableTiming));
             WV_HIP(hipEventCreateWithFlags(&c->ev_enc[b], hipEventDisableTiming));
@@ -1121,10 +1141,9 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
             WV_HIP(hipEventCreateWithFlags(&c->ev_free[b], hipEventDisableTiming));
         }
         WV_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        for (int b = 0; b < 2; ++b) {
-            WV_HIP(hipEventCreateWithFlags(&c->ev_dstep[b], hipEventDisableTiming));
-            WV_HIP(hipEventCreateWithFlags(&c->ev_dstored[b], hipEventDisableTiming));
-        }
+        for (int b = 0; b < 3; ++b)
+            for (hipEvent_t* e : {&c->ev_dstep[b], &c->ev_denc[b], &c->ev_dstored[b]})
+                WV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         c->tds.side = 1;
         for (TimeStore* T : {&c->ts, &c->tds})
             for (int b = 0; b < 2; ++b)
@@ -1144,12 +1163,14 @@ int wv_destroy(wv_ctx* c)
     (void)hipStreamSynchronize(c->st);
     if (c->side) (void)hipStreamSynchronize(c->side);
     if (c->side2) (void)hipStreamSynchronize(c->side2);
+    if (c->side3) (void)hipStreamSynchronize(c->side3);
     c->tm.destroy();
     free_store(c);
     free_tiling(c->tl);
     for (hipEvent_t e : {c->ev_step[0], c->ev_step[1], c->ev_step[2], c->ev_enc[0], c->ev_enc[1], c->ev_enc[2],
                          c->ev_stored[0], c->ev_stored[1], c->ev_stored[2], c->ev_join, c->ev_dstep[0],
-                         c->ev_dstep[1], c->ev_dstored[0], c->ev_dstored[1]})
+                         c->ev_dstep[1], c->ev_dstep[2], c->ev_denc[0], c->ev_denc[1], c->ev_denc[2],
+                         c->ev_dstored[0], c->ev_dstored[1], c->ev_dstored[2]})
         if (e) (void)hipEventDestroy(e);
     for (int b = 0; b < NEB; ++b) {
         if (c->ev_ready[b]) (void)hipEventDestroy(c->ev_ready[b]);
@@ -1161,12 +1182,13 @@ int wv_destroy(wv_ctx* c)
                 if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->side2) (void)hipStreamDestroy(c->side2);
+    if (c->side3) (void)hipStreamDestroy(c->side3);
     dev_free(c->tab);
     dev_free(c->src_kji);
     dev_free(c->src_w);
     for (float** p : {&c->m, &c->c_last, &c->wavelet, &c->work[0], &c->work[1], &c->adj[0], &c->adj[1],
-                      &c->incb[0], &c->incb[1], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces, &c->resid, &c->dtr,
-                      &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf,
+                      &c->incb[0], &c->incb[1], &c->incb[2], &c->acc, &c->blk, &c->ebuf, &c->dm, &c->traces,
+                      &c->resid, &c->dtr, &c->dresid, &c->adj2[0], &c->adj2[1], &c->dacc, &c->dblk, &c->qbuf, &c->dehist, &c->dbuf,
                       &c->prior_c0, &c->prior_w, &c->nvec, &c->pvec})
         dev_free(*p);
     dev_free(c->partial);
@@ -1507,13 +1529,15 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
         c->tds.buf_w[0] = c->tds.buf_w[1] = -1;
         c->tds.cur_w = -1;
     }
-    // the incremental latent store is written on the second side stream, beside the
-    // steps and the decodes of e on the first: dx_{n+1} (in the buffer step n wrote)
-    // is encoded while step n + 1 runs, and step n + 2, which overwrites it, waits
-    const hipStream_t sd = keep_delta ? side_stream(c, 1) : c->st;
-    const bool dasync = sd != c->st;
-    // the step writing dx_{n+1} also writes its per-patch (min, max) partials into
-    // slot (n + 1) % 2 of the forward store's partial buffer, for the encode
+    // The incremental latent store runs beside the steps (and the decodes of e):
+    // dx_j is encoded on `se` and its exception patches selected and copied on `sx`.
+    // The states then rotate through three buffers, so the store of dx_j may take
+    // until the step that overwrites it, two steps later.
+    const hipStream_t se = side_stream(c, 2), sx = side_stream(c, 1);
+    const bool dasync = keep_delta && (se != c->st || sx != c->st);
+    if (dasync && !c->incb[2]) c->incb[2] = dev_alloc<float>(c->state_floats());
+    // the step writing dx_j also writes its per-patch (min, max) partials into slot
+    // j % 3 of the forward store's partial buffer, for the encode
     const bool dmm = keep_delta && c->mmpart && c->has_y;
     const long long mm_stride = (long long)c->S * c->P * c->H * 8;
     if (pipe) pipe_start(c);
@@ -1547,19 +1571,29 @@ float* inc_forward_sweep(wv_ctx* c, const float* cdev, const float* dc, const st
             en = load_e(c, n, &stride, +1);
         }
         float* dew = keep_time && n + 1 <= c->T - 1 ? time_slot(c, c->tds, n + 1) : nullptr;
-        if (dasync && n >= 2) wait_event(c->st, c->ev_dstored[(n - 1) & 1]);  // dout held dx_{n-1}
-        float* dmmp = dmm && n + 1 <= c->T - 1 ? c->mmpart + ((n + 1) & 1) * mm_stride : nullptr;
+        if (dasync) {
+            din = c->incb[n % 3];
+            dout = c->incb[(n + 1) % 3];
+            if (n >= 3) wait_event(c->st, c->ev_dstored[(n - 2) % 3]);  // dout held dx_{n-2}
+        }
+        float* dmmp = dmm && n + 1 <= c->T - 1 ? c->mmpart + ((n + 1) % 3) * mm_stride : nullptr;
         inc_step(c, din, dout, n, en, stride, c->dtr, dew, dmmp);
         if (pipe) pipe_release(c, n % NEB);
         std::swap(din, dout);
         if (keep_time) time_store_level(c, c->tds, n + 1);
         if (keep_delta && n + 1 <= c->T - 1) {
+            const int j = n + 1, b = j % 3;
             if (dasync) {
-                WV_HIP(hipEventRecord(c->ev_dstep[(n + 1) & 1], c->st));
-                wait_event(sd, c->ev_dstep[(n + 1) & 1]);
+                WV_HIP(hipEventRecord(c->ev_dstep[b], c->st));
+                wait_event(se, c->ev_dstep[b]);
+                encode_state_into(c, c->ds, j, din, se, dmmp);
+                WV_HIP(hipEventRecord(c->ev_denc[b], se));
+                wait_event(sx, c->ev_denc[b]);
+                exceptions_into(c, c->ds, j, din, sx);
+                WV_HIP(hipEventRecord(c->ev_dstored[b], sx));
+            } else {
+                store_state(c, c->ds, j, din, c->st, dmmp);
             }
-            store_state(c, c->ds, n + 1, din, sd, dmmp);
-            if (dasync) WV_HIP(hipEventRecord(c->ev_dstored[(n + 1) & 1], sd));
         }
         if (keep_full && n + 1 <= c->T - 1)
             for (int s = 0; s < c->S; ++s)
