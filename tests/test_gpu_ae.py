@@ -347,6 +347,35 @@ def test_full_newton_hessvec_from_compressed_stores():
     assert torch.equal(H, H0)
 
 
+def test_full_newton_two_sources_incremental_store_exact():
+    """Two sources (encodes on the main stream, exception patches selected and copied
+    on a side stream, incremental states in three rotating buffers): with every
+    patch exact the full-Newton and Gauss-Newton products with the incremental
+    store kept equal the full-storage ones bit for bit."""
+    p = ae_problem(nt=60, shape=(32, 32, 40))
+    p.src = np.array([[4, 16, 20], [6, 12, 28]], dtype=np.int32)
+    p.wavelet = np.stack([p.wavelet[0], 0.6 * W.ricker(11.0, p.dt, p.nt) / p.dx ** 3]).astype(np.float32)
+    p.wavelet = p.wavelet.astype(np.float64)
+    p.noise = np.random.default_rng(1).standard_normal((2, p.nt, len(p.rec)))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    dc = np.asarray(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2), np.float32).astype(np.float64)
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    full.gradient(p.c_start, p.wavelet, d, sigma)
+    F0 = full.hessvec(p.c_start, dc, gauss_newton=False)
+    G0 = full.hessvec(p.c_start, dc)
+    s = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(s.ctx, 4 * 4 * 5)
+    s.set_storage(L.STORE_AE_BF16, ae=raw)
+    s.set_delta_storage(True)
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    for _ in range(2):
+        assert torch.equal(s.hessvec(p.c_start, dc, gauss_newton=False), F0)
+        assert torch.equal(s.hessvec(p.c_start, dc), G0)
+
+
 def test_full_newton_fp8_stores_reproducible():
     """FP8 latents without exception patches: the incremental forward decodes e on
     a side stream while it encodes the incremental states on the main stream, each
