@@ -2,6 +2,7 @@
 Sec. 3.1 layout, Sec. 3.3 dense network and training, Sec. 3.3.1
 normalisation; Sec. 1 checkpointing)."""
 import math
+import struct
 
 import numpy as np
 import pytest
@@ -168,15 +169,171 @@ def test_linear_autoencoder_reaches_pca_optimum():
     ev = np.sort(np.linalg.eigvalsh(np.cov(Y.T, bias=True)))[::-1]
     opt_mse = ev[lat:].sum() / n
     ae = oae.AE(W.ae_init(n, 8, lat, seed=6), act="identity")
-    perms = np.tile(np.arange(ns), (1, 1))
-    opt = oae.Adam(ae.p, lr=1e-2)
-    for it in range(6000):
-        lr = 1e-2 if it < 3000 else (3e-3 if it < 5000 else 1e-3)
-        loss, g = ae.loss_and_grads(Y)
-        opt.step(ae.p, g, lr=lr)
+    # the oracle's own training loop: full-batch epochs, rate 1e-2 cut to 3e-3
+    # and 9e-4 after 2000 and 4000 epochs
+    perms = np.tile(np.arange(ns), (6000, 1))
+    oae.train(ae, Y, perms, batch=ns, lr=1e-2, decay_every=2000, decay=0.3)
     loss, _ = ae.loss_and_grads(Y)
     assert loss >= opt_mse * (1 - 1e-9)
     assert loss <= opt_mse * 1.01
+
+
+def _bf16_torch(x: float) -> float:
+    """bfloat16 RNE of the float32 RNE of x, by torch's CPU casts."""
+    return float(torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64))
+
+
+def _f32_struct(x: float) -> float:
+    return struct.unpack("f", struct.pack("f", x))[0]
+
+
+def _e4m3_torch(x: float) -> float:
+    return float(torch.tensor(x, dtype=torch.float64).to(torch.float8_e4m3fn).to(torch.float64))
+
+
+def _hand_chain(prm, Y, latent="bf16", act=True):
+    """The HIP path's precision contract applied by hand, one scalar at a time:
+    y, weights, hidden activations and the latent rounded to bfloat16 (torch
+    casts), biases and the latent and output to float32 (struct), exact sums
+    (math.fsum), GELU from math.erf."""
+    gel = (lambda a: 0.5 * a * (1.0 + math.erf(a / math.sqrt(2.0)))) if act else (lambda a: a)
+    Wq = {k: [[_bf16_torch(v) for v in row] for row in prm[k]] for k in ("W1", "W2", "W3", "W4")}
+    bq = {k: [_f32_struct(v) for v in prm[k]] for k in ("b1", "b2", "b3", "b4")}
+    i, h = len(Wq["W1"]), len(Wq["W1"][0])
+    l = len(Wq["W2"][0])
+    out = {k: [] for k in ("y", "a1", "h1", "z", "zq", "a3", "h3", "yhat")}
+    for row in Y:
+        y = [_bf16_torch(v) for v in row]
+        a1 = [math.fsum(y[q] * Wq["W1"][q][j] for q in range(i)) + bq["b1"][j] for j in range(h)]
+        h1 = [_bf16_torch(gel(a)) for a in a1]
+        z = [math.fsum(h1[q] * Wq["W2"][q][j] for q in range(h)) + bq["b2"][j] for j in range(l)]
+        zf = [_f32_struct(v) for v in z]
+        if latent == "bf16":
+            zq = [_bf16_torch(v) for v in zf]
+        else:
+            s = max(abs(v) for v in zf)
+            s = _f32_struct(s / 448.0) if s > 0 else 1.0
+            zq = [_bf16_torch(_e4m3_torch(_f32_struct(v / s)) * s) for v in zf]
+        a3 = [math.fsum(zq[q] * Wq["W3"][q][j] for q in range(l)) + bq["b3"][j] for j in range(h)]
+        h3 = [_bf16_torch(gel(a)) for a in a3]
+        yh = [_f32_struct(math.fsum(h3[q] * Wq["W4"][q][j] for q in range(h)) + bq["b4"][j]) for j in range(i)]
+        for k, v in (("y", y), ("a1", a1), ("h1", h1), ("z", z), ("zq", zq), ("a3", a3), ("h3", h3), ("yhat", yh)):
+            out[k].append(v)
+    return {k: np.array(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("latent", ["bf16", "fp8"])
+def test_emulated_chain_equals_hand_rounding(latent):
+    """Every rounding point of the emulation mode, checked against the contract
+    applied by hand on a tiny network (8 -> 6 -> 3 -> 6 -> 8): rounded quantities
+    (h1, latent, h3, output) bit for bit, unrounded pre-activations to float64
+    summation order. Dropping any rounding point (of y, a weight, a bias, a hidden
+    layer, the latent or the output) changes a compared quantity by far more than
+    that order."""
+    prm = W.ae_init(8, 6, 3, seed=21)
+    for k in prm:                       # weights of order 1 (the fan-ins are small)
+        prm[k] = prm[k] * (3.0 if k.startswith("W") else 1.0)
+    rng = np.random.default_rng(22)
+    Y = rng.random((5, 8))
+    hand = _hand_chain(prm, Y, latent)
+    ae = oae.AE(prm)
+    f = ae.forward(Y, emulate=True, latent=latent)
+    for k in ("y", "h1", "zq", "h3", "yhat"):
+        assert np.array_equal(f[k], hand[k]), k
+    assert np.array_equal(rd.f32(f["z"]), rd.f32(hand["z"]))
+    for k in ("a1", "z", "a3"):
+        assert np.allclose(f[k], hand[k], rtol=0, atol=1e-14 * np.abs(hand[k]).max()), k
+    # encode and decode (row subset) follow the same points
+    assert np.array_equal(ae.encode(Y, emulate=True), rd.f32(hand["z"]))
+    assert np.array_equal(ae.decode(hand["zq"], emulate=True), hand["yhat"])
+    assert np.array_equal(ae.decode(hand["zq"], emulate=True, rows=slice(2, 5)), hand["yhat"][:, 2:5])
+    # the test data exercises every rounding point: each omission moves a quantity
+    assert not np.array_equal(oae.AE(prm).forward(Y)["yhat"], hand["yhat"])
+    assert np.max(np.abs(np.asarray([_bf16_torch(v) for v in Y.ravel()]) - Y.ravel())) > 1e-4
+    Wd = max(abs(_bf16_torch(v) - v) for v in prm["W1"].ravel())
+    bd = max(abs(_f32_struct(v) - v) for v in prm["b1"].ravel())
+    assert Wd > 1e-4 and bd > 1e-12 > 1e-14 * np.abs(hand["a1"]).max()
+    assert np.max(np.abs(oae.gelu(hand["a1"]) - hand["h1"])) > 1e-4
+    assert np.max(np.abs(hand["z"] - hand["zq"])) > 1e-4
+    assert np.max(np.abs(oae.gelu(hand["a3"]) - hand["h3"])) > 1e-4
+    out_unrounded = hand["h3"] @ np.vectorize(_bf16_torch)(prm["W4"]) + np.vectorize(_f32_struct)(prm["b4"])
+    assert np.max(np.abs(out_unrounded - hand["yhat"])) > 1e-12
+
+
+def test_fp8_scale_rule_hand_rows():
+    """Per-row FP8 storage of the latents: s = max|z| / 448 (float32), s = 1 for a
+    zero row, codes e4m3(z / s). Rows worked out by hand."""
+    z = np.array([[448.0, -224.0, 1.0, 0.0],
+                  [3.5, -1.75, 0.875, 0.0],          # s = 2^-7: quotients 448, -224, 112, 0
+                  [0.0, 0.0, 0.0, 0.0],              # zero row: s = 1, all codes 0
+                  [2e-3, 1e-3, -5e-4, 7.77e-4]])     # quotients 448, 224, -112, 174.05 -> 176
+    codes, s = oae.fp8_quantize(z)
+    assert s.shape == (4,)
+    assert s[0] == 1.0 and s[1] == 2.0 ** -7 and s[2] == 1.0
+    assert s[3] == np.float32(2e-3 / 448.0)
+    # 448 = 1.75 * 2^8 -> (15 << 3) | 6; 224 -> (14 << 3) | 6; 1 -> 7 << 3;
+    # 112 -> (13 << 3) | 6; 176 = 1.375 * 2^7 -> (14 << 3) | 3; sign bit 0x80
+    assert codes.tolist() == [[0x7E, 0xF6, 0x38, 0x00],
+                              [0x7E, 0xF6, 0x6E, 0x00],
+                              [0x00, 0x00, 0x00, 0x00],
+                              [0x7E, 0x76, 0xEE, 0x73]]
+    back = oae.fp8_roundtrip(z)
+    assert np.array_equal(back[:3], z[:3])            # exactly representable after scaling
+    assert np.allclose(back[3], np.array([448.0, 224.0, -112.0, 176.0]) * s[3], rtol=0, atol=0)
+
+
+def test_fp8_row_maximum_maps_to_448():
+    """For any nonzero row the entry of largest magnitude is stored as +-448 times
+    the scale (code 0x7E or 0xFE), every value keeps its sign, and the round trip
+    is within the e4m3 half-spacing (2^-4 relative above 2^-6 s, 2^-10 s below)."""
+    rng = np.random.default_rng(23)
+    z = rng.standard_normal((200, 32)) * 10.0 ** rng.uniform(-8, 4, (200, 1))
+    codes, s = oae.fp8_quantize(z)
+    top = np.argmax(np.abs(z), axis=1)
+    c = codes[np.arange(200), top]
+    assert np.all((c == 0x7E) | (c == 0xFE))
+    assert np.all(np.sign(z[np.arange(200), top]) == np.where(c == 0x7E, 1.0, -1.0))
+    back = oae.fp8_roundtrip(z)
+    a = np.abs(z) / s[:, None]
+    bound = np.where(a >= 2.0 ** -6, 2.0 ** -4 * np.abs(z) * (1 + 1e-6), 2.0 ** -10 * s[:, None] * (1 + 1e-6))
+    assert np.all(np.abs(back - z) <= bound)
+    assert np.all((back == 0) | (np.sign(back) == np.sign(z)))
+
+
+def test_train_loop_schedule_and_dropped_batch():
+    """oracle.ae.train: epoch e visits perms[e] in batches, drops the last partial
+    batch, steps Adam at rate lr * decay^(e // decay_every) and reports each
+    epoch's mean batch loss; max_steps ends the loop early."""
+    class Probe:
+        def __init__(self):
+            self.p = {"w": np.zeros(1)}
+            self.batches = []
+
+        def loss_and_grads(self, Yb, emulate=False):
+            self.batches.append(Yb[:, 0].astype(int).tolist())
+            return float(Yb[:, 0].sum()), {"w": np.zeros(1)}
+
+    class Opt:
+        def __init__(self):
+            self.rates = []
+
+        def step(self, params, grads, lr=None):
+            self.rates.append(lr)
+
+    n, batch, epochs = 10, 4, 12
+    Y = np.arange(n, dtype=np.float64)[:, None]
+    perms = W.shuffles(n, epochs, seed=31)
+    probe, opt = Probe(), Opt()
+    losses, _ = oae.train(probe, Y, perms, batch, lr=1e-3, decay_every=5, decay=0.5, opt=opt)
+    expect = [perms[e][b * 4:(b + 1) * 4].tolist() for e in range(epochs) for b in range(2)]
+    assert probe.batches == expect                      # samples perm[8:10] never seen
+    assert opt.rates == [1e-3 * 0.5 ** (e // 5) for e in range(epochs) for _ in range(2)]
+    assert opt.rates[9] == 1e-3 and opt.rates[10] == 5e-4 and opt.rates[-1] == 2.5e-4
+    assert losses == [float(np.mean([sum(perms[e][:4]), sum(perms[e][4:8])])) for e in range(epochs)]
+    probe2, opt2 = Probe(), Opt()
+    losses2, _ = oae.train(probe2, Y, perms, batch, opt=opt2, max_steps=7)
+    assert len(probe2.batches) == 7 and len(losses2) == 4
+    assert losses2[3] == float(sum(perms[3][:4]))
 
 
 def test_emulated_forward_close_to_fp64():
