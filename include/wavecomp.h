@@ -405,6 +405,20 @@ int ae_time_decode(const ae_net* net, const wv_grid* grid, const uint16_t* laten
 int ae_encode(const ae_net* net, const wv_grid* grid, const float* state, int latent_fmt,
               void* latent, float* meta, float* qscale, void* stream);
 
+/* ae_encode for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results as ae_encode, bit for bit, but no allocation of any kind. The float32
+ * latents of an FP8 encode are staged in a static device array of 16 MiB that the
+ * library holds on each device it runs on until the process ends (its address is
+ * looked up at the first FP8 call on a device); bfloat16 latents need no staging.
+ * Limits: the fused network shape (hidden 512, latent 32, else WV_EINVAL) and, for
+ * AE_LATENT_FP8, P * latent * 4 <= 16 MiB, i.e. at most 131072 patches (WV_EINVAL
+ * beyond, before any work is queued). Every call on one device shares that
+ * device's array and nothing in it needs to start at zero; calls that overlap in
+ * time on one device (two streams, or two threads) race on it. */
+int ae_encode_noalloc(const ae_net* net, const wv_grid* grid, const float* state, int latent_fmt,
+                      void* latent, float* meta, float* qscale, void* stream);
+
 /* Decompress into state [4][N]: decoder, de-normalisation x = min + r y. Only
  * the fields whose bit is set in field_mask (bit f = field f) are computed and
  * written (the gradient needs only e, mask 1). */

@@ -77,6 +77,8 @@ EXPORTS = {
     "ae_normalize": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ae_encode": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p]),
+    "ae_encode_noalloc": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
     "ae_decode": (C.c_int, [C.c_void_p, C.POINTER(WvGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                             C.c_uint32, C.c_void_p, C.c_void_p]),
     "ae_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(AeTrainCfg), C.c_void_p,
@@ -321,6 +323,11 @@ def ae_normalize(net, grid: WvGrid, state, y, meta, stream=None) -> None:
 def ae_encode(net, grid: WvGrid, state, latent_fmt, latent, meta, qscale=None, stream=None) -> None:
     _check(load().ae_encode(net, C.byref(grid), ptr(state, torch.float32), int(latent_fmt), ptr(latent),
                             ptr(meta, torch.float32), ptr(qscale, torch.float32), stream_handle(stream)))
+
+
+def ae_encode_noalloc(net, grid: WvGrid, state, latent_fmt, latent, meta, qscale=None, stream=None) -> None:
+    _check(load().ae_encode_noalloc(net, C.byref(grid), ptr(state, torch.float32), int(latent_fmt), ptr(latent),
+                                    ptr(meta, torch.float32), ptr(qscale, torch.float32), stream_handle(stream)))
 
 
 def ae_decode(net, grid: WvGrid, latent, meta, qscale, latent_fmt, field_mask, state, stream=None) -> None:

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1346,6 +1347,40 @@ void free_net(ae_net* a)
 }
 
 }  // namespace
+
+// ---- the allocation-free encode ----------------------------------------------------
+// ae_encode_noalloc stages the float32 latents of an FP8 encode (P x latent floats)
+// in this file-scope device array instead of the per-stream work buffer. Each device
+// holds its own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a host-side
+// stand-in, not a device address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+__device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device, looked up once per device
+void* noalloc_scratch()
+{
+    int dev = -1;
+    WV_HIP(hipGetDevice(&dev));
+    WV_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, WV_EDEVICE, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw Error{WV_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 }  // namespace wv
 
 // ======================================================================================
@@ -1693,6 +1728,45 @@ int ae_train(ae_net* a, const uint16_t* y, const float* meta, int64_t nsamples, 
         }
         WV_HIP(hipStreamSynchronize(st));
         if (dseq) (void)hipFree(dseq);
+        return WV_OK;
+    });
+}
+
+int ae_encode_noalloc(const ae_net* a, const wv_grid* g, const float* state, int fmt, void* latent, float* meta,
+                      float* qscale, void* stream)
+{
+    return guarded_ae([&]() -> int {
+        WV_REQUIRE(a && state && latent && meta, WV_EINVAL, "null argument");
+        WV_REQUIRE(fmt == AE_LATENT_BF16 || (fmt == AE_LATENT_FP8 && qscale), WV_EINVAL, "bad latent format/scale");
+        check_grid(g);
+        WV_REQUIRE(fused_supported(a->hid, a->lat), WV_EINVAL,
+                   "ae_encode_noalloc needs the fused network shape (hidden 512, latent 32)");
+        const PatchGrid pg = patch_grid(g->nz, g->ny, g->nx);
+        const hipStream_t st = (hipStream_t)stream;
+        const long long N = (long long)pg.nz * pg.ny * pg.nx;
+        const int rows = (pg.nz / 8) * (pg.ny / 8);
+        if (fmt == AE_LATENT_FP8) {
+            const size_t need = (size_t)pg.P * a->lat * sizeof(float);
+            WV_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, WV_EINVAL,
+                       "ae_encode_noalloc: FP8 staging needs " + std::to_string(need) + " bytes, beyond the " +
+                           std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte static scratch (at most " +
+                           std::to_string(NOALLOC_SCRATCH_BYTES / (a->lat * sizeof(float))) + " patches)");
+        }
+        // the same kernels as ae_encode; only the FP8 staging buffer differs
+        hipLaunchKernelGGL(minmax_kernel, dim3(rows), dim3(std::min(256, ((pg.nx + 63) / 64) * 64)), 0, st, state,
+                           pg.ny, pg.nx, N, pg.ny / 8, pg.nx / 8, a->beta_d, meta);
+        WV_HIP(hipGetLastError());
+        if (fmt == AE_LATENT_BF16) {
+            fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
+                         (uint16_t*)latent, nullptr, st);
+            return WV_OK;
+        }
+        float* z = (float*)noalloc_scratch();
+        fused_encode(pg, state, meta, nullptr, 0, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr, z,
+                     st);
+        hipLaunchKernelGGL(quantize_kernel, dim3(blocks(pg.P, 4)), dim3(256), 0, st, z, pg.P, a->lat,
+                           (uint8_t*)latent, qscale);
+        WV_HIP(hipGetLastError());
         return WV_OK;
     });
 }
