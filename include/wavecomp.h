@@ -140,9 +140,15 @@ int wv_destroy(wv_ctx* ctx);
  * by WV_STORE_CHECKPOINT and by the fallback; ae must be non-NULL for the AE
  * modes (the context keeps a reference; the net must outlive it).
  * mem_budget_bytes > 0 caps the history allocation (WV_ENOMEM beyond it).
- * guard_tol > 0 enables the accuracy guard of the AE modes: after each forward
- * solve the last stored state is decoded and compared with the true state;
- * a relative L2 error above guard_tol marks the store degraded, and with
+ * guard_tol > 0 enables the accuracy guard of the AE modes: during each forward
+ * solve, 16 stored states spread evenly over it (every ceil((T-1)/16)-th state)
+ * and the last one are decoded as the reverse solves read them (exception patches
+ * exact) and their e compared with the true e while the solve still holds it
+ * (one e field of scratch per source). The guard error is, per source, the
+ * largest L2 error of a checked state over the largest L2 norm of the checked
+ * states' e (so an early state that holds little of the wavefield does not
+ * magnify the decoder's noise floor); its worst over sources above guard_tol
+ * marks the store degraded, and with
  * fallback_policy WV_FALLBACK_CHECKPOINT gradient/hessvec then recompute with
  * checkpointing and return WV_OK_FALLBACK. Allocation happens here. */
 int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
@@ -159,6 +165,18 @@ int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
  * residuals to bound the error (Sec. 1, Sec. 3.3). Takes effect at the next
  * wv_set_storage. */
 int wv_set_ae_exceptions(wv_ctx* ctx, int32_t k_per_step);
+
+/* Precision of the per-patch normalisation metadata (lo, r) of the space-compressed
+ * stores (Sec. 3.3.1 keeps an offset and a scale per vector): bits = 32 (default)
+ * stores float32 pairs, 32 B per patch; bits = 16 stores bfloat16 pairs, 16 B per
+ * patch, with lo rounded down and r rounded up to bfloat16 before the encoder
+ * normalises, so lo <= min, lo + r >= max and the decoder reads exactly the values
+ * the encoder used (no inconsistency; a patch whose offset dwarfs its range loses
+ * up to 8 bits of its normalised resolution). This is what lets the 8-source FP8
+ * workload keep 4000 steps of latents within one GPU. Needs the fused network
+ * shape (hidden 512, latent 32). Applies to the incremental store too; takes
+ * effect at the next wv_set_storage. WV_EINVAL for other bit counts. */
+int wv_set_ae_metadata(wv_ctx* ctx, int32_t bits);
 
 /* Compression of the incremental forward states (AE modes). The paper notes
  * that the incremental forward states can be compressed as well (Sec. 4); the
@@ -457,8 +475,10 @@ int wv_revolve_schedule(int32_t nsteps, int32_t nslots, int32_t* h_actions, int6
                         int64_t* h_count, int64_t* h_forward_steps);
 
 /* Diagnostics of the last solve: step evaluations of the forward model (sweep
- * plus checkpoint recomputation), relative L2 error measured by the accuracy
- * guard (-1 if not run) and whether it tripped. Any pointer may be NULL. */
+ * plus checkpoint recomputation), the guard error of the accuracy guard (the
+ * largest L2 error of e among its checked states over their largest e norm, worst
+ * source; -1 if not run) and whether it tripped.
+ * Any pointer may be NULL. */
 int wv_stats(const wv_ctx* ctx, int64_t* h_forward_steps, double* h_guard_err, int* h_degraded);
 
 /* Kernel timing. every > 0: every every-th launch of each timed class is
@@ -487,6 +507,18 @@ int wv_kernel_time(wv_ctx* ctx, int32_t cls, double* h_mean_us, int64_t* h_count
  * the time integral of the gradient): the adjoint step reads and writes the
  * float32 partial every step and the compensated pair once per block. */
 int wv_accumulation_block(void);
+
+/* Measurement aid, no part of the solves: the HBM rate of a plain streaming kernel
+ * with the stencils' array mix, the practical ceiling they are compared with next
+ * to the published peak. in: n_in arrays [n_in][n], out: n_out arrays [n_out][n]
+ * (device float32, n a positive multiple of 4); every element of every array is
+ * read or written once per launch (float4 per thread, non-temporal). Mixes
+ * (n_in, n_out): (1, 1) copy, (5, 4) the forward step's, (7, 5) the adjoint
+ * step's. Runs one warm-up and reps timed launches on stream (HIP events) and
+ * returns the mean duration in microseconds in *h_us; synchronises. WV_EINVAL for
+ * another mix, reps < 1 or a bad n. */
+int wv_stream_probe(const float* in, float* out, int32_t n_in, int32_t n_out, int64_t n, int32_t reps,
+                    void* stream, double* h_us);
 
 const char* wv_last_error(void);
 const char* wv_version(void);

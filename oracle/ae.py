@@ -112,16 +112,33 @@ def normalize_vectors(X: np.ndarray, beta: float, emulate: bool = False):
 
 
 # ----- normalisation ----------------------------------------------------------
-def normalize(X: np.ndarray, beta, emulate: bool = False):
+def normalize(X: np.ndarray, beta, emulate: bool = False, meta_bits: int = 32):
     """Per-(patch, field) min/range normalisation. Returns Y [P, 2048],
     lo [P, 4], r [P, 4]. emulate=True forms the range in FP32 and the
     quotient as the FP32 product of FP32(x - lo) with the FP32-rounded
-    reciprocal of the range, as the kernels do."""
+    reciprocal of the range, as the kernels do.
+    meta_bits=16: the offset and scale are kept as bfloat16 (a reading of the
+    per-vector offset and scale of Sec. 3.3.1 that fits the 8-source store in
+    one GPU): lo is rounded down to bfloat16 first, then r = max(max - lo, beta)
+    is rounded up, so lo <= min and lo + r >= max, and the normalisation uses
+    exactly the stored values."""
     P = X.shape[0]
     Xf = X.reshape(P, NFIELD, 512)
     lo = Xf.min(axis=2)
     hi = Xf.max(axis=2)
     beta = np.asarray(beta, dtype=np.float64)[None, :]
+    if meta_bits == 16:
+        lo = rd.bf16_down(lo)
+        r = np.maximum(rd.f32(hi - lo), rd.f32(beta)) if emulate else np.maximum(hi - lo, beta)
+        r = rd.bf16_up(r)
+        if emulate:
+            rinv = rd.f32(1.0 / r)
+            Y = rd.f32(rd.f32(Xf - lo[..., None]) * rinv[..., None])
+        else:
+            Y = (Xf - lo[..., None]) / r[..., None]
+        return Y.reshape(P, VEC), lo, r
+    if meta_bits != 32:
+        raise ValueError("meta_bits must be 32 or 16")
     if emulate:
         r = np.maximum(rd.f32(hi - lo), rd.f32(beta))
         rinv = rd.f32(1.0 / r)

@@ -6,7 +6,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   * bfloat16: 1 sign, 8 exponent, 7 mantissa bits; a float32 is rounded
     to its upper 16 bits, ties to the even upper half. Values arrive as
     float32 first (the kernels round FP32 accumulators), so bf16(x) is
-    RNE_bf16(RNE_f32(x)).
+    RNE_bf16(RNE_f32(x)). bf16_down / bf16_up round toward -inf / +inf (the
+    16-bit normalisation metadata).
   * OCP FP8 E4M3FN: 1 sign, 4 exponent (bias 7), 3 mantissa bits, no
     infinities, largest finite 448, smallest subnormal 2^-9; rounding to
     nearest even with saturation at +-448 (the latent quantiser never
@@ -39,6 +40,36 @@ def bf16_from_bits(b) -> np.ndarray:
 
 def bf16(x) -> np.ndarray:
     return bf16_from_bits(bf16_bits(x))
+
+
+def _bf16_ordered(b):
+    """bfloat16 bits -> integers ordered like the values (sign-magnitude to two's
+    complement order; -0 and +0 both map to 0)."""
+    b = np.asarray(b, dtype=np.uint16).astype(np.int64)
+    return np.where(b & 0x8000, -(b & 0x7FFF), b)
+
+
+def _bf16_from_ordered(o):
+    o = np.asarray(o, dtype=np.int64)
+    return np.where(o < 0, (-o) | 0x8000, o).astype(np.uint16)
+
+
+def bf16_down(x) -> np.ndarray:
+    """Largest bfloat16 value <= x (finite x, float64 exact comparison)."""
+    x = np.asarray(x, dtype=np.float64)
+    o = _bf16_ordered(bf16_bits(x))
+    c = bf16_from_bits(_bf16_from_ordered(o))
+    o = np.where(c > x, o - 1, o)
+    return bf16_from_bits(_bf16_from_ordered(o))
+
+
+def bf16_up(x) -> np.ndarray:
+    """Smallest bfloat16 value >= x (finite x, float64 exact comparison)."""
+    x = np.asarray(x, dtype=np.float64)
+    o = _bf16_ordered(bf16_bits(x))
+    c = bf16_from_bits(_bf16_from_ordered(o))
+    o = np.where(c < x, o + 1, o)
+    return bf16_from_bits(_bf16_from_ordered(o))
 
 
 def e4m3(x) -> np.ndarray:

@@ -91,10 +91,13 @@ EXPORTS = {
     "wv_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "wv_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "wv_stream_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
+                                  C.POINTER(C.c_double)]),
     "wv_last_error": (C.c_char_p, []),
     "wv_version": (C.c_char_p, []),
     "wv_accumulation_block": (C.c_int, []),
     "wv_set_delta_storage": (C.c_int, [C.c_void_p, C.c_int32]),
+    "wv_set_ae_metadata": (C.c_int, [C.c_void_p, C.c_int32]),
     "wv_decode_delta": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p]),
     "wv_set_prior": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "wave_forward_e": (C.c_int, [C.c_void_p] * 4 + [C.c_int32, C.c_void_p]),
@@ -363,6 +366,14 @@ def wv_set_ae_exceptions(ctx, k_per_step: int) -> int:
     return _check(load().wv_set_ae_exceptions(ctx, int(k_per_step)))
 
 
+def wv_stream_probe(inp, out, n_in: int, n_out: int, n: int, reps: int = 10, stream=None) -> float:
+    """Mean microseconds per launch of the streaming probe (n_in arrays read, n_out written, n floats each)."""
+    us = C.c_double()
+    _check(load().wv_stream_probe(ptr(inp, torch.float32), ptr(out, torch.float32), int(n_in), int(n_out), int(n),
+                                  int(reps), stream_handle(stream), C.byref(us)))
+    return us.value
+
+
 def wv_last_error() -> str:
     return load().wv_last_error().decode()
 
@@ -373,6 +384,10 @@ def wv_version() -> str:
 
 def wv_accumulation_block() -> int:
     return int(load().wv_accumulation_block())
+
+
+def wv_set_ae_metadata(ctx, bits: int) -> int:
+    return _check(load().wv_set_ae_metadata(ctx, int(bits)))
 
 
 def wv_set_delta_storage(ctx, enable: bool) -> int:

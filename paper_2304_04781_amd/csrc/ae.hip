@@ -1015,21 +1015,23 @@ void ae_encode_state(const ae_net* a, const PatchGrid& pg, const float* state, i
 }
 
 void ae_encode_state_mm(const ae_net* a, const PatchGrid& pg, const float* state, const float* mm, int H, int fmt,
-                        void* latent, float* meta, float* qscale, hipStream_t st)
+                        void* latent, float* meta, float* qscale, hipStream_t st, uint16_t* meta16)
 {
     if (!fused_supported(a->hid, a->lat)) {
+        WV_REQUIRE(!meta16, WV_EINVAL, "16-bit metadata needs the fused network shape (hidden 512, latent 32)");
         ae_encode_state(a, pg, state, fmt, latent, meta, qscale, st);
         return;
     }
-    WV_REQUIRE(a && state && mm && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
+    WV_REQUIRE(a && state && mm && latent && (meta || meta16) && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "encode: null buffer");
     const long long P = pg.P;
     if (fmt == AE_LATENT_BF16) {
         fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1),
-                     (uint16_t*)latent, nullptr, st);
+                     (uint16_t*)latent, nullptr, st, meta16);
     } else {
         float* z = (float*)workspace(a, align256(P * (size_t)a->lat * 4), st);
-        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr, z, st);
+        fused_encode(pg, state, meta, mm, H, a->beta_d, a->wp1, a->bias(0), a->wt[1], a->bias(1), nullptr, z, st,
+                     meta16);
         hipLaunchKernelGGL(quantize_kernel, dim3(blocks(P, 4)), dim3(256), 0, st, z, P, a->lat, (uint8_t*)latent,
                            qscale);
         WV_HIP(hipGetLastError());
@@ -1095,10 +1097,12 @@ void ae_time_decode(const ae_net* a, const TimeGrid& tg, const uint16_t* latent,
 
 void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st,
-                     const ExcPatches* exc)
+                     const ExcPatches* exc, const uint16_t* meta16)
 {
-    WV_REQUIRE(a && state && latent && meta && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
+    WV_REQUIRE(a && state && latent && (meta || meta16) && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "decode: null buffer");
+    WV_REQUIRE(!meta16 || fused_supported(a->hid, a->lat), WV_EINVAL,
+               "16-bit metadata needs the fused network shape (hidden 512, latent 32)");
     const long long P = pg.P;
     if (fused_supported(a->hid, a->lat)) {
         const uint16_t* zb = (const uint16_t*)latent;
@@ -1112,7 +1116,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
         for (int f = 0; f < 4; ++f)
             if (mask & (1u << f))
                 fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wp4, a->bias(3), f, state, st,
-                             (exc && exc->K > 0 && f == 0) ? exc : nullptr);
+                             (exc && exc->K > 0 && f == 0) ? exc : nullptr, meta16);
         return;
     }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);

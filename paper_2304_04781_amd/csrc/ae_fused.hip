@@ -46,6 +46,8 @@ constexpr int ENC_META_OFF = ENC_PH1 > ENC_PH2 ? ENC_PH1 : ENC_PH2;  // bytes; [
 struct EncArgs {
     const float* state;   // [4][N]
     const float* meta;    // [P][4][2] (min, range); output when mm is given
+    uint16_t* meta16;     // with mm: 16-bit output instead of meta (bfloat16 (lo, r), lo rounded
+                          // down and r up, the values the normalisation then uses)
     const float* mm;      // optional [P][H][4][2] partial (min, max) from the forward step
     int H;
     const float* beta;    // [4] range floors (with mm)
@@ -62,6 +64,7 @@ struct EncArgs {
 struct DecArgs {
     const uint16_t* z;    // [P][L] bf16
     const float* meta;
+    const uint16_t* meta16;  // bfloat16 (lo, r) instead of meta when non-null
     const uint16_t* w3t;  // [HID][L]
     const float* b3;
     const uint16_t* w4p;  // W4^T [2048][HID] in fragment order, rows of field f at f*512
@@ -128,8 +131,19 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
                         hi = fmaxf(hi, a.mm[(p * a.H + h) * 8 + 2 * f + 1]);
                     }
                     r = fmaxf(hi - lo, a.beta[f]);
-                    const_cast<float*>(a.meta)[p * 8 + 2 * f] = lo;
-                    const_cast<float*>(a.meta)[p * 8 + 2 * f + 1] = r;
+                    if (a.meta16) {
+                        // 16-bit metadata: lo_b <= lo and lo_b + r_b >= hi, so y stays in [0, 1]
+                        // up to rounding and the decode reads the very values used here
+                        const uint16_t lb = bf16_down(lo);
+                        lo = bf2f(lb);
+                        const uint16_t rb = bf16_up(fmaxf(hi - lo, a.beta[f]));
+                        r = bf2f(rb);
+                        a.meta16[p * 8 + 2 * f] = lb;
+                        a.meta16[p * 8 + 2 * f + 1] = rb;
+                    } else {
+                        const_cast<float*>(a.meta)[p * 8 + 2 * f] = lo;
+                        const_cast<float*>(a.meta)[p * 8 + 2 * f + 1] = r;
+                    }
                 }
                 sMeta[tid * 8 + 2 * f] = lo;
                 sMeta[tid * 8 + 2 * f + 1] = 1.0f / r;
@@ -400,8 +414,13 @@ __global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
         if (p < a.P) {
             const long long px = p % a.Px, py = (p / a.Px) % a.Py, pz = p / ((long long)a.Px * a.Py);
             base = (pz * 8 * a.ny + py * 8) * a.nx + px * 8;
-            lo = a.meta[p * 8 + 2 * a.f];
-            rg = a.meta[p * 8 + 2 * a.f + 1];
+            if (a.meta16) {
+                lo = bf2f(a.meta16[p * 8 + 2 * a.f]);
+                rg = bf2f(a.meta16[p * 8 + 2 * a.f + 1]);
+            } else {
+                lo = a.meta[p * 8 + 2 * a.f];
+                rg = a.meta[p * 8 + 2 * a.f + 1];
+            }
         }
         sBase[tid] = base;
         sLo[tid] = lo;
@@ -558,10 +577,11 @@ void fused_pack(const uint16_t* w, int rows, int K, uint16_t* out, hipStream_t s
 
 void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
                   const uint16_t* w1p, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
-                  hipStream_t st)
+                  hipStream_t st, uint16_t* meta16)
 {
-    EncArgs a{state, meta, mm, H, beta, w1p, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny,
-              pg.nx, pg.ny / 8, pg.nx / 8};
+    WV_REQUIRE(!meta16 || mm, WV_EINVAL, "16-bit metadata is written from the step's (min, max) partials");
+    EncArgs a{state, meta, meta16, mm, H, beta, w1p, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx,
+              pg.ny, pg.nx, pg.ny / 8, pg.nx / 8};
     const size_t sm = enc_smem();
     allow_smem(encode_kernel<32>, sm);
     hipLaunchKernelGGL(encode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), sm, st, a);
@@ -569,10 +589,11 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 }
 
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
-                  const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st, const ExcPatches* exc)
+                  const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st, const ExcPatches* exc,
+                  const uint16_t* meta16)
 {
     static_assert(DEC_BM % 16 == 0 && DEC_BM <= 512, "decode work-groups hold whole 16-patch tiles");
-    DecArgs a{z, meta, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
+    DecArgs a{z, meta, meta16, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
               pg.ny / 8, pg.nx / 8, nullptr, nullptr, nullptr};
     if (exc && exc->K > 0) {
         WV_REQUIRE(exc->idx && exc->exc && exc->rng, WV_EINVAL, "decode: null exception buffer");

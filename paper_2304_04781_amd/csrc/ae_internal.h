@@ -59,8 +59,10 @@ void ae_encode_state(const ae_net* net, const PatchGrid& pg, const float* state,
                      void* latent, float* meta, float* qscale, hipStream_t st);
 // Compress with the per-patch (min, max) partials [P][H][4][2] computed by the
 // forward step (no separate pass over the state for the normalisation).
+// meta16 (optional): bfloat16 (lo, r) written instead of meta, lo rounded down and
+// r up to bfloat16 before the normalisation uses them.
 void ae_encode_state_mm(const ae_net* net, const PatchGrid& pg, const float* state, const float* mm, int H, int fmt,
-                        void* latent, float* meta, float* qscale, hipStream_t st);
+                        void* latent, float* meta, float* qscale, hipStream_t st, uint16_t* meta16 = nullptr);
 // Exception patches of one stored state: K patch indices in increasing order,
 // their exact e values [K][512] ((lz, ly, lx) order), and rng [ceil(P/DEC_BM) + 1]:
 // the exceptions of patches [DEC_BM b, DEC_BM b + DEC_BM) are idx[rng[b] .. rng[b+1]).
@@ -76,9 +78,10 @@ struct ExcPatches {
 constexpr int DEC_BM = WV_DEC_BM;  // patches per decode work-group
 // Decompress the fields in field_mask into state [4][N]; with exc, the e values of
 // its patches are the exact ones.
+// meta16 (optional): bfloat16 (lo, r) read instead of meta.
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st,
-                     const ExcPatches* exc = nullptr);
+                     const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr);
 
 // Fused inference kernels (hidden width 512, latent 32): meta must already hold
 // the per-patch (min, range) of the state for encode.
@@ -92,11 +95,11 @@ void fused_pack(const uint16_t* w, int rows, int K, uint16_t* out, hipStream_t s
 // w1p: W1^T packed by fused_pack; w4p: W4^T packed by fused_pack.
 void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
                   const uint16_t* w1p, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
-                  hipStream_t st);
+                  hipStream_t st, uint16_t* meta16 = nullptr);
 // exc (field 0 only): exception patches written with their exact values
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st,
-                  const ExcPatches* exc = nullptr);
+                  const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr);
 
 // Exception patches: the K largest-e-range patches of one compressed state are
 // kept exactly. Ranges are compared by key = bits(r_e) >> EXC_BIN_SHIFT (bins 2^-5
@@ -106,12 +109,13 @@ constexpr int EXC_BIN_SHIFT = 18;
 constexpr int EXC_NBIN = 1 << (32 - EXC_BIN_SHIFT);
 // selection from meta [P][4][2] into idx [K] (increasing patch order); a single
 // work-group kernel, cheap to overlap with other work
-void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st);
+void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st,
+                       const uint16_t* meta16 = nullptr);
 // copy the e values of the selected patches to exc [K][512]
 void exceptions_gather(const PatchGrid& pg, const float* state, int K, const int* idx, float* exc, hipStream_t st);
 // both
 void exceptions_store(const PatchGrid& pg, const float* state, const float* meta, int K, int* idx, float* exc,
-                      hipStream_t st);
+                      hipStream_t st, const uint16_t* meta16 = nullptr);
 // rng [ceil(P/bm) + 1]: rng[b] = number of idx entries below patch bm b
 void exceptions_ranges(const PatchGrid& pg, int K, const int* idx, int bm, int* rng, hipStream_t st);
 // Write the stored e values back into an e field [N].

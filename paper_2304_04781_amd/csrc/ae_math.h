@@ -22,6 +22,19 @@ __device__ __forceinline__ uint32_t f2bf2(float x, float y)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((ae_f32x2{x, y}), ae_bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+// bfloat16 bits of the largest bfloat16 <= x and of the smallest bfloat16 >= x
+// (finite x): truncation toward zero, moved one step away from zero when the
+// dropped bits are nonzero and zero lies on the wrong side
+__device__ __forceinline__ uint16_t bf16_down(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u >> 16) + (((u >> 31) != 0u && (u & 0xFFFFu) != 0u) ? 1u : 0u));
+}
+__device__ __forceinline__ uint16_t bf16_up(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u >> 16) + (((u >> 31) == 0u && (u & 0xFFFFu) != 0u) ? 1u : 0u));
+}
 
 // erf(x) by the rational-exponential approximation of Abramowitz & Stegun 7.1.26
 // (Hastings): |error| <= 1.5e-7, far below the bfloat16 rounding of the hidden

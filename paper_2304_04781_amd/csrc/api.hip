@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -157,7 +158,8 @@ constexpr int NEB = 3;
 // per-patch metadata, FP8 scales and the exact e values of the exception patches
 struct LatStore {
     uint8_t* lat = nullptr;   // [T-1][S][P][L]
-    float* meta = nullptr;    // [T-1][S][P][4][2]
+    float* meta = nullptr;    // [T-1][S][P][4][2] float32 (lo, r), or
+    uint16_t* meta16 = nullptr;  // the same as bfloat16 (16-bit metadata)
     float* qs = nullptr;      // [T-1][S][P]
     int* exc_idx = nullptr;   // [T-1][S][K]
     float* exc = nullptr;     // [T-1][S][K][512]
@@ -182,6 +184,9 @@ struct TimeStore {
     int cur_w = -1;              // window the main stream reads now
     hipEvent_t ev_fill[2] = {}, ev_enc[2] = {}, ev_ready[2] = {}, ev_free[2] = {};
 };
+
+// stored states checked by the accuracy guard per forward solve (plus the last)
+constexpr int GUARD_CHECKS = 16;
 
 struct wv_ctx {
     KernelTimer tm;
@@ -240,6 +245,8 @@ struct wv_ctx {
     bool delta_ok = false;       // ds holds the incremental states of the last incremental forward
     int64_t delta_bytes = 0;
     int exc_req = 0;             // requested exception patches per state
+    int meta_req = 32;           // requested bits per (lo, r) value of the AE stores (32 or 16)
+    bool m16 = false;            // the AE stores keep bfloat16 (lo, r)
     int K = 0;                   // active exception patches per state
     int nbd = 0;                 // decode work-groups per state
     float* mmpart = nullptr;     // [3][S][P][H][4][2] (min, max) partials of the forward step
@@ -250,6 +257,7 @@ struct wv_ctx {
     // the store of x_j may take until the step that overwrites x_j, two later.
     // The incremental forward's latent store encodes dx_n on `side3` (the decodes of
     // e^n are on `side`) and selects and copies its exception patches on `side2`.
+    // The three side streams belong to the device, not the context (shared_side).
     hipStream_t side = nullptr;
     hipStream_t side2 = nullptr;
     hipStream_t side3 = nullptr;
@@ -269,6 +277,12 @@ struct wv_ctx {
     bool store_ok = false;       // the store matches c_last
     bool degraded = false;       // accuracy guard tripped
     double guard_err = -1.0;
+    // accuracy guard buffers (allocated with the AE store when guard_tol > 0): the
+    // decoded e of a checked state [S][N], the reduction partials of its error and the
+    // errors [GUARD_CHECKS + 1][S] of the checked states of the last forward solve
+    float* gbuf = nullptr;
+    double* gpart = nullptr;
+    double* gres = nullptr;
     bool have_grad = false;
     double sigma = 1.0;
     long long last_fwd_steps = 0;
@@ -466,6 +480,7 @@ void free_latstore(LatStore& L)
 {
     dev_free(L.lat);
     dev_free(L.meta);
+    dev_free(L.meta16);
     dev_free(L.qs);
     dev_free(L.exc_idx);
     dev_free(L.exc);
@@ -495,10 +510,14 @@ void free_store(wv_ctx* c)
     c->delta_bytes = 0;
     dev_free(c->mmpart);
     dev_free(c->work[2]);
+    dev_free(c->gbuf);
+    dev_free(c->gpart);
+    dev_free(c->gres);
     free_timestore(c->ts);
     free_timestore(c->tds);
     c->tdelta_ok = false;
     c->K = 0;
+    c->m16 = false;
     c->store_bytes = 0;
     c->store_ok = false;
 }
@@ -586,7 +605,14 @@ uint8_t* lat_slot(wv_ctx* c, const LatStore& L, int idx, int s)
 {
     return L.lat + ((long long)idx * c->S + s) * c->P * c->lat_bytes;
 }
-float* meta_slot(wv_ctx* c, const LatStore& L, int idx, int s) { return L.meta + ((long long)idx * c->S + s) * c->P * 8; }
+float* meta_slot(wv_ctx* c, const LatStore& L, int idx, int s)
+{
+    return L.meta ? L.meta + ((long long)idx * c->S + s) * c->P * 8 : nullptr;
+}
+uint16_t* meta16_slot(wv_ctx* c, const LatStore& L, int idx, int s)
+{
+    return L.meta16 ? L.meta16 + ((long long)idx * c->S + s) * c->P * 8 : nullptr;
+}
 int* rng_slot(wv_ctx* c, const LatStore& L, long long q) { return L.exc_rng + q * (c->nbd + 1); }
 float* qs_slot(wv_ctx* c, const LatStore& L, int idx, int s)
 {
@@ -598,7 +624,8 @@ long long latstore_bytes(wv_ctx* c, int mode, int K)
 {
     const long long slots = (long long)std::max(c->T - 1, 1) * c->S;
     const long long nbd = (c->P + DEC_BM - 1) / DEC_BM;
-    return slots * (c->P * (c->lat_bytes + 32 + (mode == WV_STORE_AE_FP8 ? 4 : 0)) + (long long)K * (512 * 4 + 4) +
+    return slots * (c->P * (c->lat_bytes + (c->m16 ? 16 : 32) + (mode == WV_STORE_AE_FP8 ? 4 : 0)) +
+                    (long long)K * (512 * 4 + 4) +
                     (K > 0 ? (nbd + 1) * 4 : 0));
 }
 
@@ -606,7 +633,10 @@ void alloc_latstore(wv_ctx* c, LatStore& L, int mode, int K)
 {
     const long long slots = (long long)std::max(c->T - 1, 1) * c->S;
     L.lat = dev_alloc<uint8_t>(slots * c->P * c->lat_bytes);
-    L.meta = dev_alloc<float>(slots * c->P * 8);
+    if (c->m16)
+        L.meta16 = dev_alloc<uint16_t>(slots * c->P * 8);
+    else
+        L.meta = dev_alloc<float>(slots * c->P * 8);
     if (mode == WV_STORE_AE_FP8) L.qs = dev_alloc<float>(slots * c->P);
     if (K > 0) {
         L.exc_idx = dev_alloc<int>(slots * K);
@@ -629,10 +659,12 @@ void encode_state_into(wv_ctx* c, LatStore& L, int n, const float* state, hipStr
         if (mm)
             ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
                                ae_fmt(c->mode), lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s),
-                               qs_slot(c, L, n - 1, s), st);
-        else
+                               qs_slot(c, L, n - 1, s), st, meta16_slot(c, L, n - 1, s));
+        else {
+            WV_REQUIRE(!c->m16, WV_EINVAL, "16-bit metadata needs the step's (min, max) partials");
             ae_encode_state(c->ae, pg, state + s * 4 * c->N, ae_fmt(c->mode), lat_slot(c, L, n - 1, s),
                             meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s), st);
+        }
     }
     c->tm.end(te, st);
 }
@@ -646,7 +678,7 @@ void exceptions_into(wv_ctx* c, LatStore& L, int n, const float* state, hipStrea
     for (int s = 0; s < c->S; ++s) {
         const long long q = (long long)(n - 1) * c->S + s;
         exceptions_store(pg, state + s * 4 * c->N, meta_slot(c, L, n - 1, s), c->K, L.exc_idx + q * c->K,
-                         L.exc + q * c->K * 512, st);
+                         L.exc + q * c->K * 512, st, meta16_slot(c, L, n - 1, s));
         exceptions_ranges(pg, c->K, L.exc_idx + q * c->K, DEC_BM, rng_slot(c, L, q), st);
     }
     c->tm.end(tx, st);
@@ -745,7 +777,7 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
     for (int s = 0; s < c->S; ++s)
         ae_encode_state_mm(c->ae, pg, state + s * 4 * c->N, mm + (long long)s * c->P * c->H * 8, c->H,
                            ae_fmt(c->mode), lat_slot(c, c->fs, j - 1, s), meta_slot(c, c->fs, j - 1, s),
-                           qs_slot(c, c->fs, j - 1, s), s1);
+                           qs_slot(c, c->fs, j - 1, s), s1, meta16_slot(c, c->fs, j - 1, s));
     c->tm.end(te, s1);
     if (c->K <= 0) {
         WV_HIP(hipEventRecord(c->ev_stored[b], s1));
@@ -756,7 +788,8 @@ void store_state_async(wv_ctx* c, int j, const float* state, const float* mm)
     const int tx = c->tm.begin(TM_EXC_SELECT, s2);
     for (int s = 0; s < c->S; ++s) {
         const long long q = (long long)(j - 1) * c->S + s;
-        exceptions_select(pg, meta_slot(c, c->fs, j - 1, s), c->K, c->fs.exc_idx + q * c->K, s2);
+        exceptions_select(pg, meta_slot(c, c->fs, j - 1, s), c->K, c->fs.exc_idx + q * c->K, s2,
+                          meta16_slot(c, c->fs, j - 1, s));
         exceptions_ranges(pg, c->K, c->fs.exc_idx + q * c->K, DEC_BM, rng_slot(c, c->fs, q), s2);
     }
     c->tm.end(tx, s2);
@@ -807,7 +840,8 @@ void decode_state(wv_ctx* c, const LatStore& L, int n, uint32_t mask, float* out
                             c->K > 0 ? rng_slot(c, L, q) : nullptr};
         const int td = c->tm.begin(TM_DECODE, st);
         ae_decode_state(c->ae, pg, lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s),
-                        ae_fmt(c->mode), mask, out + s * stride, st, c->K > 0 ? &ex : nullptr);
+                        ae_fmt(c->mode), mask, out + s * stride, st, c->K > 0 ? &ex : nullptr,
+                        meta16_slot(c, L, n - 1, s));
         c->tm.end(td, st);
     }
 }
@@ -893,6 +927,69 @@ void pipe_release(wv_ctx* c, int b) { WV_HIP(hipEventRecord(c->ev_free[b], c->st
 
 float* other_work(wv_ctx* c, const float* cur) { return cur == c->work[0] ? c->work[1] : c->work[0]; }
 
+// Accuracy guard: GUARD_CHECKS stored states spread evenly over the forward solve
+// (every guard_every-th) and the last one are decoded as the reverse solves would
+// read them (exception patches exact) and compared with the true e, while the true
+// state is still in its buffer; the worst relative L2 error decides.
+int guard_every(const wv_ctx* c) { return std::max(1, (c->T - 1 + GUARD_CHECKS - 1) / GUARD_CHECKS); }
+
+// check slot of stored state j, or -1 when j is not checked
+int guard_slot(const wv_ctx* c, int j)
+{
+    if (!is_ae(c->mode) || c->guard_tol <= 0.0 || !c->gres || j < 1 || j > c->T - 1) return -1;
+    const int every = guard_every(c);
+    if (j % every == 0 && j / every <= GUARD_CHECKS) return j / every - 1;
+    return j == c->T - 1 ? GUARD_CHECKS : -1;
+}
+
+// queue the check of stored state j, whose true state is x: on the store's side
+// stream after the store (rotation slot b; ev_stored[b] then also covers the check,
+// so the buffer is not reused before it), or on the main stream (b < 0)
+void guard_check(wv_ctx* c, int j, const float* x, int b)
+{
+    const int slot = guard_slot(c, j);
+    if (slot < 0) return;
+    hipStream_t st = c->st;
+    if (b >= 0) {
+        st = side_stream(c, 0);
+        wait_event(st, c->ev_stored[b]);
+    }
+    decode_state(c, c->fs, j, 1u, c->gbuf, c->N, st);
+    for (int s = 0; s < c->S; ++s)
+        launch_err_norms(c->gbuf + s * c->N, x + s * 4 * c->N, c->N, c->gpart, c->nblk_red,
+                         c->gres + 2 * ((long long)slot * c->S + s), st);
+    if (b >= 0) WV_HIP(hipEventRecord(c->ev_stored[b], st));
+}
+
+// after the forward sweep (its side work joined): per source, the largest error norm
+// of a checked state relative to the largest e norm among the checked states (an
+// early state holds little of the wavefield, so its own norm would magnify the
+// decoder's floor-level noise); the worst over sources decides
+void run_guard(wv_ctx* c)
+{
+    c->degraded = false;
+    c->guard_err = -1.0;
+    if (!is_ae(c->mode) || c->guard_tol <= 0.0 || !c->gres || c->T < 2) return;
+    std::vector<double> h(2 * (size_t)(GUARD_CHECKS + 1) * c->S, 0.0);
+    WV_HIP(hipMemcpyAsync(h.data(), c->gres, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->st));
+    WV_HIP(hipStreamSynchronize(c->st));
+    double worst = 0.0;
+    for (int s = 0; s < c->S; ++s) {
+        double emax = 0.0, nmax = 0.0;
+        for (int j = 1; j <= c->T - 1; ++j) {
+            const int slot = guard_slot(c, j);
+            if (slot < 0) continue;
+            const double e2 = h[2 * ((size_t)slot * c->S + s)], n2 = h[2 * ((size_t)slot * c->S + s) + 1];
+            emax = std::isnan(e2) || std::isnan(emax) ? NAN : std::max(emax, e2);
+            nmax = std::max(nmax, n2);
+        }
+        const double r = nmax > 0.0 ? std::sqrt(emax / nmax) : std::sqrt(emax);
+        worst = std::isnan(r) || std::isnan(worst) ? NAN : std::max(worst, r);
+    }
+    c->guard_err = worst;
+    c->degraded = !(worst <= c->guard_tol);
+}
+
 // Forward sweep over T steps from the zero state. Records traces, fills the FULL/AE
 // store, writes checkpoint snapshots (snap[n] = slot of x_n or 0), captures.
 // Returns the buffer holding x_{T-1}; *last receives the one holding x_T.
@@ -936,6 +1033,7 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
                 store_state_async(c, j, out, mm);
             else
                 store_state(c, c->fs, j, out);
+            guard_check(c, j, out, ae ? j % 3 : -1);
         }
         if (ncap > 0 && j % every == 0 && j / every <= ncap)
             WV_HIP(hipMemcpyAsync(capture + (long long)(j / every - 1) * c->state_floats(), out,
@@ -950,26 +1048,6 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
     c->last_fwd_steps = c->T;
     if (last) *last = cur;
     return prev;
-}
-
-// accuracy guard: decode the last stored state and compare its e field
-void run_guard(wv_ctx* c, const float* x_tm1)
-{
-    c->degraded = false;
-    c->guard_err = -1.0;
-    if (!is_ae(c->mode) || c->guard_tol <= 0.0 || c->T < 2) return;
-    long long stride;
-    const float* e = load_e(c, c->T - 1, &stride);
-    double worst = 0.0;
-    for (int s = 0; s < c->S; ++s) {
-        launch_rel_err(e + s * stride, x_tm1 + s * 4 * c->N, c->N, c->partial, c->nblk_red, c->dscal, c->st);
-        double h;
-        WV_HIP(hipMemcpyAsync(&h, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->st));
-        WV_HIP(hipStreamSynchronize(c->st));
-        worst = std::max(worst, h);
-    }
-    c->guard_err = worst;
-    c->degraded = !(worst <= c->guard_tol);
 }
 
 // snapshot map of the initial sweep of a schedule: snap[n] = slot holding x_n
@@ -1076,6 +1154,32 @@ double gradient_checkpoint(wv_ctx* c, const float* cdev, const float* d_obs, dou
     return J;
 }
 
+// Side streams shared by every context on a device: one set of three per process
+// and device, created by the first wv_create on the device and kept until the
+// process ends. With a context's main stream they make four streams, so under HIP's
+// default of four hardware queues per process each of them has a queue of its own
+// however many contexts exist (per-context side streams gave a stream-to-queue
+// mapping that depended on how many contexts had been created before). Work of
+// different contexts on a shared side stream runs in order; every sweep ends with
+// its main stream waiting for the side streams, so contexts used one after the
+// other never wait for each other's side work.
+constexpr int SIDE_MAX_DEVICES = 64;
+std::mutex g_side_mu;
+hipStream_t g_side[SIDE_MAX_DEVICES][3] = {};
+
+void shared_side(wv_ctx* c)
+{
+    int dev = -1;
+    WV_HIP(hipGetDevice(&dev));
+    WV_REQUIRE(dev >= 0 && dev < SIDE_MAX_DEVICES, WV_EDEVICE, "device ordinal beyond the side-stream table");
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if (!g_side[dev][0])
+        for (int q = 0; q < 3; ++q) WV_HIP(hipStreamCreateWithFlags(&g_side[dev][q], hipStreamNonBlocking));
+    c->side = g_side[dev][0];
+    c->side2 = g_side[dev][1];
+    c->side3 = g_side[dev][2];
+}
+
 }  // namespace
 
 // ====================================================================================
@@ -1128,9 +1232,7 @@ int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec, v
         c->resid = dev_alloc<float>(ntr);
         c->dtr = dev_alloc<float>(ntr);
         c->dresid = dev_alloc<float>(ntr);
-        WV_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        WV_HIP(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
-        WV_HIP(hipStreamCreateWithFlags(&c->side3, hipStreamNonBlocking));
+        shared_side(c.get());
         for (int b = 0; b < 3; ++b) {
             WV_HIP(hipEventCreateWithFlags(&c->ev_step[b], hipEventDisableTiming));
             WV_HIP(hipEventCreateWithFlags(&c->ev_enc[b], hipEventDisableTiming));
@@ -1180,9 +1282,6 @@ int wv_destroy(wv_ctx* c)
         for (int b = 0; b < 2; ++b)
             for (hipEvent_t e : {T->ev_fill[b], T->ev_enc[b], T->ev_ready[b], T->ev_free[b]})
                 if (e) (void)hipEventDestroy(e);
-    if (c->side) (void)hipStreamDestroy(c->side);
-    if (c->side2) (void)hipStreamDestroy(c->side2);
-    if (c->side3) (void)hipStreamDestroy(c->side3);
     dev_free(c->tab);
     dev_free(c->src_kji);
     dev_free(c->src_w);
@@ -1248,6 +1347,9 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
             c->P = pg.P;
             c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
+            c->m16 = c->meta_req == 16;
+            WV_REQUIRE(!c->m16 || (ae_input_dim(ae) == 2048 && ae_latent_dim(ae) == 32), WV_EINVAL,
+                       "16-bit metadata needs the fused network shape (hidden 512, latent 32)");
             const int K = (int)std::min<long long>(c->exc_req, c->P);
             c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
             const long long bytes = latstore_bytes(c, mode, K);
@@ -1256,6 +1358,11 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
             c->K = K;
             c->H = 8 / c->tl.by;
             c->mmpart = dev_alloc<float>((size_t)3 * c->S * c->P * c->H * 8);
+            if (guard_tol > 0.0) {
+                c->gbuf = dev_alloc<float>((size_t)c->S * c->N);
+                c->gpart = dev_alloc<double>(3 * (size_t)c->nblk_red);
+                c->gres = dev_alloc<double>(2 * (size_t)(GUARD_CHECKS + 1) * c->S);
+            }
             c->store_bytes = bytes;
             if (fallback_policy == WV_FALLBACK_CHECKPOINT)
                 WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
@@ -1291,6 +1398,16 @@ int wv_set_ae_exceptions(wv_ctx* c, int32_t k_per_step)
         return WV_EINVAL;
     }
     c->exc_req = k_per_step;
+    return WV_OK;
+}
+
+int wv_set_ae_metadata(wv_ctx* c, int32_t bits)
+{
+    if (!c || (bits != 32 && bits != 16)) {
+        set_error("metadata bits must be 32 or 16");
+        return WV_EINVAL;
+    }
+    c->meta_req = bits;
     return WV_OK;
 }
 
@@ -1418,7 +1535,7 @@ void forward_solve(wv_ctx* c, const float* cdev, const float* wavelet, float* tr
     if (final_state)
         WV_HIP(hipMemcpyAsync(final_state, last, sizeof(float) * c->state_floats(), hipMemcpyDeviceToDevice,
                               c->st));
-    run_guard(c, xtm1);
+    run_guard(c);
     c->store_ok = c->mode != WV_STORE_NONE;
 }
 
@@ -1465,7 +1582,7 @@ int gradient(wv_ctx* c, const float* cdev, const float* wavelet, const float* d_
             prepare_model(c, cdev, wavelet);
             float* last = nullptr;
             float* xtm1 = forward_sweep(c, c->traces, nullptr, nullptr, 0, &last);
-            run_guard(c, xtm1);
+            run_guard(c);
             c->store_ok = true;
             if (c->degraded && c->fallback == WV_FALLBACK_CHECKPOINT) {
                 J = gradient_checkpoint(c, cdev, d_obs, sigma, g, std::max(c->nslots, 2));

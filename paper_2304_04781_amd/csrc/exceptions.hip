@@ -52,13 +52,17 @@ constexpr int BIN_SHIFT = EXC_BIN_SHIFT;
 constexpr int NBIN = EXC_NBIN;
 
 // r of row p sits at meta[p * ms + 1]: ms = 8 for patches ((lo, r) of 4 fields, e
-// first), 2 for the e-only vectors of the time scheme
-__device__ __forceinline__ unsigned bin_of(const float* meta, int ms, int p)
+// first), 2 for the e-only vectors of the time scheme; with 16-bit metadata at
+// meta16[p * ms + 1] as bfloat16 bits (the upper half of the same float)
+__device__ __forceinline__ unsigned bin_of(const float* meta, const uint16_t* meta16, int ms, int p)
 {
-    return __float_as_uint(meta[(long long)p * ms + 1]) >> BIN_SHIFT;
+    const unsigned u = meta16 ? (unsigned)meta16[(long long)p * ms + 1] << 16
+                              : __float_as_uint(meta[(long long)p * ms + 1]);
+    return u >> BIN_SHIFT;
 }
 
-__global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __restrict__ meta, int ms, int P, int K,
+__global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __restrict__ meta,
+                                                             const uint16_t* __restrict__ meta16, int ms, int P, int K,
                                                              int* __restrict__ out)
 {
     constexpr int BPT = NBIN / SEL_THREADS;  // bins per thread, highest bins to thread 0
@@ -77,7 +81,7 @@ __global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __rest
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int p = c0 + q * SEL_THREADS + tid;
-            key[q] = p < P ? bin_of(meta, ms, p) : 0xFFFFFFFFu;
+            key[q] = p < P ? bin_of(meta, meta16, ms, p) : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
@@ -125,7 +129,7 @@ __global__ void __launch_bounds__(SEL_THREADS) select_kernel(const float* __rest
         for (int q = 0; q < KPT; ++q) {
             const int i = q * SEL_THREADS + tid;  // coalesced
             const int p = c0 + i;
-            skey[(i / KPT) * (KPT + 1) + i % KPT] = p < P ? bin_of(meta, ms, p) : 0u;
+            skey[(i / KPT) * (KPT + 1) + i % KPT] = p < P ? bin_of(meta, meta16, ms, p) : 0u;
         }
         __syncthreads();
         const int r0 = tid * KPT;  // run of this thread within the chunk
@@ -244,12 +248,13 @@ __global__ void ranges_kernel(const int* __restrict__ idx, int K, int bm, int nb
 
 }  // namespace
 
-void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st)
+void exceptions_select(const PatchGrid& pg, const float* meta, int K, int* idx, hipStream_t st,
+                       const uint16_t* meta16)
 {
     if (K <= 0) return;
     WV_REQUIRE(K <= pg.P, WV_EINVAL, "more exception patches than patches");
     WV_REQUIRE(pg.P < (1LL << 31), WV_EINVAL, "too many patches for the exception selector");
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, 8, (int)pg.P, K, idx);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, meta16, 8, (int)pg.P, K, idx);
     WV_HIP(hipGetLastError());
 }
 
@@ -262,10 +267,10 @@ void exceptions_gather(const PatchGrid& pg, const float* state, int K, const int
 }
 
 void exceptions_store(const PatchGrid& pg, const float* state, const float* meta, int K, int* idx, float* exc,
-                      hipStream_t st)
+                      hipStream_t st, const uint16_t* meta16)
 {
     if (K <= 0) return;
-    exceptions_select(pg, meta, K, idx, st);
+    exceptions_select(pg, meta, K, idx, st, meta16);
     exceptions_gather(pg, state, K, idx, exc, st);
 }
 
@@ -290,7 +295,7 @@ void time_exceptions_store(const TimeGrid& tg, const float* e_win, int s, int nv
     if (K <= 0) return;
     WV_REQUIRE(K <= tg.B, WV_EINVAL, "more exception vectors than blocks");
     WV_REQUIRE(tg.B < (1LL << 31), WV_EINVAL, "too many blocks for the exception selector");
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, 2, (int)tg.B, K, idx);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(SEL_THREADS), 0, st, meta, nullptr, 2, (int)tg.B, K, idx);
     const long long N = (long long)tg.nz * tg.ny * tg.nx;
     hipLaunchKernelGGL(time_gather_kernel, dim3(K), dim3(256), 0, st, e_win, tg.S, s, tg.ny, tg.nx, N, tg.ny / 4,
                        tg.nx / 4, tg.B, nvalid, idx, exc);

@@ -149,6 +149,22 @@ __global__ void rel_err_finalize(const double* __restrict__ partial, int n, doub
     if (threadIdx.x == 0) out[0] = tr > 0.0 ? sqrt(te / tr) : sqrt(te);
 }
 
+// both sums of rel_err_kernel's partials: out[0] = sum (a - b)^2, out[1] = sum b^2
+__global__ void err_norms_finalize(const double* __restrict__ partial, int n, double* __restrict__ out)
+{
+    double e = 0.0, r = 0.0;
+    for (int q = threadIdx.x; q < n; q += RB) {
+        e += partial[2 * q];
+        r += partial[2 * q + 1];
+    }
+    const double te = block_sum(e);
+    const double tr = block_sum(r);
+    if (threadIdx.x == 0) {
+        out[0] = te;
+        out[1] = tr;
+    }
+}
+
 // per-field max |x| over a stack of states [nstates][4][N]; one block row per field
 __global__ void absmax_kernel(const float* __restrict__ st, long long nstates, long long N,
                               double* __restrict__ partial)
@@ -298,6 +314,14 @@ void launch_rel_err(const float* a, const float* b, long long n, double* partial
 {
     hipLaunchKernelGGL(rel_err_kernel, dim3(nblocks), dim3(RB), 0, st, a, b, n, partial);
     hipLaunchKernelGGL(rel_err_finalize, dim3(1), dim3(RB), 0, st, partial, nblocks, d_out);
+    WV_HIP(hipGetLastError());
+}
+
+void launch_err_norms(const float* a, const float* b, long long n, double* partial, int nblocks, double* d_out2,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(rel_err_kernel, dim3(nblocks), dim3(RB), 0, st, a, b, n, partial);
+    hipLaunchKernelGGL(err_norms_finalize, dim3(1), dim3(RB), 0, st, partial, nblocks, d_out2);
     WV_HIP(hipGetLastError());
 }
 

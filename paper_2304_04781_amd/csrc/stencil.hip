@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(BX* BY)
         load_col(k0, c0);
         load_col(k0 - 1, cl);
 #pragma unroll
-        for (int u = 1; u <= WV_PF; ++u) load_col(k0 + u, cb[u % NB]);
+        for (int u = 1; u <= WV_PF; ++u) load_col(min(k0 + u, k1), cb[u % NB]);
 #pragma unroll
         for (int u = 0; u < WV_PF; ++u) load_pln(min(k0 + u, k1 - 1), pb[u]);
         A_cur = c0.A;
@@ -351,9 +351,12 @@ __global__ void __launch_bounds__(BX* BY)
     auto level = [&](const int k, const Col& cn, Col& cnn, const Pln& pc, Pln& pn) {
         const long long lk = (long long)k * plane;
         const bool has_next = k + 1 < nz;
-        // issue the loads of the next pipeline stages (levels past the chunk
-        // re-read its last plane rather than branching)
-        load_col(k + 1 + WV_PF, cnn);
+        // issue the loads of the next pipeline stages (levels past the chunk re-read
+        // its last needed level rather than branching: column data up to k1, where
+        // the last cell's upper face reads P and v_z; plane data up to k1 - 1). A
+        // level past k1 belongs to the next chunk, which another work-group, often on
+        // another XCD, reads much later, so fetching it here would cost HBM bytes.
+        load_col(min(k + 1 + WV_PF, k1), cnn);
         load_pln(min(k + WV_PF, k1 - 1), pn);
         const float P_nx = (inside && has_next) ? P_col(k + 1, cn) : 0.f;
         const float Vz_nx_in = cn.Vz;

@@ -116,6 +116,9 @@ void launch_newton_finish(const float* c, const float* dc, const float* acc, con
                           int nsrc, double scale, float* h, hipStream_t st);
 void launch_compare(const float* a, const float* b, long long n, int* flag, hipStream_t st);
 void launch_copy(float* dst, const float* src, long long n, hipStream_t st);
+// d_out2[0] = sum (a - b)^2, d_out2[1] = sum b^2 (float64, fixed order)
+void launch_err_norms(const float* a, const float* b, long long n, double* partial, int nblocks, double* d_out2,
+                      hipStream_t st);
 void launch_rel_err(const float* a, const float* b, long long n, double* partial, int nblocks,
                     double* d_out, hipStream_t st);
 void launch_absmax_fields(const float* states, long long nstates, long long N, double* d_out4,
