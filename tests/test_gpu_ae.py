@@ -31,6 +31,19 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def latent_agreement(gpu_bits, ref_bits):
+    """(fraction of identical bfloat16 codes, whether every code is within one
+    rounding step of the reference): the GPU and the oracle round the same float32
+    and float64 sums, so codes differ only where a sum sits within summation-order
+    error of a rounding tie, by one step (at most 2^-7 relative), or, for latents
+    near zero, by what a one-step flip of a hidden unit moves them (bounded here
+    by 3e-3 of the rms latent)."""
+    a = rd.bf16_from_bits(gpu_bits)
+    b = rd.bf16_from_bits(ref_bits)
+    tol = 2.0 ** -7 * np.abs(b) + 3e-3 * np.sqrt(np.mean(b * b))
+    return float(np.mean(np.asarray(gpu_bits) == np.asarray(ref_bits))), bool(np.all(np.abs(a - b) <= tol))
+
+
 def flat_params(prm):
     return np.concatenate([np.asarray(prm[k], np.float64).ravel() for k in oae.NAMES])
 
@@ -102,15 +115,22 @@ def test_encode_decode_against_oracle(fmt):
     Y, lo, r = oae.normalize(X, [1e-7] * 4, emulate=True)
     z_o = ae.encode(Y, emulate=True)
     if fmt == L.LATENT_BF16:
-        z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16))
-        assert rel(z_gpu, rd.bf16(z_o)) < 5e-3
+        bits = lat.cpu().numpy().view(np.uint16)
+        z_gpu = rd.bf16_from_bits(bits)
+        same, near = latent_agreement(bits, rd.bf16_bits(z_o))
+        err = rel(z_gpu, rd.bf16(z_o))
+        print(f"encode bf16: rel err {err:.3e}, identical codes {same:.4f}, all within a step {near}", flush=True)
+        assert err < 5e-4 and same > 0.99 and near
     else:
         codes = lat.cpu().numpy()
         s = qs.cpu().numpy().astype(np.float64)
         q_o, s_o = oae.fp8_quantize(z_o)
+        err = rel(rd.e4m3_decode(codes) * s[:, None], rd.e4m3_decode(q_o) * s_o[:, None])
+        print(f"encode fp8: rel err {err:.3e}, identical codes {np.mean(codes == q_o):.4f}, "
+              f"scale rel diff {np.max(np.abs(s / s_o - 1)):.2e}", flush=True)
         assert np.allclose(s, s_o, rtol=1e-5)
-        assert np.mean(codes == q_o) > 0.97
-        assert rel(rd.e4m3_decode(codes) * s[:, None], rd.e4m3_decode(q_o) * s_o[:, None]) < 3e-2
+        assert np.mean(codes == q_o) > 0.99
+        assert err < 5e-3
     # decoder on seeded latents and metadata (both sides get the same inputs)
     rng = np.random.default_rng(17)
     ms = np.zeros((P, 4, 2), np.float32)
@@ -134,7 +154,9 @@ def test_encode_decode_against_oracle(fmt):
     dec_ref = ae.decode(z_dec, emulate=True)
     x_ref = oae.unpatchify(oae.denormalize(dec_ref, ms[:, :, 0].astype(np.float64), ms[:, :, 1].astype(np.float64)),
                            *SHAPE)
-    assert rel(out.cpu().numpy(), x_ref) < 5e-3
+    derr = rel(out.cpu().numpy(), x_ref)
+    print(f"decode fmt {fmt}: rel err {derr:.3e}", flush=True)
+    assert derr < 1e-6
     # e-only decode writes the e field and leaves the others untouched
     out2 = torch.full((4,) + SHAPE, 7.0, dtype=torch.float32, device="cuda")
     L.ae_decode(net.handle, grid_of(SHAPE), lat_in, torch.tensor(ms, device="cuda"), qs_in, fmt, 0x1, out2)
@@ -161,16 +183,48 @@ def test_train_step_gradients_and_adam_against_oracle(weighting):
     ae = oae.AE(net.prm32)
     fw = (meta[idx, :, 1].astype(np.float64) / np.float32(1e-7)) ** 2 if weighting else None
     loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True, field_weights=fw)
-    assert abs(loss - loss_o) / loss_o < 1e-3
     gg = unflat(g)
+    errs = {k: rel(gg[k], g_o[k]) for k in oae.NAMES}
+    print(f"train step B={B} weighting={weighting}: loss rel diff {abs(loss - loss_o) / loss_o:.2e}, "
+          "gradient rel err " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert abs(loss - loss_o) / loss_o < 1e-6
     for k in oae.NAMES:
-        assert rel(gg[k], g_o[k]) < 2e-2, k
+        assert errs[k] < 5e-4, k
     # Adam: the first step applied to the GPU's own gradients, in float64
     new = unflat(L.ae_get_params(net.handle))
     ref = {k: v.copy() for k, v in net.prm32.items()}
     oae.Adam(ref, lr=1e-3).step(ref, {k: gg[k] for k in oae.NAMES})
     for k in oae.NAMES:
         assert np.allclose(new[k], ref[k], rtol=0, atol=2e-6 + 1e-6 * np.abs(ref[k]).max()), k
+
+
+def test_train_step_batch_4096_against_oracle():
+    """One Adam step at the training batch of the workloads (4096 patch vectors):
+    the decoder's output layer and the weight-gradient products then run on the
+    128 x 128 work-group tiles (the batch-128 test above reaches only the 64 x 64
+    ones). Loss and all eight parameter gradients against the emulating oracle
+    over the whole batch."""
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    B = 4096
+    X = np.concatenate([oae.patchify(W.smooth_random_state(4, 64, 64, 64, seed=s)) for s in range(40, 48)])
+    assert X.shape[0] == B
+    Y, lo, r = oae.normalize(X, [1e-7] * 4)
+    ybits = rd.bf16_bits(Y)
+    yt = torch.tensor(ybits.view(np.int16), device="cuda")
+    idx = np.random.default_rng(41).permutation(B).astype(np.int32)
+    cfg = L.train_cfg(epochs=1, batch=B)
+    print("case: train step batch 4096", flush=True)
+    loss, g = L.ae_train_step(net.handle, yt, torch.tensor(idx, device="cuda"), B, 1e-3, cfg, want_grads=True)
+    ae = oae.AE(net.prm32)
+    loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True)
+    gg = unflat(g)
+    errs = {k: rel(gg[k], g_o[k]) for k in oae.NAMES}
+    print(f"train step B={B}: loss rel diff {abs(loss - loss_o) / loss_o:.2e}, gradient rel err "
+          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert abs(loss - loss_o) / loss_o < 1e-6
+    for k in oae.NAMES:
+        assert errs[k] < 2e-4, k
 
 
 def test_training_reduces_loss_and_beats_untrained():
@@ -224,14 +278,14 @@ def trained_net(p, every=4, epochs=40, weighting=0):
     L.ae_fit_beta(net.handle, g, cap, ncap, 1e-7)
     P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
     y = torch.empty((ncap * P, 2048), dtype=torch.int16, device="cuda")
-    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    meta = torch.empty((ncap * P, 4, 2), dtype=torch.float32, device="cuda")
     for q in range(ncap):
-        L.ae_normalize(net.handle, g, cap[q, 0], y[q * P:(q + 1) * P], meta)
+        L.ae_normalize(net.handle, g, cap[q, 0], y[q * P:(q + 1) * P], meta[q * P:(q + 1) * P])
     n = ncap * P
     batch = 64
     perm = torch.tensor(W.shuffles(n, epochs, seed=5), device="cuda")
     losses = L.ae_train(net.handle, y, n, L.train_cfg(epochs=epochs, batch=batch, lr=1e-3, decay_every=10,
-                                                     weighting=weighting), perm)
+                                                     weighting=weighting), perm, meta=meta)
     s.close()
     return net, losses
 
@@ -327,6 +381,79 @@ def test_incremental_states_stored_and_decoded():
         s.decode_delta(1)
 
 
+def two_source(p):
+    p.src = np.array([[4, 16, 20], [6, 12, 28]], dtype=np.int32)
+    p.wavelet = np.stack([p.wavelet[0], 0.6 * W.ricker(11.0, p.dt, p.nt) / p.dx ** 3]).astype(np.float32)
+    p.wavelet = p.wavelet.astype(np.float64)
+    p.noise = np.random.default_rng(1).standard_normal((2, p.nt, len(p.rec)))
+    return p
+
+
+@pytest.mark.parametrize("nsrc,mode", [(1, L.STORE_AE_BF16), (2, L.STORE_AE_BF16), (1, L.STORE_AE_FP8)])
+def test_incremental_store_latents_only_matches_codec(nsrc, mode):
+    """The incremental latent store without exact patches (K = 0): every decoded
+    incremental state dx_n equals the codec (ae_encode, ae_decode) applied to the
+    exact dx_n. The exact dx_n comes from the oracle's incremental forward driven
+    by the e^n the GPU decoded (wv_load_e), so both sides compress the same state
+    up to float32 rounding. The store's parts are checked together: the per-patch
+    (min, max) partials of the incremental stencil in slot n % 3, the encode (on
+    the third side stream for one source, on the main stream for two) and the
+    three rotating state buffers (levels 1 to 6 cover every slot twice). The
+    neighbouring level's codec output is far from each stored level, so a slot
+    mix-up would not pass."""
+    p = ae_problem(nt=40, shape=(32, 32, 40))
+    if nsrc == 2:
+        p = two_source(p)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    dc = np.asarray(p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 6.0, 2), np.float32).astype(np.float64)
+    s = WaveSolver.for_problem(p)
+    s.set_storage(mode, ae=raw)
+    s.set_delta_storage(True)
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    s.hessvec(p.c_start, dc)
+    T = p.nt
+    e_dec = np.zeros((T, nsrc) + s.shape)
+    for n in range(1, T):
+        e_dec[n] = s.load_e(n).cpu().numpy()
+    levels = [1, 2, 3, 4, 5, 6, T // 2, T - 1]
+    m = p.c_start * p.c_start
+    dm = 2.0 * p.c_start * dc
+    exact = {}
+    for src in range(nsrc):
+        dv, de = sol.zero_v(), np.zeros(sol.shape)
+        for n in range(T - 1):
+            dv, de = sol.step(dv, de, m, extra=dm * e_dec[n, src])
+            if n + 1 in levels:
+                exact[(n + 1, src)] = np.stack([de] + [dv[a] for a in sol.axes]).astype(np.float32)
+    fmt = L.LATENT_BF16 if mode == L.STORE_AE_BF16 else L.LATENT_FP8
+    Pn = 4 * 4 * 5
+    g = L.make_grid(*s.shape, p.dx, p.dt, T, 0, 1.0, 1, 0)
+    lat = torch.empty((Pn, 32), dtype=torch.int16 if fmt == L.LATENT_BF16 else torch.uint8, device="cuda")
+    meta = torch.empty((Pn, 4, 2), dtype=torch.float32, device="cuda")
+    qs = torch.empty((Pn,), dtype=torch.float32, device="cuda") if fmt == L.LATENT_FP8 else None
+    out = torch.empty((4,) + s.shape, dtype=torch.float32, device="cuda")
+
+    def codec(x):
+        L.ae_encode(raw.handle, g, torch.tensor(x, device="cuda"), fmt, lat, meta, qs)
+        L.ae_decode(raw.handle, g, lat, meta, qs, fmt, 0xF, out)
+        return out.cpu().numpy().astype(np.float64)
+
+    tol = 1e-3 if fmt == L.LATENT_BF16 else 1e-2
+    for n in levels:
+        stored = s.decode_delta(n, 0xF).cpu().numpy().astype(np.float64)
+        for src in range(nsrc):
+            x = exact[(n, src)]                               # dx_1 = 0: its code decodes to ~beta
+            ref = codec(x)
+            err = rel(stored[src], ref)
+            far = rel(codec(exact[(n - 1, src)]), ref) if (n - 1, src) in exact else float("nan")
+            print(f"sources {nsrc} mode {mode} level {n} source {src}: stored vs codec(exact) {err:.2e}, "
+                  f"neighbouring level {far:.2e}", flush=True)
+            assert err < tol, (n, src)
+            assert not far < 10 * tol, (n, src)
+
+
 def test_full_newton_hessvec_from_compressed_stores():
     """The full-Newton product from the AE stores (forward and incremental states
     compressed) equals the full-storage one bit for bit when every patch is exact."""
@@ -397,6 +524,36 @@ def test_full_newton_fp8_stores_reproducible():
         assert torch.equal(s.hessvec(p.c_start, dc), G1)
 
 
+@pytest.mark.parametrize("bits", [32, 16])
+def test_store_metadata_bits_against_oracle_codec(bits):
+    """The e the reverse solves read from the space store (latents only) against
+    the oracle's emulated codec applied to the exact state of the same solve:
+    normalise with float32 or bfloat16 (lo, r) (16-bit: lo rounded down and r up
+    first), encode, round the latent to bfloat16, decode the e rows, de-normalise.
+    Latent codes may differ at rounding ties, so the decoded e agrees to 2e-3; the
+    16-bit store is 16 B per patch and state smaller."""
+    p = ae_problem(nt=40, shape=(32, 32, 40))
+    raw = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    L.wv_set_ae_metadata(s.ctx, bits)
+    s.set_storage(L.STORE_AE_BF16, ae=raw)
+    Pn = 4 * 4 * 5
+    assert s.storage_bytes() == (p.nt - 1) * Pn * (32 * 2 + (16 if bits == 16 else 32))
+    _, _, cap = s.forward(p.c_start, p.wavelet, capture_every=13)
+    ae = oae.AE(raw.prm32)
+    for q, n in enumerate((13, 26, 39)):
+        x = cap[q, 0].cpu().numpy().astype(np.float64)
+        Y, lo, r = oae.normalize(oae.patchify(x), [1e-7] * 4, emulate=True, meta_bits=bits)
+        z = rd.bf16(ae.encode(Y, emulate=True))
+        e_ref = oae.unpatchify(oae.denormalize(ae.decode(z, emulate=True, rows=slice(0, 512)), lo, r), *s.shape)[0]
+        got = s.load_e(n)[0].cpu().numpy()
+        err = rel(got, e_ref)
+        print(f"metadata {bits} bits, level {n}: decoded e vs oracle codec {err:.2e}", flush=True)
+        assert err < 2e-3
+    with pytest.raises(L.WvError):
+        L.wv_set_ae_metadata(s.ctx, 8)
+
+
 def test_guard_falls_back_to_checkpointing():
     p = ae_problem(nt=120, shape=(32, 32, 32))
     sol = ow.solver_for(p)
@@ -415,12 +572,50 @@ def test_guard_falls_back_to_checkpointing():
     assert J == Jr and torch.equal(g, gr)
 
 
+@pytest.mark.parametrize("K", [0, 8])
+def test_guard_checks_states_spread_over_the_solve(K):
+    """The guard checks 16 stored states spread evenly over the forward solve (every
+    ceil((T-1)/16)-th: 8, 16, ..., 112 for T = 120) and the last (119), each decoded
+    as the reverse solve reads it (exception patches exact): the error it reports is
+    the largest L2 error of e among those states over the largest e norm among them,
+    recomputed here from the decoded store (wv_load_e) and the exact states of a
+    full-storage solve."""
+    p = ae_problem(nt=120, shape=(32, 32, 32))
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    raw = Net(W.ae_init(seed=4))
+    s = WaveSolver.for_problem(p)
+    L.wv_set_ae_exceptions(s.ctx, K)
+    s.set_storage(L.STORE_AE_BF16, ae=raw, guard_tol=1e30)
+    s.gradient(p.c_start, p.wavelet, d, sigma)
+    assert s.last_status == L.OK
+    _, gerr, degraded = s.stats()
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    full.gradient(p.c_start, p.wavelet, d, sigma)
+    levels = list(range(8, 120, 8)) + [119]
+    err, nrm = {}, {}
+    for n in range(1, 120):
+        dec = s.load_e(n).double()
+        ex = full.load_e(n).double()
+        err[n] = float(torch.linalg.norm(dec - ex))
+        nrm[n] = float(torch.linalg.norm(ex))
+    ref = max(err[n] for n in levels) / max(nrm[n] for n in levels)
+    worst = max(levels, key=err.get)
+    print(f"K {K}: guard error {gerr:.6e}, recomputed {ref:.6e} (largest error at level {worst}), last state "
+          f"alone {err[119] / max(nrm[n] for n in levels):.6e}", flush=True)
+    assert not degraded
+    assert abs(gerr - ref) <= 1e-9 * ref
+
+
 def test_compressed_gradient_and_hessvec():
     """Trained on snapshots of the forward solve itself; the compressed
-    gradient and Hv are judged against the uncompressed (full-storage) ones.
-    With the largest-range 2 % of patches kept exactly the gradient is within
-    0.1 relative L2 and cosine 0.995 on this 48^3 problem; latents alone are
-    reported, and an untrained network is far worse."""
+    gradient, Gauss-Newton and full-Newton Hv are judged against the
+    uncompressed (full-storage) ones. With the largest-range 2 % of patches kept
+    exactly the gradient is within 0.06 relative L2 and cosine 0.998 on this 48^3
+    problem; latents alone are held to their measured level, the network trained
+    with the physically weighted loss is reported beside the plain one, and an
+    untrained network is far worse."""
     p = ae_problem(nt=240, shape=(48, 48, 48))
     p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
     sol = ow.solver_for(p)
@@ -436,6 +631,7 @@ def test_compressed_gradient_and_hessvec():
     P = 6 * 6 * 6
     dc = p.c_start * W.direction_grf(p.c_start.shape, 6.0, 2)
     H0 = plain.hessvec(p.c_start, dc).cpu().numpy()
+    F0 = plain.hessvec(p.c_start, dc, gauss_newton=False).cpu().numpy()
     errs = {}
     for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
         for K in (0, 4):
@@ -446,16 +642,32 @@ def test_compressed_gradient_and_hessvec():
             gn = g.cpu().numpy().astype(np.float64)
             err = rel(gn, g0n)
             cos = float(np.sum(gn * g0n) / np.linalg.norm(gn) / np.linalg.norm(g0n))
-            H = s.hessvec(p.c_start, dc).cpu().numpy()
-            herr = rel(H, H0)
-            errs[(mode, K)] = (err, cos, herr)
-            print("mode", mode, "K", K, "grad rel err", err, "cos", cos, "Hv rel err", herr, flush=True)
             assert J == J0                  # the forward solve itself is not compressed
             assert s.storage_bytes() * 10 < plain.storage_bytes()
+            H = s.hessvec(p.c_start, dc).cpu().numpy()
+            herr = rel(H, H0)
+            # full Newton: the incremental states go through the incremental latent store
+            ferr = rel(s.hessvec(p.c_start, dc, gauss_newton=False).cpu().numpy(), F0)
+            errs[(mode, K)] = (err, cos, herr, ferr)
+            print("mode", mode, "K", K, "grad rel err", err, "cos", cos, "Hv rel err", herr,
+                  "full-Newton Hv rel err", ferr, flush=True)
+    # the weighted loss (each field slice's error in its physical scale) on the same data
+    netw, lw = trained_net(p, weighting=1)
+    for K in (0, 4):
+        s = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s.ctx, K)
+        s.set_storage(L.STORE_AE_BF16, ae=netw)
+        _, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+        gn = g.cpu().numpy().astype(np.float64)
+        print("weighted loss: K", K, "grad rel err", rel(gn, g0n), "Hv rel err",
+              rel(s.hessvec(p.c_start, dc).cpu().numpy(), H0), flush=True)
+    # bounds: the measured figures (K = 4: gradient 0.047, cosine 0.9989, Hv 0.064, full-Newton
+    # Hv 0.33, whose incremental states pass through a network trained on forward states only;
+    # K = 0: gradient 0.19, Hv 0.34) plus a margin for kernel changes that alter summation order
     for mode in (L.STORE_AE_BF16, L.STORE_AE_FP8):
-        err, cos, herr = errs[(mode, 4)]
-        assert err < 0.1 and cos > 0.995 and herr < 0.1
-        assert errs[(mode, 0)][0] < 0.35
+        err, cos, herr, ferr = errs[(mode, 4)]
+        assert err < 0.06 and cos > 0.998 and herr < 0.08 and ferr < 0.4
+        assert errs[(mode, 0)][0] < 0.25 and errs[(mode, 0)][2] < 0.45
     # an untrained network is far worse than the trained one
     raw = Net(W.ae_init(seed=4))
     L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))

@@ -40,6 +40,13 @@ def cosine(a, b):
     return float(a @ b / np.linalg.norm(a) / np.linalg.norm(b))
 
 
+# latents-only (K = 0) gradient at 256^3 x 2000 with the in-run network (bf16,
+# plain loss): measured 0.3998 / cosine 0.928; the bounds leave a margin for
+# kernel changes that alter the summation order
+K0_GRAD_BOUND = 0.45
+K0_COS_BOUND = 0.91
+
+
 def f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
@@ -113,9 +120,13 @@ def test_encode_decode_256_cube_sampled_patches():
     assert np.array_equal(meta_g[:, :, 1], np.asarray(r, np.float32))
     ae = oae.AE(prm32)
     z_ref = rd.bf16(ae.encode(Y, emulate=True))
-    z_gpu = rd.bf16_from_bits(lat.cpu().numpy().view(np.uint16)[sample])
-    print("encode rel err on sampled patches", rel(z_gpu, z_ref), flush=True)
-    assert rel(z_gpu, z_ref) < 5e-3
+    bits = lat.cpu().numpy().view(np.uint16)[sample]
+    z_gpu = rd.bf16_from_bits(bits)
+    same = float(np.mean(bits == rd.bf16_bits(z_ref)))
+    # codes differ only at rounding ties, by one step, or near zero by what a flipped hidden unit moves them
+    near = np.all(np.abs(z_gpu - z_ref) <= 2.0 ** -7 * np.abs(z_ref) + 3e-3 * np.sqrt(np.mean(z_ref ** 2)))
+    print("encode rel err on sampled patches", rel(z_gpu, z_ref), "identical codes", same, flush=True)
+    assert rel(z_gpu, z_ref) < 5e-4 and same > 0.99 and near
     # decoder: seeded latents (bf16) and metadata for every patch of the grid
     zs = rd.bf16(0.5 * rng.standard_normal((P, 32)))
     ms = np.zeros((P, 4, 2), np.float32)
@@ -132,11 +143,105 @@ def test_encode_decode_256_cube_sampled_patches():
     yhat = ae.decode(zs[sample], emulate=True)[:, :512]
     ref = ms[sample, 0, 0][:, None].astype(np.float64) + ms[sample, 0, 1][:, None].astype(np.float64) * yhat
     print("decode rel err on sampled patches", rel(got, ref), flush=True)
-    assert rel(got, ref) < 5e-3
+    assert rel(got, ref) < 3e-5
     L.ae_destroy(net)
 
 
+def test_compressed_gradient_256_cube_headline():
+    """The gradient workload exactly as the benchmark runs it (256^3 x 2000 steps,
+    network trained for 20 epochs at batch 4096 on every 10th state of the solve at
+    the start model, bf16 latents): with the 1 % largest-range patches of every
+    state kept exact (K = 328) the compressed gradient is within 5e-2 relative L2
+    of the checkpointed float32 gradient with cosine >= 0.99; latents alone (K = 0,
+    the paper's method) are reported and held to their measured level. A central
+    difference of the misfit along a GRF direction (h = 1e-3) checks both
+    gradients' directional derivative."""
+    p = rounded(W.problem_256(2000))
+    print("case", p.name, flush=True)
+    dev = torch.device("cuda", 0)
+    c = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    plain = WaveSolver.for_problem(p)
+    plain.set_storage(L.STORE_NONE)
+    clean, _, _ = plain.forward(torch.tensor(p.c_true, dtype=torch.float32, device=dev), wav)
+    sigma = 0.01 * float(clean.abs().max())
+    d = (clean.double() + sigma * torch.tensor(p.noise, device=dev)).float()
+    del clean
+    P = 32 ** 3
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    nsamp = (1999 // 10) * P
+    info = train_from_forward(plain, net, c, wav, every=10, epochs=20, batch=4096,
+                              perms=W.shuffles(nsamp, 20, seed=5))
+    print("training", info, flush=True)
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=64)
+    J0, g0 = ck.gradient(c, wav, d, sigma)
+    ck.close()
+    g0n = g0.double()
+    res = {}
+    for K in (328, 0):
+        ae = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(ae.ctx, K)
+        ae.set_storage(L.STORE_AE_BF16, ae=net)
+        J, g = ae.gradient(c, wav, d, sigma)
+        assert ae.last_status == 0 and J == J0
+        gn = g.double()
+        res[K] = (float(torch.linalg.norm(gn - g0n) / torch.linalg.norm(g0n)),
+                  float(torch.sum(gn * g0n) / torch.linalg.norm(gn) / torch.linalg.norm(g0n)), gn)
+        print(f"K {K}: gradient rel err {res[K][0]:.4f}, cosine {res[K][1]:.5f}", flush=True)
+        ae.close()
+    assert res[328][0] < 5e-2 and res[328][1] > 0.99
+    assert res[0][0] < K0_GRAD_BOUND and res[0][1] > K0_COS_BOUND
+    # directional derivative: (J(c + h u) - J(c - h u)) / 2h against <g, u>, u = c * GRF(12 cells)
+    u = c * torch.tensor(W.direction_grf(p.c_start.shape, 12.0, 2), dtype=torch.float32, device=dev)
+    h = 1e-3
+    Js = []
+    for sgn in (1.0, -1.0):
+        tr, _, _ = plain.forward(c + sgn * h * u, wav)
+        Js.append(float(torch.sum((tr.double() - d.double()) ** 2)) * p.dt / (2.0 * sigma ** 2))
+    fd = (Js[0] - Js[1]) / (2.0 * h)
+    ud = u.double()
+    dd = {"checkpoint": float(torch.sum(g0n * ud)), "K=328": float(torch.sum(res[328][2] * ud)),
+          "K=0": float(torch.sum(res[0][2] * ud))}
+    print("directional derivative: FD", fd, {k: (v, abs(v - fd) / abs(fd)) for k, v in dd.items()}, flush=True)
+    assert abs(dd["checkpoint"] - fd) < 1e-3 * abs(fd)
+    assert abs(dd["K=328"] - fd) < 2e-2 * abs(fd)
+
+
 # ----- 384^3 x 3000 ---------------------------------------------------------------------------------
+def test_gradient_fd_equals_gn_hessvec_384_cube():
+    """At a zero-residual point (data = F(c), noise-free) the Gauss-Newton and the
+    full Hessian coincide, so the central difference of the gradient along
+    dc = c * GRF(12 cells) with h = 1e-3 must reproduce the Gauss-Newton Hv. Full
+    384^3 x 3000 grid, every gradient and the Hv with revolve checkpointing (64
+    slots); the gradient at the point itself is zero."""
+    p = rounded(W.problem_384(3000))
+    print("case", p.name, flush=True)
+    dev = torch.device("cuda", 0)
+    c = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
+    wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
+    dc = torch.tensor(p.c_start * W.direction_grf(p.c_start.shape, 12.0, 2), dtype=torch.float32, device=dev)
+    ck = WaveSolver.for_problem(p)
+    ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=64)
+    d, _, _ = ck.forward(c, wav)
+    sigma = 0.01 * float(d.abs().max())
+    h = 1e-3
+    gs = []
+    for sgn in (1.0, -1.0):
+        _, g = ck.gradient(c + sgn * h * dc, wav, d, sigma)
+        gs.append(g.double())
+    fd = (gs[0] - gs[1]) / (2.0 * h)
+    del gs
+    J, g = ck.gradient(c, wav, d, sigma)
+    assert J == 0.0 and not bool(torch.any(g))
+    H = ck.hessvec(c, dc).double()
+    err = float(torch.linalg.norm(fd - H) / torch.linalg.norm(H))
+    print("FD of the gradient vs GN Hv: rel err", err, "cos", float(torch.sum(fd * H) / torch.linalg.norm(fd) /
+                                                                   torch.linalg.norm(H)), flush=True)
+    assert err < 1e-3
+
+
+
 def test_gn_hessvec_384_cube():
     """The Gauss-Newton workload at full size: the checkpointed GN Hessian is
     symmetric to FP32 round-off, and the compressed Hv (trained network, 1 %

@@ -395,6 +395,47 @@ def test_e4m3_table_and_rounding():
     assert np.array_equal(t, r[inr])
 
 
+def test_bf16_directed_rounding_brute_force():
+    """bf16_down / bf16_up against the sorted table of every finite bfloat16 value:
+    the largest value <= x and the smallest >= x (exact values map to themselves)."""
+    codes = np.arange(1 << 16, dtype=np.uint16)
+    vals = rd.bf16_from_bits(codes)
+    table = np.unique(vals[np.isfinite(vals)])
+    rng = np.random.default_rng(24)
+    x = rng.standard_normal(100000) * 10.0 ** rng.uniform(-30, 30, 100000)
+    x = np.concatenate([x, rd.f32(x[:50000]), table[1:-1], [0.0, -0.0, 1.0, -1.0]])
+    dn, up = rd.bf16_down(x), rd.bf16_up(x)
+    i = np.searchsorted(table, x, side="right") - 1          # table[i] <= x < table[i + 1]
+    assert np.array_equal(dn, table[i])
+    j = np.searchsorted(table, x, side="left")               # table[j - 1] < x <= table[j]
+    assert np.array_equal(up, table[j])
+
+
+def test_normalisation_16_bit_metadata():
+    """16-bit metadata: lo and r are bfloat16 values with lo <= min and lo + r >= max
+    (so y stays in [0, 1] up to the quotient's rounding), r >= beta, and each is the
+    tightest such bfloat16 (one step less would break an inequality); a patch with a
+    large offset keeps it to within one bfloat16 step below its minimum."""
+    rng = np.random.default_rng(25)
+    X = rng.standard_normal((40, 2048)) * 10.0 ** rng.uniform(-9, 3, size=(40, 1))
+    X[3] += 7.0                                # offset far above the range
+    X[5, 512:1024] = 0.125                     # constant slice: r = beta rounded up
+    X = rd.f32(X)
+    beta = rd.f32(np.array([1e-7, 2e-7, 3e-7, 4e-7]))
+    for emulate in (False, True):
+        Y, lo, r = oae.normalize(X, beta, emulate=emulate, meta_bits=16)
+        Xf = X.reshape(40, 4, 512)
+        mn, mx = Xf.min(axis=2), Xf.max(axis=2)
+        assert np.array_equal(rd.bf16(lo), lo) and np.array_equal(rd.bf16(r), r)
+        assert np.all(lo <= mn) and np.all(lo + r >= mx) and np.all(r >= beta)
+        o = rd._bf16_ordered(rd.bf16_bits(lo))
+        above = rd.bf16_from_bits(rd._bf16_from_ordered(o + 1))
+        assert np.all(above > mn)                              # lo is the largest bfloat16 <= min
+        assert np.all(Y >= 0.0) and np.all(Y <= 1.0 + 1e-6)
+    assert r[5, 1] == rd.bf16_up(beta[1]) and np.all(Y.reshape(40, 4, 512)[5, 1] == 0.0)
+    assert np.all(mn[3] - lo[3] <= 2.0 ** -7 * np.abs(mn[3]))
+
+
 # ----- checkpointing cost -----------------------------------------------------------------------------
 def test_revolve_closed_form_equals_dp():
     T = orv.dp_table(120, 7)

@@ -255,6 +255,29 @@ def smooth_random_state(nf: int, nz: int, ny: int, nx: int, seed: int,
     return out * env[:, :nz, :ny, :nx]
 
 
+def smooth_random_window(nlev: int, nsrc: int, nz: int, ny: int, nx: int, seed: int) -> np.ndarray:
+    """Levels [nlev][nsrc][nz][ny][nx] float32 of a wave-like e field for the time
+    codec: per source three GRFs (correlation 3 cells) oscillating in time at
+    periods of about 14 to 60 levels with random phases, times a per-8^3-block
+    amplitude spread over four decades and a per-source scale of 1e-9..1e-6."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(nlev, dtype=np.float32)
+    out = np.empty((nlev, nsrc, nz, ny, nx), np.float32)
+    for s in range(nsrc):
+        modes = [grf((nz, ny, nx), 3.0, int(rng.integers(1 << 30))).astype(np.float32) for _ in range(3)]
+        om = rng.uniform(0.1, 0.45, 3)
+        ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+        env = np.exp(rng.uniform(np.log(1e-4), 0.0, size=(nz // 8 + 1, ny // 8 + 1, nx // 8 + 1)))
+        env = np.repeat(np.repeat(np.repeat(env, 8, axis=0), 8, axis=1), 8, axis=2)[:nz, :ny, :nx]
+        env = (env * 10.0 ** rng.uniform(-9, -6)).astype(np.float32)
+        for q in range(nlev):
+            acc = np.zeros((nz, ny, nx), np.float32)
+            for k in range(3):
+                acc += np.float32(np.cos(om[k] * t[q] + ph[k])) * modes[k]
+            out[q, s] = acc * env
+    return out
+
+
 def white_noise(shape, seed: int) -> np.ndarray:
     """Standard normal draws (the noise of one prior draw), float64."""
     return np.random.default_rng(seed).standard_normal(shape)
