@@ -46,12 +46,19 @@ def parse():
     ap.add_argument("--snapshot-every", type=int, default=10)
     ap.add_argument("--exceptions", type=float, default=0.01, help="fraction of patches kept exactly")
     ap.add_argument("--latent", choices=["bf16", "fp8"], default="bf16")
+    ap.add_argument("--weighting", type=int, default=0,
+                    help="training loss: 0 plain MSE of the normalised vectors (the paper's), 1 each field slice "
+                         "weighted by (r / beta)^2")
     ap.add_argument("--checkpoints", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--multisource", action="store_true",
-                    help="kernel rates of the 8-source 512 x 512 x 256 workload with FP8 latents (horizon --ms-nt); "
-                         "prints its own JSON line")
-    ap.add_argument("--ms-nt", type=int, default=120)
+                    help="the 8-source 512 x 512 x 256 workload with FP8 latents at its full horizon (--ms-nt): "
+                         "compressed gradient vs checkpointing source by source, kernel rates; prints its own JSON "
+                         "line")
+    ap.add_argument("--ms-nt", type=int, default=4000)
+    ap.add_argument("--ms-every", type=int, default=500, help="training states of the multi-source leg")
+    ap.add_argument("--ms-epochs", type=int, default=10)
+    ap.add_argument("--ms-rate-nt", type=int, default=120, help="horizon of the multi-source kernel-rate pass")
     ap.add_argument("--bayes", action="store_true",
                     help="training on prior draws (Algorithm 1) against in-run snapshots at 256^3: "
                          "compression and gradient errors on the start, true, midway and a held-out model")
@@ -136,6 +143,36 @@ def counters_pass():
                       "stencil_source_sha256": stencil_source_hash()}), flush=True)
 
 
+def timed_kernels(sol, c0, wav, d_obs, sigma, every=4):
+    """Mean launch durations per kernel class over one gradient, with HIP events
+    around every `every`-th launch of each class (a pass of its own, so the timed
+    gradients carry no events)."""
+    sol.set_timing(every)
+    sol.gradient(c0, wav, d_obs, sigma)
+    kt = sol.kernel_times()
+    sol.set_timing(0)
+    return kt
+
+
+def stream_ceilings(torch, dev, n, reps=20):
+    """HBM rate (read + write bytes per second) of the library's streaming probe with
+    the stencils' array mixes, n floats per array: the practical ceiling beside the
+    published 8 TB/s."""
+    from paper_2304_04781_amd import _lib as L
+    n = n // 4 * 4
+    inp = torch.ones((7, n), dtype=torch.float32, device=dev)
+    out = torch.empty((5, n), dtype=torch.float32, device=dev)
+    res = {}
+    for name, (a, b) in (("copy_1in_1out", (1, 1)), ("forward_mix_5in_4out", (5, 4)),
+                         ("adjoint_mix_7in_5out", (7, 5))):
+        us = L.wv_stream_probe(inp, out, a, b, n, reps)
+        res[name] = round((a + b) * 4.0 * n / (us * 1e-6) / 1e9, 1)
+    torch.cuda.synchronize()
+    del inp, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def gemm_peak_tflops(torch, dev, n=8192, reps=10):
     """Dense bf16 GEMM rate of the vendor library (torch.matmul, n x n x n, contiguous
     operands): the measured MFMA reference next to the published 2.5 PFLOP/s."""
@@ -175,13 +212,17 @@ def copy_peak_gbs(torch, dev, nbytes=1 << 30, reps=10):
 
 
 def multisource_pass(args):
-    """The 8-source 512 x 512 x 256 workload (one launch per step for all sources,
-    FP8 latents, 1 % exact patches) over a shortened horizon: mean kernel durations
-    and their HBM / MFMA rates. The network is untrained (rates do not depend on it)."""
+    """The 8-source 512 x 512 x 256 workload at its full horizon (--ms-nt, default 4000
+    steps): one launch per step for all sources, FP8 latents with per-patch scales and
+    16-bit (lo, r) metadata, latents only (the 8 x 3999 stored states take 218 GB; with
+    float32 metadata 285 GB, and exact patches would add 86 GB). The network is trained
+    on a random half of the patches of every 500th state of all sources at the start
+    model; the summed compressed gradient is compared with the checkpointed float32
+    gradient computed source by source (64 slots each). Also reports kernel rates."""
     import torch
     import workloads as W
     from paper_2304_04781_amd import _lib as L
-    from paper_2304_04781_amd.compressor import Autoencoder
+    from paper_2304_04781_amd import compressor as C
     from paper_2304_04781_amd.solver import WaveSolver
     L.load()
     dev = torch.device("cuda", 0)
@@ -191,20 +232,104 @@ def multisource_pass(args):
     P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
     c0 = torch.tensor(p.c_start, dtype=torch.float32, device=dev)
     wav = torch.tensor(p.wavelet, dtype=torch.float32, device=dev)
-    d = torch.zeros((S, T, len(p.rec)), dtype=torch.float32, device=dev)
-    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    t_all = time.perf_counter()
+    # observations: the 8-source forward solve at the true model plus 1 % noise
+    plain = WaveSolver.for_problem(p)
+    plain.set_storage(L.STORE_NONE)
+    clean, _, _ = plain.forward(torch.tensor(p.c_true, dtype=torch.float32, device=dev), wav)
+    sigma = 0.01 * float(clean.abs().max())
+    d = (clean.double() + sigma * torch.tensor(p.noise, device=dev)).float()
+    del clean
+    log(f"multisource: observations done ({time.perf_counter() - t_all:.1f} s)")
+    # training vectors: half the patches of every ms_every-th state of every source at c0
+    every = args.ms_every
+    net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    ncap = (T - 1) // every
+    rows = W.keep_rows(1, ncap * S, P, 0.5, seed=6)
+    y, meta, t_cap = C.prior_draw_samples(plain, net, [c0], p.wavelet, every, rows)
+    n = int(y.shape[0])
+    info = C.train_samples(net, y, meta, epochs=args.ms_epochs, batch=args.batch,
+                           perms=W.shuffles(n, args.ms_epochs, seed=5))
+    del y, meta
+    plain.close()
+    torch.cuda.empty_cache()
+    log(f"multisource: training {info}")
+    # compressed gradient, all sources per launch
     ae = WaveSolver.for_problem(p)
-    L.wv_set_ae_exceptions(ae.ctx, int(round(0.01 * P)))
+    L.wv_set_ae_metadata(ae.ctx, 16)
     ae.set_storage(L.STORE_AE_FP8, ae=net)
-    ae.gradient(c0, wav, d, 1.0)
+    store_gb = ae.storage_bytes() / 1e9
+    log(f"multisource: AE store {store_gb:.1f} GB")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ae.set_timing(2)
-    t0 = time.perf_counter()
-    ae.gradient(c0, wav, d, 1.0)
+    ev0.record()
+    J, g_ae = ae.gradient(c0, wav, d, sigma)
+    ev1.record()
     torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
-    kt = ae.kernel_times()
-    ae.set_timing(0)
+    t_ae = ev0.elapsed_time(ev1) / 1e3
+    log(f"multisource: AE gradient {t_ae:.2f} s")
+    # kernel rates over a short horizon (the same kernels; timed launches every 2nd)
+    g_ae = g_ae.double().cpu()
+    ae.close()
+    torch.cuda.empty_cache()
+    # checkpointed reference, one source at a time (64 slots of one wavefield each)
+    g_ck = torch.zeros(N, dtype=torch.float64)
+    J_ck, t_ck = 0.0, 0.0
+    import copy
+    for src in range(S):
+        ps = copy.copy(p)
+        ps.src = ps.src[src:src + 1]
+        ps.wavelet = ps.wavelet[src:src + 1]
+        ps.noise = ps.noise[src:src + 1]
+        ck = WaveSolver.for_problem(ps)
+        ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Js, gs = ck.gradient(c0, wav[src:src + 1].contiguous(), d[src:src + 1].contiguous(), sigma)
+        torch.cuda.synchronize()
+        t_ck += time.perf_counter() - t0
+        J_ck += Js
+        g_ck += gs.double().cpu()
+        ck.close()
+        log(f"multisource: checkpointed source {src} done ({t_ck:.1f} s so far)")
+    err = float(torch.linalg.norm(g_ae - g_ck) / torch.linalg.norm(g_ck))
+    cos = float(torch.sum(g_ae * g_ck) / torch.linalg.norm(g_ae) / torch.linalg.norm(g_ck))
+    # kernel rates on a short horizon of the same grid
+    rates = multisource_rates(args, p, net, c0, wav)
+    print(json.dumps({"workload": f"{p.name}: 8 sources per launch, FP8 latents + per-patch scale, 16-bit (lo, r) "
+                                  f"metadata, latents only, horizon {T} steps",
+                      "grid": [p.nz, p.ny, p.nx], "sources": S, "nt": T,
+                      "training": info, "capture_s": round(t_cap, 2),
+                      "ae_gradient_s": round(t_ae, 3), "checkpoint_gradient_s_sum_over_sources": round(t_ck, 3),
+                      "speedup_vs_checkpoint": round(t_ck / t_ae, 4),
+                      "summed_grad_rel_err_vs_checkpoint_fp32": round(err, 5), "summed_grad_cos": round(cos, 6),
+                      "misfit": {"ae": J, "checkpoint_sum": J_ck},
+                      "ae_store_GB": round(store_gb, 2),
+                      "compression_vs_float32_history": round(16.0 * N * (T - 1) * S / (store_gb * 1e9), 1),
+                      "kernels": rates, "wall_s": round(time.perf_counter() - t_all, 1)}), flush=True)
+
+
+def multisource_rates(args, p, net, c0, wav):
+    """Mean kernel durations of the 8-source workload over a short horizon (the same grid
+    and launches) and their HBM / MFMA rates."""
+    import torch
+    import workloads as W
+    from paper_2304_04781_amd import _lib as L
+    from paper_2304_04781_amd.solver import WaveSolver
+    import copy
+    T = args.ms_rate_nt
+    pr = copy.copy(p)
+    pr.nt = T
+    S, N = len(pr.src), pr.n
+    P = (pr.nz // 8) * (pr.ny // 8) * (pr.nx // 8)
+    d = torch.zeros((S, T, len(pr.rec)), dtype=torch.float32, device=c0.device)
+    ae = WaveSolver.for_problem(pr)
+    L.wv_set_ae_metadata(ae.ctx, 16)
+    ae.set_storage(L.STORE_AE_FP8, ae=net)
+    w = wav[:, :T].contiguous()
+    ae.gradient(c0, w, d, 1.0)
+    kt = timed_kernels(ae, c0, w, d, 1.0, every=2)
+    ae.close()
     blk = L.wv_accumulation_block()
     work = {  # per timed launch (the stencils launch all sources at once; encode/decode time one state)
         "forward_stencil": ("hbm", (32.0 * S + 4.0) * N),
@@ -218,19 +343,17 @@ def multisource_pass(args):
             continue
         row = {"us": round(us, 2), "timed_launches": n}
         if name in work:
-            kind, w = work[name]
-            rate = w / (us * 1e-6)
+            kind, wk = work[name]
+            rate = wk / (us * 1e-6)
             if kind == "hbm":
                 row.update({"GB/s": round(rate / 1e9, 1), "frac_hbm": round(rate / 1e9 / HBM_PEAK_GBS, 4)})
             else:
                 row.update({"TFLOP/s": round(rate / 1e12, 1),
                             "frac_mfma_bf16": round(rate / 1e12 / BF16_PEAK_TFLOPS, 4)})
         rows[name] = row
-    print(json.dumps({"workload": f"{p.name}: 8 sources, FP8 latents, 1 % exact patches, horizon {T} steps",
-                      "grid": [p.nz, p.ny, p.nx], "sources": S, "gradient_s": round(t_grad, 3),
-                      "store_GB": round(ae.storage_bytes() / 1e9, 2), "kernels": rows,
-                      "note": "with several sources the encode and decode run in order on the main stream; "
-                              "the exception selection and copy on a side stream"}), flush=True)
+    rows["note"] = (f"horizon {T} steps; with several sources the encode and decode run in order on the main "
+                    "stream")
+    return rows
 
 
 def bayes_pass(args):
@@ -659,7 +782,7 @@ def main():
     nsamp = ((T - 1) // args.snapshot_every) * P * len(p.src)
     perms = W.shuffles(nsamp, args.epochs, seed=5)
     train_info = train_from_forward(solver, net, c0, wav, every=args.snapshot_every, epochs=args.epochs,
-                                    batch=args.batch, perms=perms)
+                                    batch=args.batch, perms=perms, weighting=args.weighting)
     del perms
     t_train_total = time.perf_counter() - t0
     log(f"training {train_info}")
@@ -672,8 +795,7 @@ def main():
     for _ in range(args.warmup):
         ae_solver.gradient(c0, wav, d_obs, sigma)
     torch.cuda.synchronize()
-    # per-kernel durations: HIP events around every 4th launch, on the library's stream
-    ae_solver.set_timing(4)
+    # the timed gradients run with the library's kernel timing off
     times = []
     g_ae = None
     for _ in range(args.steps):
@@ -684,8 +806,9 @@ def main():
         torch.cuda.synchronize()
         times.append(ev0.elapsed_time(ev1) / 1e3)
     t_ae = float(np.median(times))
-    kt_ae = ae_solver.kernel_times()
-    ae_solver.set_timing(0)
+    # per-kernel durations from one more gradient: HIP events around every 4th launch of
+    # each kernel class, on the stream that runs it
+    kt_ae = timed_kernels(ae_solver, c0, wav, d_obs, sigma)
     status = ae_solver.last_status
     store_bytes = ae_solver.storage_bytes()
     log(f"AE gradient {t_ae:.3f} s (runs {['%.3f' % x for x in times]}), store {store_bytes / 1e9:.2f} GB")
@@ -696,17 +819,17 @@ def main():
     ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=args.checkpoints)
     J_ck, g_ck = ck.gradient(c0, wav, d_obs, sigma)
     torch.cuda.synchronize()
-    ck.set_timing(4)
+    nrep = max(1, min(args.steps, 5))   # 5 timed runs of each reference path (1 warm-up above)
     times_ck = []
-    for _ in range(max(1, min(args.steps, 2))):
+    for _ in range(nrep):
+        torch.cuda.synchronize()
         ev0.record()
         J_ck, g_ck = ck.gradient(c0, wav, d_obs, sigma)
         ev1.record()
         torch.cuda.synchronize()
         times_ck.append(ev0.elapsed_time(ev1) / 1e3)
     t_ck = float(np.median(times_ck))
-    kt_ck = ck.kernel_times()
-    ck.set_timing(0)
+    kt_ck = timed_kernels(ck, c0, wav, d_obs, sigma)
     fsteps, _, _ = ck.stats()
     ck_bytes = ck.storage_bytes()
     log(f"checkpointed gradient {t_ck:.3f} s, {fsteps} forward steps; kernel times {kt_ck}")
@@ -718,14 +841,19 @@ def main():
                            device=dev)
     hv = {}
     for name, sol in (("ae", ae_solver), ("checkpoint", ck)):  # both hold the last gradient's c0
-        torch.cuda.synchronize()
-        ev0.record()
-        Hv = sol.hessvec(c0, dc)
-        ev1.record()
-        torch.cuda.synchronize()
-        hv[name] = (ev0.elapsed_time(ev1) / 1e3, Hv.double())
+        runs = []
+        for _ in range(nrep):
+            torch.cuda.synchronize()
+            ev0.record()
+            Hv = sol.hessvec(c0, dc)
+            ev1.record()
+            torch.cuda.synchronize()
+            runs.append(ev0.elapsed_time(ev1) / 1e3)
+        hv[name] = (float(np.median(runs)), Hv.double(), runs)
     h_ae, h_ck = hv["ae"][1], hv["checkpoint"][1]
     hessvec = {"ae_s": round(hv["ae"][0], 4), "checkpoint_s": round(hv["checkpoint"][0], 4),
+               "runs_s": {k: [round(x, 4) for x in hv[k][2]] for k in hv},
+               "min_s": {k: round(min(hv[k][2]), 4) for k in hv},
                "speedup_vs_checkpoint": round(hv["checkpoint"][0] / hv["ae"][0], 4),
                "rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(h_ae - h_ck) / torch.linalg.norm(h_ck)), 5),
                "cos_vs_checkpoint_fp32": round(float(torch.sum(h_ae * h_ck) / (torch.linalg.norm(h_ae) *
@@ -742,8 +870,37 @@ def main():
     hessvec["full_newton_vs_gn_rel_diff"] = round(float(torch.linalg.norm(Hf.double() - h_ae) /
                                                         torch.linalg.norm(h_ae)), 5)
     hessvec["store_with_incremental_GB"] = round(ae_solver.storage_bytes() / 1e9, 3)
-    del h_ae, hv
+    del hv
     log(f"GN Hv: {hessvec}")
+
+    # ---- the paper's method as published: latents only, no exact patches (K = 0), same network
+    k0 = WaveSolver.for_problem(p)
+    k0.set_storage(fmt, ae=net)
+    k0.gradient(c0, wav, d_obs, sigma)
+    runs0 = []
+    for _ in range(nrep):
+        torch.cuda.synchronize()
+        ev0.record()
+        _, g0 = k0.gradient(c0, wav, d_obs, sigma)
+        ev1.record()
+        torch.cuda.synchronize()
+        runs0.append(ev0.elapsed_time(ev1) / 1e3)
+    H0 = k0.hessvec(c0, dc).double()
+    g0d, gckd = g0.double(), g_ck.double()
+    latents_only = {
+        "exact_patches_per_state": 0, "gradient_s": round(float(np.median(runs0)), 4),
+        "gradient_runs_s": [round(x, 4) for x in runs0],
+        "speedup_vs_checkpoint": round(t_ck / float(np.median(runs0)), 4),
+        "grad_rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(g0d - gckd) / torch.linalg.norm(gckd)), 5),
+        "grad_cos_vs_checkpoint_fp32": round(float(torch.sum(g0d * gckd) / torch.linalg.norm(g0d) /
+                                                   torch.linalg.norm(gckd)), 6),
+        "hv_rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(H0 - h_ck) / torch.linalg.norm(h_ck)), 5),
+        "hv_cos_vs_checkpoint_fp32": round(float(torch.sum(H0 * h_ck) / torch.linalg.norm(H0) /
+                                                 torch.linalg.norm(h_ck)), 6),
+        "store_GB": round(k0.storage_bytes() / 1e9, 3)}
+    k0.close()
+    del g0, H0, g0d, gckd, h_ae
+    log(f"latents only (K = 0): {latents_only}")
 
     # ---- the time-compression scheme on the same workload (e on 4^3 blocks x 32 levels,
     # 1 % exact vectors per window), against the same checkpointed gradient and Hv
@@ -770,8 +927,9 @@ def main():
 
     copy_gbs = copy_peak_gbs(torch, dev)
     gemm_tf = gemm_peak_tflops(torch, dev)
+    probe = stream_ceilings(torch, dev, N)
     log(f"library bf16 GEMM {gemm_tf:.0f} TFLOP/s")
-    log(f"device copy {copy_gbs:.0f} GB/s")
+    log(f"device copy {copy_gbs:.0f} GB/s; streaming probe {probe}")
 
     # ---- rooflines: algorithmic bytes (flops) per launch over the measured mean launch duration
     per_launch = {
@@ -807,6 +965,8 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kernels[dom]["frac_hbm"], 4),
                     "measured_copy_GBps": round(copy_gbs, 1),
                     "frac_of_copy": round(kernels[dom]["GB/s"] / copy_gbs, 4),
+                    "frac_of_streaming_mix": round(kernels[dom]["GB/s"] / probe[
+                        "adjoint_mix_7in_5out" if dom == "adjoint_stencil" else "forward_mix_5in_4out"], 4),
                     "traffic": measured_traffic(dom), "mean_launch_us": round(kernels[dom]["us"], 2),
                     "algorithmic_bytes_per_launch": work}
         if dom == "forward_stencil" and "encode" in kernels:
@@ -858,6 +1018,7 @@ def main():
         "gradient_runs_s": {"ae": [round(x, 4) for x in times], "ae_min": round(min(times), 4),
                             "checkpoint": [round(x, 4) for x in times_ck], "checkpoint_min": round(min(times_ck), 4)},
         "gn_hessvec": hessvec,
+        "latents_only": latents_only,
         "time_compression": time_scheme,
         "newton_iteration": newton,
         "grad_rel_err_vs_checkpoint_fp32": round(rel_err, 5),
@@ -867,13 +1028,17 @@ def main():
         "ae_store_GB": round(store_bytes / 1e9, 3),
         "compression": {"latent_only": 2048 * 4 / (32 * (2 if args.latent == "bf16" else 1)),
                         "effective_vs_float32_history": round(4.0 * 4 * N * (T - 1) / store_bytes, 1)},
-        "train": dict(train_info, wall_s=round(t_train_total, 2)),
+        "train": dict(train_info, wall_s=round(t_train_total, 2), weighting=args.weighting),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
-        "measured_peaks": {"device_copy_GBps": round(copy_gbs, 1), "library_bf16_gemm_TFLOPs": round(gemm_tf, 1)},
+        "measured_peaks": {"device_copy_GBps": round(copy_gbs, 1), "library_bf16_gemm_TFLOPs": round(gemm_tf, 1),
+                           "streaming_probe_GBps": probe},
         # the same stencil kernels with the GPU to themselves (no encode or decode beside them)
         "checkpoint_kernels": {k: dict({"us": round(us, 2), "timed_launches": n},
                                        **({"GB/s": round(per_launch[k][1] / (us * 1e-6) / 1e9, 1),
-                                           "frac_hbm": round(per_launch[k][1] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                                           "frac_hbm": round(per_launch[k][1] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                                           "frac_of_streaming_mix": round(per_launch[k][1] / (us * 1e-6) / 1e9 / probe[
+                                               "adjoint_mix_7in_5out" if k == "adjoint_stencil"
+                                               else "forward_mix_5in_4out"], 4)}
                                           if k in per_launch and per_launch[k][0] == "hbm" else {}))
                                for k, (us, n) in kt_ck.items() if n},
         "first_gradient_s": round(t_train_total + t_ae, 3),
@@ -908,7 +1073,7 @@ def time_leg(args, p, solver, c0, wav, d_obs, sigma, g_ck, h_ck, dc, t_ck, hv_ck
     tm.gradient(c0, wav, d_obs, sigma)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     times = []
-    for _ in range(2):
+    for _ in range(3):
         torch.cuda.synchronize()
         ev0.record()
         _, g = tm.gradient(c0, wav, d_obs, sigma)
@@ -931,9 +1096,10 @@ def time_leg(args, p, solver, c0, wav, d_obs, sigma, g_ck, h_ck, dc, t_ck, hv_ck
     torch.cuda.synchronize()
     t_hf = ev0.elapsed_time(ev1) / 1e3
     hf, hs = Hf.double(), hf_space.double()
-    t_g = min(times)
+    t_g = float(np.median(times))
     out = {"exact_vectors_per_window": K, "train_s": info["train_s"],
            "gradient_s": round(t_g, 4), "gradient_runs_s": [round(x, 4) for x in times],
+           "gradient_min_s": round(min(times), 4),
            "gradients_per_hour": round(3600.0 / t_g, 1), "speedup_vs_checkpoint": round(t_ck / t_g, 4),
            "grad_rel_err_vs_checkpoint_fp32": round(float(torch.linalg.norm(gt - gc) / torch.linalg.norm(gc)), 5),
            "grad_cos_vs_checkpoint_fp32": round(float(torch.sum(gt * gc) / torch.linalg.norm(gt) /
@@ -1013,7 +1179,12 @@ def cpu_baseline(p, T, nsteps=20):
         acc += e * q
     t_a = (time.perf_counter() - t0) / nsteps
     t_grad = T * t_f + (T - 1) * t_a
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return {"value": round(3600.0 / t_grad, 4), "unit": "gradients/hour", "cores": 1, "kind": "oracle",
+            "host_cores": os.cpu_count(), "host_cores_usable": affinity,
             "sample": f"{nsteps} forward + {nsteps} adjoint FP64 numpy steps on the {p.nz}x{p.ny}x{p.nx} grid "
                       f"({t_f:.2f} s + {t_a:.2f} s per step), extrapolated to {T} + {T - 1} steps"}
 
