@@ -255,6 +255,8 @@ def multisource_pass(args):
     torch.cuda.empty_cache()
     log(f"multisource: training {info}")
     # compressed gradient, all sources per launch
+    free, total = torch.cuda.mem_get_info()
+    log(f"multisource: device memory free {free / 1e9:.1f} GB of {total / 1e9:.1f} GB")
     ae = WaveSolver.for_problem(p)
     L.wv_set_ae_metadata(ae.ctx, 16)
     ae.set_storage(L.STORE_AE_FP8, ae=net)
@@ -269,7 +271,7 @@ def multisource_pass(args):
     t_ae = ev0.elapsed_time(ev1) / 1e3
     log(f"multisource: AE gradient {t_ae:.2f} s")
     # kernel rates over a short horizon (the same kernels; timed launches every 2nd)
-    g_ae = g_ae.double().cpu()
+    g_ae = g_ae.double().cpu().reshape(-1)
     ae.close()
     torch.cuda.empty_cache()
     # checkpointed reference, one source at a time (64 slots of one wavefield each)
@@ -289,7 +291,7 @@ def multisource_pass(args):
         torch.cuda.synchronize()
         t_ck += time.perf_counter() - t0
         J_ck += Js
-        g_ck += gs.double().cpu()
+        g_ck += gs.double().cpu().reshape(-1)
         ck.close()
         log(f"multisource: checkpointed source {src} done ({t_ck:.1f} s so far)")
     err = float(torch.linalg.norm(g_ae - g_ck) / torch.linalg.norm(g_ck))
