@@ -376,17 +376,26 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
 // Decode: DEC_NW waves per work-group of DEC_BM patches; wave w owns hidden units
 // and field-f outputs [OPW w, OPW w + OPW). W4 fragments are read from L2 PFD
 // k-steps ahead of their use.
+// 8 waves over 64 patches, at least 4 waves per SIMD: two work-groups share a CU (about
+// 68 KB of LDS each), so one computes while the other writes its outputs, and a work-group
+// also fits beside stencil work-groups (36 us alone at 256^3, against 42 us for 16 waves
+// over 128 patches, one work-group per CU)
 #ifndef WV_DEC_WAVES
-#define WV_DEC_WAVES 16
+#define WV_DEC_WAVES 8
 #endif
 #ifndef WV_DEC_PF
 #define WV_DEC_PF 2
+#endif
+// minimum waves per SIMD asked of the register allocator (0: no request)
+#ifndef WV_DEC_WPE
+#define WV_DEC_WPE 4
 #endif
 constexpr int DEC_NW = WV_DEC_WAVES;
 constexpr int DEC_NT = DEC_NW * 64;
 
 template <int L>
-__global__ void __launch_bounds__(DEC_NT) decode_kernel(const DecArgs a)
+__global__ void __launch_bounds__(DEC_NT) __attribute__((amdgpu_waves_per_eu(WV_DEC_WPE > 0 ? WV_DEC_WPE : 1)))
+    decode_kernel(const DecArgs a)
 {
     constexpr int BM = DEC_BM;         // patches per work-group
     constexpr int IT = BM / 16;        // 16-row tiles

@@ -73,7 +73,7 @@ struct ExcPatches {
     const int* rng;
 };
 #ifndef WV_DEC_BM
-#define WV_DEC_BM 128
+#define WV_DEC_BM 64
 #endif
 constexpr int DEC_BM = WV_DEC_BM;  // patches per decode work-group
 // Decompress the fields in field_mask into state [4][N]; with exc, the e values of
