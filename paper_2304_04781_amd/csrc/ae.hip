@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
 #pragma unroll
                 for (int r = 0; r < 4; ++r) C[(wm0 + a * 16 + cr + r) * LDC + wn0 + b * 16 + cc] = acc[a][b][r];
         __syncthreads();
-        epi.tile(m0, n0, min(BM, M - m0), min(BN, N - n0), C, LDC);
+        epi.tile(m0, n0, min(BM, M - m0), min(BN, N - n0), C, LDC, BM);
         return;
     }
 #pragma unroll
@@ -253,7 +253,7 @@ struct EpiF32 {  // out[z][row][col] = v (+ bias[col])
         out[z * zstride + (long long)r * ld + c] = v + (bias ? bias[c] : 0.f);
     }
     // 4 consecutive columns per thread, one float4 store (cols and ld are multiples of 4)
-    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int) const
     {
         const int nq = cols / 4;
         float* o = out + blockIdx.z * zstride;
@@ -303,7 +303,7 @@ struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
     // 8 consecutive columns per thread (cols is a multiple of 8): one 16-byte store of
     // bf16 activations, two float4 stores of the pre-activation; 16 threads write one
     // 128-column row segment in 256 contiguous bytes
-    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int) const
     {
         const int nq = cols / 8;
         for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
@@ -326,12 +326,27 @@ struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
         }
     }
 };
-struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
+// Column sums of a float32 C tile (rows x cols in LDS, row stride ldc) into
+// colpart[m0 / bm][n0 + c]: the bias gradient of a training layer summed over the
+// tile's batch rows (a fixed order; the partials of all row tiles are summed after).
+__device__ __forceinline__ void tile_colsum(float* colpart, long long ldp, int m0, int n0, int rows, int cols,
+                                            const float* C, int ldc, int bm)
+{
+    __syncthreads();
+    for (int c = threadIdx.x; c < cols; c += 256) {
+        float s = 0.f;
+        for (int r = 0; r < rows; ++r) s += C[r * ldc + c];
+        colpart[(long long)(m0 / bm) * ldp + n0 + c] = s;
+    }
+}
+
+struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16, and fp32 or the tile's column sums
     static constexpr bool kTile = true;
     uint16_t* out;
     float* f32out;
     const float* pre;
     long long ld;
+    float* colpart = nullptr;  // [row tiles][ld] column sums of d (then f32out is not written)
     __device__ __forceinline__ void operator()(int r, int c, float v, int) const
     {
         const long long o = (long long)r * ld + c;
@@ -341,7 +356,7 @@ struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
     }
     // 8 consecutive columns per thread: vector loads of pre, one 16-byte bf16 store,
     // two float4 stores (cols and ld are multiples of 8)
-    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
     {
         const int nq = cols / 8;
         for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
@@ -355,11 +370,71 @@ struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 and fp32
                                           v0.w * gelu_prime(p0.w));
             const float4 d1 = make_float4(v1.x * gelu_prime(p1.x), v1.y * gelu_prime(p1.y), v1.z * gelu_prime(p1.z),
                                           v1.w * gelu_prime(p1.w));
-            *reinterpret_cast<float4*>(f32out + o) = d0;
-            *reinterpret_cast<float4*>(f32out + o + 4) = d1;
+            if (colpart) {
+                *reinterpret_cast<float4*>(C + rr * ldc + q * 8) = d0;
+                *reinterpret_cast<float4*>(C + rr * ldc + q * 8 + 4) = d1;
+            } else {
+                *reinterpret_cast<float4*>(f32out + o) = d0;
+                *reinterpret_cast<float4*>(f32out + o + 4) = d1;
+            }
             *reinterpret_cast<uint4*>(out + o) = make_uint4(f2bf2(d0.x, d0.y), f2bf2(d0.z, d0.w), f2bf2(d1.x, d1.y),
                                                             f2bf2(d1.z, d1.w));
         }
+        if (colpart) tile_colsum(colpart, ld, m0, n0, rows, cols, C, ldc, bm);
+    }
+};
+
+// The decoder's output layer in training with the loss folded in: yhat = v + b4 never
+// leaves the tile. d = 2 w_bf (yhat - y) / (512 W) goes out as bf16 (the operand of
+// the next products), its column sums over the tile's rows as float32 partials (the
+// b4 gradient), and each row's share of sum_f w_bf sum_i (yhat - y)^2 / (512 W) over
+// the tile's columns as a float64 partial lossp[row][n0 / cols_per_tile].
+struct EpiMse {
+    static constexpr bool kTile = true;
+    const float* bias;      // b4
+    const uint16_t* y;      // normalised inputs [.][ld], batch row b at y[idx[b]]
+    const int* idx;
+    long long ld;
+    const float* w;         // [B][4] per-sample field weights
+    const double* wsum;     // their total
+    uint16_t* dq;           // [B][ld]
+    float* colpart;         // [row tiles][ld]
+    double* lossp;          // [B][column tiles]
+    int ntn;                // column tiles
+    __device__ __forceinline__ void operator()(int, int, float, int) const {}
+    // 8 consecutive columns per thread; 16 threads cover a 128-column row segment
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
+    {
+        const double inv = 1.0 / (512.0 * wsum[0]);
+        const int nq = cols / 8;
+        const int tn = n0 / cols;  // column tile (every tile of this layer has the full width)
+        for (int idx8 = threadIdx.x; idx8 < rows * nq; idx8 += 256) {
+            const int rr = idx8 / nq, q = idx8 % nq;
+            const int b = m0 + rr, c = n0 + q * 8;
+            const long long src = idx ? idx[b] : b;
+            const float wf = w[b * 4 + (c >> 9)];
+            const float f = (float)(2.0 * wf / (512.0 * wsum[0]));
+            const uint4 yv = *reinterpret_cast<const uint4*>(y + src * ld + c);
+            const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+            float d[8];
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float yh = C[rr * ldc + q * 8 + u] + bias[c + u];
+                const float yi = bf2f((uint16_t)(u & 1 ? yw[u >> 1] >> 16 : yw[u >> 1] & 0xFFFFu));
+                const float diff = yh - yi;
+                acc += (double)wf * diff * diff;
+                d[u] = f * diff;
+                C[rr * ldc + q * 8 + u] = d[u];
+            }
+            *reinterpret_cast<uint4*>(dq + (long long)b * ld + c) =
+                make_uint4(f2bf2(d[0], d[1]), f2bf2(d[2], d[3]), f2bf2(d[4], d[5]), f2bf2(d[6], d[7]));
+            // the row's share over the tile's columns: the nq threads of a row are consecutive
+            // and aligned (nq = cols / 8 is 8 or 16), so a width-nq shuffle sum closes it
+            for (int o = nq / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, nq);
+            if (q == 0) lossp[(long long)b * ntn + tn] = acc * inv;
+        }
+        tile_colsum(colpart, ld, m0, n0, rows, cols, C, ldc, bm);
     }
 };
 struct EpiDenorm {  // decoder output of field f -> lo + r (v + b) scattered into the state
@@ -415,7 +490,7 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
     // 4 x-cells of one (t, lz, ly) row of the block, so each thread moves float4s
     // (one LDS read, one store), and a wave's store covers 64 consecutive blocks
     // (a contiguous run of x). The row's block and (lo, r) are resolved once.
-    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, const float* C, int ldc) const
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int) const
     {
         const int rr = threadIdx.x & 127;
         if (rr >= rows) return;
@@ -440,15 +515,27 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
     }
 };
 
+// Work-group tile (rows, columns) that gemm_auto launches for an M x N product:
+// 128 x 128 when that gives at least two work-groups per CU, else 64 x 64 (training
+// batches of a few thousand rows); 128 x 32 for products 32 columns wide.
+inline int gemm_auto_bm(int M, int N, int splits = 1)
+{
+    const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
+    return N <= 32 ? 128 : (wg128 < 512 ? 64 : 128);
+}
+inline int gemm_auto_bn(int M, int N, int splits = 1)
+{
+    const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
+    return N <= 32 ? 32 : (wg128 < 512 ? 64 : 128);
+}
+
 template <class LA, class LB, class EPI>
 void gemm_auto(int M, int N, int K, const LA& la, const LB& lb, const EPI& epi, hipStream_t st, int splits = 1)
 {
-    // 128 x 128 tiles when they give at least two work-groups per CU, else 64 x 64
-    // (training batches of a few thousand rows)
-    const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
-    if (N <= 32)
+    const int bm = gemm_auto_bm(M, N, splits), bn = gemm_auto_bn(M, N, splits);
+    if (bn == 32)
         gemm<128, 32, 32, 32>(M, N, K, la, lb, epi, st, splits);
-    else if (wg128 < 512)
+    else if (bm == 64)
         gemm<64, 64, 32, 32>(M, N, K, la, lb, epi, st, splits);
     else
         gemm<128, 128, 64, 64>(M, N, K, la, lb, epi, st, splits);
@@ -689,36 +776,6 @@ __global__ void batch_weights_kernel(const float* __restrict__ meta, const int* 
         __syncthreads();
     }
     if (threadIdx.x == 0) wsum[0] = sh[0];
-}
-
-// yhat fp32 [B][n], y = bf16 rows idx: loss = sum_b,f w_bf sum_i (yhat - y)^2 / (512 W),
-// d = 2 w_bf (yhat - y) / (512 W) (bf16 + fp32), per-sample loss partials
-__global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ yhat, const uint16_t* __restrict__ y,
-                                                 const int* __restrict__ idx, int B, int n,
-                                                 const float* __restrict__ w, const double* __restrict__ wsum,
-                                                 uint16_t* __restrict__ dq, float* __restrict__ df,
-                                                 double* __restrict__ partial)
-{
-    const int b = blockIdx.x;
-    const long long src = idx ? idx[b] : b;
-    const double norm = 512.0 * wsum[0];
-    double acc = 0.0;
-    for (int c = threadIdx.x; c < n; c += 256) {
-        const float wf = w[b * 4 + (c >> 9)];
-        const float diff = yhat[(long long)b * n + c] - bf2f(y[src * n + c]);
-        acc += (double)wf * diff * diff;
-        const float d = (float)(2.0 * wf / norm) * diff;
-        dq[(long long)b * n + c] = f2bf(d);
-        df[(long long)b * n + c] = d;
-    }
-    __shared__ double sh[256];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[b] = sh[0] / norm;
 }
 
 __global__ void sum_partials_kernel(const double* __restrict__ partial, int n, double scale, double* __restrict__ out,
@@ -1146,10 +1203,12 @@ namespace {
 
 // One Adam step on a batch. Returns (device) the batch loss in *dloss (added if accumulate).
 struct TrainBufs {
-    float *a1, *a3, *yhat, *d4f, *d3f, *dzf, *d1f, *zf, *part, *w;
+    float *a1, *a3, *dzf, *zf, *part, *w;
+    float* colpart;  // column sums of a layer's d per row tile [ceil(B/64)][max(in, hid)]
+    double* lossp;   // [B][column tiles] loss partials of the output layer
     uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
     uint16_t *xt, *dt;  // transposed operands of a weight gradient, [width][batch]
-    double *lpart, *wsum;
+    double* wsum;
 };
 
 TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
@@ -1161,21 +1220,19 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
         o = align256(o + bytes);
         return r;
     };
-    const size_t o_a1 = take(B * hid * 4), o_a3 = take(B * hid * 4), o_yh = take(B * in * 4), o_d4f = take(B * in * 4),
-                 o_d3f = take(B * hid * 4), o_dzf = take(B * lat * 4), o_d1f = take(B * hid * 4),
+    const size_t o_a1 = take(B * hid * 4), o_a3 = take(B * hid * 4), o_cp = take(((B + 63) / 64) * std::max(in, hid) * 4),
+                 o_loss = take((size_t)B * (in / 32) * 8), o_dzf = take(B * lat * 4),
                  o_zf = take(B * lat * 4), o_part = take((size_t)splits * in * hid * 4), o_h1 = take(B * hid * 2),
                  o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
-                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_lp = take(B * 8), o_w = take(B * 16),
+                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_w = take(B * 16),
                  o_ws = take(8), o_xt = take(B * std::max(in, hid) * 2), o_dt = take(B * std::max(in, hid) * 2);
     uint8_t* w = (uint8_t*)workspace(a, o, st);
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
     t.a3 = (float*)(w + o_a3);
-    t.yhat = (float*)(w + o_yh);
-    t.d4f = (float*)(w + o_d4f);
-    t.d3f = (float*)(w + o_d3f);
+    t.colpart = (float*)(w + o_cp);
+    t.lossp = (double*)(w + o_loss);
     t.dzf = (float*)(w + o_dzf);
-    t.d1f = (float*)(w + o_d1f);
     t.zf = (float*)(w + o_zf);
     t.part = (float*)(w + o_part);
     t.h1 = (uint16_t*)(w + o_h1);
@@ -1187,7 +1244,6 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
     t.d1 = (uint16_t*)(w + o_d1);
     t.xt = (uint16_t*)(w + o_xt);
     t.dt = (uint16_t*)(w + o_dt);
-    t.lpart = (double*)(w + o_lp);
     t.w = (float*)(w + o_w);
     t.wsum = (double*)(w + o_ws);
     return t;
@@ -1262,31 +1318,37 @@ void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting,
               EpiBF16{t.zb, lat, a->bias(1), t.zf}, st);
     gemm_auto(B, hid, lat, LoadK{t.zb, lat, nullptr, B, lat}, LoadK{a->wt[2], lat, nullptr, hid, lat},
               EpiGelu{t.h3, hid, a->bias(2), t.a3}, st);
-    gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
-              EpiF32{t.yhat, in, 0, a->bias(3)}, st);
+    // output layer with the loss: d4 (bf16), the b4 gradient's row-tile partials, loss partials
     hipLaunchKernelGGL(batch_weights_kernel, dim3(1), dim3(256), 0, st, meta, idx, B, a->beta_d, weighting, t.w,
                        t.wsum);
-    hipLaunchKernelGGL(mse_kernel, dim3(B), dim3(256), 0, st, t.yhat, y, idx, B, in, t.w, t.wsum, t.d4, t.d4f,
-                       t.lpart);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lpart, B, 1.0, dloss, accumulate);
+    const int bm4 = gemm_auto_bm(B, in), bn4 = gemm_auto_bn(B, in);
+    gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
+              EpiMse{a->bias(3), y, idx, in, t.w, t.wsum, t.d4, t.colpart, t.lossp, in / bn4}, st);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lossp, B * (in / bn4), 1.0, dloss,
+                       accumulate);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(in, 256)), dim3(256), 0, st, t.colpart, (B + bm4 - 1) / bm4,
+                       (long long)in, a->grad + a->ob[3]);
     // backward: layer 4
     weight_grad(a, 3, B, t.h3, nullptr, t.d4, t, splits, st);
-    colsum(t.d4f, B, in, t.part, a->grad + a->ob[3], st);
+    const int bm3 = gemm_auto_bm(B, hid);
     gemm_auto(B, hid, in, LoadK{t.d4, in, nullptr, B, in}, LoadK{a->wb[3], in, nullptr, hid, in},
-              EpiGeluBack{t.d3, t.d3f, t.a3, hid}, st);
+              EpiGeluBack{t.d3, nullptr, t.a3, hid, t.colpart}, st);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(hid, 256)), dim3(256), 0, st, t.colpart, (B + bm3 - 1) / bm3,
+                       (long long)hid, a->grad + a->ob[2]);
     // layer 3
     weight_grad(a, 2, B, t.zb, nullptr, t.d3, t, splits, st);
-    colsum(t.d3f, B, hid, t.part, a->grad + a->ob[2], st);
     gemm_auto(B, lat, hid, LoadK{t.d3, hid, nullptr, B, hid}, LoadK{a->wb[2], hid, nullptr, lat, hid},
               EpiBF16{t.dz, lat, nullptr, t.dzf}, st);
     // layer 2
     weight_grad(a, 1, B, t.h1, nullptr, t.dz, t, splits, st);
     colsum(t.dzf, B, lat, t.part, a->grad + a->ob[1], st);
+    const int bm1 = gemm_auto_bm(B, hid);
     gemm_auto(B, hid, lat, LoadK{t.dz, lat, nullptr, B, lat}, LoadK{a->wb[1], lat, nullptr, hid, lat},
-              EpiGeluBack{t.d1, t.d1f, t.a1, hid}, st);
+              EpiGeluBack{t.d1, nullptr, t.a1, hid, t.colpart}, st);
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(hid, 256)), dim3(256), 0, st, t.colpart, (B + bm1 - 1) / bm1,
+                       (long long)hid, a->grad + a->ob[0]);
     // layer 1
     weight_grad(a, 0, B, y, idx, t.d1, t, splits, st);
-    colsum(t.d1f, B, hid, t.part, a->grad + a->ob[0], st);
     WV_HIP(hipGetLastError());
 }
 
