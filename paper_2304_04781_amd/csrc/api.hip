@@ -1050,19 +1050,6 @@ float* forward_sweep(wv_ctx* c, float* traces, const std::vector<int>* snap, flo
     return prev;
 }
 
-// snapshot map of the initial sweep of a schedule: snap[n] = slot holding x_n
-std::vector<int> sweep_snapshots(const std::vector<RevAction>& acts, int T, size_t* first_deliver)
-{
-    std::vector<int> snap(T + 1, 0);
-    size_t q = 0;
-    for (; q < acts.size(); ++q) {
-        if (acts[q].kind == 3) break;
-        if (acts[q].kind == 1) snap[acts[q].a] = acts[q].b;
-    }
-    *first_deliver = q;
-    return snap;
-}
-
 // Reverse sweep. e^k comes from the FULL/AE store, or (checkpointing) from the
 // action list starting at `first` with x_{T-1} in `xtm1`.
 void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* acts, size_t first,

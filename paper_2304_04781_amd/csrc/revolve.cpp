@@ -11,10 +11,9 @@
 
 #include <algorithm>
 #include <cstdint>
-#include <stdexcept>
 #include <vector>
 
-#include "wv_internal.h"
+#include "plan.h"
 
 namespace wv {
 
@@ -114,6 +113,21 @@ std::vector<RevAction> revolve_schedule(int nsteps, int nslots, long long* forwa
     g.rev(0, nsteps, nslots, 0);
     if (forward_steps) *forward_steps = g.fwd;
     return g.out;
+}
+
+std::vector<int> sweep_snapshots(const std::vector<RevAction>& acts, int T, size_t* first_deliver)
+{
+    std::vector<int> snap(T + 1, 0);
+    size_t q = 0;
+    for (; q < acts.size(); ++q) {
+        if (acts[q].kind == 3) break;
+        if (acts[q].kind == 1) {
+            WV_REQUIRE(acts[q].a >= 0 && acts[q].a <= T, WV_EINVAL, "sweep_snapshots: store outside the solve");
+            snap[acts[q].a] = acts[q].b;
+        }
+    }
+    *first_deliver = q;
+    return snap;
 }
 
 }  // namespace wv

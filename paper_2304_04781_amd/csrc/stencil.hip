@@ -611,49 +611,20 @@ Tiling make_tiling(int nz, int ny, int nx, const std::vector<int>& rec_kji)
     const int tiles = t.tiles_x * t.tiles_y;
     // enough work-groups to fill 256 CUs several times; chunks of a multiple of
     // 8 levels (patch layers) when the depth allows
-    auto chunking = [&](int target, int* kc_out, int* chunks_out) {
-        int chunks = (target + tiles - 1) / tiles;
-        chunks = std::max(1, std::min(chunks, nz / 8 > 0 ? nz / 8 : 1));
-        int kc = (nz + chunks - 1) / chunks;
-        if (kc >= 8) kc = (kc + 7) / 8 * 8;
-        *kc_out = kc;
-        *chunks_out = (nz + kc - 1) / kc;
-    };
-    chunking(WV_CHUNK_TARGET, &t.kc, &t.chunks_z);
-    chunking(WV_CHUNK_TARGET_ADJ, &t.kc_adj, &t.chunks_adj);
-
+    const ChunkPlan f = plan_chunks(nz, tiles, WV_CHUNK_TARGET), a = plan_chunks(nz, tiles, WV_CHUNK_TARGET_ADJ);
+    t.kc = f.kc;
+    t.chunks_z = f.chunks;
+    t.kc_adj = a.kc;
+    t.chunks_adj = a.chunks;
     // receivers bucketed by tile, then level, then local cell: one pointer per
     // (tile, level) so a work-group finds the receivers of a level in O(1)
-    auto bucket = [&](const std::vector<int>& kji, int** d_ptr, int4** d_ent) {
-        const int n = (int)kji.size() / 3;
-        std::vector<std::vector<int4>> per(tiles);
-        for (int q = 0; q < n; ++q) {
-            const int k = kji[3 * q], j = kji[3 * q + 1], i = kji[3 * q + 2];
-            const int tl = (j / t.by) * t.tiles_x + (i / t.bx);
-            per[tl].push_back(make_int4(k, (j % t.by) * t.bx + (i % t.bx), q, 0));
-        }
-        std::vector<int> ptr((size_t)tiles * (nz + 1), 0);
-        std::vector<int4> ent;
-        for (int tl = 0; tl < tiles; ++tl) {
-            std::stable_sort(per[tl].begin(), per[tl].end(), [](const int4& x, const int4& y) {
-                return x.x != y.x ? x.x < y.x : x.y < y.y;
-            });
-            const int base = (int)ent.size();
-            size_t q = 0;
-            for (int k = 0; k <= nz; ++k) {
-                while (q < per[tl].size() && per[tl][q].x < k) ++q;
-                ptr[(size_t)tl * (nz + 1) + k] = base + (int)q;
-            }
-            ent.insert(ent.end(), per[tl].begin(), per[tl].end());
-        }
-        WV_HIP(hipMalloc(d_ptr, sizeof(int) * ptr.size()));
-        WV_HIP(hipMemcpy(*d_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice));
-        const size_t ne = std::max<size_t>(ent.size(), 1);
-        WV_HIP(hipMalloc(d_ent, sizeof(int4) * ne));
-        if (!ent.empty())
-            WV_HIP(hipMemcpy(*d_ent, ent.data(), sizeof(int4) * ent.size(), hipMemcpyHostToDevice));
-    };
-    bucket(rec_kji, &t.rec_ptr, &t.rec_ent);
+    std::vector<int> ptr;
+    std::vector<RecEnt> ent;
+    bucket_receivers(nz, t.bx, t.by, t.tiles_x, t.tiles_y, rec_kji, ptr, ent);
+    WV_HIP(hipMalloc(&t.rec_ptr, sizeof(int) * ptr.size()));
+    WV_HIP(hipMemcpy(t.rec_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice));
+    WV_HIP(hipMalloc(&t.rec_ent, sizeof(int4) * std::max<size_t>(ent.size(), 1)));
+    if (!ent.empty()) WV_HIP(hipMemcpy(t.rec_ent, ent.data(), sizeof(int4) * ent.size(), hipMemcpyHostToDevice));
     return t;
 }
 

@@ -7,29 +7,19 @@
 #include <string>
 #include <vector>
 
+#include "plan.h"
 #include "wavecomp.h"
 
 namespace wv {
 
 void set_error(const std::string& msg);
 
-struct Error {
-    int code;
-    std::string msg;
-};
-
-// Throwing check used inside the library; every C entry point converts
-// the exception into a return code (no exception crosses the ABI).
+// HIP call whose failure throws (converted to WV_EDEVICE at the entry point)
 #define WV_HIP(expr)                                                                   \
     do {                                                                               \
         hipError_t _e = (expr);                                                        \
         if (_e != hipSuccess)                                                          \
             throw ::wv::Error{WV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
-    } while (0)
-
-#define WV_REQUIRE(cond, code, text)                                                    \
-    do {                                                                               \
-        if (!(cond)) throw ::wv::Error{code, text};                                    \
     } while (0)
 
 // ---- stencil -----------------------------------------------------------------------
@@ -135,14 +125,5 @@ void launch_axpby(float* y, const float* x, double a, double b, long long n, hip
 void launch_lincomb(float* out, const float* x, double a, const float* y, long long n, hipStream_t st);
 void launch_dot(const float* a, const float* b, long long n, double* partial, int nblocks, double* d_out,
                 hipStream_t st);
-
-// ---- revolve --------------------------------------------------------------------------
-
-struct RevAction {
-    int kind;  // 0 advance(a -> a+b), 1 store(step a, slot b), 2 restore(step a, slot b), 3 deliver(a)
-    int a, b;
-};
-long long revolve_cost(long long l, int s);
-std::vector<RevAction> revolve_schedule(int nsteps, int nslots, long long* forward_steps);
 
 }  // namespace wv
