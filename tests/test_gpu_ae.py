@@ -722,6 +722,69 @@ def state_error(p, net, c, every=8):
     return (num / den) ** 0.5
 
 
+def pca_basis(Y, k=32):
+    """Mean and the k leading principal directions (columns) of the rows of Y."""
+    mu = Y.mean(axis=0)
+    X = Y - mu
+    _, V = np.linalg.eigh(X.T @ X)
+    return mu, V[:, ::-1][:, :k].copy()
+
+
+def normalized_rows(p, net, c, every):
+    """Normalised patch rows (float64) and their (lo, r) of every `every`-th state of
+    the forward solve at c, with the network's floors; the states themselves."""
+    s = WaveSolver.for_problem(p)
+    s.set_storage(L.STORE_NONE)
+    _, _, cap = s.forward(c, p.wavelet, capture_every=every)
+    P = (p.nz // 8) * (p.ny // 8) * (p.nx // 8)
+    y = torch.empty((P, 2048), dtype=torch.int16, device="cuda")
+    meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
+    for q in range(cap.shape[0]):
+        L.ae_normalize(net.handle, s.grid, cap[q, 0], y, meta)
+        yield (y.view(torch.bfloat16).double().cpu().numpy(), meta.double().cpu().numpy(),
+               cap[q, 0, 0].double().cpu().numpy())
+    s.close()
+
+
+def pca_state_error(p, net, mu, V, c, every=8):
+    """state_error with the network replaced by the projection onto the 32 principal
+    directions (float64): each patch row y becomes mu + (y - mu) V V^T, and e is
+    lo + r times its first 512 entries, put back in place."""
+    Pz, Py, Px = p.nz // 8, p.ny // 8, p.nx // 8
+    num = den = 0.0
+    for Y, meta, e in normalized_rows(p, net, c, every):
+        R = mu + ((Y - mu) @ V) @ V.T
+        ep = meta[:, 0, 0, None] + meta[:, 0, 1, None] * R[:, :512]
+        rec = ep.reshape(Pz, Py, Px, 8, 8, 8).transpose(0, 3, 1, 4, 2, 5).reshape(e.shape)
+        num += float(((rec - e) ** 2).sum())
+        den += float((e ** 2).sum())
+    return (num / den) ** 0.5
+
+
+def test_trained_network_against_untrained_and_pca32():
+    """What the training buys, at equal latent size (32 numbers per patch): the e
+    error of encode -> decode (latents only) over the states of the start and true
+    models, for the trained network, the untrained one and the 32 leading principal
+    directions of the same training rows (the optimum of a linear autoencoder, kept in
+    float64 and not rounded to bfloat16)."""
+    p = ae_problem(nt=240, shape=(48, 48, 48))
+    p.wavelet = np.asarray(W.ricker(8.0, p.dt, p.nt)[None, :] / p.dx ** 3, np.float32).astype(np.float64)
+    net, _ = trained_net(p)
+    Y = np.concatenate([r[0] for r in normalized_rows(p, net, p.c_start, 4)])
+    assert Y.shape == ((p.nt - 1) // 4 * 216, 2048)
+    mu, V = pca_basis(Y)
+    raw = Net(W.ae_init(seed=4))
+    L.ae_set_beta(raw.handle, L.ae_get_beta(net.handle))
+    res = {}
+    for name, c in (("start", p.c_start), ("true", p.c_true)):
+        res[name] = (state_error(p, net, c), state_error(p, raw, c), pca_state_error(p, net, mu, V, c))
+        print(f"model {name}: e rel err trained {res[name][0]:.4f}, untrained {res[name][1]:.4f}, "
+              f"PCA-32 {res[name][2]:.4f}", flush=True)
+    for tr, un, pca in res.values():
+        assert np.isfinite(pca) and 0.0 < pca < 1.0
+        assert tr < 0.5 * un
+
+
 def test_training_on_prior_draws():
     """Algorithm 1 with draws from the BiLaplacian prior about the start model
     (pointwise std about 100 m/s, correlation length about 10 cells): four forward
