@@ -288,12 +288,45 @@ struct EpiBF16 {  // bf16(v + bias), optional fp32 copy
         if (f32out) f32out[(long long)r * ld + c] = x;
     }
 };
-struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
+// Column sums of a float32 C tile (rows x cols in LDS, row stride ldc) into
+// colpart[m0 / bm][n0 + c]: the bias gradient of a training layer summed over the
+// tile's batch rows (a fixed order; the partials of all row tiles are summed after).
+__device__ __forceinline__ void tile_colsum(float* colpart, long long ldp, int m0, int n0, int rows, int cols,
+                                            const float* C, int ldc, int bm)
+{
+    __syncthreads();
+    for (int c = threadIdx.x; c < cols; c += 256) {
+        float s = 0.f;
+        for (int r = 0; r < rows; ++r) s += C[r * ldc + c];
+        colpart[(long long)(m0 / bm) * ldp + n0 + c] = s;
+    }
+}
+
+// bf16 copy of a float32 C tile (rows x cols in LDS), transposed: T[(n0 + c) tld + m0 + r].
+// Thread item (column c, group of 8 rows): one 16-byte store; the 8 threads of a column
+// write 128 contiguous bytes (rows is a multiple of 8, tld of 8).
+__device__ __forceinline__ void tile_store_t(uint16_t* T, long long tld, int m0, int n0, int rows, int cols,
+                                             const float* C, int ldc)
+{
+    __syncthreads();
+    const int rg = rows / 8;
+    for (int i = threadIdx.x; i < cols * rg; i += 256) {
+        const int c = i / rg, g = i % rg;
+        const float* q = C + (g * 8) * ldc + c;
+        *reinterpret_cast<uint4*>(T + (long long)(n0 + c) * tld + m0 + g * 8) =
+            make_uint4(f2bf2(q[0], q[ldc]), f2bf2(q[2 * ldc], q[3 * ldc]), f2bf2(q[4 * ldc], q[5 * ldc]),
+                       f2bf2(q[6 * ldc], q[7 * ldc]));
+    }
+}
+
+struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a)) [and its transpose]
     static constexpr bool kTile = true;
     uint16_t* out;
     long long ld;
     const float* bias;
     float* pre;
+    uint16_t* tout = nullptr;  // optional [ld][tld]: the bf16 activations transposed
+    long long tld = 0;
     __device__ __forceinline__ void operator()(int r, int c, float v, int) const
     {
         const float a = v + bias[c];
@@ -320,42 +353,33 @@ struct EpiGelu {  // a = v + bias -> (pre-activation), bf16(gelu(a))
                 *reinterpret_cast<float4*>(pre + o) = a0;
                 *reinterpret_cast<float4*>(pre + o + 4) = a1;
             }
+            const float4 g0 = make_float4(gelu(a0.x), gelu(a0.y), gelu(a0.z), gelu(a0.w));
+            const float4 g1 = make_float4(gelu(a1.x), gelu(a1.y), gelu(a1.z), gelu(a1.w));
             *reinterpret_cast<uint4*>(out + o) =
-                make_uint4(f2bf2(gelu(a0.x), gelu(a0.y)), f2bf2(gelu(a0.z), gelu(a0.w)),
-                           f2bf2(gelu(a1.x), gelu(a1.y)), f2bf2(gelu(a1.z), gelu(a1.w)));
+                make_uint4(f2bf2(g0.x, g0.y), f2bf2(g0.z, g0.w), f2bf2(g1.x, g1.y), f2bf2(g1.z, g1.w));
+            if (tout) {
+                *reinterpret_cast<float4*>(C + rr * ldc + q * 8) = g0;
+                *reinterpret_cast<float4*>(C + rr * ldc + q * 8 + 4) = g1;
+            }
         }
+        if (tout) tile_store_t(tout, tld, m0, n0, rows, cols, C, ldc);
     }
 };
-// Column sums of a float32 C tile (rows x cols in LDS, row stride ldc) into
-// colpart[m0 / bm][n0 + c]: the bias gradient of a training layer summed over the
-// tile's batch rows (a fixed order; the partials of all row tiles are summed after).
-__device__ __forceinline__ void tile_colsum(float* colpart, long long ldp, int m0, int n0, int rows, int cols,
-                                            const float* C, int ldc, int bm)
-{
-    __syncthreads();
-    for (int c = threadIdx.x; c < cols; c += 256) {
-        float s = 0.f;
-        for (int r = 0; r < rows; ++r) s += C[r * ldc + c];
-        colpart[(long long)(m0 / bm) * ldp + n0 + c] = s;
-    }
-}
-
-struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16, and fp32 or the tile's column sums
+struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16 [and its transpose], the tile's column sums of d
     static constexpr bool kTile = true;
     uint16_t* out;
-    float* f32out;
     const float* pre;
     long long ld;
-    float* colpart = nullptr;  // [row tiles][ld] column sums of d (then f32out is not written)
+    float* colpart;            // [row tiles][ld] column sums of d
+    uint16_t* tout = nullptr;  // optional [ld][tld]: bf16 d transposed
+    long long tld = 0;
     __device__ __forceinline__ void operator()(int r, int c, float v, int) const
     {
         const long long o = (long long)r * ld + c;
-        const float d = v * gelu_prime(pre[o]);
-        out[o] = f2bf(d);
-        f32out[o] = d;
+        out[o] = f2bf(v * gelu_prime(pre[o]));
     }
-    // 8 consecutive columns per thread: vector loads of pre, one 16-byte bf16 store,
-    // two float4 stores (cols and ld are multiples of 8)
+    // 8 consecutive columns per thread: vector loads of pre, one 16-byte bf16 store
+    // (cols and ld are multiples of 8); d goes back into the tile for the sums
     __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
     {
         const int nq = cols / 8;
@@ -370,17 +394,47 @@ struct EpiGeluBack {  // d = v * gelu'(pre) -> bf16, and fp32 or the tile's colu
                                           v0.w * gelu_prime(p0.w));
             const float4 d1 = make_float4(v1.x * gelu_prime(p1.x), v1.y * gelu_prime(p1.y), v1.z * gelu_prime(p1.z),
                                           v1.w * gelu_prime(p1.w));
-            if (colpart) {
-                *reinterpret_cast<float4*>(C + rr * ldc + q * 8) = d0;
-                *reinterpret_cast<float4*>(C + rr * ldc + q * 8 + 4) = d1;
-            } else {
-                *reinterpret_cast<float4*>(f32out + o) = d0;
-                *reinterpret_cast<float4*>(f32out + o + 4) = d1;
-            }
+            *reinterpret_cast<float4*>(C + rr * ldc + q * 8) = d0;
+            *reinterpret_cast<float4*>(C + rr * ldc + q * 8 + 4) = d1;
             *reinterpret_cast<uint4*>(out + o) = make_uint4(f2bf2(d0.x, d0.y), f2bf2(d0.z, d0.w), f2bf2(d1.x, d1.y),
                                                             f2bf2(d1.z, d1.w));
         }
+        tile_colsum(colpart, ld, m0, n0, rows, cols, C, ldc, bm);
+        if (tout) tile_store_t(tout, tld, m0, n0, rows, cols, C, ldc);
+    }
+};
+
+// A narrow training product (the latent layer, 32 columns): x = v (+ bias) -> bf16
+// [and its transpose], optionally the tile's column sums of x.
+struct EpiBF16T {
+    static constexpr bool kTile = true;
+    uint16_t* out;
+    long long ld;
+    const float* bias;         // nullable
+    float* colpart = nullptr;  // optional [row tiles][ld]
+    uint16_t* tout = nullptr;  // optional [ld][tld]
+    long long tld = 0;
+    __device__ __forceinline__ void operator()(int r, int c, float v, int) const
+    {
+        out[(long long)r * ld + c] = f2bf(v + (bias ? bias[c] : 0.f));
+    }
+    __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
+    {
+        const int nq = cols / 8;
+        for (int idx = threadIdx.x; idx < rows * nq; idx += 256) {
+            const int rr = idx / nq, q = idx % nq;
+            const int c = n0 + q * 8;
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                x[u] = C[rr * ldc + q * 8 + u] + (bias ? bias[c + u] : 0.f);
+                C[rr * ldc + q * 8 + u] = x[u];
+            }
+            *reinterpret_cast<uint4*>(out + (long long)(m0 + rr) * ld + c) =
+                make_uint4(f2bf2(x[0], x[1]), f2bf2(x[2], x[3]), f2bf2(x[4], x[5]), f2bf2(x[6], x[7]));
+        }
         if (colpart) tile_colsum(colpart, ld, m0, n0, rows, cols, C, ldc, bm);
+        if (tout) tile_store_t(tout, tld, m0, n0, rows, cols, C, ldc);
     }
 };
 
@@ -399,15 +453,17 @@ struct EpiMse {
     const double* wsum;     // their total
     uint16_t* dq;           // [B][ld]
     float* colpart;         // [row tiles][ld]
-    double* lossp;          // [B][column tiles]
+    double* lossp;          // [row tiles][column tiles]
     int ntn;                // column tiles
+    uint16_t* tout = nullptr;  // optional [ld][tld]: bf16 d transposed
+    long long tld = 0;
     __device__ __forceinline__ void operator()(int, int, float, int) const {}
     // 8 consecutive columns per thread; 16 threads cover a 128-column row segment
     __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
     {
         const double inv = 1.0 / (512.0 * wsum[0]);
         const int nq = cols / 8;
-        const int tn = n0 / cols;  // column tile (every tile of this layer has the full width)
+        double tl = 0.0;  // this thread's rows (their q = 0 thread) of the tile's loss
         for (int idx8 = threadIdx.x; idx8 < rows * nq; idx8 += 256) {
             const int rr = idx8 / nq, q = idx8 % nq;
             const int b = m0 + rr, c = n0 + q * 8;
@@ -432,9 +488,16 @@ struct EpiMse {
             // the row's share over the tile's columns: the nq threads of a row are consecutive
             // and aligned (nq = cols / 8 is 8 or 16), so a width-nq shuffle sum closes it
             for (int o = nq / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, nq);
-            if (q == 0) lossp[(long long)b * ntn + tn] = acc * inv;
+            if (q == 0) tl += acc;
         }
+        // the tile's loss: rows summed per wave (fixed shuffle order), then the 4 waves in order
+        for (int o = 32; o > 0; o >>= 1) tl += __shfl_xor(tl, o, 64);
+        __shared__ double wsh[4];
+        if ((threadIdx.x & 63) == 0) wsh[threadIdx.x >> 6] = tl;
+        __syncthreads();
+        if (threadIdx.x == 0) lossp[(long long)(m0 / bm) * ntn + n0 / cols] = ((wsh[0] + wsh[1]) + (wsh[2] + wsh[3])) * inv;
         tile_colsum(colpart, ld, m0, n0, rows, cols, C, ldc, bm);
+        if (tout) tile_store_t(tout, tld, m0, n0, rows, cols, C, ldc);
     }
 };
 struct EpiDenorm {  // decoder output of field f -> lo + r (v + b) scattered into the state
@@ -793,25 +856,6 @@ __global__ void sum_partials_kernel(const double* __restrict__ partial, int n, d
     if (threadIdx.x == 0) out[0] = (accumulate ? out[0] : 0.0) + scale * sh[0];
 }
 
-// column sums of d [B][n] (bias gradients): 64 columns x 4 row lanes per block,
-// 16 row chunks -> partial [16][n], then a fixed-order sum
-constexpr int COLSUM_CHUNKS = 16;
-__global__ void colsum_partial_kernel(const float* __restrict__ d, int B, int n, float* __restrict__ part)
-{
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int rl = threadIdx.x >> 6;
-    const int rows = (B + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
-    const int r0 = blockIdx.y * rows, r1 = min(B, r0 + rows);
-    float s = 0.f;
-    if (c < n)
-        for (int b = r0 + rl; b < r1; b += 4) s += d[(long long)b * n + c];
-    __shared__ float sh[4][64];
-    sh[rl][threadIdx.x & 63] = s;
-    __syncthreads();
-    if (rl == 0 && c < n) part[(long long)blockIdx.y * n + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
-                                                             (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
-}
-
 // sum split-K partials [splits][n] -> out[n]
 __global__ void splitsum_kernel(const float* __restrict__ part, int splits, long long n, float* __restrict__ out)
 {
@@ -837,25 +881,49 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
     w[i] = w[i] - lr * mh / (sqrtf(vh) + eps);
 }
 
-// fp32 W [fi][fo] -> bf16 W [fi][fo] and bf16 W^T [fo][fi]
-__global__ void convert_kernel(const float* __restrict__ w, int fi, int fo, uint16_t* __restrict__ wb,
-                               uint16_t* __restrict__ wt)
+// fp32 W_l [fi][fo] -> bf16 W_l [fi][fo] and bf16 W_l^T [fo][fi] for the 4 layers in one
+// launch: a work-group converts a 64 x 64 tile of one layer and writes its transpose
+// through LDS, so both outputs are written in whole rows
+struct ConvLayers {
+    const float* w[4];
+    uint16_t* wb[4];
+    uint16_t* wt[4];
+    int fi[4], fo[4];
+    int first[5];  // first work-group of each layer
+    int tx[4];     // column tiles of each layer
+};
+__global__ void __launch_bounds__(256) convert_kernel(const ConvLayers a)
 {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= (long long)fi * fo) return;
-    const int r = i / fo, c = i % fo;
-    const uint16_t b = f2bf(w[i]);
-    wb[i] = b;
-    wt[(long long)c * fi + r] = b;
+    __shared__ uint16_t s[64][64 + 2];
+    int t = blockIdx.x, l = 0;
+    while (l < 3 && t >= a.first[l + 1]) ++l;
+    t -= a.first[l];
+    const int fi = a.fi[l], fo = a.fo[l];
+    const int r0 = (t / a.tx[l]) * 64, c0 = (t % a.tx[l]) * 64;
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+        const int r = i >> 4, c = (i & 15) * 4;
+        if (r0 + r < fi && c0 + c < fo) {
+            const float4 v = *reinterpret_cast<const float4*>(a.w[l] + (long long)(r0 + r) * fo + c0 + c);
+            const uint16_t b0 = f2bf(v.x), b1 = f2bf(v.y), b2 = f2bf(v.z), b3 = f2bf(v.w);
+            *reinterpret_cast<uint2*>(a.wb[l] + (long long)(r0 + r) * fo + c0 + c) =
+                make_uint2(b0 | (uint32_t)b1 << 16, b2 | (uint32_t)b3 << 16);
+            s[r][c] = b0;
+            s[r][c + 1] = b1;
+            s[r][c + 2] = b2;
+            s[r][c + 3] = b3;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+        const int c = i >> 4, r = (i & 15) * 4;
+        if (c0 + c < fo && r0 + r < fi)
+            *reinterpret_cast<uint2*>(a.wt[l] + (long long)(c0 + c) * fi + r0 + r) =
+                make_uint2(s[r][c] | (uint32_t)s[r + 1][c] << 16, s[r + 2][c] | (uint32_t)s[r + 3][c] << 16);
+    }
 }
 
 int blocks(long long n, int bs) { return (int)std::max<long long>(1, (n + bs - 1) / bs); }
 
-void colsum(const float* d, int B, int n, float* part, float* out, hipStream_t st)
-{
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks(n, 64), COLSUM_CHUNKS), dim3(256), 0, st, d, B, n, part);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, part, COLSUM_CHUNKS, (long long)n, out);
-}
 
 }  // namespace
 }  // namespace wv
@@ -923,18 +991,35 @@ void layout(ae_net* a)
     a->nparam = o;
 }
 
-void refresh_bf16(ae_net* a, hipStream_t st)
+void pack_fused(ae_net* a, hipStream_t st)
 {
-    for (int l = 0; l < 4; ++l) {
-        const long long n = (long long)a->fi[l] * a->fo[l];
-        hipLaunchKernelGGL(convert_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, a->master + a->oW[l], a->fi[l],
-                           a->fo[l], a->wb[l], a->wt[l]);
-    }
-    WV_HIP(hipGetLastError());
     if (a->wp1) {
         fused_pack(a->wt[0], a->hid, a->in, a->wp1, st);
         fused_pack(a->wt[3], a->in, a->hid, a->wp4, st);
     }
+}
+
+// bf16 copies of the weights after a change of the fp32 masters; with pack, also the
+// fragment-ordered copies of the fused encode and decode (training skips them until
+// its last step: only the inference kernels read them)
+void refresh_bf16(ae_net* a, hipStream_t st, bool pack = true)
+{
+    ConvLayers c{};
+    int n = 0;
+    for (int l = 0; l < 4; ++l) {
+        c.w[l] = a->master + a->oW[l];
+        c.wb[l] = a->wb[l];
+        c.wt[l] = a->wt[l];
+        c.fi[l] = a->fi[l];
+        c.fo[l] = a->fo[l];
+        c.tx[l] = (a->fo[l] + 63) / 64;
+        c.first[l] = n;
+        n += c.tx[l] * ((a->fi[l] + 63) / 64);
+    }
+    c.first[4] = n;
+    hipLaunchKernelGGL(convert_kernel, dim3(n), dim3(256), 0, st, c);
+    WV_HIP(hipGetLastError());
+    if (pack) pack_fused(a, st);
 }
 
 void upload_beta(ae_net* a)
@@ -1203,11 +1288,13 @@ namespace {
 
 // One Adam step on a batch. Returns (device) the batch loss in *dloss (added if accumulate).
 struct TrainBufs {
-    float *a1, *a3, *dzf, *zf, *part, *w;
+    float *a1, *a3, *part, *w;  // pre-activations of layers 1 and 3; split-K partials; sample weights
     float* colpart;  // column sums of a layer's d per row tile [ceil(B/64)][max(in, hid)]
-    double* lossp;   // [B][column tiles] loss partials of the output layer
+    double* lossp;   // [row tiles][column tiles] loss partials of the output layer
     uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
-    uint16_t *xt, *dt;  // transposed operands of a weight gradient, [width][batch]
+    // the same [width][batch] (written transposed by the epilogues: the weight gradients'
+    // operands), and the batch's input rows transposed
+    uint16_t *h1t, *zbt, *h3t, *d4t, *d3t, *dzt, *d1t, *yt;
     double* wsum;
 };
 
@@ -1220,20 +1307,22 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
         o = align256(o + bytes);
         return r;
     };
-    const size_t o_a1 = take(B * hid * 4), o_a3 = take(B * hid * 4), o_cp = take(((B + 63) / 64) * std::max(in, hid) * 4),
-                 o_loss = take((size_t)B * (in / 32) * 8), o_dzf = take(B * lat * 4),
-                 o_zf = take(B * lat * 4), o_part = take((size_t)splits * in * hid * 4), o_h1 = take(B * hid * 2),
-                 o_zb = take(B * lat * 2), o_h3 = take(B * hid * 2), o_d4 = take(B * in * 2), o_d3 = take(B * hid * 2),
-                 o_dz = take(B * lat * 2), o_d1 = take(B * hid * 2), o_w = take(B * 16),
-                 o_ws = take(8), o_xt = take(B * std::max(in, hid) * 2), o_dt = take(B * std::max(in, hid) * 2);
+    const size_t nb = B;
+    const size_t o_a1 = take(nb * hid * 4), o_a3 = take(nb * hid * 4),
+                 o_cp = take(((nb + 63) / 64) * std::max(in, hid) * 4),
+                 o_loss = take(((nb + 63) / 64) * (in / 32) * 8), o_part = take((size_t)splits * in * hid * 4),
+                 o_h1 = take(nb * hid * 2), o_zb = take(nb * lat * 2), o_h3 = take(nb * hid * 2),
+                 o_d4 = take(nb * in * 2), o_d3 = take(nb * hid * 2), o_dz = take(nb * lat * 2),
+                 o_d1 = take(nb * hid * 2), o_h1t = take(nb * hid * 2), o_zbt = take(nb * lat * 2),
+                 o_h3t = take(nb * hid * 2), o_d4t = take(nb * in * 2), o_d3t = take(nb * hid * 2),
+                 o_dzt = take(nb * lat * 2), o_d1t = take(nb * hid * 2), o_yt = take(nb * in * 2),
+                 o_w = take(nb * 16), o_ws = take(8);
     uint8_t* w = (uint8_t*)workspace(a, o, st);
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
     t.a3 = (float*)(w + o_a3);
     t.colpart = (float*)(w + o_cp);
     t.lossp = (double*)(w + o_loss);
-    t.dzf = (float*)(w + o_dzf);
-    t.zf = (float*)(w + o_zf);
     t.part = (float*)(w + o_part);
     t.h1 = (uint16_t*)(w + o_h1);
     t.zb = (uint16_t*)(w + o_zb);
@@ -1242,8 +1331,14 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
     t.d3 = (uint16_t*)(w + o_d3);
     t.dz = (uint16_t*)(w + o_dz);
     t.d1 = (uint16_t*)(w + o_d1);
-    t.xt = (uint16_t*)(w + o_xt);
-    t.dt = (uint16_t*)(w + o_dt);
+    t.h1t = (uint16_t*)(w + o_h1t);
+    t.zbt = (uint16_t*)(w + o_zbt);
+    t.h3t = (uint16_t*)(w + o_h3t);
+    t.d4t = (uint16_t*)(w + o_d4t);
+    t.d3t = (uint16_t*)(w + o_d3t);
+    t.dzt = (uint16_t*)(w + o_dzt);
+    t.d1t = (uint16_t*)(w + o_d1t);
+    t.yt = (uint16_t*)(w + o_yt);
     t.w = (float*)(w + o_w);
     t.wsum = (double*)(w + o_ws);
     return t;
@@ -1293,66 +1388,76 @@ void transpose_rows(const uint16_t* src, long long ld, const int* rows, int R, i
     WV_HIP(hipGetLastError());
 }
 
-// dW_l = X^T D summed over the batch: both operands are transposed into k-contiguous
-// rows first (the batch rows of X gathered by xrows), so the GEMM streams whole rows
-void weight_grad(ae_net* a, int l, int B, const uint16_t* X, const int* xrows, const uint16_t* D, TrainBufs& t,
-                 int splits, hipStream_t st)
+// dW_l = X^T D summed over the batch, from both operands stored transposed
+// ([width][batch], so the GEMM streams whole k-contiguous rows): split over the batch,
+// the partials summed in a fixed order
+void weight_grad(ae_net* a, int l, int B, const uint16_t* Xt, const uint16_t* Dt, TrainBufs& t, int splits,
+                 hipStream_t st)
 {
     const int fi = a->fi[l], fo = a->fo[l];
     const long long n = (long long)fi * fo;
-    transpose_rows(X, fi, xrows, B, fi, t.xt, st);
-    transpose_rows(D, fo, nullptr, B, fo, t.dt, st);
-    gemm_auto(fi, fo, B, LoadK{t.xt, B, nullptr, fi, B}, LoadK{t.dt, B, nullptr, fo, B},
+    gemm_auto(fi, fo, B, LoadK{Xt, B, nullptr, fi, B}, LoadK{Dt, B, nullptr, fo, B},
               EpiF32{t.part, fo, n, nullptr}, st, splits);
     hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, t.part, splits, n, a->grad + a->oW[l]);
+}
+
+// bias gradient of layer l: the row-tile partial column sums of width n, summed in order
+void bias_grad(ae_net* a, int l, int B, int bm, int n, TrainBufs& t, hipStream_t st)
+{
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, t.colpart, (B + bm - 1) / bm,
+                       (long long)n, a->grad + a->ob[l]);
 }
 
 void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting, const int* idx, int B,
                  TrainBufs& t, int splits, double* dloss, int accumulate, hipStream_t st)
 {
     const int in = a->in, hid = a->hid, lat = a->lat;
-    // forward
+    // forward; the epilogues also write the transposed activations the weight gradients read
     gemm_auto(B, hid, in, LoadK{y, in, idx, B, in}, LoadK{a->wt[0], in, nullptr, hid, in},
-              EpiGelu{t.h1, hid, a->bias(0), t.a1}, st);
+              EpiGelu{t.h1, hid, a->bias(0), t.a1, t.h1t, B}, st);
     gemm_auto(B, lat, hid, LoadK{t.h1, hid, nullptr, B, hid}, LoadK{a->wt[1], hid, nullptr, lat, hid},
-              EpiBF16{t.zb, lat, a->bias(1), t.zf}, st);
+              EpiBF16T{t.zb, lat, a->bias(1), nullptr, t.zbt, B}, st);
     gemm_auto(B, hid, lat, LoadK{t.zb, lat, nullptr, B, lat}, LoadK{a->wt[2], lat, nullptr, hid, lat},
-              EpiGelu{t.h3, hid, a->bias(2), t.a3}, st);
-    // output layer with the loss: d4 (bf16), the b4 gradient's row-tile partials, loss partials
+              EpiGelu{t.h3, hid, a->bias(2), t.a3, t.h3t, B}, st);
+    // output layer with the loss: d4 (bf16 and transposed), the b4 gradient's row-tile
+    // partials, the loss per tile
     hipLaunchKernelGGL(batch_weights_kernel, dim3(1), dim3(256), 0, st, meta, idx, B, a->beta_d, weighting, t.w,
                        t.wsum);
     const int bm4 = gemm_auto_bm(B, in), bn4 = gemm_auto_bn(B, in);
     gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
-              EpiMse{a->bias(3), y, idx, in, t.w, t.wsum, t.d4, t.colpart, t.lossp, in / bn4}, st);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lossp, B * (in / bn4), 1.0, dloss,
-                       accumulate);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(in, 256)), dim3(256), 0, st, t.colpart, (B + bm4 - 1) / bm4,
-                       (long long)in, a->grad + a->ob[3]);
+              EpiMse{a->bias(3), y, idx, in, t.w, t.wsum, t.d4, t.colpart, t.lossp, in / bn4, t.d4t, B}, st);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lossp, ((B + bm4 - 1) / bm4) * (in / bn4),
+                       1.0, dloss, accumulate);
+    bias_grad(a, 3, B, bm4, in, t, st);
     // backward: layer 4
-    weight_grad(a, 3, B, t.h3, nullptr, t.d4, t, splits, st);
-    const int bm3 = gemm_auto_bm(B, hid);
+    weight_grad(a, 3, B, t.h3t, t.d4t, t, splits, st);
     gemm_auto(B, hid, in, LoadK{t.d4, in, nullptr, B, in}, LoadK{a->wb[3], in, nullptr, hid, in},
-              EpiGeluBack{t.d3, nullptr, t.a3, hid, t.colpart}, st);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(hid, 256)), dim3(256), 0, st, t.colpart, (B + bm3 - 1) / bm3,
-                       (long long)hid, a->grad + a->ob[2]);
+              EpiGeluBack{t.d3, t.a3, hid, t.colpart, t.d3t, B}, st);
+    bias_grad(a, 2, B, gemm_auto_bm(B, hid), hid, t, st);
     // layer 3
-    weight_grad(a, 2, B, t.zb, nullptr, t.d3, t, splits, st);
+    weight_grad(a, 2, B, t.zbt, t.d3t, t, splits, st);
     gemm_auto(B, lat, hid, LoadK{t.d3, hid, nullptr, B, hid}, LoadK{a->wb[2], hid, nullptr, lat, hid},
-              EpiBF16{t.dz, lat, nullptr, t.dzf}, st);
+              EpiBF16T{t.dz, lat, nullptr, t.colpart, t.dzt, B}, st);
+    bias_grad(a, 1, B, gemm_auto_bm(B, lat), lat, t, st);
     // layer 2
-    weight_grad(a, 1, B, t.h1, nullptr, t.dz, t, splits, st);
-    colsum(t.dzf, B, lat, t.part, a->grad + a->ob[1], st);
-    const int bm1 = gemm_auto_bm(B, hid);
+    weight_grad(a, 1, B, t.h1t, t.dzt, t, splits, st);
     gemm_auto(B, hid, lat, LoadK{t.dz, lat, nullptr, B, lat}, LoadK{a->wb[1], lat, nullptr, hid, lat},
-              EpiGeluBack{t.d1, nullptr, t.a1, hid, t.colpart}, st);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(hid, 256)), dim3(256), 0, st, t.colpart, (B + bm1 - 1) / bm1,
-                       (long long)hid, a->grad + a->ob[0]);
-    // layer 1
-    weight_grad(a, 0, B, y, idx, t.d1, t, splits, st);
+              EpiGeluBack{t.d1, t.a1, hid, t.colpart, t.d1t, B}, st);
+    bias_grad(a, 0, B, gemm_auto_bm(B, hid), hid, t, st);
+    // layer 1: the batch's input rows, gathered and transposed
+    transpose_rows(y, in, idx, B, in, t.yt, st);
+    weight_grad(a, 0, B, t.yt, t.d1t, t, splits, st);
     WV_HIP(hipGetLastError());
 }
 
-void adam_update(ae_net* a, double lr, const ae_train_cfg& cfg, hipStream_t st)
+// split of the batch (the GEMM depth) in the weight gradients: enough work-groups to
+// fill the CUs, partials summed in a fixed order
+#ifndef WV_TRAIN_SPLITS_MAX
+#define WV_TRAIN_SPLITS_MAX 8
+#endif
+int train_splits(int B) { return std::max(1, std::min(WV_TRAIN_SPLITS_MAX, B / 512)); }
+
+void adam_update(ae_net* a, double lr, const ae_train_cfg& cfg, hipStream_t st, bool pack = true)
 {
     a->step += 1;
     const double c1 = 1.0 - std::pow(cfg.beta1, (double)a->step);
@@ -1360,7 +1465,7 @@ void adam_update(ae_net* a, double lr, const ae_train_cfg& cfg, hipStream_t st)
     hipLaunchKernelGGL(adam_kernel, dim3(blocks(a->nparam, 256)), dim3(256), 0, st, a->master, a->m1, a->m2, a->grad,
                        a->nparam, (float)lr, (float)cfg.beta1, (float)cfg.beta2, (float)cfg.eps, (float)c1, (float)c2);
     WV_HIP(hipGetLastError());
-    refresh_bf16(a, st);
+    refresh_bf16(a, st, pack);
 }
 
 ae_net* new_net(int in, int hid, int lat)
@@ -1744,7 +1849,7 @@ int ae_train_step(ae_net* a, const uint16_t* y, const float* meta, const int32_t
         WV_REQUIRE(!cfg->weighting || meta, WV_EINVAL, "weighted loss needs meta");
         WV_REQUIRE(B % 32 == 0, WV_EINVAL, "batch must be a multiple of 32");
         hipStream_t st = (hipStream_t)stream;
-        const int splits = std::max(1, std::min(8, B / 512));
+        const int splits = train_splits(B);
         TrainBufs t = train_buffers(a, B, splits, st);
         double* dloss = a->loss_d;
         train_batch(a, y, meta, cfg->weighting, idx, B, t, splits, dloss, 0, st);
@@ -1768,7 +1873,7 @@ int ae_train(ae_net* a, const uint16_t* y, const float* meta, int64_t nsamples, 
         WV_REQUIRE(cfg->epochs >= 0 && nsamples >= cfg->batch, WV_EINVAL, "need at least one full batch");
         hipStream_t st = (hipStream_t)stream;
         const int B = cfg->batch;
-        const int splits = std::max(1, std::min(8, B / 512));
+        const int splits = train_splits(B);
         TrainBufs t = train_buffers(a, B, splits, st);
         double* dloss = a->loss_d;
         const long long nb = nsamples / B;
@@ -1785,13 +1890,14 @@ int ae_train(ae_net* a, const uint16_t* y, const float* meta, int64_t nsamples, 
             const int* order = perm ? perm + (long long)e * nsamples : dseq;
             for (long long b = 0; b < nb; ++b) {
                 train_batch(a, y, meta, cfg->weighting, order + b * B, B, t, splits, dloss, b > 0, st);
-                adam_update(a, lr, *cfg, st);
+                adam_update(a, lr, *cfg, st, false);
             }
             double L = 0;
             WV_HIP(hipMemcpyAsync(&L, dloss, sizeof(double), hipMemcpyDeviceToHost, st));
             WV_HIP(hipStreamSynchronize(st));
             if (h_loss) h_loss[e] = (float)(L / (double)nb);
         }
+        pack_fused(a, st);
         WV_HIP(hipStreamSynchronize(st));
         if (dseq) (void)hipFree(dseq);
         return WV_OK;
