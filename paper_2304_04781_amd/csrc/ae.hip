@@ -857,14 +857,31 @@ __global__ void sum_partials_kernel(const double* __restrict__ partial, int n, d
 }
 
 // sum split-K partials [splits][n] -> out[n]
-__global__ void splitsum_kernel(const float* __restrict__ part, int splits, long long n, float* __restrict__ out)
+// (n a multiple of 4): four consecutive elements per thread, eight partials loaded
+// ahead of their sums, every element summed in the order z = 0, 1, ...
+__global__ void __launch_bounds__(256) splitsum_kernel(const float* __restrict__ part, int splits, long long n,
+                                                      float* __restrict__ out)
 {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long i = (blockIdx.x * (long long)blockDim.x + threadIdx.x) * 4;
     if (i >= n) return;
-    float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += part[z * n + i];
-    out[i] = s;
+    const float4* p = reinterpret_cast<const float4*>(part + i);
+    const long long n4 = n / 4;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(long long)(z + u) * n4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = make_float4(s.x + v[u].x, s.y + v[u].y, s.z + v[u].z, s.w + v[u].w);
+    }
+    for (; z < splits; ++z) {
+        const float4 v = p[(long long)z * n4];
+        s = make_float4(s.x + v.x, s.y + v.y, s.z + v.z, s.w + v.w);
+    }
+    *reinterpret_cast<float4*>(out + i) = s;
 }
+
 
 __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                             const float* __restrict__ g, long long n, float lr, float b1, float b2, float eps,
@@ -923,6 +940,13 @@ __global__ void __launch_bounds__(256) convert_kernel(const ConvLayers a)
 }
 
 int blocks(long long n, int bs) { return (int)std::max<long long>(1, (n + bs - 1) / bs); }
+
+// out[n] = sum over z of part[z][n], n a multiple of 4 (the layer widths are)
+void splitsum(const float* part, int splits, long long n, float* out, hipStream_t st)
+{
+    WV_REQUIRE(n % 4 == 0, WV_EINVAL, "split sums need a multiple of 4 elements");
+    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks((n + 3) / 4, 256)), dim3(256), 0, st, part, splits, n, out);
+}
 
 
 }  // namespace
@@ -1398,14 +1422,13 @@ void weight_grad(ae_net* a, int l, int B, const uint16_t* Xt, const uint16_t* Dt
     const long long n = (long long)fi * fo;
     gemm_auto(fi, fo, B, LoadK{Xt, B, nullptr, fi, B}, LoadK{Dt, B, nullptr, fo, B},
               EpiF32{t.part, fo, n, nullptr}, st, splits);
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, t.part, splits, n, a->grad + a->oW[l]);
+    splitsum(t.part, splits, n, a->grad + a->oW[l], st);
 }
 
 // bias gradient of layer l: the row-tile partial column sums of width n, summed in order
 void bias_grad(ae_net* a, int l, int B, int bm, int n, TrainBufs& t, hipStream_t st)
 {
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, t.colpart, (B + bm - 1) / bm,
-                       (long long)n, a->grad + a->ob[l]);
+    splitsum(t.colpart, (B + bm - 1) / bm, n, a->grad + a->ob[l], st);
 }
 
 void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting, const int* idx, int B,
