@@ -856,16 +856,27 @@ __global__ void sum_partials_kernel(const double* __restrict__ partial, int n, d
     if (threadIdx.x == 0) out[0] = (accumulate ? out[0] : 0.0) + scale * sh[0];
 }
 
-// sum split-K partials [splits][n] -> out[n]
-// (n a multiple of 4): four consecutive elements per thread, eight partials loaded
-// ahead of their sums, every element summed in the order z = 0, 1, ...
-__global__ void __launch_bounds__(256) splitsum_kernel(const float* __restrict__ part, int splits, long long n,
-                                                      float* __restrict__ out)
+// Several split sums in one launch: segment g sums part[g] ([splits[g]][4 n4[g]]) into
+// out[g], four consecutive elements per thread, eight partials loaded ahead of their
+// sums, each element summed in the order z = 0, 1, ...
+struct SumSegs {
+    const float* part[8];
+    float* out[8];
+    long long n4[8];
+    int splits[8];
+    long long first[9];  // first float4 of each segment in the launch
+    int nseg;
+};
+__global__ void __launch_bounds__(256) sums_kernel(const SumSegs g)
 {
-    const long long i = (blockIdx.x * (long long)blockDim.x + threadIdx.x) * 4;
-    if (i >= n) return;
-    const float4* p = reinterpret_cast<const float4*>(part + i);
-    const long long n4 = n / 4;
+    const long long q = blockIdx.x * 256LL + threadIdx.x;
+    if (q >= g.first[g.nseg]) return;
+    int sg = 0;
+    while (sg + 1 < g.nseg && q >= g.first[sg + 1]) ++sg;
+    const long long j = q - g.first[sg];
+    const long long n4 = g.n4[sg];
+    const int splits = g.splits[sg];
+    const float4* p = reinterpret_cast<const float4*>(g.part[sg]) + j;
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     int z = 0;
     for (; z + 8 <= splits; z += 8) {
@@ -879,7 +890,7 @@ __global__ void __launch_bounds__(256) splitsum_kernel(const float* __restrict__
         const float4 v = p[(long long)z * n4];
         s = make_float4(s.x + v.x, s.y + v.y, s.z + v.z, s.w + v.w);
     }
-    *reinterpret_cast<float4*>(out + i) = s;
+    reinterpret_cast<float4*>(g.out[sg])[j] = s;
 }
 
 
@@ -941,12 +952,6 @@ __global__ void __launch_bounds__(256) convert_kernel(const ConvLayers a)
 
 int blocks(long long n, int bs) { return (int)std::max<long long>(1, (n + bs - 1) / bs); }
 
-// out[n] = sum over z of part[z][n], n a multiple of 4 (the layer widths are)
-void splitsum(const float* part, int splits, long long n, float* out, hipStream_t st)
-{
-    WV_REQUIRE(n % 4 == 0, WV_EINVAL, "split sums need a multiple of 4 elements");
-    hipLaunchKernelGGL(splitsum_kernel, dim3(blocks((n + 3) / 4, 256)), dim3(256), 0, st, part, splits, n, out);
-}
 
 
 }  // namespace
@@ -1312,14 +1317,16 @@ namespace {
 
 // One Adam step on a batch. Returns (device) the batch loss in *dloss (added if accumulate).
 struct TrainBufs {
-    float *a1, *a3, *part, *w;  // pre-activations of layers 1 and 3; split-K partials; sample weights
-    float* colpart;  // column sums of a layer's d per row tile [ceil(B/64)][max(in, hid)]
+    float *a1, *a3, *w;  // pre-activations of layers 1 and 3; sample weights
+    float* wpart[4];     // per layer: weight-gradient partials of the batch splits [splits][fi][fo]
+    float* bpart[4];     // per layer: bias-gradient partials, column sums per row tile [ceil(B/64)][fo]
     double* lossp;   // [row tiles][column tiles] loss partials of the output layer
     uint16_t *h1, *zb, *h3, *d4, *d3, *dz, *d1;
     // the same [width][batch] (written transposed by the epilogues: the weight gradients'
     // operands), and the batch's input rows transposed
     uint16_t *h1t, *zbt, *h3t, *d4t, *d3t, *dzt, *d1t, *yt;
     double* wsum;
+    bool w_const = false;  // w and wsum hold the unweighted loss's constant weights
 };
 
 TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
@@ -1332,9 +1339,13 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
         return r;
     };
     const size_t nb = B;
+    size_t o_wp[4], o_bp[4];
+    for (int l = 0; l < 4; ++l) {
+        o_wp[l] = take((size_t)splits * a->fi[l] * a->fo[l] * 4);
+        o_bp[l] = take(((nb + 63) / 64) * a->fo[l] * 4);
+    }
     const size_t o_a1 = take(nb * hid * 4), o_a3 = take(nb * hid * 4),
-                 o_cp = take(((nb + 63) / 64) * std::max(in, hid) * 4),
-                 o_loss = take(((nb + 63) / 64) * (in / 32) * 8), o_part = take((size_t)splits * in * hid * 4),
+                 o_loss = take(((nb + 63) / 64) * (in / 32) * 8),
                  o_h1 = take(nb * hid * 2), o_zb = take(nb * lat * 2), o_h3 = take(nb * hid * 2),
                  o_d4 = take(nb * in * 2), o_d3 = take(nb * hid * 2), o_dz = take(nb * lat * 2),
                  o_d1 = take(nb * hid * 2), o_h1t = take(nb * hid * 2), o_zbt = take(nb * lat * 2),
@@ -1345,9 +1356,11 @@ TrainBufs train_buffers(const ae_net* a, int B, int splits, hipStream_t st)
     TrainBufs t;
     t.a1 = (float*)(w + o_a1);
     t.a3 = (float*)(w + o_a3);
-    t.colpart = (float*)(w + o_cp);
+    for (int l = 0; l < 4; ++l) {
+        t.wpart[l] = (float*)(w + o_wp[l]);
+        t.bpart[l] = (float*)(w + o_bp[l]);
+    }
     t.lossp = (double*)(w + o_loss);
-    t.part = (float*)(w + o_part);
     t.h1 = (uint16_t*)(w + o_h1);
     t.zb = (uint16_t*)(w + o_zb);
     t.h3 = (uint16_t*)(w + o_h3);
@@ -1412,23 +1425,40 @@ void transpose_rows(const uint16_t* src, long long ld, const int* rows, int R, i
     WV_HIP(hipGetLastError());
 }
 
-// dW_l = X^T D summed over the batch, from both operands stored transposed
-// ([width][batch], so the GEMM streams whole k-contiguous rows): split over the batch,
-// the partials summed in a fixed order
+// dW_l = X^T D over the batch, from both operands stored transposed ([width][batch], so
+// the GEMM streams whole k-contiguous rows): the batch is split `splits` ways and the
+// partials are summed at the end of the batch (sum_grads)
 void weight_grad(ae_net* a, int l, int B, const uint16_t* Xt, const uint16_t* Dt, TrainBufs& t, int splits,
                  hipStream_t st)
 {
     const int fi = a->fi[l], fo = a->fo[l];
-    const long long n = (long long)fi * fo;
     gemm_auto(fi, fo, B, LoadK{Xt, B, nullptr, fi, B}, LoadK{Dt, B, nullptr, fo, B},
-              EpiF32{t.part, fo, n, nullptr}, st, splits);
-    splitsum(t.part, splits, n, a->grad + a->oW[l], st);
+              EpiF32{t.wpart[l], fo, (long long)fi * fo, nullptr}, st, splits);
 }
 
-// bias gradient of layer l: the row-tile partial column sums of width n, summed in order
-void bias_grad(ae_net* a, int l, int B, int bm, int n, TrainBufs& t, hipStream_t st)
+// every gradient of the batch from its partials, in one launch: the 4 weight gradients
+// (split sums) and the 4 bias gradients (row-tile column sums of width fo_l, from
+// work-group tiles of bm[l] rows), each summed in a fixed order
+void sum_grads(ae_net* a, int B, int splits, const int* bm, TrainBufs& t, hipStream_t st)
 {
-    splitsum(t.colpart, (B + bm - 1) / bm, n, a->grad + a->ob[l], st);
+    SumSegs g{};
+    long long q = 0;
+    int sg = 0;
+    for (int l = 0; l < 4; ++l)
+        for (int b = 0; b < 2; ++b) {
+            const long long n = b ? a->fo[l] : (long long)a->fi[l] * a->fo[l];
+            WV_REQUIRE(n % 4 == 0, WV_EINVAL, "gradient sums need layer widths that are multiples of 4");
+            g.part[sg] = b ? t.bpart[l] : t.wpart[l];
+            g.out[sg] = a->grad + (b ? a->ob[l] : a->oW[l]);
+            g.n4[sg] = n / 4;
+            g.splits[sg] = b ? (B + bm[l] - 1) / bm[l] : splits;
+            g.first[sg] = q;
+            q += n / 4;
+            ++sg;
+        }
+    g.first[sg] = q;
+    g.nseg = sg;
+    hipLaunchKernelGGL(sums_kernel, dim3(blocks(q, 256)), dim3(256), 0, st, g);
 }
 
 void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting, const int* idx, int B,
@@ -1444,32 +1474,35 @@ void train_batch(ae_net* a, const uint16_t* y, const float* meta, int weighting,
               EpiGelu{t.h3, hid, a->bias(2), t.a3, t.h3t, B}, st);
     // output layer with the loss: d4 (bf16 and transposed), the b4 gradient's row-tile
     // partials, the loss per tile
-    hipLaunchKernelGGL(batch_weights_kernel, dim3(1), dim3(256), 0, st, meta, idx, B, a->beta_d, weighting, t.w,
-                       t.wsum);
-    const int bm4 = gemm_auto_bm(B, in), bn4 = gemm_auto_bn(B, in);
+    // (the plain loss's weights are all 1, the same for every batch: set once)
+    if (weighting || !t.w_const) {
+        hipLaunchKernelGGL(batch_weights_kernel, dim3(1), dim3(256), 0, st, meta, idx, B, a->beta_d, weighting, t.w,
+                           t.wsum);
+        t.w_const = !weighting;
+    }
+    // rows of the work-group tiles whose column sums make each layer's bias gradient
+    const int bm[4] = {gemm_auto_bm(B, hid), gemm_auto_bm(B, lat), gemm_auto_bm(B, hid), gemm_auto_bm(B, in)};
+    const int bn4 = gemm_auto_bn(B, in);
     gemm_auto(B, in, hid, LoadK{t.h3, hid, nullptr, B, hid}, LoadK{a->wt[3], hid, nullptr, in, hid},
-              EpiMse{a->bias(3), y, idx, in, t.w, t.wsum, t.d4, t.colpart, t.lossp, in / bn4, t.d4t, B}, st);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lossp, ((B + bm4 - 1) / bm4) * (in / bn4),
-                       1.0, dloss, accumulate);
-    bias_grad(a, 3, B, bm4, in, t, st);
+              EpiMse{a->bias(3), y, idx, in, t.w, t.wsum, t.d4, t.bpart[3], t.lossp, in / bn4, t.d4t, B}, st);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, t.lossp,
+                       ((B + bm[3] - 1) / bm[3]) * (in / bn4), 1.0, dloss, accumulate);
     // backward: layer 4
     weight_grad(a, 3, B, t.h3t, t.d4t, t, splits, st);
     gemm_auto(B, hid, in, LoadK{t.d4, in, nullptr, B, in}, LoadK{a->wb[3], in, nullptr, hid, in},
-              EpiGeluBack{t.d3, t.a3, hid, t.colpart, t.d3t, B}, st);
-    bias_grad(a, 2, B, gemm_auto_bm(B, hid), hid, t, st);
+              EpiGeluBack{t.d3, t.a3, hid, t.bpart[2], t.d3t, B}, st);
     // layer 3
     weight_grad(a, 2, B, t.zbt, t.d3t, t, splits, st);
     gemm_auto(B, lat, hid, LoadK{t.d3, hid, nullptr, B, hid}, LoadK{a->wb[2], hid, nullptr, lat, hid},
-              EpiBF16T{t.dz, lat, nullptr, t.colpart, t.dzt, B}, st);
-    bias_grad(a, 1, B, gemm_auto_bm(B, lat), lat, t, st);
+              EpiBF16T{t.dz, lat, nullptr, t.bpart[1], t.dzt, B}, st);
     // layer 2
     weight_grad(a, 1, B, t.h1t, t.dzt, t, splits, st);
     gemm_auto(B, hid, lat, LoadK{t.dz, lat, nullptr, B, lat}, LoadK{a->wb[1], lat, nullptr, hid, lat},
-              EpiGeluBack{t.d1, t.a1, hid, t.colpart, t.d1t, B}, st);
-    bias_grad(a, 0, B, gemm_auto_bm(B, hid), hid, t, st);
+              EpiGeluBack{t.d1, t.a1, hid, t.bpart[0], t.d1t, B}, st);
     // layer 1: the batch's input rows, gathered and transposed
     transpose_rows(y, in, idx, B, in, t.yt, st);
     weight_grad(a, 0, B, t.yt, t.d1t, t, splits, st);
+    sum_grads(a, B, splits, bm, t, st);
     WV_HIP(hipGetLastError());
 }
 
