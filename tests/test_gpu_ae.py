@@ -198,6 +198,35 @@ def test_train_step_gradients_and_adam_against_oracle(weighting):
         assert np.allclose(new[k], ref[k], rtol=0, atol=2e-6 + 1e-6 * np.abs(ref[k]).max()), k
 
 
+@pytest.mark.parametrize("B", [96, 160])
+def test_train_step_ragged_batch_against_oracle(B):
+    """Batches that are not a multiple of the 64-row work-group tile: the last row
+    tile of every training product is partial (32 rows), so the loss per tile, the
+    bias column sums per row tile and the transposed epilogue outputs run on ragged
+    tiles. Loss and all eight gradients against the emulating oracle."""
+    prm = W.ae_init(seed=4)
+    net = Net(prm)
+    X = np.concatenate([oae.patchify(W.smooth_random_state(4, 32, 32, 32, seed=s)) for s in range(60, 63)])[:B]
+    Y, lo, r = oae.normalize(X, [1e-7] * 4)
+    meta = np.stack([lo, r], axis=2).astype(np.float32)
+    ybits = rd.bf16_bits(Y)
+    idx = np.random.default_rng(B).permutation(B).astype(np.int32)
+    print(f"case: train step ragged batch {B}", flush=True)
+    loss, g = L.ae_train_step(net.handle, torch.tensor(ybits.view(np.int16), device="cuda"),
+                              torch.tensor(idx, device="cuda"), B, 1e-3, L.train_cfg(epochs=1, batch=B, weighting=1),
+                              want_grads=True, meta=torch.tensor(meta, device="cuda"))
+    ae = oae.AE(net.prm32)
+    fw = (meta[idx, :, 1].astype(np.float64) / np.float32(1e-7)) ** 2
+    loss_o, g_o = ae.loss_and_grads(rd.bf16_from_bits(ybits[idx]), emulate=True, field_weights=fw)
+    gg = unflat(g)
+    errs = {k: rel(gg[k], g_o[k]) for k in oae.NAMES}
+    print(f"train step B={B}: loss rel diff {abs(loss - loss_o) / loss_o:.2e}, gradient rel err "
+          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert abs(loss - loss_o) / loss_o < 1e-6
+    for k in oae.NAMES:
+        assert errs[k] < 5e-4, k
+
+
 def test_train_step_batch_4096_against_oracle():
     """One Adam step at the training batch of the workloads (4096 patch vectors):
     the decoder's output layer and the weight-gradient products then run on the
