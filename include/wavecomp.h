@@ -119,9 +119,13 @@ typedef struct ae_train_cfg {
 /* Create a solver context on the current device. h_src: [nsrc][3] (k, j, i) of
  * the v_z face carrying each source's vertical point force; h_rec: [nrec][3]
  * (k, j, i) of the sampled v_z faces (shared by all sources). stream: a
- * hipStream_t (NULL = default stream). Fails with WV_EINVAL for indices outside
- * the grid or a (y, x) plane of 2^30 cells or more, WV_ENOMEM when work buffers
- * cannot be allocated. */
+ * hipStream_t (NULL = default stream) that runs the stencil steps; the
+ * compression, decompression and exception work of the autoencoder modes runs on
+ * three non-blocking side streams at the default priority, created with the first
+ * context on a device and shared by every context on it (calls on different
+ * contexts of one device are serialised there, and events order them with each
+ * context's stream). Fails with WV_EINVAL for indices outside the grid or a (y, x)
+ * plane of 2^30 cells or more, WV_ENOMEM when work buffers cannot be allocated. */
 int wv_create(const wv_grid* grid, const int32_t* h_src, const int32_t* h_rec,
               void* stream, wv_ctx** out);
 
@@ -483,7 +487,7 @@ int wv_stats(const wv_ctx* ctx, int64_t* h_forward_steps, double* h_guard_err, i
 
 /* Kernel timing. every > 0: every every-th launch of each timed class is
  * bracketed by HIP events recorded on the stream that runs it: the context's
- * stream for the stencil steps; in the autoencoder modes the context's own side
+ * stream for the stencil steps; in the autoencoder modes the device's side
  * streams for the compression (forward sweep), the exception selection and copy
  * (forward sweep) and the decompressions of the reverse and incremental sweeps,
  * which run beside the stencil steps. every = 0 switches timing off. Either call

@@ -1160,8 +1160,18 @@ void shared_side(wv_ctx* c)
     WV_HIP(hipGetDevice(&dev));
     WV_REQUIRE(dev >= 0 && dev < SIDE_MAX_DEVICES, WV_EDEVICE, "device ordinal beyond the side-stream table");
     std::lock_guard<std::mutex> lock(g_side_mu);
-    if (!g_side[dev][0])
-        for (int q = 0; q < 3; ++q) WV_HIP(hipStreamCreateWithFlags(&g_side[dev][q], hipStreamNonBlocking));
+    if (!g_side[dev][0]) {
+        // all three or none: a failed creation leaves the table empty for the next context
+        hipStream_t made[3] = {};
+        for (int q = 0; q < 3; ++q) {
+            const hipError_t e = hipStreamCreateWithFlags(&made[q], hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                for (int r = 0; r < q; ++r) (void)hipStreamDestroy(made[r]);
+                WV_HIP(e);
+            }
+        }
+        for (int q = 0; q < 3; ++q) g_side[dev][q] = made[q];
+    }
     c->side = g_side[dev][0];
     c->side2 = g_side[dev][1];
     c->side3 = g_side[dev][2];
