@@ -72,11 +72,14 @@ constexpr int BK = 64;  // k per LDS stage: two 32-deep MFMA steps; depths below
 constexpr int LDS_PAD = WV_LDS_PAD;  // bf16 elements of padding per LDS row
 
 // registers holding one BR x BK tile between its global load and its LDS store:
-// chunk c = tid + 256 i of 8 bf16 in v[i]
+// chunk c = tid + 256 i of 8 bf16 in v[i], kept where m[i] is all ones (zero elsewhere:
+// past the last row or the depth limit); the mask is applied at the store, so the
+// loaded registers are not waited for before then
 template <int BR>
 struct Frag {
     static constexpr int NC = (BR * (BK / 8) + 255) / 256;
     uint4 v[NC];
+    unsigned m[NC];
 };
 
 // an epilogue with kTile = true takes the whole C tile from LDS: tile(m0, n0, rows, cols, C, ldc)
@@ -89,12 +92,13 @@ struct EpiHasTile<E, std::void_t<decltype(E::kTile)>> {
     static constexpr bool value = E::kTile;
 };
 
-// per-thread loader state of one work-group's tile rows, set before the k loop:
-// the source address of each of its chunks (null: past the last row), so a stage
-// only adds its k offset
+// per-thread loader state of one work-group's tile rows, set before the k loop: the
+// source row of each of its chunks (clamped to a valid row past the last one, with its
+// bit in `ok` cleared), so every stage issues the same loads and only adds its k offset
 template <int BR>
 struct LoadState {
     const uint16_t* row[Frag<BR>::NC];
+    unsigned ok;
 };
 
 // source stored [rows][ld] with k contiguous; optional row gather
@@ -107,23 +111,34 @@ struct LoadK {
     template <int BR>
     __device__ __forceinline__ void prepare(int r0, int tid, LoadState<BR>& s) const
     {
+        static_assert(BR * (BK / 8) % 256 == 0, "every thread owns whole chunks");
+        s.ok = 0;
 #pragma unroll
         for (int i = 0; i < Frag<BR>::NC; ++i) {
             const int c = tid + 256 * i;
-            const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-            const int gr = r0 + r;
-            s.row[i] = (c < BR * (BK / 8) && gr < nrows) ? p + (long long)(rows ? rows[gr] : gr) * ld + kc : nullptr;
+            const int gr = r0 + c / (BK / 8);
+            const bool ok = gr < nrows;
+            const int rr = ok ? gr : 0;
+            s.row[i] = p + (long long)(rows ? rows[rr] : rr) * ld;
+            s.ok |= (unsigned)ok << i;
         }
     }
+    // chunk (row, k0 + kc .. + 7) of every owned chunk, zero past the last row or at
+    // depths >= klim; the load itself is always issued (at depth 0 of the row when the
+    // chunk is out of range), so every stage has the same number of loads in flight
     template <int BR>
-    __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int tid, Frag<BR>& f) const
+    __device__ __forceinline__ void fetch(const LoadState<BR>& s, int k0, int klim, int tid, Frag<BR>& f) const
     {
 #pragma unroll
         for (int i = 0; i < Frag<BR>::NC; ++i) {
             const int kc = ((tid + 256 * i) % (BK / 8)) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (s.row[i] && k0 + kc < k_total) v = *reinterpret_cast<const uint4*>(s.row[i] + k0);
-            f.v[i] = v;
+            const bool in = ((s.ok >> i) & 1u) && k0 + kc < klim;
+            f.v[i] = *reinterpret_cast<const uint4*>(s.row[i] + (in ? k0 + kc : 0));
+            // the mask passes through an empty asm statement, so the compiler cannot tell
+            // when the loaded value is unused and keeps the load unconditional
+            unsigned m = in ? 0xFFFFFFFFu : 0u;
+            asm volatile("" : "+v"(m));
+            f.m[i] = m;
         }
     }
     template <int BR>
@@ -132,7 +147,9 @@ struct LoadK {
 #pragma unroll
         for (int i = 0; i < Frag<BR>::NC; ++i) {
             const int c = tid + 256 * i;
-            if (c < BR * (BK / 8)) *reinterpret_cast<uint4*>(&lds[c / (BK / 8)][(c % (BK / 8)) * 8]) = f.v[i];
+            const unsigned m = f.m[i];
+            *reinterpret_cast<uint4*>(&lds[c / (BK / 8)][(c % (BK / 8)) * 8]) =
+                make_uint4(f.v[i].x & m, f.v[i].y & m, f.v[i].z & m, f.v[i].w & m);
         }
     }
 };
@@ -171,47 +188,64 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
         for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    Frag<BM> fa;
-    Frag<BN> fb;
+    // PF k-tiles in flight: while tile i is multiplied from one LDS stage, tile i + 1 waits
+    // in registers to be stored to the other and tiles up to i + PF - 1 are being loaded
+    // (a ring of PF - 1 register fragments). Every stage issues the same loads (zeros past
+    // this split's depth), so the compiler counts the loads in flight exactly and waits
+    // only for the tile it stores.
+    constexpr int PF = (BM >= 128 && BN >= 128) ? 3 : 4;
+    Frag<BM> fa[PF - 1];
+    Frag<BN> fb[PF - 1];
     LoadState<BM> sla;
     LoadState<BN> slb;
     la.template prepare<BM>(m0, tid, sla);
     lb.template prepare<BN>(n0, tid, slb);
-    if (kb < ke) {
-        la.template fetch<BM>(sla, kb, tid, fa);
-        lb.template fetch<BN>(slb, kb, tid, fb);
-        la.template store<BM>(fa, tid, sA[0]);
-        lb.template store<BN>(fb, tid, sB[0]);
+    const int nkt = kb < ke ? (ke - kb + BK - 1) / BK : 0;
+    {
+        Frag<BM> f0;
+        Frag<BN> g0;
+        la.template fetch<BM>(sla, kb, ke, tid, f0);
+        lb.template fetch<BN>(slb, kb, ke, tid, g0);
+#pragma unroll
+        for (int q = 0; q < PF - 1; ++q) {
+            la.template fetch<BM>(sla, kb + (q + 1) * BK, ke, tid, fa[q]);
+            lb.template fetch<BN>(slb, kb + (q + 1) * BK, ke, tid, fb[q]);
+        }
+        la.template store<BM>(f0, tid, sA[0]);
+        lb.template store<BN>(g0, tid, sB[0]);
     }
     __syncthreads();
-    int cur = 0;
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        const bool more = k0 + BK < ke;
-        if (more) {
-            la.template fetch<BM>(sla, k0 + BK, tid, fa);
-            lb.template fetch<BN>(slb, k0 + BK, tid, fb);
+    // tile t waits in ring slot (t - 1) % (PF - 1); the loop runs whole rounds of the ring
+    // (the tiles past the last are zeros and are not multiplied)
+    const int nit = (nkt + PF - 2) / (PF - 1) * (PF - 1);
+    for (int i0 = 0; i0 < nit; i0 += PF - 1) {
+#pragma unroll
+        for (int u = 0; u < PF - 1; ++u) {
+            const int i = i0 + u;
+            const int cur = i & 1;
+            if (i < nkt) {
+#pragma unroll
+                for (int ks = 0; ks < BK; ks += 32) {
+                    bf16x8 af[TM], bfr[TN];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+                        af[a] = *reinterpret_cast<const bf16x8*>(&sA[cur][wm0 + a * 16 + fr][ks + fk]);
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[cur][wn0 + b * 16 + fr][ks + fk]);
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < TN; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+                }
+            }
+            la.template store<BM>(fa[u], tid, sA[cur ^ 1]);
+            lb.template store<BN>(fb[u], tid, sB[cur ^ 1]);
+            la.template fetch<BM>(sla, kb + (i + PF) * BK, ke, tid, fa[u]);
+            lb.template fetch<BN>(slb, kb + (i + PF) * BK, ke, tid, fb[u]);
+            __syncthreads();
         }
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 32) {
-            bf16x8 af[TM], bfr[TN];
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-                af[a] = *reinterpret_cast<const bf16x8*>(&sA[cur][wm0 + a * 16 + fr][ks + fk]);
-#pragma unroll
-            for (int b = 0; b < TN; ++b)
-                bfr[b] = *reinterpret_cast<const bf16x8*>(&sB[cur][wn0 + b * 16 + fr][ks + fk]);
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
-        }
-        if (more) {
-            la.template store<BM>(fa, tid, sA[cur ^ 1]);
-            lb.template store<BN>(fb, tid, sB[cur ^ 1]);
-        }
-        __syncthreads();
-        cur ^= 1;
     }
     // C layout of a 16x16 tile: lane holds column lane%16, rows 4*(lane/16) + r
     const int cc = lane & 15, cr = (lane >> 4) * 4;
@@ -291,14 +325,35 @@ struct EpiBF16 {  // bf16(v + bias), optional fp32 copy
 // Column sums of a float32 C tile (rows x cols in LDS, row stride ldc) into
 // colpart[m0 / bm][n0 + c]: the bias gradient of a training layer summed over the
 // tile's batch rows (a fixed order; the partials of all row tiles are summed after).
+// All 256 threads take part: column c's rows are split into 256 / cols contiguous
+// ranges, each summed in row order with eight loads ahead of the adds, and the range
+// sums are added in range order (cols <= 256).
 __device__ __forceinline__ void tile_colsum(float* colpart, long long ldp, int m0, int n0, int rows, int cols,
                                             const float* C, int ldc, int bm)
 {
+    __shared__ float red[256];
+    __syncthreads();
+    const int parts = 256 / cols;
+    if ((int)threadIdx.x < parts * cols) {
+        const int c = threadIdx.x % cols, part = threadIdx.x / cols;
+        const int r1 = (part + 1) * rows / parts;
+        int r = part * rows / parts;
+        float s = 0.f;
+        for (; r + 8 <= r1; r += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = C[(r + u) * ldc + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; r < r1; ++r) s += C[r * ldc + c];
+        red[threadIdx.x] = s;
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < cols; c += 256) {
-        float s = 0.f;
-        for (int r = 0; r < rows; ++r) s += C[r * ldc + c];
-        colpart[(long long)(m0 / bm) * ldp + n0 + c] = s;
+        float t = 0.f;
+        for (int p = 0; p < parts; ++p) t += red[p * cols + c];
+        colpart[(long long)(m0 / bm) * ldp + n0 + c] = t;
     }
 }
 
