@@ -66,6 +66,15 @@ __device__ __forceinline__ float e4m32f(uint8_t c)
 // that know the source layout; epilogues consume (row, col, value).
 // ------------------------------------------------------------------------------------
 constexpr int BK = 64;  // k per LDS stage: two 32-deep MFMA steps; depths below a multiple are zero-filled
+// k-tiles in flight in the generic GEMM (128 x 128 work-group tiles, smaller ones)
+#ifndef WV_GEMM_PF_BIG
+#define WV_GEMM_PF_BIG 3
+#endif
+#ifndef WV_GEMM_PF_SMALL
+#define WV_GEMM_PF_SMALL 4
+#endif
+constexpr int GEMM_PF_BIG = WV_GEMM_PF_BIG, GEMM_PF_SMALL = WV_GEMM_PF_SMALL;
+static_assert(GEMM_PF_BIG >= 2 && GEMM_PF_SMALL >= 2, "at least the next k-tile in flight");
 #ifndef WV_LDS_PAD
 #define WV_LDS_PAD 8
 #endif
@@ -193,7 +202,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, int k_pe
     // (a ring of PF - 1 register fragments). Every stage issues the same loads (zeros past
     // this split's depth), so the compiler counts the loads in flight exactly and waits
     // only for the tile it stores.
-    constexpr int PF = (BM >= 128 && BN >= 128) ? 3 : 4;
+    constexpr int PF = (BM >= 128 && BN >= 128) ? GEMM_PF_BIG : GEMM_PF_SMALL;
     Frag<BM> fa[PF - 1];
     Frag<BN> fb[PF - 1];
     LoadState<BM> sla;
