@@ -1,17 +1,18 @@
 // Fused autoencoder inference kernels for the time loop (gfx950, bf16 MFMA).
 //
-// encode: one work-group compresses 128 patches. The A operand (the normalised
-// patch vectors) is built on the fly from the float32 state and the per-patch
-// (min, range) metadata, rounded to bfloat16 and staged through LDS; the B
-// operand (W1^T, k contiguous) goes straight from L2 into registers, each of the
-// 8 waves owning 64 of the 512 hidden units. The hidden layer (bias + GELU,
-// bfloat16) stays in LDS and the second layer runs in the same work-group.
+// encode: one work-group of eight waves compresses 128 patches. The A operand (the
+// normalised patch vectors) is built on the fly from the float32 state and the per-patch
+// (min, range) metadata, rounded to bfloat16 and shared through LDS; each wave owns 64 of
+// the 512 hidden units and keeps their W1 fragments in registers, loaded straight from L2.
+// The second layer runs in the same work-group, split over the waves' hidden units.
 // decode: the mirror image for one field: latent -> hidden (bias + GELU, LDS)
 // -> 512 outputs of that field -> de-normalised float32 written into the state.
 //
 // Layout of a 16x16x32 bf16 MFMA (v_mfma_f32_16x16x32_bf16): A lane l holds
 // row l%16, k = 8*(l/16)..+7; B lane l holds column l%16, same k; C lane l
 // holds column l%16, rows 4*(l/16)..+3.
+
+#include <type_traits>
 
 #include "ae_internal.h"
 #include "ae_math.h"
@@ -24,24 +25,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// byte address of a shared-memory location, for inline-asm LDS instructions
-template <class T>
-__device__ __forceinline__ uint32_t lds_addr(T* p)
-{
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) T*)p;
-}
-
-constexpr int BM = 128;       // patches per work-group
+constexpr int BM = 128;       // patches per encode work-group
 constexpr int NT = 512;       // threads (8 waves)
 constexpr int HID = 512;      // hidden width handled by these kernels
 constexpr int KB = 32;        // k per MFMA step
-constexpr int APAD = 8;       // bf16 padding per LDS row
-constexpr int HPAD = 8;
-constexpr int RS = 4;  // raw A stages in flight (encode); the wait counts below assume 4
-// encode LDS: raw ring + two W1 fragment stages + bfloat16 double buffer, or the hidden layer
-constexpr int ENC_PH1 = RS * BM * KB * 4 + 2 * HID * KB * 2 + 2 * BM * (KB + APAD) * 2;
-constexpr int ENC_PH2 = BM * (HID + HPAD) * 2;
-constexpr int ENC_META_OFF = ENC_PH1 > ENC_PH2 ? ENC_PH1 : ENC_PH2;  // bytes; [BM][8] floats follow
+constexpr int HPAD = 8;       // bf16 padding per row of the decode's hidden layer
 
 struct EncArgs {
     const float* state;   // [4][N]
@@ -80,43 +68,13 @@ struct DecArgs {
     const int* erng;
 };
 
-template <int L>
-__global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
+// Per-patch (lo, 1/r) of the work-group's bm patches into sMeta [bm][8] (threads
+// tid < bm, one patch each). From the forward step's (min, max) partials the metadata is
+// also computed here and published (float32, or bfloat16 with lo rounded down and r up);
+// otherwise it is read from `meta`.
+__device__ __forceinline__ void enc_meta(const EncArgs& a, long long m0, int tid, float* sMeta, int bm)
 {
-    extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
-    // phase 1: a ring of RS raw float32 stages [RS][BM][KB] and two stages of W1
-    // fragments [2][8 waves][4][64 lanes][8] (both filled by direct global->LDS
-    // loads), then the normalised bfloat16 double buffer [2][BM][KB + APAD];
-    // phase 2: H [BM][HID + HPAD] over the same bytes
-    float(*sRaw)[BM * KB] = reinterpret_cast<float(*)[BM * KB]>(smem);
-    uint16_t* sB = smem + RS * BM * KB * 2;                                    // 2 x 32 KiB
-    uint16_t(*sA)[BM][KB + APAD] = reinterpret_cast<uint16_t(*)[BM][KB + APAD]>(sB + 2 * HID * KB);
-    uint16_t(*sH)[HID + HPAD] = reinterpret_cast<uint16_t(*)[HID + HPAD]>(smem);
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const long long m0 = (long long)blockIdx.x * BM;
-
-    // A staging: thread -> (patch row m, one of 4 ly rows of a k-step)
-    const int am = tid >> 2, aq = tid & 3;
-    const long long pa = m0 + am;
-    const bool a_ok = pa < a.P;
-    // per-field (min, 1/range) of the block's patches, in LDS after the hidden-layer area
-    float* sMeta = reinterpret_cast<float*>(smem + ENC_META_OFF / 2);  // [BM][8]
-    // direct loads: a stage holds 1024 pieces of 16 bytes, piece = 8 m + 2 row + half
-    // (patch m, y row 4 (kk % 2) + row, x half); wave w loads pieces [128 w, 128 w + 128)
-    // in two instructions, so a lane of instruction t owns piece 128 w + 64 t + lane.
-    long long dbase[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int pc = 128 * wave + 64 * t + lane;
-        const long long pm = m0 + (pc >> 3);
-        dbase[t] = -1;
-        if (pm < a.P) {
-            const long long px = pm % a.Px, py = (pm / a.Px) % a.Py, pz = pm / ((long long)a.Px * a.Py);
-            dbase[t] = (pz * 8 * a.ny + py * 8 + ((pc >> 1) & 3)) * a.nx + px * 8 + (pc & 1) * 4;
-        }
-    }
-    if (tid < BM) {
+    if (tid < bm) {
         const long long p = m0 + tid;
         if (a.mm) {
             // combine the y sub-tile partials: r = max(max - min, beta_f); publish the metadata
@@ -155,220 +113,234 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
             *reinterpret_cast<float4*>(sMeta + tid * 8 + 4) = make_float4(m23.x, 1.0f / m23.y, m23.z, 1.0f / m23.w);
         }
     }
-    __syncthreads();
-    // k-step kk covers field f = kk/16, lz = (kk%16)/2, ly = 4*(kk%2) + aq: rows of 8 x-cells
-    const int fr = lane & 15, fq = (lane >> 4) * 8;
+}
 
-    f32x4 acc[8][4];
+// The encode work-group: eight waves over BM = 128 patches, wave w owning hidden units
+// 64 w .. 64 w + 63. A wave loads the W1 fragments of its hidden units straight from L2
+// into a register ring and each thread one raw state row of its patch into another; LDS
+// holds only the normalised bfloat16 A double buffer, in the order the MFMA reads it (each
+// fragment read is one contiguous 1 KiB per wave, free of bank conflicts), and the
+// per-field (lo, 1/r). The second layer runs split over the waves' hidden units: each wave
+// multiplies its 64 GELU outputs (staged per row tile through a private LDS area) by the
+// matching columns of W2, and the eight partial latent blocks are summed in wave order
+// through LDS. A work-group takes about 230 registers per lane of each wave, so one fills a
+// CU's register file.
+#ifndef WV_ENC_WD
+#define WV_ENC_WD 3
+#endif
+#ifndef WV_ENC_RD
+#define WV_ENC_RD 3
+#endif
+constexpr int ENC_WD = WV_ENC_WD, ENC_RD = WV_ENC_RD;  // register ring depths (W1, raw rows): 2 or 3
+constexpr int ENC_HLD = 64 + 8;  // bf16 row of a wave's hidden staging tile [16][ENC_HLD]
+constexpr int ENC_ZLD = 32 + 4;  // float row of the latent partial sums [BM][ENC_ZLD]
+constexpr int ENC_R_BYTES = 8 * 16 * ENC_HLD * 2;  // the largest use of the shared region
+
+template <int L, int WD, int RD>
+__global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
+{
+    static_assert(L == 32, "two latent column tiles");
+    static_assert((WD == 2 || WD == 3) && (RD == 2 || RD == 3), "ring depths");
+    constexpr int TI = BM / 16;             // row tiles
+    constexpr int A_HALF = TI * 64 * 8;     // bf16 per A buffer: [TI][64 lanes][8]
+    static_assert(NT == 4 * BM, "one thread per raw row of a step");
+    static_assert(2 * A_HALF * 2 <= ENC_R_BYTES && BM * ENC_ZLD * 4 <= ENC_R_BYTES && BM * 8 * 4 <= ENC_R_BYTES,
+                  "the A buffers, the second layer's staging and the metadata share one region");
+    __shared__ __attribute__((aligned(16))) uint16_t sR[ENC_R_BYTES / 2];
+    __shared__ __attribute__((aligned(16))) float2 sLR[4][BM];  // (lo, 1/r) per field and patch
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const long long m0 = (long long)blockIdx.x * BM;
+    const int fr = lane & 15, fq = (lane >> 4) * 8, cr = (lane >> 4) * 4;
+
+    // thread (am, aq) loads and normalises y row aq (of the four of a k-step) of patch am:
+    // a wave covers one row of 64 patches. Rows of patches past P read patch 0 and are zeroed.
+    const int am = tid & (BM - 1), aq = tid / BM;
+    const long long pa = m0 + am;
+    const bool a_ok = pa < a.P;
+    long long abase = 0;
+    if (a_ok) {
+        const long long px = pa % a.Px, py = (pa / a.Px) % a.Py, pz = pa / ((long long)a.Px * a.Py);
+        abase = ((pz * 8) * a.ny + py * 8 + aq) * a.nx + px * 8;
+    }
+    const float* rsrc = a.state + abase;
+    const long long plane = (long long)a.ny * a.nx;
+    // k-step kk: field kk / 16, z level (kk % 16) / 2, y rows 4 (kk % 2) .. + 3. Steps past
+    // the last reload the last one, so every step issues the same loads.
+    auto load_raw = [&](int kk, float4(&d)[2]) {
+        const int k = kk < 64 ? kk : 63;
+        const float* s = rsrc + ((k >> 4) * a.N + ((k & 15) >> 1) * plane + 4 * (k & 1) * a.nx);
+        d[0] = *reinterpret_cast<const float4*>(s);
+        d[1] = *reinterpret_cast<const float4*>(s + 4);
+    };
+    // fragment-ordered W1: block (kk, hidden tile t) of 64 lanes x 8 values at ((kk * 32 + t) * 64) * 8;
+    // wave w owns hidden tiles 4 w .. 4 w + 3
+    const uint16_t* wsrc = a.w1p + ((long long)(wave * 4) * 64 + lane) * 8;
+    auto load_w = [&](int kk, uint4(&d)[4]) {
+        const int k = kk < 64 ? kk : 63;
+        const uint16_t* s = wsrc + (long long)k * (HID * KB);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 4; ++j) d[j] = *reinterpret_cast<const uint4*>(s + j * 512);
+    };
+    // register rings: W1 of kk in slot kk % WD, loaded at the start of step kk - WD + 1; the
+    // raw rows of kk in slot kk % RD, loaded at the start of step kk - RD and normalised at
+    // the end of step kk - 1
+    uint4 wb[WD][4];
+    float4 rw[RD][2];
+#pragma unroll
+    for (int q = 0; q < RD; ++q) load_raw(q, rw[q]);
+#pragma unroll
+    for (int q = 0; q < WD - 1; ++q) load_w(q, wb[q]);
+
+    {
+        float* sMeta = reinterpret_cast<float*>(sR);  // [BM][8], free again once sLR is filled
+        enc_meta(a, m0, tid, sMeta, BM);
+        __syncthreads();
+        if (tid < BM) {
+            const float4 m01 = *reinterpret_cast<const float4*>(sMeta + tid * 8);
+            const float4 m23 = *reinterpret_cast<const float4*>(sMeta + tid * 8 + 4);
+            sLR[0][tid] = make_float2(m01.x, m01.y);
+            sLR[1][tid] = make_float2(m01.z, m01.w);
+            sLR[2][tid] = make_float2(m23.x, m23.y);
+            sLR[3][tid] = make_float2(m23.z, m23.w);
+        }
+        __syncthreads();
+    }
+    // A fragment (row tile i, lane l) holds patch 16 i + l % 16, k 8 (l / 16) .. + 7, i.e. y row
+    // l / 16 of the step: thread (am, aq) writes lane am % 16 + 16 aq of tile am / 16
+    const uint32_t amask = a_ok ? 0xFFFFFFFFu : 0u;
+    uint16_t* const a_dst = sR + ((am >> 4) * 64 + (am & 15) + 16 * aq) * 8;
+    auto normalize = [&](int kk, const float4(&x)[2], int buf) {
+        const int f = (kk < 64 ? kk : 63) >> 4;
+        const float2 lr = sLR[f][am];
+        const float l = lr.x, ri = lr.y;
+        uint4 w;
+        w.x = f2bf2((x[0].x - l) * ri, (x[0].y - l) * ri) & amask;
+        w.y = f2bf2((x[0].z - l) * ri, (x[0].w - l) * ri) & amask;
+        w.z = f2bf2((x[1].x - l) * ri, (x[1].y - l) * ri) & amask;
+        w.w = f2bf2((x[1].z - l) * ri, (x[1].w - l) * ri) & amask;
+        *reinterpret_cast<uint4*>(a_dst + buf * A_HALF) = w;
+    };
+    normalize(0, rw[0], 0);
+    __syncthreads();
+
+    f32x4 acc[TI][4];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // Pipeline over the 64 k-steps. All operands reach LDS by direct global->LDS
-    // loads, whose completion is tracked by hand with vmcnt (loads finish in issue
-    // order); every LDS access of the loop is inline asm that waits for its own
-    // results, so the compiler adds no waits of its own. Per step kk:
-    //   wait for this wave's W1 fragments of kk; read them into registers;
-    //   load the W1 fragments of kk + 2 into the stage just read (4 loads);
-    //   load the raw state rows of kk + RS into the raw stage converted last step (2);
-    //   MFMAs on the bfloat16 A tile of kk;
-    //   normalise the raw rows of kk + 1 into the other bfloat16 buffer;
-    //   wait for this wave's raw loads of kk + 2; barrier.
-    // Indices past the last step are clamped (harmless reloads), so the number of
-    // loads per step, and with it every wait count, stays fixed.
-    static_assert(RS == 4, "the wait counts assume four raw stages");
-#define WV_WAIT_VM_LGKM0(n) __builtin_amdgcn_s_waitcnt(((n)&15) | (((n) >> 4) << 14) | (7 << 4))
-#define WV_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(((n)&15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
-    // raw stage pieces: 1024 x 16 bytes, piece = 8 m + 2 row + half; wave w, load t owns 128 w + 64 t + lane
-#define WV_DMA_A(kk)                                                                                \
-    {                                                                                               \
-        const int k_ = (kk) < 64 ? (kk) : 63;                                                       \
-        const long long o_ = (k_ >> 4) * a.N + ((long long)((k_ & 15) >> 1) * a.ny + 4 * (k_ & 1)) * a.nx; \
-        float* d_ = sRaw[(kk) % RS] + wave * 512;                                                   \
-        __builtin_amdgcn_global_load_lds(a.state + (dbase[0] >= 0 ? o_ + dbase[0] : 0), d_, 16, 0, 0); \
-        __builtin_amdgcn_global_load_lds(a.state + (dbase[1] >= 0 ? o_ + dbase[1] : 0), d_ + 256, 16, 0, 0); \
-    }
-    // W1 fragment stage of wave w: [4 tiles j][64 lanes] x 16 bytes in the order the MFMA reads them
-    // (fragment-ordered W1: block (ks, r) of 64 x 8 values at ((ks * 32 + r) * 64) * 8)
-    const uint16_t* wsrc = a.w1p + ((long long)(wave * 4) * 64 + lane) * 8;
-#define WV_DMA_B(kk, st)                                                                            \
-    {                                                                                               \
-        const int k_ = (kk) < 64 ? (kk) : 63;                                                       \
-        uint16_t* d_ = sB + (st) * (HID * KB) + wave * (64 * KB);                                   \
-        _Pragma("unroll") for (int j_ = 0; j_ < 4; ++j_)                                            \
-            __builtin_amdgcn_global_load_lds(wsrc + (long long)k_ * (HID * KB) + j_ * 512, d_ + j_ * 512, 16, 0, 0); \
-    }
-    const uint32_t b_addr = lds_addr(sB + wave * (64 * KB) + lane * 8);
-    // A fragments of tile i: row 16 i + fr, k fq..fq+7 of a bfloat16 buffer
-    const uint32_t af_addr = lds_addr(&sA[0][fr][fq]);
-    // normalisation: thread (am, aq) converts row aq of patch am
-    const uint32_t raw_addr = lds_addr(&sRaw[0][am * KB + aq * 8]);
-    const uint32_t sa_addr = lds_addr(&sA[0][am][aq * 8]);
-    const float4 mlo = *reinterpret_cast<const float4*>(sMeta + am * 8);      // (lo0, ri0, lo1, ri1)
-    const float4 mhi = *reinterpret_cast<const float4*>(sMeta + am * 8 + 4);  // (lo2, ri2, lo3, ri3)
-    __builtin_amdgcn_sched_barrier(0);
-#define WV_CONVERT(kk, buf)                                                                         \
-    {                                                                                               \
-        const int k_ = (kk) < 64 ? (kk) : 63, f_ = k_ >> 4;                                         \
-        f32x4 x0, x1;                                                                               \
-        asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:16\n\ts_waitcnt lgkmcnt(0)"   \
-                     : "=&v"(x0), "=&v"(x1)                                                           \
-                     : "v"(raw_addr + (uint32_t)(k_ % RS) * (BM * KB * 4))                          \
-                     : "memory");                                                                   \
-        const float l_ = f_ == 0 ? mlo.x : f_ == 1 ? mlo.z : f_ == 2 ? mhi.x : mhi.z;              \
-        const float ri_ = f_ == 0 ? mlo.y : f_ == 1 ? mlo.w : f_ == 2 ? mhi.y : mhi.w;             \
-        u32x4 w_ = {0u, 0u, 0u, 0u};                                                                \
-        if (a_ok) {                                                                                 \
-            w_.x = f2bf2((x0.x - l_) * ri_, (x0.y - l_) * ri_);                                     \
-            w_.y = f2bf2((x0.z - l_) * ri_, (x0.w - l_) * ri_);                                     \
-            w_.z = f2bf2((x1.x - l_) * ri_, (x1.y - l_) * ri_);                                     \
-            w_.w = f2bf2((x1.z - l_) * ri_, (x1.w - l_) * ri_);                                     \
-        }                                                                                           \
-        asm volatile("ds_write_b128 %0, %1 offset:%2"                                               \
-                     :                                                                              \
-                     : "v"(sa_addr), "v"(w_), "i"((buf) * BM * (KB + APAD) * 2)                     \
-                     : "memory");                                                                   \
-    }
-
-    // prologue: the raw rows of steps 0 and 1, then as in steps -2 and -1 (W1 of 0
-    // and 1, raw rows of 2 and 3); normalise step 0.
-    WV_DMA_A(0);
-    WV_DMA_A(1);
-    WV_DMA_B(0, 0);
-    WV_DMA_A(2);
-    WV_DMA_B(1, 1);
-    WV_DMA_A(3);
-    __builtin_amdgcn_sched_barrier(0);
-    WV_WAIT_VM(14);  // raw rows of step 0 (14 loads issued after them)
-    __builtin_amdgcn_s_barrier();
-    WV_CONVERT(0, 0);
-    WV_WAIT_VM_LGKM0(12);  // raw rows of step 1
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    // One step, in issue order (sched_barrier pins it): a single LDS read block for
-    // the W1 fragments of kk, the raw rows of kk + 1 and A tiles 0-3; then the 32
-    // MFMAs in row tiles, with the direct loads, the reads of A tiles 4-7 and the
-    // normalisation of kk + 1 slotted between tiles so that they issue while the
-    // matrix pipe is busy.
-#define WV_TILE(t)                                                                                  \
-    _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                   \
-        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[t], bw[j], acc[t][j], 0, 0, 0);     \
-    __builtin_amdgcn_sched_barrier(0);
-    for (int k0 = 0; k0 < 64; k0 += 2) {
+    const uint16_t* const a_src = sR + lane * 8;
+    // step kk (q = kk mod the unroll period) refills the slots the previous steps freed (W1 of
+    // kk + WD - 1, raw rows of kk + RD), multiplies the A tile of kk, normalises the rows of
+    // kk + 1 into the other A buffer and ends with the one barrier that separates the
+    // buffers' writes and reads
+    auto step = [&](int kk, auto qc) {
+        constexpr int q = decltype(qc)::value;
+        load_w(kk + WD - 1, wb[(q + WD - 1) % WD]);
+        load_raw(kk + RD, rw[q % RD]);
+        const uint16_t* src = a_src + (kk & 1) * A_HALF;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int kk = k0 + u;
-            const int kn = kk + 1 < 64 ? kk + 1 : 63;  // the step normalised at the end of this one
-            WV_WAIT_VM(8);  // W1 fragments of kk: issued two steps ago, 8 loads since
-            u32x4 g0, g1, g2, g3, r0, r1, f0, f1, f2, f3;
-            asm volatile(
-                "ds_read_b128 %0, %10 offset:%13\n\tds_read_b128 %1, %10 offset:%14\n\t"
-                "ds_read_b128 %2, %10 offset:%15\n\tds_read_b128 %3, %10 offset:%16\n\t"
-                "ds_read_b128 %4, %11\n\tds_read_b128 %5, %11 offset:16\n\t"
-                "ds_read_b128 %6, %12 offset:%17\n\tds_read_b128 %7, %12 offset:%18\n\t"
-                "ds_read_b128 %8, %12 offset:%19\n\tds_read_b128 %9, %12 offset:%20\n\t"
-                "s_waitcnt lgkmcnt(0)"
-                : "=&v"(g0), "=&v"(g1), "=&v"(g2), "=&v"(g3), "=&v"(r0), "=&v"(r1), "=&v"(f0), "=&v"(f1), "=&v"(f2), "=&v"(f3)
-                : "v"(b_addr), "v"(raw_addr + (uint32_t)(kn % RS) * (BM * KB * 4)), "v"(af_addr),
-                  "i"(u * HID * KB * 2), "i"(u * HID * KB * 2 + 1024), "i"(u * HID * KB * 2 + 2048),
-                  "i"(u * HID * KB * 2 + 3072), "i"(u * BM * (KB + APAD) * 2),
-                  "i"(u * BM * (KB + APAD) * 2 + 16 * (KB + APAD) * 2),
-                  "i"(u * BM * (KB + APAD) * 2 + 32 * (KB + APAD) * 2),
-                  "i"(u * BM * (KB + APAD) * 2 + 48 * (KB + APAD) * 2)
-                : "memory");
-            const bf16x8 bw[4] = {__builtin_bit_cast(bf16x8, g0), __builtin_bit_cast(bf16x8, g1),
-                                  __builtin_bit_cast(bf16x8, g2), __builtin_bit_cast(bf16x8, g3)};
-            bf16x8 fa[8];
-            fa[0] = __builtin_bit_cast(bf16x8, f0);
-            fa[1] = __builtin_bit_cast(bf16x8, f1);
-            fa[2] = __builtin_bit_cast(bf16x8, f2);
-            fa[3] = __builtin_bit_cast(bf16x8, f3);
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(0);
-            WV_DMA_B(kk + 2, u);
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(1);
-            WV_DMA_A(kk + RS);
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(2);
+        for (int i = 0; i < TI; ++i) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(src + i * 512);
 #pragma unroll
-            for (int t = 4; t < 8; ++t) fa[t] = *reinterpret_cast<const bf16x8*>(&sA[u][t * 16 + fr][fq]);
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(3);
-            // normalise the raw rows of kn (held in r0, r1)
-            const int fn = kn >> 4;
-            const float l_ = fn == 0 ? mlo.x : fn == 1 ? mlo.z : fn == 2 ? mhi.x : mhi.z;
-            const float ri_ = fn == 0 ? mlo.y : fn == 1 ? mlo.w : fn == 2 ? mhi.y : mhi.w;
-            const f32x4 x0 = __builtin_bit_cast(f32x4, r0), x1 = __builtin_bit_cast(f32x4, r1);
-            u32x4 w_;
-            w_.x = a_ok ? f2bf2((x0.x - l_) * ri_, (x0.y - l_) * ri_) : 0u;
-            w_.y = a_ok ? f2bf2((x0.z - l_) * ri_, (x0.w - l_) * ri_) : 0u;
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(4);
-            w_.z = a_ok ? f2bf2((x1.x - l_) * ri_, (x1.y - l_) * ri_) : 0u;
-            w_.w = a_ok ? f2bf2((x1.z - l_) * ri_, (x1.w - l_) * ri_) : 0u;
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(5);
-            asm volatile("ds_write_b128 %0, %1 offset:%2"
-                         :
-                         : "v"(sa_addr), "v"(w_), "i"((u ^ 1) * BM * (KB + APAD) * 2)
-                         : "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            WV_TILE(6);
-            WV_TILE(7);
-            WV_WAIT_VM_LGKM0(12);  // raw rows of kk + 2: issued at step kk - 2, 12 loads since
-            __builtin_amdgcn_s_barrier();
-            __builtin_amdgcn_sched_barrier(0);
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, __builtin_bit_cast(bf16x8, wb[q % WD][j]),
+                                                                    acc[i][j], 0, 0, 0);
+        }
+        normalize(kk + 1, rw[(q + 1) % RD], (kk + 1) & 1);
+        __syncthreads();
+    };
+    // the loop is unrolled by the rings' common period U, so every slot index is a constant;
+    // the 64 % U steps left over run after it
+    using std::integral_constant;
+    constexpr int U = WD == RD ? WD : 6;
+    int k0 = 0;
+#define WV_ENC_STEP(q) step(k0 + (q), integral_constant<int, (q)>{})
+    for (; k0 + U <= 64; k0 += U) {
+        WV_ENC_STEP(0);
+        WV_ENC_STEP(1);
+        if constexpr (U >= 3) WV_ENC_STEP(2);
+        if constexpr (U == 6) {
+            WV_ENC_STEP(3);
+            WV_ENC_STEP(4);
+            WV_ENC_STEP(5);
         }
     }
-#undef WV_TILE
-    // no direct load may land in the ring once the hidden layer reuses its bytes
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-#undef WV_DMA_A
-#undef WV_DMA_B
-#undef WV_CONVERT
-#undef WV_WAIT_VM
-#undef WV_WAIT_VM_LGKM0
-    // hidden layer: bias + GELU -> bf16 in LDS (aliases the A buffers)
-    const int cr = (lane >> 4) * 4;
-    #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n = wave * 64 + j * 16 + fr;
-        const float bias = a.b1[n];
-        #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            #pragma unroll
-            for (int r = 0; r < 4; ++r) sH[i * 16 + cr + r][n] = f2bf(gelu(acc[i][j][r] + bias));
-    }
-    __syncthreads();
-    // second layer: Z[BM][L] = H W2^T; wave handles rows [16*wave, 16*wave+16), all L columns
-    constexpr int TJ = L / 16;
-    f32x4 z[TJ];
-    #pragma unroll
-    for (int j = 0; j < TJ; ++j) z[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (64 % U >= 1) WV_ENC_STEP(0);
+    if constexpr (64 % U >= 2) WV_ENC_STEP(1);
+    if constexpr (64 % U >= 3) WV_ENC_STEP(2);
+    if constexpr (64 % U >= 4) WV_ENC_STEP(3);
+#undef WV_ENC_STEP
+
+    // second layer, split over the waves' hidden units: H[:, 64 w .. 64 w + 63] W2[:, same]^T.
+    // The loop ended with a barrier, so the region is free: wave w stages one row tile of its
+    // GELU outputs at a time in its own [16][ENC_HLD] area (LDS accesses of one wave complete
+    // in issue order, so no barrier is needed between its writes and reads).
+    uint16_t* sHw = sR + wave * 16 * ENC_HLD;
+    float bias1[4];
 #pragma unroll
-    for (int kk = 0; kk < HID / KB; ++kk) {
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sH[wave * 16 + fr][kk * KB + fq]);
-        #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-            const bf16x8 bw = *reinterpret_cast<const bf16x8*>(a.w2t + (long long)(j * 16 + fr) * HID + kk * KB + fq);
-            z[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw, z[j], 0, 0, 0);
+    for (int j = 0; j < 4; ++j) bias1[j] = a.b1[wave * 64 + j * 16 + fr];
+    // W2 fragments: B lane l = latent 16 jj + l % 16, hidden 64 w + 32 ks + 8 (l / 16) .. + 7
+    bf16x8 w2f[2][2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+            w2f[ks][jj] = *reinterpret_cast<const bf16x8*>(a.w2t + (long long)(jj * 16 + fr) * HID + wave * 64 +
+                                                           ks * 32 + fq);
+    f32x4 zp[TI][2];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sHw[(cr + r) * ENC_HLD + j * 16 + fr] = f2bf(gelu(acc[i][j][r] + bias1[j]));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        zp[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        zp[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(sHw + fr * ENC_HLD + ks * 32 + fq);
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+                zp[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, w2f[ks][jj], zp[i][jj], 0, 0, 0);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    #pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-        const int n = j * 16 + fr;
-        const float bias = a.b2[n];
-        #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long long p = m0 + wave * 16 + cr + r;
-            if (p < a.P) {
-                const float v = z[j][r] + bias;
-                if (a.zbf) a.zbf[p * L + n] = f2bf(v);
-                if (a.zf) a.zf[p * L + n] = v;
-            }
+    // the partial blocks summed in wave order: ((z_0 + z_1) + z_2) + ... in a [BM][ENC_ZLD] area
+    float* sZ = reinterpret_cast<float*>(sR);
+    __syncthreads();  // every wave is done with its staging area
+    for (int w = 0; w < 8; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float* z = sZ + (i * 16 + cr + r) * ENC_ZLD + jj * 16 + fr;
+                        *z = w == 0 ? zp[i][jj][r] : *z + zp[i][jj][r];
+                    }
+        }
+        __syncthreads();
+    }
+    // bias, then the latents: thread t writes 8 values of patch t / 4
+    const int zr = tid >> 2, zc = (tid & 3) * 8;
+    const long long p = m0 + zr;
+    if (p < a.P) {
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = sZ[zr * ENC_ZLD + zc + c] + a.b2[zc + c];
+        if (a.zbf) {
+            uint16_t* o = a.zbf + p * L + zc;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) o[c] = f2bf(v[c]);
+        }
+        if (a.zf) {
+            float* o = a.zf + p * L + zc;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) o[c] = v[c];
         }
     }
 }
@@ -560,8 +532,6 @@ __global__ void pack_kernel(const uint16_t* __restrict__ w, int rows, int K, uin
     *reinterpret_cast<uint4*>(out + c * 8) = *reinterpret_cast<const uint4*>(w + row * K + k);
 }
 
-size_t enc_smem() { return (size_t)ENC_META_OFF + (size_t)BM * 8 * 4; }
-
 template <class K>
 void allow_smem(K kernel, size_t bytes)
 {
@@ -591,9 +561,7 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
     WV_REQUIRE(!meta16 || mm, WV_EINVAL, "16-bit metadata is written from the step's (min, max) partials");
     EncArgs a{state, meta, meta16, mm, H, beta, w1p, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx,
               pg.ny, pg.nx, pg.ny / 8, pg.nx / 8};
-    const size_t sm = enc_smem();
-    allow_smem(encode_kernel<32>, sm);
-    hipLaunchKernelGGL(encode_kernel<32>, dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), sm, st, a);
+    hipLaunchKernelGGL((encode_kernel<32, ENC_WD, ENC_RD>), dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), 0, st, a);
     WV_HIP(hipGetLastError());
 }
 
