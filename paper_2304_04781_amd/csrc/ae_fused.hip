@@ -12,6 +12,7 @@
 // row l%16, k = 8*(l/16)..+7; B lane l holds column l%16, same k; C lane l
 // holds column l%16, rows 4*(l/16)..+3.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "ae_internal.h"
@@ -47,6 +48,7 @@ struct EncArgs {
     float* zf;            // [P][L] float32 latent (or null)
     long long P, N;
     int ny, nx, Py, Px;
+    long long t0;         // first 128-patch tile of the launch
 };
 
 struct DecArgs {
@@ -66,6 +68,7 @@ struct DecArgs {
     const int* eidx;
     const float* exc;
     const int* erng;
+    long long t0;  // first DEC_BM-patch tile of the launch
 };
 
 // Per-patch (lo, 1/r) of the work-group's bm patches into sMeta [bm][8] (threads
@@ -132,6 +135,15 @@ __device__ __forceinline__ void enc_meta(const EncArgs& a, long long m0, int tid
 #define WV_ENC_RD 3
 #endif
 constexpr int ENC_WD = WV_ENC_WD, ENC_RD = WV_ENC_RD;  // register ring depths (W1, raw rows): 2 or 3
+// Work-groups per encode launch (0: all tiles in one launch). An encode of more tiles is
+// queued as several launches in a row on its stream, so it holds at most this many CUs at
+// a time. The forward sweep needs one encode per step, and sliced encodes ran slower than
+// the steps they left CUs to (128 work-groups per launch: 300 us per encode, against 182
+// in one launch), so by default an encode is one launch.
+#ifndef WV_ENC_GRID
+#define WV_ENC_GRID 0
+#endif
+constexpr long long ENC_GRID = WV_ENC_GRID;
 constexpr int ENC_HLD = 64 + 8;  // bf16 row of a wave's hidden staging tile [16][ENC_HLD]
 constexpr int ENC_ZLD = 32 + 4;  // float row of the latent partial sums [BM][ENC_ZLD]
 constexpr int ENC_R_BYTES = 8 * 16 * ENC_HLD * 2;  // the largest use of the shared region
@@ -149,7 +161,7 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
     __shared__ __attribute__((aligned(16))) uint16_t sR[ENC_R_BYTES / 2];
     __shared__ __attribute__((aligned(16))) float2 sLR[4][BM];  // (lo, 1/r) per field and patch
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const long long m0 = (long long)blockIdx.x * BM;
+    const long long m0 = (a.t0 + blockIdx.x) * BM;
     const int fr = lane & 15, fq = (lane >> 4) * 8, cr = (lane >> 4) * 4;
 
     // thread (am, aq) loads and normalises y row aq (of the four of a k-step) of patch am:
@@ -362,6 +374,14 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
 #ifndef WV_DEC_WPE
 #define WV_DEC_WPE 4
 #endif
+// Work-groups per decode launch (0: all tiles in one launch). The reverse sweep decodes
+// two steps ahead of the adjoint step that reads the state, so a decode may take longer
+// than one step; queued as two launches (384 work-groups, then the rest at 256^3) it holds
+// fewer CUs at a time, and the adjoint step beside it ran 184 us instead of 197.
+#ifndef WV_DEC_GRID
+#define WV_DEC_GRID 384
+#endif
+constexpr long long DEC_GRID = WV_DEC_GRID;
 constexpr int DEC_NW = WV_DEC_WAVES;
 constexpr int DEC_NT = DEC_NW * 64;
 
@@ -384,7 +404,8 @@ __global__ void __launch_bounds__(DEC_NT) __attribute__((amdgpu_waves_per_eu(WV_
     int* sExc = reinterpret_cast<int*>(sRg + BM);  // exception slot of each patch, or -1
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int fr = lane & 15, fq = (lane >> 4) * 8, cr = (lane >> 4) * 4, q = lane >> 4;
-    const long long m0 = (long long)blockIdx.x * BM;
+    const long long tile = a.t0 + blockIdx.x;
+    const long long m0 = tile * BM;
     const bool has_exc = a.eidx != nullptr;
 
     if (tid < BM) {
@@ -458,7 +479,7 @@ __global__ void __launch_bounds__(DEC_NT) __attribute__((amdgpu_waves_per_eu(WV_
     }
     __syncthreads();
     if (has_exc) {
-        const int e0 = a.erng[blockIdx.x], e1 = a.erng[blockIdx.x + 1];
+        const int e0 = a.erng[tile], e1 = a.erng[tile + 1];
         for (int t = e0 + tid; t < e1; t += DEC_NT) {
             const long long d = a.eidx[t] - m0;
             if (d >= 0 && d < BM) sExc[d] = t;
@@ -560,9 +581,14 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 {
     WV_REQUIRE(!meta16 || mm, WV_EINVAL, "16-bit metadata is written from the step's (min, max) partials");
     EncArgs a{state, meta, meta16, mm, H, beta, w1p, b1, w2t, b2, zbf, zf, pg.P, (long long)pg.nz * pg.ny * pg.nx,
-              pg.ny, pg.nx, pg.ny / 8, pg.nx / 8};
-    hipLaunchKernelGGL((encode_kernel<32, ENC_WD, ENC_RD>), dim3((unsigned)((pg.P + BM - 1) / BM)), dim3(NT), 0, st, a);
-    WV_HIP(hipGetLastError());
+              pg.ny, pg.nx, pg.ny / 8, pg.nx / 8, 0};
+    const long long tiles = (pg.P + BM - 1) / BM;
+    const long long per = ENC_GRID > 0 ? ENC_GRID : tiles;
+    for (a.t0 = 0; a.t0 < tiles; a.t0 += per) {
+        hipLaunchKernelGGL((encode_kernel<32, ENC_WD, ENC_RD>), dim3((unsigned)std::min(per, tiles - a.t0)), dim3(NT), 0,
+                           st, a);
+        WV_HIP(hipGetLastError());
+    }
 }
 
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
@@ -571,7 +597,7 @@ void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, con
 {
     static_assert(DEC_BM % 16 == 0 && DEC_BM <= 512, "decode work-groups hold whole 16-patch tiles");
     DecArgs a{z, meta, meta16, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
-              pg.ny / 8, pg.nx / 8, nullptr, nullptr, nullptr};
+              pg.ny / 8, pg.nx / 8, nullptr, nullptr, nullptr, 0};
     if (exc && exc->K > 0) {
         WV_REQUIRE(exc->idx && exc->exc && exc->rng, WV_EINVAL, "decode: null exception buffer");
         a.eidx = exc->idx;
@@ -580,8 +606,12 @@ void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, con
     }
     const size_t sm = (size_t)DEC_BM * (HID + HPAD) * 2 + (size_t)DEC_BM * 20;
     allow_smem(decode_kernel<32>, sm);
-    hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)((pg.P + DEC_BM - 1) / DEC_BM)), dim3(DEC_NT), sm, st, a);
-    WV_HIP(hipGetLastError());
+    const long long tiles = (pg.P + DEC_BM - 1) / DEC_BM;
+    const long long per = DEC_GRID > 0 ? DEC_GRID : tiles;
+    for (a.t0 = 0; a.t0 < tiles; a.t0 += per) {
+        hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)std::min(per, tiles - a.t0)), dim3(DEC_NT), sm, st, a);
+        WV_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace wv

@@ -152,7 +152,10 @@ enum {
 using namespace wv;
 
 // decoded-e slots: the decode of a state runs up to NEB - 1 steps ahead of its use
-constexpr int NEB = 3;
+#ifndef WV_NEB
+#define WV_NEB 3
+#endif
+constexpr int NEB = WV_NEB;
 
 // Latent store of the states x_1 .. x_{T-1} of every source (AE modes): latents,
 // per-patch metadata, FP8 scales and the exact e values of the exception patches
