@@ -1332,7 +1332,7 @@ void ae_time_decode(const ae_net* a, const TimeGrid& tg, const uint16_t* latent,
 
 void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t mask, float* state, hipStream_t st,
-                     const ExcPatches* exc, const uint16_t* meta16)
+                     const ExcPatches* exc, const uint16_t* meta16, long long grid)
 {
     WV_REQUIRE(a && state && latent && (meta || meta16) && (fmt == AE_LATENT_BF16 || qscale), WV_EINVAL,
                "decode: null buffer");
@@ -1351,7 +1351,7 @@ void ae_decode_state(const ae_net* a, const PatchGrid& pg, const void* latent, c
         for (int f = 0; f < 4; ++f)
             if (mask & (1u << f))
                 fused_decode(pg, zb, meta, a->wt[2], a->bias(2), a->wp4, a->bias(3), f, state, st,
-                             (exc && exc->K > 0 && f == 0) ? exc : nullptr, meta16);
+                             (exc && exc->K > 0 && f == 0) ? exc : nullptr, meta16, grid);
         return;
     }
     const size_t oh = 0, ozb = align256(oh + P * (size_t)a->hid * 2);

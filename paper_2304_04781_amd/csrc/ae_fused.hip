@@ -374,14 +374,6 @@ __global__ void __launch_bounds__(NT) encode_kernel(const EncArgs a)
 #ifndef WV_DEC_WPE
 #define WV_DEC_WPE 4
 #endif
-// Work-groups per decode launch (0: all tiles in one launch). The reverse sweep decodes
-// two steps ahead of the adjoint step that reads the state, so a decode may take longer
-// than one step; queued as two launches (384 work-groups, then the rest at 256^3) it holds
-// fewer CUs at a time, and the adjoint step beside it ran 184 us instead of 197.
-#ifndef WV_DEC_GRID
-#define WV_DEC_GRID 384
-#endif
-constexpr long long DEC_GRID = WV_DEC_GRID;
 constexpr int DEC_NW = WV_DEC_WAVES;
 constexpr int DEC_NT = DEC_NW * 64;
 
@@ -593,7 +585,7 @@ void fused_encode(const PatchGrid& pg, const float* state, float* meta, const fl
 
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st, const ExcPatches* exc,
-                  const uint16_t* meta16)
+                  const uint16_t* meta16, long long grid)
 {
     static_assert(DEC_BM % 16 == 0 && DEC_BM <= 512, "decode work-groups hold whole 16-patch tiles");
     DecArgs a{z, meta, meta16, w3t, b3, w4p, b4, state, f, pg.P, (long long)pg.nz * pg.ny * pg.nx, pg.ny, pg.nx,
@@ -607,7 +599,7 @@ void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, con
     const size_t sm = (size_t)DEC_BM * (HID + HPAD) * 2 + (size_t)DEC_BM * 20;
     allow_smem(decode_kernel<32>, sm);
     const long long tiles = (pg.P + DEC_BM - 1) / DEC_BM;
-    const long long per = DEC_GRID > 0 ? DEC_GRID : tiles;
+    const long long per = grid > 0 ? grid : tiles;
     for (a.t0 = 0; a.t0 < tiles; a.t0 += per) {
         hipLaunchKernelGGL(decode_kernel<32>, dim3((unsigned)std::min(per, tiles - a.t0)), dim3(DEC_NT), sm, st, a);
         WV_HIP(hipGetLastError());

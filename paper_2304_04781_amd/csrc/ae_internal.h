@@ -81,7 +81,7 @@ constexpr int DEC_BM = WV_DEC_BM;  // patches per decode work-group
 // meta16 (optional): bfloat16 (lo, r) read instead of meta.
 void ae_decode_state(const ae_net* net, const PatchGrid& pg, const void* latent, const float* meta,
                      const float* qscale, int fmt, uint32_t field_mask, float* state, hipStream_t st,
-                     const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr);
+                     const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr, long long grid = 0);
 
 // Fused inference kernels (hidden width 512, latent 32): meta must already hold
 // the per-patch (min, range) of the state for encode.
@@ -96,10 +96,12 @@ void fused_pack(const uint16_t* w, int rows, int K, uint16_t* out, hipStream_t s
 void fused_encode(const PatchGrid& pg, const float* state, float* meta, const float* mm, int H, const float* beta,
                   const uint16_t* w1p, const float* b1, const uint16_t* w2t, const float* b2, uint16_t* zbf, float* zf,
                   hipStream_t st, uint16_t* meta16 = nullptr);
-// exc (field 0 only): exception patches written with their exact values
+// exc (field 0 only): exception patches written with their exact values.
+// grid > 0: the decode is queued as launches of at most grid work-groups, one after the
+// other on st, so it holds fewer CUs at a time (0: one launch).
 void fused_decode(const PatchGrid& pg, const uint16_t* z, const float* meta, const uint16_t* w3t, const float* b3,
                   const uint16_t* w4p, const float* b4, int f, float* state, hipStream_t st,
-                  const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr);
+                  const ExcPatches* exc = nullptr, const uint16_t* meta16 = nullptr, long long grid = 0);
 
 // Exception patches: the K largest-e-range patches of one compressed state are
 // kept exactly. Ranges are compared by key = bits(r_e) >> EXC_BIN_SHIFT (bins 2^-5

@@ -156,6 +156,16 @@ using namespace wv;
 #define WV_NEB 3
 #endif
 constexpr int NEB = WV_NEB;
+// Work-groups per decode launch in the reverse sweep of a gradient (0: one launch). A
+// decode there runs two steps ahead of the adjoint step that reads it, so it may take
+// longer than a step; queued as two launches (384 work-groups, then the rest at 256^3) it
+// holds fewer CUs at a time, and the adjoint step beside it ran 184 us instead of 197.
+// The incremental forward sweep of a Hessian action keeps one launch (its decodes run
+// beside the encodes of the incremental states, and sliced they ran slower).
+#ifndef WV_REV_DEC_GRID
+#define WV_REV_DEC_GRID 384
+#endif
+constexpr long long REV_DEC_GRID = WV_REV_DEC_GRID;
 
 // Latent store of the states x_1 .. x_{T-1} of every source (AE modes): latents,
 // per-patch metadata, FP8 scales and the exact e values of the exception patches
@@ -252,6 +262,7 @@ struct wv_ctx {
     bool m16 = false;            // the AE stores keep bfloat16 (lo, r)
     int K = 0;                   // active exception patches per state
     int nbd = 0;                 // decode work-groups per state
+    long long pipe_grid = 0;     // work-groups per decode launch of the running decode pipeline (0: one launch)
     float* mmpart = nullptr;     // [3][S][P][H][4][2] (min, max) partials of the forward step
     int H = 1;                   // y sub-tiles per patch
     // Autoencoder stores and decodes run beside the stencil steps: `side` encodes
@@ -830,9 +841,10 @@ void ensure_adj(wv_ctx* c)
 float* ebuf_slot(wv_ctx* c, int b) { return c->ebuf + (long long)b * c->S * c->N; }
 
 // decode the fields in mask of stored state n of every source from the AE store L
-// into out (per-source stride `stride` floats; field f at + f N) on stream st
+// into out (per-source stride `stride` floats; field f at + f N) on stream st, in
+// launches of at most grid work-groups (0: one launch per field)
 void decode_state(wv_ctx* c, const LatStore& L, int n, uint32_t mask, float* out, long long stride,
-                  hipStream_t st)
+                  hipStream_t st, long long grid = 0)
 {
     WV_REQUIRE(n >= 1 && n <= c->T - 1, WV_ESTATE, "stored state index out of range");
     const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
@@ -844,13 +856,16 @@ void decode_state(wv_ctx* c, const LatStore& L, int n, uint32_t mask, float* out
         const int td = c->tm.begin(TM_DECODE, st);
         ae_decode_state(c->ae, pg, lat_slot(c, L, n - 1, s), meta_slot(c, L, n - 1, s), qs_slot(c, L, n - 1, s),
                         ae_fmt(c->mode), mask, out + s * stride, st, c->K > 0 ? &ex : nullptr,
-                        meta16_slot(c, L, n - 1, s));
+                        meta16_slot(c, L, n - 1, s), grid);
         c->tm.end(td, st);
     }
 }
 
 // decode e^n of every source from the forward AE store into ebuf slot b on stream st
-void decode_e(wv_ctx* c, int n, int b, hipStream_t st) { decode_state(c, c->fs, n, 1u, ebuf_slot(c, b), c->N, st); }
+void decode_e(wv_ctx* c, int n, int b, hipStream_t st, long long grid = 0)
+{
+    decode_state(c, c->fs, n, 1u, ebuf_slot(c, b), c->N, st, grid);
+}
 
 // e^n of every source from the FULL or AE store (decoded on the main stream into
 // ebuf slot 0): pointer + per-source stride
@@ -906,19 +921,21 @@ const float* load_e(wv_ctx* c, int n, long long* stride, int dir = -1)
 
 // Decode pipeline of the sweeps that read the AE store (adjoint, incremental
 // forward): e^n is decoded on `side` into slot n % NEB up to NEB - 1 steps before
-// the main stream's step reads it. pipe_start marks all slots free; pipe_issue
+// the main stream's step reads it, in launches of at most `grid` work-groups (pipe_start;
+// 0: one launch). pipe_start marks all slots free; pipe_issue
 // queues the decode of e^n once the slot's last reader is done; pipe_take makes
 // the main stream wait for it; pipe_release marks the slot read.
-void pipe_start(wv_ctx* c)
+void pipe_start(wv_ctx* c, long long grid = 0)
 {
     ensure_adj(c);
+    c->pipe_grid = grid;
     for (int b = 0; b < NEB; ++b) WV_HIP(hipEventRecord(c->ev_free[b], c->st));
 }
 void pipe_issue(wv_ctx* c, int n, int b)
 {
     hipStream_t s1 = side_stream(c, 0);
     wait_event(s1, c->ev_free[b]);
-    decode_e(c, n, b, s1);
+    decode_e(c, n, b, s1, c->pipe_grid);
     WV_HIP(hipEventRecord(c->ev_ready[b], s1));
 }
 const float* pipe_take(wv_ctx* c, int b)
@@ -1070,8 +1087,9 @@ void reverse_sweep(wv_ctx* c, const float* resid, const std::vector<RevAction>* 
         std::swap(ain, aout);
     };
     if (!acts && is_ae(c->mode)) {
-        // e^{k-2} is decoded beside the adjoint steps k and k - 1
-        pipe_start(c);
+        // e^{k-2} is decoded beside the adjoint steps k and k - 1, in launches of at most
+        // REV_DEC_GRID work-groups
+        pipe_start(c, REV_DEC_GRID);
         for (int n = c->T - 1; n >= std::max(1, c->T - NEB + 1); --n) pipe_issue(c, n, n % NEB);
         for (int k = c->T - 1; k >= 1; --k) {
             if (k - NEB + 1 >= 1) pipe_issue(c, k - NEB + 1, (k - NEB + 1) % NEB);
