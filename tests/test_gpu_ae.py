@@ -99,12 +99,18 @@ def test_normalize_bitwise():
     assert np.all(y.cpu().numpy().view(np.uint16)[0, :512] == 0)
 
 
-@pytest.mark.parametrize("fmt", [L.LATENT_BF16, L.LATENT_FP8])
-def test_encode_decode_against_oracle(fmt):
+# 5 x 6 x 7 = 210 patches: one full 128-patch encode work-group and a partial one, three full
+# 64-patch decode work-groups and a partial one
+SHAPE_TILES = (40, 48, 56)
+
+
+@pytest.mark.parametrize("fmt,shape", [(L.LATENT_BF16, SHAPE), (L.LATENT_FP8, SHAPE), (L.LATENT_BF16, SHAPE_TILES)])
+def test_encode_decode_against_oracle(fmt, shape):
     prm = W.ae_init(seed=4)
     net = Net(prm)
+    SHAPE = shape
     st, ts = state_tensor(SHAPE, 2)
-    P = 30
+    P = (SHAPE[0] // 8) * (SHAPE[1] // 8) * (SHAPE[2] // 8)
     lat = torch.empty((P, 32), dtype=torch.int16 if fmt == L.LATENT_BF16 else torch.uint8, device="cuda")
     meta = torch.empty((P, 4, 2), dtype=torch.float32, device="cuda")
     qs = torch.empty((P,), dtype=torch.float32, device="cuda") if fmt == L.LATENT_FP8 else None
@@ -156,7 +162,11 @@ def test_encode_decode_against_oracle(fmt):
                            *SHAPE)
     derr = rel(out.cpu().numpy(), x_ref)
     print(f"decode fmt {fmt}: rel err {derr:.3e}", flush=True)
-    assert derr < 1e-6
+    # a hidden unit whose pre-activation sits within summation-order error of a bfloat16
+    # rounding tie comes out one step apart on the two sides, and moves that patch's outputs
+    # by one step of that unit times its W4 column: measured 1.7e-7 over 30 patches and
+    # 5.2e-6 over 210; a wrong index or tile would be off by order one
+    assert derr < 2e-5
     # e-only decode writes the e field and leaves the others untouched
     out2 = torch.full((4,) + SHAPE, 7.0, dtype=torch.float32, device="cuda")
     L.ae_decode(net.handle, grid_of(SHAPE), lat_in, torch.tensor(ms, device="cuda"), qs_in, fmt, 0x1, out2)
