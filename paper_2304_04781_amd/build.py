@@ -30,8 +30,11 @@ def hipcc() -> str:
 
 
 def common_flags():
+    # MFMA accumulators in ordinary VGPRs: with accumulation registers the allocator copies a
+    # GEMM's accumulators through a[0:3] around every MFMA of the k loop
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I", INCLUDE, "-I", CSRC, "-Wno-unused-result"]
 
 

@@ -645,15 +645,18 @@ struct EpiTimeDenorm {  // decoder output of a time vector -> lo + r (v + b) int
 // Work-group tile (rows, columns) that gemm_auto launches for an M x N product:
 // 128 x 128 when that gives at least two work-groups per CU, else 64 x 64 (training
 // batches of a few thousand rows); 128 x 32 for products 32 columns wide.
+#ifndef WV_GEMM_BIG_MIN_WG
+#define WV_GEMM_BIG_MIN_WG 512
+#endif
 inline int gemm_auto_bm(int M, int N, int splits = 1)
 {
     const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
-    return N <= 32 ? 128 : (wg128 < 512 ? 64 : 128);
+    return N <= 32 ? 128 : (wg128 < WV_GEMM_BIG_MIN_WG ? 64 : 128);
 }
 inline int gemm_auto_bn(int M, int N, int splits = 1)
 {
     const long long wg128 = (long long)((M + 127) / 128) * ((N + 127) / 128) * splits;
-    return N <= 32 ? 32 : (wg128 < 512 ? 64 : 128);
+    return N <= 32 ? 32 : (wg128 < WV_GEMM_BIG_MIN_WG ? 64 : 128);
 }
 
 template <class LA, class LB, class EPI>
