@@ -1,0 +1,83 @@
+"""Degenerate horizons: solves of T = 2, 3 and 6 steps, whose stores hold one to five
+states, fewer than the decode pipeline's slots, the checkpoint slots and one time window.
+The full-storage gradient against the FP64 oracle; checkpointing with one slot and with
+more slots than states, and the space and time stores with every patch or vector kept
+exact, against full storage bit for bit (gradient and Gauss-Newton Hv)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import revolve as orv
+from oracle import wave as ow
+from paper_2304_04781_amd import _lib as L
+from paper_2304_04781_amd.compressor import Autoencoder
+from paper_2304_04781_amd.solver import WaveSolver
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (32, 32, 40)
+P = (SHAPE[0] // 8) * (SHAPE[1] // 8) * (SHAPE[2] // 8)   # space patches
+B = (SHAPE[0] // 4) * (SHAPE[1] // 4) * (SHAPE[2] // 4)   # time vectors per level
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def short_problem(nt):
+    """The small 3D box with a seeded random wavelet (nonzero from the first step) and
+    receivers next to the source besides the surface grid, so a few steps already give a
+    nonzero misfit gradient."""
+    p = W.problem_3d(*SHAPE, nt, f0=15.0, sponge=8, name=f"short{nt}")
+    rng = np.random.default_rng(11 + nt)
+    p.wavelet = rng.standard_normal((1, nt)) / p.dx ** 3
+    k, j, i = (int(x) for x in p.src[0])
+    near = np.array([[k, j, i + 1], [k - 1, j, i], [k + 1, j + 1, i], [k, j - 2, i - 1]], dtype=np.int32)
+    p.rec = np.concatenate([np.asarray(p.rec, np.int32), near])
+    p.noise = rng.standard_normal((1, nt, len(p.rec)))
+    for name in ("c_true", "c_start", "wavelet"):
+        setattr(p, name, np.asarray(getattr(p, name), np.float32).astype(np.float64))
+    return p
+
+
+@pytest.mark.parametrize("nt", [2, 3, 6])
+def test_short_horizons(nt):
+    p = short_problem(nt)
+    print("case nt", nt, flush=True)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    J_o, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
+    assert np.linalg.norm(g_o) > 0
+
+    full = WaveSolver.for_problem(p)
+    full.set_storage(L.STORE_FULL)
+    J0, g0 = full.gradient(p.c_start, p.wavelet, d, sigma)
+    assert abs(J0 - J_o) / J_o < 1e-5
+    assert rel(g0.cpu().numpy(), g_o) < 1e-4
+    dc = p.c_start * 0.01 * W.direction_grf(p.c_start.shape, 4.0, 3)
+    H0 = full.hessvec(p.c_start, dc)
+    assert torch.count_nonzero(H0) > 0
+
+    for slots in (1, 8):
+        ck = WaveSolver.for_problem(p)
+        ck.set_storage(L.STORE_CHECKPOINT, n_checkpoints=slots)
+        J, g = ck.gradient(p.c_start, p.wavelet, d, sigma)
+        assert J == J0 and torch.equal(g, g0), slots
+        steps, _, _ = ck.stats()
+        assert steps == orv.closed_form(nt, slots) + 1, (slots, steps)
+        assert torch.equal(ck.hessvec(p.c_start, dc), H0), slots
+        ck.close()
+
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    for mode, k in ((L.STORE_AE_BF16, P), (L.STORE_AE_FP8, P), (L.STORE_AE_TIME, B)):
+        s = WaveSolver.for_problem(p)
+        L.wv_set_ae_exceptions(s.ctx, k)
+        s.set_storage(mode, ae=net)
+        J, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+        assert J == J0 and torch.equal(g, g0), mode
+        assert torch.equal(s.hessvec(p.c_start, dc), H0), mode
+        s.close()
+    full.close()
