@@ -1325,6 +1325,73 @@ int wv_destroy(wv_ctx* c)
     return WV_OK;
 }
 
+namespace {
+// the allocations and checks of one storage mode on a context whose store is free
+void set_storage_mode(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64_t mem_budget_bytes,
+                      int fallback_policy, double guard_tol)
+{
+    c->mode = mode;
+    c->budget = mem_budget_bytes;
+    c->guard_tol = guard_tol;
+    c->fallback = fallback_policy;
+    c->ae = ae;
+    c->nslots = n_checkpoints;
+    c->degraded = false;
+    c->have_grad = false;
+    const int T = c->T;
+    if (mode == WV_STORE_FULL) {
+        const long long n = (long long)std::max(T - 1, 1) * c->S * c->N;
+        WV_REQUIRE(c->budget <= 0 || n * 4 <= c->budget, WV_ENOMEM, "full history exceeds the memory budget");
+        c->ehist = dev_alloc<float>(n);
+        c->store_bytes = n * 4;
+    } else if (mode == WV_STORE_CHECKPOINT) {
+        alloc_slots(c, n_checkpoints);
+        c->store_bytes = (int64_t)(n_checkpoints - 1) * c->state_floats() * 4;
+    } else if (is_time(mode)) {
+        WV_REQUIRE(ae, WV_EINVAL, "time compression needs an ae_net");
+        WV_REQUIRE(ae_input_dim(ae) == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
+        WV_REQUIRE(c->has_y && c->g.nz % 4 == 0 && c->g.ny % 4 == 0 && c->g.nx % 4 == 0, WV_ESHAPE,
+                   "time compression needs a 3D grid divisible into 4^3 blocks");
+        WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE && guard_tol <= 0.0, WV_EINVAL,
+                   "the accuracy guard and its fallback apply to the space modes");
+        c->TB = ctx_time_grid(c).B;
+        c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
+        c->tlat_dim = ae_latent_dim(ae);
+        const int K = (int)std::min<long long>(c->exc_req, c->TB);
+        const long long bytes = timestore_bytes(c, K);
+        WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
+        alloc_timestore(c, c->ts, K);
+        c->store_bytes = bytes;
+    } else if (is_ae(mode)) {
+        WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
+        WV_REQUIRE(c->has_y && c->g.nz % 8 == 0 && c->g.ny % 8 == 0 && c->g.nx % 8 == 0, WV_ESHAPE,
+                   "autoencoder storage needs a 3D grid divisible into 8^3 patches");
+        const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
+        c->P = pg.P;
+        c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
+        c->m16 = c->meta_req == 16;
+        WV_REQUIRE(!c->m16 || (ae_input_dim(ae) == 2048 && ae_latent_dim(ae) == 32), WV_EINVAL,
+                   "16-bit metadata needs the fused network shape (hidden 512, latent 32)");
+        const int K = (int)std::min<long long>(c->exc_req, c->P);
+        c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
+        const long long bytes = latstore_bytes(c, mode, K);
+        WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
+        alloc_latstore(c, c->fs, mode, K);
+        c->K = K;
+        c->H = 8 / c->tl.by;
+        c->mmpart = dev_alloc<float>((size_t)3 * c->S * c->P * c->H * 8);
+        if (guard_tol > 0.0) {
+            c->gbuf = dev_alloc<float>((size_t)c->S * c->N);
+            c->gpart = dev_alloc<double>(3 * (size_t)c->nblk_red);
+            c->gres = dev_alloc<double>(2 * (size_t)(GUARD_CHECKS + 1) * c->S);
+        }
+        c->store_bytes = bytes;
+        if (fallback_policy == WV_FALLBACK_CHECKPOINT)
+            WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
+    }
+}
+}  // namespace
+
 int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64_t mem_budget_bytes,
                    double guard_tol, int fallback_policy)
 {
@@ -1336,64 +1403,15 @@ int wv_set_storage(wv_ctx* c, int mode, int32_t n_checkpoints, ae_net* ae, int64
         WV_HIP(hipStreamSynchronize(c->st));
         free_store(c);
         dev_free(c->slots);
-        c->mode = mode;
-        c->budget = mem_budget_bytes;
-        c->guard_tol = guard_tol;
-        c->fallback = fallback_policy;
-        c->ae = ae;
-        c->nslots = n_checkpoints;
-        c->degraded = false;
-        c->have_grad = false;
-        const int T = c->T;
-        if (mode == WV_STORE_FULL) {
-            const long long n = (long long)std::max(T - 1, 1) * c->S * c->N;
-            WV_REQUIRE(c->budget <= 0 || n * 4 <= c->budget, WV_ENOMEM, "full history exceeds the memory budget");
-            c->ehist = dev_alloc<float>(n);
-            c->store_bytes = n * 4;
-        } else if (mode == WV_STORE_CHECKPOINT) {
-            alloc_slots(c, n_checkpoints);
-            c->store_bytes = (int64_t)(n_checkpoints - 1) * c->state_floats() * 4;
-        } else if (is_time(mode)) {
-            WV_REQUIRE(ae, WV_EINVAL, "time compression needs an ae_net");
-            WV_REQUIRE(ae_input_dim(ae) == TWIN * 64, WV_EINVAL, "time compression needs an input width of 2048");
-            WV_REQUIRE(c->has_y && c->g.nz % 4 == 0 && c->g.ny % 4 == 0 && c->g.nx % 4 == 0, WV_ESHAPE,
-                       "time compression needs a 3D grid divisible into 4^3 blocks");
-            WV_REQUIRE(fallback_policy == WV_FALLBACK_NONE && guard_tol <= 0.0, WV_EINVAL,
-                       "the accuracy guard and its fallback apply to the space modes");
-            c->TB = ctx_time_grid(c).B;
-            c->nwin = (std::max(T - 1, 1) + TWIN - 1) / TWIN;
-            c->tlat_dim = ae_latent_dim(ae);
-            const int K = (int)std::min<long long>(c->exc_req, c->TB);
-            const long long bytes = timestore_bytes(c, K);
-            WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
-            alloc_timestore(c, c->ts, K);
-            c->store_bytes = bytes;
-        } else if (is_ae(mode)) {
-            WV_REQUIRE(ae, WV_EINVAL, "autoencoder storage needs an ae_net");
-            WV_REQUIRE(c->has_y && c->g.nz % 8 == 0 && c->g.ny % 8 == 0 && c->g.nx % 8 == 0, WV_ESHAPE,
-                       "autoencoder storage needs a 3D grid divisible into 8^3 patches");
-            const PatchGrid pg = patch_grid(c->g.nz, c->g.ny, c->g.nx);
-            c->P = pg.P;
-            c->lat_bytes = ae_latent_bytes_per_patch(ae, ae_fmt(mode));
-            c->m16 = c->meta_req == 16;
-            WV_REQUIRE(!c->m16 || (ae_input_dim(ae) == 2048 && ae_latent_dim(ae) == 32), WV_EINVAL,
-                       "16-bit metadata needs the fused network shape (hidden 512, latent 32)");
-            const int K = (int)std::min<long long>(c->exc_req, c->P);
-            c->nbd = (int)((c->P + DEC_BM - 1) / DEC_BM);
-            const long long bytes = latstore_bytes(c, mode, K);
-            WV_REQUIRE(c->budget <= 0 || bytes <= c->budget, WV_ENOMEM, "latent store exceeds the memory budget");
-            alloc_latstore(c, c->fs, mode, K);
-            c->K = K;
-            c->H = 8 / c->tl.by;
-            c->mmpart = dev_alloc<float>((size_t)3 * c->S * c->P * c->H * 8);
-            if (guard_tol > 0.0) {
-                c->gbuf = dev_alloc<float>((size_t)c->S * c->N);
-                c->gpart = dev_alloc<double>(3 * (size_t)c->nblk_red);
-                c->gres = dev_alloc<double>(2 * (size_t)(GUARD_CHECKS + 1) * c->S);
-            }
-            c->store_bytes = bytes;
-            if (fallback_policy == WV_FALLBACK_CHECKPOINT)
-                WV_REQUIRE(n_checkpoints >= 1, WV_EINVAL, "fallback needs n_checkpoints >= 1");
+        try {
+            set_storage_mode(c, mode, n_checkpoints, ae, mem_budget_bytes, fallback_policy, guard_tol);
+        } catch (...) {
+            // a rejected mode leaves no partial store behind: the context stores nothing, so
+            // the solves that need a history fail with WV_ESTATE until a mode is set
+            free_store(c);
+            c->mode = WV_STORE_NONE;
+            c->ae = nullptr;
+            throw;
         }
         return WV_OK;
     });

@@ -81,3 +81,55 @@ def test_short_horizons(nt):
         assert torch.equal(s.hessvec(p.c_start, dc), H0), mode
         s.close()
     full.close()
+
+
+def test_compressed_stores_reject_grids_that_do_not_tile():
+    """The space store needs 8^3 patches, the time store 4^3 blocks, both a 3D grid: other
+    grids fail with WV_ESHAPE when the storage is set. A rejected mode leaves the context
+    storing nothing, so a gradient then fails with WV_ESTATE instead of reading a store that
+    was never allocated, and a valid mode set afterwards works."""
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    cases = [((40, 36, 72), (L.STORE_AE_BF16, L.STORE_AE_FP8)),   # 36 % 8 != 0
+             ((32, 32, 70), (L.STORE_AE_BF16, L.STORE_AE_TIME))]   # 70 % 8, 70 % 4 != 0
+    for shape, modes in cases:
+        p = W.problem_3d(*shape, 10, f0=15.0, sponge=6, name="ragged")
+        for mode in modes:
+            s = WaveSolver.for_problem(p)
+            with pytest.raises(L.WvError) as e:
+                s.set_storage(mode, ae=net)
+            assert e.value.code == -6, (shape, mode)
+            d = torch.zeros((1, p.nt, len(p.rec)), dtype=torch.float32, device="cuda")
+            with pytest.raises(L.WvError) as e:
+                s.gradient(p.c_start, p.wavelet, d, 1.0)
+            assert e.value.code == -4, (shape, mode)
+            s.close()
+    p2 = W.problem_2d_small()
+    for mode in (L.STORE_AE_BF16, L.STORE_AE_TIME):
+        s = WaveSolver.for_problem(p2)
+        with pytest.raises(L.WvError) as e:
+            s.set_storage(mode, ae=net)
+        assert e.value.code == -6, mode
+        s.close()
+
+
+def test_rejected_storage_leaves_no_partial_store():
+    """A mode that fails its memory budget leaves the context storing nothing (WV_ESTATE on
+    the next gradient); the next accepted mode gives the oracle's gradient."""
+    p = short_problem(6)
+    sol = ow.solver_for(p)
+    d, sigma, _ = ow.observed_data(sol, p)
+    _, g_o, _, _ = ow.gradient(sol, p.c_start, p.wavelet, p.src, p.rec, d, sigma, src_w=p.src_w)
+    net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
+    s = WaveSolver.for_problem(p)
+    for mode in (L.STORE_FULL, L.STORE_CHECKPOINT, L.STORE_AE_BF16, L.STORE_AE_TIME):
+        with pytest.raises(L.WvError) as e:
+            s.set_storage(mode, n_checkpoints=4, ae=net, mem_budget_bytes=1000)
+        assert e.value.code == -2, mode
+        assert s.storage_bytes() == 0, mode
+        with pytest.raises(L.WvError) as e:
+            s.gradient(p.c_start, p.wavelet, d, sigma)
+        assert e.value.code == -4, mode
+    s.set_storage(L.STORE_CHECKPOINT, n_checkpoints=4)
+    _, g = s.gradient(p.c_start, p.wavelet, d, sigma)
+    assert rel(g.cpu().numpy(), g_o) < 1e-4
+    s.close()
