@@ -154,7 +154,12 @@ int wv_destroy(wv_ctx* ctx);
  * magnify the decoder's noise floor); its worst over sources above guard_tol
  * marks the store degraded, and with
  * fallback_policy WV_FALLBACK_CHECKPOINT gradient/hessvec then recompute with
- * checkpointing and return WV_OK_FALLBACK. Allocation happens here. */
+ * checkpointing and return WV_OK_FALLBACK. Allocation happens here; the previous
+ * store is freed first. Errors: WV_EINVAL (unknown mode or policy, missing net,
+ * n_checkpoints < 1 where slots are needed), WV_ESHAPE (an AE mode on a grid that is
+ * not 3D or not divisible into 8^3 patches, 4^3 blocks for WV_STORE_AE_TIME),
+ * WV_ENOMEM (budget or device memory). After an error the context stores nothing
+ * (as WV_STORE_NONE): gradient and hessvec return WV_ESTATE until a mode is set. */
 int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
                    int64_t mem_budget_bytes, double guard_tol, int fallback_policy);
 
