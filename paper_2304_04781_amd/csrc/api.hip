@@ -1427,9 +1427,14 @@ int wv_set_source_stencil(wv_ctx* c, int32_t radius, const float* h_weights)
         for (long long q = 0; q < n; ++q)
             WV_REQUIRE(std::isfinite(h_weights[q]), WV_EINVAL, "source weights must be finite");
         WV_HIP(hipStreamSynchronize(c->st));
+        // the new weights are in place before the old ones go, so a failed call keeps the
+        // previous stencil whole
+        float* wd = dev_alloc<float>(n);
+        const hipError_t e = hipMemcpy(wd, h_weights, sizeof(float) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) dev_free(wd);
+        WV_HIP(e);
         dev_free(c->src_w);
-        c->src_w = dev_alloc<float>(n);
-        WV_HIP(hipMemcpy(c->src_w, h_weights, sizeof(float) * n, hipMemcpyHostToDevice));
+        c->src_w = wd;
         c->src_radius = radius;
         c->store_ok = false;
         c->have_grad = false;
