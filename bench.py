@@ -154,6 +154,16 @@ def timed_kernels(sol, c0, wav, d_obs, sigma, every=4):
     return kt
 
 
+
+def device_shuffles(n, epochs, seed=5):
+    """One random permutation of range(n) per training epoch, int32 [epochs, n], drawn on
+    cuda:0 by torch's generator seeded with `seed`: twenty host permutations of the 256^3
+    training set take about two seconds, on the device a few milliseconds."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.stack([torch.randperm(n, generator=g, device="cuda", dtype=torch.int32) for _ in range(epochs)])
+
 def stream_ceilings(torch, dev, n, reps=20):
     """HBM rate (read + write bytes per second) of the library's streaming probe with
     the stencils' array mixes, n floats per array: the practical ceiling beside the
@@ -249,7 +259,7 @@ def multisource_pass(args):
     y, meta, t_cap = C.prior_draw_samples(plain, net, [c0], p.wavelet, every, rows)
     n = int(y.shape[0])
     info = C.train_samples(net, y, meta, epochs=args.ms_epochs, batch=args.batch,
-                           perms=W.shuffles(n, args.ms_epochs, seed=5))
+                           perms=device_shuffles(n, args.ms_epochs, seed=5))
     del y, meta
     plain.close()
     torch.cuda.empty_cache()
@@ -388,7 +398,7 @@ def bayes_pass(args):
     nets, info = {}, {}
     net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
     info["in-run"] = C.train_from_forward(s, net, c0, wav, every=every, epochs=args.epochs, batch=args.batch,
-                                          perms=W.shuffles(ncap * P, args.epochs, seed=5))
+                                          perms=device_shuffles(ncap * P, args.epochs, seed=5))
     nets["in-run"] = net
     log(f"in-run training {info['in-run']}")
     theta = (1e4, 1e4, 1e4)
@@ -409,7 +419,7 @@ def bayes_pass(args):
     y, meta, t_cap = C.prior_draw_samples(s, net, draws, wav, every, rows)
     n = int(y.shape[0])
     info["prior draws"] = dict(C.train_samples(net, y, meta, args.epochs, args.batch,
-                                               perms=W.shuffles(n, args.epochs, seed=5)), capture_s=round(t_cap, 2))
+                                               perms=device_shuffles(n, args.epochs, seed=5)), capture_s=round(t_cap, 2))
     del y, meta
     torch.cuda.empty_cache()
     nets["prior draws"] = net
@@ -490,12 +500,12 @@ def inversion_pass(args):
     if args.inv_store == "space":
         ncap = (T - 1) // args.snapshot_every
         info = C.train_from_forward(s, net, c0, wav, every=args.snapshot_every, epochs=args.epochs,
-                                    batch=args.batch, perms=W.shuffles(ncap * P, args.epochs, seed=5))
+                                    batch=args.batch, perms=device_shuffles(ncap * P, args.epochs, seed=5))
     else:
         nwin = (T - 1 + L.TWIN - 1) // L.TWIN
         y, meta, _ = C.time_window_samples(s, net, c0, wav, list(range(0, nwin, 4)))
         info = C.train_samples(net, y, None, args.epochs, args.batch,
-                               perms=W.shuffles(int(y.shape[0]), args.epochs, seed=5))
+                               perms=device_shuffles(int(y.shape[0]), args.epochs, seed=5))
         del y, meta
         torch.cuda.empty_cache()
         P = (p.nz // 4) * (p.ny // 4) * (p.nx // 4)    # exception vectors count 4^3 blocks
@@ -570,7 +580,7 @@ def hv384_pass(args):
     every = 60
     ncap = (T - 1) // every
     info = C.train_from_forward(s, net, c, wav, every=every, epochs=args.hv_epochs, batch=args.batch,
-                                perms=W.shuffles(ncap * P, args.hv_epochs, seed=5))
+                                perms=device_shuffles(ncap * P, args.hv_epochs, seed=5))
     s.close()
     torch.cuda.empty_cache()
     log(f"training {info}")
@@ -650,7 +660,7 @@ def time_pass(args):
     net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
     y, meta, t_cap = C.time_window_samples(s, net, c0, wav, windows)
     n = int(y.shape[0])
-    info = dict(C.train_samples(net, y, None, args.epochs, args.batch, perms=W.shuffles(n, args.epochs, seed=5)),
+    info = dict(C.train_samples(net, y, None, args.epochs, args.batch, perms=device_shuffles(n, args.epochs, seed=5)),
                 windows=len(windows), capture_s=round(t_cap, 2))
     del y, meta
     torch.cuda.empty_cache()
@@ -782,7 +792,7 @@ def main():
     t0 = time.perf_counter()
     net = Autoencoder(W.ae_init(2048, 512, 32, seed=4))
     nsamp = ((T - 1) // args.snapshot_every) * P * len(p.src)
-    perms = W.shuffles(nsamp, args.epochs, seed=5)
+    perms = device_shuffles(nsamp, args.epochs, seed=5)
     train_info = train_from_forward(solver, net, c0, wav, every=args.snapshot_every, epochs=args.epochs,
                                     batch=args.batch, perms=perms, weighting=args.weighting)
     del perms
@@ -1064,7 +1074,7 @@ def time_leg(args, p, solver, c0, wav, d_obs, sigma, g_ck, h_ck, dc, t_ck, hv_ck
     nwin = (T - 1 + L.TWIN - 1) // L.TWIN
     net = C.Autoencoder(W.ae_init(2048, 512, 32, seed=4))
     y, meta, _ = C.time_window_samples(solver, net, c0, wav, list(range(0, nwin, 4)))
-    info = C.train_samples(net, y, None, args.epochs, args.batch, perms=W.shuffles(int(y.shape[0]), args.epochs, seed=5))
+    info = C.train_samples(net, y, None, args.epochs, args.batch, perms=device_shuffles(int(y.shape[0]), args.epochs, seed=5))
     del y, meta
     torch.cuda.empty_cache()
     B = (p.nz // 4) * (p.ny // 4) * (p.nx // 4)

@@ -129,14 +129,22 @@ def time_window_samples(solver, ae: Autoencoder, c, wavelet, windows, rows=None,
     return y, meta, t_cap
 
 
+def _perm_tensor(perms, device):
+    """Visiting orders [epochs, nsamples] as a contiguous int32 device tensor (a numpy array
+    or a torch tensor; None: in order)."""
+    if perms is None:
+        return None
+    if torch.is_tensor(perms):
+        return perms.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(perms, dtype=np.int32), device=device)
+
+
 def train_samples(ae: Autoencoder, y, meta, epochs: int, batch: int, perms: Optional[np.ndarray] = None,
                   weighting: int = 0, lr: float = 1e-3, decay_every: int = 5, decay_factor: float = 0.5):
     """Adam on the training vectors y (with meta for the weighted loss).
     Returns a dict with sizes, first/last epoch losses and timings."""
     nsamp = int(y.shape[0])
-    perm_t = None
-    if perms is not None:
-        perm_t = torch.as_tensor(np.ascontiguousarray(perms, dtype=np.int32), device=y.device)
+    perm_t = _perm_tensor(perms, y.device)
     cfg = L.train_cfg(epochs=epochs, batch=batch, lr=lr, decay_every=decay_every, decay_factor=decay_factor,
                       weighting=weighting)
     t1 = time.perf_counter()
@@ -156,7 +164,7 @@ def train_from_forward(solver, ae: Autoencoder, c, wavelet, every: int, epochs: 
                        decay_every: int = 5, decay_factor: float = 0.5, beta_rel: float = 1e-7):
     """Capture every `every`-th state of a forward solve at c, set the floors
     beta_f = beta_rel * max|x_f|, normalise the snapshots and train.
-    perms: [epochs, nsamples] int32 visiting orders (None: in order).
+    perms: [epochs, nsamples] int32 visiting orders, numpy or a torch tensor (None: in order).
     Returns a dict with sizes, per-epoch losses and timings."""
     S = solver.S
     t0 = time.perf_counter()
@@ -176,9 +184,7 @@ def train_from_forward(solver, ae: Autoencoder, c, wavelet, every: int, epochs: 
     torch.cuda.synchronize()
     del cap
     torch.cuda.empty_cache()
-    perm_t = None
-    if perms is not None:
-        perm_t = torch.as_tensor(np.ascontiguousarray(perms, dtype=np.int32), device=y.device)
+    perm_t = _perm_tensor(perms, y.device)
     cfg = L.train_cfg(epochs=epochs, batch=batch, lr=lr, decay_every=decay_every, decay_factor=decay_factor,
                       weighting=weighting)
     t1 = time.perf_counter()
