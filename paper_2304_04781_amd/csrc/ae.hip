@@ -526,6 +526,7 @@ struct EpiMse {
     __device__ __forceinline__ void tile(int m0, int n0, int rows, int cols, float* C, int ldc, int bm) const
     {
         const double inv = 1.0 / (512.0 * wsum[0]);
+        const double inv2 = 2.0 * inv;  // d(loss)/d(yhat) per unit weight and difference
         const int nq = cols / 8;
         double tl = 0.0;  // this thread's rows (their q = 0 thread) of the tile's loss
         for (int idx8 = threadIdx.x; idx8 < rows * nq; idx8 += 256) {
@@ -533,7 +534,7 @@ struct EpiMse {
             const int b = m0 + rr, c = n0 + q * 8;
             const long long src = idx ? idx[b] : b;
             const float wf = w[b * 4 + (c >> 9)];
-            const float f = (float)(2.0 * wf / (512.0 * wsum[0]));
+            const float f = (float)(wf * inv2);
             const uint4 yv = *reinterpret_cast<const uint4*>(y + src * ld + c);
             const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
             float d[8];
