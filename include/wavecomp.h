@@ -158,8 +158,10 @@ int wv_destroy(wv_ctx* ctx);
  * store is freed first. Errors: WV_EINVAL (unknown mode or policy, missing net,
  * n_checkpoints < 1 where slots are needed), WV_ESHAPE (an AE mode on a grid that is
  * not 3D or not divisible into 8^3 patches, 4^3 blocks for WV_STORE_AE_TIME),
- * WV_ENOMEM (budget or device memory). After an error the context stores nothing
- * (as WV_STORE_NONE): gradient and hessvec return WV_ESTATE until a mode is set. */
+ * WV_ENOMEM (budget or device memory). An unknown mode or policy is rejected before
+ * anything changes; after any other error the previous store is gone and the context
+ * stores nothing (as WV_STORE_NONE): gradient and hessvec return WV_ESTATE until a
+ * mode is set. */
 int wv_set_storage(wv_ctx* ctx, int mode, int32_t n_checkpoints, ae_net* ae,
                    int64_t mem_budget_bytes, double guard_tol, int fallback_policy);
 
